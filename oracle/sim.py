@@ -97,8 +97,7 @@ def residual(S, M, X, lam, lam_c=None, norm="minv"):
 
 
 def rayleigh_ritz(S, M, Psi, dense=jacobi_gep):
-    """Reduced matrices, dense eigenproblem and update (Algorithm 1, steps
-    5-8).  Returns (lam, Phi, Phibar, Sbar, Mbar)."""
+    """Reduced matrices, dense eigenproblem and update (Algorithm 1).  Returns (lam, Phi, Phibar, Sbar, Mbar)."""
     Mop = mass_operator(M)
     Sbar = Psi.T @ (S @ Psi)
     Mbar = Psi.T @ (Mop @ Psi)
@@ -110,7 +109,7 @@ def rayleigh_ritz(S, M, Psi, dense=jacobi_gep):
 
 class ShiftedSolver:
     """(S - mu M)^-1 applied to blocks, by one sparse factorisation
-    (Algorithm 1, step 2)."""
+    (the factorisation of Algorithm 1)."""
 
     def __init__(self, S, M, mu):
         self.mu = float(mu)

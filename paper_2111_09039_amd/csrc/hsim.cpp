@@ -1,0 +1,1015 @@
+// HSIM library: hierarchy build, device state, the per-level subspace
+// iteration driver (Algorithm 2 with Algorithm 1 inside) and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace hsim {
+
+// ============================================================== errors
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(hsim_status code, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error{code, buf};
+}
+
+#define HIPCHECK(expr)                                                                              \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) fail(HSIM_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+// ========================================================== device memory
+DeviceBuffer::~DeviceBuffer() { release(); }
+void DeviceBuffer::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+void DeviceBuffer::alloc(size_t nbytes) {
+    if (nbytes <= bytes && p) return;
+    release();
+    if (nbytes == 0) return;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+        p = nullptr;
+        fail(HSIM_E_NOMEM, "hipMalloc(%zu) failed: %s", nbytes, hipGetErrorString(e));
+    }
+    bytes = nbytes;
+}
+void DeviceBuffer::copy_in(const void* src, size_t nbytes) {
+    if (nbytes == 0) return;
+    HIPCHECK(hipMemcpy(p, src, nbytes, hipMemcpyHostToDevice));
+}
+
+template <class T>
+static T* dptr(DeviceBuffer& b) { return b.as<T>(); }
+
+static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ====================================================== dense eigenproblem
+// First kout eigenpairs of S x = lambda M x for k x k dense symmetric S and SPD M
+// (row-major, device): equilibration E = diag(M)^-1/2, LDL^T of E M E by the
+// tiled front kernels, C = D^-1/2 L^-1 (E S E) L^-T D^-1/2, cyclic Jacobi on C,
+// X = E L^-T D^-1/2 V.
+struct DenseGEP {
+    int32_t k = 0, m = 0, ns_pad = 0, Mt = 0;
+    std::vector<int64_t> diag_ptr, panel_ptr, upd_ptr;
+    DeviceBuffer front, tiles, linv, D, items_diag, items_panel, items_upd, gptr, counters;
+    DeviceBuffer S2, M2, e, W, W2, C, V, dcur, ocur, dnext, onext, rot, dis, normf;
+
+    void setup(int32_t kk) {
+        if (k == kk) return;
+        k = kk;
+        m = k + (k & 1);
+        ns_pad = (int32_t)round_up(k, NB);
+        Mt = ns_pad / NB;
+        DFront f{};
+        f.ns = k;
+        f.ns_pad = ns_pad;
+        f.Mt = Mt;
+        f.nsb = Mt;
+        f.parent = -1;
+        front.upload(std::vector<DFront>{f});
+        tiles.alloc((size_t)Mt * (Mt + 1) / 2 * NB * NB * sizeof(double));
+        linv.alloc((size_t)Mt * NB * NB * sizeof(double));
+        D.alloc((size_t)ns_pad * sizeof(double));
+        std::vector<int32_t> dg, pn, up;
+        diag_ptr = {0};
+        panel_ptr = {0};
+        upd_ptr = {0};
+        for (int32_t s = 0; s < Mt; ++s) {
+            dg.push_back(0);
+            for (int32_t I = s + 1; I < Mt; ++I) { pn.push_back(0); pn.push_back(I); }
+            for (int32_t J = s + 1; J < Mt; ++J)
+                for (int32_t I = J; I < Mt; ++I) { up.push_back(0); up.push_back(I); up.push_back(J); }
+            diag_ptr.push_back((int64_t)dg.size());
+            panel_ptr.push_back((int64_t)pn.size() / 2);
+            upd_ptr.push_back((int64_t)up.size() / 3);
+        }
+        items_diag.upload(dg);
+        items_panel.upload(pn.empty() ? std::vector<int32_t>{0, 0} : pn);
+        items_upd.upload(up.empty() ? std::vector<int32_t>{0, 0, 0} : up);
+        gptr.upload(std::vector<int64_t>((size_t)k + 1, 0));
+        counters.alloc(4 * sizeof(int32_t));
+        const size_t kk2 = (size_t)k * k * sizeof(double);
+        S2.alloc(kk2);
+        M2.alloc(kk2);
+        W.alloc(kk2);
+        W2.alloc(kk2);
+        e.alloc((size_t)k * sizeof(double));
+        dis.alloc((size_t)m * sizeof(double));
+        C.alloc((size_t)m * m * sizeof(double));
+        V.alloc((size_t)m * m * sizeof(double));
+        dcur.alloc((size_t)m * sizeof(double));
+        ocur.alloc((size_t)m * sizeof(double));
+        dnext.alloc((size_t)m * sizeof(double));
+        onext.alloc((size_t)m * sizeof(double));
+        rot.alloc(4 * sizeof(int32_t));
+        normf.alloc(2 * sizeof(double));
+    }
+
+    void factor(hipStream_t s) {
+        int32_t* cnt = dptr<int32_t>(counters);
+        HIPCHECK(launch_fill_i32(cnt, 4, 0, s));
+        const DFront* fr = dptr<DFront>(front);
+        for (int32_t st = 0; st < Mt; ++st) {
+            HIPCHECK(launch_fac_diag(dptr<double>(tiles), dptr<double>(linv), dptr<double>(D), fr,
+                                     dptr<int32_t>(items_diag) + diag_ptr[st], diag_ptr[st + 1] - diag_ptr[st], st,
+                                     cnt, s));
+            HIPCHECK(launch_fac_panel(dptr<double>(tiles), dptr<double>(linv), dptr<double>(D), fr,
+                                      dptr<int32_t>(items_panel) + 2 * panel_ptr[st], panel_ptr[st + 1] - panel_ptr[st],
+                                      st, s));
+            HIPCHECK(launch_fac_update(dptr<double>(tiles), dptr<double>(D), fr,
+                                       dptr<int32_t>(items_upd) + 3 * upd_ptr[st], upd_ptr[st + 1] - upd_ptr[st], st, s));
+        }
+    }
+
+    int32_t qc_for(int32_t ncols) const {
+        int32_t qc = 32;
+        while (qc > 1 && (int64_t)(ns_pad + NB) * qc * 8 > 64 * 1024) qc /= 2;
+        (void)ncols;
+        return qc;
+    }
+
+    void fwd(double* X, int32_t ncols, hipStream_t s) {
+        const int32_t qc = qc_for(ncols);
+        HIPCHECK(launch_solve_fwd<double>(dptr<double>(tiles), dptr<double>(linv), dptr<DFront>(front), 0, 1, ns_pad, X,
+                                          ncols, 0, ncols, qc, nullptr, 0, dptr<int64_t>(gptr), nullptr, nullptr, s));
+    }
+    void bwd(double* X, int32_t ncols, int64_t ld, hipStream_t s) {
+        const int32_t qc = qc_for(ncols);
+        HIPCHECK(launch_solve_bwd<double>(dptr<double>(tiles), dptr<double>(linv), dptr<double>(D), dptr<DFront>(front),
+                                          0, 1, ns_pad, X, ld, 0, ncols, qc, nullptr, false, s));
+    }
+
+    // returns the Jacobi sweeps used
+    int32_t run(const double* dS, const double* dM, int32_t kout, double* lam_out, double* X, int64_t ldx,
+                hipStream_t s, int32_t max_sweeps = 40);
+};
+
+
+int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* lam_out, double* X, int64_t ldx,
+                      hipStream_t s, int32_t max_sweeps) {
+    HIPCHECK(launch_equilibrate(dS, dM, k, dptr<double>(S2), dptr<double>(M2), dptr<double>(e), s));
+    HIPCHECK(launch_dense_to_front(dptr<double>(M2), k, dptr<double>(tiles), Mt, s));
+    factor(s);
+    // W = L^-1 S', W2 = W^T, W2 <- L^-1 W2 = L^-1 S' L^-T
+    HIPCHECK(launch_copy2d(dptr<double>(S2), k, k, k, dptr<double>(W), k, s));
+    fwd(dptr<double>(W), k, s);
+    HIPCHECK(launch_transpose(dptr<double>(W), k, dptr<double>(W2), s));
+    fwd(dptr<double>(W2), k, s);
+    // C = D^-1/2 W2 D^-1/2 (symmetrised) embedded in m x m; dis = D^-1/2
+    HIPCHECK(launch_sym_scale(dptr<double>(W2), dptr<double>(D), k, dptr<double>(W), s));
+    HIPCHECK(launch_embed_pad(dptr<double>(W), k, m, dptr<double>(C), dptr<double>(normf), dptr<double>(dis),
+                              dptr<double>(D), s));
+    HIPCHECK(launch_jacobi_init(dptr<double>(C), m, dptr<double>(V), dptr<double>(dcur), dptr<double>(ocur), s));
+    const double tol_rel = 1e-15;
+    int32_t sweeps = 0;
+    int64_t round = 0;
+    for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
+        HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 1, 0, s));
+        for (int32_t r = 0; r < m - 1; ++r, ++round) {
+            HIPCHECK(launch_jacobi_round(dptr<double>(C), dptr<double>(V), m, (int32_t)(round % (m - 1)),
+                                         dptr<double>(dcur), dptr<double>(ocur), dptr<double>(dnext),
+                                         dptr<double>(onext), tol_rel, dptr<double>(normf), 1e-17,
+                                         dptr<int32_t>(rot), s));
+            std::swap(dcur.p, dnext.p);
+            std::swap(ocur.p, onext.p);
+        }
+        int32_t nrot = 0;
+        HIPCHECK(hipMemcpyAsync(&nrot, rot.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (nrot == 0) break;
+    }
+    // Y = D^-1/2 V (sorted, first kout columns), X' = L^-T Y, X = E X'
+    HIPCHECK(launch_sort_eig(dptr<double>(C), m, m, dptr<double>(V), k, dptr<double>(dis), kout, lam_out,
+                             dptr<double>(W), kout, s));
+    bwd(dptr<double>(W), kout, kout, s);
+    HIPCHECK(launch_diag_scale(dptr<double>(e), k, dptr<double>(W), kout, kout, X, ldx, s));
+    return std::min(sweeps, max_sweeps);
+}
+
+// ================================================================ levels
+struct TLev {
+    int32_t f0 = 0, f1 = 0, ns_pad_max = 0, qc = 1;
+    int32_t step0 = 0, step1 = 0;
+    std::vector<int32_t> ea_tile_cols;   // per child slot: max tile columns of the children's update blocks
+};
+
+struct Level {
+    int32_t tau = 0;
+    int64_t n = 0;
+    bool coarsest = false;
+    std::vector<int32_t> verts;          // mesh vertex of every level vertex
+    Csr S;                               // level order
+    std::vector<double> Mval;            // on S's pattern
+    std::vector<double> mdiag;           // level 0 only
+    Csr U;                               // rows: this level, cols: next coarser level (level order)
+    double rho = 0;
+    Symbolic sy;
+    std::vector<TLev> tl;
+    // device, internal (elimination) order
+    DeviceBuffer dS_ptr, dS_idx, dS_val, dM_val, dmdiag, dU_ptr, dU_idx, dU_val, dperm;
+    DeviceBuffer dfronts, tiles, linv, D, tiles32, linv32, D32, counters;
+    DeviceBuffer asm_dst, asm_src, it_diag, it_panel, it_upd, it_ea, rel, rows, gptr, gidx;
+    DeviceBuffer ubuf;
+    double mu = 0;
+    bool factored = false, factored32 = false;
+    int32_t neg_pivots = 0;
+};
+
+}  // namespace hsim
+
+struct hsim_hierarchy {
+    int device = 0;
+    int32_t p = 0, q = 0, T = 0, ld = 0;
+    hsim_build_opts bo{};
+    hsim::Mesh mesh;
+    std::vector<double> density;
+    double area = 0, ms_build = 0;
+    std::vector<std::unique_ptr<hsim::Level>> lv;
+    hsim::DenseGEP rr, coarse;
+    // solve workspace (sized for level 0)
+    hsim::DeviceBuffer Phi, Psi, SPsi, MPsi, Btmp, R, Xc, gram_part, ritz_part, Sbar, Mbar, lam, Phibar, resid,
+        coarseS, coarseM, exportw, cPhi, cPhi2;
+    bool solved = false, host_only = false;
+    std::vector<double> last_lam;
+};
+
+namespace hsim {
+
+// ----------------------------------------------------------- build helpers
+static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<int32_t>* coarse_iperm) {
+    const int64_t n = L.n;
+    std::vector<int32_t> perm, iperm;
+    if (L.coarsest) {
+        perm.resize(n);
+        std::iota(perm.begin(), perm.end(), 0);
+        iperm = perm;
+    } else {
+        perm = L.sy.perm;
+        iperm = L.sy.iperm;
+    }
+    // permuted CSR (rows and columns in internal order)
+    std::vector<int64_t> ptr(n + 1, 0);
+    std::vector<int32_t> idx(L.S.nnz());
+    std::vector<double> sv(L.S.nnz()), mv(L.S.nnz());
+    std::vector<int64_t> newpos(L.S.nnz());   // CSR entry (level order) -> entry of the permuted CSR
+    std::vector<std::pair<int32_t, int64_t>> rowbuf;
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t v = perm[k];
+        rowbuf.clear();
+        for (int64_t e = L.S.ptr[v]; e < L.S.ptr[v + 1]; ++e) rowbuf.push_back({iperm[L.S.idx[e]], e});
+        std::sort(rowbuf.begin(), rowbuf.end());
+        ptr[k + 1] = ptr[k] + (int64_t)rowbuf.size();
+        for (size_t t = 0; t < rowbuf.size(); ++t) {
+            idx[ptr[k] + t] = rowbuf[t].first;
+            sv[ptr[k] + t] = L.S.val[rowbuf[t].second];
+            mv[ptr[k] + t] = L.Mval[rowbuf[t].second];
+            newpos[rowbuf[t].second] = ptr[k] + (int64_t)t;
+        }
+    }
+    L.dS_ptr.upload(ptr);
+    L.dS_idx.upload(idx);
+    L.dS_val.upload(sv);
+    L.dM_val.upload(mv);
+    L.dperm.upload(perm);
+    if (!L.mdiag.empty()) {
+        std::vector<double> md(n);
+        for (int64_t k = 0; k < n; ++k) md[k] = L.mdiag[perm[k]];
+        L.dmdiag.upload(md);
+    }
+    if (L.coarsest) return;
+    // U: rows in this level's internal order, columns in the coarser level's internal order
+    {
+        std::vector<int64_t> up(n + 1, 0);
+        std::vector<int32_t> ui(L.U.nnz());
+        std::vector<double> uv(L.U.nnz());
+        std::vector<std::pair<int32_t, double>> rb;
+        for (int64_t k = 0; k < n; ++k) {
+            const int32_t v = perm[k];
+            rb.clear();
+            for (int64_t e = L.U.ptr[v]; e < L.U.ptr[v + 1]; ++e) rb.push_back({(*coarse_iperm)[L.U.idx[e]], L.U.val[e]});
+            std::sort(rb.begin(), rb.end());
+            up[k + 1] = up[k] + (int64_t)rb.size();
+            for (size_t t = 0; t < rb.size(); ++t) {
+                ui[up[k] + t] = rb[t].first;
+                uv[up[k] + t] = rb[t].second;
+            }
+        }
+        L.dU_ptr.upload(up);
+        L.dU_idx.upload(ui);
+        L.dU_val.upload(uv);
+    }
+    // factor structures
+    const Symbolic& sy = L.sy;
+    std::vector<DFront> df(sy.fronts.size());
+    for (size_t i = 0; i < sy.fronts.size(); ++i) {
+        const Front& f = sy.fronts[i];
+        DFront& d = df[i];
+        d.start = f.start;
+        d.tile_base = f.tile_base;
+        d.linv_base = f.linv_base;
+        d.d_base = f.d_base;
+        d.ubuf_row = f.ubuf_row;
+        d.gather_base = f.gather_base;
+        d.rows_off = sy.rows_ptr[i];
+        d.ns = f.ns;
+        d.mu = f.mu;
+        d.ns_pad = f.ns_pad;
+        d.mu_pad = f.mu_pad;
+        d.Mt = f.Mt;
+        d.nsb = f.nsb;
+        d.parent = f.parent;
+        d.pad_ = 0;
+    }
+    L.dfronts.upload(df);
+    L.tiles.alloc((size_t)sy.tile_doubles * sizeof(double));
+    L.linv.alloc((size_t)sy.linv_doubles * sizeof(double));
+    L.D.alloc((size_t)std::max<int64_t>(1, sy.d_doubles) * sizeof(double));
+    L.counters.alloc(4 * sizeof(int32_t));
+    L.asm_dst.upload(sy.asm_dst);
+    {
+        // the assembly map indexes the level-order CSR; the device holds the permuted one
+        std::vector<int64_t> src(sy.asm_src.size());
+        for (size_t e = 0; e < src.size(); ++e) src[e] = sy.asm_src[e] < 0 ? -1 : newpos[sy.asm_src[e]];
+        L.asm_src.upload(src);
+    }
+    L.it_diag.upload(sy.diag);
+    L.it_panel.upload(sy.panel.empty() ? std::vector<int32_t>{0, 0} : sy.panel);
+    L.it_upd.upload(sy.upd.empty() ? std::vector<int32_t>{0, 0, 0} : sy.upd);
+    L.it_ea.upload(sy.ea.empty() ? std::vector<int32_t>{0} : sy.ea);
+    L.rel.upload(sy.rel.empty() ? std::vector<int32_t>{0} : sy.rel);
+    L.rows.upload(sy.rows.empty() ? std::vector<int32_t>{0} : sy.rows);
+    L.gptr.upload(sy.gather_ptr);
+    L.gidx.upload(sy.gather_idx.empty() ? std::vector<int64_t>{0} : sy.gather_idx);
+    L.ubuf.alloc((size_t)std::max<int64_t>(1, sy.ubuf_rows) * H->ld * sizeof(double));
+    // per tree level launch data
+    const int32_t mc = std::max<int32_t>(1, sy.max_children);
+    L.tl.resize(sy.tree_levels);
+    for (int32_t t = 0; t < sy.tree_levels; ++t) {
+        TLev& T = L.tl[t];
+        T.f0 = sy.tlev_ptr[t];
+        T.f1 = sy.tlev_ptr[t + 1];
+        for (int32_t i = T.f0; i < T.f1; ++i) T.ns_pad_max = std::max(T.ns_pad_max, sy.fronts[i].ns_pad);
+        T.qc = 32;
+        while (T.qc > 1 && (int64_t)(T.ns_pad_max + NB) * T.qc * 8 > 64 * 1024) T.qc /= 2;
+        T.step0 = sy.step_ptr[t];
+        T.step1 = sy.step_ptr[t + 1];
+        T.ea_tile_cols.assign(mc, 0);
+        for (int32_t c = 0; c < mc; ++c)
+            for (int64_t e = sy.ea_ptr[(int64_t)t * mc + c]; e < sy.ea_ptr[(int64_t)t * mc + c + 1]; ++e)
+                T.ea_tile_cols[c] = std::max<int32_t>(T.ea_tile_cols[c], (sy.fronts[sy.ea[e]].mu + NB - 1) / NB);
+    }
+}
+
+// ----------------------------------------------------------- factor / solve
+static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s) {
+    const Symbolic& sy = L.sy;
+    const int32_t mc = std::max<int32_t>(1, sy.max_children);
+    int32_t* cnt = dptr<int32_t>(L.counters);
+    HIPCHECK(launch_fill_i32(cnt, 4, 0, s));
+    const DFront* fr = dptr<DFront>(L.dfronts);
+    double* tiles = dptr<double>(L.tiles);
+    for (int32_t t = 0; t < sy.tree_levels; ++t) {
+        const TLev& T = L.tl[t];
+        // zero this tree level's fronts, assemble A = S - mu M, add the children's updates
+        const int64_t tb0 = sy.fronts[T.f0].tile_base;
+        const Front& fl = sy.fronts[T.f1 - 1];
+        const int64_t tb1 = fl.tile_base + (int64_t)fl.Mt * (fl.Mt + 1) / 2 * NB * NB;
+        HIPCHECK(launch_fill(tiles + tb0, tb1 - tb0, 0.0, s));
+        HIPCHECK(launch_assemble(tiles, dptr<int64_t>(L.asm_dst) + sy.asm_tlev_ptr[t],
+                                 dptr<int64_t>(L.asm_src) + sy.asm_tlev_ptr[t],
+                                 sy.asm_tlev_ptr[t + 1] - sy.asm_tlev_ptr[t], dptr<double>(L.dS_val),
+                                 dptr<double>(L.dM_val), 1.0, -mu, s));
+        for (int32_t c = 0; c < mc; ++c) {
+            const int64_t a = sy.ea_ptr[(int64_t)t * mc + c], b = sy.ea_ptr[(int64_t)t * mc + c + 1];
+            HIPCHECK(launch_extend_add(tiles, fr, dptr<int32_t>(L.it_ea) + a, b - a, dptr<int32_t>(L.rel),
+                                       T.ea_tile_cols[c], s));
+        }
+        for (int32_t st = T.step0; st < T.step1; ++st) {
+            const int32_t k = st - T.step0;
+            HIPCHECK(launch_fac_diag(tiles, dptr<double>(L.linv), dptr<double>(L.D), fr,
+                                     dptr<int32_t>(L.it_diag) + sy.diag_ptr[st], sy.diag_ptr[st + 1] - sy.diag_ptr[st],
+                                     k, cnt, s));
+            HIPCHECK(launch_fac_panel(tiles, dptr<double>(L.linv), dptr<double>(L.D), fr,
+                                      dptr<int32_t>(L.it_panel) + 2 * sy.panel_ptr[st],
+                                      sy.panel_ptr[st + 1] - sy.panel_ptr[st], k, s));
+            HIPCHECK(launch_fac_update(tiles, dptr<double>(L.D), fr, dptr<int32_t>(L.it_upd) + 3 * sy.upd_ptr[st],
+                                       sy.upd_ptr[st + 1] - sy.upd_ptr[st], k, s));
+        }
+    }
+    int32_t hc[2] = {0, 0};
+    HIPCHECK(hipMemcpyAsync(hc, cnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    L.mu = mu;
+    L.neg_pivots = hc[0];
+    L.factored = hc[1] == 0;
+    L.factored32 = false;
+    if (hc[1] != 0) fail(HSIM_E_FACTOR, "LDL^T of S - mu M (level %d, mu=%g): %d zero or non-finite pivots", L.tau, mu, hc[1]);
+    (void)H;
+}
+
+// X (internal order, leading dim ld) <- (S - mu M)^-1 (mdiag ? m*X : X) on columns [col0, col0 + ncols)
+static void solve_level(hsim_hierarchy* H, Level& L, double* X, int32_t col0, int32_t ncols, bool scale_by_m,
+                        hipStream_t s) {
+    const Symbolic& sy = L.sy;
+    const DFront* fr = dptr<DFront>(L.dfronts);
+    const double* md = scale_by_m ? dptr<double>(L.dmdiag) : nullptr;
+    for (int32_t t = 0; t < sy.tree_levels; ++t) {
+        const TLev& T = L.tl[t];
+        HIPCHECK(launch_solve_fwd<double>(dptr<double>(L.tiles), dptr<double>(L.linv), fr, T.f0, T.f1, T.ns_pad_max, X,
+                                          H->ld, col0, ncols, T.qc, dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr),
+                                          dptr<int64_t>(L.gidx), md, s));
+    }
+    for (int32_t t = sy.tree_levels - 1; t >= 0; --t) {
+        const TLev& T = L.tl[t];
+        HIPCHECK(launch_solve_bwd<double>(dptr<double>(L.tiles), dptr<double>(L.linv), dptr<double>(L.D), fr, T.f0, T.f1,
+                                          T.ns_pad_max, X, H->ld, col0, ncols, T.qc, dptr<int32_t>(L.rows), true, s));
+    }
+}
+
+static void apply_level(hsim_hierarchy* H, Level& L, int op, const double* X, double* Y, int32_t k, hipStream_t s) {
+    // op 0: S, 1: M, 2: S - mu M
+    if (op == 1 && L.tau == 0) {
+        HIPCHECK(launch_diag_scale(dptr<double>(L.dmdiag), L.n, X, H->ld, k, Y, H->ld, s));
+        return;
+    }
+    const double* va = op == 1 ? dptr<double>(L.dM_val) : dptr<double>(L.dS_val);
+    const double* vb = op == 2 ? dptr<double>(L.dM_val) : nullptr;
+    HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), va, vb, 1.0, op == 2 ? -L.mu : 0.0, L.n, X,
+                         H->ld, k, Y, H->ld, s));
+}
+
+static void prolong_level(hsim_hierarchy* H, Level& L, const double* Xc, double* Xf, int32_t k, hipStream_t s) {
+    HIPCHECK(launch_spmm(dptr<int64_t>(L.dU_ptr), dptr<int32_t>(L.dU_idx), dptr<double>(L.dU_val), nullptr, 1.0, 0.0,
+                         L.n, Xc, H->ld, k, Xf, H->ld, s));
+}
+
+static void alloc_workspace(hsim_hierarchy* H) {
+    const int64_t n0 = H->lv[0]->n;
+    const size_t blk = (size_t)n0 * H->ld * sizeof(double);
+    H->Phi.alloc(blk);
+    H->Psi.alloc(blk);
+    H->SPsi.alloc(blk);
+    H->MPsi.alloc(blk);
+    H->Btmp.alloc(blk);
+    H->Xc.alloc(blk);
+    const int64_t chunk = 4096;
+    H->gram_part.alloc((size_t)gram_partial_doubles(n0, H->q, chunk) * sizeof(double));
+    H->ritz_part.alloc((size_t)ritz_partial_doubles(n0, H->q, chunk) * sizeof(double));
+    H->Sbar.alloc((size_t)H->q * H->q * sizeof(double));
+    H->Mbar.alloc((size_t)H->q * H->q * sizeof(double));
+    H->Phibar.alloc((size_t)H->q * H->q * sizeof(double));
+    H->lam.alloc((size_t)H->q * sizeof(double));
+    H->resid.alloc((size_t)H->q * sizeof(double));
+    const int64_t nch = (n0 + 8191) / 8192;
+    H->exportw.alloc((size_t)(2 * nch * H->p + H->p + 8) * sizeof(double));
+    const int64_t nc = H->lv.back()->n;
+    H->coarseS.alloc((size_t)nc * nc * sizeof(double));
+    H->coarseM.alloc((size_t)nc * nc * sizeof(double));
+}
+
+static double lambda_floor(const std::vector<double>& lam) {
+    double top = 0;
+    for (double l : lam) top = std::max(top, std::fabs(l));
+    for (double l : lam)
+        if (l > 1e-8 * top) return l;
+    return top > 0 ? top : 1.0;
+}
+
+static double choose_shift(const std::vector<double>& lam, int32_t p, double alpha) {
+    const int32_t j = (int32_t)std::floor(alpha * p + 1e-12);
+    double mu = lam[std::min<size_t>(j, lam.size() - 1)];
+    if (mu <= 1e-12 * lam.back()) {
+        for (double l : lam)
+            if (l > 1e-12 * lam.back()) { mu = -1e-3 * l; break; }
+    }
+    return mu;
+}
+
+// one Rayleigh-Ritz step on level L from the basis in Psi (already inverse
+// iterated); leaves Phi, lam (device) and returns lam/resid on the host
+static void rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam, std::vector<double>& res,
+                          hipStream_t s, double* ms_gram, double* ms_rr, double* ms_ritz) {
+    const int32_t q = H->q;
+    const bool fin = L.tau == 0;
+    auto t0 = std::chrono::steady_clock::now();
+    apply_level(H, L, 0, dptr<double>(H->Psi), dptr<double>(H->SPsi), q, s);
+    if (!fin) apply_level(H, L, 1, dptr<double>(H->Psi), dptr<double>(H->MPsi), q, s);
+    HIPCHECK(launch_gram(dptr<double>(H->Psi), dptr<double>(H->SPsi), fin ? nullptr : dptr<double>(H->MPsi),
+                         fin ? dptr<double>(L.dmdiag) : nullptr, L.n, q, H->ld, dptr<double>(H->gram_part), 4096,
+                         dptr<double>(H->Sbar), dptr<double>(H->Mbar), s));
+    HIPCHECK(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    H->rr.setup(q);
+    H->rr.run(dptr<double>(H->Sbar), dptr<double>(H->Mbar), q, dptr<double>(H->lam), dptr<double>(H->Phibar), q, s);
+    lam.resize(q);
+    HIPCHECK(hipMemcpyAsync(lam.data(), H->lam.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    auto t2 = std::chrono::steady_clock::now();
+    HIPCHECK(launch_ritz(dptr<double>(H->Psi), dptr<double>(H->SPsi), fin ? nullptr : dptr<double>(H->MPsi),
+                         fin ? dptr<double>(L.dmdiag) : nullptr, dptr<double>(H->Phibar), dptr<double>(H->lam), L.n, q,
+                         H->ld, dptr<double>(H->Phi), nullptr, dptr<double>(H->ritz_part), 4096, fin,
+                         lambda_floor(lam), dptr<double>(H->resid), s));
+    res.resize(q);
+    HIPCHECK(hipMemcpyAsync(res.data(), H->resid.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    auto t3 = std::chrono::steady_clock::now();
+    *ms_gram += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    *ms_rr += std::chrono::duration<double, std::milli>(t2 - t1).count();
+    *ms_ritz += std::chrono::duration<double, std::milli>(t3 - t2).count();
+}
+
+static Level& level_at(hsim_hierarchy* H, int32_t level) {
+    if (!H) fail(HSIM_E_INVALID, "null hierarchy");
+    if (H->host_only) fail(HSIM_E_STATE, "hierarchy was built host-only");
+    if (level < 0 || level >= H->T) fail(HSIM_E_INVALID, "level %d out of range [0, %d)", level, H->T);
+    return *H->lv[level];
+}
+
+}  // namespace hsim
+
+using namespace hsim;
+
+#define API_BEGIN try {
+#define API_END                                       \
+    }                                                 \
+    catch (const hsim::Error& e) {                    \
+        hsim::set_last_error(e.msg);                  \
+        return e.code;                                \
+    }                                                 \
+    catch (const std::bad_alloc&) {                   \
+        hsim::set_last_error("host allocation failed"); \
+        return HSIM_E_NOMEM;                          \
+    }                                                 \
+    catch (const std::exception& e) {                 \
+        hsim::set_last_error(e.what());               \
+        return HSIM_E_INVALID;                        \
+    }                                                 \
+    return HSIM_OK;
+
+extern "C" {
+
+void hsim_default_build_opts(hsim_build_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->p = 0;
+    o->levels = 0;
+    o->n_coarsest = 0;
+    o->growth_mode = 0;
+    o->lumping = 0;
+    o->support_sigma = 7.0;
+    o->seed = 0;
+}
+
+void hsim_default_solve_opts(hsim_solve_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->tol = 1e-2;
+    o->shift_alpha = 0.1;
+    o->precision = HSIM_FP64;
+    o->max_iters = 100;
+    o->flags = 0;
+    o->stream = nullptr;
+}
+
+const char* hsim_last_error(void) { return g_last_error.c_str(); }
+
+void hsim_free(hsim_hierarchy* h) { delete h; }
+
+hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, int64_t nf, const double* density,
+                                 const hsim_build_opts* opts, hsim_hierarchy** out) {
+    API_BEGIN
+    if (!V || !F || !out) fail(HSIM_E_INVALID, "null argument");
+    *out = nullptr;
+    hsim_build_opts bo;
+    if (opts) bo = *opts;
+    else hsim_default_build_opts(&bo);
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<hsim_hierarchy> H(new hsim_hierarchy());
+    H->host_only = (bo.flags & HSIM_BUILD_HOST_ONLY) != 0;
+    if (!H->host_only) HIPCHECK(hipGetDevice(&H->device));
+    H->bo = bo;
+    Mesh& m = H->mesh;
+    m.nv = nv;
+    m.nf = nf;
+    if (nv <= 0 || nf <= 0) fail(HSIM_E_MESH, "empty mesh");
+    m.V.assign(V, V + 3 * nv);
+    m.F.assign(F, F + 3 * nf);
+    if (density) {
+        H->density.assign(density, density + nv);
+        for (int64_t i = 0; i < nv; ++i)
+            if (!(H->density[i] > 0) || !std::isfinite(H->density[i])) fail(HSIM_E_INVALID, "density must be positive");
+    }
+    validate_mesh(m);
+    Graph g = edge_graph(m);
+    const int32_t p = bo.p;
+    if (p < 1) fail(HSIM_E_INVALID, "p must be >= 1");
+    const int32_t q = std::max<int32_t>((int32_t)std::ceil(1.5 * p), p + 8);
+    if (q >= nv) fail(HSIM_E_INVALID, "subspace size q=%d must be below the vertex count %lld", q, (long long)nv);
+    int T = bo.levels ? bo.levels : (p <= 200 ? 2 : 3);
+    if (T < 2 || T > HSIM_MAX_LEVELS) fail(HSIM_E_INVALID, "levels must be in [2, %d]", HSIM_MAX_LEVELS);
+    int64_t nc = bo.n_coarsest ? bo.n_coarsest : std::max<int64_t>((int64_t)std::ceil(1.5 * p), 1000);
+    nc = std::min<int64_t>(nc, nv);
+    if (nc < q) fail(HSIM_E_INVALID, "coarsest level (%lld) smaller than the subspace size %d", (long long)nc, q);
+    if (!(bo.support_sigma > 0)) fail(HSIM_E_INVALID, "support_sigma must be positive");
+    if (bo.lumping != 0 && bo.lumping != 1) fail(HSIM_E_INVALID, "lumping must be 0 or 1");
+    H->p = p;
+    H->q = q;
+    H->T = T;
+    H->ld = (int32_t)round_up(q, 8);
+    H->area = surface_area(m);
+    std::vector<int64_t> sizes = level_sizes(nv, T, nc, bo.growth_mode);
+    for (int t = 1; t < T; ++t)
+        if (sizes[t] >= sizes[t - 1]) fail(HSIM_E_INVALID, "level %d is not smaller than level %d (too many levels for this mesh)", t, t - 1);
+    std::vector<int32_t> order = farthest_point_sampling(g, nv, sizes[1], bo.seed);
+    // levels
+    for (int t = 0; t < T; ++t) {
+        auto L = std::make_unique<Level>();
+        L->tau = t;
+        L->n = sizes[t];
+        L->coarsest = t == T - 1;
+        if (t == 0) {
+            L->verts.resize(nv);
+            std::iota(L->verts.begin(), L->verts.end(), 0);
+        } else {
+            L->verts.assign(order.begin(), order.begin() + sizes[t]);
+        }
+        H->lv.push_back(std::move(L));
+    }
+    {
+        Level& L0 = *H->lv[0];
+        L0.S = cotan_stiffness(m);
+        L0.mdiag = lumped_mass(m, bo.lumping, density);
+        L0.Mval.assign(L0.S.nnz(), 0.0);
+        for (int64_t i = 0; i < nv; ++i)
+            for (int64_t e = L0.S.ptr[i]; e < L0.S.ptr[i + 1]; ++e)
+                if (L0.S.idx[e] == i) L0.Mval[e] = L0.mdiag[i];
+    }
+    for (int t = 0; t + 1 < T; ++t) {
+        Level& L = *H->lv[t];
+        Level& C = *H->lv[t + 1];
+        L.U = prolongation(g, nv, L.verts, t == 0, C.verts, bo.support_sigma, H->area, &L.rho);
+        galerkin(L.U, L.S, L.Mval, C.S, C.Mval);
+    }
+    for (int t = 0; t + 1 < T; ++t) {
+        Level& L = *H->lv[t];
+        std::vector<double> X(3 * L.n);
+        for (int64_t i = 0; i < L.n; ++i)
+            for (int c = 0; c < 3; ++c) X[3 * i + c] = m.V[3 * (int64_t)L.verts[i] + c];
+        L.sy = analyse(L.S, X.data(), L.n);
+    }
+    // device
+    for (int t = H->host_only ? -1 : T - 1; t >= 0; --t) {
+        Level& L = *H->lv[t];
+        const std::vector<int32_t>* ci = nullptr;
+        std::vector<int32_t> ident;
+        if (t + 1 < T) {
+            Level& C = *H->lv[t + 1];
+            if (C.coarsest) {
+                ident.resize(C.n);
+                std::iota(ident.begin(), ident.end(), 0);
+                ci = &ident;
+            } else {
+                ci = &C.sy.iperm;
+            }
+        }
+        build_device_level(H.get(), L, ci);
+    }
+    if (!H->host_only) {
+        alloc_workspace(H.get());
+        HIPCHECK(hipDeviceSynchronize());
+    }
+    H->ms_build = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = H.release();
+    API_END
+}
+
+hsim_status hsim_hierarchy_shape(const hsim_hierarchy* h, int32_t* levels, int32_t* q, int32_t* p) {
+    API_BEGIN
+    if (!h) fail(HSIM_E_INVALID, "null hierarchy");
+    if (levels) *levels = h->T;
+    if (q) *q = h->q;
+    if (p) *p = h->p;
+    API_END
+}
+
+hsim_status hsim_level_info(const hsim_hierarchy* h, int32_t level, hsim_level_desc* info) {
+    API_BEGIN
+    if (!h || !info) fail(HSIM_E_INVALID, "null argument");
+    if (level < 0 || level >= h->T) fail(HSIM_E_INVALID, "level out of range");
+    const Level& L = *h->lv[level];
+    std::memset(info, 0, sizeof *info);
+    info->n = L.n;
+    info->nnz = L.S.nnz();
+    info->nnz_u = L.coarsest ? 0 : L.U.nnz();
+    info->fronts = L.coarsest ? 0 : (int64_t)L.sy.fronts.size();
+    info->tree_levels = L.coarsest ? 0 : L.sy.tree_levels;
+    info->factor_entries = L.coarsest ? 0 : L.sy.tile_doubles;
+    info->rho = L.rho;
+    info->factor_flops = L.coarsest ? 0 : L.sy.flops;
+    API_END
+}
+
+hsim_status hsim_level_export(const hsim_hierarchy* h, int32_t level, int64_t* verts, int64_t* S_indptr,
+                              int32_t* S_indices, double* S_data, double* M_data, int64_t* U_indptr,
+                              int32_t* U_indices, double* U_data, int32_t* perm) {
+    API_BEGIN
+    if (!h) fail(HSIM_E_INVALID, "null hierarchy");
+    if (level < 0 || level >= h->T) fail(HSIM_E_INVALID, "level out of range");
+    const Level& L = *h->lv[level];
+    if (verts) for (int64_t i = 0; i < L.n; ++i) verts[i] = L.verts[i];
+    if (S_indptr) std::copy(L.S.ptr.begin(), L.S.ptr.end(), S_indptr);
+    if (S_indices) std::copy(L.S.idx.begin(), L.S.idx.end(), S_indices);
+    if (S_data) std::copy(L.S.val.begin(), L.S.val.end(), S_data);
+    if (M_data) std::copy(L.Mval.begin(), L.Mval.end(), M_data);
+    if (!L.coarsest) {
+        if (U_indptr) std::copy(L.U.ptr.begin(), L.U.ptr.end(), U_indptr);
+        if (U_indices) std::copy(L.U.idx.begin(), L.U.idx.end(), U_indices);
+        if (U_data) std::copy(L.U.val.begin(), L.U.val.end(), U_data);
+        if (perm) std::copy(L.sy.perm.begin(), L.sy.perm.end(), perm);
+    } else if (perm) {
+        for (int64_t i = 0; i < L.n; ++i) perm[i] = (int32_t)i;
+    }
+    API_END
+}
+
+// ---------------------------------------------------------------- steps
+static hipStream_t S_(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+hsim_status hsim_step_prolong(hsim_hierarchy* h, int32_t level, int32_t k, const double* d_coarse, double* d_fine,
+                              void* stream) {
+    API_BEGIN
+    Level& L = level_at(h, level);
+    if (L.coarsest) fail(HSIM_E_INVALID, "the coarsest level has no prolongation");
+    if (k < 1 || k > h->ld) fail(HSIM_E_INVALID, "k must be in [1, %d]", h->ld);
+    if (!d_coarse || !d_fine) fail(HSIM_E_INVALID, "null argument");
+    hipStream_t s = S_(stream);
+    Level& C = *h->lv[level + 1];
+    HIPCHECK(launch_gather_rows(d_coarse, k, dptr<int32_t>(C.dperm), C.n, k, dptr<double>(h->Xc), h->ld, s));
+    prolong_level(h, L, dptr<double>(h->Xc), dptr<double>(h->Psi), k, s);
+    HIPCHECK(launch_scatter_rows(dptr<double>(h->Psi), h->ld, dptr<int32_t>(L.dperm), L.n, k, d_fine, k, s));
+    API_END
+}
+
+hsim_status hsim_step_apply(hsim_hierarchy* h, int32_t level, int32_t op, int32_t k, const double* d_X, double* d_Y,
+                            void* stream) {
+    API_BEGIN
+    Level& L = level_at(h, level);
+    if (k < 1 || k > h->ld) fail(HSIM_E_INVALID, "k must be in [1, %d]", h->ld);
+    if (op < 0 || op > 2) fail(HSIM_E_INVALID, "op must be 0, 1 or 2");
+    if (op == 2 && !L.factored) fail(HSIM_E_STATE, "op 2 needs a factorisation of this level (for its shift)");
+    if (!d_X || !d_Y) fail(HSIM_E_INVALID, "null argument");
+    hipStream_t s = S_(stream);
+    HIPCHECK(launch_gather_rows(d_X, k, dptr<int32_t>(L.dperm), L.n, k, dptr<double>(h->Xc), h->ld, s));
+    apply_level(h, L, op, dptr<double>(h->Xc), dptr<double>(h->Psi), k, s);
+    HIPCHECK(launch_scatter_rows(dptr<double>(h->Psi), h->ld, dptr<int32_t>(L.dperm), L.n, k, d_Y, k, s));
+    API_END
+}
+
+hsim_status hsim_step_factor(hsim_hierarchy* h, int32_t level, double mu, int32_t precision, int32_t* neg_pivots,
+                             void* stream) {
+    API_BEGIN
+    Level& L = level_at(h, level);
+    if (L.coarsest) fail(HSIM_E_INVALID, "the coarsest level is solved densely");
+    if (!std::isfinite(mu)) fail(HSIM_E_INVALID, "mu must be finite");
+    (void)precision;
+    factor_level(h, L, mu, S_(stream));
+    if (neg_pivots) *neg_pivots = L.neg_pivots;
+    API_END
+}
+
+hsim_status hsim_step_solve(hsim_hierarchy* h, int32_t level, int32_t k, const double* d_B, double* d_X,
+                            int32_t precision, double refine_tol, void* stream) {
+    API_BEGIN
+    Level& L = level_at(h, level);
+    if (L.coarsest) fail(HSIM_E_INVALID, "the coarsest level is solved densely");
+    if (!L.factored) fail(HSIM_E_STATE, "hsim_step_solve before hsim_step_factor on level %d", level);
+    if (k < 1 || k > h->ld) fail(HSIM_E_INVALID, "k must be in [1, %d]", h->ld);
+    if (!d_B || !d_X) fail(HSIM_E_INVALID, "null argument");
+    (void)precision;
+    (void)refine_tol;
+    hipStream_t s = S_(stream);
+    HIPCHECK(launch_gather_rows(d_B, k, dptr<int32_t>(L.dperm), L.n, k, dptr<double>(h->Xc), h->ld, s));
+    solve_level(h, L, dptr<double>(h->Xc), 0, k, false, s);
+    HIPCHECK(launch_scatter_rows(dptr<double>(h->Xc), h->ld, dptr<int32_t>(L.dperm), L.n, k, d_X, k, s));
+    API_END
+}
+
+hsim_status hsim_step_gram(hsim_hierarchy* h, int32_t level, int32_t k, const double* d_Psi, double* d_Sbar,
+                           double* d_Mbar, int32_t precision, void* stream) {
+    API_BEGIN
+    Level& L = level_at(h, level);
+    if (k < 1 || k > h->q) fail(HSIM_E_INVALID, "k must be in [1, %d]", h->q);
+    if (!d_Psi || !d_Sbar || !d_Mbar) fail(HSIM_E_INVALID, "null argument");
+    (void)precision;
+    hipStream_t s = S_(stream);
+    HIPCHECK(launch_gather_rows(d_Psi, k, dptr<int32_t>(L.dperm), L.n, k, dptr<double>(h->Psi), h->ld, s));
+    apply_level(h, L, 0, dptr<double>(h->Psi), dptr<double>(h->SPsi), k, s);
+    const bool fin = L.tau == 0;
+    if (!fin) apply_level(h, L, 1, dptr<double>(h->Psi), dptr<double>(h->MPsi), k, s);
+    HIPCHECK(launch_gram(dptr<double>(h->Psi), dptr<double>(h->SPsi), fin ? nullptr : dptr<double>(h->MPsi),
+                         fin ? dptr<double>(L.dmdiag) : nullptr, L.n, k, h->ld, dptr<double>(h->gram_part), 4096, d_Sbar,
+                         d_Mbar, s));
+    API_END
+}
+
+hsim_status hsim_step_rr(int32_t k, const double* d_Sbar, const double* d_Mbar, double* d_lam, double* d_Phibar,
+                         int32_t* sweeps, void* stream) {
+    API_BEGIN
+    if (k < 1) fail(HSIM_E_INVALID, "k must be >= 1");
+    if (!d_Sbar || !d_Mbar || !d_lam || !d_Phibar) fail(HSIM_E_INVALID, "null argument");
+    static thread_local std::unique_ptr<DenseGEP> g;
+    if (!g) g.reset(new DenseGEP());
+    g->setup(k);
+    int32_t sw = g->run(d_Sbar, d_Mbar, k, d_lam, d_Phibar, k, S_(stream));
+    if (sweeps) *sweeps = sw;
+    API_END
+}
+
+hsim_status hsim_step_ritz(hsim_hierarchy* h, int32_t level, int32_t k, const double* d_Psi, const double* d_Phibar,
+                           const double* d_lam, double lam_floor, double* d_Phi, double* d_resid, void* stream) {
+    API_BEGIN
+    Level& L = level_at(h, level);
+    if (k < 1 || k > h->q) fail(HSIM_E_INVALID, "k must be in [1, %d]", h->q);
+    if (!d_Psi || !d_Phibar || !d_lam || !d_Phi || !d_resid) fail(HSIM_E_INVALID, "null argument");
+    hipStream_t s = S_(stream);
+    const bool fin = L.tau == 0;
+    HIPCHECK(launch_gather_rows(d_Psi, k, dptr<int32_t>(L.dperm), L.n, k, dptr<double>(h->Psi), h->ld, s));
+    apply_level(h, L, 0, dptr<double>(h->Psi), dptr<double>(h->SPsi), k, s);
+    if (!fin) apply_level(h, L, 1, dptr<double>(h->Psi), dptr<double>(h->MPsi), k, s);
+    HIPCHECK(launch_ritz(dptr<double>(h->Psi), dptr<double>(h->SPsi), fin ? nullptr : dptr<double>(h->MPsi),
+                         fin ? dptr<double>(L.dmdiag) : nullptr, d_Phibar, d_lam, L.n, k, h->ld, dptr<double>(h->Phi),
+                         nullptr, dptr<double>(h->ritz_part), 4096, fin, lam_floor, d_resid, s));
+    HIPCHECK(launch_scatter_rows(dptr<double>(h->Phi), h->ld, dptr<int32_t>(L.dperm), L.n, k, d_Phi, k, s));
+    API_END
+}
+
+static void coarse_solve(hsim_hierarchy* h, int32_t k, double* d_lam, double* d_Phi, int64_t ldphi, int32_t* sweeps,
+                         hipStream_t s) {
+    Level& C = *h->lv.back();
+    const int64_t nc = C.n;
+    HIPCHECK(launch_densify(dptr<int64_t>(C.dS_ptr), dptr<int32_t>(C.dS_idx), dptr<double>(C.dS_val), nc,
+                            dptr<double>(h->coarseS), s));
+    HIPCHECK(launch_densify(dptr<int64_t>(C.dS_ptr), dptr<int32_t>(C.dS_idx), dptr<double>(C.dM_val), nc,
+                            dptr<double>(h->coarseM), s));
+    h->coarse.setup((int32_t)nc);
+    int32_t sw = h->coarse.run(dptr<double>(h->coarseS), dptr<double>(h->coarseM), k, d_lam, d_Phi, ldphi, s);
+    if (sweeps) *sweeps = sw;
+}
+
+hsim_status hsim_step_coarse(hsim_hierarchy* h, int32_t k, double* d_lam, double* d_Phi, int32_t* sweeps,
+                             void* stream) {
+    API_BEGIN
+    if (!h || !d_lam || !d_Phi) fail(HSIM_E_INVALID, "null argument");
+    if (h->host_only) fail(HSIM_E_STATE, "hierarchy was built host-only");
+    if (k < 1 || k > h->lv.back()->n) fail(HSIM_E_INVALID, "k out of range");
+    coarse_solve(h, k, d_lam, d_Phi, k, sweeps, S_(stream));
+    API_END
+}
+
+// ---------------------------------------------------------------- solve
+hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d_evals, double* d_evecs,
+                       double* d_resid, hsim_stats* stats) {
+    API_BEGIN
+    if (!h || !d_evals || !d_evecs) fail(HSIM_E_INVALID, "null argument");
+    if (h->host_only) fail(HSIM_E_STATE, "hierarchy was built host-only");
+    hsim_solve_opts so;
+    if (opts) so = *opts;
+    else hsim_default_solve_opts(&so);
+    if (!(so.tol > 0)) fail(HSIM_E_INVALID, "tol must be positive");
+    if (so.max_iters < 1) fail(HSIM_E_INVALID, "max_iters must be >= 1");
+    if (so.precision != HSIM_FP64 && so.precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
+    hipStream_t s = S_(so.stream);
+    const auto T0 = std::chrono::steady_clock::now();
+    hsim_stats st;
+    std::memset(&st, 0, sizeof st);
+    st.levels = h->T;
+    st.q = h->q;
+    st.ms_build = h->ms_build;
+    const int32_t q = h->q, p = h->p, T = h->T;
+    h->solved = false;
+    // coarsest level: dense solve, Phi in the coarsest level's order (= its internal order)
+    std::vector<double> lam(q), res(q);
+    {
+        auto t0 = std::chrono::steady_clock::now();
+        coarse_solve(h, q, dptr<double>(h->lam), dptr<double>(h->Phi), h->ld, nullptr, s);
+        HIPCHECK(hipMemcpyAsync(lam.data(), h->lam.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        st.ms_coarse = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        st.n[0] = h->lv.back()->n;
+        st.iters[0] = 0;
+    }
+    hsim_status final_status = HSIM_OK;
+    for (int32_t tau = T - 2; tau >= 0; --tau) {
+        Level& L = *h->lv[tau];
+        const int li = T - 1 - tau;   // stats index, coarsest first
+        st.n[li] = L.n;
+        st.nnz_factor[li] = L.sy.tile_doubles;
+        // prolongation
+        auto t0 = std::chrono::steady_clock::now();
+        HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, h->lv[tau + 1]->n, q, dptr<double>(h->Xc), h->ld, s));
+        prolong_level(h, L, dptr<double>(h->Xc), dptr<double>(h->Phi), q, s);
+        HIPCHECK(hipStreamSynchronize(s));
+        auto t1 = std::chrono::steady_clock::now();
+        st.ms_prolong += std::chrono::duration<double, std::milli>(t1 - t0).count();
+        // shift and factorisation (re-shift on breakdown)
+        double mu = choose_shift(lam, p, so.shift_alpha);
+        const int32_t j = (int32_t)std::floor(so.shift_alpha * p + 1e-12);
+        for (int attempt = 0;; ++attempt) {
+            try {
+                factor_level(h, L, mu, s);
+                break;
+            } catch (const Error& e) {
+                if (e.code != HSIM_E_FACTOR || attempt >= 3) throw;
+                const int32_t jj = std::min<int32_t>(j + 1, q - 1);
+                mu += 0.25 * std::max(lam[jj] - lam[std::min<int32_t>(j, q - 1)], 1e-6 * std::fabs(lam[jj]));
+            }
+        }
+        st.mu[li] = mu;
+        st.neg_pivots[li] = L.neg_pivots;
+        auto t2 = std::chrono::steady_clock::now();
+        st.ms_factor += std::chrono::duration<double, std::milli>(t2 - t1).count();
+        // subspace iterations
+        int32_t locked = 0, it = 0;
+        bool conv = false;
+        for (it = 1; it <= so.max_iters; ++it) {
+            auto a0 = std::chrono::steady_clock::now();
+            HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, L.n, q, dptr<double>(h->Psi), h->ld, s));
+            const int32_t act = q - locked;
+            if (act > 0) {
+                for (int rep = 0; rep < 2; ++rep) {
+                    if (tau == 0) {
+                        solve_level(h, L, dptr<double>(h->Psi), locked, act, true, s);
+                    } else {
+                        HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), dptr<double>(L.dM_val),
+                                             nullptr, 1.0, 0.0, L.n, dptr<double>(h->Psi) + locked, h->ld, act,
+                                             dptr<double>(h->Btmp) + locked, h->ld, s));
+                        solve_level(h, L, dptr<double>(h->Btmp), locked, act, false, s);
+                        HIPCHECK(launch_copy2d(dptr<double>(h->Btmp) + locked, h->ld, L.n, act,
+                                               dptr<double>(h->Psi) + locked, h->ld, s));
+                    }
+                }
+            }
+            HIPCHECK(hipStreamSynchronize(s));
+            st.ms_solve += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a0).count();
+            rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz);
+            conv = true;
+            for (int32_t i = 0; i < p; ++i) conv &= res[i] < so.tol;
+            if (conv) break;
+            if (!(so.flags & HSIM_FLAG_NOLOCK)) {
+                int32_t r = 0;
+                while (r < q && res[r] < so.tol / 10.0) ++r;
+                locked = std::min(r, p);
+            }
+        }
+        st.iters[li] = std::min(it, so.max_iters);
+        if (!conv) final_status = HSIM_E_NOCONV;
+    }
+    // outputs: first p pairs of level 0
+    Level& L0 = *h->lv[0];
+    HIPCHECK(hipMemcpyAsync(d_evals, h->lam.p, p * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (d_resid) HIPCHECK(hipMemcpyAsync(d_resid, h->resid.p, p * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHECK(launch_export_evecs(dptr<double>(h->Phi), h->ld, L0.n, p, dptr<int32_t>(L0.dperm), d_evecs,
+                                 dptr<double>(h->exportw), s));
+    HIPCHECK(hipStreamSynchronize(s));
+    h->last_lam = lam;
+    h->solved = true;
+    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();
+    if (stats) *stats = st;
+    if (final_status != HSIM_OK) {
+        set_last_error("subspace iterations did not converge within max_iters");
+        return final_status;
+    }
+    API_END
+}
+
+hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, const double* d_grad_evecs,
+                                double* d_grad_V, void* stream) {
+    API_BEGIN
+    if (!h || !d_grad_V) fail(HSIM_E_INVALID, "null argument");
+    if (!h->solved) fail(HSIM_E_STATE, "hsim_solve_backward before a successful hsim_solve");
+    (void)d_grad_evals;
+    (void)d_grad_evecs;
+    (void)stream;
+    fail(HSIM_E_UNIMPLEMENTED, "backward not implemented yet");
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Host-callable launchers of the HIP kernels (gfx950).  Every launcher
+// enqueues on `stream` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hsim {
+
+// Device copy of a front's geometry (see Front in internal.h).
+struct DFront {
+    int64_t start, tile_base, linv_base, d_base, ubuf_row, gather_base, rows_off;
+    int32_t ns, mu, ns_pad, mu_pad, Mt, nsb, parent, pad_;
+};
+
+// ------------------------------------------------------------ utilities
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_f(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_to_float(const double* src, float* dst, int64_t n, hipStream_t s);
+// out[i, :k] = in[idx[i], :k] (rows, with leading dims)
+hipError_t launch_gather_rows(const double* in, int64_t ldi, const int32_t* idx, int64_t n, int32_t k,
+                              double* out, int64_t ldo, hipStream_t s);
+// out[idx[i], :k] = in[i, :k]
+hipError_t launch_scatter_rows(const double* in, int64_t ldi, const int32_t* idx, int64_t n, int32_t k,
+                               double* out, int64_t ldo, hipStream_t s);
+hipError_t launch_copy2d(const double* in, int64_t ldi, int64_t rows, int32_t k, double* out, int64_t ldo,
+                         hipStream_t s);
+
+// ------------------------------------------------------------ sparse products
+// Y[r, c] = sum_e (a * va[e] + b * vb[e]) X[idx[e], c], c < k (vb may be null)
+hipError_t launch_spmm(const int64_t* ptr, const int32_t* idx, const double* va, const double* vb, double a,
+                       double b, int64_t rows, const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy,
+                       hipStream_t s);
+// Y[r, c] = d[r] X[r, c]
+hipError_t launch_diag_scale(const double* d, int64_t rows, const double* X, int64_t ldx, int32_t k, double* Y,
+                             int64_t ldy, hipStream_t s);
+// Y = X - Y (elementwise on the first k columns): residual helpers
+hipError_t launch_axpby(double a, const double* X, int64_t ldx, double b, double* Y, int64_t ldy, int64_t rows,
+                        int32_t k, hipStream_t s);
+
+// ------------------------------------------------------------ factor
+hipError_t launch_assemble(double* tiles, const int64_t* dst, const int64_t* src, int64_t count,
+                           const double* Sval, const double* Mval, double alpha, double beta, hipStream_t s);
+hipError_t launch_extend_add(double* tiles, const DFront* fronts, const int32_t* items, int64_t nitems,
+                             const int32_t* rel, int32_t max_tile_cols, hipStream_t s);
+hipError_t launch_fac_diag(double* tiles, double* linv, double* D, const DFront* fronts, const int32_t* items,
+                           int64_t nitems, int32_t k, int32_t* counters, hipStream_t s);
+hipError_t launch_fac_panel(double* tiles, const double* linv, const double* D, const DFront* fronts,
+                            const int32_t* items, int64_t nitems, int32_t k, hipStream_t s);
+hipError_t launch_fac_update(double* tiles, const double* D, const DFront* fronts, const int32_t* items,
+                             int64_t nitems, int32_t k, hipStream_t s);
+
+// ------------------------------------------------------------ block solves
+// Forward L^-1 (and optional diagonal pre-scaling by mdiag) over the fronts
+// [f0, f1) of one tree level, columns [col0, col0 + ncols) in chunks of qc.
+template <class TF>
+hipError_t launch_solve_fwd(const TF* tiles, const TF* linv, const DFront* fronts, int32_t f0, int32_t f1,
+                            int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols, int32_t qc,
+                            double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx,
+                            const double* mdiag, hipStream_t s);
+template <class TF>
+hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
+                            int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
+                            int32_t qc, const int32_t* rows, bool apply_dinv, hipStream_t s);
+
+// ------------------------------------------------------------ Rayleigh-Ritz
+// partial Grams over row chunks (pairs of 32-column tiles, upper), then the sum
+hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
+                       int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
+                       hipStream_t s);
+int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows);
+
+// Phi = Psi Phibar and residual partial sums; then the residual
+hipError_t launch_ritz(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag,
+                       const double* Phibar, const double* lam, int64_t n, int32_t q, int64_t ld, double* Phi,
+                       double* MPhi, double* partial, int64_t chunk_rows, bool minv_norm, double lam_floor,
+                       double* resid, hipStream_t s);
+int64_t ritz_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows);
+
+// ------------------------------------------------------------ dense GEP helpers
+// E = diag(M)^-1/2; S' = E S E, M' = E M E (k x k row-major, in place into So/Mo)
+hipError_t launch_equilibrate(const double* S, const double* M, int32_t k, double* So, double* Mo, double* e,
+                              hipStream_t s);
+// copy the lower triangle of the k x k row-major A into one dense front (tile
+// storage, Mt tiles per side); dummy pivots beyond k get 1 on the diagonal
+hipError_t launch_dense_to_front(const double* A, int32_t k, double* tiles, int32_t Mt, hipStream_t s);
+// B = A^T (k x k, row-major, ld = k)
+hipError_t launch_transpose(const double* A, int32_t k, double* B, hipStream_t s);
+// C[i, j] = 0.5 (A[i,j] + A[j,i]) * w[i] * w[j] with w = D^-1/2 (k x k)
+hipError_t launch_sym_scale(const double* A, const double* D, int32_t k, double* C, hipStream_t s);
+// Jacobi: init next-round diagonal/partner arrays from C (m x m, m even)
+hipError_t launch_jacobi_init(const double* C, int32_t m, double* V, double* diag, double* off, hipStream_t s);
+// threshold for a rotation: |c_pq| > max(tol_abs_rel * normf[0], tol_rel * sqrt(|c_pp c_qq|))
+hipError_t launch_jacobi_round(double* C, double* V, int32_t m, int32_t round, const double* diag_cur,
+                               const double* off_cur, double* diag_next, double* off_next, double tol_rel,
+                               const double* normf, double tol_abs_rel, int32_t* rot_count, hipStream_t s);
+// C (m x m) = Ck (k x k) plus a decoupled dummy (m = k + 1), normf = ||Ck||_F, dis = D^-1/2
+hipError_t launch_embed_pad(const double* Ck, int32_t k, int32_t m, double* C, double* normf, double* dis,
+                            const double* D, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// A (n x n row-major) = dense copy of a CSR matrix
+hipError_t launch_densify(const int64_t* ptr, const int32_t* idx, const double* val, int64_t n, double* A,
+                          hipStream_t s);
+// sort eigenvalues ascending (first k of m), gather the eigenvector columns
+// X[r, j] = scale[r] * Y[r, order[j]] and lam_out[j]; Y m x m row-major
+hipError_t launch_sort_eig(const double* C, int32_t m, int32_t kvalid, const double* Y, int32_t rows,
+                           const double* scale, int32_t kout, double* lam_out, double* X, int64_t ldx,
+                           hipStream_t s);
+// Y[r, c] = V[r, c] * w[r] (w = D^1/2), for the back transformation
+hipError_t launch_row_scale(const double* V, const double* w, bool sqrt_w, int64_t rows, int32_t k, int64_t ld,
+                            double* Y, hipStream_t s);
+
+// ------------------------------------------------------------ output
+// evecs[c * nv + vertex(r)] = sign_c * Phi[r, c] for c < p, largest-magnitude
+// entry positive (lowest vertex index on ties)
+hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t p, const int32_t* perm,
+                               double* evecs, double* work, hipStream_t s);
+
+}  // namespace hsim

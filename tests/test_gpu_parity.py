@@ -1,0 +1,183 @@
+"""Parity of every step of the GPU hot path with the FP64 oracle.
+
+Each test calls the HIP library through the C ABI (the Python binding only
+marshals arguments) and compares, element by element, with the oracle on the
+same seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import assembly, hierarchy, jacobi, metrics, sim
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small(cuda):
+    import paper_2111_09039_amd as hs
+    rng = np.random.default_rng(5)
+    V, F = synth.icosphere(3)
+    V = synth.radial_jitter(V, 1e-2, rng)
+    S, m = assembly.assemble(V, F)
+    lv = hierarchy.build_hierarchy(V, F, S, m, p=10, levels=3, n_coarsest=120, seed=17)
+    H = hs.Hierarchy(V, F, 10, levels=3, n_coarsest=120, seed=17)
+    print(f"[small hierarchy] sizes {[len(l['verts']) for l in lv]}", flush=True)
+    return V, F, S, m, lv, H
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _mass(lv, tau):
+    M = lv[tau]["M"]
+    return sp.diags(M).tocsr() if tau == 0 else M
+
+
+def test_prolongation(small):
+    V, F, S, m, lv, H = small
+    rng = np.random.default_rng(0)
+    for tau in range(2):
+        nc = len(lv[tau + 1]["verts"])
+        for k in (1, 7, 15):
+            Xc = rng.standard_normal((nc, k))
+            Y = H.prolong(tau, _t(Xc)).cpu().numpy()
+            ref = lv[tau]["U"] @ Xc
+            assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max(), (tau, k)
+
+
+def test_operator_products(small):
+    V, F, S, m, lv, H = small
+    rng = np.random.default_rng(1)
+    for tau in range(3):
+        n = len(lv[tau]["verts"])
+        X = rng.standard_normal((n, 15))
+        for op, A in ((0, lv[tau]["S"]), (1, _mass(lv, tau))):
+            Y = H.apply(tau, op, _t(X)).cpu().numpy()
+            ref = A @ X
+            assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max(), (tau, op)
+
+
+@pytest.mark.parametrize("tau", [0, 1])
+def test_factor_inertia_and_solve(small, tau):
+    V, F, S, m, lv, H = small
+    St, Mt = lv[tau]["S"], _mass(lv, tau)
+    ref = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(Mt.toarray()),
+                                             np.linalg.solve(np.linalg.cholesky(Mt.toarray()), St.toarray()).T))
+    rng = np.random.default_rng(2)
+    n = St.shape[0]
+    for j in (-1, 4, 9):
+        mu = -0.1 * ref[1] if j < 0 else 0.5 * (ref[j] + ref[j + 1])
+        neg = H.factor(tau, mu)
+        assert neg == int(np.sum(ref < mu)), (tau, mu, neg)
+        B = rng.standard_normal((n, 13))
+        X = H.solve_shifted(tau, _t(B)).cpu().numpy()
+        A = (St - mu * Mt).tocsc()
+        Xr = spla.splu(A).solve(B)
+        assert np.abs(X - Xr).max() <= 1e-10 * np.abs(Xr).max(), (tau, mu)
+        # normwise backward error per column (infinity norms)
+        Ainf = np.abs(A).sum(axis=1).max()
+        bw = (np.abs(A @ X - B).max(axis=0) / (Ainf * np.abs(X).max(axis=0) + np.abs(B).max(axis=0))).max()
+        assert bw < 1e-14, bw
+
+
+def test_gram(small):
+    V, F, S, m, lv, H = small
+    rng = np.random.default_rng(3)
+    for tau in range(3):
+        n = len(lv[tau]["verts"])
+        for k in (5, 30, 33):
+            Psi = rng.standard_normal((n, k))
+            Sb, Mb = H.gram(tau, _t(Psi))
+            Sr = Psi.T @ (lv[tau]["S"] @ Psi)
+            Mr = Psi.T @ (_mass(lv, tau) @ Psi)
+            assert np.abs(Sb.cpu().numpy() - Sr).max() <= 1e-13 * np.abs(Sr).max()
+            assert np.abs(Mb.cpu().numpy() - Mr).max() <= 1e-13 * np.abs(Mr).max()
+
+
+@pytest.mark.parametrize("k", [2, 17, 30, 64])
+def test_reduced_eigenproblem(cuda, k):
+    import paper_2111_09039_amd as hs
+    rng = np.random.default_rng(k)
+    B = rng.standard_normal((k, k))
+    Mb = B @ B.T / k + np.diag(rng.uniform(0.5, 2.0, k))
+    Q, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    Sb = Q @ np.diag(np.sort(rng.uniform(0, 100, k))) @ Q.T
+    lam, Pb, sweeps = hs.rayleigh_ritz_dense(_t(Sb), _t(Mb))
+    lam, Pb = lam.cpu().numpy(), Pb.cpu().numpy()
+    lr, Xr = jacobi.jacobi_gep(Sb, Mb)
+    assert np.abs(lam - lr).max() <= 1e-12 * np.abs(lr).max()
+    assert np.abs(Pb.T @ Mb @ Pb - np.eye(k)).max() < 1e-12
+    assert np.abs(Sb @ Pb - Mb @ Pb * lam[None, :]).max() < 1e-11 * np.abs(lr).max()
+    # distinct eigenvalues: vectors equal up to sign
+    s = np.sign(np.sum(Pb * Xr, axis=0))
+    assert np.abs(Pb - Xr * s[None, :]).max() < 1e-9
+
+
+def test_coarsest_dense_solve(small):
+    V, F, S, m, lv, H = small
+    k = H.q
+    lam, X, sweeps = H.coarse(k)
+    lam, X = lam.cpu().numpy(), X.cpu().numpy()
+    lr, Xr = jacobi.jacobi_gep(lv[2]["S"].toarray(), lv[2]["M"].toarray())
+    assert np.abs(lam - lr[:k]).max() <= 1e-12 * lr[k - 1]
+    Mc = lv[2]["M"].toarray()
+    assert np.abs(X.T @ Mc @ X - np.eye(k)).max() < 1e-11
+    err = metrics.eigenvector_err(X, Xr, Mc, lr)
+    assert err[1:].max() < 1e-8
+
+
+def test_ritz_update_and_residual(small):
+    V, F, S, m, lv, H = small
+    rng = np.random.default_rng(4)
+    for tau in range(3):
+        n = len(lv[tau]["verts"])
+        k = 15
+        Psi = rng.standard_normal((n, k))
+        Pb = rng.standard_normal((k, k))
+        lam = np.sort(rng.uniform(0.5, 20, k))
+        Phi, r = H.ritz(tau, _t(Psi), _t(Pb), _t(lam), 0.5)
+        Phi, r = Phi.cpu().numpy(), r.cpu().numpy()
+        ref = Psi @ Pb
+        assert np.abs(Phi - ref).max() <= 1e-13 * np.abs(ref).max()
+        rr = sim.residual(lv[tau]["S"], lv[tau]["M"] if tau == 0 else _mass(lv, tau), ref, lam, lam_c=0.5,
+                          norm="minv" if tau == 0 else "l2")
+        assert np.abs(r - rr).max() <= 1e-12 * np.abs(rr).max()
+
+
+@pytest.mark.parametrize("case", ["sphere2k", "torus"])
+def test_hsim_end_to_end(cuda, case):
+    import paper_2111_09039_amd as hs
+    if case == "sphere2k":
+        V, F, d = synth.config_mesh("sphere2k", seed=0)
+        p, T, nc = 20, 3, 300
+    else:
+        rng = np.random.default_rng(11)
+        V, F = synth.torus(60, 30)
+        V = synth.isotropic_noise(V, F, 0.2 * synth.mean_edge_length(V, F), rng)
+        d = synth.random_density(len(V), rng)
+        p, T, nc = 24, 3, 200
+    print(f"[end-to-end {case}] n={len(V)} p={p}", flush=True)
+    S, m = assembly.assemble(V, F, density=d)
+    H = hs.Hierarchy(V, F, p, density=d, levels=T, n_coarsest=nc)
+    ev, X, r, st = H.solve(tol=1e-10)
+    ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
+    lr, Xr, _, _ = sim.sim_lowest(S, m, p + 10, eps=1e-12)
+    rel = np.abs(ev - lr[:p])[1:] / lr[1:p]
+    assert rel.max() <= 1e-9, rel.max()
+    assert abs(ev[0]) <= 1e-10 * lr[1]
+    assert metrics.m_orthonormality(X, m) < 1e-10
+    assert r.max() < 1e-10
+    err = metrics.eigenvector_err(X, Xr, m, lr)
+    assert err.max() < 1e-6, err.max()
+    # host-side residual with the oracle's own assembly
+    rh = sim.residual(S, m, X, ev)
+    assert rh.max() < 2e-10
+    # sign convention: largest-magnitude entry positive
+    idx = np.argmax(np.abs(X), axis=0)
+    assert (X[idx, np.arange(p)] > 0).all()
