@@ -73,7 +73,21 @@ enum { HSIM_FP64 = 0, HSIM_MIXED = 1 };
 /* flags of hsim_solve_opts */
 enum {
     HSIM_FLAG_NOLOCK = 1,        /* disable locking of converged vectors (Section 4.2) */
-    HSIM_FLAG_SAVE_FORWARD = 2   /* keep what hsim_solve_backward needs (set by the autograd wrapper) */
+    HSIM_FLAG_SAVE_FORWARD = 2,  /* keep what hsim_solve_backward needs (set by the autograd wrapper) */
+    HSIM_FLAG_PROFILE = 4        /* time every kernel launch with HIP events (fills k_ms / k_launches) */
+};
+
+/* kernel classes of the profile counters in hsim_stats */
+enum {
+    HSIM_K_SOLVE_FWD = 0,   /* forward block triangular solve, one launch per tree level      */
+    HSIM_K_SOLVE_BWD = 1,   /* backward block triangular solve, one launch per tree level     */
+    HSIM_K_FACTOR = 2,      /* numeric factorisation: assembly, extend-add, tile kernels      */
+    HSIM_K_GRAM = 3,        /* Rayleigh-Ritz Gram products                                    */
+    HSIM_K_RITZ = 4,        /* Ritz update with the fused residual                            */
+    HSIM_K_SPMM = 5,        /* CSR products (S, M, prolongation)                              */
+    HSIM_K_JACOBI = 6,      /* dense eigenproblems (Cholesky, transforms, Jacobi rounds)      */
+    HSIM_K_OTHER = 7,
+    HSIM_KCLASSES = 8
 };
 
 /* Options of hsim_solve (the multilevel iterations of Algorithm 2, Algorithm 1). */
@@ -102,6 +116,14 @@ typedef struct {
     int32_t escalated;                    /* mixed precision: levels that fell back to FP64 solves    */
     double ms_build;                      /* host hierarchy build (from hsim_build_hierarchy)         */
     double ms_coarse, ms_factor, ms_solve, ms_gram, ms_rr, ms_ritz, ms_prolong, ms_total;
+    /* HSIM_FLAG_PROFILE: device time (HIP events around each launch), launch
+     * count, and the algorithmic bytes and flops of those launches (bytes:
+     * each operand counted once per launch; flops: the arithmetic of the
+     * operation, not of the padding) per kernel class */
+    double k_ms[HSIM_KCLASSES];
+    int64_t k_launches[HSIM_KCLASSES];
+    double k_bytes[HSIM_KCLASSES];
+    double k_flops[HSIM_KCLASSES];
 } hsim_stats;
 
 /* Per-level sizes (hsim_level_desc). */
@@ -114,6 +136,7 @@ typedef struct {
     int64_t factor_entries;/* stored factor entries (padded panels)                   */
     double rho;            /* support radius of U^tau (eq. radius); 0 on the coarsest */
     double factor_flops;   /* flops of one numeric factorisation                      */
+    int64_t factor_nnz;    /* nonzeros of L (unpadded supernodal panels, incl. diagonal) */
 } hsim_level_desc;
 
 void hsim_default_build_opts(hsim_build_opts* opts);

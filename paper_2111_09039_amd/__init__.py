@@ -18,7 +18,7 @@ from ._lib import HsimError
 __all__ = ["Hierarchy", "HsimError", "FP64", "MIXED", "build_library"]
 
 FP64, MIXED = 0, 1
-FLAG_NOLOCK, FLAG_SAVE_FORWARD = 1, 2
+FLAG_NOLOCK, FLAG_SAVE_FORWARD, FLAG_PROFILE = 1, 2, 4
 
 
 def build_library(verbose=False):
@@ -95,7 +95,7 @@ class Hierarchy:
 
     # ----------------------------------------------------------- solve
     def solve(self, tol=1e-2, shift_alpha=0.1, precision=FP64, max_iters=100, lock=True, save_forward=False,
-              stream=None, raise_noconv=True):
+              stream=None, raise_noconv=True, profile=False):
         """Returns (evals [p], evecs [nv, p], resid [p], stats dict) with CUDA
         float64 tensors; evecs is the transpose view of a (p, nv) buffer."""
         torch = _torch()
@@ -103,7 +103,8 @@ class Hierarchy:
         o = _lib.SolveOpts()
         lib.hsim_default_solve_opts(C.byref(o))
         o.tol, o.shift_alpha, o.precision, o.max_iters = float(tol), float(shift_alpha), int(precision), int(max_iters)
-        o.flags = (0 if lock else FLAG_NOLOCK) | (FLAG_SAVE_FORWARD if save_forward else 0)
+        o.flags = ((0 if lock else FLAG_NOLOCK) | (FLAG_SAVE_FORWARD if save_forward else 0)
+                   | (FLAG_PROFILE if profile else 0))
         o.stream = _stream_ptr(stream)
         dev = torch.device("cuda", torch.cuda.current_device())
         ev = torch.empty(self.p, dtype=torch.float64, device=dev)

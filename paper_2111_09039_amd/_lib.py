@@ -20,6 +20,7 @@ class SolveOpts(C.Structure):
 
 
 MAX_LEVELS = 8
+KCLASSES = ["solve_fwd", "solve_bwd", "factor", "gram", "ritz", "spmm", "dense_eig", "other"]
 
 
 class Stats(C.Structure):
@@ -29,7 +30,9 @@ class Stats(C.Structure):
                 ("refine_steps", C.c_int32), ("escalated", C.c_int32), ("ms_build", C.c_double),
                 ("ms_coarse", C.c_double), ("ms_factor", C.c_double), ("ms_solve", C.c_double),
                 ("ms_gram", C.c_double), ("ms_rr", C.c_double), ("ms_ritz", C.c_double),
-                ("ms_prolong", C.c_double), ("ms_total", C.c_double)]
+                ("ms_prolong", C.c_double), ("ms_total", C.c_double),
+                ("k_ms", C.c_double * 8), ("k_launches", C.c_int64 * 8), ("k_bytes", C.c_double * 8),
+                ("k_flops", C.c_double * 8)]
 
     def as_dict(self):
         T = self.levels
@@ -38,13 +41,15 @@ class Stats(C.Structure):
                     mu=list(self.mu[:T]), refine_steps=self.refine_steps, escalated=self.escalated,
                     ms_build=self.ms_build, ms_coarse=self.ms_coarse, ms_factor=self.ms_factor,
                     ms_solve=self.ms_solve, ms_gram=self.ms_gram, ms_rr=self.ms_rr, ms_ritz=self.ms_ritz,
-                    ms_prolong=self.ms_prolong, ms_total=self.ms_total)
+                    ms_prolong=self.ms_prolong, ms_total=self.ms_total,
+                    kernels={name: dict(ms=self.k_ms[i], launches=self.k_launches[i], bytes=self.k_bytes[i],
+                                        flops=self.k_flops[i]) for i, name in enumerate(KCLASSES)})
 
 
 class LevelDesc(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("nnz_u", C.c_int64), ("fronts", C.c_int64),
                 ("tree_levels", C.c_int64), ("factor_entries", C.c_int64), ("rho", C.c_double),
-                ("factor_flops", C.c_double)]
+                ("factor_flops", C.c_double), ("factor_nnz", C.c_int64)]
 
 
 STATUS = {0: "HSIM_OK", -1: "HSIM_E_INVALID", -2: "HSIM_E_MESH", -3: "HSIM_E_FACTOR", -4: "HSIM_E_NOCONV",

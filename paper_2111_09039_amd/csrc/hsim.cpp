@@ -61,6 +61,62 @@ static T* dptr(DeviceBuffer& b) { return b.as<T>(); }
 
 static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// ============================================================ profiling
+// HIP events around every launch of a kernel class (only when asked for).
+struct Prof {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int cls;
+        double bytes, flops;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    ~Prof() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            HIPCHECK(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void reset(bool enable) {
+        on = enable;
+        used = 0;
+        recs.clear();
+    }
+    template <class F>
+    void run(int cls, double bytes, double flops, hipStream_t s, F&& f) {
+        if (!on) {
+            f();
+            return;
+        }
+        hipEvent_t a = get(), b = get();
+        HIPCHECK(hipEventRecord(a, s));
+        f();
+        HIPCHECK(hipEventRecord(b, s));
+        recs.push_back({a, b, cls, bytes, flops});
+    }
+    void collect(hsim_stats& st, hipStream_t s) {
+        if (!on) return;
+        HIPCHECK(hipStreamSynchronize(s));
+        for (const Rec& r : recs) {
+            float ms = 0;
+            HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+            st.k_ms[r.cls] += ms;
+            st.k_launches[r.cls] += 1;
+            st.k_bytes[r.cls] += r.bytes;
+            st.k_flops[r.cls] += r.flops;
+        }
+        recs.clear();
+        used = 0;
+    }
+};
+
 // ====================================================== dense eigenproblem
 // First kout eigenpairs of S x = lambda M x for k x k dense symmetric S and SPD M
 // (row-major, device): equilibration E = diag(M)^-1/2, LDL^T of E M E by the
@@ -207,6 +263,7 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
 // ================================================================ levels
 struct TLev {
     int32_t f0 = 0, f1 = 0, ns_pad_max = 0, qc = 1;
+    double l_entries = 0, pivots = 0;    // unpadded L entries and pivot rows of the level's fronts
     int32_t step0 = 0, step1 = 0;
     std::vector<int32_t> ea_tile_cols;   // per child slot: max tile columns of the children's update blocks
 };
@@ -246,9 +303,15 @@ struct hsim_hierarchy {
     hsim::DenseGEP rr, coarse;
     // solve workspace (sized for level 0)
     hsim::DeviceBuffer Phi, Psi, SPsi, MPsi, Btmp, R, Xc, gram_part, ritz_part, Sbar, Mbar, lam, Phibar, resid,
-        coarseS, coarseM, exportw, cPhi, cPhi2;
+        coarseS, coarseM, exportw, cPhi, cPhi2, cn_part, cn_ratio;
+    // adjoint state (allocated by the first hsim_solve_backward)
+    hsim::DeviceBuffer bV, bF, bRho, bIperm, bVtPtr, bVt, bG, bNu, bGbar, bMX, bW, bY, bR, bZ, bP, bQ, bSmall, bPart,
+        bDots;
+    bool bw_ready = false;
+    int32_t cg_iters = 0;
     bool solved = false, host_only = false;
     std::vector<double> last_lam;
+    hsim::Prof prof;
 };
 
 namespace hsim {
@@ -366,7 +429,13 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
         TLev& T = L.tl[t];
         T.f0 = sy.tlev_ptr[t];
         T.f1 = sy.tlev_ptr[t + 1];
-        for (int32_t i = T.f0; i < T.f1; ++i) T.ns_pad_max = std::max(T.ns_pad_max, sy.fronts[i].ns_pad);
+        for (int32_t i = T.f0; i < T.f1; ++i) {
+            const Front& f = sy.fronts[i];
+            T.ns_pad_max = std::max(T.ns_pad_max, f.ns_pad);
+            T.l_entries += (double)f.ns * (f.ns + 1) / 2 + (double)f.ns * f.mu;
+            T.pivots += f.ns;
+        }
+        if ((int64_t)(T.ns_pad_max + NB) * 8 > 64 * 1024) fail(HSIM_E_UNIMPLEMENTED, "supernode wider than the solve kernels support");
         T.qc = 32;
         while (T.qc > 1 && (int64_t)(T.ns_pad_max + NB) * T.qc * 8 > 64 * 1024) T.qc /= 2;
         T.step0 = sy.step_ptr[t];
@@ -379,14 +448,17 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
 }
 
 // ----------------------------------------------------------- factor / solve
-static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s) {
+static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, bool mixed = false) {
     const Symbolic& sy = L.sy;
     const int32_t mc = std::max<int32_t>(1, sy.max_children);
     int32_t* cnt = dptr<int32_t>(L.counters);
     HIPCHECK(launch_fill_i32(cnt, 4, 0, s));
     const DFront* fr = dptr<DFront>(L.dfronts);
     double* tiles = dptr<double>(L.tiles);
+    Prof& P = H->prof;
+    const double lvflops = sy.flops / std::max(1, sy.tree_levels);
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
+      P.run(HSIM_K_FACTOR, 8.0 * L.tl[t].l_entries, lvflops, s, [&] {
         const TLev& T = L.tl[t];
         // zero this tree level's fronts, assemble A = S - mu M, add the children's updates
         const int64_t tb0 = sy.fronts[T.f0].tile_base;
@@ -413,6 +485,7 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s) 
             HIPCHECK(launch_fac_update(tiles, dptr<double>(L.D), fr, dptr<int32_t>(L.it_upd) + 3 * sy.upd_ptr[st],
                                        sy.upd_ptr[st + 1] - sy.upd_ptr[st], k, s));
         }
+      });
     }
     int32_t hc[2] = {0, 0};
     HIPCHECK(hipMemcpyAsync(hc, cnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -422,25 +495,60 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s) 
     L.factored = hc[1] == 0;
     L.factored32 = false;
     if (hc[1] != 0) fail(HSIM_E_FACTOR, "LDL^T of S - mu M (level %d, mu=%g): %d zero or non-finite pivots", L.tau, mu, hc[1]);
-    (void)H;
+    if (mixed) {
+        // FP32 copy of the FP64 factor for the low-precision solves
+        L.tiles32.alloc((size_t)sy.tile_doubles * sizeof(float));
+        L.linv32.alloc((size_t)sy.linv_doubles * sizeof(float));
+        L.D32.alloc((size_t)std::max<int64_t>(1, sy.d_doubles) * sizeof(float));
+        H->prof.run(HSIM_K_OTHER, 12.0 * (sy.tile_doubles + sy.linv_doubles), 0.0, s, [&] {
+            HIPCHECK(launch_to_float(dptr<double>(L.tiles), dptr<float>(L.tiles32), sy.tile_doubles, s));
+            HIPCHECK(launch_to_float(dptr<double>(L.linv), dptr<float>(L.linv32), sy.linv_doubles, s));
+            HIPCHECK(launch_to_float(dptr<double>(L.D), dptr<float>(L.D32), sy.d_doubles, s));
+        });
+        L.factored32 = true;
+    }
 }
 
-// X (internal order, leading dim ld) <- (S - mu M)^-1 (mdiag ? m*X : X) on columns [col0, col0 + ncols)
-static void solve_level(hsim_hierarchy* H, Level& L, double* X, int32_t col0, int32_t ncols, bool scale_by_m,
-                        hipStream_t s) {
+// X (internal order, leading dim ld) <- (S - mu M)^-1 (mdiag ? m*X : X) on columns [col0, col0 + ncols);
+// fp32: with the FP32 copy of the factor (FP32 arithmetic, FP64 in and out)
+template <class TF>
+static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF* linv, const TF* D, double* X,
+                         int32_t col0, int32_t ncols, const double* md, hipStream_t s) {
     const Symbolic& sy = L.sy;
     const DFront* fr = dptr<DFront>(L.dfronts);
-    const double* md = scale_by_m ? dptr<double>(L.dmdiag) : nullptr;
+    Prof& P = H->prof;
+    const double bL = sizeof(TF);
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
         const TLev& T = L.tl[t];
-        HIPCHECK(launch_solve_fwd<double>(dptr<double>(L.tiles), dptr<double>(L.linv), fr, T.f0, T.f1, T.ns_pad_max, X,
-                                          H->ld, col0, ncols, T.qc, dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr),
-                                          dptr<int64_t>(L.gidx), md, s));
+        const double bytes = bL * T.l_entries + 2.0 * 8.0 * T.pivots * ncols;
+        const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
+        P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
+            HIPCHECK(launch_solve_fwd<TF>(tiles, linv, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols, T.qc,
+                                          dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr), dptr<int64_t>(L.gidx), md,
+                                          s));
+        });
     }
     for (int32_t t = sy.tree_levels - 1; t >= 0; --t) {
         const TLev& T = L.tl[t];
-        HIPCHECK(launch_solve_bwd<double>(dptr<double>(L.tiles), dptr<double>(L.linv), dptr<double>(L.D), fr, T.f0, T.f1,
-                                          T.ns_pad_max, X, H->ld, col0, ncols, T.qc, dptr<int32_t>(L.rows), true, s));
+        const double bytes = bL * T.l_entries + 2.0 * 8.0 * T.pivots * ncols;
+        const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
+        P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
+            HIPCHECK(launch_solve_bwd<TF>(tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols, T.qc,
+                                          dptr<int32_t>(L.rows), true, s));
+        });
+    }
+}
+
+static void solve_level(hsim_hierarchy* H, Level& L, double* X, int32_t col0, int32_t ncols, bool scale_by_m,
+                        hipStream_t s, bool fp32 = false) {
+    const double* md = scale_by_m ? dptr<double>(L.dmdiag) : nullptr;
+    if (fp32) {
+        if (!L.factored32) fail(HSIM_E_STATE, "no FP32 factor on level %d", L.tau);
+        solve_sweeps<float>(H, L, dptr<float>(L.tiles32), dptr<float>(L.linv32), dptr<float>(L.D32), X, col0, ncols, md,
+                            s);
+    } else {
+        solve_sweeps<double>(H, L, dptr<double>(L.tiles), dptr<double>(L.linv), dptr<double>(L.D), X, col0, ncols, md,
+                             s);
     }
 }
 
@@ -452,13 +560,62 @@ static void apply_level(hsim_hierarchy* H, Level& L, int op, const double* X, do
     }
     const double* va = op == 1 ? dptr<double>(L.dM_val) : dptr<double>(L.dS_val);
     const double* vb = op == 2 ? dptr<double>(L.dM_val) : nullptr;
-    HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), va, vb, 1.0, op == 2 ? -L.mu : 0.0, L.n, X,
-                         H->ld, k, Y, H->ld, s));
+    const double nnz = (double)L.S.nnz();
+    H->prof.run(HSIM_K_SPMM, nnz * (op == 2 ? 20.0 : 12.0) + 16.0 * L.n * k, 2.0 * nnz * k, s, [&] {
+        HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), va, vb, 1.0, op == 2 ? -L.mu : 0.0, L.n,
+                             X, H->ld, k, Y, H->ld, s));
+    });
+}
+
+// X = (S - mu M)^-1 B on columns [col0, col0 + ncols) with FP32 solves and
+// FP64 iterative refinement until every column's relative residual
+// ||B - A X|| / ||B|| is at most eta; falls back to the FP64 solve when the
+// refinement stalls.  B is not modified.  Returns the refinement sweeps.
+static int32_t refine_solve(hsim_hierarchy* H, Level& L, const double* B, double* X, int32_t col0, int32_t ncols,
+                            double eta, hipStream_t s, int32_t* escalated) {
+    const int64_t n = L.n;
+    const int32_t ld = H->ld;
+    double* R = dptr<double>(H->R);
+    HIPCHECK(launch_copy2d(B + col0, ld, n, ncols, X + col0, ld, s));
+    solve_level(H, L, X, col0, ncols, false, s, true);
+    std::vector<double> ratio(ncols);
+    double prev = INFINITY;
+    int32_t sweeps = 0, stall = 0;
+    const double nnz = (double)L.S.nnz();
+    for (int it = 0; it < 12; ++it) {
+        // R = B - (S - mu M) X
+        H->prof.run(HSIM_K_SPMM, nnz * 20.0 + 16.0 * n * ncols, 2.0 * nnz * ncols, s, [&] {
+            HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), dptr<double>(L.dS_val),
+                                 dptr<double>(L.dM_val), 1.0, -L.mu, n, X + col0, ld, ncols, R + col0, ld, s));
+        });
+        HIPCHECK(launch_axpby(1.0, B + col0, ld, -1.0, R + col0, ld, n, ncols, s));
+        HIPCHECK(launch_colnorm_ratio(R, B, n, ld, col0, ncols, dptr<double>(H->cn_part), dptr<double>(H->cn_ratio), s));
+        HIPCHECK(hipMemcpyAsync(ratio.data(), H->cn_ratio.p, ncols * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        double worst = 0;
+        for (double r : ratio) worst = std::max(worst, std::isfinite(r) ? r : INFINITY);
+        if (worst <= eta) return sweeps;
+        if (!(worst < 0.5 * prev)) ++stall;
+        if (stall >= 2 || !std::isfinite(worst)) break;
+        prev = worst;
+        solve_level(H, L, R, col0, ncols, false, s, true);
+        HIPCHECK(launch_axpby(1.0, R + col0, ld, 1.0, X + col0, ld, n, ncols, s));
+        ++sweeps;
+    }
+    // stalled: solve this block in FP64
+    ++*escalated;
+    HIPCHECK(launch_copy2d(B + col0, ld, n, ncols, X + col0, ld, s));
+    solve_level(H, L, X, col0, ncols, false, s, false);
+    return sweeps;
 }
 
 static void prolong_level(hsim_hierarchy* H, Level& L, const double* Xc, double* Xf, int32_t k, hipStream_t s) {
-    HIPCHECK(launch_spmm(dptr<int64_t>(L.dU_ptr), dptr<int32_t>(L.dU_idx), dptr<double>(L.dU_val), nullptr, 1.0, 0.0,
-                         L.n, Xc, H->ld, k, Xf, H->ld, s));
+    const double nnz = (double)L.U.nnz();
+    const double nc = (double)H->lv[L.tau + 1]->n;
+    H->prof.run(HSIM_K_SPMM, nnz * 12.0 + 8.0 * (L.n + nc) * k, 2.0 * nnz * k, s, [&] {
+        HIPCHECK(launch_spmm(dptr<int64_t>(L.dU_ptr), dptr<int32_t>(L.dU_idx), dptr<double>(L.dU_val), nullptr, 1.0, 0.0,
+                             L.n, Xc, H->ld, k, Xf, H->ld, s));
+    });
 }
 
 static void alloc_workspace(hsim_hierarchy* H) {
@@ -470,6 +627,9 @@ static void alloc_workspace(hsim_hierarchy* H) {
     H->MPsi.alloc(blk);
     H->Btmp.alloc(blk);
     H->Xc.alloc(blk);
+    H->R.alloc(blk);
+    H->cn_part.alloc((size_t)colnorm_partial_doubles(n0, H->ld) * sizeof(double));
+    H->cn_ratio.alloc((size_t)H->ld * sizeof(double));
     const int64_t chunk = 4096;
     H->gram_part.alloc((size_t)gram_partial_doubles(n0, H->q, chunk) * sizeof(double));
     H->ritz_part.alloc((size_t)ritz_partial_doubles(n0, H->q, chunk) * sizeof(double));
@@ -506,27 +666,37 @@ static double choose_shift(const std::vector<double>& lam, int32_t p, double alp
 // one Rayleigh-Ritz step on level L from the basis in Psi (already inverse
 // iterated); leaves Phi, lam (device) and returns lam/resid on the host
 static void rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam, std::vector<double>& res,
-                          hipStream_t s, double* ms_gram, double* ms_rr, double* ms_ritz) {
+                          hipStream_t s, double* ms_gram, double* ms_rr, double* ms_ritz, bool fp32_gram = false) {
     const int32_t q = H->q;
     const bool fin = L.tau == 0;
     auto t0 = std::chrono::steady_clock::now();
     apply_level(H, L, 0, dptr<double>(H->Psi), dptr<double>(H->SPsi), q, s);
     if (!fin) apply_level(H, L, 1, dptr<double>(H->Psi), dptr<double>(H->MPsi), q, s);
-    HIPCHECK(launch_gram(dptr<double>(H->Psi), dptr<double>(H->SPsi), fin ? nullptr : dptr<double>(H->MPsi),
-                         fin ? dptr<double>(L.dmdiag) : nullptr, L.n, q, H->ld, dptr<double>(H->gram_part), 4096,
-                         dptr<double>(H->Sbar), dptr<double>(H->Mbar), s));
+    const double nq = (double)L.n * q;
+    H->prof.run(HSIM_K_GRAM, 8.0 * nq * (fin ? 2.0 : 3.0) + 8.0 * (fin ? L.n : 0), 2.0 * nq * q, s, [&] {
+        HIPCHECK(launch_gram(dptr<double>(H->Psi), dptr<double>(H->SPsi), fin ? nullptr : dptr<double>(H->MPsi),
+                             fin ? dptr<double>(L.dmdiag) : nullptr, L.n, q, H->ld, dptr<double>(H->gram_part), 4096,
+                             dptr<double>(H->Sbar), dptr<double>(H->Mbar), s, fp32_gram));
+    });
     HIPCHECK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     H->rr.setup(q);
-    H->rr.run(dptr<double>(H->Sbar), dptr<double>(H->Mbar), q, dptr<double>(H->lam), dptr<double>(H->Phibar), q, s);
+    H->prof.run(HSIM_K_JACOBI, 0.0, 0.0, s, [&] {
+        H->rr.run(dptr<double>(H->Sbar), dptr<double>(H->Mbar), q, dptr<double>(H->lam), dptr<double>(H->Phibar), q, s);
+    });
     lam.resize(q);
     HIPCHECK(hipMemcpyAsync(lam.data(), H->lam.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     auto t2 = std::chrono::steady_clock::now();
-    HIPCHECK(launch_ritz(dptr<double>(H->Psi), dptr<double>(H->SPsi), fin ? nullptr : dptr<double>(H->MPsi),
-                         fin ? dptr<double>(L.dmdiag) : nullptr, dptr<double>(H->Phibar), dptr<double>(H->lam), L.n, q,
-                         H->ld, dptr<double>(H->Phi), nullptr, dptr<double>(H->ritz_part), 4096, fin,
-                         lambda_floor(lam), dptr<double>(H->resid), s));
+    const double lf = lambda_floor(lam);
+    H->prof.run(HSIM_K_RITZ, 8.0 * nq * (fin ? 3.0 : 4.0) + 8.0 * (fin ? L.n : 0), 2.0 * nq * q * (fin ? 2.0 : 3.0), s,
+                [&] {
+                    HIPCHECK(launch_ritz(dptr<double>(H->Psi), dptr<double>(H->SPsi),
+                                         fin ? nullptr : dptr<double>(H->MPsi), fin ? dptr<double>(L.dmdiag) : nullptr,
+                                         dptr<double>(H->Phibar), dptr<double>(H->lam), L.n, q, H->ld,
+                                         dptr<double>(H->Phi), nullptr, dptr<double>(H->ritz_part), 4096, fin, lf,
+                                         dptr<double>(H->resid), s));
+                });
     res.resize(q);
     HIPCHECK(hipMemcpyAsync(res.data(), H->resid.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
@@ -539,6 +709,8 @@ static void rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam,
 static Level& level_at(hsim_hierarchy* H, int32_t level) {
     if (!H) fail(HSIM_E_INVALID, "null hierarchy");
     if (H->host_only) fail(HSIM_E_STATE, "hierarchy was built host-only");
+    H->prof.reset(false);
+    H->solved = false;   // step calls reuse the solve workspace and factors
     if (level < 0 || level >= H->T) fail(HSIM_E_INVALID, "level %d out of range [0, %d)", level, H->T);
     return *H->lv[level];
 }
@@ -724,6 +896,7 @@ hsim_status hsim_level_info(const hsim_hierarchy* h, int32_t level, hsim_level_d
     info->factor_entries = L.coarsest ? 0 : L.sy.tile_doubles;
     info->rho = L.rho;
     info->factor_flops = L.coarsest ? 0 : L.sy.flops;
+    info->factor_nnz = L.coarsest ? 0 : L.sy.factor_nnz;
     API_END
 }
 
@@ -789,8 +962,8 @@ hsim_status hsim_step_factor(hsim_hierarchy* h, int32_t level, double mu, int32_
     Level& L = level_at(h, level);
     if (L.coarsest) fail(HSIM_E_INVALID, "the coarsest level is solved densely");
     if (!std::isfinite(mu)) fail(HSIM_E_INVALID, "mu must be finite");
-    (void)precision;
-    factor_level(h, L, mu, S_(stream));
+    if (precision != HSIM_FP64 && precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
+    factor_level(h, L, mu, S_(stream), precision == HSIM_MIXED);
     if (neg_pivots) *neg_pivots = L.neg_pivots;
     API_END
 }
@@ -803,12 +976,19 @@ hsim_status hsim_step_solve(hsim_hierarchy* h, int32_t level, int32_t k, const d
     if (!L.factored) fail(HSIM_E_STATE, "hsim_step_solve before hsim_step_factor on level %d", level);
     if (k < 1 || k > h->ld) fail(HSIM_E_INVALID, "k must be in [1, %d]", h->ld);
     if (!d_B || !d_X) fail(HSIM_E_INVALID, "null argument");
-    (void)precision;
-    (void)refine_tol;
+    if (precision != HSIM_FP64 && precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
     hipStream_t s = S_(stream);
     HIPCHECK(launch_gather_rows(d_B, k, dptr<int32_t>(L.dperm), L.n, k, dptr<double>(h->Xc), h->ld, s));
-    solve_level(h, L, dptr<double>(h->Xc), 0, k, false, s);
-    HIPCHECK(launch_scatter_rows(dptr<double>(h->Xc), h->ld, dptr<int32_t>(L.dperm), L.n, k, d_X, k, s));
+    if (precision == HSIM_MIXED) {
+        if (!L.factored32) fail(HSIM_E_STATE, "mixed solve needs hsim_step_factor with HSIM_MIXED");
+        if (!(refine_tol > 0)) fail(HSIM_E_INVALID, "refine_tol must be positive");
+        int32_t esc = 0;
+        refine_solve(h, L, dptr<double>(h->Xc), dptr<double>(h->Btmp), 0, k, refine_tol, s, &esc);
+        HIPCHECK(launch_scatter_rows(dptr<double>(h->Btmp), h->ld, dptr<int32_t>(L.dperm), L.n, k, d_X, k, s));
+    } else {
+        solve_level(h, L, dptr<double>(h->Xc), 0, k, false, s);
+        HIPCHECK(launch_scatter_rows(dptr<double>(h->Xc), h->ld, dptr<int32_t>(L.dperm), L.n, k, d_X, k, s));
+    }
     API_END
 }
 
@@ -818,7 +998,7 @@ hsim_status hsim_step_gram(hsim_hierarchy* h, int32_t level, int32_t k, const do
     Level& L = level_at(h, level);
     if (k < 1 || k > h->q) fail(HSIM_E_INVALID, "k must be in [1, %d]", h->q);
     if (!d_Psi || !d_Sbar || !d_Mbar) fail(HSIM_E_INVALID, "null argument");
-    (void)precision;
+    if (precision != HSIM_FP64 && precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
     hipStream_t s = S_(stream);
     HIPCHECK(launch_gather_rows(d_Psi, k, dptr<int32_t>(L.dperm), L.n, k, dptr<double>(h->Psi), h->ld, s));
     apply_level(h, L, 0, dptr<double>(h->Psi), dptr<double>(h->SPsi), k, s);
@@ -826,7 +1006,7 @@ hsim_status hsim_step_gram(hsim_hierarchy* h, int32_t level, int32_t k, const do
     if (!fin) apply_level(h, L, 1, dptr<double>(h->Psi), dptr<double>(h->MPsi), k, s);
     HIPCHECK(launch_gram(dptr<double>(h->Psi), dptr<double>(h->SPsi), fin ? nullptr : dptr<double>(h->MPsi),
                          fin ? dptr<double>(L.dmdiag) : nullptr, L.n, k, h->ld, dptr<double>(h->gram_part), 4096, d_Sbar,
-                         d_Mbar, s));
+                         d_Mbar, s, precision == HSIM_MIXED));
     API_END
 }
 
@@ -896,6 +1076,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     if (!(so.tol > 0)) fail(HSIM_E_INVALID, "tol must be positive");
     if (so.max_iters < 1) fail(HSIM_E_INVALID, "max_iters must be >= 1");
     if (so.precision != HSIM_FP64 && so.precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
+    const bool mixed = so.precision == HSIM_MIXED;
     hipStream_t s = S_(so.stream);
     const auto T0 = std::chrono::steady_clock::now();
     hsim_stats st;
@@ -905,11 +1086,13 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     st.ms_build = h->ms_build;
     const int32_t q = h->q, p = h->p, T = h->T;
     h->solved = false;
+    h->prof.reset((so.flags & HSIM_FLAG_PROFILE) != 0);
     // coarsest level: dense solve, Phi in the coarsest level's order (= its internal order)
     std::vector<double> lam(q), res(q);
     {
         auto t0 = std::chrono::steady_clock::now();
-        coarse_solve(h, q, dptr<double>(h->lam), dptr<double>(h->Phi), h->ld, nullptr, s);
+        h->prof.run(HSIM_K_JACOBI, 0.0, 0.0, s,
+                    [&] { coarse_solve(h, q, dptr<double>(h->lam), dptr<double>(h->Phi), h->ld, nullptr, s); });
         HIPCHECK(hipMemcpyAsync(lam.data(), h->lam.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         st.ms_coarse = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -934,7 +1117,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         const int32_t j = (int32_t)std::floor(so.shift_alpha * p + 1e-12);
         for (int attempt = 0;; ++attempt) {
             try {
-                factor_level(h, L, mu, s);
+                factor_level(h, L, mu, s, mixed);
                 break;
             } catch (const Error& e) {
                 if (e.code != HSIM_E_FACTOR || attempt >= 3) throw;
@@ -949,18 +1132,33 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         // subspace iterations
         int32_t locked = 0, it = 0;
         bool conv = false;
+        double rmax = INFINITY;   // largest residual of the first p pairs after the last Rayleigh-Ritz step
         for (it = 1; it <= so.max_iters; ++it) {
             auto a0 = std::chrono::steady_clock::now();
             HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, L.n, q, dptr<double>(h->Psi), h->ld, s));
             const int32_t act = q - locked;
             if (act > 0) {
                 for (int rep = 0; rep < 2; ++rep) {
-                    if (tau == 0) {
+                    if (!mixed && tau == 0) {
                         solve_level(h, L, dptr<double>(h->Psi), locked, act, true, s);
+                        continue;
+                    }
+                    // B = M Psi
+                    if (tau == 0)
+                        HIPCHECK(launch_diag_scale(dptr<double>(L.dmdiag), L.n, dptr<double>(h->Psi) + locked, h->ld,
+                                                   act, dptr<double>(h->Btmp) + locked, h->ld, s));
+                    else
+                        h->prof.run(HSIM_K_SPMM, 12.0 * L.S.nnz() + 16.0 * L.n * act, 2.0 * L.S.nnz() * act, s, [&] {
+                            HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx),
+                                                 dptr<double>(L.dM_val), nullptr, 1.0, 0.0, L.n,
+                                                 dptr<double>(h->Psi) + locked, h->ld, act,
+                                                 dptr<double>(h->Btmp) + locked, h->ld, s));
+                        });
+                    if (mixed) {
+                        const double eta = std::min(1e-3, 0.1 * (std::isfinite(rmax) ? rmax : 1e-2));
+                        st.refine_steps += refine_solve(h, L, dptr<double>(h->Btmp), dptr<double>(h->Psi), locked, act,
+                                                        eta, s, &st.escalated);
                     } else {
-                        HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), dptr<double>(L.dM_val),
-                                             nullptr, 1.0, 0.0, L.n, dptr<double>(h->Psi) + locked, h->ld, act,
-                                             dptr<double>(h->Btmp) + locked, h->ld, s));
                         solve_level(h, L, dptr<double>(h->Btmp), locked, act, false, s);
                         HIPCHECK(launch_copy2d(dptr<double>(h->Btmp) + locked, h->ld, L.n, act,
                                                dptr<double>(h->Psi) + locked, h->ld, s));
@@ -969,9 +1167,22 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
             }
             HIPCHECK(hipStreamSynchronize(s));
             st.ms_solve += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a0).count();
-            rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz);
-            conv = true;
-            for (int32_t i = 0; i < p; ++i) conv &= res[i] < so.tol;
+            const bool low_gram = mixed && !(rmax < 10.0 * so.tol);
+            rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, low_gram);
+            auto check = [&] {
+                conv = true;
+                rmax = 0;
+                for (int32_t i = 0; i < p; ++i) {
+                    conv &= res[i] < so.tol;
+                    rmax = std::max(rmax, res[i]);
+                }
+            };
+            check();
+            // the returned basis always comes from an FP64 Gram (M-orthonormal to FP64 accuracy)
+            if (conv && low_gram) {
+                rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, false);
+                check();
+            }
             if (conv) break;
             if (!(so.flags & HSIM_FLAG_NOLOCK)) {
                 int32_t r = 0;
@@ -991,6 +1202,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     HIPCHECK(hipStreamSynchronize(s));
     h->last_lam = lam;
     h->solved = true;
+    h->prof.collect(st, s);
     st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();
     if (stats) *stats = st;
     if (final_status != HSIM_OK) {
@@ -1000,15 +1212,156 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     API_END
 }
 
+static void backward_setup(hsim_hierarchy* h) {
+    if (h->bw_ready) return;
+    const Mesh& m = h->mesh;
+    Level& L0 = *h->lv[0];
+    h->bV.upload(m.V);
+    h->bF.upload(m.F);
+    if (!h->density.empty()) h->bRho.upload(h->density);
+    h->bIperm.upload(L0.sy.iperm);
+    // vertex -> (triangle, corner) lists in triangle order
+    std::vector<int64_t> ptr(m.nv + 1, 0), vt(3 * m.nf);
+    for (int64_t t = 0; t < m.nf; ++t)
+        for (int c = 0; c < 3; ++c) ptr[m.F[3 * t + c] + 1]++;
+    for (int64_t v = 0; v < m.nv; ++v) ptr[v + 1] += ptr[v];
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t t = 0; t < m.nf; ++t)
+        for (int c = 0; c < 3; ++c) vt[fill[m.F[3 * t + c]]++] = 3 * t + c;
+    h->bVtPtr.upload(ptr);
+    h->bVt.upload(vt);
+    h->bG.alloc((size_t)m.nf * 9 * sizeof(double));
+    h->bNu.alloc((size_t)m.nv * sizeof(double));
+    const size_t blk = (size_t)L0.n * h->ld * sizeof(double);
+    for (DeviceBuffer* b : {&h->bGbar, &h->bMX, &h->bW, &h->bY, &h->bR, &h->bZ, &h->bP, &h->bQ}) b->alloc(blk);
+    h->bSmall.alloc((size_t)(4 * h->q * h->q + 16 * h->ld) * sizeof(double));
+    h->bPart.alloc((size_t)std::max(tsgemm_partial_doubles(L0.n, h->q, h->ld), coldot_partial_doubles(L0.n, h->ld)) *
+                   sizeof(double));
+    h->bDots.alloc((size_t)8 * h->ld * sizeof(double));
+    h->bw_ready = true;
+}
+
 hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, const double* d_grad_evecs,
                                 double* d_grad_V, void* stream) {
     API_BEGIN
     if (!h || !d_grad_V) fail(HSIM_E_INVALID, "null argument");
+    if (h->host_only) fail(HSIM_E_STATE, "hierarchy was built host-only");
     if (!h->solved) fail(HSIM_E_STATE, "hsim_solve_backward before a successful hsim_solve");
-    (void)d_grad_evals;
-    (void)d_grad_evecs;
-    (void)stream;
-    fail(HSIM_E_UNIMPLEMENTED, "backward not implemented yet");
+    if (h->bo.lumping != 0) fail(HSIM_E_UNIMPLEMENTED, "the adjoint supports the barycentric lumping only");
+    hipStream_t s = S_(stream);
+    backward_setup(h);
+    Level& L0 = *h->lv[0];
+    const int64_t n = L0.n, nv = h->mesh.nv, nf = h->mesh.nf;
+    const int32_t p = h->p, q = h->q, ld = h->ld;
+    const double* X = dptr<double>(h->Phi);    // level-0 Ritz vectors, internal order
+    const double* lam = dptr<double>(h->lam);
+    const double* md = dptr<double>(L0.dmdiag);
+    double* W = nullptr;
+    double* Y = nullptr;
+    double* part = dptr<double>(h->bPart);
+    h->cg_iters = 0;
+    if (d_grad_evecs) {
+        double* Gb = dptr<double>(h->bGbar);
+        double* MX = dptr<double>(h->bMX);
+        double* R = dptr<double>(h->bR);
+        double* Z = dptr<double>(h->bZ);
+        double* P = dptr<double>(h->bP);
+        double* Qm = dptr<double>(h->bQ);
+        W = dptr<double>(h->bW);
+        Y = dptr<double>(h->bY);
+        double* C0 = dptr<double>(h->bSmall);                 // q x p
+        double* Cin = C0 + (size_t)q * q;                    // q x p
+        double* Gam = Cin + (size_t)q * q;                   // q x p
+        double* Cp = Gam + (size_t)q * q;                    // q x p (projections)
+        double* dots = dptr<double>(h->bDots);
+        double* rz = dots, *pq = dots + ld, *alpha = dots + 2 * ld, *rz2 = dots + 3 * ld, *beta = dots + 4 * ld,
+              *rr = dots + 5 * ld;
+        HIPCHECK(launch_import_cols(d_grad_evecs, nv, dptr<int32_t>(L0.dperm), n, p, Gb, ld, s));
+        HIPCHECK(launch_diag_scale(md, n, X, ld, q, MX, ld, s));
+        // coefficients of the gradient in the Ritz basis: C0 = X_q^T Gbar
+        HIPCHECK(launch_tsgemm_tn(X, ld, Gb, ld, n, q, p, part, C0, s));
+        std::vector<double> c0((size_t)q * p), lamh(q);
+        HIPCHECK(hipMemcpyAsync(c0.data(), C0, c0.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(lamh.data(), lam, q * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        // clusters: maximal runs of Ritz values with relative gaps below 1e-2
+        std::vector<int32_t> cl(q, 0);
+        for (int32_t j = 1; j < q; ++j) {
+            const double den = std::fabs(lamh[j]) > 0 ? std::fabs(lamh[j]) : 1.0;
+            cl[j] = cl[j - 1] + (((lamh[j] - lamh[j - 1]) / den) >= 1e-2 ? 1 : 0);
+        }
+        std::vector<double> cin((size_t)q * p, 0.0), gam((size_t)q * p, 0.0);
+        for (int32_t k = 0; k < p; ++k)
+            for (int32_t j = 0; j < q; ++j) {
+                const double cjk = c0[(size_t)j * p + k];
+                if (cl[j] != cl[k]) {
+                    cin[(size_t)j * p + k] = cjk / (lamh[j] - lamh[k]);
+                } else {
+                    // same cluster: normalisation term with the symmetrised coefficient
+                    const double ckj = j < p ? c0[(size_t)k * p + j] : 0.0;   // no gradient on x_j, j >= p
+                    gam[(size_t)j * p + k] = j == k ? cjk : 0.5 * (cjk + ckj);
+                }
+            }
+        HIPCHECK(hipMemcpyAsync(Cin, cin.data(), cin.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(Gam, gam.data(), gam.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        // right-hand side on the complement: r = Gbar - M X_q C0
+        HIPCHECK(launch_copy2d(Gb, ld, n, p, R, ld, s));
+        HIPCHECK(launch_tsgemm_nn(MX, ld, n, q, C0, p, -1.0, 1.0, R, ld, s));
+        // PCG on {w : X_q^T M w = 0} for (S - lam_k M) w_k = r_k, preconditioned by
+        // the level-0 factor of S - mu M and the M-orthogonal projection
+        auto apply_prec = [&](const double* Rin, double* Zout) {
+            HIPCHECK(launch_copy2d(Rin, ld, n, p, Zout, ld, s));
+            solve_level(h, L0, Zout, 0, p, false, s);
+            HIPCHECK(launch_tsgemm_tn(MX, ld, Zout, ld, n, q, p, part, Cp, s));
+            HIPCHECK(launch_tsgemm_nn(X, ld, n, q, Cp, p, -1.0, 1.0, Zout, ld, s));
+        };
+        HIPCHECK(launch_fill(W, n * ld, 0.0, s));
+        apply_prec(R, Z);
+        HIPCHECK(launch_copy2d(Z, ld, n, p, P, ld, s));
+        HIPCHECK(launch_coldot(R, Z, n, ld, p, part, rz, s));
+        HIPCHECK(launch_coldot(R, R, n, ld, p, part, rr, s));
+        std::vector<double> r0(p), rc(p);
+        HIPCHECK(hipMemcpyAsync(r0.data(), rr, p * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        const double cg_tol = 1e-12;
+        int it = 0;
+        for (it = 1; it <= 300; ++it) {
+            apply_level(h, L0, 0, P, Qm, p, s);                       // Q = S P
+            HIPCHECK(launch_shift_cols(Qm, P, md, lam, n, ld, p, s));  // Q -= lam_k M P
+            HIPCHECK(launch_coldot(P, Qm, n, ld, p, part, pq, s));
+            HIPCHECK(launch_div_cols(rz, pq, alpha, p, s));
+            HIPCHECK(launch_axpy_cols(W, P, alpha, 0, n, ld, p, s));
+            HIPCHECK(launch_axpy_cols(R, Qm, alpha, 1, n, ld, p, s));
+            // keep the residual in the dual of the complement
+            HIPCHECK(launch_tsgemm_tn(X, ld, R, ld, n, q, p, part, Cp, s));
+            HIPCHECK(launch_tsgemm_nn(MX, ld, n, q, Cp, p, -1.0, 1.0, R, ld, s));
+            if (it % 4 == 0) {
+                HIPCHECK(launch_coldot(R, R, n, ld, p, part, rr, s));
+                HIPCHECK(hipMemcpyAsync(rc.data(), rr, p * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHECK(hipStreamSynchronize(s));
+                bool done = true;
+                for (int32_t k = 0; k < p; ++k) done &= !(rc[k] > cg_tol * cg_tol * r0[k]);
+                if (done) break;
+            }
+            apply_prec(R, Z);
+            HIPCHECK(launch_coldot(R, Z, n, ld, p, part, rz2, s));
+            HIPCHECK(launch_div_cols(rz2, rz, beta, p, s));
+            HIPCHECK(launch_axpy_cols(P, Z, beta, 2, n, ld, p, s));
+            std::swap(rz, rz2);
+        }
+        h->cg_iters = it;
+        if (it > 300) fail(HSIM_E_NOCONV, "adjoint PCG did not converge");
+        // w_k += in-span part; Y = X_cluster Gamma
+        HIPCHECK(launch_tsgemm_nn(X, ld, n, q, Cin, p, 1.0, 1.0, W, ld, s));
+        HIPCHECK(launch_tsgemm_nn(X, ld, n, q, Gam, p, 1.0, 0.0, Y, ld, s));
+    }
+    const int32_t* ip = dptr<int32_t>(h->bIperm);
+    HIPCHECK(launch_bwd_vertex(nv, p, X, W, Y, ld, ip, lam, d_grad_evals, h->density.empty() ? nullptr : dptr<double>(h->bRho),
+                               dptr<double>(h->bNu), s));
+    HIPCHECK(launch_bwd_tri(nf, dptr<int32_t>(h->bF), dptr<double>(h->bV), p, X, W, ld, ip, d_grad_evals,
+                            dptr<double>(h->bNu), dptr<double>(h->bG), s));
+    HIPCHECK(launch_bwd_gather(nv, dptr<int64_t>(h->bVtPtr), dptr<int64_t>(h->bVt), dptr<double>(h->bG), d_grad_V, s));
+    HIPCHECK(hipStreamSynchronize(s));
     API_END
 }
 

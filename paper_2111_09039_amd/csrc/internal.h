@@ -94,6 +94,7 @@ struct Symbolic {
     int32_t tree_levels = 0;
     int64_t tile_doubles = 0, linv_doubles = 0, d_doubles = 0, ubuf_rows = 0;
     double flops = 0;
+    int64_t factor_nnz = 0;       // unpadded L entries (lower triangle incl. diagonal)
     // fronts of every tree level, contiguous (fronts are renumbered so that
     // tree level t holds fronts [tlev_ptr[t], tlev_ptr[t+1]))
     std::vector<int32_t> tlev_ptr;

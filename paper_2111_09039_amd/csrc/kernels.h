@@ -66,9 +66,10 @@ hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const 
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 // partial Grams over row chunks (pairs of 32-column tiles, upper), then the sum
+// fp32: operands rounded to FP32, FP32 accumulation over runs of 256 rows, FP64 sum of the runs
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
                        int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
-                       hipStream_t s);
+                       hipStream_t s, bool fp32 = false);
 int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows);
 
 // Phi = Psi Phibar and residual partial sums; then the residual
@@ -110,6 +111,38 @@ hipError_t launch_sort_eig(const double* C, int32_t m, int32_t kvalid, const dou
 // Y[r, c] = V[r, c] * w[r] (w = D^1/2), for the back transformation
 hipError_t launch_row_scale(const double* V, const double* w, bool sqrt_w, int64_t rows, int32_t k, int64_t ld,
                             double* Y, hipStream_t s);
+
+// ratio[c] = ||R_c|| / ||B_c|| over columns [col0, col0 + k) of n-row blocks with leading dim ld
+int64_t colnorm_partial_doubles(int64_t n, int32_t k);
+hipError_t launch_colnorm_ratio(const double* R, const double* B, int64_t n, int64_t ld, int32_t col0, int32_t k,
+                                double* partial, double* ratio, hipStream_t s);
+
+// ------------------------------------------------------------ adjoint helpers
+int64_t tsgemm_partial_doubles(int64_t n, int32_t ka, int32_t kb);
+// C (ka x kb, row-major) = A^T B
+hipError_t launch_tsgemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t n, int32_t ka,
+                            int32_t kb, double* partial, double* C, hipStream_t s);
+// Y = beta Y + alpha A C
+hipError_t launch_tsgemm_nn(const double* A, int64_t lda, int64_t n, int32_t ka, const double* C, int32_t kb,
+                            double alpha, double beta, double* Y, int64_t ldy, hipStream_t s);
+int64_t coldot_partial_doubles(int64_t n, int32_t k);
+hipError_t launch_coldot(const double* A, const double* B, int64_t n, int64_t ld, int32_t k, double* partial,
+                         double* out, hipStream_t s);
+hipError_t launch_shift_cols(double* Y, const double* X, const double* m, const double* lam, int64_t n, int64_t ld,
+                             int32_t k, hipStream_t s);
+hipError_t launch_axpy_cols(double* Y, const double* X, const double* coef, int mode, int64_t n, int64_t ld, int32_t k,
+                            hipStream_t s);
+hipError_t launch_div_cols(const double* num, const double* den, double* out, int32_t k, hipStream_t s);
+hipError_t launch_bwd_vertex(int64_t nv, int32_t p, const double* X, const double* W, const double* Y, int64_t ld,
+                             const int32_t* iperm, const double* lam, const double* glam, const double* rho, double* nu,
+                             hipStream_t s);
+hipError_t launch_bwd_tri(int64_t nf, const int32_t* F, const double* V, int32_t p, const double* X, const double* W,
+                          int64_t ld, const int32_t* iperm, const double* glam, const double* nu, double* G,
+                          hipStream_t s);
+hipError_t launch_bwd_gather(int64_t nv, const int64_t* vt_ptr, const int64_t* vt, const double* G, double* gradV,
+                             hipStream_t s);
+hipError_t launch_import_cols(const double* in, int64_t nv, const int32_t* perm, int64_t n, int32_t k, double* out,
+                              int64_t ld, hipStream_t s);
 
 // ------------------------------------------------------------ output
 // evecs[c * nv + vertex(r)] = sign_c * Phi[r, c] for c < p, largest-magnitude

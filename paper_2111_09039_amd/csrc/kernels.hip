@@ -554,7 +554,10 @@ int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows) {
 }
 
 // partial[chunk][pair][0|1][r][c]: sum over the chunk's rows of
-// Psi[row, a*32+r] * (S Psi)[row, b*32+c]  and  Psi[row, a*32+r] * (M Psi)[row, b*32+c]
+// Psi[row, a*32+r] * (S Psi)[row, b*32+c]  and  Psi[row, a*32+r] * (M Psi)[row, b*32+c].
+// TA = double: FP64 throughout.  TA = float: operands rounded to FP32, FP32
+// products and accumulation over runs of 256 rows, FP64 sum of the runs.
+template <class TA>
 __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ Psi, const double* __restrict__ SPsi,
                                                       const double* __restrict__ MPsi, const double* __restrict__ mdiag,
                                                       int64_t n, int32_t q, int64_t ld, int64_t chunk_rows,
@@ -566,32 +569,43 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__
     const int32_t b = a + pair;
     const int64_t r0 = blockIdx.x * chunk_rows;
     const int64_t r1 = min(n, r0 + chunk_rows);
-    __shared__ double P[T32][T32 + 1], Q[T32][T32 + 1], R[T32][T32 + 1];
+    __shared__ TA P[T32][T32 + 1], Q[T32][T32 + 1], R[T32][T32 + 1];
     const int tid = threadIdx.x;
     const int r = tid & 31;
     double accS[4] = {0, 0, 0, 0}, accM[4] = {0, 0, 0, 0};
+    TA runS[4] = {0, 0, 0, 0}, runM[4] = {0, 0, 0, 0};
+    int tiles_in_run = 0;
     for (int64_t row0 = r0; row0 < r1; row0 += T32) {
         for (int idx = tid; idx < TT; idx += 256) {
             const int i = idx >> 5, c = idx & 31;
             const int64_t row = row0 + i;
             const int ca = a * T32 + c, cb = b * T32 + c;
             const bool ok = row < r1;
-            P[i][c] = (ok && ca < q) ? Psi[row * ld + ca] : 0.0;
-            Q[i][c] = (ok && cb < q) ? SPsi[row * ld + cb] : 0.0;
-            R[i][c] = (ok && cb < q) ? (mdiag ? mdiag[row] * Psi[row * ld + cb] : MPsi[row * ld + cb]) : 0.0;
+            P[i][c] = (TA)((ok && ca < q) ? Psi[row * ld + ca] : 0.0);
+            Q[i][c] = (TA)((ok && cb < q) ? SPsi[row * ld + cb] : 0.0);
+            R[i][c] = (TA)((ok && cb < q) ? (mdiag ? mdiag[row] * Psi[row * ld + cb] : MPsi[row * ld + cb]) : 0.0);
         }
         __syncthreads();
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             const int c = (tid >> 5) + 8 * o;
-            double s = 0, m = 0;
+            TA sv = 0, mv = 0;
 #pragma unroll 8
             for (int i = 0; i < T32; ++i) {
-                s += P[i][r] * Q[i][c];
-                m += P[i][r] * R[i][c];
+                sv += P[i][r] * Q[i][c];
+                mv += P[i][r] * R[i][c];
             }
-            accS[o] += s;
-            accM[o] += m;
+            runS[o] += sv;
+            runM[o] += mv;
+        }
+        if (++tiles_in_run == 8) {
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                accS[o] += (double)runS[o];
+                accM[o] += (double)runM[o];
+                runS[o] = runM[o] = 0;
+            }
+            tiles_in_run = 0;
         }
         __syncthreads();
     }
@@ -600,8 +614,8 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         const int c = (tid >> 5) + 8 * o;
-        out[r * T32 + c] = accS[o];
-        out[TT + r * T32 + c] = accM[o];
+        out[r * T32 + c] = accS[o] + (double)runS[o];
+        out[TT + r * T32 + c] = accM[o] + (double)runM[o];
     }
 }
 
@@ -631,11 +645,14 @@ __global__ void k_gram_reduce(const double* __restrict__ partial, int64_t nchunk
 
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
                        int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
-                       hipStream_t s) {
+                       hipStream_t s, bool fp32) {
     const int64_t nt = cdiv(q, T32);
     const int64_t nch = cdiv(n, chunk_rows);
-    k_gram_partial<<<dim3((unsigned)nch, (unsigned)(nt * (nt + 1) / 2)), 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld,
-                                                                                       chunk_rows, partial);
+    const dim3 grid((unsigned)nch, (unsigned)(nt * (nt + 1) / 2));
+    if (fp32)
+        k_gram_partial<float><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, chunk_rows, partial);
+    else
+        k_gram_partial<double><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, chunk_rows, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_gram_reduce<<<grid_for((int64_t)q * q, 256), 256, 0, s>>>(partial, nch, q, Sbar, Mbar);
@@ -1047,6 +1064,376 @@ hipError_t launch_densify(const int64_t* ptr, const int32_t* idx, const double* 
     hipError_t e = launch_fill(A, n * n, 0.0, s);
     if (e != hipSuccess) return e;
     k_densify<<<grid_for(n, 256), 256, 0, s>>>(ptr, idx, val, n, A);
+    return hipGetLastError();
+}
+
+// per column c in [col0, col0 + k): num[c] = ||R_c||^2, den[c] = ||B_c||^2 (partial sums by row chunks)
+__global__ __launch_bounds__(256) void k_colnorm2(const double* __restrict__ R, const double* __restrict__ B,
+                                                  int64_t n, int64_t ld, int32_t col0, int32_t k, int64_t chunk,
+                                                  double* __restrict__ partial) {
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int lane_row = threadIdx.x >> 6;   // 4 row lanes
+    const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+    double a = 0, b = 0;
+    if (c < k) {
+        for (int64_t r = r0 + lane_row; r < r1; r += 4) {
+            const double x = R[r * ld + col0 + c], y = B[r * ld + col0 + c];
+            a += x * x;
+            b += y * y;
+        }
+    }
+    __shared__ double sa[4][64], sb[4][64];
+    sa[lane_row][threadIdx.x & 63] = a;
+    sb[lane_row][threadIdx.x & 63] = b;
+    __syncthreads();
+    if (threadIdx.x < 64 && c < k) {
+        double ta = 0, tb = 0;
+        for (int l = 0; l < 4; ++l) {
+            ta += sa[l][threadIdx.x];
+            tb += sb[l][threadIdx.x];
+        }
+        partial[(int64_t)blockIdx.x * 2 * k + c] = ta;
+        partial[(int64_t)blockIdx.x * 2 * k + k + c] = tb;
+    }
+}
+__global__ void k_colnorm_ratio(const double* __restrict__ partial, int64_t nch, int32_t k, double* ratio) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= k) return;
+    double a = 0, b = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+        a += partial[ch * 2 * k + c];
+        b += partial[ch * 2 * k + k + c];
+    }
+    ratio[c] = b > 0 ? sqrt(a / b) : sqrt(a);
+}
+int64_t colnorm_partial_doubles(int64_t n, int32_t k) { return cdiv(n, 16384) * 2 * (int64_t)k; }
+hipError_t launch_colnorm_ratio(const double* R, const double* B, int64_t n, int64_t ld, int32_t col0, int32_t k,
+                                double* partial, double* ratio, hipStream_t s) {
+    if (k <= 0 || n <= 0) return hipSuccess;
+    const int64_t chunk = 16384, nch = cdiv(n, chunk);
+    k_colnorm2<<<dim3((unsigned)nch, (unsigned)cdiv(k, 64)), 256, 0, s>>>(R, B, n, ld, col0, k, chunk, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_colnorm_ratio<<<(unsigned)cdiv(k, 256), 256, 0, s>>>(partial, nch, k, ratio);
+    return hipGetLastError();
+}
+
+// ============================================================ tall-skinny products (adjoint solve)
+// C (ka x kb, row-major) = A^T B for n-row blocks A (lda), B (ldb): partial
+// sums over row chunks for each 32 x 32 output tile, then a fixed-order sum.
+int64_t tsgemm_partial_doubles(int64_t n, int32_t ka, int32_t kb) {
+    return cdiv(n, 4096) * cdiv(ka, T32) * cdiv(kb, T32) * TT;
+}
+__global__ __launch_bounds__(256) void k_tsgemm_tn_partial(const double* __restrict__ A, int64_t lda,
+                                                           const double* __restrict__ B, int64_t ldb, int64_t n,
+                                                           int32_t ka, int32_t kb, int64_t chunk, double* partial) {
+    const int ta = blockIdx.y / ((kb + T32 - 1) / T32), tb = blockIdx.y % ((kb + T32 - 1) / T32);
+    const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+    __shared__ double P[T32][T32 + 1], Q[T32][T32 + 1];
+    const int tid = threadIdx.x, r = tid & 31;
+    double acc[4] = {0, 0, 0, 0};
+    for (int64_t row0 = r0; row0 < r1; row0 += T32) {
+        for (int idx = tid; idx < TT; idx += 256) {
+            const int i = idx >> 5, c = idx & 31;
+            const int64_t row = row0 + i;
+            const int ca = ta * T32 + c, cb = tb * T32 + c;
+            P[i][c] = (row < r1 && ca < ka) ? A[row * lda + ca] : 0.0;
+            Q[i][c] = (row < r1 && cb < kb) ? B[row * ldb + cb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int c = (tid >> 5) + 8 * o;
+            double v = 0;
+#pragma unroll 8
+            for (int i = 0; i < T32; ++i) v += P[i][r] * Q[i][c];
+            acc[o] += v;
+        }
+        __syncthreads();
+    }
+    double* out = partial + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * TT;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) out[r * T32 + (tid >> 5) + 8 * o] = acc[o];
+}
+__global__ void k_tsgemm_tn_reduce(const double* __restrict__ partial, int64_t nch, int32_t ka, int32_t kb, double* C) {
+    const int ntb = (kb + T32 - 1) / T32;
+    const int64_t ntiles = (int64_t)((ka + T32 - 1) / T32) * ntb;
+    const int64_t tot = (int64_t)ka * kb;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t / kb), j = (int)(t % kb);
+        const int64_t tile = (int64_t)(i / T32) * ntb + j / T32;
+        double v = 0;
+        for (int64_t ch = 0; ch < nch; ++ch) v += partial[(ch * ntiles + tile) * TT + (i % T32) * T32 + j % T32];
+        C[t] = v;
+    }
+}
+hipError_t launch_tsgemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t n, int32_t ka,
+                            int32_t kb, double* partial, double* C, hipStream_t s) {
+    if (ka <= 0 || kb <= 0) return hipSuccess;
+    const int64_t chunk = 4096, nch = cdiv(n, chunk);
+    const unsigned tiles = (unsigned)(cdiv(ka, T32) * cdiv(kb, T32));
+    k_tsgemm_tn_partial<<<dim3((unsigned)nch, tiles), 256, 0, s>>>(A, lda, B, ldb, n, ka, kb, chunk, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tsgemm_tn_reduce<<<grid_for((int64_t)ka * kb, 256), 256, 0, s>>>(partial, nch, ka, kb, C);
+    return hipGetLastError();
+}
+// Y = beta Y + alpha A C for A (n x ka, lda), C (ka x kb row-major), Y (n x kb, ldy)
+__global__ __launch_bounds__(256) void k_tsgemm_nn(const double* __restrict__ A, int64_t lda, int64_t n, int32_t ka,
+                                                   const double* __restrict__ Cm, int32_t kb, double alpha, double beta,
+                                                   double* __restrict__ Y, int64_t ldy, int64_t chunk) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* Cs = reinterpret_cast<double*>(smem_raw);   // ka x 32
+    const int tid = threadIdx.x, cl = tid & 31, rl = tid >> 5;
+    const int col = blockIdx.y * T32 + cl;
+    for (int idx = tid; idx < ka * T32; idx += 256) {
+        const int kk = idx >> 5, c = blockIdx.y * T32 + (idx & 31);
+        Cs[idx] = c < kb ? Cm[(int64_t)kk * kb + c] : 0.0;
+    }
+    __syncthreads();
+    if (col >= kb) return;
+    const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+    for (int64_t row = r0 + rl; row < r1; row += 8) {
+        const double* ar = A + row * lda;
+        double v = 0;
+        for (int kk = 0; kk < ka; ++kk) v += ar[kk] * Cs[kk * T32 + cl];
+        double* y = Y + row * ldy + col;
+        *y = (beta == 0.0 ? 0.0 : beta * *y) + alpha * v;
+    }
+}
+hipError_t launch_tsgemm_nn(const double* A, int64_t lda, int64_t n, int32_t ka, const double* C, int32_t kb,
+                            double alpha, double beta, double* Y, int64_t ldy, hipStream_t s) {
+    if (kb <= 0 || n <= 0) return hipSuccess;
+    const int64_t chunk = 2048;
+    const size_t lds = (size_t)ka * T32 * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsgemm_nn),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e0 != hipSuccess) return e0;
+        attr = true;
+    }
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    k_tsgemm_nn<<<dim3((unsigned)cdiv(n, chunk), (unsigned)cdiv(kb, T32)), 256, lds, s>>>(A, lda, n, ka, C, kb, alpha,
+                                                                                           beta, Y, ldy, chunk);
+    return hipGetLastError();
+}
+// out[c] = sum_r A[r, c] B[r, c], c < k
+__global__ __launch_bounds__(256) void k_coldot_partial(const double* __restrict__ A, const double* __restrict__ B,
+                                                        int64_t n, int64_t ld, int32_t k, int64_t chunk,
+                                                        double* __restrict__ partial) {
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int lr = threadIdx.x >> 6;
+    const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+    double a = 0;
+    if (c < k)
+        for (int64_t r = r0 + lr; r < r1; r += 4) a += A[r * ld + c] * B[r * ld + c];
+    __shared__ double sa[4][64];
+    sa[lr][threadIdx.x & 63] = a;
+    __syncthreads();
+    if (threadIdx.x < 64 && c < k) partial[(int64_t)blockIdx.x * k + c] = sa[0][threadIdx.x] + sa[1][threadIdx.x] +
+                                                                          sa[2][threadIdx.x] + sa[3][threadIdx.x];
+}
+__global__ void k_coldot_reduce(const double* __restrict__ partial, int64_t nch, int32_t k, double* out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= k) return;
+    double a = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) a += partial[ch * k + c];
+    out[c] = a;
+}
+int64_t coldot_partial_doubles(int64_t n, int32_t k) { return cdiv(n, 16384) * (int64_t)k; }
+hipError_t launch_coldot(const double* A, const double* B, int64_t n, int64_t ld, int32_t k, double* partial,
+                         double* out, hipStream_t s) {
+    if (k <= 0 || n <= 0) return hipSuccess;
+    const int64_t chunk = 16384, nch = cdiv(n, chunk);
+    k_coldot_partial<<<dim3((unsigned)nch, (unsigned)cdiv(k, 64)), 256, 0, s>>>(A, B, n, ld, k, chunk, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_coldot_reduce<<<(unsigned)cdiv(k, 256), 256, 0, s>>>(partial, nch, k, out);
+    return hipGetLastError();
+}
+// Y[r, c] -= m[r] lam[c] X[r, c]
+__global__ void k_shift_cols(double* Y, const double* X, const double* m, const double* lam, int64_t n, int64_t ld,
+                             int32_t k) {
+    const int64_t tot = n * k;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t / k;
+        const int c = (int)(t % k);
+        Y[r * ld + c] -= m[r] * lam[c] * X[r * ld + c];
+    }
+}
+hipError_t launch_shift_cols(double* Y, const double* X, const double* m, const double* lam, int64_t n, int64_t ld,
+                             int32_t k, hipStream_t s) {
+    if (n <= 0 || k <= 0) return hipSuccess;
+    k_shift_cols<<<grid_for(n * k, 256), 256, 0, s>>>(Y, X, m, lam, n, ld, k);
+    return hipGetLastError();
+}
+// mode 0: Y += coef[c] X ; mode 1: Y -= coef[c] X ; mode 2: Y = X + coef[c] Y
+__global__ void k_axpy_cols(double* Y, const double* X, const double* coef, int mode, int64_t n, int64_t ld, int32_t k) {
+    const int64_t tot = n * k;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t / k;
+        const int c = (int)(t % k);
+        double* y = Y + r * ld + c;
+        const double x = X[r * ld + c];
+        if (mode == 0) *y += coef[c] * x;
+        else if (mode == 1) *y -= coef[c] * x;
+        else *y = x + coef[c] * *y;
+    }
+}
+hipError_t launch_axpy_cols(double* Y, const double* X, const double* coef, int mode, int64_t n, int64_t ld, int32_t k,
+                            hipStream_t s) {
+    if (n <= 0 || k <= 0) return hipSuccess;
+    k_axpy_cols<<<grid_for(n * k, 256), 256, 0, s>>>(Y, X, coef, mode, n, ld, k);
+    return hipGetLastError();
+}
+// out[c] = (den[c] != 0) ? num[c] / den[c] : 0
+__global__ void k_div_cols(const double* num, const double* den, double* out, int32_t k) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < k) out[c] = den[c] != 0.0 ? num[c] / den[c] : 0.0;
+}
+hipError_t launch_div_cols(const double* num, const double* den, double* out, int32_t k, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    k_div_cols<<<(unsigned)cdiv(k, 256), 256, 0, s>>>(num, den, out, k);
+    return hipGetLastError();
+}
+
+// ============================================================ assembly derivative (vertex positions)
+// Per vertex (mesh order): nu_i = rho_i sum_k [ -lam_k glam_k x_ki^2 + lam_k w_ki x_ki - y_ki x_ki / 2 ],
+// the coefficient of the lumped-mass derivative (Y = X_cluster Gamma carries
+// the normalisation terms).
+__global__ void k_bwd_vertex(int64_t nv, int32_t p, const double* __restrict__ X, const double* __restrict__ W,
+                             const double* __restrict__ Y, int64_t ld, const int32_t* __restrict__ iperm,
+                             const double* __restrict__ lam, const double* __restrict__ glam,
+                             const double* __restrict__ rho, double* __restrict__ nu) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = iperm[v];
+        double s = 0;
+        for (int k = 0; k < p; ++k) {
+            const double x = X[r * ld + k];
+            double t = 0;
+            if (glam) t -= lam[k] * glam[k] * x * x;
+            if (W) t += lam[k] * W[r * ld + k] * x;
+            if (Y) t -= 0.5 * Y[r * ld + k] * x;
+            s += t;
+        }
+        nu[v] = (rho ? rho[v] : 1.0) * s;
+    }
+}
+hipError_t launch_bwd_vertex(int64_t nv, int32_t p, const double* X, const double* W, const double* Y, int64_t ld,
+                             const int32_t* iperm, const double* lam, const double* glam, const double* rho, double* nu,
+                             hipStream_t s) {
+    k_bwd_vertex<<<grid_for(nv, 256), 256, 0, s>>>(nv, p, X, W, Y, ld, iperm, lam, glam, rho, nu);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Per triangle: derivative of sum over corners of (1/2) e_opp cot(theta) plus
+// (nu_a + nu_b + nu_c)/3 * area, with e_opp = sum_k [glam_k (x_i - x_j)^2 -
+// (w_i - w_j)(x_i - x_j)] over the edge opposite the corner.  G[t][corner][xyz].
+__global__ void k_bwd_tri(int64_t nf, const int32_t* __restrict__ F, const double* __restrict__ V, int32_t p,
+                          const double* __restrict__ X, const double* __restrict__ W, int64_t ld,
+                          const int32_t* __restrict__ iperm, const double* __restrict__ glam,
+                          const double* __restrict__ nu, double* __restrict__ G) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t vi[3] = {F[3 * t], F[3 * t + 1], F[3 * t + 2]};
+        const int64_t ri[3] = {iperm[vi[0]], iperm[vi[1]], iperm[vi[2]]};
+        double P[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) P[a][d] = V[3 * (int64_t)vi[a] + d];
+        double e[3] = {0, 0, 0};   // per corner: its opposite edge
+        for (int k = 0; k < p; ++k) {
+            const double x0 = X[ri[0] * ld + k], x1 = X[ri[1] * ld + k], x2 = X[ri[2] * ld + k];
+            const double xs[3] = {x0, x1, x2};
+            double ws[3] = {0, 0, 0};
+            if (W) { ws[0] = W[ri[0] * ld + k]; ws[1] = W[ri[1] * ld + k]; ws[2] = W[ri[2] * ld + k]; }
+            const double g = glam ? glam[k] : 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const int i = (c + 1) % 3, j = (c + 2) % 3;
+                const double dx = xs[i] - xs[j], dw = ws[i] - ws[j];
+                e[c] += g * dx * dx - dw * dx;
+            }
+        }
+        double grad[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int c = 0; c < 3; ++c) {
+            const int i = (c + 1) % 3, j = (c + 2) % 3;
+            double u[3], w[3], cr[3];
+            for (int d = 0; d < 3; ++d) { u[d] = P[i][d] - P[c][d]; w[d] = P[j][d] - P[c][d]; }
+            cross3(u, w, cr);
+            const double dot = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+            const double s2 = cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2];
+            const double sn = sqrt(s2);
+            double wc[3], cu[3];
+            cross3(w, cr, wc);
+            cross3(cr, u, cu);
+            const double f = 0.5 * e[c];
+            for (int d = 0; d < 3; ++d) {
+                const double du = w[d] / sn - dot * wc[d] / (s2 * sn);   // d cot / d u
+                const double dw = u[d] / sn - dot * cu[d] / (s2 * sn);   // d cot / d w
+                grad[i][d] += f * du;
+                grad[j][d] += f * dw;
+                grad[c][d] -= f * (du + dw);
+            }
+        }
+        // area term
+        {
+            double e1[3], e2[3], cr[3], a1[3], a2[3];
+            for (int d = 0; d < 3; ++d) { e1[d] = P[1][d] - P[0][d]; e2[d] = P[2][d] - P[0][d]; }
+            cross3(e1, e2, cr);
+            const double sn = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+            cross3(e2, cr, a1);
+            cross3(cr, e1, a2);
+            const double f = (nu[vi[0]] + nu[vi[1]] + nu[vi[2]]) / 3.0 * 0.5 / sn;
+            for (int d = 0; d < 3; ++d) {
+                grad[1][d] += f * a1[d];
+                grad[2][d] += f * a2[d];
+                grad[0][d] -= f * (a1[d] + a2[d]);
+            }
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) G[9 * t + 3 * a + d] = grad[a][d];
+    }
+}
+hipError_t launch_bwd_tri(int64_t nf, const int32_t* F, const double* V, int32_t p, const double* X, const double* W,
+                          int64_t ld, const int32_t* iperm, const double* glam, const double* nu, double* G,
+                          hipStream_t s) {
+    k_bwd_tri<<<grid_for(nf, 256), 256, 0, s>>>(nf, F, V, p, X, W, ld, iperm, glam, nu, G);
+    return hipGetLastError();
+}
+// gradV[v] = sum over the (triangle, corner) entries listed for v, in list order
+__global__ void k_bwd_gather(int64_t nv, const int64_t* __restrict__ vt_ptr, const int64_t* __restrict__ vt,
+                             const double* __restrict__ G, double* __restrict__ gradV) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        double g[3] = {0, 0, 0};
+        for (int64_t e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e)
+            for (int d = 0; d < 3; ++d) g[d] += G[3 * vt[e] + d];
+        for (int d = 0; d < 3; ++d) gradV[3 * v + d] = g[d];
+    }
+}
+hipError_t launch_bwd_gather(int64_t nv, const int64_t* vt_ptr, const int64_t* vt, const double* G, double* gradV,
+                             hipStream_t s) {
+    k_bwd_gather<<<grid_for(nv, 256), 256, 0, s>>>(nv, vt_ptr, vt, G, gradV);
+    return hipGetLastError();
+}
+// out[r, c] = in[c * nv + perm[r]] for r < n, c < k (column-major mesh order -> row-major internal order)
+__global__ void k_import_cols(const double* in, int64_t nv, const int32_t* perm, int64_t n, int32_t k, double* out,
+                              int64_t ld) {
+    const int64_t tot = n * k;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t % n;
+        const int c = (int)(t / n);
+        out[r * ld + c] = in[(int64_t)c * nv + perm[r]];
+    }
+}
+hipError_t launch_import_cols(const double* in, int64_t nv, const int32_t* perm, int64_t n, int32_t k, double* out,
+                              int64_t ld, hipStream_t s) {
+    if (n <= 0 || k <= 0) return hipSuccess;
+    k_import_cols<<<grid_for(n * k, 256), 256, 0, s>>>(in, nv, perm, n, k, out, ld);
     return hipGetLastError();
 }
 

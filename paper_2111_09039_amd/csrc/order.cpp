@@ -191,6 +191,7 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
         for (size_t c = 0; c < children[i].size(); ++c) sy.fronts[children[i][c]].child_slot = (int32_t)c;
         sy.max_children = std::max<int32_t>(sy.max_children, (int32_t)children[i].size());
         const double m = f.ns + f.mu;
+        sy.factor_nnz += (int64_t)f.ns * (f.ns + 1) / 2 + (int64_t)f.ns * f.mu;
         for (int c = 0; c < f.ns; ++c) {
             const double r = m - c - 1;
             sy.flops += r * r + 2 * r;      // rank-1 update of the lower trailing part + column scaling

@@ -181,3 +181,144 @@ def test_hsim_end_to_end(cuda, case):
     # sign convention: largest-magnitude entry positive
     idx = np.argmax(np.abs(X), axis=0)
     assert (X[idx, np.arange(p)] > 0).all()
+
+
+# ---------------------------------------------------------------- mixed precision
+def test_mixed_solve_refinement(small):
+    import paper_2111_09039_amd as hs
+    V, F, S, m, lv, H = small
+    rng = np.random.default_rng(7)
+    for tau in (0, 1):
+        St, Mt = lv[tau]["S"], _mass(lv, tau)
+        n = St.shape[0]
+        mu = 3.0
+        H.factor(tau, mu, precision=hs.MIXED)
+        B = rng.standard_normal((n, 9))
+        X = H.solve_shifted(tau, _t(B), precision=hs.MIXED, refine_tol=1e-13).cpu().numpy()
+        A = (St - mu * Mt).tocsc()
+        Xr = spla.splu(A).solve(B)
+        assert np.abs(X - Xr).max() <= 1e-10 * np.abs(Xr).max(), tau
+        rel = np.linalg.norm(A @ X - B, axis=0) / np.linalg.norm(B, axis=0)
+        assert rel.max() <= 1e-13
+
+
+def test_mixed_gram(small):
+    import paper_2111_09039_amd as hs
+    V, F, S, m, lv, H = small
+    rng = np.random.default_rng(8)
+    for tau in range(3):
+        n = len(lv[tau]["verts"])
+        Psi = rng.standard_normal((n, 30))
+        Sb, Mb = H.gram(tau, _t(Psi), precision=hs.MIXED)
+        Sr = Psi.T @ (lv[tau]["S"] @ Psi)
+        Mr = Psi.T @ (_mass(lv, tau) @ Psi)
+        # FP32 rounding of the operands and FP32 accumulation over 256 rows
+        assert np.abs(Sb.cpu().numpy() - Sr).max() <= 2e-5 * np.abs(Sr).max()
+        assert np.abs(Mb.cpu().numpy() - Mr).max() <= 2e-5 * np.abs(Mr).max()
+        assert np.abs(Sb.cpu().numpy() - Sr).max() > 0      # really the low-precision path
+
+
+def test_hsim_mixed_end_to_end(cuda):
+    import paper_2111_09039_amd as hs
+    V, F, d = synth.config_mesh("sphere2k", seed=0)
+    p = 20
+    S, m = assembly.assemble(V, F)
+    H = hs.Hierarchy(V, F, p, levels=3, n_coarsest=300)
+    ev, X, r, st = H.solve(tol=1e-6, precision=hs.MIXED)
+    ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
+    lr, Xr, _, _ = sim.sim_lowest(S, m, p + 10, eps=1e-12)
+    rel = np.abs(ev - lr[:p])[1:] / lr[1:p]
+    print(f"[mixed] max rel eig err {rel.max():.2e}, refine {st['refine_steps']}, escalated {st['escalated']}")
+    assert rel.max() <= 1e-6
+    assert r.max() < 1e-6
+    assert sim.residual(S, m, X, ev).max() < 1.5e-6
+    assert metrics.m_orthonormality(X, m) < 1e-8
+
+
+# ---------------------------------------------------------------- adjoint
+def _adjoint_mesh(nu=40, nv_=24, seed=0):
+    rng = np.random.default_rng(seed)
+    V, F = synth.torus(nu, nv_)
+    V = synth.isotropic_noise(V, F, 0.2 * synth.mean_edge_length(V, F), rng)
+    return V, F
+
+
+def test_adjoint_eigenvalues_vs_dense_reference(cuda):
+    import torch
+    import paper_2111_09039_amd as hs
+    from oracle import gradient
+    V, F = _adjoint_mesh()
+    p = 16
+    wl = np.random.default_rng(1).uniform(0.5, 2.0, p)
+    H = hs.Hierarchy(V, F, p, levels=2, n_coarsest=200)
+    ev, X, r, st = H.solve(tol=1e-11, save_forward=True)
+    gl = torch.from_numpy(2 * wl * ev.cpu().numpy()).cuda()
+    gV = H.backward(grad_evals=gl).cpu().numpy()
+    gr, lam, _ = gradient.reference_gradient(V, F, p, grad_lam=lambda l: 2 * wl * l)
+    assert np.abs(ev.cpu().numpy() - lam)[1:].max() < 1e-9 * lam[-1]
+    err = np.linalg.norm(gV - gr) / np.linalg.norm(gr)
+    print(f"[adjoint eigenvalues] rel err vs dense reference {err:.2e}")
+    assert err < 1e-7
+
+
+def test_adjoint_eigenvectors_vs_dense_reference(cuda):
+    import torch
+    import paper_2111_09039_amd as hs
+    from oracle import gradient
+    V, F = _adjoint_mesh(seed=2)
+    p = 12
+    H = hs.Hierarchy(V, F, p, levels=2, n_coarsest=200)
+    ev, X, r, st = H.solve(tol=1e-11, save_forward=True)
+    lam = ev.cpu().numpy()
+    cl = gradient.clusters_of(lam, 1e-2)
+    T = np.random.default_rng(4).standard_normal((len(V), p))
+
+    def grad_X(Xn):
+        G = np.zeros_like(Xn)
+        for c in np.unique(cl[:p]):
+            idx = np.nonzero(cl[:p] == c)[0]
+            G[:, idx] = 2 * T[:, idx] @ (Xn[:, idx].T @ T[:, idx]).T
+        return G
+
+    gX = torch.from_numpy(grad_X(X.cpu().numpy())).cuda()
+    gV = H.backward(grad_evecs=gX).cpu().numpy()
+    gr, _, _ = gradient.reference_gradient(V, F, p, grad_X=grad_X)
+    err = np.linalg.norm(gV - gr) / np.linalg.norm(gr)
+    print(f"[adjoint eigenvectors] rel err vs dense reference {err:.2e}")
+    assert err < 1e-6
+
+
+def test_autograd_function_fd(cuda):
+    import torch
+    import paper_2111_09039_amd as hs
+    from paper_2111_09039_amd.autograd import eigs
+    from oracle import gradient
+    V, F = _adjoint_mesh(30, 20, seed=7)
+    p = 10
+    Vt = torch.tensor(V, requires_grad=True)
+    Ft = torch.tensor(F)
+    ev, X = eigs(Vt, Ft, p, levels=2, n_coarsest=150, tol=1e-12)
+    cl = gradient.clusters_of(ev.detach().cpu().numpy(), 1e-2)
+    T = torch.from_numpy(np.random.default_rng(3).standard_normal((len(V), p))).cuda()
+    wl = torch.linspace(0.5, 1.5, p, dtype=torch.float64, device=ev.device)
+
+    def loss_fn(ev, X):
+        tot = (wl * ev ** 2).sum()
+        for c in np.unique(cl[:p]):
+            idx = torch.from_numpy(np.nonzero(cl[:p] == c)[0]).cuda()
+            tot = tot + ((X[:, idx].T @ T[:, idx]) ** 2).sum()
+        return tot
+
+    loss_fn(ev, X).backward()
+    g = Vt.grad.numpy()
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        D = rng.standard_normal(V.shape)
+        h = 1e-6
+        with torch.no_grad():
+            lp = loss_fn(*eigs(torch.tensor(V + h * D), Ft, p, levels=2, n_coarsest=150, tol=1e-12)).item()
+            lm = loss_fn(*eigs(torch.tensor(V - h * D), Ft, p, levels=2, n_coarsest=150, tol=1e-12)).item()
+        fd = (lp - lm) / (2 * h)
+        an = float(np.sum(g * D))
+        print(f"[autograd fd] fd {fd:.10e} adjoint {an:.10e}")
+        assert abs(fd - an) <= 1e-5 * abs(fd)

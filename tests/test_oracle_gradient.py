@@ -1,0 +1,85 @@
+"""Pins of the dense reference gradient (oracle/gradient.py) against central
+finite differences of library eigensolves and exact invariances."""
+import numpy as np
+import scipy.linalg as sl
+
+import synth
+from oracle import assembly, gradient
+
+
+def _mesh(seed=0):
+    rng = np.random.default_rng(seed)
+    V, F = synth.torus(14, 9)
+    V = synth.isotropic_noise(V, F, 0.15 * synth.mean_edge_length(V, F), rng)
+    return V, F, synth.random_density(len(V), rng)
+
+
+def _eig(V, F, d):
+    S, m = assembly.assemble(V, F, density=d)
+    return sl.eigh(S.toarray(), np.diag(m))
+
+
+def _loss_parts(p, seed=1):
+    rng = np.random.default_rng(seed)
+    wl = rng.uniform(0.5, 2.0, p)
+    T = rng.standard_normal((0, p))  # placeholder
+    return wl
+
+
+def test_eigenvalue_gradient_matches_fd():
+    V, F, d = _mesh()
+    p = 8
+    wl = np.random.default_rng(1).uniform(0.5, 2.0, p)
+    loss = lambda lam: np.sum(wl * lam[:p] ** 2)
+    g, lam, X = gradient.reference_gradient(V, F, p, grad_lam=lambda l: 2 * wl * l, density=d)
+    rng = np.random.default_rng(2)
+    for _ in range(4):
+        D = rng.standard_normal(V.shape)
+        h = 1e-6
+        fd = (loss(_eig(V + h * D, F, d)[0]) - loss(_eig(V - h * D, F, d)[0])) / (2 * h)
+        assert abs(fd - np.sum(g * D)) <= 1e-6 * abs(fd)
+
+
+def test_eigenvector_gradient_matches_fd():
+    V, F, d = _mesh(3)
+    p = 10
+    lam0, X0 = _eig(V, F, d)
+    cl = gradient.clusters_of(lam0, 1e-2)
+    T = np.random.default_rng(4).standard_normal((len(V), p))
+
+    def loss_of(X):
+        # sum over clusters of ||X_C^T T_C||_F^2: invariant to signs and rotations in a cluster
+        tot = 0.0
+        for c in np.unique(cl[:p]):
+            idx = np.nonzero(cl[:p] == c)[0]
+            tot += np.sum((X[:, idx].T @ T[:, idx]) ** 2)
+        return tot
+
+    def grad_X(X):
+        G = np.zeros_like(X)
+        for c in np.unique(cl[:p]):
+            idx = np.nonzero(cl[:p] == c)[0]
+            A = X[:, idx].T @ T[:, idx]
+            G[:, idx] = 2 * T[:, idx] @ A.T
+        return G
+
+    g, lam, X = gradient.reference_gradient(V, F, p, grad_X=grad_X, density=d)
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        D = rng.standard_normal(V.shape)
+        h = 1e-6
+        fd = (loss_of(_eig(V + h * D, F, d)[1][:, :p]) - loss_of(_eig(V - h * D, F, d)[1][:, :p])) / (2 * h)
+        assert abs(fd - np.sum(g * D)) <= 1e-5 * max(abs(fd), 1e-8)
+
+
+def test_gradient_invariances():
+    """Translation and rotation invariance; scaling: sum_v x_v . grad lambda_k = -2 lambda_k."""
+    V, F, d = _mesh(6)
+    p = 6
+    for k in range(1, p):
+        e = np.zeros(p)
+        e[k] = 1.0
+        g, lam, _ = gradient.reference_gradient(V, F, p, grad_lam=lambda l, e=e: e, density=d)
+        assert np.abs(g.sum(axis=0)).max() < 1e-10 * np.abs(g).max()
+        assert np.abs(np.cross(V, g).sum(axis=0)).max() < 1e-9 * np.abs(g).max()
+        assert abs(np.sum(V * g) + 2 * lam[k]) < 1e-10 * lam[k]
