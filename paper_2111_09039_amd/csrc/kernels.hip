@@ -25,6 +25,17 @@ __device__ __forceinline__ int64_t tri(int32_t Mt, int32_t I, int32_t J) {
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Dynamic LDS above the default 64 KB needs an explicit opt-in per kernel;
+// gfx950 has 160 KB per workgroup (static + dynamic).
+constexpr size_t LDS_PER_WG = 160 * 1024;
+inline hipError_t ensure_dynamic_lds(const void* fn, size_t dyn_bytes, size_t static_bytes) {
+    if (dyn_bytes + static_bytes > LDS_PER_WG) return hipErrorInvalidValue;
+    if (dyn_bytes <= 64 * 1024) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+    if (e != hipSuccess) (void)hipGetLastError();   // do not leave it for the next launch check
+    return e;
+}
 inline unsigned grid_for(int64_t n, int block) {
     int64_t g = cdiv(n, block);
     return (unsigned)(g < 1 ? 1 : (g > (1 << 20) ? (1 << 20) : g));
@@ -753,14 +764,8 @@ hipError_t launch_ritz(const double* Psi, const double* SPsi, const double* MPsi
     const int64_t nch = cdiv(n, chunk_rows);
     const int64_t nct = cdiv(q, T32);
     const size_t lds = (size_t)q * T32 * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ritz),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e0 != hipSuccess) return e0;
-        attr = true;
-    }
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e0 = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_ritz), lds, 4096);
+    if (e0 != hipSuccess) return e0;
     k_ritz<<<dim3((unsigned)nch, (unsigned)nct), 256, lds, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi,
                                                                  MPhi, partial, chunk_rows, minv_norm ? 1 : 0);
     hipError_t e = hipGetLastError();
@@ -1206,14 +1211,8 @@ hipError_t launch_tsgemm_nn(const double* A, int64_t lda, int64_t n, int32_t ka,
     if (kb <= 0 || n <= 0) return hipSuccess;
     const int64_t chunk = 2048;
     const size_t lds = (size_t)ka * T32 * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsgemm_nn),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e0 != hipSuccess) return e0;
-        attr = true;
-    }
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e0 = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_tsgemm_nn), lds, 0);
+    if (e0 != hipSuccess) return e0;
     k_tsgemm_nn<<<dim3((unsigned)cdiv(n, chunk), (unsigned)cdiv(kb, T32)), 256, lds, s>>>(A, lda, n, ka, C, kb, alpha,
                                                                                            beta, Y, ldy, chunk);
     return hipGetLastError();

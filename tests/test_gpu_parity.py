@@ -23,8 +23,8 @@ def small(cuda):
     V, F = synth.icosphere(3)
     V = synth.radial_jitter(V, 1e-2, rng)
     S, m = assembly.assemble(V, F)
-    lv = hierarchy.build_hierarchy(V, F, S, m, p=10, levels=3, n_coarsest=120, seed=17)
-    H = hs.Hierarchy(V, F, 10, levels=3, n_coarsest=120, seed=17)
+    lv = hierarchy.build_hierarchy(V, F, S, m, p=24, levels=3, n_coarsest=120, seed=17)
+    H = hs.Hierarchy(V, F, 24, levels=3, n_coarsest=120, seed=17)
     print(f"[small hierarchy] sizes {[len(l['verts']) for l in lv]}", flush=True)
     return V, F, S, m, lv, H
 
@@ -83,7 +83,8 @@ def test_factor_inertia_and_solve(small, tau):
         # normwise backward error per column (infinity norms)
         Ainf = np.abs(A).sum(axis=1).max()
         bw = (np.abs(A @ X - B).max(axis=0) / (Ainf * np.abs(X).max(axis=0) + np.abs(B).max(axis=0))).max()
-        assert bw < 1e-14, bw
+        # bound c n u of a backward-stable solve (n = 642)
+        assert bw < 1e-13, bw
 
 
 def test_gram(small):
@@ -91,7 +92,7 @@ def test_gram(small):
     rng = np.random.default_rng(3)
     for tau in range(3):
         n = len(lv[tau]["verts"])
-        for k in (5, 30, 33):
+        for k in (5, 30, 36):
             Psi = rng.standard_normal((n, k))
             Sb, Mb = H.gram(tau, _t(Psi))
             Sr = Psi.T @ (lv[tau]["S"] @ Psi)
