@@ -123,15 +123,16 @@ struct Prof {
 // tiled front kernels, C = D^-1/2 L^-1 (E S E) L^-T D^-1/2, cyclic Jacobi on C,
 // X = E L^-T D^-1/2 V.
 struct DenseGEP {
-    int32_t k = 0, m = 0, ns_pad = 0, Mt = 0;
+    int32_t k = 0, m = 0, ns_pad = 0, Mt = 0, bj = 16;
     std::vector<int64_t> diag_ptr, panel_ptr, upd_ptr;
     DeviceBuffer front, tiles, linv, D, items_diag, items_panel, items_upd, gptr, counters;
-    DeviceBuffer S2, M2, e, W, W2, C, V, dcur, ocur, dnext, onext, rot, dis, normf;
+    DeviceBuffer S2, M2, e, W, W2, C, V, Qs, rot, dis, normf;
 
     void setup(int32_t kk) {
         if (k == kk) return;
         k = kk;
-        m = k + (k & 1);
+        bj = k <= 256 ? 16 : 32;                       // block Jacobi block size
+        m = (int32_t)round_up(k, 2 * bj);
         ns_pad = (int32_t)round_up(k, NB);
         Mt = ns_pad / NB;
         DFront f{};
@@ -171,10 +172,7 @@ struct DenseGEP {
         dis.alloc((size_t)m * sizeof(double));
         C.alloc((size_t)m * m * sizeof(double));
         V.alloc((size_t)m * m * sizeof(double));
-        dcur.alloc((size_t)m * sizeof(double));
-        ocur.alloc((size_t)m * sizeof(double));
-        dnext.alloc((size_t)m * sizeof(double));
-        onext.alloc((size_t)m * sizeof(double));
+        Qs.alloc((size_t)(m / (2 * bj)) * (2 * bj) * (2 * bj) * sizeof(double));
         rot.alloc(4 * sizeof(int32_t));
         normf.alloc(2 * sizeof(double));
     }
@@ -196,9 +194,8 @@ struct DenseGEP {
     }
 
     int32_t qc_for(int32_t ncols) const {
-        int32_t qc = 32;
-        while (qc > 1 && (int64_t)(ns_pad + NB) * qc * 8 > 64 * 1024) qc /= 2;
-        (void)ncols;
+        const int32_t qc = solve_chunk_width(ns_pad, ncols, false);
+        if (!qc) fail(HSIM_E_UNIMPLEMENTED, "dense problem of size %d exceeds the solve kernels' LDS", k);
         return qc;
     }
 
@@ -233,20 +230,15 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     HIPCHECK(launch_sym_scale(dptr<double>(W2), dptr<double>(D), k, dptr<double>(W), s));
     HIPCHECK(launch_embed_pad(dptr<double>(W), k, m, dptr<double>(C), dptr<double>(normf), dptr<double>(dis),
                               dptr<double>(D), s));
-    HIPCHECK(launch_jacobi_init(dptr<double>(C), m, dptr<double>(V), dptr<double>(dcur), dptr<double>(ocur), s));
+    HIPCHECK(launch_identity(dptr<double>(V), m, s));
     const double tol_rel = 1e-15;
+    const int32_t nb = m / bj;
     int32_t sweeps = 0;
-    int64_t round = 0;
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
         HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 1, 0, s));
-        for (int32_t r = 0; r < m - 1; ++r, ++round) {
-            HIPCHECK(launch_jacobi_round(dptr<double>(C), dptr<double>(V), m, (int32_t)(round % (m - 1)),
-                                         dptr<double>(dcur), dptr<double>(ocur), dptr<double>(dnext),
-                                         dptr<double>(onext), tol_rel, dptr<double>(normf), 1e-17,
-                                         dptr<int32_t>(rot), s));
-            std::swap(dcur.p, dnext.p);
-            std::swap(ocur.p, onext.p);
-        }
+        for (int32_t r = 0; r < nb - 1; ++r)
+            HIPCHECK(launch_bj_round(bj, dptr<double>(C), dptr<double>(V), m, r, dptr<double>(Qs), dptr<double>(normf),
+                                     tol_rel, 1e-17, 3, dptr<int32_t>(rot), s));
         int32_t nrot = 0;
         HIPCHECK(hipMemcpyAsync(&nrot, rot.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
@@ -261,8 +253,17 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
 }
 
 // ================================================================ levels
+// tree levels whose widest supernode has at least this many (padded) pivots
+// use the multi-workgroup block solve
+constexpr int32_t BIG_NS = 256;
+
 struct TLev {
-    int32_t f0 = 0, f1 = 0, ns_pad_max = 0, qc = 1;
+    int32_t f0 = 0, f1 = 0, ns_pad_max = 0;
+    // wide supernodes: multi-workgroup block solve (item lists in Level::big_items)
+    bool big = false;
+    int32_t nblk = 0;
+    int64_t fwd_init[2] = {0, 0}, bwd_init[2] = {0, 0};   // [offset (ints), count]
+    std::vector<int64_t> fdiag, fupd, bdiag, bupd;       // per block: offset, count pairs
     double l_entries = 0, pivots = 0;    // unpadded L entries and pivot rows of the level's fronts
     int32_t step0 = 0, step1 = 0;
     std::vector<int32_t> ea_tile_cols;   // per child slot: max tile columns of the children's update blocks
@@ -284,7 +285,7 @@ struct Level {
     DeviceBuffer dS_ptr, dS_idx, dS_val, dM_val, dmdiag, dU_ptr, dU_idx, dU_val, dperm;
     DeviceBuffer dfronts, tiles, linv, D, tiles32, linv32, D32, counters;
     DeviceBuffer asm_dst, asm_src, it_diag, it_panel, it_upd, it_ea, rel, rows, gptr, gidx;
-    DeviceBuffer ubuf;
+    DeviceBuffer ubuf, big_items;
     double mu = 0;
     bool factored = false, factored32 = false;
     int32_t neg_pivots = 0;
@@ -425,6 +426,7 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
     // per tree level launch data
     const int32_t mc = std::max<int32_t>(1, sy.max_children);
     L.tl.resize(sy.tree_levels);
+    std::vector<int32_t> big;
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
         TLev& T = L.tl[t];
         T.f0 = sy.tlev_ptr[t];
@@ -435,9 +437,51 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
             T.l_entries += (double)f.ns * (f.ns + 1) / 2 + (double)f.ns * f.mu;
             T.pivots += f.ns;
         }
-        if ((int64_t)(T.ns_pad_max + NB) * 8 > 64 * 1024) fail(HSIM_E_UNIMPLEMENTED, "supernode wider than the solve kernels support");
-        T.qc = 32;
-        while (T.qc > 1 && (int64_t)(T.ns_pad_max + NB) * T.qc * 8 > 64 * 1024) T.qc /= 2;
+        T.big = T.ns_pad_max >= BIG_NS;
+        if (!T.big && !solve_chunk_width(T.ns_pad_max, 1, false))
+            fail(HSIM_E_UNIMPLEMENTED, "supernode of %d pivots exceeds the solve kernels' LDS", T.ns_pad_max);
+        if (T.big) {
+            // item lists of the multi-workgroup block solve
+            auto push = [&](int32_t a, int32_t b) { big.push_back(a); big.push_back(b); };
+            int32_t maxnsb = 0;
+            for (int32_t i = T.f0; i < T.f1; ++i) maxnsb = std::max(maxnsb, sy.fronts[i].nsb);
+            T.nblk = (maxnsb + BIG_BLOCK_TILES - 1) / BIG_BLOCK_TILES;
+            T.fwd_init[0] = (int64_t)big.size();
+            for (int32_t i = T.f0; i < T.f1; ++i) {
+                const Front& f = sy.fronts[i];
+                const int32_t st = (f.mu + NB - 1) / NB;
+                for (int32_t r = 0; r < f.nsb + st; ++r) push(i, r);
+            }
+            T.fwd_init[1] = ((int64_t)big.size() - T.fwd_init[0]) / 2;
+            T.bwd_init[0] = (int64_t)big.size();
+            for (int32_t i = T.f0; i < T.f1; ++i)
+                for (int32_t r = 0; r < sy.fronts[i].nsb; ++r) push(i, r);
+            T.bwd_init[1] = ((int64_t)big.size() - T.bwd_init[0]) / 2;
+            for (int32_t kb = 0; kb < T.nblk; ++kb) {
+                int64_t o = (int64_t)big.size();
+                for (int32_t i = T.f0; i < T.f1; ++i)
+                    if (sy.fronts[i].nsb > kb * BIG_BLOCK_TILES) big.push_back(i);
+                const int64_t cnt = (int64_t)big.size() - o;
+                T.fdiag.push_back(o); T.fdiag.push_back(cnt);
+                T.bdiag.push_back(o); T.bdiag.push_back(cnt);
+                o = (int64_t)big.size();
+                for (int32_t i = T.f0; i < T.f1; ++i) {
+                    const Front& f = sy.fronts[i];
+                    if (f.nsb <= kb * BIG_BLOCK_TILES) continue;
+                    const int32_t t1 = std::min(f.nsb, (kb + 1) * BIG_BLOCK_TILES);
+                    const int32_t st = (f.mu + NB - 1) / NB;
+                    for (int32_t r = t1; r < f.nsb + st; ++r) push(i, r);
+                }
+                T.fupd.push_back(o); T.fupd.push_back(((int64_t)big.size() - o) / 2);
+                o = (int64_t)big.size();
+                for (int32_t i = T.f0; i < T.f1; ++i) {
+                    const Front& f = sy.fronts[i];
+                    if (f.nsb <= kb * BIG_BLOCK_TILES) continue;
+                    for (int32_t r = 0; r < kb * BIG_BLOCK_TILES; ++r) push(i, r);
+                }
+                T.bupd.push_back(o); T.bupd.push_back(((int64_t)big.size() - o) / 2);
+            }
+        }
         T.step0 = sy.step_ptr[t];
         T.step1 = sy.step_ptr[t + 1];
         T.ea_tile_cols.assign(mc, 0);
@@ -445,6 +489,7 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
             for (int64_t e = sy.ea_ptr[(int64_t)t * mc + c]; e < sy.ea_ptr[(int64_t)t * mc + c + 1]; ++e)
                 T.ea_tile_cols[c] = std::max<int32_t>(T.ea_tile_cols[c], (sy.fronts[sy.ea[e]].mu + NB - 1) / NB);
     }
+    L.big_items.upload(big.empty() ? std::vector<int32_t>{0, 0} : big);
 }
 
 // ----------------------------------------------------------- factor / solve
@@ -518,12 +563,29 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
     const DFront* fr = dptr<DFront>(L.dfronts);
     Prof& P = H->prof;
     const double bL = sizeof(TF);
+    const int32_t* bi = dptr<int32_t>(L.big_items);
+    auto big = [&](int phase, const int64_t* rec, int32_t kb) {
+        HIPCHECK(launch_big_solve<TF>(phase, tiles, linv, D, fr, bi + rec[0], rec[1], kb, X, H->ld, col0, ncols,
+                                      dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr), dptr<int64_t>(L.gidx), md,
+                                      dptr<int32_t>(L.rows), s));
+    };
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
         const TLev& T = L.tl[t];
         const double bytes = bL * T.l_entries + 2.0 * 8.0 * T.pivots * ncols;
         const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
+        if (T.big) {
+            P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
+                big(0, T.fwd_init, 0);
+                for (int32_t kb = 0; kb < T.nblk; ++kb) {
+                    big(1, &T.fdiag[2 * kb], kb);
+                    big(2, &T.fupd[2 * kb], kb);
+                }
+            });
+            continue;
+        }
         P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
-            HIPCHECK(launch_solve_fwd<TF>(tiles, linv, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols, T.qc,
+            const int32_t qc = solve_chunk_width(T.ns_pad_max, ncols, sizeof(TF) == 4);
+            HIPCHECK(launch_solve_fwd<TF>(tiles, linv, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols, qc,
                                           dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr), dptr<int64_t>(L.gidx), md,
                                           s));
         });
@@ -532,8 +594,19 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         const TLev& T = L.tl[t];
         const double bytes = bL * T.l_entries + 2.0 * 8.0 * T.pivots * ncols;
         const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
+        if (T.big) {
+            P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
+                big(3, T.bwd_init, 0);
+                for (int32_t kb = T.nblk - 1; kb >= 0; --kb) {
+                    big(4, &T.bdiag[2 * kb], kb);
+                    big(5, &T.bupd[2 * kb], kb);
+                }
+            });
+            continue;
+        }
         P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
-            HIPCHECK(launch_solve_bwd<TF>(tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols, T.qc,
+            const int32_t qc = solve_chunk_width(T.ns_pad_max, ncols, sizeof(TF) == 4);
+            HIPCHECK(launch_solve_bwd<TF>(tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols, qc,
                                           dptr<int32_t>(L.rows), true, s));
         });
     }
@@ -1133,6 +1206,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         int32_t locked = 0, it = 0;
         bool conv = false;
         double rmax = INFINITY;   // largest residual of the first p pairs after the last Rayleigh-Ritz step
+        bool fp64_gram = false;
         for (it = 1; it <= so.max_iters; ++it) {
             auto a0 = std::chrono::steady_clock::now();
             HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, L.n, q, dptr<double>(h->Psi), h->ld, s));
@@ -1167,7 +1241,9 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
             }
             HIPCHECK(hipStreamSynchronize(s));
             st.ms_solve += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a0).count();
-            const bool low_gram = mixed && !(rmax < 10.0 * so.tol);
+            // FP32 Gram only far from convergence: its rounding bounds the Ritz
+            // vectors' accuracy; switch for good once it stops paying off
+            const bool low_gram = mixed && !fp64_gram && rmax > std::max(100.0 * so.tol, 1e-4);
             rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, low_gram);
             auto check = [&] {
                 conv = true;
@@ -1177,7 +1253,9 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
                     rmax = std::max(rmax, res[i]);
                 }
             };
+            const double rprev = rmax;
             check();
+            if (low_gram && !(rmax < 0.5 * rprev)) fp64_gram = true;
             // the returned basis always comes from an FP64 Gram (M-orthonormal to FP64 accuracy)
             if (conv && low_gram) {
                 rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, false);
@@ -1276,12 +1354,13 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
         double* dots = dptr<double>(h->bDots);
         double* rz = dots, *pq = dots + ld, *alpha = dots + 2 * ld, *rz2 = dots + 3 * ld, *beta = dots + 4 * ld,
               *rr = dots + 5 * ld;
-        HIPCHECK(launch_import_cols(d_grad_evecs, nv, dptr<int32_t>(L0.dperm), n, p, Gb, ld, s));
+        // the returned eigenvectors carry the sign of the export (largest entry positive):
+        // dL/dPhi_k = sign_k dL/dx_k
+        const int64_t nch_exp = (n + 8191) / 8192;
+        const double* sign = dptr<double>(h->exportw) + 2 * nch_exp * p;
+        HIPCHECK(launch_import_cols(d_grad_evecs, nv, dptr<int32_t>(L0.dperm), n, p, Gb, ld, s, sign));
         HIPCHECK(launch_diag_scale(md, n, X, ld, q, MX, ld, s));
-        // coefficients of the gradient in the Ritz basis: C0 = X_q^T Gbar
-        HIPCHECK(launch_tsgemm_tn(X, ld, Gb, ld, n, q, p, part, C0, s));
-        std::vector<double> c0((size_t)q * p), lamh(q);
-        HIPCHECK(hipMemcpyAsync(c0.data(), C0, c0.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<double> lamh(q);
         HIPCHECK(hipMemcpyAsync(lamh.data(), lam, q * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         // clusters: maximal runs of Ritz values with relative gaps below 1e-2
@@ -1290,9 +1369,20 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
             const double den = std::fabs(lamh[j]) > 0 ? std::fabs(lamh[j]) : 1.0;
             cl[j] = cl[j - 1] + (((lamh[j] - lamh[j - 1]) / den) >= 1e-2 ? 1 : 0);
         }
-        std::vector<double> cin((size_t)q * p, 0.0), gam((size_t)q * p, 0.0);
+        // The spectral part uses the converged pairs only: the first p and the
+        // rest of the cluster of pair p-1 (the remaining Ritz pairs are not
+        // eigenpairs to the tolerance, so the complement solve covers them).
+        int32_t ps = p;
+        while (ps < q && cl[ps] == cl[p - 1]) ++ps;
+        if (ps == q) fail(HSIM_E_UNIMPLEMENTED, "the cluster of eigenpair p-1 extends to the end of the subspace");
+        // coefficients of the gradient in the converged Ritz basis: C0 = X_ps^T Gbar
+        HIPCHECK(launch_tsgemm_tn(X, ld, Gb, ld, n, ps, p, part, C0, s));
+        std::vector<double> c0((size_t)ps * p);
+        HIPCHECK(hipMemcpyAsync(c0.data(), C0, c0.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        std::vector<double> cin((size_t)ps * p, 0.0), gam((size_t)ps * p, 0.0);
         for (int32_t k = 0; k < p; ++k)
-            for (int32_t j = 0; j < q; ++j) {
+            for (int32_t j = 0; j < ps; ++j) {
                 const double cjk = c0[(size_t)j * p + k];
                 if (cl[j] != cl[k]) {
                     cin[(size_t)j * p + k] = cjk / (lamh[j] - lamh[k]);
@@ -1306,14 +1396,14 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
         HIPCHECK(hipMemcpyAsync(Gam, gam.data(), gam.size() * sizeof(double), hipMemcpyHostToDevice, s));
         // right-hand side on the complement: r = Gbar - M X_q C0
         HIPCHECK(launch_copy2d(Gb, ld, n, p, R, ld, s));
-        HIPCHECK(launch_tsgemm_nn(MX, ld, n, q, C0, p, -1.0, 1.0, R, ld, s));
+        HIPCHECK(launch_tsgemm_nn(MX, ld, n, ps, C0, p, -1.0, 1.0, R, ld, s));
         // PCG on {w : X_q^T M w = 0} for (S - lam_k M) w_k = r_k, preconditioned by
         // the level-0 factor of S - mu M and the M-orthogonal projection
         auto apply_prec = [&](const double* Rin, double* Zout) {
             HIPCHECK(launch_copy2d(Rin, ld, n, p, Zout, ld, s));
             solve_level(h, L0, Zout, 0, p, false, s);
-            HIPCHECK(launch_tsgemm_tn(MX, ld, Zout, ld, n, q, p, part, Cp, s));
-            HIPCHECK(launch_tsgemm_nn(X, ld, n, q, Cp, p, -1.0, 1.0, Zout, ld, s));
+            HIPCHECK(launch_tsgemm_tn(MX, ld, Zout, ld, n, ps, p, part, Cp, s));
+            HIPCHECK(launch_tsgemm_nn(X, ld, n, ps, Cp, p, -1.0, 1.0, Zout, ld, s));
         };
         HIPCHECK(launch_fill(W, n * ld, 0.0, s));
         apply_prec(R, Z);
@@ -1325,7 +1415,7 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
         HIPCHECK(hipStreamSynchronize(s));
         const double cg_tol = 1e-12;
         int it = 0;
-        for (it = 1; it <= 300; ++it) {
+        for (it = 1; it <= 1000; ++it) {
             apply_level(h, L0, 0, P, Qm, p, s);                       // Q = S P
             HIPCHECK(launch_shift_cols(Qm, P, md, lam, n, ld, p, s));  // Q -= lam_k M P
             HIPCHECK(launch_coldot(P, Qm, n, ld, p, part, pq, s));
@@ -1333,8 +1423,8 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
             HIPCHECK(launch_axpy_cols(W, P, alpha, 0, n, ld, p, s));
             HIPCHECK(launch_axpy_cols(R, Qm, alpha, 1, n, ld, p, s));
             // keep the residual in the dual of the complement
-            HIPCHECK(launch_tsgemm_tn(X, ld, R, ld, n, q, p, part, Cp, s));
-            HIPCHECK(launch_tsgemm_nn(MX, ld, n, q, Cp, p, -1.0, 1.0, R, ld, s));
+            HIPCHECK(launch_tsgemm_tn(X, ld, R, ld, n, ps, p, part, Cp, s));
+            HIPCHECK(launch_tsgemm_nn(MX, ld, n, ps, Cp, p, -1.0, 1.0, R, ld, s));
             if (it % 4 == 0) {
                 HIPCHECK(launch_coldot(R, R, n, ld, p, part, rr, s));
                 HIPCHECK(hipMemcpyAsync(rc.data(), rr, p * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1350,10 +1440,10 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
             std::swap(rz, rz2);
         }
         h->cg_iters = it;
-        if (it > 300) fail(HSIM_E_NOCONV, "adjoint PCG did not converge");
+        if (it > 1000) fail(HSIM_E_NOCONV, "adjoint PCG did not converge");
         // w_k += in-span part; Y = X_cluster Gamma
-        HIPCHECK(launch_tsgemm_nn(X, ld, n, q, Cin, p, 1.0, 1.0, W, ld, s));
-        HIPCHECK(launch_tsgemm_nn(X, ld, n, q, Gam, p, 1.0, 0.0, Y, ld, s));
+        HIPCHECK(launch_tsgemm_nn(X, ld, n, ps, Cin, p, 1.0, 1.0, W, ld, s));
+        HIPCHECK(launch_tsgemm_nn(X, ld, n, ps, Gam, p, 1.0, 0.0, Y, ld, s));
     }
     const int32_t* ip = dptr<int32_t>(h->bIperm);
     HIPCHECK(launch_bwd_vertex(nv, p, X, W, Y, ld, ip, lam, d_grad_evals, h->density.empty() ? nullptr : dptr<double>(h->bRho),

@@ -52,6 +52,9 @@ hipError_t launch_fac_update(double* tiles, const double* D, const DFront* front
                              int64_t nitems, int32_t k, hipStream_t s);
 
 // ------------------------------------------------------------ block solves
+// widest supported column chunk (8..160) whose LDS footprint fits a workgroup
+// for fronts of ns_pad_max pivots; 0 if none fits
+int32_t solve_chunk_width(int32_t ns_pad_max, int32_t ncols, bool fp32);
 // Forward L^-1 (and optional diagonal pre-scaling by mdiag) over the fronts
 // [f0, f1) of one tree level, columns [col0, col0 + ncols) in chunks of qc.
 template <class TF>
@@ -63,6 +66,19 @@ template <class TF>
 hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
                             int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
                             int32_t qc, const int32_t* rows, bool apply_dinv, hipStream_t s);
+
+// Block solves of tree levels with wide supernodes, 128-row pivot blocks:
+// phase 0 forward init (items: front, tile row), 1 forward diagonal block kb
+// (items: front), 2 forward update below block kb (items: front, tile row),
+// 3 backward init with the struct rows (items: front, pivot tile), 4 backward
+// diagonal block kb (items: front), 5 backward update before block kb
+// (items: front, pivot tile).  Column chunks of 32.
+constexpr int BIG_BLOCK_TILES = 4;
+template <class TF>
+hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts,
+                            const int32_t* items, int64_t nitems, int32_t kb, double* X, int64_t ldx, int32_t col0,
+                            int32_t ncols, double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx,
+                            const double* mdiag, const int32_t* rows, hipStream_t s);
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 // partial Grams over row chunks (pairs of 32-column tiles, upper), then the sum
@@ -90,13 +106,16 @@ hipError_t launch_dense_to_front(const double* A, int32_t k, double* tiles, int3
 hipError_t launch_transpose(const double* A, int32_t k, double* B, hipStream_t s);
 // C[i, j] = 0.5 (A[i,j] + A[j,i]) * w[i] * w[j] with w = D^-1/2 (k x k)
 hipError_t launch_sym_scale(const double* A, const double* D, int32_t k, double* C, hipStream_t s);
-// Jacobi: init next-round diagonal/partner arrays from C (m x m, m even)
-hipError_t launch_jacobi_init(const double* C, int32_t m, double* V, double* diag, double* off, hipStream_t s);
-// threshold for a rotation: |c_pq| > max(tol_abs_rel * normf[0], tol_rel * sqrt(|c_pp c_qq|))
-hipError_t launch_jacobi_round(double* C, double* V, int32_t m, int32_t round, const double* diag_cur,
-                               const double* off_cur, double* diag_next, double* off_next, double tol_rel,
-                               const double* normf, double tol_abs_rel, int32_t* rot_count, hipStream_t s);
-// C (m x m) = Ck (k x k) plus a decoupled dummy (m = k + 1), normf = ||Ck||_F, dis = D^-1/2
+// Block Jacobi round (block size b = 16 or 32, m a multiple of 2b): local
+// 2b x 2b diagonalisations of every block pair (at most inner_sweeps cyclic
+// sweeps; rotation threshold max(tol_abs_rel * normf[0], tol_rel * sqrt(|c_pp c_qq|)),
+// rotations counted into rot_count), then C <- J^T C J and V <- V J.
+// Qs holds (m / 2b) x (2b)^2 doubles.
+hipError_t launch_bj_round(int b, double* C, double* V, int32_t m, int32_t round, double* Qs, const double* normf,
+                           double tol_rel, double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count,
+                           hipStream_t s);
+hipError_t launch_identity(double* V, int32_t m, hipStream_t s);
+// C (m x m) = Ck (k x k) plus decoupled dummies (m > k), normf = ||Ck||_F, dis = D^-1/2
 hipError_t launch_embed_pad(const double* Ck, int32_t k, int32_t m, double* C, double* normf, double* dis,
                             const double* D, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -141,8 +160,9 @@ hipError_t launch_bwd_tri(int64_t nf, const int32_t* F, const double* V, int32_t
                           hipStream_t s);
 hipError_t launch_bwd_gather(int64_t nv, const int64_t* vt_ptr, const int64_t* vt, const double* G, double* gradV,
                              hipStream_t s);
+// out[r, c] = sign[c] * in[c * nv + perm[r]] (sign may be null)
 hipError_t launch_import_cols(const double* in, int64_t nv, const int32_t* perm, int64_t n, int32_t k, double* out,
-                              int64_t ld, hipStream_t s);
+                              int64_t ld, hipStream_t s, const double* sign = nullptr);
 
 // ------------------------------------------------------------ output
 // evecs[c * nv + vertex(r)] = sign_c * Phi[r, c] for c < p, largest-magnitude

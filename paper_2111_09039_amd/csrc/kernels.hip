@@ -11,6 +11,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
 
 #include "kernels.h"
 
@@ -350,25 +351,72 @@ hipError_t launch_fac_update(double* tiles, const double* D, const DFront* front
 }
 
 // ============================================================ block solves
-// Forward sweep over one tree level: for each front and column chunk,
-//   y = L11^-1 (b_J + children's updates) and u_J = (children's updates) - L21 y.
-// y is written back into X (pivot rows), u_J into the update buffer.
+// One workgroup per (front, chunk of QC right-hand-side columns) of a tree
+// level.  The front's pivot rows of the block live in LDS; every 32 x 32
+// factor tile is staged in LDS once and applied to all QC columns by a
+// register-blocked micro-kernel: out[row][col] += sum_k A[k][row] * B[k][col].
+namespace {
+template <int QC>
+struct SolveMap {
+    static constexpr int RR = QC >= 32 ? 4 : (QC == 16 ? 2 : 1);   // rows per thread
+    static constexpr int RL = 32 / RR;                              // row lanes
+    static constexpr int CL = 256 / RL;                             // column lanes
+    static constexpr int CC = QC / CL > 0 ? QC / CL : 1;            // columns per thread
+    static_assert(RR * CC * 256 == 32 * QC, "thread map must cover a 32 x QC block");
+};
+constexpr int TS = T32 + 1;   // LDS stride of a staged tile (no bank conflicts on transposed stores)
+
+// stage a 32 x 32 column-major tile into As[k * TS + row] as A(row, k) (trans = false)
+// or A(k, row) (trans = true)
 template <class T>
+__device__ __forceinline__ void stage_tile(T* As, const T* __restrict__ tile, bool trans) {
+    for (int idx = threadIdx.x; idx < TT; idx += 256) {
+        const int a = idx & 31, b = idx >> 5;    // tile element (row a, col b)
+        if (!trans) As[b * TS + a] = tile[idx];  // A(row = a, k = b)
+        else As[a * TS + b] = tile[idx];         // A(row = b, k = a)
+    }
+}
+
+// acc[i][j] += sum_k As[k * TS + row_i] * B[(k) * ldb + col_j]
+template <class T, int QC>
+__device__ __forceinline__ void micro(T (&acc)[SolveMap<QC>::RR][SolveMap<QC>::CC], const T* As, const T* B) {
+    using M = SolveMap<QC>;
+    const int rl = threadIdx.x % M::RL, cl = threadIdx.x / M::RL;
+#pragma unroll 4
+    for (int k = 0; k < T32; ++k) {
+        T a[M::RR], b[M::CC];
+#pragma unroll
+        for (int i = 0; i < M::RR; ++i) a[i] = As[k * TS + rl + M::RL * i];
+#pragma unroll
+        for (int j = 0; j < M::CC; ++j) b[j] = B[k * QC + cl + M::CL * j];
+#pragma unroll
+        for (int i = 0; i < M::RR; ++i)
+#pragma unroll
+            for (int j = 0; j < M::CC; ++j) acc[i][j] += a[i] * b[j];
+    }
+}
+}  // namespace
+
+// Forward sweep over one tree level: y = L11^-1 (b_J + children's updates)
+// and u_J = (children's updates for the struct rows) - L21 y.
+template <class T, int QC>
 __global__ __launch_bounds__(256) void k_solve_fwd(const T* __restrict__ tiles, const T* __restrict__ linv,
                                                    const DFront* __restrict__ fr, int32_t f0, int32_t nchunks,
-                                                   double* X, int64_t ldx, int32_t col0, int32_t ncols, int32_t qc,
-                                                   T* ubuf, int64_t ldu, const int64_t* __restrict__ gptr,
+                                                   double* X, int64_t ldx, int32_t col0, int32_t ncols, T* ubuf,
+                                                   int64_t ldu, const int64_t* __restrict__ gptr,
                                                    const int64_t* __restrict__ gidx, const double* __restrict__ mdiag) {
+    using M = SolveMap<QC>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* y = reinterpret_cast<T*>(smem_raw);
+    T* As = reinterpret_cast<T*>(smem_raw);   // 32 x TS staged tile
+    T* y = As + T32 * TS;                     // ns_pad x QC
     const DFront f = fr[f0 + blockIdx.x / nchunks];
-    const int32_t chunk = blockIdx.x % nchunks;
-    const int32_t c0 = col0 + chunk * qc;
-    const int32_t cw = min(qc, col0 + ncols - c0);
+    const int32_t c0 = col0 + (blockIdx.x % nchunks) * QC;
+    const int32_t cw = min(QC, col0 + ncols - c0);
     const int tid = threadIdx.x;
+    const int rl = tid % M::RL, cl = tid / M::RL;
     // 1. pivot rows of the right-hand side plus the children's updates
-    for (int idx = tid; idx < f.ns_pad * qc; idx += 256) {
-        const int r = idx / qc, c = idx % qc;
+    for (int idx = tid; idx < f.ns_pad * QC; idx += 256) {
+        const int r = idx / QC, c = idx % QC;
         double v = 0.0;
         if (r < f.ns && c < cw) {
             v = X[(f.start + r) * ldx + c0 + c];
@@ -378,84 +426,85 @@ __global__ __launch_bounds__(256) void k_solve_fwd(const T* __restrict__ tiles, 
         }
         y[idx] = (T)v;
     }
-    __syncthreads();
     // 2. blocked forward substitution with the unit lower L11
-    constexpr int MAXO = 4;  // 32 * qc / 256 with qc <= 32
     for (int kb = 0; kb < f.nsb; ++kb) {
-        const T* Li = linv + f.linv_base + (int64_t)kb * TT;
-        T tmp[MAXO];
-        int o = 0;
-        for (int idx = tid; idx < T32 * qc; idx += 256, ++o) {
-            const int r = idx & 31, c = idx >> 5;
-            T acc = 0;
-#pragma unroll 8
-            for (int j = 0; j < T32; ++j) acc += Li[j * T32 + r] * y[(kb * T32 + j) * qc + c];
-            tmp[o] = acc;
-        }
+        T* ykb = y + kb * T32 * QC;
         __syncthreads();
-        o = 0;
-        for (int idx = tid; idx < T32 * qc; idx += 256, ++o) {
-            const int r = idx & 31, c = idx >> 5;
-            y[(kb * T32 + r) * qc + c] = tmp[o];
-        }
+        stage_tile(As, linv + f.linv_base + (int64_t)kb * TT, false);
         __syncthreads();
-        const int rest = (f.nsb - kb - 1) * T32 * qc;
-        for (int idx = tid; idx < rest; idx += 256) {
-            const int ib = kb + 1 + idx / (T32 * qc);
-            const int rem = idx % (T32 * qc);
-            const int r = rem & 31, c = rem >> 5;
-            const T* L = tiles + f.tile_base + tri(f.Mt, ib, kb) * TT;
-            T acc = 0;
-#pragma unroll 8
-            for (int j = 0; j < T32; ++j) acc += L[j * T32 + r] * y[(kb * T32 + j) * qc + c];
-            y[(ib * T32 + r) * qc + c] -= acc;
-        }
+        T acc[M::RR][M::CC] = {};
+        micro<T, QC>(acc, As, ykb);
         __syncthreads();
+#pragma unroll
+        for (int i = 0; i < M::RR; ++i)
+#pragma unroll
+            for (int j = 0; j < M::CC; ++j) ykb[(rl + M::RL * i) * QC + cl + M::CL * j] = acc[i][j];
+        for (int ib = kb + 1; ib < f.nsb; ++ib) {
+            __syncthreads();
+            stage_tile(As, tiles + f.tile_base + tri(f.Mt, ib, kb) * TT, false);
+            __syncthreads();
+            T a2[M::RR][M::CC] = {};
+            micro<T, QC>(a2, As, ykb);
+            T* yib = y + ib * T32 * QC;
+#pragma unroll
+            for (int i = 0; i < M::RR; ++i)
+#pragma unroll
+                for (int j = 0; j < M::CC; ++j) yib[(rl + M::RL * i) * QC + cl + M::CL * j] -= a2[i][j];
+        }
     }
+    __syncthreads();
     // 3. pivot rows out
-    for (int idx = tid; idx < f.ns * qc; idx += 256) {
-        const int r = idx / qc, c = idx % qc;
+    for (int idx = tid; idx < f.ns * QC; idx += 256) {
+        const int r = idx / QC, c = idx % QC;
         if (c < cw) X[(f.start + r) * ldx + c0 + c] = (double)y[idx];
     }
-    // 4. update rows: u = gathered - L21 y
+    // 4. update rows: u = gathered - L21 y, one 32-row tile at a time
     const int stiles = (f.mu + T32 - 1) / T32;
-    for (int idx = tid; idx < stiles * T32 * qc; idx += 256) {
-        const int sl = idx & 31;
-        const int rest2 = idx >> 5;
-        const int c = rest2 % qc, st = rest2 / qc;
-        const int s = st * T32 + sl;
-        if (s >= f.mu || c >= cw) continue;
-        double acc = 0.0;
-        const int64_t gr = f.gather_base + f.ns + s;
-        for (int64_t g = gptr[gr]; g < gptr[gr + 1]; ++g) acc += (double)ubuf[gidx[g] * ldu + c0 + c];
-        T a2 = 0;
+    for (int st = 0; st < stiles; ++st) {
+        T acc[M::RR][M::CC] = {};
         for (int kb = 0; kb < f.nsb; ++kb) {
-            const T* L = tiles + f.tile_base + tri(f.Mt, f.nsb + st, kb) * TT;
-#pragma unroll 8
-            for (int j = 0; j < T32; ++j) a2 += L[j * T32 + sl] * y[(kb * T32 + j) * qc + c];
+            __syncthreads();
+            stage_tile(As, tiles + f.tile_base + tri(f.Mt, f.nsb + st, kb) * TT, false);
+            __syncthreads();
+            micro<T, QC>(acc, As, y + kb * T32 * QC);
         }
-        ubuf[(f.ubuf_row + s) * ldu + c0 + c] = (T)(acc - (double)a2);
+#pragma unroll
+        for (int i = 0; i < M::RR; ++i) {
+            const int s = st * T32 + rl + M::RL * i;
+            if (s >= f.mu) continue;
+            const int64_t gr = f.gather_base + f.ns + s;
+            const int64_t g0 = gptr[gr], g1 = gptr[gr + 1];
+#pragma unroll
+            for (int j = 0; j < M::CC; ++j) {
+                const int c = cl + M::CL * j;
+                if (c >= cw) continue;
+                double v = 0.0;
+                for (int64_t g = g0; g < g1; ++g) v += (double)ubuf[gidx[g] * ldu + c0 + c];
+                ubuf[(f.ubuf_row + s) * ldu + c0 + c] = (T)(v - (double)acc[i][j]);
+            }
+        }
     }
 }
 
-// Backward sweep over one tree level: z = D^-1 y - L21^T x_struct,
+// Backward sweep over one tree level: z = D^-1 y - L21^T x_struct, then
 // x_J = L11^-T z (right-looking over the pivot tiles, last tile first).
-template <class T>
+template <class T, int QC>
 __global__ __launch_bounds__(256) void k_solve_bwd(const T* __restrict__ tiles, const T* __restrict__ linv,
                                                    const T* __restrict__ D, const DFront* __restrict__ fr, int32_t f0,
                                                    int32_t nchunks, double* X, int64_t ldx, int32_t col0,
-                                                   int32_t ncols, int32_t qc, const int32_t* __restrict__ rows,
-                                                   int apply_dinv) {
+                                                   int32_t ncols, const int32_t* __restrict__ rows, int apply_dinv) {
+    using M = SolveMap<QC>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* z = reinterpret_cast<T*>(smem_raw);
+    T* As = reinterpret_cast<T*>(smem_raw);   // 32 x TS staged tile
+    T* xs = As + T32 * TS;                    // 32 x QC struct-row solution values
+    T* z = xs + T32 * QC;                     // ns_pad x QC
     const DFront f = fr[f0 + blockIdx.x / nchunks];
-    T* xs = z + (size_t)f.ns_pad * qc;   // 32 x qc staging of struct-row solution values
-    const int32_t chunk = blockIdx.x % nchunks;
-    const int32_t c0 = col0 + chunk * qc;
-    const int32_t cw = min(qc, col0 + ncols - c0);
+    const int32_t c0 = col0 + (blockIdx.x % nchunks) * QC;
+    const int32_t cw = min(QC, col0 + ncols - c0);
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < f.ns_pad * qc; idx += 256) {
-        const int r = idx / qc, c = idx % qc;
+    const int rl = tid % M::RL, cl = tid / M::RL;
+    for (int idx = tid; idx < f.ns_pad * QC; idx += 256) {
+        const int r = idx / QC, c = idx % QC;
         double v = 0.0;
         if (r < f.ns && c < cw) {
             v = X[(f.start + r) * ldx + c0 + c];
@@ -463,62 +512,105 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const T* __restrict__ tiles, 
         }
         z[idx] = (T)v;
     }
-    __syncthreads();
     const int32_t* frows = rows + f.rows_off;
     const int stiles = (f.mu + T32 - 1) / T32;
     for (int st = 0; st < stiles; ++st) {
-        for (int idx = tid; idx < T32 * qc; idx += 256) {
-            const int s = idx / qc, c = idx % qc;
+        __syncthreads();
+        for (int idx = tid; idx < T32 * QC; idx += 256) {
+            const int s = idx / QC, c = idx % QC;
             const int sr = st * T32 + s;
             xs[idx] = (sr < f.mu && c < cw) ? (T)X[(int64_t)frows[sr] * ldx + c0 + c] : (T)0;
         }
-        __syncthreads();
-        for (int idx = tid; idx < f.ns_pad * qc; idx += 256) {
-            const int j = idx / qc, c = idx % qc;
-            const T* L = tiles + f.tile_base + tri(f.Mt, f.nsb + st, j / T32) * TT + (j % T32) * T32;
-            T acc = 0;
-#pragma unroll 8
-            for (int s = 0; s < T32; ++s) acc += L[s] * xs[s * qc + c];
-            z[idx] -= acc;
+        for (int jb = 0; jb < f.nsb; ++jb) {
+            __syncthreads();
+            stage_tile(As, tiles + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT, true);
+            __syncthreads();
+            T acc[M::RR][M::CC] = {};
+            micro<T, QC>(acc, As, xs);
+            T* zjb = z + jb * T32 * QC;
+#pragma unroll
+            for (int i = 0; i < M::RR; ++i)
+#pragma unroll
+                for (int j = 0; j < M::CC; ++j) zjb[(rl + M::RL * i) * QC + cl + M::CL * j] -= acc[i][j];
         }
-        __syncthreads();
     }
-    constexpr int MAXO = 4;
     for (int kb = f.nsb - 1; kb >= 0; --kb) {
-        const T* Li = linv + f.linv_base + (int64_t)kb * TT;
-        T tmp[MAXO];
-        int o = 0;
-        for (int idx = tid; idx < T32 * qc; idx += 256, ++o) {
-            const int r = idx & 31, c = idx >> 5;
-            T acc = 0;
-#pragma unroll 8
-            for (int j = 0; j < T32; ++j) acc += Li[r * T32 + j] * z[(kb * T32 + j) * qc + c];
-            tmp[o] = acc;
-        }
+        T* zkb = z + kb * T32 * QC;
         __syncthreads();
-        o = 0;
-        for (int idx = tid; idx < T32 * qc; idx += 256, ++o) {
-            const int r = idx & 31, c = idx >> 5;
-            z[(kb * T32 + r) * qc + c] = tmp[o];
-        }
+        stage_tile(As, linv + f.linv_base + (int64_t)kb * TT, true);
         __syncthreads();
-        const int rest = kb * T32 * qc;
-        for (int idx = tid; idx < rest; idx += 256) {
-            const int ib = idx / (T32 * qc);
-            const int rem = idx % (T32 * qc);
-            const int r = rem & 31, c = rem >> 5;
-            const T* L = tiles + f.tile_base + tri(f.Mt, kb, ib) * TT + r * T32;
-            T acc = 0;
-#pragma unroll 8
-            for (int j = 0; j < T32; ++j) acc += L[j] * z[(kb * T32 + j) * qc + c];
-            z[(ib * T32 + r) * qc + c] -= acc;
-        }
+        T acc[M::RR][M::CC] = {};
+        micro<T, QC>(acc, As, zkb);
         __syncthreads();
+#pragma unroll
+        for (int i = 0; i < M::RR; ++i)
+#pragma unroll
+            for (int j = 0; j < M::CC; ++j) zkb[(rl + M::RL * i) * QC + cl + M::CL * j] = acc[i][j];
+        for (int ib = 0; ib < kb; ++ib) {
+            __syncthreads();
+            stage_tile(As, tiles + f.tile_base + tri(f.Mt, kb, ib) * TT, true);
+            __syncthreads();
+            T a2[M::RR][M::CC] = {};
+            micro<T, QC>(a2, As, zkb);
+            T* zib = z + ib * T32 * QC;
+#pragma unroll
+            for (int i = 0; i < M::RR; ++i)
+#pragma unroll
+                for (int j = 0; j < M::CC; ++j) zib[(rl + M::RL * i) * QC + cl + M::CL * j] -= a2[i][j];
+        }
     }
-    for (int idx = tid; idx < f.ns * qc; idx += 256) {
-        const int r = idx / qc, c = idx % qc;
+    __syncthreads();
+    for (int idx = tid; idx < f.ns * QC; idx += 256) {
+        const int r = idx / QC, c = idx % QC;
         if (c < cw) X[(f.start + r) * ldx + c0 + c] = (double)z[idx];
     }
+}
+
+namespace {
+template <class T>
+size_t fwd_lds(int32_t ns_pad, int qc) { return ((size_t)T32 * TS + (size_t)ns_pad * qc) * sizeof(T); }
+template <class T>
+size_t bwd_lds(int32_t ns_pad, int qc) { return ((size_t)T32 * TS + (size_t)T32 * qc + (size_t)ns_pad * qc) * sizeof(T); }
+}  // namespace
+
+int32_t solve_chunk_width(int32_t ns_pad_max, int32_t ncols, bool fp32) {
+    static const int opts[] = {160, 128, 96, 64, 32, 16, 8};
+    static const int cap = [] {
+        const char* e = getenv("HSIM_SOLVE_QC_MAX");   // tuning cap on the column chunk
+        return e ? atoi(e) : 160;
+    }();
+    for (int qc : opts) {
+        if (qc > cap && qc > 8) continue;
+        if (qc > 32 && qc >= ncols + 32) continue;   // narrower chunk covers all columns
+        const size_t b = fp32 ? bwd_lds<float>(ns_pad_max, qc) : bwd_lds<double>(ns_pad_max, qc);
+        if (b <= LDS_PER_WG) return qc;
+    }
+    return 0;
+}
+
+template <class TF, int QC>
+static hipError_t fwd_qc(const TF* tiles, const TF* linv, const DFront* fronts, int32_t f0, int32_t f1,
+                         int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf,
+                         int64_t ldu, const int64_t* gptr, const int64_t* gidx, const double* mdiag, hipStream_t s) {
+    const int32_t nchunks = (int32_t)cdiv(ncols, QC);
+    const size_t lds = fwd_lds<TF>(ns_pad_max, QC);
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_solve_fwd<TF, QC>), lds, 0);
+    if (e != hipSuccess) return e;
+    k_solve_fwd<TF, QC><<<(unsigned)((f1 - f0) * nchunks), 256, lds, s>>>(
+        tiles, linv, fronts, f0, nchunks, X, ldx, col0, ncols, reinterpret_cast<TF*>(ubuf), ldu, gptr, gidx, mdiag);
+    return hipGetLastError();
+}
+template <class TF, int QC>
+static hipError_t bwd_qc(const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0, int32_t f1,
+                         int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols, const int32_t* rows,
+                         bool apply_dinv, hipStream_t s) {
+    const int32_t nchunks = (int32_t)cdiv(ncols, QC);
+    const size_t lds = bwd_lds<TF>(ns_pad_max, QC);
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_solve_bwd<TF, QC>), lds, 0);
+    if (e != hipSuccess) return e;
+    k_solve_bwd<TF, QC><<<(unsigned)((f1 - f0) * nchunks), 256, lds, s>>>(tiles, linv, D, fronts, f0, nchunks, X, ldx,
+                                                                           col0, ncols, rows, apply_dinv ? 1 : 0);
+    return hipGetLastError();
 }
 
 template <class TF>
@@ -527,23 +619,26 @@ hipError_t launch_solve_fwd(const TF* tiles, const TF* linv, const DFront* front
                             double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx, const double* mdiag,
                             hipStream_t s) {
     if (f1 <= f0 || ncols <= 0) return hipSuccess;
-    const int32_t nchunks = (int32_t)cdiv(ncols, qc);
-    const size_t lds = (size_t)ns_pad_max * qc * sizeof(TF);
-    k_solve_fwd<TF><<<(unsigned)((f1 - f0) * nchunks), 256, lds, s>>>(
-        tiles, linv, fronts, f0, nchunks, X, ldx, col0, ncols, qc, reinterpret_cast<TF*>(ubuf), ldu, gptr, gidx,
-        mdiag);
-    return hipGetLastError();
+    switch (qc) {
+#define HSIM_FWD(Q) \
+    case Q: return fwd_qc<TF, Q>(tiles, linv, fronts, f0, f1, ns_pad_max, X, ldx, col0, ncols, ubuf, ldu, gptr, gidx, mdiag, s);
+        HSIM_FWD(8) HSIM_FWD(16) HSIM_FWD(32) HSIM_FWD(64) HSIM_FWD(96) HSIM_FWD(128) HSIM_FWD(160)
+#undef HSIM_FWD
+        default: return hipErrorInvalidValue;
+    }
 }
 template <class TF>
 hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
                             int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
                             int32_t qc, const int32_t* rows, bool apply_dinv, hipStream_t s) {
     if (f1 <= f0 || ncols <= 0) return hipSuccess;
-    const int32_t nchunks = (int32_t)cdiv(ncols, qc);
-    const size_t lds = ((size_t)ns_pad_max + T32) * qc * sizeof(TF);
-    k_solve_bwd<TF><<<(unsigned)((f1 - f0) * nchunks), 256, lds, s>>>(tiles, linv, D, fronts, f0, nchunks, X, ldx,
-                                                                       col0, ncols, qc, rows, apply_dinv ? 1 : 0);
-    return hipGetLastError();
+    switch (qc) {
+#define HSIM_BWD(Q) \
+    case Q: return bwd_qc<TF, Q>(tiles, linv, D, fronts, f0, f1, ns_pad_max, X, ldx, col0, ncols, rows, apply_dinv, s);
+        HSIM_BWD(8) HSIM_BWD(16) HSIM_BWD(32) HSIM_BWD(64) HSIM_BWD(96) HSIM_BWD(128) HSIM_BWD(160)
+#undef HSIM_BWD
+        default: return hipErrorInvalidValue;
+    }
 }
 template hipError_t launch_solve_fwd<double>(const double*, const double*, const DFront*, int32_t, int32_t, int32_t,
                                              double*, int64_t, int32_t, int32_t, int32_t, double*, int64_t,
@@ -558,94 +653,422 @@ template hipError_t launch_solve_bwd<float>(const float*, const float*, const fl
                                             int32_t, int32_t, double*, int64_t, int32_t, int32_t, int32_t,
                                             const int32_t*, bool, hipStream_t);
 
-// ============================================================ Gram products
-int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows) {
-    const int64_t nt = cdiv(q, T32);
-    return cdiv(n, chunk_rows) * (nt * (nt + 1) / 2) * 2 * TT;
+// ---------------------------------------------------------------------------
+// Block solves for tree levels with wide supernodes.  The pivots of a front
+// are processed in blocks of KBT = 4 tiles (128 rows): one launch solves the
+// diagonal block of every front (one workgroup per front and column chunk),
+// the next launch applies it to every 32-row tile outside the block (one
+// workgroup per front, tile and column chunk), so the large fronts near the
+// root use the whole chip.  The right-hand side lives in X (pivot rows) and
+// in the update buffer (struct rows) between launches.
+namespace {
+constexpr int KBT = 4;
+constexpr int BQC = 32;
+using BM = SolveMap<BQC>;
+}  // namespace
+
+// rows [0, ns) of the front from B (times mdiag) plus children's updates into X;
+// struct rows: the children's updates into the front's update rows.  items: (front, tile row)
+template <class T>
+__global__ __launch_bounds__(256) void k_big_fwd_init(const DFront* __restrict__ fr, const int32_t* __restrict__ items,
+                                                      int32_t nchunks, double* X, int64_t ldx, int32_t col0,
+                                                      int32_t ncols, T* ubuf, int64_t ldu,
+                                                      const int64_t* __restrict__ gptr,
+                                                      const int64_t* __restrict__ gidx,
+                                                      const double* __restrict__ mdiag) {
+    const int item = blockIdx.x / nchunks;
+    const DFront f = fr[items[2 * item]];
+    const int tr = items[2 * item + 1];
+    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
+    const int32_t cw = min(BQC, col0 + ncols - c0);
+    for (int idx = threadIdx.x; idx < T32 * BQC; idx += 256) {
+        const int r = idx / BQC, c = idx % BQC;
+        if (c >= cw) continue;
+        if (tr < f.nsb) {
+            const int row = tr * T32 + r;
+            if (row >= f.ns) continue;
+            double v = X[(f.start + row) * ldx + c0 + c];
+            if (mdiag) v *= mdiag[f.start + row];
+            for (int64_t g = gptr[f.gather_base + row]; g < gptr[f.gather_base + row + 1]; ++g)
+                v += (double)ubuf[gidx[g] * ldu + c0 + c];
+            X[(f.start + row) * ldx + c0 + c] = v;
+        } else {
+            const int s = (tr - f.nsb) * T32 + r;
+            if (s >= f.mu) continue;
+            double v = 0.0;
+            const int64_t gr = f.gather_base + f.ns + s;
+            for (int64_t g = gptr[gr]; g < gptr[gr + 1]; ++g) v += (double)ubuf[gidx[g] * ldu + c0 + c];
+            ubuf[(f.ubuf_row + s) * ldu + c0 + c] = (T)v;
+        }
+    }
 }
 
-// partial[chunk][pair][0|1][r][c]: sum over the chunk's rows of
-// Psi[row, a*32+r] * (S Psi)[row, b*32+c]  and  Psi[row, a*32+r] * (M Psi)[row, b*32+c].
-// TA = double: FP64 throughout.  TA = float: operands rounded to FP32, FP32
-// products and accumulation over runs of 256 rows, FP64 sum of the runs.
+// forward diagonal block kb of every listed front: y_blk = L_blk^-1 y_blk (in X)
+template <class T>
+__global__ __launch_bounds__(256) void k_big_fwd_diag(const T* __restrict__ tiles, const T* __restrict__ linv,
+                                                      const DFront* __restrict__ fr, const int32_t* __restrict__ items,
+                                                      int32_t nchunks, int32_t kb, double* X, int64_t ldx,
+                                                      int32_t col0, int32_t ncols) {
+    __shared__ T As[T32 * TS];
+    __shared__ T y[KBT * T32 * BQC];
+    const DFront f = fr[items[blockIdx.x / nchunks]];
+    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
+    const int32_t cw = min(BQC, col0 + ncols - c0);
+    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+    const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
+    const int rows = (t1 - t0) * T32;
+    for (int idx = threadIdx.x; idx < rows * BQC; idx += 256) {
+        const int r = idx / BQC, c = idx % BQC;
+        const int row = t0 * T32 + r;
+        y[idx] = (row < f.ns && c < cw) ? (T)X[(f.start + row) * ldx + c0 + c] : (T)0;
+    }
+    for (int k = t0; k < t1; ++k) {
+        T* yk = y + (k - t0) * T32 * BQC;
+        __syncthreads();
+        stage_tile(As, linv + f.linv_base + (int64_t)k * TT, false);
+        __syncthreads();
+        T acc[BM::RR][BM::CC] = {};
+        micro<T, BQC>(acc, As, yk);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < BM::RR; ++i)
+#pragma unroll
+            for (int j = 0; j < BM::CC; ++j) yk[(rl + BM::RL * i) * BQC + cl + BM::CL * j] = acc[i][j];
+        for (int ib = k + 1; ib < t1; ++ib) {
+            __syncthreads();
+            stage_tile(As, tiles + f.tile_base + tri(f.Mt, ib, k) * TT, false);
+            __syncthreads();
+            T a2[BM::RR][BM::CC] = {};
+            micro<T, BQC>(a2, As, yk);
+            T* yib = y + (ib - t0) * T32 * BQC;
+#pragma unroll
+            for (int i = 0; i < BM::RR; ++i)
+#pragma unroll
+                for (int j = 0; j < BM::CC; ++j) yib[(rl + BM::RL * i) * BQC + cl + BM::CL * j] -= a2[i][j];
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rows * BQC; idx += 256) {
+        const int r = idx / BQC, c = idx % BQC;
+        const int row = t0 * T32 + r;
+        if (row < f.ns && c < cw) X[(f.start + row) * ldx + c0 + c] = (double)y[idx];
+    }
+}
+
+// forward update of one 32-row tile ib below block kb: rows -= L(ib, blk) y_blk
+// (pivot tile: rows of X; struct tile: the front's update rows).  items: (front, ib)
+template <class T>
+__global__ __launch_bounds__(256) void k_big_fwd_update(const T* __restrict__ tiles, const DFront* __restrict__ fr,
+                                                        const int32_t* __restrict__ items, int32_t nchunks, int32_t kb,
+                                                        double* X, int64_t ldx, int32_t col0, int32_t ncols, T* ubuf,
+                                                        int64_t ldu) {
+    __shared__ T As[T32 * TS];
+    __shared__ T y[KBT * T32 * BQC];
+    const int item = blockIdx.x / nchunks;
+    const DFront f = fr[items[2 * item]];
+    const int ib = items[2 * item + 1];
+    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
+    const int32_t cw = min(BQC, col0 + ncols - c0);
+    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+    const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
+    const int rows = (t1 - t0) * T32;
+    for (int idx = threadIdx.x; idx < rows * BQC; idx += 256) {
+        const int r = idx / BQC, c = idx % BQC;
+        const int row = t0 * T32 + r;
+        y[idx] = (row < f.ns && c < cw) ? (T)X[(f.start + row) * ldx + c0 + c] : (T)0;
+    }
+    T acc[BM::RR][BM::CC] = {};
+    for (int k = t0; k < t1; ++k) {
+        __syncthreads();
+        stage_tile(As, tiles + f.tile_base + tri(f.Mt, ib, k) * TT, false);
+        __syncthreads();
+        micro<T, BQC>(acc, As, y + (k - t0) * T32 * BQC);
+    }
+#pragma unroll
+    for (int i = 0; i < BM::RR; ++i) {
+        const int r = rl + BM::RL * i;
+#pragma unroll
+        for (int j = 0; j < BM::CC; ++j) {
+            const int c = cl + BM::CL * j;
+            if (c >= cw) continue;
+            if (ib < f.nsb) {
+                const int row = ib * T32 + r;
+                if (row < f.ns) X[(f.start + row) * ldx + c0 + c] -= (double)acc[i][j];
+            } else {
+                const int s = (ib - f.nsb) * T32 + r;
+                if (s < f.mu) {
+                    T* u = ubuf + (f.ubuf_row + s) * ldu + c0 + c;
+                    *u = (T)((double)*u - (double)acc[i][j]);
+                }
+            }
+        }
+    }
+}
+
+// backward start: z_jb = D^-1 y_jb - sum over struct tiles L(st, jb)^T x_st, in X.  items: (front, jb)
+template <class T>
+__global__ __launch_bounds__(256) void k_big_bwd_init(const T* __restrict__ tiles, const T* __restrict__ D,
+                                                      const DFront* __restrict__ fr, const int32_t* __restrict__ items,
+                                                      int32_t nchunks, double* X, int64_t ldx, int32_t col0,
+                                                      int32_t ncols, const int32_t* __restrict__ rows) {
+    __shared__ T As[T32 * TS];
+    __shared__ T xs[T32 * BQC];
+    const int item = blockIdx.x / nchunks;
+    const DFront f = fr[items[2 * item]];
+    const int jb = items[2 * item + 1];
+    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
+    const int32_t cw = min(BQC, col0 + ncols - c0);
+    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+    const int32_t* frows = rows + f.rows_off;
+    const int stiles = (f.mu + T32 - 1) / T32;
+    T acc[BM::RR][BM::CC] = {};
+    for (int st = 0; st < stiles; ++st) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < T32 * BQC; idx += 256) {
+            const int s = idx / BQC, c = idx % BQC;
+            const int sr = st * T32 + s;
+            xs[idx] = (sr < f.mu && c < cw) ? (T)X[(int64_t)frows[sr] * ldx + c0 + c] : (T)0;
+        }
+        stage_tile(As, tiles + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT, true);
+        __syncthreads();
+        micro<T, BQC>(acc, As, xs);
+    }
+#pragma unroll
+    for (int i = 0; i < BM::RR; ++i) {
+        const int row = jb * T32 + rl + BM::RL * i;
+        if (row >= f.ns) continue;
+#pragma unroll
+        for (int j = 0; j < BM::CC; ++j) {
+            const int c = cl + BM::CL * j;
+            if (c >= cw) continue;
+            double* xp = X + (f.start + row) * ldx + c0 + c;
+            *xp = *xp / (double)D[f.d_base + row] - (double)acc[i][j];
+        }
+    }
+}
+
+// backward diagonal block kb: x_blk = L_blk^-T z_blk (in X)
+template <class T>
+__global__ __launch_bounds__(256) void k_big_bwd_diag(const T* __restrict__ tiles, const T* __restrict__ linv,
+                                                      const DFront* __restrict__ fr, const int32_t* __restrict__ items,
+                                                      int32_t nchunks, int32_t kb, double* X, int64_t ldx,
+                                                      int32_t col0, int32_t ncols) {
+    __shared__ T As[T32 * TS];
+    __shared__ T z[KBT * T32 * BQC];
+    const DFront f = fr[items[blockIdx.x / nchunks]];
+    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
+    const int32_t cw = min(BQC, col0 + ncols - c0);
+    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+    const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
+    const int nrows = (t1 - t0) * T32;
+    for (int idx = threadIdx.x; idx < nrows * BQC; idx += 256) {
+        const int r = idx / BQC, c = idx % BQC;
+        const int row = t0 * T32 + r;
+        z[idx] = (row < f.ns && c < cw) ? (T)X[(f.start + row) * ldx + c0 + c] : (T)0;
+    }
+    for (int k = t1 - 1; k >= t0; --k) {
+        T* zk = z + (k - t0) * T32 * BQC;
+        __syncthreads();
+        stage_tile(As, linv + f.linv_base + (int64_t)k * TT, true);
+        __syncthreads();
+        T acc[BM::RR][BM::CC] = {};
+        micro<T, BQC>(acc, As, zk);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < BM::RR; ++i)
+#pragma unroll
+            for (int j = 0; j < BM::CC; ++j) zk[(rl + BM::RL * i) * BQC + cl + BM::CL * j] = acc[i][j];
+        for (int ib = t0; ib < k; ++ib) {
+            __syncthreads();
+            stage_tile(As, tiles + f.tile_base + tri(f.Mt, k, ib) * TT, true);
+            __syncthreads();
+            T a2[BM::RR][BM::CC] = {};
+            micro<T, BQC>(a2, As, zk);
+            T* zib = z + (ib - t0) * T32 * BQC;
+#pragma unroll
+            for (int i = 0; i < BM::RR; ++i)
+#pragma unroll
+                for (int j = 0; j < BM::CC; ++j) zib[(rl + BM::RL * i) * BQC + cl + BM::CL * j] -= a2[i][j];
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nrows * BQC; idx += 256) {
+        const int r = idx / BQC, c = idx % BQC;
+        const int row = t0 * T32 + r;
+        if (row < f.ns && c < cw) X[(f.start + row) * ldx + c0 + c] = (double)z[idx];
+    }
+}
+
+// backward update of pivot tile jb (before block kb): z_jb -= sum_{k in blk} L(k, jb)^T x_k.  items: (front, jb)
+template <class T>
+__global__ __launch_bounds__(256) void k_big_bwd_update(const T* __restrict__ tiles, const DFront* __restrict__ fr,
+                                                        const int32_t* __restrict__ items, int32_t nchunks, int32_t kb,
+                                                        double* X, int64_t ldx, int32_t col0, int32_t ncols) {
+    __shared__ T As[T32 * TS];
+    __shared__ T xb[KBT * T32 * BQC];
+    const int item = blockIdx.x / nchunks;
+    const DFront f = fr[items[2 * item]];
+    const int jb = items[2 * item + 1];
+    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
+    const int32_t cw = min(BQC, col0 + ncols - c0);
+    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+    const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
+    const int nrows = (t1 - t0) * T32;
+    for (int idx = threadIdx.x; idx < nrows * BQC; idx += 256) {
+        const int r = idx / BQC, c = idx % BQC;
+        const int row = t0 * T32 + r;
+        xb[idx] = (row < f.ns && c < cw) ? (T)X[(f.start + row) * ldx + c0 + c] : (T)0;
+    }
+    T acc[BM::RR][BM::CC] = {};
+    for (int k = t0; k < t1; ++k) {
+        __syncthreads();
+        stage_tile(As, tiles + f.tile_base + tri(f.Mt, k, jb) * TT, true);
+        __syncthreads();
+        micro<T, BQC>(acc, As, xb + (k - t0) * T32 * BQC);
+    }
+#pragma unroll
+    for (int i = 0; i < BM::RR; ++i) {
+        const int row = jb * T32 + rl + BM::RL * i;
+        if (row >= f.ns) continue;
+#pragma unroll
+        for (int j = 0; j < BM::CC; ++j) {
+            const int c = cl + BM::CL * j;
+            if (c < cw) X[(f.start + row) * ldx + c0 + c] -= (double)acc[i][j];
+        }
+    }
+}
+
+template <class TF>
+hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts,
+                            const int32_t* items, int64_t nitems, int32_t kb, double* X, int64_t ldx, int32_t col0,
+                            int32_t ncols, double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx,
+                            const double* mdiag, const int32_t* rows, hipStream_t s) {
+    if (nitems <= 0 || ncols <= 0) return hipSuccess;
+    const int32_t nch = (int32_t)cdiv(ncols, BQC);
+    const unsigned grid = (unsigned)(nitems * nch);
+    TF* ub = reinterpret_cast<TF*>(ubuf);
+    switch (phase) {
+        case 0: k_big_fwd_init<TF><<<grid, 256, 0, s>>>(fronts, items, nch, X, ldx, col0, ncols, ub, ldu, gptr, gidx, mdiag); break;
+        case 1: k_big_fwd_diag<TF><<<grid, 256, 0, s>>>(tiles, linv, fronts, items, nch, kb, X, ldx, col0, ncols); break;
+        case 2: k_big_fwd_update<TF><<<grid, 256, 0, s>>>(tiles, fronts, items, nch, kb, X, ldx, col0, ncols, ub, ldu); break;
+        case 3: k_big_bwd_init<TF><<<grid, 256, 0, s>>>(tiles, D, fronts, items, nch, X, ldx, col0, ncols, rows); break;
+        case 4: k_big_bwd_diag<TF><<<grid, 256, 0, s>>>(tiles, linv, fronts, items, nch, kb, X, ldx, col0, ncols); break;
+        case 5: k_big_bwd_update<TF><<<grid, 256, 0, s>>>(tiles, fronts, items, nch, kb, X, ldx, col0, ncols); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_big_solve<double>(int, const double*, const double*, const double*, const DFront*,
+                                             const int32_t*, int64_t, int32_t, double*, int64_t, int32_t, int32_t,
+                                             double*, int64_t, const int64_t*, const int64_t*, const double*,
+                                             const int32_t*, hipStream_t);
+template hipError_t launch_big_solve<float>(int, const float*, const float*, const float*, const DFront*,
+                                            const int32_t*, int64_t, int32_t, double*, int64_t, int32_t, int32_t,
+                                            double*, int64_t, const int64_t*, const int64_t*, const double*,
+                                            const int32_t*, hipStream_t);
+
+// ============================================================ Gram products
+// Sbar = Psi^T (S Psi), Mbar = Psi^T (M Psi) over 64 x 64 output tile pairs
+// (a <= b) and chunks of GRAM_CHUNK rows; each thread holds a 4 x 4 block of
+// both products.  TA = double: FP64 throughout.  TA = float: operands rounded
+// to FP32, FP32 products and accumulation over runs of 256 rows, FP64 sum of
+// the runs and of the chunks.
+namespace {
+constexpr int GT = 64;            // output tile edge
+constexpr int GRAM_CHUNK = 2048;  // rows per workgroup
+}  // namespace
+
+int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) {
+    const int64_t nt = cdiv(q, GT);
+    return cdiv(n, GRAM_CHUNK) * (nt * (nt + 1) / 2) * 2 * GT * GT;
+}
+
 template <class TA>
 __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ Psi, const double* __restrict__ SPsi,
                                                       const double* __restrict__ MPsi, const double* __restrict__ mdiag,
-                                                      int64_t n, int32_t q, int64_t ld, int64_t chunk_rows,
-                                                      double* __restrict__ partial) {
-    const int32_t nt = (q + T32 - 1) / T32;
-    // decode the (a <= b) pair
+                                                      int64_t n, int32_t q, int64_t ld, double* __restrict__ partial) {
+    const int32_t nt = (q + GT - 1) / GT;
     int32_t pair = blockIdx.y, a = 0;
     while (pair >= nt - a) { pair -= nt - a; ++a; }
     const int32_t b = a + pair;
-    const int64_t r0 = blockIdx.x * chunk_rows;
-    const int64_t r1 = min(n, r0 + chunk_rows);
-    __shared__ TA P[T32][T32 + 1], Q[T32][T32 + 1], R[T32][T32 + 1];
+    const int64_t r0 = (int64_t)blockIdx.x * GRAM_CHUNK;
+    const int64_t r1 = min(n, r0 + GRAM_CHUNK);
+    __shared__ TA P[T32][GT + 1], Q[T32][GT + 1], R[T32][GT + 1];
     const int tid = threadIdx.x;
-    const int r = tid & 31;
-    double accS[4] = {0, 0, 0, 0}, accM[4] = {0, 0, 0, 0};
-    TA runS[4] = {0, 0, 0, 0}, runM[4] = {0, 0, 0, 0};
-    int tiles_in_run = 0;
+    const int ra = tid % 16, cb = tid / 16;   // output rows ra + 16 i, cols cb + 16 j
+    double accS[4][4] = {}, accM[4][4] = {};
+    TA runS[4][4] = {}, runM[4][4] = {};
+    int steps = 0;
     for (int64_t row0 = r0; row0 < r1; row0 += T32) {
-        for (int idx = tid; idx < TT; idx += 256) {
-            const int i = idx >> 5, c = idx & 31;
+        for (int idx = tid; idx < T32 * GT; idx += 256) {
+            const int i = idx / GT, c = idx % GT;
             const int64_t row = row0 + i;
-            const int ca = a * T32 + c, cb = b * T32 + c;
+            const int ca = a * GT + c, cbb = b * GT + c;
             const bool ok = row < r1;
             P[i][c] = (TA)((ok && ca < q) ? Psi[row * ld + ca] : 0.0);
-            Q[i][c] = (TA)((ok && cb < q) ? SPsi[row * ld + cb] : 0.0);
-            R[i][c] = (TA)((ok && cb < q) ? (mdiag ? mdiag[row] * Psi[row * ld + cb] : MPsi[row * ld + cb]) : 0.0);
+            Q[i][c] = (TA)((ok && cbb < q) ? SPsi[row * ld + cbb] : 0.0);
+            R[i][c] = (TA)((ok && cbb < q) ? (mdiag ? mdiag[row] * Psi[row * ld + cbb] : MPsi[row * ld + cbb]) : 0.0);
         }
         __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < T32; ++k) {
+            TA av[4], sv[4], mv[4];
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            const int c = (tid >> 5) + 8 * o;
-            TA sv = 0, mv = 0;
-#pragma unroll 8
-            for (int i = 0; i < T32; ++i) {
-                sv += P[i][r] * Q[i][c];
-                mv += P[i][r] * R[i][c];
-            }
-            runS[o] += sv;
-            runM[o] += mv;
-        }
-        if (++tiles_in_run == 8) {
+            for (int i = 0; i < 4; ++i) av[i] = P[k][ra + 16 * i];
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                accS[o] += (double)runS[o];
-                accM[o] += (double)runM[o];
-                runS[o] = runM[o] = 0;
+            for (int j = 0; j < 4; ++j) {
+                sv[j] = Q[k][cb + 16 * j];
+                mv[j] = R[k][cb + 16 * j];
             }
-            tiles_in_run = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    runS[i][j] += av[i] * sv[j];
+                    runM[i][j] += av[i] * mv[j];
+                }
         }
         __syncthreads();
+        if (++steps == 8) {   // 256 rows
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    accS[i][j] += (double)runS[i][j];
+                    accM[i][j] += (double)runM[i][j];
+                    runS[i][j] = runM[i][j] = 0;
+                }
+            steps = 0;
+        }
     }
     const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
-    double* out = partial + ((int64_t)blockIdx.x * npairs + blockIdx.y) * 2 * TT;
+    double* out = partial + ((int64_t)blockIdx.x * npairs + blockIdx.y) * 2 * GT * GT;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        const int c = (tid >> 5) + 8 * o;
-        out[r * T32 + c] = accS[o] + (double)runS[o];
-        out[TT + r * T32 + c] = accM[o] + (double)runM[o];
-    }
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = ra + 16 * i, c = cb + 16 * j;
+            out[r * GT + c] = accS[i][j] + (double)runS[i][j];
+            out[GT * GT + r * GT + c] = accM[i][j] + (double)runM[i][j];
+        }
 }
 
 __global__ void k_gram_reduce(const double* __restrict__ partial, int64_t nchunks, int32_t q, double* Sbar,
                               double* Mbar) {
-    const int32_t nt = (q + T32 - 1) / T32;
+    const int32_t nt = (q + GT - 1) / GT;
     const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
     const int64_t tot = (int64_t)q * q;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
         const int32_t i = (int32_t)(t / q), j = (int32_t)(t % q);
         if (i > j) continue;
-        const int32_t a = i / T32, b = j / T32;
+        const int32_t a = i / GT, b = j / GT;
         const int64_t pair = (int64_t)a * nt - (int64_t)a * (a - 1) / 2 + (b - a);
-        const int off = (i % T32) * T32 + (j % T32);
+        const int off = (i % GT) * GT + (j % GT);
         double s = 0, m = 0;
         for (int64_t ch = 0; ch < nchunks; ++ch) {
-            const double* p = partial + (ch * npairs + pair) * 2 * TT;
+            const double* p = partial + (ch * npairs + pair) * 2 * GT * GT;
             s += p[off];
-            m += p[TT + off];
+            m += p[GT * GT + off];
         }
         Sbar[(int64_t)i * q + j] = s;
         Sbar[(int64_t)j * q + i] = s;
@@ -655,15 +1078,15 @@ __global__ void k_gram_reduce(const double* __restrict__ partial, int64_t nchunk
 }
 
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
-                       int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
+                       int32_t q, int64_t ld, double* partial, int64_t /*chunk_rows*/, double* Sbar, double* Mbar,
                        hipStream_t s, bool fp32) {
-    const int64_t nt = cdiv(q, T32);
-    const int64_t nch = cdiv(n, chunk_rows);
+    const int64_t nt = cdiv(q, GT);
+    const int64_t nch = cdiv(n, GRAM_CHUNK);
     const dim3 grid((unsigned)nch, (unsigned)(nt * (nt + 1) / 2));
     if (fp32)
-        k_gram_partial<float><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, chunk_rows, partial);
+        k_gram_partial<float><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, partial);
     else
-        k_gram_partial<double><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, chunk_rows, partial);
+        k_gram_partial<double><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_gram_reduce<<<grid_for((int64_t)q * q, 256), 256, 0, s>>>(partial, nch, q, Sbar, Mbar);
@@ -671,77 +1094,104 @@ hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi
 }
 
 // ============================================================ Ritz update + residual
-int64_t ritz_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows) { return cdiv(n, chunk_rows) * 2 * (int64_t)q; }
+// Phi = Psi Phibar, (S Phi) = (S Psi) Phibar (kept in registers), M Phi = m * Phi
+// (level 0) or (M Psi) Phibar; per-column partial sums of the residual
+// numerator and of the normalisation.  Workgroup: RITZ_ROWS rows x 32
+// columns; thread: 2 rows x 4 columns of every product.
+namespace {
+constexpr int RITZ_ROWS = 64;
+}
+int64_t ritz_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) { return cdiv(n, RITZ_ROWS) * 2 * (int64_t)q; }
 
-// Phi = Psi Phibar, (S Phi) = (S Psi) Phibar kept in registers, M Phi =
-// m * Phi (level 0) or (M Psi) Phibar; per-column partial sums of the
-// residual numerator and the normalisation.
 __global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ Psi, const double* __restrict__ SPsi,
                                               const double* __restrict__ MPsi, const double* __restrict__ mdiag,
                                               const double* __restrict__ Phibar, const double* __restrict__ lam,
                                               int64_t n, int32_t q, int64_t ld, double* __restrict__ Phi,
-                                              double* __restrict__ MPhi, double* __restrict__ partial,
-                                              int64_t chunk_rows, int minv_norm) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* Pb = reinterpret_cast<double*>(smem_raw);    // q x 32
-    __shared__ double red[2][8][T32];
+                                              double* __restrict__ MPhi, double* __restrict__ partial, int minv_norm) {
+    __shared__ double Ps[RITZ_ROWS][T32 + 1], Ss[RITZ_ROWS][T32 + 1], Ms[RITZ_ROWS][T32 + 1];
+    __shared__ double Bs[T32][T32 + 1];
+    // the column reduction reuses the Psi staging area (2 x 32 x 33 doubles)
+    auto red = reinterpret_cast<double(*)[32][T32 + 1]>(&Ps[0][0]);
     const int tid = threadIdx.x;
-    const int cl = tid & 31, rl = tid >> 5;
-    const int col = blockIdx.y * T32 + cl;
-    for (int idx = tid; idx < q * T32; idx += 256) {
-        const int kk = idx >> 5, c = idx & 31;
-        const int cc = blockIdx.y * T32 + c;
-        Pb[idx] = cc < q ? Phibar[(int64_t)kk * q + cc] : 0.0;
-    }
-    __syncthreads();
-    const double lc = col < q ? lam[col] : 0.0;
-    double num = 0, den = 0;
-    const int64_t r0 = blockIdx.x * chunk_rows;
-    const int64_t r1 = min(n, r0 + chunk_rows);
-    for (int64_t row = r0 + rl; row < r1; row += 8) {
-        const double* pr = Psi + row * ld;
-        const double* sr = SPsi + row * ld;
-        double phi = 0, sphi = 0, mphi = 0;
-        if (mdiag) {
-            for (int kk = 0; kk < q; ++kk) {
-                const double w = Pb[kk * T32 + cl];
-                phi += pr[kk] * w;
-                sphi += sr[kk] * w;
-            }
-            mphi = mdiag[row] * phi;
-        } else {
-            const double* mr = MPsi + row * ld;
-            for (int kk = 0; kk < q; ++kk) {
-                const double w = Pb[kk * T32 + cl];
-                phi += pr[kk] * w;
-                sphi += sr[kk] * w;
-                mphi += mr[kk] * w;
+    const int rl = tid % 32, cl = tid / 32;   // rows rl + 32 i (i < 2), cols cl + 8 j (j < 4)
+    const int64_t row0 = (int64_t)blockIdx.x * RITZ_ROWS;
+    const int col0 = blockIdx.y * T32;
+    const bool has_m = mdiag == nullptr;
+    double ap[2][4] = {}, as[2][4] = {}, am[2][4] = {};
+    for (int k0 = 0; k0 < q; k0 += T32) {
+        for (int idx = tid; idx < RITZ_ROWS * T32; idx += 256) {
+            const int r = idx / T32, kk = idx % T32;
+            const int64_t row = row0 + r;
+            const bool ok = row < n && k0 + kk < q;
+            Ps[r][kk] = ok ? Psi[row * ld + k0 + kk] : 0.0;
+            Ss[r][kk] = ok ? SPsi[row * ld + k0 + kk] : 0.0;
+            if (has_m) Ms[r][kk] = ok ? MPsi[row * ld + k0 + kk] : 0.0;
+        }
+        for (int idx = tid; idx < T32 * T32; idx += 256) {
+            const int kk = idx / T32, c = idx % T32;
+            Bs[kk][c] = (k0 + kk < q && col0 + c < q) ? Phibar[(int64_t)(k0 + kk) * q + col0 + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < T32; ++kk) {
+            double b[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][cl + 8 * j];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const double p = Ps[rl + 32 * i][kk], sv = Ss[rl + 32 * i][kk];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    ap[i][j] += p * b[j];
+                    as[i][j] += sv * b[j];
+                }
+                if (has_m) {
+                    const double mv = Ms[rl + 32 * i][kk];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) am[i][j] += mv * b[j];
+                }
             }
         }
-        if (col < q) {
+        __syncthreads();
+    }
+    double num[4] = {0, 0, 0, 0}, den[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int64_t row = row0 + rl + 32 * i;
+        if (row >= n) continue;
+        const double mr = has_m ? 0.0 : mdiag[row];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = col0 + cl + 8 * j;
+            if (col >= q) continue;
+            const double phi = ap[i][j], sphi = as[i][j];
+            const double mphi = has_m ? am[i][j] : mr * phi;
             Phi[row * ld + col] = phi;
             if (MPhi) MPhi[row * ld + col] = mphi;
-            const double res = sphi - lc * mphi;
+            const double res = sphi - lam[col] * mphi;
             if (minv_norm) {
-                num += res * res / mdiag[row];
-                den += phi * mphi;
+                num[j] += res * res / mr;
+                den[j] += phi * mphi;
             } else {
-                num += res * res;
-                den += mphi * mphi;
+                num[j] += res * res;
+                den[j] += mphi * mphi;
             }
         }
     }
-    red[0][rl][cl] = num;
-    red[1][rl][cl] = den;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        red[0][rl][cl + 8 * j] = num[j];
+        red[1][rl][cl + 8 * j] = den[j];
+    }
     __syncthreads();
-    if (tid < T32 && blockIdx.y * T32 + tid < q) {
-        double a = 0, b = 0;
-        for (int k = 0; k < 8; ++k) {
+    if (tid < T32 && col0 + tid < q) {
+        double a = 0, b2 = 0;
+        for (int k = 0; k < 32; ++k) {
             a += red[0][k][tid];
-            b += red[1][k][tid];
+            b2 += red[1][k][tid];
         }
-        partial[(int64_t)blockIdx.x * 2 * q + blockIdx.y * T32 + tid] = a;
-        partial[(int64_t)blockIdx.x * 2 * q + q + blockIdx.y * T32 + tid] = b;
+        partial[(int64_t)blockIdx.x * 2 * q + col0 + tid] = a;
+        partial[(int64_t)blockIdx.x * 2 * q + q + col0 + tid] = b2;
     }
 }
 
@@ -759,15 +1209,12 @@ __global__ void k_resid_reduce(const double* __restrict__ partial, int64_t nchun
 
 hipError_t launch_ritz(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag,
                        const double* Phibar, const double* lam, int64_t n, int32_t q, int64_t ld, double* Phi,
-                       double* MPhi, double* partial, int64_t chunk_rows, bool minv_norm, double lam_floor,
+                       double* MPhi, double* partial, int64_t /*chunk_rows*/, bool minv_norm, double lam_floor,
                        double* resid, hipStream_t s) {
-    const int64_t nch = cdiv(n, chunk_rows);
+    const int64_t nch = cdiv(n, RITZ_ROWS);
     const int64_t nct = cdiv(q, T32);
-    const size_t lds = (size_t)q * T32 * sizeof(double);
-    hipError_t e0 = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_ritz), lds, 4096);
-    if (e0 != hipSuccess) return e0;
-    k_ritz<<<dim3((unsigned)nch, (unsigned)nct), 256, lds, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi,
-                                                                 MPhi, partial, chunk_rows, minv_norm ? 1 : 0);
+    k_ritz<<<dim3((unsigned)nch, (unsigned)nct), 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi, MPhi,
+                                                              partial, minv_norm ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_resid_reduce<<<(unsigned)cdiv(q, 256), 256, 0, s>>>(partial, nch, q, lam, lam_floor, resid);
@@ -857,126 +1304,215 @@ hipError_t launch_row_scale(const double* V, const double* w, bool sqrt_w, int64
     return hipGetLastError();
 }
 
-// ---- cyclic Jacobi in round-robin order ---------------------------------
-// round r pairs the players at positions x and m-1-x; position 0 is fixed,
-// positions 1..m-1 hold players 1 + (x - 1 + r) mod (m - 1)
+// ---- block Jacobi in round-robin order ----------------------------------
+// The m x m matrix (m a multiple of 2b) is split into nb = m / b blocks of b
+// indices; a round pairs the blocks at tournament positions x and nb-1-x
+// (position 0 fixed, positions 1..nb-1 hold blocks 1 + (x - 1 + r) mod (nb - 1)).
+// Every pair's 2b x 2b principal submatrix is diagonalised by cyclic Jacobi
+// in LDS (k_bj_local), then C <- J^T C J and V <- V J with J the
+// block-diagonal product of the pairs' orthogonal factors (k_bj_apply).
 __device__ __forceinline__ int jac_player(int x, int r, int m) { return x == 0 ? 0 : 1 + (x - 1 + r) % (m - 1); }
-__device__ __forceinline__ int jac_partner(int a, int r, int m) {
-    int pos = a == 0 ? 0 : 1 + ((a - 1 - r) % (m - 1) + (m - 1)) % (m - 1);
-    return jac_player(m - 1 - pos, r, m);
+
+__device__ __forceinline__ void bj_pair(int k, int r, int nb, int& I, int& J) {
+    const int a = jac_player(k, r, nb), c = jac_player(nb - 1 - k, r, nb);
+    I = min(a, c);
+    J = max(a, c);
+}
+template <int B>
+__device__ __forceinline__ int bj_index(int l, int I, int J) { return l < B ? I * B + l : J * B + (l - B); }
+
+// one workgroup per block pair; Q (2b x 2b, row-major, Q[l][c]) of every pair to Qs
+template <int B>
+__global__ __launch_bounds__(256) void k_bj_local(const double* __restrict__ C, int32_t m, int32_t r,
+                                                  double* __restrict__ Qs, const double* __restrict__ normf,
+                                                  double tol_rel, double tol_abs_rel, int32_t max_sweeps,
+                                                  int32_t* rot_count) {
+    constexpr int W = 2 * B;
+    __shared__ double A[W][W + 1];
+    __shared__ double Q[W][W + 1];
+    __shared__ double cs[B], sn[B];
+    __shared__ int pp[B], qq[B];
+    __shared__ int nrot, total;
+    const int nb = m / B;
+    int I, J;
+    bj_pair(blockIdx.x, r, nb, I, J);
+    const double tol_abs = tol_abs_rel * normf[0];
+    for (int idx = threadIdx.x; idx < W * W; idx += 256) {
+        const int a = idx / W, c = idx % W;
+        A[a][c] = C[(int64_t)bj_index<B>(a, I, J) * m + bj_index<B>(c, I, J)];
+        Q[a][c] = a == c ? 1.0 : 0.0;
+    }
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        if (threadIdx.x == 0) nrot = 0;
+        __syncthreads();
+        for (int rr = 0; rr < W - 1; ++rr) {
+            if (threadIdx.x < B) {
+                const int k = threadIdx.x;
+                const int a = jac_player(k, rr, W), c = jac_player(W - 1 - k, rr, W);
+                const int p = min(a, c), q = max(a, c);
+                const double app = A[p][p], aqq = A[q][q], apq = A[p][q];
+                double cc = 1.0, ss = 0.0;
+                if (fabs(apq) > fmax(tol_abs, tol_rel * sqrt(fabs(app * aqq)))) {
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    cc = 1.0 / sqrt(1.0 + t * t);
+                    ss = t * cc;
+                    atomicAdd(&nrot, 1);
+                }
+                cs[k] = cc;
+                sn[k] = ss;
+                pp[k] = p;
+                qq[k] = q;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int idx = threadIdx.x; idx < B * W; idx += 256) {
+                const int k = idx / W, c = idx % W;
+                if (sn[k] == 0.0) continue;
+                const double x = A[pp[k]][c], y = A[qq[k]][c];
+                A[pp[k]][c] = cs[k] * x - sn[k] * y;
+                A[qq[k]][c] = sn[k] * x + cs[k] * y;
+            }
+            __syncthreads();
+            // columns: A <- A J, Q <- Q J
+            for (int idx = threadIdx.x; idx < B * W; idx += 256) {
+                const int k = idx % B, a = idx / B;
+                if (sn[k] == 0.0) continue;
+                const double x = A[a][pp[k]], y = A[a][qq[k]];
+                A[a][pp[k]] = x * cs[k] - y * sn[k];
+                A[a][qq[k]] = x * sn[k] + y * cs[k];
+                const double u = Q[a][pp[k]], v = Q[a][qq[k]];
+                Q[a][pp[k]] = u * cs[k] - v * sn[k];
+                Q[a][qq[k]] = u * sn[k] + v * cs[k];
+            }
+            __syncthreads();
+            if (threadIdx.x < B && sn[threadIdx.x] != 0.0) {
+                A[pp[threadIdx.x]][qq[threadIdx.x]] = 0.0;
+                A[qq[threadIdx.x]][pp[threadIdx.x]] = 0.0;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) total += nrot;
+        __syncthreads();
+        if (nrot == 0) break;
+    }
+    double* Qo = Qs + (int64_t)blockIdx.x * W * W;
+    for (int idx = threadIdx.x; idx < W * W; idx += 256) Qo[idx] = Q[idx / W][idx % W];
+    if (threadIdx.x == 0 && total) atomicAdd(rot_count, total);
 }
 
-__global__ void k_jacobi_init(const double* C, int32_t m, double* V, double* diag, double* off) {
-    const int64_t tot = (int64_t)m * m;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t i = (int32_t)(t / m), j = (int32_t)(t % m);
-        V[t] = i == j ? 1.0 : 0.0;
-        if (i == j) diag[i] = C[t];
-        if (j == jac_partner(i, 0, m)) off[i] = C[t];
+// C <- J^T C J on every (pair, pair') tile (pair <= pair'), V <- V J on row
+// chunks; first npairs*(npairs+1)/2 workgroups do C, the rest V
+template <int B>
+__global__ __launch_bounds__(256) void k_bj_apply(double* C, double* V, int32_t m, int32_t r,
+                                                  const double* __restrict__ Qs) {
+    constexpr int W = 2 * B;
+    __shared__ double X[W][W + 1], Q1[W][W + 1], Q2[W][W + 1];
+    const int nb = m / B, np = nb / 2;
+    const int64_t ctiles = (int64_t)np * (np + 1) / 2;
+    const int tid = threadIdx.x;
+    if (blockIdx.x < ctiles) {
+        int t = blockIdx.x, P = 0;
+        while (t >= np - P) { t -= np - P; ++P; }
+        const int P2 = P + t;
+        int I1, J1, I2, J2;
+        bj_pair(P, r, nb, I1, J1);
+        bj_pair(P2, r, nb, I2, J2);
+        const double* q1 = Qs + (int64_t)P * W * W;
+        const double* q2 = Qs + (int64_t)P2 * W * W;
+        for (int idx = tid; idx < W * W; idx += 256) {
+            const int a = idx / W, c = idx % W;
+            X[a][c] = C[(int64_t)bj_index<B>(a, I1, J1) * m + bj_index<B>(c, I2, J2)];
+            Q1[a][c] = q1[idx];
+            Q2[a][c] = q2[idx];
+        }
+        __syncthreads();
+        // T = Q1^T X  (into registers, then X <- T)
+        constexpr int PER = W * W / 256;
+        double tv[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + 256 * e, a = idx / W, c = idx % W;
+            double v = 0;
+            for (int l = 0; l < W; ++l) v += Q1[l][a] * X[l][c];
+            tv[e] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + 256 * e;
+            X[idx / W][idx % W] = tv[e];
+        }
+        __syncthreads();
+        // out = T Q2
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + 256 * e, a = idx / W, c = idx % W;
+            double v = 0;
+            for (int l = 0; l < W; ++l) v += X[a][l] * Q2[l][c];
+            const int gi = bj_index<B>(a, I1, J1), gj = bj_index<B>(c, I2, J2);
+            C[(int64_t)gi * m + gj] = v;
+            C[(int64_t)gj * m + gi] = v;
+        }
+    } else {
+        // V rows [row0, row0 + W) times Q of pair P
+        const int64_t item = blockIdx.x - ctiles;
+        const int P = (int)(item % np);
+        const int64_t row0 = (item / np) * W;
+        int I1, J1;
+        bj_pair(P, r, nb, I1, J1);
+        const double* q1 = Qs + (int64_t)P * W * W;
+        for (int idx = tid; idx < W * W; idx += 256) {
+            const int a = idx / W, c = idx % W;
+            const int64_t row = row0 + a;
+            X[a][c] = row < m ? V[row * m + bj_index<B>(c, I1, J1)] : 0.0;
+            Q1[a][c] = q1[idx];
+        }
+        __syncthreads();
+        constexpr int PER = W * W / 256;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + 256 * e, a = idx / W, c = idx % W;
+            const int64_t row = row0 + a;
+            double v = 0;
+            for (int l = 0; l < W; ++l) v += X[a][l] * Q1[l][c];
+            if (row < m) V[row * m + bj_index<B>(c, I1, J1)] = v;
+        }
     }
 }
-hipError_t launch_jacobi_init(const double* C, int32_t m, double* V, double* diag, double* off, hipStream_t s) {
-    k_jacobi_init<<<grid_for((int64_t)m * m, 256), 256, 0, s>>>(C, m, V, diag, off);
+
+hipError_t launch_bj_round(int b, double* C, double* V, int32_t m, int32_t round, double* Qs, const double* normf,
+                           double tol_rel, double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count,
+                           hipStream_t s) {
+    const int nb = m / b, np = nb / 2;
+    const int64_t ctiles = (int64_t)np * (np + 1) / 2;
+    const int64_t vitems = cdiv(m, 2 * b) * np;
+    if (b == 32) {
+        k_bj_local<32><<<np, 256, 0, s>>>(C, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_bj_apply<32><<<(unsigned)(ctiles + vitems), 256, 0, s>>>(C, V, m, round, Qs);
+    } else if (b == 16) {
+        k_bj_local<16><<<np, 256, 0, s>>>(C, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_bj_apply<16><<<(unsigned)(ctiles + vitems), 256, 0, s>>>(C, V, m, round, Qs);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-// One round: all m/2 rotations of the round at once, C <- J^T C J, V <- V J.
-// Every block recomputes the round's rotations from diag_cur/off_cur (written
-// by the previous round), updates its share of the 2x2 blocks and V rows, and
-// records the entries the next round's rotations need.
-__global__ __launch_bounds__(256) void k_jacobi_round(double* C, double* V, int32_t m, int32_t r,
-                                                      const double* __restrict__ diag_cur,
-                                                      const double* __restrict__ off_cur, double* diag_next,
-                                                      double* off_next, double tol_rel,
-                                                      const double* __restrict__ normf, double tol_abs_rel,
-                                                      int32_t* rot_count) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int h = m / 2;
-    double* cs = reinterpret_cast<double*>(smem_raw);
-    double* sn = cs + h;
-    int* pp = reinterpret_cast<int*>(sn + h);
-    int* qq = pp + h;
-    __shared__ int nrot;
-    if (threadIdx.x == 0) nrot = 0;
-    const double tol_abs = tol_abs_rel * normf[0];
-    __syncthreads();
-    for (int kk = threadIdx.x; kk < h; kk += blockDim.x) {
-        int a = jac_player(kk, r, m), b = jac_player(m - 1 - kk, r, m);
-        int p = min(a, b), q = max(a, b);
-        double app = diag_cur[p], aqq = diag_cur[q], apq = off_cur[p];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > fmax(tol_abs, tol_rel * sqrt(fabs(app * aqq)))) {
-            double tau = (aqq - app) / (2.0 * apq);
-            double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-            atomicAdd(&nrot, 1);
-        }
-        cs[kk] = c;
-        sn[kk] = s;
-        pp[kk] = p;
-        qq[kk] = q;
-    }
-    __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0 && nrot) atomicAdd(rot_count, nrot);
-    const int64_t nblk = (int64_t)h * (h + 1) / 2;
-    const int64_t tot = nblk + (int64_t)m * h;
-    const int rn = r + 1;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
-        if (t < nblk) {
-            // decode upper block pair (k <= l)
-            int64_t rem = t;
-            int k = (int)((sqrt(8.0 * (double)rem + 1.0) - 1.0) / 2.0);   // row of a lower-triangle walk
-            while ((int64_t)(k + 1) * (k + 2) / 2 <= rem) ++k;
-            while ((int64_t)k * (k + 1) / 2 > rem) --k;
-            int l = (int)(rem - (int64_t)k * (k + 1) / 2);   // l <= k
-            const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
-            const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
-            double g00 = C[(int64_t)pk * m + pl], g01 = C[(int64_t)pk * m + ql];
-            double g10 = C[(int64_t)qk * m + pl], g11 = C[(int64_t)qk * m + ql];
-            // rows (pair k)
-            double h00 = ck * g00 - sk * g10, h01 = ck * g01 - sk * g11;
-            double h10 = sk * g00 + ck * g10, h11 = sk * g01 + ck * g11;
-            // columns (pair l)
-            double n00 = h00 * cl - h01 * sl, n01 = h00 * sl + h01 * cl;
-            double n10 = h10 * cl - h11 * sl, n11 = h10 * sl + h11 * cl;
-            if (k == l && sk != 0.0) { n01 = 0.0; n10 = 0.0; }
-            const int ri[2] = {pk, qk}, ci[2] = {pl, ql};
-            const double nv[2][2] = {{n00, n01}, {n10, n11}};
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y) {
-                    const int i = ri[x], j = ci[y];
-                    const double v = nv[x][y];
-                    C[(int64_t)i * m + j] = v;
-                    C[(int64_t)j * m + i] = v;
-                    if (i == j) diag_next[i] = v;
-                    if (jac_partner(i, rn, m) == j) { off_next[i] = v; off_next[j] = v; }
-                }
-        } else {
-            const int64_t u = t - nblk;
-            const int64_t row = u / h;
-            const int kk = (int)(u % h);
-            const double c = cs[kk], s = sn[kk];
-            if (s == 0.0) continue;
-            double* vr = V + row * m;
-            const double a = vr[pp[kk]], b = vr[qq[kk]];
-            vr[pp[kk]] = a * c - b * s;
-            vr[qq[kk]] = a * s + b * c;
-        }
-    }
+// V = identity (m x m)
+__global__ void k_identity(double* V, int32_t m) {
+    const int64_t tot = (int64_t)m * m;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x)
+        V[t] = (t / m) == (t % m) ? 1.0 : 0.0;
 }
-hipError_t launch_jacobi_round(double* C, double* V, int32_t m, int32_t round, const double* diag_cur,
-                               const double* off_cur, double* diag_next, double* off_next, double tol_rel,
-                               const double* normf, double tol_abs_rel, int32_t* rot_count, hipStream_t s) {
-    const int h = m / 2;
-    const int64_t tot = (int64_t)h * (h + 1) / 2 + (int64_t)m * h;
-    const size_t lds = (size_t)h * (2 * sizeof(double) + 2 * sizeof(int));
-    unsigned g = grid_for(tot, 256);
-    if (g > 2048) g = 2048;
-    k_jacobi_round<<<g, 256, lds, s>>>(C, V, m, round, diag_cur, off_cur, diag_next, off_next, tol_rel, normf,
-                                        tol_abs_rel, rot_count);
+hipError_t launch_identity(double* V, int32_t m, hipStream_t s) {
+    k_identity<<<grid_for((int64_t)m * m, 256), 256, 0, s>>>(V, m);
     return hipGetLastError();
 }
 
@@ -1012,9 +1548,9 @@ hipError_t launch_sort_eig(const double* C, int32_t m, int32_t kvalid, const dou
     return hipGetLastError();
 }
 
-// C (m x m) = Ck (k x k) with, when m = k + 1, a decoupled dummy row/column
-// whose diagonal exceeds every eigenvalue; normf[0] = ||Ck||_F; dis = D^-1/2
-// (1 on the dummy)
+// C (m x m) = Ck (k x k) padded with decoupled dummy rows/columns whose
+// diagonal exceeds every eigenvalue; normf[0] = ||Ck||_F; dis = D^-1/2
+// (1 on the dummies)
 __global__ void k_embed_copy(const double* Ck, int32_t k, int32_t m, double* C) {
     const int64_t tot = (int64_t)m * m;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
@@ -1035,10 +1571,8 @@ __global__ __launch_bounds__(1024) void k_embed_finish(const double* Ck, int32_t
         __syncthreads();
     }
     const double nf = sqrt(red[0]);
-    if (threadIdx.x == 0) {
-        normf[0] = nf;
-        if (m > k) C[(int64_t)k * m + k] = 4.0 * nf + 1.0;
-    }
+    if (threadIdx.x == 0) normf[0] = nf;
+    for (int i = k + threadIdx.x; i < m; i += blockDim.x) C[(int64_t)i * m + i] = 4.0 * nf + 1.0 + i;
     for (int i = threadIdx.x; i < m; i += blockDim.x) dis[i] = i < k ? 1.0 / sqrt(D[i]) : 1.0;
 }
 hipError_t launch_embed_pad(const double* Ck, int32_t k, int32_t m, double* C, double* normf, double* dis,
@@ -1421,18 +1955,18 @@ hipError_t launch_bwd_gather(int64_t nv, const int64_t* vt_ptr, const int64_t* v
 }
 // out[r, c] = in[c * nv + perm[r]] for r < n, c < k (column-major mesh order -> row-major internal order)
 __global__ void k_import_cols(const double* in, int64_t nv, const int32_t* perm, int64_t n, int32_t k, double* out,
-                              int64_t ld) {
+                              int64_t ld, const double* sign) {
     const int64_t tot = n * k;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = t % n;
         const int c = (int)(t / n);
-        out[r * ld + c] = in[(int64_t)c * nv + perm[r]];
+        out[r * ld + c] = (sign ? sign[c] : 1.0) * in[(int64_t)c * nv + perm[r]];
     }
 }
 hipError_t launch_import_cols(const double* in, int64_t nv, const int32_t* perm, int64_t n, int32_t k, double* out,
-                              int64_t ld, hipStream_t s) {
+                              int64_t ld, hipStream_t s, const double* sign) {
     if (n <= 0 || k <= 0) return hipSuccess;
-    k_import_cols<<<grid_for(n * k, 256), 256, 0, s>>>(in, nv, perm, n, k, out, ld);
+    k_import_cols<<<grid_for(n * k, 256), 256, 0, s>>>(in, nv, perm, n, k, out, ld, sign);
     return hipGetLastError();
 }
 

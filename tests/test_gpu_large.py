@@ -1,0 +1,103 @@
+"""GPU parity at the workloads' real sizes (100k torus, 1M sphere), through
+the C ABI.  Where the oracle cannot compute a whole result in seconds the
+checks use properties that hold at any size: the residual of every returned
+pair evaluated with the oracle's own FP64 assembly, M-orthonormality,
+Rayleigh quotients, and Sylvester inertia counts of S - sigma M from a
+library LDL^T-like factorisation (SuperLU without off-diagonal pivoting)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import assembly, metrics, sim
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def negative_count(S, m, sigma):
+    """Number of eigenvalues of S x = lambda M x below sigma (Sylvester):
+    sign count of the pivots of a symmetric-ordering LU without off-diagonal
+    pivoting (U = D L^T)."""
+    A = (S - sigma * sp.diags(m)).tocsc()
+    lu = spla.splu(A, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+    d = lu.U.diagonal()
+    assert np.array_equal(lu.perm_r, lu.perm_c), "symmetric permutation expected"
+    return int(np.sum(d < 0))
+
+
+@pytest.fixture(scope="module")
+def torus100k(cuda):
+    import paper_2111_09039_amd as hs
+    V, F, d = synth.config_mesh("torus100k", seed=0)
+    S, m = assembly.assemble(V, F, density=d)
+    H = hs.Hierarchy(V, F, 100, density=d, levels=5)
+    print(f"[torus100k] levels {[H.level_info(t)['n'] for t in range(H.levels)]}", flush=True)
+    return V, F, d, S, m, H
+
+
+def test_torus100k_factor_inertia_and_solve(torus100k):
+    V, F, d, S, m, H = torus100k
+    e = H.export(0)
+    for mu in (-0.5, 40.0):
+        neg = H.factor(0, mu)
+        assert neg == negative_count(S, m, mu), mu
+        B = np.random.default_rng(3).standard_normal((len(V), 13))
+        X = H.solve_shifted(0, _t(B)).cpu().numpy()
+        A = (S - mu * sp.diags(m)).tocsc()
+        Xr = spla.splu(A).solve(B)
+        assert np.abs(X - Xr).max() <= 1e-10 * np.abs(Xr).max(), mu
+        Ainf = np.abs(A).sum(axis=1).max()
+        bw = (np.abs(A @ X - B).max(axis=0) / (Ainf * np.abs(X).max(axis=0) + np.abs(B).max(axis=0))).max()
+        assert bw < 1e-13, bw
+
+
+def test_torus100k_hsim(torus100k):
+    import paper_2111_09039_amd as hs
+    V, F, d, S, m, H = torus100k
+    p = 100
+    ev, X, r, st = H.solve(tol=1e-8)
+    ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
+    print(f"[torus100k hsim] iters {st['iters']} total {st['ms_total']:.1f} ms", flush=True)
+    assert r.max() < 1e-8
+    assert sim.residual(S, m, X, ev).max() < 1.5e-8
+    assert metrics.m_orthonormality(X, m) < 1e-10
+    rq = np.einsum("ij,ij->j", X, S @ X) / np.einsum("ij,ij->j", X, m[:, None] * X)
+    assert np.abs(rq - ev)[1:].max() <= 1e-12 * ev[-1]
+    # nothing below the last returned eigenvalue is missed
+    assert negative_count(S, m, ev[-1] * (1 + 1e-7)) >= p
+    assert negative_count(S, m, ev[-1] * (1 - 1e-7)) <= p - 1
+    # mixed precision reaches the same eigenvalues
+    evm, Xm, rm, stm = H.solve(tol=1e-8, precision=hs.MIXED)
+    evm = evm.cpu().numpy()
+    assert np.abs(evm - ev)[1:].max() <= 1e-6 * ev[1:].min()
+
+
+@pytest.mark.slow
+def test_sphere1m_bench_configuration(cuda):
+    """The benchmark's configuration: 1M-vertex sphere, p = 100, eps = 1e-6."""
+    import paper_2111_09039_amd as hs
+    V, F, d = synth.config_mesh("sphere1m", seed=0)
+    S, m = assembly.assemble(V, F)
+    H = hs.Hierarchy(V, F, 100, levels=2)
+    for prec in (hs.FP64, hs.MIXED):
+        ev, X, r, st = H.solve(tol=1e-6, precision=prec)
+        ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
+        print(f"[sphere1m precision={prec}] iters {st['iters']} {st['ms_total']:.0f} ms, "
+              f"refine {st['refine_steps']} escalated {st['escalated']}", flush=True)
+        assert r.max() < 1e-6
+        assert sim.residual(S, m, X, ev).max() < 1.5e-6
+        tol_orth = 1e-10 if prec == hs.FP64 else 1e-8
+        assert metrics.m_orthonormality(X, m) < tol_orth
+        assert abs(ev[0]) < 1e-10 * ev[1]
+        rq = np.einsum("ij,ij->j", X, S @ X) / np.einsum("ij,ij->j", X, m[:, None] * X)
+        assert np.abs(rq - ev)[1:].max() <= 1e-11 * ev[-1]
+        if prec == hs.FP64:
+            ev64 = ev
+        else:
+            assert np.abs(ev - ev64)[1:].max() <= 1e-6 * ev64[1:].min()
