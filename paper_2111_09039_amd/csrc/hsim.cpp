@@ -61,6 +61,14 @@ static T* dptr(DeviceBuffer& b) { return b.as<T>(); }
 
 static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+int env_int(const char* name, int dflt) {
+    const char* e = getenv(name);
+    if (!e || !*e) return dflt;
+    char* end = nullptr;
+    const long v = strtol(e, &end, 10);
+    return (end && *end == 0) ? (int)v : dflt;
+}
+
 // ============================================================ profiling
 // HIP events around every launch of a kernel class (only when asked for).
 struct Prof {
@@ -131,7 +139,8 @@ struct DenseGEP {
     void setup(int32_t kk) {
         if (k == kk) return;
         k = kk;
-        bj = k <= 256 ? 16 : 32;                       // block Jacobi block size
+        bj = env_int("HSIM_BJ_B", 16);  // block Jacobi block size
+        if (bj != 16 && bj != 32) bj = 16;
         m = (int32_t)round_up(k, 2 * bj);
         ns_pad = (int32_t)round_up(k, NB);
         Mt = ns_pad / NB;
@@ -233,12 +242,13 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     HIPCHECK(launch_identity(dptr<double>(V), m, s));
     const double tol_rel = 1e-15;
     const int32_t nb = m / bj;
+    const int32_t inner = std::max(1, std::min(3, env_int("HSIM_BJ_INNER", 1)));
     int32_t sweeps = 0;
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
         HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 1, 0, s));
         for (int32_t r = 0; r < nb - 1; ++r)
             HIPCHECK(launch_bj_round(bj, dptr<double>(C), dptr<double>(V), m, r, dptr<double>(Qs), dptr<double>(normf),
-                                     tol_rel, 1e-17, 3, dptr<int32_t>(rot), s));
+                                     tol_rel, 1e-17, inner, dptr<int32_t>(rot), s));
         int32_t nrot = 0;
         HIPCHECK(hipMemcpyAsync(&nrot, rot.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
@@ -437,7 +447,7 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
             T.l_entries += (double)f.ns * (f.ns + 1) / 2 + (double)f.ns * f.mu;
             T.pivots += f.ns;
         }
-        T.big = T.ns_pad_max >= BIG_NS;
+        T.big = T.ns_pad_max > wsolve_max_ns() || T.ns_pad_max >= env_int("HSIM_BIG_NS", BIG_NS);
         if (!T.big && !solve_chunk_width(T.ns_pad_max, 1, false))
             fail(HSIM_E_UNIMPLEMENTED, "supernode of %d pivots exceeds the solve kernels' LDS", T.ns_pad_max);
         if (T.big) {
@@ -584,10 +594,9 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
             continue;
         }
         P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
-            const int32_t qc = solve_chunk_width(T.ns_pad_max, ncols, sizeof(TF) == 4);
-            HIPCHECK(launch_solve_fwd<TF>(tiles, linv, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols, qc,
-                                          dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr), dptr<int64_t>(L.gidx), md,
-                                          s));
+            HIPCHECK(launch_wsolve<TF>(true, tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols,
+                                       dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr), dptr<int64_t>(L.gidx), md,
+                                       nullptr, false, s));
         });
     }
     for (int32_t t = sy.tree_levels - 1; t >= 0; --t) {
@@ -605,9 +614,8 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
             continue;
         }
         P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
-            const int32_t qc = solve_chunk_width(T.ns_pad_max, ncols, sizeof(TF) == 4);
-            HIPCHECK(launch_solve_bwd<TF>(tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols, qc,
-                                          dptr<int32_t>(L.rows), true, s));
+            HIPCHECK(launch_wsolve<TF>(false, tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols,
+                                       nullptr, H->ld, nullptr, nullptr, nullptr, dptr<int32_t>(L.rows), true, s));
         });
     }
 }

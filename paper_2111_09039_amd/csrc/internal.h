@@ -19,6 +19,9 @@ struct Error {
 [[noreturn]] void fail(hsim_status code, const char* fmt, ...);
 void set_last_error(const std::string& msg);
 
+// integer tuning knob from the environment (dflt when unset or not a number)
+int env_int(const char* name, int dflt);
+
 // tile edge of the supernodal factor panels (doubles per tile = NB * NB)
 constexpr int NB = 32;
 

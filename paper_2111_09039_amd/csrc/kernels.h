@@ -67,6 +67,18 @@ hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const 
                             int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
                             int32_t qc, const int32_t* rows, bool apply_dinv, hipStream_t s);
 
+// Wave-level matrix-core solves of one tree level (fronts [f0, f1), pivot
+// counts up to wsolve_max_ns()): one wave per (front, 16 columns), the
+// front's block of the right-hand side in registers.  fwd: forward sweep
+// (mdiag optional pre-scaling, children's updates gathered from ubuf, own
+// updates written to ubuf); !fwd: backward sweep (apply_dinv divides by D).
+int32_t wsolve_max_ns();
+template <class TF>
+hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
+                         int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
+                         double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx, const double* mdiag,
+                         const int32_t* rows, bool apply_dinv, hipStream_t s);
+
 // Block solves of tree levels with wide supernodes, 128-row pivot blocks:
 // phase 0 forward init (items: front, tile row), 1 forward diagonal block kb
 // (items: front), 2 forward update below block kb (items: front, tile row),

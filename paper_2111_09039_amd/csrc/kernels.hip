@@ -12,6 +12,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -26,6 +27,23 @@ __device__ __forceinline__ int64_t tri(int32_t Mt, int32_t I, int32_t J) {
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// 16 x 16 x 4 matrix-core products.  Operand layout (lane l of the wave):
+// A (16 x 4) element (l % 16, l / 16), B (4 x 16) element (l / 16, l % 16).
+// Result element v of lane l: FP64 (l / 16 + 4 v, l % 16), FP32
+// (4 (l / 16) + v, l % 16).  In the FP64 layout, element v of a 16 x 16
+// result is exactly the B operand of rows 4 v .. 4 v + 3 of that result.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma4(float a, float b, flt4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// (row, col) inside a 16 x 16 MFMA result of lane l, element v
+__device__ __forceinline__ void frag_rc(double, int l, int v, int& r, int& c) { r = l / 16 + 4 * v; c = l % 16; }
+__device__ __forceinline__ void frag_rc(float, int l, int v, int& r, int& c) { r = 4 * (l / 16) + v; c = l % 16; }
 
 // Dynamic LDS above the default 64 KB needs an explicit opt-in per kernel;
 // gfx950 has 160 KB per workgroup (static + dynamic).
@@ -566,6 +584,264 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const T* __restrict__ tiles, 
     }
 }
 
+// ------------------------------------------------------------ wave-level solves
+// One wave per (front, 16 right-hand-side columns); the waves of a
+// workgroup take consecutive column chunks of one front and never
+// synchronise.  The front's pivot rows of the block stay in registers as
+// 16 x 16 FP64 MFMA results (tile t, element v of lane l = row
+// 16 t + l / 16 + 4 v, column l % 16), which are at the same time the B
+// operands of the next product.  Factor fragments are loaded straight from
+// the column-major tiles (an FP32 factor is widened to FP64).  Work is done
+// per 16-row tile and per 4 columns of the contraction, so the 32 x 32
+// padding of small fronts costs nothing beyond those granules.
+namespace {
+constexpr int WCOLS = 16;   // right-hand-side columns per wave
+__device__ __forceinline__ double ldw(const double* p) { return *p; }
+__device__ __forceinline__ double ldw(const float* p) { return (double)*p; }
+}  // namespace
+
+// forward sweep over one tree level: y = L11^-1 (b_J + children's updates),
+// u_J = (children's updates of the struct rows) - L21 y
+// widest workgroup (waves) of the wave-level solves for NT pivot row tiles
+template <int NT>
+struct WsolveWaves {
+    static constexpr int value = NT >= 16 ? 4 : 8;
+};
+
+template <class TF, int NT>
+__global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(const TF* __restrict__ tiles, const TF* __restrict__ linv,
+                                                    const DFront* __restrict__ fr, int32_t f0, double* X, int64_t ldx,
+                                                    int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu,
+                                                    const int64_t* __restrict__ gptr, const int64_t* __restrict__ gidx,
+                                                    const double* __restrict__ mdiag) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
+    if (cbase >= col0 + ncols) return;
+    const int32_t c = cbase + (lane & 15);
+    const bool cok = c < col0 + ncols;
+    const DFront f = fr[f0 + blockIdx.x];
+    const int nt = (f.ns + 15) >> 4;
+    dbl4 y[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * t + lr + 4 * v;
+            double val = 0.0;
+            if (r < f.ns && cok) {
+                val = X[(f.start + r) * ldx + c];
+                if (mdiag) val *= mdiag[f.start + r];
+                const int64_t g1 = gptr[f.gather_base + r + 1];
+                for (int64_t g = gptr[f.gather_base + r]; g < g1; ++g) val += (double)ubuf[gidx[g] * ldu + c];
+            }
+            y[t][v] = val;
+        }
+#pragma unroll
+    for (int kb = 0; kb < NT / 2; ++kb) {
+        if (2 * kb < nt) {
+            const int kmax = min(32, f.ns - 32 * kb);
+            const bool two = 2 * kb + 1 < nt;
+            // y_kb <- Linv_kb y_kb
+            const TF* Li = linv + f.linv_base + (int64_t)kb * TT + (lane & 15);
+            dbl4 n0 = {0, 0, 0, 0}, n1 = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks)
+                if (4 * ks < kmax) {
+                    const double b = y[2 * kb + ks / 4][ks % 4];
+                    const TF* pa = Li + (4 * ks + lr) * T32;
+                    n0 = mfma4(ldw(pa), b, n0);
+                    if (two) n1 = mfma4(ldw(pa + 16), b, n1);
+                }
+            y[2 * kb] = n0;
+            if (two) y[2 * kb + 1] = n1;
+            // y_ib -= L_ib,kb y_kb
+#pragma unroll
+            for (int ib = kb + 1; ib < NT / 2; ++ib)
+                if (2 * ib < nt) {
+                    const bool two_i = 2 * ib + 1 < nt;
+                    const TF* Lt = tiles + f.tile_base + tri(f.Mt, ib, kb) * TT + (lane & 15);
+#pragma unroll
+                    for (int ks = 0; ks < 8; ++ks)
+                        if (4 * ks < kmax) {
+                            const double b = y[2 * kb + ks / 4][ks % 4];
+                            const TF* pa = Lt + (4 * ks + lr) * T32;
+                            y[2 * ib] = mfma4(-ldw(pa), b, y[2 * ib]);
+                            if (two_i) y[2 * ib + 1] = mfma4(-ldw(pa + 16), b, y[2 * ib + 1]);
+                        }
+                }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * t + lr + 4 * v;
+            if (r < f.ns && cok) X[(f.start + r) * ldx + c] = y[t][v];
+        }
+    // update rows, 16 at a time
+    const int mt = (f.mu + 15) >> 4;
+    for (int rt = 0; rt < mt; ++rt) {
+        const int st = rt >> 1, half = rt & 1;
+        dbl4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kb = 0; kb < NT / 2; ++kb)
+            if (2 * kb < nt) {
+                const int kmax = min(32, f.ns - 32 * kb);
+                const TF* Lt = tiles + f.tile_base + tri(f.Mt, f.nsb + st, kb) * TT + 16 * half + (lane & 15);
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks)
+                    if (4 * ks < kmax) acc = mfma4(ldw(Lt + (4 * ks + lr) * T32), y[2 * kb + ks / 4][ks % 4], acc);
+            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int sr = 16 * rt + lr + 4 * v;
+            if (sr < f.mu && cok) {
+                const int64_t gr = f.gather_base + f.ns + sr;
+                const int64_t g1 = gptr[gr + 1];
+                double u = 0.0;
+                for (int64_t g = gptr[gr]; g < g1; ++g) u += (double)ubuf[gidx[g] * ldu + c];
+                ubuf[(f.ubuf_row + sr) * ldu + c] = (TF)(u - acc[v]);
+            }
+        }
+    }
+}
+
+// backward sweep over one tree level: z = D^-1 y - L21^T x_struct, then
+// x_J = L11^-T z (last pivot block first)
+template <class TF, int NT>
+__global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_bwd(const TF* __restrict__ tiles, const TF* __restrict__ linv,
+                                                    const TF* __restrict__ D, const DFront* __restrict__ fr,
+                                                    int32_t f0, double* X, int64_t ldx, int32_t col0, int32_t ncols,
+                                                    int32_t wpg, const int32_t* __restrict__ rows, int apply_dinv) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
+    if (cbase >= col0 + ncols) return;
+    const int32_t c = cbase + (lane & 15);
+    const bool cok = c < col0 + ncols;
+    const DFront f = fr[f0 + blockIdx.x];
+    const int nt = (f.ns + 15) >> 4;
+    dbl4 z[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * t + lr + 4 * v;
+            double val = 0.0;
+            if (r < f.ns && cok) {
+                val = X[(f.start + r) * ldx + c];
+                if (apply_dinv) val /= (double)D[f.d_base + r];
+            }
+            z[t][v] = val;
+        }
+    // z -= L21^T x_struct, 16 struct rows at a time
+    const int32_t* frows = rows + f.rows_off;
+    const int mt = (f.mu + 15) >> 4;
+    for (int rt = 0; rt < mt; ++rt) {
+        const int st = rt >> 1, half = rt & 1;
+        double xs[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int sr = 16 * rt + 4 * ks + lr;
+            xs[ks] = (sr < f.mu && cok) ? X[(int64_t)frows[sr] * ldx + c] : 0.0;
+        }
+#pragma unroll
+        for (int jb = 0; jb < NT / 2; ++jb)
+            if (2 * jb < nt) {
+                const bool two = 2 * jb + 1 < nt;
+                // A(i, k) = L(k, i): element (struct row k, pivot i) of tile (nsb + st, jb)
+                const TF* Lt = tiles + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT + (lane & 15) * T32 + 16 * half + lr;
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    z[2 * jb] = mfma4(-ldw(Lt + 4 * ks), xs[ks], z[2 * jb]);
+                    if (two) z[2 * jb + 1] = mfma4(-ldw(Lt + 16 * T32 + 4 * ks), xs[ks], z[2 * jb + 1]);
+                }
+            }
+    }
+#pragma unroll
+    for (int kb = NT / 2 - 1; kb >= 0; --kb) {
+        if (2 * kb < nt) {
+            const int kmax = min(32, f.ns - 32 * kb);
+            const bool two = 2 * kb + 1 < nt;
+            // x_kb = Linv_kb^T z_kb
+            const TF* Li = linv + f.linv_base + (int64_t)kb * TT + (lane & 15) * T32 + lr;
+            dbl4 n0 = {0, 0, 0, 0}, n1 = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks)
+                if (4 * ks < kmax) {
+                    const double b = z[2 * kb + ks / 4][ks % 4];
+                    n0 = mfma4(ldw(Li + 4 * ks), b, n0);
+                    if (two) n1 = mfma4(ldw(Li + 16 * T32 + 4 * ks), b, n1);
+                }
+            z[2 * kb] = n0;
+            if (two) z[2 * kb + 1] = n1;
+            // z_ib -= L_kb,ib^T x_kb
+#pragma unroll
+            for (int ib = 0; ib < kb; ++ib) {
+                const TF* Lt = tiles + f.tile_base + tri(f.Mt, kb, ib) * TT + (lane & 15) * T32 + lr;
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks)
+                    if (4 * ks < kmax) {
+                        const double b = z[2 * kb + ks / 4][ks % 4];
+                        z[2 * ib] = mfma4(-ldw(Lt + 4 * ks), b, z[2 * ib]);
+                        z[2 * ib + 1] = mfma4(-ldw(Lt + 16 * T32 + 4 * ks), b, z[2 * ib + 1]);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * t + lr + 4 * v;
+            if (r < f.ns && cok) X[(f.start + r) * ldx + c] = z[t][v];
+        }
+}
+
+// largest pivot count of a front the wave-level solves take
+int32_t wsolve_max_ns() { return 256; }
+
+namespace {
+inline void wsolve_shape(int32_t ncols, int32_t max_waves, int32_t& wpg, int32_t& groups) {
+    const int32_t nck = (int32_t)cdiv(ncols, WCOLS);
+    groups = (int32_t)cdiv(nck, max_waves);
+    wpg = (int32_t)cdiv(nck, groups);
+}
+}  // namespace
+
+template <class TF>
+hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
+                         int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
+                         double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx, const double* mdiag,
+                         const int32_t* rows, bool apply_dinv, hipStream_t s) {
+    if (f1 <= f0 || ncols <= 0) return hipSuccess;
+    if (ns_pad_max > wsolve_max_ns()) return hipErrorInvalidValue;
+    int32_t wpg, groups;
+    TF* ub = reinterpret_cast<TF*>(ubuf);
+#define HSIM_WS(NT)                                                                                              \
+    wsolve_shape(ncols, WsolveWaves<NT>::value, wpg, groups);                                                     \
+    const dim3 grid((unsigned)(f1 - f0), (unsigned)groups), block((unsigned)(64 * wpg));                          \
+    if (fwd)                                                                                                      \
+        k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, X, ldx, col0, ncols, wpg, ub, ldu,  \
+                                                    gptr, gidx, mdiag);                                           \
+    else                                                                                                          \
+        k_wsolve_bwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, D, fronts, f0, X, ldx, col0, ncols, wpg, rows,  \
+                                                    apply_dinv ? 1 : 0);
+    if (ns_pad_max <= 32) { HSIM_WS(2) }
+    else if (ns_pad_max <= 64) { HSIM_WS(4) }
+    else if (ns_pad_max <= 128) { HSIM_WS(8) }
+    else { HSIM_WS(16) }
+#undef HSIM_WS
+    return hipGetLastError();
+}
+template hipError_t launch_wsolve<double>(bool, const double*, const double*, const double*, const DFront*, int32_t,
+                                          int32_t, int32_t, double*, int64_t, int32_t, int32_t, double*, int64_t,
+                                          const int64_t*, const int64_t*, const double*, const int32_t*, bool,
+                                          hipStream_t);
+template hipError_t launch_wsolve<float>(bool, const float*, const float*, const float*, const DFront*, int32_t,
+                                         int32_t, int32_t, double*, int64_t, int32_t, int32_t, double*, int64_t,
+                                         const int64_t*, const int64_t*, const double*, const int32_t*, bool,
+                                         hipStream_t);
+
 namespace {
 template <class T>
 size_t fwd_lds(int32_t ns_pad, int qc) { return ((size_t)T32 * TS + (size_t)ns_pad * qc) * sizeof(T); }
@@ -968,243 +1244,367 @@ template hipError_t launch_big_solve<float>(int, const float*, const float*, con
                                             const int32_t*, hipStream_t);
 
 // ============================================================ Gram products
-// Sbar = Psi^T (S Psi), Mbar = Psi^T (M Psi) over 64 x 64 output tile pairs
-// (a <= b) and chunks of GRAM_CHUNK rows; each thread holds a 4 x 4 block of
-// both products.  TA = double: FP64 throughout.  TA = float: operands rounded
-// to FP32, FP32 products and accumulation over runs of 256 rows, FP64 sum of
-// the runs and of the chunks.
+// Sbar = Psi^T (S Psi), Mbar = Psi^T (M Psi) on the matrix cores.  The q x q
+// upper triangle is covered by 64 x 64 block pairs (a <= b); a workgroup takes
+// one block pair and GRAM_CHUNK rows, its four waves one 32 x 32 quarter each
+// (2 x 2 tiles of the 16 x 16 x 4 MFMA, both products).  Rows are staged
+// through LDS 32 at a time, the next 32 prefetched into registers.
+// TA = double: FP64 MFMA.  TA = float: operands rounded to FP32, FP32 MFMA
+// accumulation over runs of 256 rows, FP64 sum of the runs and the chunks.
+// Block ids are spread so that the block pairs of one row chunk run on one
+// XCD (dispatch is round-robin over the 8 XCDs) and share its L2.
 namespace {
-constexpr int GT = 64;            // output tile edge
-constexpr int GRAM_CHUNK = 2048;  // rows per workgroup
+constexpr int GT = 64;            // output block edge
+constexpr int GRAM_CHUNK = 4096;  // rows per workgroup
+constexpr int GROWS = 32;         // rows per LDS stage
+constexpr int GLD = GT + 8;       // LDS row stride (elements)
+constexpr int NXCD = 8;
+
+
+// workgroup id -> (chunk, pair) with the pairs of a chunk on one XCD
+__device__ __forceinline__ bool xcd_item(int64_t total, int64_t& item) {
+    const int64_t g8 = (total + NXCD - 1) / NXCD * NXCD;
+    const int64_t b = blockIdx.x;
+    item = (b % NXCD) * (g8 / NXCD) + b / NXCD;
+    return item < total;
+}
 }  // namespace
 
-int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) {
+int64_t colsum_tmp_doubles(int64_t nrows, int32_t ncols);
+hipError_t launch_colsum(const double* in, int64_t nrows, int32_t ncols, double* tmp, double* out, hipStream_t s);
+
+static int64_t gram_pairs(int32_t q) {
     const int64_t nt = cdiv(q, GT);
-    return cdiv(n, GRAM_CHUNK) * (nt * (nt + 1) / 2) * 2 * GT * GT;
+    return nt * (nt + 1) / 2;
+}
+
+// per-chunk partial blocks, their sum and the reduction's scratch
+int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) {
+    const int64_t nch = cdiv(n, GRAM_CHUNK);
+    const int64_t per = gram_pairs(q) * 2 * GT * GT;
+    return nch * per + per + colsum_tmp_doubles(nch, (int32_t)per);
 }
 
 template <class TA>
-__global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ Psi, const double* __restrict__ SPsi,
-                                                      const double* __restrict__ MPsi, const double* __restrict__ mdiag,
-                                                      int64_t n, int32_t q, int64_t ld, double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Psi, const double* __restrict__ SPsi,
+                                                   const double* __restrict__ MPsi, const double* __restrict__ mdiag,
+                                                   int64_t n, int32_t q, int64_t ld, int64_t nchunks,
+                                                   double* __restrict__ partial) {
+    using V4 = typename std::conditional<std::is_same<TA, double>::value, dbl4, flt4>::type;
     const int32_t nt = (q + GT - 1) / GT;
-    int32_t pair = blockIdx.y, a = 0;
+    const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
+    int64_t item;
+    if (!xcd_item(nchunks * npairs, item)) return;
+    const int64_t chunk = item / npairs;
+    int32_t pair = (int32_t)(item % npairs), a = 0;
     while (pair >= nt - a) { pair -= nt - a; ++a; }
     const int32_t b = a + pair;
-    const int64_t r0 = (int64_t)blockIdx.x * GRAM_CHUNK;
+    const int64_t r0 = chunk * GRAM_CHUNK;
     const int64_t r1 = min(n, r0 + GRAM_CHUNK);
-    __shared__ TA P[T32][GT + 1], Q[T32][GT + 1], R[T32][GT + 1];
-    const int tid = threadIdx.x;
-    const int ra = tid % 16, cb = tid / 16;   // output rows ra + 16 i, cols cb + 16 j
-    double accS[4][4] = {}, accM[4][4] = {};
-    TA runS[4][4] = {}, runM[4][4] = {};
-    int steps = 0;
-    for (int64_t row0 = r0; row0 < r1; row0 += T32) {
-        for (int idx = tid; idx < T32 * GT; idx += 256) {
-            const int i = idx / GT, c = idx % GT;
+
+    __shared__ TA P[GROWS][GLD], Q[GROWS][GLD], R[GROWS][GLD];
+    const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+    const int wi = w / 2, wj = w % 2;              // quarter of the 64 x 64 block pair
+    const bool active = !(a == b && wi > wj);      // strictly lower quarter of a diagonal block
+    bool tile_on[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            tile_on[t][u] = active && a * GT + wi * 32 + t * 16 < q && b * GT + wj * 32 + u * 16 < q;
+
+    dbl4 accS[2][2], accM[2][2];
+    V4 runS[2][2], runM[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            accS[t][u] = accM[t][u] = dbl4{0, 0, 0, 0};
+            runS[t][u] = runM[t][u] = V4{0, 0, 0, 0};
+        }
+
+    // staging: thread -> 8 elements of each array (rows tid / 8 + 32 j / 8 ...)
+    constexpr int PER = GROWS * GT / 256;   // 8
+    double pv[PER], qv[PER], rv[PER];
+    auto fetch = [&](int64_t row0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + 256 * e, i = idx / GT, c = idx % GT;
             const int64_t row = row0 + i;
-            const int ca = a * GT + c, cbb = b * GT + c;
+            const int ca = a * GT + c, cb = b * GT + c;
             const bool ok = row < r1;
-            P[i][c] = (TA)((ok && ca < q) ? Psi[row * ld + ca] : 0.0);
-            Q[i][c] = (TA)((ok && cbb < q) ? SPsi[row * ld + cbb] : 0.0);
-            R[i][c] = (TA)((ok && cbb < q) ? (mdiag ? mdiag[row] * Psi[row * ld + cbb] : MPsi[row * ld + cbb]) : 0.0);
+            pv[e] = (ok && ca < q) ? Psi[row * ld + ca] : 0.0;
+            qv[e] = (ok && cb < q) ? SPsi[row * ld + cb] : 0.0;
+            rv[e] = (ok && cb < q) ? (mdiag ? mdiag[row] * Psi[row * ld + cb] : MPsi[row * ld + cb]) : 0.0;
+        }
+    };
+    fetch(r0);
+    int steps = 0;
+    for (int64_t row0 = r0; row0 < r1; row0 += GROWS) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + 256 * e, i = idx / GT, c = idx % GT;
+            P[i][c] = (TA)pv[e];
+            Q[i][c] = (TA)qv[e];
+            R[i][c] = (TA)rv[e];
         }
         __syncthreads();
-#pragma unroll 4
-        for (int k = 0; k < T32; ++k) {
-            TA av[4], sv[4], mv[4];
+        if (row0 + GROWS < r1) fetch(row0 + GROWS);
+        if (active) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = P[k][ra + 16 * i];
+            for (int kk = 0; kk < GROWS; kk += 4) {
+                const int kr = kk + lane / 16;
+                TA av[2], sv[2], mv[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                sv[j] = Q[k][cb + 16 * j];
-                mv[j] = R[k][cb + 16 * j];
+                for (int t = 0; t < 2; ++t) av[t] = P[kr][wi * 32 + t * 16 + lane % 16];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    sv[u] = Q[kr][wj * 32 + u * 16 + lane % 16];
+                    mv[u] = R[kr][wj * 32 + u * 16 + lane % 16];
+                }
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        if (tile_on[t][u]) {
+                            runS[t][u] = mfma4(av[t], sv[u], runS[t][u]);
+                            runM[t][u] = mfma4(av[t], mv[u], runM[t][u]);
+                        }
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    runS[i][j] += av[i] * sv[j];
-                    runM[i][j] += av[i] * mv[j];
-                }
         }
         __syncthreads();
-        if (++steps == 8) {   // 256 rows
+        if (!std::is_same<TA, double>::value && ++steps == 8) {   // FP32: fold a run of 256 rows into FP64
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    accS[i][j] += (double)runS[i][j];
-                    accM[i][j] += (double)runM[i][j];
-                    runS[i][j] = runM[i][j] = 0;
-                }
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        accS[t][u][v] += (double)runS[t][u][v];
+                        accM[t][u][v] += (double)runM[t][u][v];
+                        runS[t][u][v] = runM[t][u][v] = 0;
+                    }
             steps = 0;
         }
     }
-    const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
-    double* out = partial + ((int64_t)blockIdx.x * npairs + blockIdx.y) * 2 * GT * GT;
+    if (!active) return;
+    double* out = partial + (chunk * npairs + (item % npairs)) * 2 * GT * GT;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = ra + 16 * i, c = cb + 16 * j;
-            out[r * GT + c] = accS[i][j] + (double)runS[i][j];
-            out[GT * GT + r * GT + c] = accM[i][j] + (double)runM[i][j];
+        for (int u = 0; u < 2; ++u) {
+            if (!tile_on[t][u]) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int rr, cc;
+                frag_rc(TA(0), lane, v, rr, cc);
+                const int r = wi * 32 + t * 16 + rr, c = wj * 32 + u * 16 + cc;
+                out[r * GT + c] = accS[t][u][v] + (double)runS[t][u][v];
+                out[GT * GT + r * GT + c] = accM[t][u][v] + (double)runM[t][u][v];
+            }
         }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ partial, int64_t nchunks, int32_t q, double* Sbar,
-                              double* Mbar) {
+// Sbar, Mbar (q x q, symmetric) from the summed upper blocks
+__global__ void k_gram_scatter(const double* __restrict__ sums, int32_t q, double* Sbar, double* Mbar) {
     const int32_t nt = (q + GT - 1) / GT;
-    const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
     const int64_t tot = (int64_t)q * q;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t i = (int32_t)(t / q), j = (int32_t)(t % q);
-        if (i > j) continue;
+        int32_t i = (int32_t)(t / q), j = (int32_t)(t % q);
+        if (i > j) { const int32_t x = i; i = j; j = x; }
         const int32_t a = i / GT, b = j / GT;
         const int64_t pair = (int64_t)a * nt - (int64_t)a * (a - 1) / 2 + (b - a);
-        const int off = (i % GT) * GT + (j % GT);
-        double s = 0, m = 0;
-        for (int64_t ch = 0; ch < nchunks; ++ch) {
-            const double* p = partial + (ch * npairs + pair) * 2 * GT * GT;
-            s += p[off];
-            m += p[GT * GT + off];
-        }
-        Sbar[(int64_t)i * q + j] = s;
-        Sbar[(int64_t)j * q + i] = s;
-        Mbar[(int64_t)i * q + j] = m;
-        Mbar[(int64_t)j * q + i] = m;
+        const int64_t off = pair * 2 * GT * GT + (i % GT) * GT + (j % GT);
+        Sbar[t] = sums[off];
+        Mbar[t] = sums[off + GT * GT];
     }
 }
 
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
                        int32_t q, int64_t ld, double* partial, int64_t /*chunk_rows*/, double* Sbar, double* Mbar,
                        hipStream_t s, bool fp32) {
-    const int64_t nt = cdiv(q, GT);
+    const int64_t npairs = gram_pairs(q);
     const int64_t nch = cdiv(n, GRAM_CHUNK);
-    const dim3 grid((unsigned)nch, (unsigned)(nt * (nt + 1) / 2));
+    const int64_t per = npairs * 2 * GT * GT;
+    const unsigned grid = (unsigned)(cdiv(nch * npairs, NXCD) * NXCD);
     if (fp32)
-        k_gram_partial<float><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, partial);
+        k_gram_mfma<float><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, partial);
     else
-        k_gram_partial<double><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, partial);
+        k_gram_mfma<double><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_gram_reduce<<<grid_for((int64_t)q * q, 256), 256, 0, s>>>(partial, nch, q, Sbar, Mbar);
+    double* sums = partial + nch * per;
+    e = launch_colsum(partial, nch, (int32_t)per, sums + per, sums, s);
+    if (e != hipSuccess) return e;
+    k_gram_scatter<<<grid_for((int64_t)q * q, 256), 256, 0, s>>>(sums, q, Sbar, Mbar);
     return hipGetLastError();
 }
 
 // ============================================================ Ritz update + residual
-// Phi = Psi Phibar, (S Phi) = (S Psi) Phibar (kept in registers), M Phi = m * Phi
-// (level 0) or (M Psi) Phibar; per-column partial sums of the residual
-// numerator and of the normalisation.  Workgroup: RITZ_ROWS rows x 32
-// columns; thread: 2 rows x 4 columns of every product.
+// Phi = Psi Phibar, S Phi = (S Psi) Phibar (registers only), M Phi = m * Phi
+// on the finest level or (M Psi) Phibar, on the FP64 matrix cores; per-column
+// partial sums of the residual numerator and of the normalisation.
+// Workgroup: RITZ_ROWS rows (in blocks of 32) x 160 columns; wave w takes rows
+// 16 (w / 2) .. +16 and column tiles 5 (w % 2) .. +5 of each 32-row block.
+// Psi, S Psi, M Psi are staged through LDS 32 columns of the contraction at a
+// time; the Phibar fragments come straight from L2.
 namespace {
-constexpr int RITZ_ROWS = 64;
-}
-int64_t ritz_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) { return cdiv(n, RITZ_ROWS) * 2 * (int64_t)q; }
+constexpr int RITZ_ROWS = 256;    // rows per workgroup
+constexpr int RB = 32;            // rows per block
+constexpr int RCOLS = 160;        // output columns per workgroup
+constexpr int RK = 32;            // contraction columns per LDS stage
+constexpr int RLD = RK + 4;       // LDS row stride
+}  // namespace
 
-__global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ Psi, const double* __restrict__ SPsi,
-                                              const double* __restrict__ MPsi, const double* __restrict__ mdiag,
-                                              const double* __restrict__ Phibar, const double* __restrict__ lam,
-                                              int64_t n, int32_t q, int64_t ld, double* __restrict__ Phi,
-                                              double* __restrict__ MPhi, double* __restrict__ partial, int minv_norm) {
-    __shared__ double Ps[RITZ_ROWS][T32 + 1], Ss[RITZ_ROWS][T32 + 1], Ms[RITZ_ROWS][T32 + 1];
-    __shared__ double Bs[T32][T32 + 1];
-    // the column reduction reuses the Psi staging area (2 x 32 x 33 doubles)
-    auto red = reinterpret_cast<double(*)[32][T32 + 1]>(&Ps[0][0]);
-    const int tid = threadIdx.x;
-    const int rl = tid % 32, cl = tid / 32;   // rows rl + 32 i (i < 2), cols cl + 8 j (j < 4)
-    const int64_t row0 = (int64_t)blockIdx.x * RITZ_ROWS;
-    const int col0 = blockIdx.y * T32;
-    const bool has_m = mdiag == nullptr;
-    double ap[2][4] = {}, as[2][4] = {}, am[2][4] = {};
-    for (int k0 = 0; k0 < q; k0 += T32) {
-        for (int idx = tid; idx < RITZ_ROWS * T32; idx += 256) {
-            const int r = idx / T32, kk = idx % T32;
-            const int64_t row = row0 + r;
-            const bool ok = row < n && k0 + kk < q;
-            Ps[r][kk] = ok ? Psi[row * ld + k0 + kk] : 0.0;
-            Ss[r][kk] = ok ? SPsi[row * ld + k0 + kk] : 0.0;
-            if (has_m) Ms[r][kk] = ok ? MPsi[row * ld + k0 + kk] : 0.0;
-        }
-        for (int idx = tid; idx < T32 * T32; idx += 256) {
-            const int kk = idx / T32, c = idx % T32;
-            Bs[kk][c] = (k0 + kk < q && col0 + c < q) ? Phibar[(int64_t)(k0 + kk) * q + col0 + c] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < T32; ++kk) {
-            double b[4];
+int64_t ritz_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) {
+    const int64_t nch = cdiv(n, RITZ_ROWS);
+    return nch * 2 * (int64_t)q + 2 * (int64_t)q + colsum_tmp_doubles(nch, 2 * q);
+}
+
+template <bool HAS_M>
+__global__ __launch_bounds__(256) void k_ritz_mfma(const double* __restrict__ Psi, const double* __restrict__ SPsi,
+                                                   const double* __restrict__ MPsi, const double* __restrict__ mdiag,
+                                                   const double* __restrict__ Phibar, const double* __restrict__ lam,
+                                                   int64_t n, int32_t q, int64_t ld, double* __restrict__ Phi,
+                                                   double* __restrict__ MPhi, double* __restrict__ partial,
+                                                   int minv_norm) {
+    __shared__ double Ps[RB][RLD], Ss[RB][RLD], Ms[HAS_M ? RB : 1][RLD];
+    __shared__ double red[2][2][RCOLS];
+    const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+    const int wr = w / 2, wc = w % 2;
+    const int col0 = blockIdx.y * RCOLS;
+    double num[5] = {0, 0, 0, 0, 0}, den[5] = {0, 0, 0, 0, 0};
+    const int64_t wg_r0 = (int64_t)blockIdx.x * RITZ_ROWS;
+    const int64_t wg_r1 = min(n, wg_r0 + RITZ_ROWS);
+    for (int64_t r0 = wg_r0; r0 < wg_r1; r0 += RB) {
+        dbl4 aP[5], aS[5], aM[5];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][cl + 8 * j];
+        for (int u = 0; u < 5; ++u) aP[u] = aS[u] = aM[u] = dbl4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < q; k0 += RK) {
+            for (int idx = tid; idx < RB * RK; idx += 256) {
+                const int r = idx / RK, kk = idx % RK;
+                const int64_t row = r0 + r;
+                const bool ok = row < n && k0 + kk < q;
+                Ps[r][kk] = ok ? Psi[row * ld + k0 + kk] : 0.0;
+                Ss[r][kk] = ok ? SPsi[row * ld + k0 + kk] : 0.0;
+                if (HAS_M) Ms[r][kk] = ok ? MPsi[row * ld + k0 + kk] : 0.0;
+            }
+            __syncthreads();
+            const int r = wr * 16 + lane % 16;
+            for (int kk = 0; kk < RK; kk += 4) {
+                const int kr = k0 + kk + lane / 16;
+                double bv[5];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const double p = Ps[rl + 32 * i][kk], sv = Ss[rl + 32 * i][kk];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    ap[i][j] += p * b[j];
-                    as[i][j] += sv * b[j];
+                for (int u = 0; u < 5; ++u) {
+                    const int c = col0 + (wc * 5 + u) * 16 + lane % 16;
+                    bv[u] = (kr < q && c < q) ? Phibar[(int64_t)kr * q + c] : 0.0;
                 }
-                if (has_m) {
-                    const double mv = Ms[rl + 32 * i][kk];
+                const int kc = kk + lane / 16;
+                const double ap = Ps[r][kc], as = Ss[r][kc];
+                const double am = HAS_M ? Ms[r][kc] : 0.0;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) am[i][j] += mv * b[j];
+                for (int u = 0; u < 5; ++u) {
+                    aP[u] = mfma4(ap, bv[u], aP[u]);
+                    aS[u] = mfma4(as, bv[u], aS[u]);
+                    if (HAS_M) aM[u] = mfma4(am, bv[u], aM[u]);
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = r0 + wr * 16 + lane / 16 + 4 * v;
+            if (row >= n) continue;
+            const double mr = HAS_M ? 0.0 : mdiag[row];
+#pragma unroll
+            for (int u = 0; u < 5; ++u) {
+                const int col = col0 + (wc * 5 + u) * 16 + lane % 16;
+                if (col >= q) continue;
+                const double phi = aP[u][v], sphi = aS[u][v];
+                const double mphi = HAS_M ? aM[u][v] : mr * phi;
+                Phi[row * ld + col] = phi;
+                if (MPhi) MPhi[row * ld + col] = mphi;
+                const double res = sphi - lam[col] * mphi;
+                if (minv_norm) {
+                    num[u] += res * res / mr;
+                    den[u] += phi * mphi;
+                } else {
+                    num[u] += res * res;
+                    den[u] += mphi * mphi;
                 }
             }
         }
-        __syncthreads();
     }
-    double num[4] = {0, 0, 0, 0}, den[4] = {0, 0, 0, 0};
+    // lanes l, l + 16, l + 32, l + 48 hold the same columns
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int64_t row = row0 + rl + 32 * i;
-        if (row >= n) continue;
-        const double mr = has_m ? 0.0 : mdiag[row];
+    for (int u = 0; u < 5; ++u) {
+        num[u] += __shfl_xor(num[u], 16);
+        num[u] += __shfl_xor(num[u], 32);
+        den[u] += __shfl_xor(den[u], 16);
+        den[u] += __shfl_xor(den[u], 32);
+    }
+    if (lane < 16) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = col0 + cl + 8 * j;
-            if (col >= q) continue;
-            const double phi = ap[i][j], sphi = as[i][j];
-            const double mphi = has_m ? am[i][j] : mr * phi;
-            Phi[row * ld + col] = phi;
-            if (MPhi) MPhi[row * ld + col] = mphi;
-            const double res = sphi - lam[col] * mphi;
-            if (minv_norm) {
-                num[j] += res * res / mr;
-                den[j] += phi * mphi;
-            } else {
-                num[j] += res * res;
-                den[j] += mphi * mphi;
-            }
+        for (int u = 0; u < 5; ++u) {
+            red[wr][0][(wc * 5 + u) * 16 + lane] = num[u];
+            red[wr][1][(wc * 5 + u) * 16 + lane] = den[u];
         }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        red[0][rl][cl + 8 * j] = num[j];
-        red[1][rl][cl + 8 * j] = den[j];
     }
     __syncthreads();
-    if (tid < T32 && col0 + tid < q) {
-        double a = 0, b2 = 0;
-        for (int k = 0; k < 32; ++k) {
-            a += red[0][k][tid];
-            b2 += red[1][k][tid];
-        }
-        partial[(int64_t)blockIdx.x * 2 * q + col0 + tid] = a;
-        partial[(int64_t)blockIdx.x * 2 * q + q + col0 + tid] = b2;
+    if (tid < RCOLS && col0 + tid < q) {
+        partial[(int64_t)blockIdx.x * 2 * q + col0 + tid] = red[0][0][tid] + red[1][0][tid];
+        partial[(int64_t)blockIdx.x * 2 * q + q + col0 + tid] = red[0][1][tid] + red[1][1][tid];
     }
 }
 
-__global__ void k_resid_reduce(const double* __restrict__ partial, int64_t nchunks, int32_t q,
-                               const double* __restrict__ lam, double lam_floor, double* resid) {
+// out[blockIdx.y, c] = sum of rows [y * rpb, (y + 1) * rpb) of column c of
+// the row-major nrows x ncols array; 64 columns x 4 row lanes per workgroup
+__global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ in, int64_t nrows, int32_t ncols,
+                                                int64_t rpb, double* __restrict__ out) {
+    __shared__ double red[4][64];
+    const int cl = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cl;
+    const int64_t r0 = (int64_t)blockIdx.y * rpb, r1 = min(nrows, r0 + rpb);
+    double a0 = 0, a1 = 0;
+    if (c < ncols) {
+        int64_t r = r0 + g;
+        for (; r + 4 < r1; r += 8) {
+            a0 += in[r * ncols + c];
+            a1 += in[(r + 4) * ncols + c];
+        }
+        if (r < r1) a0 += in[r * ncols + c];
+    }
+    red[g][cl] = a0 + a1;
+    __syncthreads();
+    if (g == 0 && c < ncols) out[(int64_t)blockIdx.y * ncols + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+}
+
+// column sums of a tall row-major array into out[ncols]; tmp holds
+// colsum_tmp_doubles(nrows, ncols) doubles
+namespace {
+constexpr int64_t COLSUM_RPB = 128;
+}
+int64_t colsum_tmp_doubles(int64_t nrows, int32_t ncols) { return cdiv(nrows, COLSUM_RPB) * (int64_t)ncols; }
+
+hipError_t launch_colsum(const double* in, int64_t nrows, int32_t ncols, double* tmp, double* out, hipStream_t s) {
+    const unsigned gx = (unsigned)cdiv(ncols, 64);
+    if (nrows <= COLSUM_RPB * 8) {
+        k_colsum<<<dim3(gx, 1), 256, 0, s>>>(in, nrows, ncols, nrows, out);
+        return hipGetLastError();
+    }
+    const int64_t n1 = cdiv(nrows, COLSUM_RPB);
+    k_colsum<<<dim3(gx, (unsigned)n1), 256, 0, s>>>(in, nrows, ncols, COLSUM_RPB, tmp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_colsum<<<dim3(gx, 1), 256, 0, s>>>(tmp, n1, ncols, n1, out);
+    return hipGetLastError();
+}
+
+__global__ void k_resid_final(const double* __restrict__ sums, int32_t q, const double* __restrict__ lam,
+                              double lam_floor, double* resid) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= q) return;
-    double a = 0, b = 0;
-    for (int64_t ch = 0; ch < nchunks; ++ch) {
-        a += partial[ch * 2 * q + c];
-        b += partial[ch * 2 * q + q + c];
-    }
-    resid[c] = sqrt(a) / (fmax(fabs(lam[c]), lam_floor) * sqrt(b));
+    resid[c] = sqrt(sums[c]) / (fmax(fabs(lam[c]), lam_floor) * sqrt(sums[q + c]));
 }
 
 hipError_t launch_ritz(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag,
@@ -1212,12 +1612,19 @@ hipError_t launch_ritz(const double* Psi, const double* SPsi, const double* MPsi
                        double* MPhi, double* partial, int64_t /*chunk_rows*/, bool minv_norm, double lam_floor,
                        double* resid, hipStream_t s) {
     const int64_t nch = cdiv(n, RITZ_ROWS);
-    const int64_t nct = cdiv(q, T32);
-    k_ritz<<<dim3((unsigned)nch, (unsigned)nct), 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi, MPhi,
-                                                              partial, minv_norm ? 1 : 0);
+    const dim3 grid((unsigned)nch, (unsigned)cdiv(q, RCOLS));
+    if (mdiag)
+        k_ritz_mfma<false><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi, MPhi, partial,
+                                                minv_norm ? 1 : 0);
+    else
+        k_ritz_mfma<true><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi, MPhi, partial,
+                                               minv_norm ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_resid_reduce<<<(unsigned)cdiv(q, 256), 256, 0, s>>>(partial, nch, q, lam, lam_floor, resid);
+    double* sums = partial + nch * 2 * (int64_t)q;
+    e = launch_colsum(partial, nch, 2 * q, sums + 2 * (int64_t)q, sums, s);
+    if (e != hipSuccess) return e;
+    k_resid_final<<<(unsigned)cdiv(q, 256), 256, 0, s>>>(sums, q, lam, lam_floor, resid);
     return hipGetLastError();
 }
 
@@ -1367,30 +1774,36 @@ __global__ __launch_bounds__(256) void k_bj_local(const double* __restrict__ C, 
                 qq[k] = q;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int idx = threadIdx.x; idx < B * W; idx += 256) {
-                const int k = idx / W, c = idx % W;
-                if (sn[k] == 0.0) continue;
-                const double x = A[pp[k]][c], y = A[qq[k]][c];
-                A[pp[k]][c] = cs[k] * x - sn[k] * y;
-                A[qq[k]][c] = sn[k] * x + cs[k] * y;
+            // A <- J^T A J: the pairs of one round are disjoint, so every 2 x 2
+            // block {p1, q1} x {p2, q2} is read and written by one thread only
+            for (int blk = threadIdx.x; blk < B * B; blk += 256) {
+                const int k1 = blk / B, k2 = blk % B;
+                const double s1 = sn[k1], s2 = sn[k2];
+                if (s1 == 0.0 && s2 == 0.0) continue;
+                const double c1 = cs[k1], c2 = cs[k2];
+                const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+                const double x00 = A[p1][p2], x01 = A[p1][q2], x10 = A[q1][p2], x11 = A[q1][q2];
+                const double t00 = c1 * x00 - s1 * x10, t01 = c1 * x01 - s1 * x11;
+                const double t10 = s1 * x00 + c1 * x10, t11 = s1 * x01 + c1 * x11;
+                A[p1][p2] = c2 * t00 - s2 * t01;
+                A[q1][q2] = s2 * t10 + c2 * t11;
+                if (k1 == k2) {
+                    A[p1][q2] = 0.0;
+                    A[q1][p2] = 0.0;
+                } else {
+                    A[p1][q2] = s2 * t00 + c2 * t01;
+                    A[q1][p2] = c2 * t10 - s2 * t11;
+                }
             }
-            __syncthreads();
-            // columns: A <- A J, Q <- Q J
+            // Q <- Q J
             for (int idx = threadIdx.x; idx < B * W; idx += 256) {
                 const int k = idx % B, a = idx / B;
-                if (sn[k] == 0.0) continue;
-                const double x = A[a][pp[k]], y = A[a][qq[k]];
-                A[a][pp[k]] = x * cs[k] - y * sn[k];
-                A[a][qq[k]] = x * sn[k] + y * cs[k];
+                const double ss = sn[k];
+                if (ss == 0.0) continue;
+                const double cc = cs[k];
                 const double u = Q[a][pp[k]], v = Q[a][qq[k]];
-                Q[a][pp[k]] = u * cs[k] - v * sn[k];
-                Q[a][qq[k]] = u * sn[k] + v * cs[k];
-            }
-            __syncthreads();
-            if (threadIdx.x < B && sn[threadIdx.x] != 0.0) {
-                A[pp[threadIdx.x]][qq[threadIdx.x]] = 0.0;
-                A[qq[threadIdx.x]][pp[threadIdx.x]] = 0.0;
+                Q[a][pp[k]] = u * cc - v * ss;
+                Q[a][qq[k]] = u * ss + v * cc;
             }
             __syncthreads();
         }
