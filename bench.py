@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -47,31 +49,78 @@ def run_solves(H, precision, tol, steps, warmup):
     return dt, out
 
 
-def cpu_baseline(V, F, density, p, cols=15):
-    """The oracle as it stands, timed on the host cores on a bounded sample of
-    the finest level of the same workload: the SuperLU factorisation of
-    S - mu M, one SuperLU solve on `cols` of the q right-hand sides (scaled to
-    q), and one Rayleigh-Ritz step of the oracle on a q-column block."""
+def cpu_baseline(p, nus=(102, 144), cols=30):
+    """The oracle as it stands, timed on the host cores on a bounded sample:
+    the finest-level work of one subspace iteration (SuperLU factorisation of
+    S - mu M, the two block solves of an iteration with q right-hand sides,
+    one oracle Rayleigh-Ritz step) on two smaller meshes of the same recipe;
+    each component is extrapolated to the benchmark mesh with the power law
+    through the two sizes."""
     import numpy as np
     import scipy.sparse as sp
+    import synth
     from oracle import assembly, sim
-    cores = len(os.sched_getaffinity(0))
-    S, m = assembly.assemble(V, F, density=density)
     q = sim.subspace_size(p)
-    M = sp.diags(m).tocsr()
-    t0 = time.perf_counter()
-    solver = sim.ShiftedSolver(S, M, -1e-3)
-    t_factor = time.perf_counter() - t0
-    log(f"cpu baseline: SuperLU factorisation {t_factor:.1f} s")
-    rng = np.random.default_rng(0)
-    Phi = rng.standard_normal((S.shape[0], q))
-    t1 = time.perf_counter()
-    solver.solve(M @ Phi[:, :cols])
-    t_solve = (time.perf_counter() - t1) * q / cols
-    t2 = time.perf_counter()
-    sim.rayleigh_ritz(S, M, Phi)
-    t_rr = time.perf_counter() - t2
-    return dict(t_factor=t_factor, t_solve=t_solve, t_rr=t_rr, cores=cores, cols=cols, q=q)
+    res = []
+    for nu in nus:
+        V, F, dens = synth.config_mesh("sphere1m", seed=0, nu=nu)
+        S, m = assembly.assemble(V, F, density=dens)
+        M = sp.diags(m).tocsr()
+        t0 = time.perf_counter()
+        solver = sim.ShiftedSolver(S, M, -1e-3)
+        t_factor = time.perf_counter() - t0
+        Phi = np.random.default_rng(0).standard_normal((S.shape[0], q))
+        t1 = time.perf_counter()
+        solver.solve(M @ Phi[:, :cols])
+        t_solve = (time.perf_counter() - t1) * q / cols
+        t2 = time.perf_counter()
+        sim.rayleigh_ritz(S, M, Phi)
+        t_rr = time.perf_counter() - t2
+        res.append(dict(n=S.shape[0], factor=t_factor, solve=t_solve, rr=t_rr))
+        log(f"cpu baseline n={S.shape[0]}: factor {t_factor:.2f} s, q-column solve {t_solve:.2f} s, RR {t_rr:.2f} s")
+    return res
+
+
+def extrapolate(res, key, n):
+    (a, b) = res[0], res[1]
+    e = np.log(b[key] / a[key]) / np.log(b["n"] / a["n"])
+    return b[key] * (n / b["n"]) ** e, e
+
+
+def kernel_source_sha(name):
+    """sha256 of a kernel's definition in the HIP source (to tell whether
+    stored counter readings still describe it)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2111_09039_amd", "csrc", "kernels.hip")).read()
+    i = src.index(f"void {name}(")
+    a = src.rfind("\n\n", 0, i)
+    b = src.index("\n}\n", i)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def stored_traffic(cls, nu, p):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary (benchmark workload only), or None when the kernel has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_sphere1m_p100.json")
+    if nu != 324 or p != 100 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))["kernels"].get(cls)
+    if rec is None or kernel_source_sha(rec["kernel"]) != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain device copy of known size (256 MiB read + 256 MiB written),
+    the reference for the HBM byte counters."""
+    import torch
+    x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 copies of 268435456 bytes")
 
 
 def main():
@@ -84,7 +133,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--profile-only", action="store_true", help="one FP64 solve, no timing loop (for rocprofv3)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="one FP64 solve and a copy of known size, no timing loop (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -106,6 +156,7 @@ def main():
     info0 = H.level_info(0)
 
     if args.profile_only:
+        copy_calibration()
         H.solve(tol=args.tol, precision=hs.FP64)
         torch.cuda.synchronize()
         log("profile-only solve done")
@@ -128,29 +179,46 @@ def main():
             log(f"mixed precision unavailable: {e}")
             results["mixed"] = dict(error=str(e))
 
-    # dominant kernel class by device time
-    dom = max((k for k in kern if kern[k]["bytes"] > 0), key=lambda k: kern[k]["ms"])
+    # roofline of the costliest single kernel: the Ritz update and the Gram
+    # products are one matrix-core kernel each (plus a reduction of a few
+    # microseconds), the SpMM one HBM-bound kernel
+    single = {"ritz": ("mfma", "TFLOP/s"), "gram": ("mfma", "TFLOP/s"), "spmm": ("hbm", "GB/s")}
+    dom = max((k for k in single if kern[k]["launches"] > 0), key=lambda k: kern[k]["ms"])
     kd = kern[dom]
+    bound, unit = single[dom]
     avg_ms = kd["ms"] / max(1, kd["launches"])
-    achieved = (kd["bytes"] / max(1, kd["launches"])) / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+    if bound == "mfma":
+        achieved = kd["flops"] / max(1, kd["launches"]) / (avg_ms * 1e-3) / 1e12
+        peak = FP64_PEAK_TFLOPS
+    else:
+        achieved = kd["bytes"] / max(1, kd["launches"]) / (avg_ms * 1e-3) / 1e9
+        peak = HBM_PEAK_GBS
+    traffic = stored_traffic(dom, args.nu, args.p)
+    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4),
+                "traffic": None if traffic is None else round(traffic), "traffic_unit": "bytes per launch",
+                "kernel": dom,
                 "avg_launch_ms": round(avg_ms, 4), "launches": kd["launches"],
-                "flops_tflops": round(kd["flops"] / (kd["ms"] * 1e-3) / 1e12, 3)}
+                "algorithmic_bytes_per_launch": kd["bytes"] / max(1, kd["launches"]),
+                "algorithmic_flops_per_launch": kd["flops"] / max(1, kd["launches"])}
 
     cpu = None
     if not args.no_cpu:
         t = time.perf_counter()
-        cb = cpu_baseline(V, F, dens, args.p)
+        res = cpu_baseline(args.p)
+        n = len(V)
         it0 = st64["iters"][-1]
-        est = cb["t_factor"] + it0 * (2 * cb["t_solve"] + cb["t_rr"])
-        cpu = {"value": round(est, 3), "unit": "s", "cores": cb["cores"], "kind": "oracle",
-               "sample": (f"finest level of the same 1M mesh: oracle SuperLU factorisation of S - mu M "
-                          f"({cb['t_factor']:.1f} s, single-threaded), one SuperLU solve on {cb['cols']} of the "
-                          f"{cb['q']} right-hand sides scaled to {cb['q']} ({cb['t_solve']:.1f} s), one oracle "
-                          f"Rayleigh-Ritz step on a {cb['q']}-column block ({cb['t_rr']:.1f} s); value = factor + "
-                          f"{it0} finest-level iterations x (2 solves + 1 Rayleigh-Ritz); hierarchy and coarse "
-                          f"level not included")}
+        fac, ef = extrapolate(res, "factor", n)
+        sol, es = extrapolate(res, "solve", n)
+        rr, er = extrapolate(res, "rr", n)
+        est = fac + it0 * (2 * sol + rr)
+        cpu = {"value": round(float(est), 3), "unit": "s", "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+               "sample": (f"finest-level work of the oracle (SuperLU factorisation of S - mu M, q={H.q}-column solve, "
+                          f"Rayleigh-Ritz step) timed on meshes of the same recipe with "
+                          f"{res[0]['n']} and {res[1]['n']} vertices, each extrapolated to {n} vertices by the power "
+                          f"law through the two (exponents factor {ef:.2f}, solve {es:.2f}, RR {er:.2f}); value = "
+                          f"factor + {it0} finest-level iterations x (2 solves + 1 RR); coarse levels and hierarchy "
+                          f"not included; SuperLU single-threaded")}
         log(f"cpu baseline sample took {time.perf_counter() - t:.1f} s")
 
     line = {

@@ -294,6 +294,7 @@ struct Level {
     // device, internal (elimination) order
     DeviceBuffer dS_ptr, dS_idx, dS_val, dM_val, dmdiag, dU_ptr, dU_idx, dU_val, dperm;
     DeviceBuffer dfronts, tiles, linv, D, tiles32, linv32, D32, counters;
+    DeviceBuffer tilesT, linvT, tiles32T, linv32T;   // tile-transposed copies for the backward sweeps
     DeviceBuffer asm_dst, asm_src, it_diag, it_panel, it_upd, it_ea, rel, rows, gptr, gidx;
     DeviceBuffer ubuf, big_items;
     double mu = 0;
@@ -410,7 +411,8 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
         d.Mt = f.Mt;
         d.nsb = f.nsb;
         d.parent = f.parent;
-        d.pad_ = 0;
+        const int64_t gb = f.gather_base, m = (int64_t)f.ns + f.mu;
+        d.flags = sy.gather_ptr[gb + m] > sy.gather_ptr[gb] ? DFRONT_GATHER : 0;
     }
     L.dfronts.upload(df);
     L.tiles.alloc((size_t)sy.tile_doubles * sizeof(double));
@@ -448,8 +450,6 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
             T.pivots += f.ns;
         }
         T.big = T.ns_pad_max > wsolve_max_ns() || T.ns_pad_max >= env_int("HSIM_BIG_NS", BIG_NS);
-        if (!T.big && !solve_chunk_width(T.ns_pad_max, 1, false))
-            fail(HSIM_E_UNIMPLEMENTED, "supernode of %d pivots exceeds the solve kernels' LDS", T.ns_pad_max);
         if (T.big) {
             // item lists of the multi-workgroup block solve
             auto push = [&](int32_t a, int32_t b) { big.push_back(a); big.push_back(b); };
@@ -550,6 +550,13 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
     L.factored = hc[1] == 0;
     L.factored32 = false;
     if (hc[1] != 0) fail(HSIM_E_FACTOR, "LDL^T of S - mu M (level %d, mu=%g): %d zero or non-finite pivots", L.tau, mu, hc[1]);
+    L.tilesT.alloc((size_t)sy.tile_doubles * sizeof(double));
+    L.linvT.alloc((size_t)std::max<int64_t>(1, sy.linv_doubles) * sizeof(double));
+    P.run(HSIM_K_FACTOR, 16.0 * (sy.tile_doubles + sy.linv_doubles), 0.0, s, [&] {
+        HIPCHECK(launch_tile_transpose<double>(tiles, dptr<double>(L.tilesT), sy.tile_doubles / (NB * NB), s));
+        HIPCHECK(launch_tile_transpose<double>(dptr<double>(L.linv), dptr<double>(L.linvT), sy.linv_doubles / (NB * NB),
+                                               s));
+    });
     if (mixed) {
         // FP32 copy of the FP64 factor for the low-precision solves
         L.tiles32.alloc((size_t)sy.tile_doubles * sizeof(float));
@@ -559,6 +566,12 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
             HIPCHECK(launch_to_float(dptr<double>(L.tiles), dptr<float>(L.tiles32), sy.tile_doubles, s));
             HIPCHECK(launch_to_float(dptr<double>(L.linv), dptr<float>(L.linv32), sy.linv_doubles, s));
             HIPCHECK(launch_to_float(dptr<double>(L.D), dptr<float>(L.D32), sy.d_doubles, s));
+            L.tiles32T.alloc((size_t)sy.tile_doubles * sizeof(float));
+            L.linv32T.alloc((size_t)std::max<int64_t>(1, sy.linv_doubles) * sizeof(float));
+            HIPCHECK(launch_tile_transpose<float>(dptr<float>(L.tiles32), dptr<float>(L.tiles32T),
+                                                  sy.tile_doubles / (NB * NB), s));
+            HIPCHECK(launch_tile_transpose<float>(dptr<float>(L.linv32), dptr<float>(L.linv32T),
+                                                  sy.linv_doubles / (NB * NB), s));
         });
         L.factored32 = true;
     }
@@ -567,8 +580,8 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
 // X (internal order, leading dim ld) <- (S - mu M)^-1 (mdiag ? m*X : X) on columns [col0, col0 + ncols);
 // fp32: with the FP32 copy of the factor (FP32 arithmetic, FP64 in and out)
 template <class TF>
-static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF* linv, const TF* D, double* X,
-                         int32_t col0, int32_t ncols, const double* md, hipStream_t s) {
+static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
+                         const TF* linvT, double* X, int32_t col0, int32_t ncols, const double* md, hipStream_t s) {
     const Symbolic& sy = L.sy;
     const DFront* fr = dptr<DFront>(L.dfronts);
     Prof& P = H->prof;
@@ -614,7 +627,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
             continue;
         }
         P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
-            HIPCHECK(launch_wsolve<TF>(false, tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols,
+            HIPCHECK(launch_wsolve<TF>(false, tilesT, linvT, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols,
                                        nullptr, H->ld, nullptr, nullptr, nullptr, dptr<int32_t>(L.rows), true, s));
         });
     }
@@ -625,11 +638,11 @@ static void solve_level(hsim_hierarchy* H, Level& L, double* X, int32_t col0, in
     const double* md = scale_by_m ? dptr<double>(L.dmdiag) : nullptr;
     if (fp32) {
         if (!L.factored32) fail(HSIM_E_STATE, "no FP32 factor on level %d", L.tau);
-        solve_sweeps<float>(H, L, dptr<float>(L.tiles32), dptr<float>(L.linv32), dptr<float>(L.D32), X, col0, ncols, md,
-                            s);
+        solve_sweeps<float>(H, L, dptr<float>(L.tiles32), dptr<float>(L.linv32), dptr<float>(L.D32),
+                            dptr<float>(L.tiles32T), dptr<float>(L.linv32T), X, col0, ncols, md, s);
     } else {
-        solve_sweeps<double>(H, L, dptr<double>(L.tiles), dptr<double>(L.linv), dptr<double>(L.D), X, col0, ncols, md,
-                             s);
+        solve_sweeps<double>(H, L, dptr<double>(L.tiles), dptr<double>(L.linv), dptr<double>(L.D),
+                             dptr<double>(L.tilesT), dptr<double>(L.linvT), X, col0, ncols, md, s);
     }
 }
 

@@ -9,9 +9,11 @@
 namespace hsim {
 
 // Device copy of a front's geometry (see Front in internal.h).
+// DFront::flags bit: some row of the front gathers children's update rows
+constexpr int32_t DFRONT_GATHER = 1;
 struct DFront {
     int64_t start, tile_base, linv_base, d_base, ubuf_row, gather_base, rows_off;
-    int32_t ns, mu, ns_pad, mu_pad, Mt, nsb, parent, pad_;
+    int32_t ns, mu, ns_pad, mu_pad, Mt, nsb, parent, flags;   // flags: DFRONT_GATHER
 };
 
 // ------------------------------------------------------------ utilities
@@ -71,8 +73,12 @@ hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const 
 // counts up to wsolve_max_ns()): one wave per (front, 16 columns), the
 // front's block of the right-hand side in registers.  fwd: forward sweep
 // (mdiag optional pre-scaling, children's updates gathered from ubuf, own
-// updates written to ubuf); !fwd: backward sweep (apply_dinv divides by D).
+// updates written to ubuf); !fwd: backward sweep (apply_dinv divides by D),
+// with tiles and linv the tile-transposed copies (launch_tile_transpose).
 int32_t wsolve_max_ns();
+// every 32 x 32 tile of in[0 .. 1024 ntiles) transposed into the same place of out
+template <class T>
+hipError_t launch_tile_transpose(const T* in, T* out, int64_t ntiles, hipStream_t s);
 template <class TF>
 hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
                          int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,

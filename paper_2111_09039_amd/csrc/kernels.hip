@@ -595,167 +595,298 @@ __global__ __launch_bounds__(256) void k_solve_bwd(const T* __restrict__ tiles, 
 // per 16-row tile and per 4 columns of the contraction, so the 32 x 32
 // padding of small fronts costs nothing beyond those granules.
 namespace {
-constexpr int WCOLS = 16;   // right-hand-side columns per wave
+constexpr int WCOLS = 16;   // right-hand-side columns per MFMA column tile
 __device__ __forceinline__ double ldw(const double* p) { return *p; }
 __device__ __forceinline__ double ldw(const float* p) { return (double)*p; }
 }  // namespace
 
-// forward sweep over one tree level: y = L11^-1 (b_J + children's updates),
-// u_J = (children's updates of the struct rows) - L21 y
+// 16 x 32 block of a 32 x 32 column-major factor tile as A fragments of the
+// eight k-steps: rows 16 it .. +16 of the tile (trans = false) or of its
+// transpose (trans = true).  All eight loads are issued together; every
+// address lies inside the tile.
+template <class TF>
+__device__ __forceinline__ void frag_rows(const TF* __restrict__ tile, int it, bool trans, double (&a)[8]) {
+    const int lane = threadIdx.x & 63;
+    const TF* p = trans ? tile + (16 * it + (lane & 15)) * T32 + (lane >> 4)
+                        : tile + (lane >> 4) * T32 + 16 * it + (lane & 15);
+    const int step = trans ? 4 : 4 * T32;
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) a[ks] = ldw(p + ks * step);
+}
+
+// acc[c] (+)= +-A y_block[c] over the k-steps below kmax for the CT column
+// tiles c; y_block = row tiles 2 kb, 2 kb + 1
+template <int NT, int CT>
+__device__ __forceinline__ void frag_mm(const double (&a)[8], const dbl4 (&y)[CT][NT], int kb, int kmax,
+                                        dbl4 (&acc)[CT], bool neg) {
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+        if (4 * ks < kmax) {
+            const double av = neg ? -a[ks] : a[ks];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[c] = mfma4(av, y[c][2 * kb + ks / 4][ks % 4], acc[c]);
+        }
+}
+
 // widest workgroup (waves) of the wave-level solves for NT pivot row tiles
 template <int NT>
 struct WsolveWaves {
     static constexpr int value = NT >= 16 ? 4 : 8;
 };
+// 16-column tiles per wave (one: many independent waves hide latency better
+// than fewer, wider ones on these solves)
+template <int NT>
+struct WsolveCols {
+    static constexpr int value = 1;
+};
 
+// forward sweep over one tree level: y = L11^-1 (b_J + children's updates),
+// u_J = (children's updates of the struct rows) - L21 y.  A wave takes CT
+// column tiles of 16.
 template <class TF, int NT>
-__global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(const TF* __restrict__ tiles, const TF* __restrict__ linv,
-                                                    const DFront* __restrict__ fr, int32_t f0, double* X, int64_t ldx,
-                                                    int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu,
-                                                    const int64_t* __restrict__ gptr, const int64_t* __restrict__ gidx,
-                                                    const double* __restrict__ mdiag) {
+__global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
+    const TF* __restrict__ tiles, const TF* __restrict__ linv, const DFront* __restrict__ fr, int32_t f0, double* X,
+    int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu, const int64_t* __restrict__ gptr,
+    const int64_t* __restrict__ gidx, const double* __restrict__ mdiag) {
+    constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
-    if (cbase >= col0 + ncols) return;
-    const int32_t c = cbase + (lane & 15);
-    const bool cok = c < col0 + ncols;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS * CT;
+    const int32_t cend = col0 + ncols;
+    if (cbase >= cend) return;
     const DFront f = fr[f0 + blockIdx.x];
+    const bool gath = (f.flags & DFRONT_GATHER) != 0;
     const int nt = (f.ns + 15) >> 4;
-    dbl4 y[NT];
+    dbl4 y[CT][NT];
+    // right-hand side, mass scaling and (fronts with children only) the
+    // gathered updates; without gathers all loads are independent
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int cc = 0; cc < CT; ++cc) {
+        const int32_t c = cbase + 16 * cc + (lane & 15);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = 16 * t + lr + 4 * v;
-            double val = 0.0;
-            if (r < f.ns && cok) {
-                val = X[(f.start + r) * ldx + c];
-                if (mdiag) val *= mdiag[f.start + r];
-                const int64_t g1 = gptr[f.gather_base + r + 1];
-                for (int64_t g = gptr[f.gather_base + r]; g < g1; ++g) val += (double)ubuf[gidx[g] * ldu + c];
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * t + lr + 4 * v;
+                double val = 0.0;
+                if (r < f.ns && c < cend) {
+                    val = X[(f.start + r) * ldx + c];
+                    if (mdiag) val *= mdiag[f.start + r];
+                    if (gath) {
+                        const int64_t g1 = gptr[f.gather_base + r + 1];
+#pragma unroll 1
+                        for (int64_t g = gptr[f.gather_base + r]; g < g1; ++g) val += (double)ubuf[gidx[g] * ldu + c];
+                    }
+                }
+                y[cc][t][v] = val;
             }
-            y[t][v] = val;
-        }
+    }
 #pragma unroll
     for (int kb = 0; kb < NT / 2; ++kb) {
         if (2 * kb < nt) {
             const int kmax = min(32, f.ns - 32 * kb);
             const bool two = 2 * kb + 1 < nt;
             // y_kb <- Linv_kb y_kb
-            const TF* Li = linv + f.linv_base + (int64_t)kb * TT + (lane & 15);
-            dbl4 n0 = {0, 0, 0, 0}, n1 = {0, 0, 0, 0};
+            const TF* Li = linv + f.linv_base + (int64_t)kb * TT;
+            double a0[8], a1[8];
+            frag_rows(Li, 0, false, a0);
+            if (two) frag_rows(Li, 1, false, a1);
+            dbl4 n0[CT], n1[CT];
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks)
-                if (4 * ks < kmax) {
-                    const double b = y[2 * kb + ks / 4][ks % 4];
-                    const TF* pa = Li + (4 * ks + lr) * T32;
-                    n0 = mfma4(ldw(pa), b, n0);
-                    if (two) n1 = mfma4(ldw(pa + 16), b, n1);
-                }
-            y[2 * kb] = n0;
-            if (two) y[2 * kb + 1] = n1;
+            for (int cc = 0; cc < CT; ++cc) n0[cc] = n1[cc] = dbl4{0, 0, 0, 0};
+            frag_mm<NT, CT>(a0, y, kb, kmax, n0, false);
+            if (two) frag_mm<NT, CT>(a1, y, kb, kmax, n1, false);
+#pragma unroll
+            for (int cc = 0; cc < CT; ++cc) {
+                y[cc][2 * kb] = n0[cc];
+                if (two) y[cc][2 * kb + 1] = n1[cc];
+            }
             // y_ib -= L_ib,kb y_kb
 #pragma unroll
             for (int ib = kb + 1; ib < NT / 2; ++ib)
                 if (2 * ib < nt) {
+                    const TF* Lt = tiles + f.tile_base + tri(f.Mt, ib, kb) * TT;
                     const bool two_i = 2 * ib + 1 < nt;
-                    const TF* Lt = tiles + f.tile_base + tri(f.Mt, ib, kb) * TT + (lane & 15);
+                    frag_rows(Lt, 0, false, a0);
+                    if (two_i) frag_rows(Lt, 1, false, a1);
+                    dbl4 t0[CT], t1[CT];
 #pragma unroll
-                    for (int ks = 0; ks < 8; ++ks)
-                        if (4 * ks < kmax) {
-                            const double b = y[2 * kb + ks / 4][ks % 4];
-                            const TF* pa = Lt + (4 * ks + lr) * T32;
-                            y[2 * ib] = mfma4(-ldw(pa), b, y[2 * ib]);
-                            if (two_i) y[2 * ib + 1] = mfma4(-ldw(pa + 16), b, y[2 * ib + 1]);
-                        }
+                    for (int cc = 0; cc < CT; ++cc) {
+                        t0[cc] = y[cc][2 * ib];
+                        t1[cc] = y[cc][2 * ib + 1];
+                    }
+                    frag_mm<NT, CT>(a0, y, kb, kmax, t0, true);
+                    if (two_i) frag_mm<NT, CT>(a1, y, kb, kmax, t1, true);
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc) {
+                        y[cc][2 * ib] = t0[cc];
+                        y[cc][2 * ib + 1] = t1[cc];
+                    }
                 }
         }
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int cc = 0; cc < CT; ++cc) {
+        const int32_t c = cbase + 16 * cc + (lane & 15);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = 16 * t + lr + 4 * v;
-            if (r < f.ns && cok) X[(f.start + r) * ldx + c] = y[t][v];
-        }
-    // update rows, 16 at a time
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * t + lr + 4 * v;
+                if (r < f.ns && c < cend) X[(f.start + r) * ldx + c] = y[cc][t][v];
+            }
+    }
+    // update rows, 16 at a time; the fragments of the next (row tile, pivot
+    // block) pair are loaded while the current one is applied
     const int mt = (f.mu + 15) >> 4;
+    if (mt == 0) return;
+    const int nkb = (nt + 1) >> 1;
+    double a[8];
+    frag_rows(tiles + f.tile_base + tri(f.Mt, f.nsb, 0) * TT, 0, false, a);
+#pragma unroll 1
     for (int rt = 0; rt < mt; ++rt) {
         const int st = rt >> 1, half = rt & 1;
-        dbl4 acc = {0, 0, 0, 0};
+        int64_t g0[4], g1[4];
+        if (gath) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int sr = 16 * rt + lr + 4 * v;
+                const int64_t gr = f.gather_base + f.ns + min(sr, f.mu - 1);
+                g0[v] = gptr[gr];
+                g1[v] = sr < f.mu ? gptr[gr + 1] : g0[v];
+            }
+        }
+        dbl4 acc[CT];
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc) acc[cc] = dbl4{0, 0, 0, 0};
 #pragma unroll
         for (int kb = 0; kb < NT / 2; ++kb)
-            if (2 * kb < nt) {
-                const int kmax = min(32, f.ns - 32 * kb);
-                const TF* Lt = tiles + f.tile_base + tri(f.Mt, f.nsb + st, kb) * TT + 16 * half + (lane & 15);
+            if (kb < nkb) {
+                double an[8];
+                const bool last = kb + 1 == nkb;
+                if (!last || rt + 1 < mt) {
+                    const int rn = last ? rt + 1 : rt, kn = last ? 0 : kb + 1;
+                    frag_rows(tiles + f.tile_base + tri(f.Mt, f.nsb + (rn >> 1), kn) * TT, rn & 1, false, an);
+                }
+                frag_mm<NT, CT>(a, y, kb, min(32, f.ns - 32 * kb), acc, false);
 #pragma unroll
-                for (int ks = 0; ks < 8; ++ks)
-                    if (4 * ks < kmax) acc = mfma4(ldw(Lt + (4 * ks + lr) * T32), y[2 * kb + ks / 4][ks % 4], acc);
+                for (int ks = 0; ks < 8; ++ks) a[ks] = an[ks];
             }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int sr = 16 * rt + lr + 4 * v;
-            if (sr < f.mu && cok) {
-                const int64_t gr = f.gather_base + f.ns + sr;
-                const int64_t g1 = gptr[gr + 1];
-                double u = 0.0;
-                for (int64_t g = gptr[gr]; g < g1; ++g) u += (double)ubuf[gidx[g] * ldu + c];
-                ubuf[(f.ubuf_row + sr) * ldu + c] = (TF)(u - acc[v]);
+        for (int cc = 0; cc < CT; ++cc) {
+            const int32_t c = cbase + 16 * cc + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int sr = 16 * rt + lr + 4 * v;
+                if (sr < f.mu && c < cend) {
+                    double u = 0.0;
+                    if (gath) {
+#pragma unroll 1
+                        for (int64_t g = g0[v]; g < g1[v]; ++g) u += (double)ubuf[gidx[g] * ldu + c];
+                    }
+                    ubuf[(f.ubuf_row + sr) * ldu + c] = (TF)(u - acc[cc][v]);
+                }
             }
         }
     }
 }
 
 // backward sweep over one tree level: z = D^-1 y - L21^T x_struct, then
-// x_J = L11^-T z (last pivot block first)
+// x_J = L11^-T z (last pivot block first); tilesT, linvT are the factor
+// tiles transposed one by one, so that L^T fragments load like L fragments
 template <class TF, int NT>
-__global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_bwd(const TF* __restrict__ tiles, const TF* __restrict__ linv,
-                                                    const TF* __restrict__ D, const DFront* __restrict__ fr,
-                                                    int32_t f0, double* X, int64_t ldx, int32_t col0, int32_t ncols,
-                                                    int32_t wpg, const int32_t* __restrict__ rows, int apply_dinv) {
+__global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_bwd(
+    const TF* __restrict__ tilesT, const TF* __restrict__ linvT, const TF* __restrict__ D,
+    const DFront* __restrict__ fr, int32_t f0, double* X, int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg,
+    const int32_t* __restrict__ rows, int apply_dinv) {
+    constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
-    if (cbase >= col0 + ncols) return;
-    const int32_t c = cbase + (lane & 15);
-    const bool cok = c < col0 + ncols;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS * CT;
+    const int32_t cend = col0 + ncols;
+    if (cbase >= cend) return;
     const DFront f = fr[f0 + blockIdx.x];
     const int nt = (f.ns + 15) >> 4;
-    dbl4 z[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = 16 * t + lr + 4 * v;
-            double val = 0.0;
-            if (r < f.ns && cok) {
-                val = X[(f.start + r) * ldx + c];
-                if (apply_dinv) val /= (double)D[f.d_base + r];
-            }
-            z[t][v] = val;
-        }
-    // z -= L21^T x_struct, 16 struct rows at a time
     const int32_t* frows = rows + f.rows_off;
     const int mt = (f.mu + 15) >> 4;
+    // struct rows of the first 16-row tile, ahead of everything else
+    int32_t rix[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) rix[ks] = frows[min(4 * ks + lr, max(f.mu - 1, 0))];
+    dbl4 z[CT][NT];
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc) {
+        const int32_t c = cbase + 16 * cc + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * t + lr + 4 * v;
+                double val = 0.0;
+                if (r < f.ns && c < cend) {
+                    val = X[(f.start + r) * ldx + c];
+                    if (apply_dinv) val /= (double)D[f.d_base + r];
+                }
+                z[cc][t][v] = val;
+            }
+    }
+    // z -= L21^T x_struct, 16 struct rows at a time; the next tile's solution
+    // values and the row indices after it are loaded one step ahead
+    double xs[CT][4];
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc) {
+        const int32_t c = cbase + 16 * cc + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            xs[cc][ks] = (4 * ks + lr < f.mu && c < cend) ? X[(int64_t)rix[ks] * ldx + c] : 0.0;
+    }
+    if (mt > 1) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) rix[ks] = frows[min(16 + 4 * ks + lr, f.mu - 1)];
+    }
+#pragma unroll 1
     for (int rt = 0; rt < mt; ++rt) {
         const int st = rt >> 1, half = rt & 1;
-        double xs[4];
+        double xn[CT][4];
+        if (rt + 1 < mt) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int sr = 16 * rt + 4 * ks + lr;
-            xs[ks] = (sr < f.mu && cok) ? X[(int64_t)frows[sr] * ldx + c] : 0.0;
+            for (int cc = 0; cc < CT; ++cc) {
+                const int32_t c = cbase + 16 * cc + (lane & 15);
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int sr = 16 * (rt + 1) + 4 * ks + lr;
+                    xn[cc][ks] = (sr < f.mu && c < cend) ? X[(int64_t)rix[ks] * ldx + c] : 0.0;
+                }
+            }
+            if (rt + 2 < mt) {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) rix[ks] = frows[min(16 * (rt + 2) + 4 * ks + lr, f.mu - 1)];
+            }
         }
 #pragma unroll
         for (int jb = 0; jb < NT / 2; ++jb)
             if (2 * jb < nt) {
                 const bool two = 2 * jb + 1 < nt;
-                // A(i, k) = L(k, i): element (struct row k, pivot i) of tile (nsb + st, jb)
-                const TF* Lt = tiles + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT + (lane & 15) * T32 + 16 * half + lr;
+                // A(i, k) = L(k, i) = element (i, k) of the transposed tile (nsb + st, jb)
+                const TF* Lt = tilesT + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT + (16 * half + lr) * T32 + (lane & 15);
+                double a0[4], a1[4];
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
-                    z[2 * jb] = mfma4(-ldw(Lt + 4 * ks), xs[ks], z[2 * jb]);
-                    if (two) z[2 * jb + 1] = mfma4(-ldw(Lt + 16 * T32 + 4 * ks), xs[ks], z[2 * jb + 1]);
+                    a0[ks] = ldw(Lt + 4 * ks * T32);
+                    a1[ks] = two ? ldw(Lt + 4 * ks * T32 + 16) : 0.0;
                 }
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc) {
+                        z[cc][2 * jb] = mfma4(-a0[ks], xs[cc][ks], z[cc][2 * jb]);
+                        if (two) z[cc][2 * jb + 1] = mfma4(-a1[ks], xs[cc][ks], z[cc][2 * jb + 1]);
+                    }
             }
+        if (rt + 1 < mt) {
+#pragma unroll
+            for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) xs[cc][ks] = xn[cc][ks];
+        }
     }
 #pragma unroll
     for (int kb = NT / 2 - 1; kb >= 0; --kb) {
@@ -763,46 +894,83 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_bwd(cons
             const int kmax = min(32, f.ns - 32 * kb);
             const bool two = 2 * kb + 1 < nt;
             // x_kb = Linv_kb^T z_kb
-            const TF* Li = linv + f.linv_base + (int64_t)kb * TT + (lane & 15) * T32 + lr;
-            dbl4 n0 = {0, 0, 0, 0}, n1 = {0, 0, 0, 0};
+            const TF* Li = linvT + f.linv_base + (int64_t)kb * TT;
+            double a0[8], a1[8];
+            frag_rows(Li, 0, false, a0);
+            if (two) frag_rows(Li, 1, false, a1);
+            dbl4 n0[CT], n1[CT];
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks)
-                if (4 * ks < kmax) {
-                    const double b = z[2 * kb + ks / 4][ks % 4];
-                    n0 = mfma4(ldw(Li + 4 * ks), b, n0);
-                    if (two) n1 = mfma4(ldw(Li + 16 * T32 + 4 * ks), b, n1);
-                }
-            z[2 * kb] = n0;
-            if (two) z[2 * kb + 1] = n1;
+            for (int cc = 0; cc < CT; ++cc) n0[cc] = n1[cc] = dbl4{0, 0, 0, 0};
+            frag_mm<NT, CT>(a0, z, kb, kmax, n0, false);
+            if (two) frag_mm<NT, CT>(a1, z, kb, kmax, n1, false);
+#pragma unroll
+            for (int cc = 0; cc < CT; ++cc) {
+                z[cc][2 * kb] = n0[cc];
+                if (two) z[cc][2 * kb + 1] = n1[cc];
+            }
             // z_ib -= L_kb,ib^T x_kb
 #pragma unroll
             for (int ib = 0; ib < kb; ++ib) {
-                const TF* Lt = tiles + f.tile_base + tri(f.Mt, kb, ib) * TT + (lane & 15) * T32 + lr;
+                const TF* Lt = tilesT + f.tile_base + tri(f.Mt, kb, ib) * TT;
+                frag_rows(Lt, 0, false, a0);
+                frag_rows(Lt, 1, false, a1);
+                dbl4 t0[CT], t1[CT];
 #pragma unroll
-                for (int ks = 0; ks < 8; ++ks)
-                    if (4 * ks < kmax) {
-                        const double b = z[2 * kb + ks / 4][ks % 4];
-                        z[2 * ib] = mfma4(-ldw(Lt + 4 * ks), b, z[2 * ib]);
-                        z[2 * ib + 1] = mfma4(-ldw(Lt + 16 * T32 + 4 * ks), b, z[2 * ib + 1]);
-                    }
+                for (int cc = 0; cc < CT; ++cc) {
+                    t0[cc] = z[cc][2 * ib];
+                    t1[cc] = z[cc][2 * ib + 1];
+                }
+                frag_mm<NT, CT>(a0, z, kb, kmax, t0, true);
+                frag_mm<NT, CT>(a1, z, kb, kmax, t1, true);
+#pragma unroll
+                for (int cc = 0; cc < CT; ++cc) {
+                    z[cc][2 * ib] = t0[cc];
+                    z[cc][2 * ib + 1] = t1[cc];
+                }
             }
         }
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int cc = 0; cc < CT; ++cc) {
+        const int32_t c = cbase + 16 * cc + (lane & 15);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = 16 * t + lr + 4 * v;
-            if (r < f.ns && cok) X[(f.start + r) * ldx + c] = z[t][v];
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * t + lr + 4 * v;
+                if (r < f.ns && c < cend) X[(f.start + r) * ldx + c] = z[cc][t][v];
+            }
+    }
 }
+
+// every 32 x 32 tile of `in` transposed into the same place of `out`
+template <class T>
+__global__ __launch_bounds__(256) void k_tile_transpose(const T* __restrict__ in, T* __restrict__ out, int64_t ntiles) {
+    __shared__ T sm[T32][T32 + 1];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const T* a = in + t * TT;
+        T* b = out + t * TT;
+        for (int idx = threadIdx.x; idx < TT; idx += 256) sm[idx / T32][idx % T32] = a[idx];   // sm[col][row]
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < TT; idx += 256) b[idx] = sm[idx % T32][idx / T32];
+        __syncthreads();
+    }
+}
+template <class T>
+hipError_t launch_tile_transpose(const T* in, T* out, int64_t ntiles, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    k_tile_transpose<T><<<(unsigned)std::min<int64_t>(ntiles, 16384), 256, 0, s>>>(in, out, ntiles);
+    return hipGetLastError();
+}
+template hipError_t launch_tile_transpose<double>(const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_tile_transpose<float>(const float*, float*, int64_t, hipStream_t);
 
 // largest pivot count of a front the wave-level solves take
 int32_t wsolve_max_ns() { return 256; }
 
 namespace {
-inline void wsolve_shape(int32_t ncols, int32_t max_waves, int32_t& wpg, int32_t& groups) {
-    const int32_t nck = (int32_t)cdiv(ncols, WCOLS);
+inline void wsolve_shape(int32_t ncols, int32_t max_waves, int32_t cols_per_wave, int32_t& wpg, int32_t& groups) {
+    const int32_t nck = (int32_t)cdiv(ncols, cols_per_wave);
     groups = (int32_t)cdiv(nck, max_waves);
     wpg = (int32_t)cdiv(nck, groups);
 }
@@ -818,7 +986,7 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
     int32_t wpg, groups;
     TF* ub = reinterpret_cast<TF*>(ubuf);
 #define HSIM_WS(NT)                                                                                              \
-    wsolve_shape(ncols, WsolveWaves<NT>::value, wpg, groups);                                                     \
+    wsolve_shape(ncols, WsolveWaves<NT>::value, WCOLS * WsolveCols<NT>::value, wpg, groups);                                                     \
     const dim3 grid((unsigned)(f1 - f0), (unsigned)groups), block((unsigned)(64 * wpg));                          \
     if (fwd)                                                                                                      \
         k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, X, ldx, col0, ncols, wpg, ub, ldu,  \
