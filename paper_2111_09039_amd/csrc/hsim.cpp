@@ -588,7 +588,8 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
     const double bL = sizeof(TF);
     const int32_t* bi = dptr<int32_t>(L.big_items);
     auto big = [&](int phase, const int64_t* rec, int32_t kb) {
-        HIPCHECK(launch_big_solve<TF>(phase, tiles, linv, D, fr, bi + rec[0], rec[1], kb, X, H->ld, col0, ncols,
+        HIPCHECK(launch_big_solve<TF>(phase, tiles, linv, D, tilesT, linvT, fr, bi + rec[0], rec[1], kb, X, H->ld,
+                                      col0, ncols,
                                       dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr), dptr<int64_t>(L.gidx), md,
                                       dptr<int32_t>(L.rows), s));
     };
@@ -783,13 +784,16 @@ static void rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam,
     HIPCHECK(hipStreamSynchronize(s));
     auto t2 = std::chrono::steady_clock::now();
     const double lf = lambda_floor(lam);
-    H->prof.run(HSIM_K_RITZ, 8.0 * nq * (fin ? 3.0 : 4.0) + 8.0 * (fin ? L.n : 0), 2.0 * nq * q * (fin ? 2.0 : 3.0), s,
+    // S Phi only for the p tested columns (whole 16-column tiles)
+    const double qres = std::min<double>(q, (double)((H->p + 15) / 16 * 16));
+    H->prof.run(HSIM_K_RITZ, 8.0 * nq * (fin ? 3.0 : 4.0) + 8.0 * (fin ? L.n : 0),
+                2.0 * nq * (q * (fin ? 1.0 : 2.0) + qres), s,
                 [&] {
                     HIPCHECK(launch_ritz(dptr<double>(H->Psi), dptr<double>(H->SPsi),
                                          fin ? nullptr : dptr<double>(H->MPsi), fin ? dptr<double>(L.dmdiag) : nullptr,
                                          dptr<double>(H->Phibar), dptr<double>(H->lam), L.n, q, H->ld,
                                          dptr<double>(H->Phi), nullptr, dptr<double>(H->ritz_part), 4096, fin, lf,
-                                         dptr<double>(H->resid), s));
+                                         dptr<double>(H->resid), s, H->p));
                 });
     res.resize(q);
     HIPCHECK(hipMemcpyAsync(res.data(), H->resid.p, q * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -90,13 +90,16 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
 // (items: front), 2 forward update below block kb (items: front, tile row),
 // 3 backward init with the struct rows (items: front, pivot tile), 4 backward
 // diagonal block kb (items: front), 5 backward update before block kb
-// (items: front, pivot tile).  Column chunks of 32.
+// (items: front, pivot tile).  Phase 0 in column chunks of 32; the others
+// on the matrix cores, one wave per (item, 16 columns); the backward phases
+// read the tile-transposed copies tilesT, linvT.
 constexpr int BIG_BLOCK_TILES = 4;
 template <class TF>
-hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts,
-                            const int32_t* items, int64_t nitems, int32_t kb, double* X, int64_t ldx, int32_t col0,
-                            int32_t ncols, double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx,
-                            const double* mdiag, const int32_t* rows, hipStream_t s);
+hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
+                            const TF* linvT, const DFront* fronts, const int32_t* items, int64_t nitems, int32_t kb,
+                            double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf, int64_t ldu,
+                            const int64_t* gptr, const int64_t* gidx, const double* mdiag, const int32_t* rows,
+                            hipStream_t s);
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 // partial Grams over row chunks (pairs of 32-column tiles, upper), then the sum
@@ -107,10 +110,11 @@ hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi
 int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows);
 
 // Phi = Psi Phibar and residual partial sums; then the residual
+// nres: residuals of the first nres columns only (the rest are set to NaN); -1 = all
 hipError_t launch_ritz(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag,
                        const double* Phibar, const double* lam, int64_t n, int32_t q, int64_t ld, double* Phi,
                        double* MPhi, double* partial, int64_t chunk_rows, bool minv_norm, double lam_floor,
-                       double* resid, hipStream_t s);
+                       double* resid, hipStream_t s, int32_t nres = -1);
 int64_t ritz_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows);
 
 // ------------------------------------------------------------ dense GEP helpers

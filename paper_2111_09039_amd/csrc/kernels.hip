@@ -11,6 +11,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -1147,268 +1148,335 @@ __global__ __launch_bounds__(256) void k_big_fwd_init(const DFront* __restrict__
     }
 }
 
+// The diagonal-block, update and backward phases run on the matrix cores in
+// the wave-level layout of the small-front solves: one wave per (item, 16
+// right-hand-side columns), the 128 rows of a pivot block as eight 16 x 16
+// FP64 MFMA results in registers, factor fragments straight from the tiles
+// (backward phases: from the tile-transposed copy).
+
+// rows r0 + 16 t .. of X (t < nt16, rows below rmax), column c, as MFMA results
+template <int NTL>
+__device__ __forceinline__ void load_rows(dbl4 (&y)[NTL], const double* X, int64_t ldx, int64_t base, int r0,
+                                          int rmax, int32_t c, bool cok) {
+    const int lr = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * t + lr + 4 * v;
+            y[t][v] = (r < rmax && cok) ? X[(base + r) * ldx + c] : 0.0;
+        }
+}
+template <int NTL>
+__device__ __forceinline__ void store_rows(const dbl4 (&y)[NTL], double* X, int64_t ldx, int64_t base, int r0, int rmax,
+                                           int32_t c, bool cok) {
+    const int lr = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * t + lr + 4 * v;
+            if (r < rmax && cok) X[(base + r) * ldx + c] = y[t][v];
+        }
+}
+
+namespace {
+constexpr int BNT = 2 * KBT;   // 16-row tiles of a pivot block
+}
+
 // forward diagonal block kb of every listed front: y_blk = L_blk^-1 y_blk (in X)
 template <class T>
-__global__ __launch_bounds__(256) void k_big_fwd_diag(const T* __restrict__ tiles, const T* __restrict__ linv,
+__global__ __launch_bounds__(512) void k_big_fwd_diag(const T* __restrict__ tiles, const T* __restrict__ linv,
                                                       const DFront* __restrict__ fr, const int32_t* __restrict__ items,
-                                                      int32_t nchunks, int32_t kb, double* X, int64_t ldx,
-                                                      int32_t col0, int32_t ncols) {
-    __shared__ T As[T32 * TS];
-    __shared__ T y[KBT * T32 * BQC];
-    const DFront f = fr[items[blockIdx.x / nchunks]];
-    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
-    const int32_t cw = min(BQC, col0 + ncols - c0);
-    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+                                                      int32_t wpg, int32_t kb, double* X, int64_t ldx, int32_t col0,
+                                                      int32_t ncols) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
+    if (cbase >= col0 + ncols) return;
+    const int32_t c = cbase + (lane & 15);
+    const bool cok = c < col0 + ncols;
+    const DFront f = fr[items[blockIdx.x]];
     const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
-    const int rows = (t1 - t0) * T32;
-    for (int idx = threadIdx.x; idx < rows * BQC; idx += 256) {
-        const int r = idx / BQC, c = idx % BQC;
-        const int row = t0 * T32 + r;
-        y[idx] = (row < f.ns && c < cw) ? (T)X[(f.start + row) * ldx + c0 + c] : (T)0;
-    }
-    for (int k = t0; k < t1; ++k) {
-        T* yk = y + (k - t0) * T32 * BQC;
-        __syncthreads();
-        stage_tile(As, linv + f.linv_base + (int64_t)k * TT, false);
-        __syncthreads();
-        T acc[BM::RR][BM::CC] = {};
-        micro<T, BQC>(acc, As, yk);
-        __syncthreads();
+    const int rbase = t0 * T32, nrow = min(f.ns - rbase, (t1 - t0) * T32);   // real rows of the block
+    const int nt = (nrow + 15) >> 4;
+    dbl4 y[BNT];
+    load_rows<BNT>(y, X, ldx, f.start, rbase, rbase + nrow, c, cok);
+    // rows of y are relative to the block: local row r = global row - rbase
 #pragma unroll
-        for (int i = 0; i < BM::RR; ++i)
+    for (int lk = 0; lk < KBT; ++lk) {
+        if (2 * lk < nt) {
+            const int kmax = min(32, nrow - 32 * lk);
+            const bool two = 2 * lk + 1 < nt;
+            const T* Li = linv + f.linv_base + (int64_t)(t0 + lk) * TT;
+            double a0[8], a1[8];
+            frag_rows(Li, 0, false, a0);
+            if (two) frag_rows(Li, 1, false, a1);
+            dbl4 n0[1] = {{0, 0, 0, 0}}, n1[1] = {{0, 0, 0, 0}};
+            dbl4 yy[1][BNT];
 #pragma unroll
-            for (int j = 0; j < BM::CC; ++j) yk[(rl + BM::RL * i) * BQC + cl + BM::CL * j] = acc[i][j];
-        for (int ib = k + 1; ib < t1; ++ib) {
-            __syncthreads();
-            stage_tile(As, tiles + f.tile_base + tri(f.Mt, ib, k) * TT, false);
-            __syncthreads();
-            T a2[BM::RR][BM::CC] = {};
-            micro<T, BQC>(a2, As, yk);
-            T* yib = y + (ib - t0) * T32 * BQC;
+            for (int t = 0; t < BNT; ++t) yy[0][t] = y[t];
+            frag_mm<BNT, 1>(a0, yy, lk, kmax, n0, false);
+            if (two) frag_mm<BNT, 1>(a1, yy, lk, kmax, n1, false);
+            y[2 * lk] = n0[0];
+            if (two) y[2 * lk + 1] = n1[0];
 #pragma unroll
-            for (int i = 0; i < BM::RR; ++i)
+            for (int li = lk + 1; li < KBT; ++li)
+                if (2 * li < nt) {
+                    const T* Lt = tiles + f.tile_base + tri(f.Mt, t0 + li, t0 + lk) * TT;
+                    const bool two_i = 2 * li + 1 < nt;
+                    frag_rows(Lt, 0, false, a0);
+                    if (two_i) frag_rows(Lt, 1, false, a1);
 #pragma unroll
-                for (int j = 0; j < BM::CC; ++j) yib[(rl + BM::RL * i) * BQC + cl + BM::CL * j] -= a2[i][j];
+                    for (int t = 0; t < BNT; ++t) yy[0][t] = y[t];
+                    dbl4 t0v[1] = {y[2 * li]}, t1v[1] = {y[2 * li + 1]};
+                    frag_mm<BNT, 1>(a0, yy, lk, kmax, t0v, true);
+                    if (two_i) frag_mm<BNT, 1>(a1, yy, lk, kmax, t1v, true);
+                    y[2 * li] = t0v[0];
+                    y[2 * li + 1] = t1v[0];
+                }
         }
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < rows * BQC; idx += 256) {
-        const int r = idx / BQC, c = idx % BQC;
-        const int row = t0 * T32 + r;
-        if (row < f.ns && c < cw) X[(f.start + row) * ldx + c0 + c] = (double)y[idx];
-    }
+    store_rows<BNT>(y, X, ldx, f.start, rbase, rbase + nrow, c, cok);
 }
 
 // forward update of one 32-row tile ib below block kb: rows -= L(ib, blk) y_blk
 // (pivot tile: rows of X; struct tile: the front's update rows).  items: (front, ib)
 template <class T>
-__global__ __launch_bounds__(256) void k_big_fwd_update(const T* __restrict__ tiles, const DFront* __restrict__ fr,
-                                                        const int32_t* __restrict__ items, int32_t nchunks, int32_t kb,
+__global__ __launch_bounds__(512) void k_big_fwd_update(const T* __restrict__ tiles, const DFront* __restrict__ fr,
+                                                        const int32_t* __restrict__ items, int32_t wpg, int32_t kb,
                                                         double* X, int64_t ldx, int32_t col0, int32_t ncols, T* ubuf,
                                                         int64_t ldu) {
-    __shared__ T As[T32 * TS];
-    __shared__ T y[KBT * T32 * BQC];
-    const int item = blockIdx.x / nchunks;
-    const DFront f = fr[items[2 * item]];
-    const int ib = items[2 * item + 1];
-    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
-    const int32_t cw = min(BQC, col0 + ncols - c0);
-    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
+    if (cbase >= col0 + ncols) return;
+    const int32_t c = cbase + (lane & 15);
+    const bool cok = c < col0 + ncols;
+    const DFront f = fr[items[2 * blockIdx.x]];
+    const int ib = items[2 * blockIdx.x + 1];
     const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
-    const int rows = (t1 - t0) * T32;
-    for (int idx = threadIdx.x; idx < rows * BQC; idx += 256) {
-        const int r = idx / BQC, c = idx % BQC;
-        const int row = t0 * T32 + r;
-        y[idx] = (row < f.ns && c < cw) ? (T)X[(f.start + row) * ldx + c0 + c] : (T)0;
-    }
-    T acc[BM::RR][BM::CC] = {};
-    for (int k = t0; k < t1; ++k) {
-        __syncthreads();
-        stage_tile(As, tiles + f.tile_base + tri(f.Mt, ib, k) * TT, false);
-        __syncthreads();
-        micro<T, BQC>(acc, As, y + (k - t0) * T32 * BQC);
-    }
+    const int rbase = t0 * T32, nrow = min(f.ns - rbase, (t1 - t0) * T32);
+    // rows of the target tile that exist
+    const bool piv = ib < f.nsb;
+    const int tr0 = piv ? ib * T32 : (ib - f.nsb) * T32;
+    const int tlim = piv ? f.ns : f.mu;
+    const int trows = min(T32, tlim - tr0);
+    if (trows <= 0) return;
+    dbl4 yy[1][BNT];
+    load_rows<BNT>(yy[0], X, ldx, f.start, rbase, rbase + nrow, c, cok);
+    dbl4 acc0[1] = {{0, 0, 0, 0}}, acc1[1] = {{0, 0, 0, 0}};
+    const bool two = trows > 16;
 #pragma unroll
-    for (int i = 0; i < BM::RR; ++i) {
-        const int r = rl + BM::RL * i;
+    for (int lk = 0; lk < KBT; ++lk)
+        if (32 * lk < nrow) {
+            const T* Lt = tiles + f.tile_base + tri(f.Mt, ib, t0 + lk) * TT;
+            double a0[8], a1[8];
+            frag_rows(Lt, 0, false, a0);
+            if (two) frag_rows(Lt, 1, false, a1);
+            const int kmax = min(32, nrow - 32 * lk);
+            frag_mm<BNT, 1>(a0, yy, lk, kmax, acc0, false);
+            if (two) frag_mm<BNT, 1>(a1, yy, lk, kmax, acc1, false);
+        }
 #pragma unroll
-        for (int j = 0; j < BM::CC; ++j) {
-            const int c = cl + BM::CL * j;
-            if (c >= cw) continue;
-            if (ib < f.nsb) {
-                const int row = ib * T32 + r;
-                if (row < f.ns) X[(f.start + row) * ldx + c0 + c] -= (double)acc[i][j];
-            } else {
-                const int s = (ib - f.nsb) * T32 + r;
-                if (s < f.mu) {
-                    T* u = ubuf + (f.ubuf_row + s) * ldu + c0 + c;
-                    *u = (T)((double)*u - (double)acc[i][j]);
+    for (int it = 0; it < 2; ++it)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * it + lr + 4 * v;
+            if (r < trows && cok) {
+                const double a = it ? acc1[0][v] : acc0[0][v];
+                if (piv) {
+                    X[(f.start + tr0 + r) * ldx + c] -= a;
+                } else {
+                    T* u = ubuf + (f.ubuf_row + tr0 + r) * ldu + c;
+                    *u = (T)((double)*u - a);
                 }
             }
         }
-    }
 }
 
 // backward start: z_jb = D^-1 y_jb - sum over struct tiles L(st, jb)^T x_st, in X.  items: (front, jb)
 template <class T>
-__global__ __launch_bounds__(256) void k_big_bwd_init(const T* __restrict__ tiles, const T* __restrict__ D,
+__global__ __launch_bounds__(512) void k_big_bwd_init(const T* __restrict__ tilesT, const T* __restrict__ D,
                                                       const DFront* __restrict__ fr, const int32_t* __restrict__ items,
-                                                      int32_t nchunks, double* X, int64_t ldx, int32_t col0,
-                                                      int32_t ncols, const int32_t* __restrict__ rows) {
-    __shared__ T As[T32 * TS];
-    __shared__ T xs[T32 * BQC];
-    const int item = blockIdx.x / nchunks;
-    const DFront f = fr[items[2 * item]];
-    const int jb = items[2 * item + 1];
-    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
-    const int32_t cw = min(BQC, col0 + ncols - c0);
-    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+                                                      int32_t wpg, double* X, int64_t ldx, int32_t col0, int32_t ncols,
+                                                      const int32_t* __restrict__ rows) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
+    if (cbase >= col0 + ncols) return;
+    const int32_t c = cbase + (lane & 15);
+    const bool cok = c < col0 + ncols;
+    const DFront f = fr[items[2 * blockIdx.x]];
+    const int jb = items[2 * blockIdx.x + 1];
+    const int r0 = jb * T32, nrow = min(T32, f.ns - r0);
+    if (nrow <= 0) return;
+    const bool two = nrow > 16;
     const int32_t* frows = rows + f.rows_off;
     const int stiles = (f.mu + T32 - 1) / T32;
-    T acc[BM::RR][BM::CC] = {};
+    dbl4 z[2];
+    load_rows<2>(z, X, ldx, f.start, r0, r0 + nrow, c, cok);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * t + lr + 4 * v;
+            if (r < r0 + nrow) z[t][v] /= (double)D[f.d_base + r];
+        }
+    // x of the struct rows, eight k-steps of 4 rows per 32-row tile, one tile ahead
+    double xs[8], xn[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        const int sr = 4 * ks + lr;
+        xs[ks] = (sr < f.mu && cok) ? X[(int64_t)frows[sr] * ldx + c] : 0.0;
+    }
+#pragma unroll 1
     for (int st = 0; st < stiles; ++st) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < T32 * BQC; idx += 256) {
-            const int s = idx / BQC, c = idx % BQC;
-            const int sr = st * T32 + s;
-            xs[idx] = (sr < f.mu && c < cw) ? (T)X[(int64_t)frows[sr] * ldx + c0 + c] : (T)0;
-        }
-        stage_tile(As, tiles + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT, true);
-        __syncthreads();
-        micro<T, BQC>(acc, As, xs);
-    }
+        if (st + 1 < stiles) {
 #pragma unroll
-    for (int i = 0; i < BM::RR; ++i) {
-        const int row = jb * T32 + rl + BM::RL * i;
-        if (row >= f.ns) continue;
-#pragma unroll
-        for (int j = 0; j < BM::CC; ++j) {
-            const int c = cl + BM::CL * j;
-            if (c >= cw) continue;
-            double* xp = X + (f.start + row) * ldx + c0 + c;
-            *xp = *xp / (double)D[f.d_base + row] - (double)acc[i][j];
+            for (int ks = 0; ks < 8; ++ks) {
+                const int sr = (st + 1) * T32 + 4 * ks + lr;
+                xn[ks] = (sr < f.mu && cok) ? X[(int64_t)frows[sr] * ldx + c] : 0.0;
+            }
         }
+        // A(i, k) = L(k, i): element (i, k) of the transposed tile (nsb + st, jb)
+        const T* Lt = tilesT + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT;
+        double a0[8], a1[8];
+        frag_rows(Lt, 0, false, a0);
+        if (two) frag_rows(Lt, 1, false, a1);
+        const int kmax = min(32, f.mu - st * T32);
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+            if (4 * ks < kmax) {
+                z[0] = mfma4(-a0[ks], xs[ks], z[0]);
+                if (two) z[1] = mfma4(-a1[ks], xs[ks], z[1]);
+            }
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) xs[ks] = xn[ks];
     }
+    store_rows<2>(z, X, ldx, f.start, r0, r0 + nrow, c, cok);
 }
 
 // backward diagonal block kb: x_blk = L_blk^-T z_blk (in X)
 template <class T>
-__global__ __launch_bounds__(256) void k_big_bwd_diag(const T* __restrict__ tiles, const T* __restrict__ linv,
+__global__ __launch_bounds__(512) void k_big_bwd_diag(const T* __restrict__ tilesT, const T* __restrict__ linvT,
                                                       const DFront* __restrict__ fr, const int32_t* __restrict__ items,
-                                                      int32_t nchunks, int32_t kb, double* X, int64_t ldx,
-                                                      int32_t col0, int32_t ncols) {
-    __shared__ T As[T32 * TS];
-    __shared__ T z[KBT * T32 * BQC];
-    const DFront f = fr[items[blockIdx.x / nchunks]];
-    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
-    const int32_t cw = min(BQC, col0 + ncols - c0);
-    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+                                                      int32_t wpg, int32_t kb, double* X, int64_t ldx, int32_t col0,
+                                                      int32_t ncols) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
+    if (cbase >= col0 + ncols) return;
+    const int32_t c = cbase + (lane & 15);
+    const bool cok = c < col0 + ncols;
+    const DFront f = fr[items[blockIdx.x]];
     const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
-    const int nrows = (t1 - t0) * T32;
-    for (int idx = threadIdx.x; idx < nrows * BQC; idx += 256) {
-        const int r = idx / BQC, c = idx % BQC;
-        const int row = t0 * T32 + r;
-        z[idx] = (row < f.ns && c < cw) ? (T)X[(f.start + row) * ldx + c0 + c] : (T)0;
-    }
-    for (int k = t1 - 1; k >= t0; --k) {
-        T* zk = z + (k - t0) * T32 * BQC;
-        __syncthreads();
-        stage_tile(As, linv + f.linv_base + (int64_t)k * TT, true);
-        __syncthreads();
-        T acc[BM::RR][BM::CC] = {};
-        micro<T, BQC>(acc, As, zk);
-        __syncthreads();
+    const int rbase = t0 * T32, nrow = min(f.ns - rbase, (t1 - t0) * T32);
+    const int nt = (nrow + 15) >> 4;
+    dbl4 zz[1][BNT];
+    load_rows<BNT>(zz[0], X, ldx, f.start, rbase, rbase + nrow, c, cok);
 #pragma unroll
-        for (int i = 0; i < BM::RR; ++i)
+    for (int lk = KBT - 1; lk >= 0; --lk) {
+        if (2 * lk < nt) {
+            const int kmax = min(32, nrow - 32 * lk);
+            const bool two = 2 * lk + 1 < nt;
+            const T* Li = linvT + f.linv_base + (int64_t)(t0 + lk) * TT;
+            double a0[8], a1[8];
+            frag_rows(Li, 0, false, a0);
+            if (two) frag_rows(Li, 1, false, a1);
+            dbl4 n0[1] = {{0, 0, 0, 0}}, n1[1] = {{0, 0, 0, 0}};
+            frag_mm<BNT, 1>(a0, zz, lk, kmax, n0, false);
+            if (two) frag_mm<BNT, 1>(a1, zz, lk, kmax, n1, false);
+            zz[0][2 * lk] = n0[0];
+            if (two) zz[0][2 * lk + 1] = n1[0];
 #pragma unroll
-            for (int j = 0; j < BM::CC; ++j) zk[(rl + BM::RL * i) * BQC + cl + BM::CL * j] = acc[i][j];
-        for (int ib = t0; ib < k; ++ib) {
-            __syncthreads();
-            stage_tile(As, tiles + f.tile_base + tri(f.Mt, k, ib) * TT, true);
-            __syncthreads();
-            T a2[BM::RR][BM::CC] = {};
-            micro<T, BQC>(a2, As, zk);
-            T* zib = z + (ib - t0) * T32 * BQC;
-#pragma unroll
-            for (int i = 0; i < BM::RR; ++i)
-#pragma unroll
-                for (int j = 0; j < BM::CC; ++j) zib[(rl + BM::RL * i) * BQC + cl + BM::CL * j] -= a2[i][j];
+            for (int li = 0; li < lk; ++li) {
+                const T* Lt = tilesT + f.tile_base + tri(f.Mt, t0 + lk, t0 + li) * TT;
+                frag_rows(Lt, 0, false, a0);
+                frag_rows(Lt, 1, false, a1);
+                dbl4 t0v[1] = {zz[0][2 * li]}, t1v[1] = {zz[0][2 * li + 1]};
+                frag_mm<BNT, 1>(a0, zz, lk, kmax, t0v, true);
+                frag_mm<BNT, 1>(a1, zz, lk, kmax, t1v, true);
+                zz[0][2 * li] = t0v[0];
+                zz[0][2 * li + 1] = t1v[0];
+            }
         }
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nrows * BQC; idx += 256) {
-        const int r = idx / BQC, c = idx % BQC;
-        const int row = t0 * T32 + r;
-        if (row < f.ns && c < cw) X[(f.start + row) * ldx + c0 + c] = (double)z[idx];
-    }
+    store_rows<BNT>(zz[0], X, ldx, f.start, rbase, rbase + nrow, c, cok);
 }
 
 // backward update of pivot tile jb (before block kb): z_jb -= sum_{k in blk} L(k, jb)^T x_k.  items: (front, jb)
 template <class T>
-__global__ __launch_bounds__(256) void k_big_bwd_update(const T* __restrict__ tiles, const DFront* __restrict__ fr,
-                                                        const int32_t* __restrict__ items, int32_t nchunks, int32_t kb,
+__global__ __launch_bounds__(512) void k_big_bwd_update(const T* __restrict__ tilesT, const DFront* __restrict__ fr,
+                                                        const int32_t* __restrict__ items, int32_t wpg, int32_t kb,
                                                         double* X, int64_t ldx, int32_t col0, int32_t ncols) {
-    __shared__ T As[T32 * TS];
-    __shared__ T xb[KBT * T32 * BQC];
-    const int item = blockIdx.x / nchunks;
-    const DFront f = fr[items[2 * item]];
-    const int jb = items[2 * item + 1];
-    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
-    const int32_t cw = min(BQC, col0 + ncols - c0);
-    const int rl = threadIdx.x % BM::RL, cl = threadIdx.x / BM::RL;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
+    if (cbase >= col0 + ncols) return;
+    const int32_t c = cbase + (lane & 15);
+    const bool cok = c < col0 + ncols;
+    const DFront f = fr[items[2 * blockIdx.x]];
+    const int jb = items[2 * blockIdx.x + 1];
     const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
-    const int nrows = (t1 - t0) * T32;
-    for (int idx = threadIdx.x; idx < nrows * BQC; idx += 256) {
-        const int r = idx / BQC, c = idx % BQC;
-        const int row = t0 * T32 + r;
-        xb[idx] = (row < f.ns && c < cw) ? (T)X[(f.start + row) * ldx + c0 + c] : (T)0;
-    }
-    T acc[BM::RR][BM::CC] = {};
-    for (int k = t0; k < t1; ++k) {
-        __syncthreads();
-        stage_tile(As, tiles + f.tile_base + tri(f.Mt, k, jb) * TT, true);
-        __syncthreads();
-        micro<T, BQC>(acc, As, xb + (k - t0) * T32 * BQC);
+    const int rbase = t0 * T32, nrow = min(f.ns - rbase, (t1 - t0) * T32);
+    const int r0 = jb * T32, trows = min(T32, f.ns - r0);
+    if (trows <= 0) return;
+    const bool two = trows > 16;
+    dbl4 xx[1][BNT];
+    load_rows<BNT>(xx[0], X, ldx, f.start, rbase, rbase + nrow, c, cok);
+    dbl4 z0[1], z1[1];
+    {
+        dbl4 zt[2];
+        load_rows<2>(zt, X, ldx, f.start, r0, r0 + trows, c, cok);
+        z0[0] = zt[0];
+        z1[0] = zt[1];
     }
 #pragma unroll
-    for (int i = 0; i < BM::RR; ++i) {
-        const int row = jb * T32 + rl + BM::RL * i;
-        if (row >= f.ns) continue;
-#pragma unroll
-        for (int j = 0; j < BM::CC; ++j) {
-            const int c = cl + BM::CL * j;
-            if (c < cw) X[(f.start + row) * ldx + c0 + c] -= (double)acc[i][j];
+    for (int lk = 0; lk < KBT; ++lk)
+        if (32 * lk < nrow) {
+            // A(i, k) = L(k, i): tile (t0 + lk, jb) transposed
+            const T* Lt = tilesT + f.tile_base + tri(f.Mt, t0 + lk, jb) * TT;
+            double a0[8], a1[8];
+            frag_rows(Lt, 0, false, a0);
+            if (two) frag_rows(Lt, 1, false, a1);
+            const int kmax = min(32, nrow - 32 * lk);
+            frag_mm<BNT, 1>(a0, xx, lk, kmax, z0, true);
+            if (two) frag_mm<BNT, 1>(a1, xx, lk, kmax, z1, true);
         }
-    }
+    dbl4 zt[2] = {z0[0], z1[0]};
+    store_rows<2>(zt, X, ldx, f.start, r0, r0 + trows, c, cok);
 }
 
 template <class TF>
-hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts,
-                            const int32_t* items, int64_t nitems, int32_t kb, double* X, int64_t ldx, int32_t col0,
-                            int32_t ncols, double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx,
-                            const double* mdiag, const int32_t* rows, hipStream_t s) {
+hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
+                            const TF* linvT, const DFront* fronts, const int32_t* items, int64_t nitems, int32_t kb,
+                            double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf, int64_t ldu,
+                            const int64_t* gptr, const int64_t* gidx, const double* mdiag, const int32_t* rows,
+                            hipStream_t s) {
     if (nitems <= 0 || ncols <= 0) return hipSuccess;
-    const int32_t nch = (int32_t)cdiv(ncols, BQC);
-    const unsigned grid = (unsigned)(nitems * nch);
     TF* ub = reinterpret_cast<TF*>(ubuf);
+    if (phase == 0) {
+        const int32_t nch = (int32_t)cdiv(ncols, BQC);
+        k_big_fwd_init<TF><<<(unsigned)(nitems * nch), 256, 0, s>>>(fronts, items, nch, X, ldx, col0, ncols, ub, ldu,
+                                                                    gptr, gidx, mdiag);
+        return hipGetLastError();
+    }
+    int32_t wpg, groups;
+    wsolve_shape(ncols, 8, WCOLS, wpg, groups);
+    const dim3 grid((unsigned)nitems, (unsigned)groups), block((unsigned)(64 * wpg));
     switch (phase) {
-        case 0: k_big_fwd_init<TF><<<grid, 256, 0, s>>>(fronts, items, nch, X, ldx, col0, ncols, ub, ldu, gptr, gidx, mdiag); break;
-        case 1: k_big_fwd_diag<TF><<<grid, 256, 0, s>>>(tiles, linv, fronts, items, nch, kb, X, ldx, col0, ncols); break;
-        case 2: k_big_fwd_update<TF><<<grid, 256, 0, s>>>(tiles, fronts, items, nch, kb, X, ldx, col0, ncols, ub, ldu); break;
-        case 3: k_big_bwd_init<TF><<<grid, 256, 0, s>>>(tiles, D, fronts, items, nch, X, ldx, col0, ncols, rows); break;
-        case 4: k_big_bwd_diag<TF><<<grid, 256, 0, s>>>(tiles, linv, fronts, items, nch, kb, X, ldx, col0, ncols); break;
-        case 5: k_big_bwd_update<TF><<<grid, 256, 0, s>>>(tiles, fronts, items, nch, kb, X, ldx, col0, ncols); break;
+        case 1: k_big_fwd_diag<TF><<<grid, block, 0, s>>>(tiles, linv, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
+        case 2: k_big_fwd_update<TF><<<grid, block, 0, s>>>(tiles, fronts, items, wpg, kb, X, ldx, col0, ncols, ub, ldu); break;
+        case 3: k_big_bwd_init<TF><<<grid, block, 0, s>>>(tilesT, D, fronts, items, wpg, X, ldx, col0, ncols, rows); break;
+        case 4: k_big_bwd_diag<TF><<<grid, block, 0, s>>>(tilesT, linvT, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
+        case 5: k_big_bwd_update<TF><<<grid, block, 0, s>>>(tilesT, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-template hipError_t launch_big_solve<double>(int, const double*, const double*, const double*, const DFront*,
-                                             const int32_t*, int64_t, int32_t, double*, int64_t, int32_t, int32_t,
-                                             double*, int64_t, const int64_t*, const int64_t*, const double*,
-                                             const int32_t*, hipStream_t);
-template hipError_t launch_big_solve<float>(int, const float*, const float*, const float*, const DFront*,
-                                            const int32_t*, int64_t, int32_t, double*, int64_t, int32_t, int32_t,
-                                            double*, int64_t, const int64_t*, const int64_t*, const double*,
+template hipError_t launch_big_solve<double>(int, const double*, const double*, const double*, const double*,
+                                             const double*, const DFront*, const int32_t*, int64_t, int32_t, double*,
+                                             int64_t, int32_t, int32_t, double*, int64_t, const int64_t*,
+                                             const int64_t*, const double*, const int32_t*, hipStream_t);
+template hipError_t launch_big_solve<float>(int, const float*, const float*, const float*, const float*, const float*,
+                                            const DFront*, const int32_t*, int64_t, int32_t, double*, int64_t, int32_t,
+                                            int32_t, double*, int64_t, const int64_t*, const int64_t*, const double*,
                                             const int32_t*, hipStream_t);
 
 // ============================================================ Gram products
@@ -1611,97 +1679,155 @@ hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi
 // ============================================================ Ritz update + residual
 // Phi = Psi Phibar, S Phi = (S Psi) Phibar (registers only), M Phi = m * Phi
 // on the finest level or (M Psi) Phibar, on the FP64 matrix cores; per-column
-// partial sums of the residual numerator and of the normalisation.
-// Workgroup: RITZ_ROWS rows (in blocks of 32) x 160 columns; wave w takes rows
-// 16 (w / 2) .. +16 and column tiles 5 (w % 2) .. +5 of each 32-row block.
-// Psi, S Psi, M Psi are staged through LDS 32 columns of the contraction at a
-// time; the Phibar fragments come straight from L2.
+// partial sums of the residual numerator and of the normalisation for the
+// first nres columns (S Phi is formed only for those).
+// Persistent grid: one workgroup of 8 waves per CU walks 64-row blocks with
+// stride gridDim.x; wave w takes rows 16 (w / 2) .. +16 and column tiles
+// 5 (w % 2) .. +5 of the 160 columns of blockIdx.y.  The stages (block,
+// 32 contraction columns) go through LDS -- Psi, S Psi, M Psi rows and the
+// Phibar chunk shared by all waves -- and the next stage is loaded into
+// registers while the current one is multiplied.
 namespace {
-constexpr int RITZ_ROWS = 256;    // rows per workgroup
-constexpr int RB = 32;            // rows per block
-constexpr int RCOLS = 160;        // output columns per workgroup
-constexpr int RK = 32;            // contraction columns per LDS stage
-constexpr int RLD = RK + 4;       // LDS row stride
+constexpr int RZ_RB = 64;            // rows per block
+constexpr int RZ_K = 32;             // contraction columns per stage
+constexpr int RZ_LD = RZ_K + 4;      // LDS row stride of the row stage
+constexpr int RZ_COLS = 160;         // output columns per workgroup
+constexpr int RZ_BLD = RZ_COLS + 8;  // LDS row stride of the Phibar stage
+constexpr int RZ_THREADS = 512;
+constexpr int RZ_MAX_WG = 2048;      // persistent workgroups at most (partial-sum rows)
+template <bool HAS_M>
+constexpr size_t ritz_lds() {
+    return ((size_t)(HAS_M ? 3 : 2) * RZ_RB * RZ_LD + (size_t)RZ_K * RZ_BLD) * sizeof(double);
+}
+int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
 }  // namespace
 
-int64_t ritz_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) {
-    const int64_t nch = cdiv(n, RITZ_ROWS);
-    return nch * 2 * (int64_t)q + 2 * (int64_t)q + colsum_tmp_doubles(nch, 2 * q);
+int64_t ritz_partial_doubles(int64_t /*n*/, int32_t q, int64_t /*chunk_rows*/) {
+    return (int64_t)RZ_MAX_WG * 2 * q + 2 * (int64_t)q + colsum_tmp_doubles(RZ_MAX_WG, 2 * q);
 }
 
 template <bool HAS_M>
-__global__ __launch_bounds__(256) void k_ritz_mfma(const double* __restrict__ Psi, const double* __restrict__ SPsi,
-                                                   const double* __restrict__ MPsi, const double* __restrict__ mdiag,
-                                                   const double* __restrict__ Phibar, const double* __restrict__ lam,
-                                                   int64_t n, int32_t q, int64_t ld, double* __restrict__ Phi,
-                                                   double* __restrict__ MPhi, double* __restrict__ partial,
-                                                   int minv_norm) {
-    __shared__ double Ps[RB][RLD], Ss[RB][RLD], Ms[HAS_M ? RB : 1][RLD];
-    __shared__ double red[2][2][RCOLS];
-    const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
-    const int wr = w / 2, wc = w % 2;
-    const int col0 = blockIdx.y * RCOLS;
-    double num[5] = {0, 0, 0, 0, 0}, den[5] = {0, 0, 0, 0, 0};
-    const int64_t wg_r0 = (int64_t)blockIdx.x * RITZ_ROWS;
-    const int64_t wg_r1 = min(n, wg_r0 + RITZ_ROWS);
-    for (int64_t r0 = wg_r0; r0 < wg_r1; r0 += RB) {
-        dbl4 aP[5], aS[5], aM[5];
+__global__ __launch_bounds__(RZ_THREADS) void k_ritz_mfma(const double* __restrict__ Psi, const double* __restrict__ SPsi,
+                                                          const double* __restrict__ MPsi, const double* __restrict__ mdiag,
+                                                          const double* __restrict__ Phibar, const double* __restrict__ lam,
+                                                          int64_t n, int32_t q, int64_t ld, double* __restrict__ Phi,
+                                                          double* __restrict__ MPhi, double* __restrict__ partial,
+                                                          int minv_norm, int32_t nres) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double(*Ps)[RZ_LD] = reinterpret_cast<double(*)[RZ_LD]>(smem_raw);
+    double(*Ss)[RZ_LD] = Ps + RZ_RB;
+    double(*Ms)[RZ_LD] = Ss + RZ_RB;   // HAS_M only
+    double(*Bs)[RZ_BLD] = reinterpret_cast<double(*)[RZ_BLD]>(&(HAS_M ? Ms : Ss)[RZ_RB][0]);
+    double(*red)[2][RZ_COLS] = reinterpret_cast<double(*)[2][RZ_COLS]>(smem_raw);   // after the last stage
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int col0 = blockIdx.y * RZ_COLS;
+    const int64_t nblk = (n + RZ_RB - 1) / RZ_RB;
+    const int nk = (q + RZ_K - 1) / RZ_K;
+    const int64_t my_blocks = blockIdx.x < nblk ? (nblk - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+    const int64_t nst = my_blocks * nk;
+    constexpr int PA = RZ_RB * RZ_K / RZ_THREADS;     // 4
+    constexpr int PB = RZ_K * RZ_COLS / RZ_THREADS;   // 10
+    double ra[PA], rs[PA], rm[PA], rb[PB];
+    auto fetch = [&](int64_t st) {
+        const int64_t r0 = (blockIdx.x + (st / nk) * gridDim.x) * RZ_RB;
+        const int k0 = (int)(st % nk) * RZ_K;
 #pragma unroll
-        for (int u = 0; u < 5; ++u) aP[u] = aS[u] = aM[u] = dbl4{0, 0, 0, 0};
-        for (int k0 = 0; k0 < q; k0 += RK) {
-            for (int idx = tid; idx < RB * RK; idx += 256) {
-                const int r = idx / RK, kk = idx % RK;
-                const int64_t row = r0 + r;
-                const bool ok = row < n && k0 + kk < q;
-                Ps[r][kk] = ok ? Psi[row * ld + k0 + kk] : 0.0;
-                Ss[r][kk] = ok ? SPsi[row * ld + k0 + kk] : 0.0;
-                if (HAS_M) Ms[r][kk] = ok ? MPsi[row * ld + k0 + kk] : 0.0;
-            }
-            __syncthreads();
-            const int r = wr * 16 + lane % 16;
-            for (int kk = 0; kk < RK; kk += 4) {
-                const int kr = k0 + kk + lane / 16;
-                double bv[5];
-#pragma unroll
-                for (int u = 0; u < 5; ++u) {
-                    const int c = col0 + (wc * 5 + u) * 16 + lane % 16;
-                    bv[u] = (kr < q && c < q) ? Phibar[(int64_t)kr * q + c] : 0.0;
-                }
-                const int kc = kk + lane / 16;
-                const double ap = Ps[r][kc], as = Ss[r][kc];
-                const double am = HAS_M ? Ms[r][kc] : 0.0;
-#pragma unroll
-                for (int u = 0; u < 5; ++u) {
-                    aP[u] = mfma4(ap, bv[u], aP[u]);
-                    aS[u] = mfma4(as, bv[u], aS[u]);
-                    if (HAS_M) aM[u] = mfma4(am, bv[u], aM[u]);
-                }
-            }
-            __syncthreads();
+        for (int e = 0; e < PA; ++e) {
+            const int idx = tid + RZ_THREADS * e, r = idx / RZ_K, kk = idx % RZ_K;
+            const int64_t row = r0 + r;
+            const bool ok = row < n && k0 + kk < q;
+            ra[e] = ok ? Psi[row * ld + k0 + kk] : 0.0;
+            rs[e] = ok ? SPsi[row * ld + k0 + kk] : 0.0;
+            rm[e] = (HAS_M && ok) ? MPsi[row * ld + k0 + kk] : 0.0;
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t row = r0 + wr * 16 + lane / 16 + 4 * v;
-            if (row >= n) continue;
-            const double mr = HAS_M ? 0.0 : mdiag[row];
+        for (int e = 0; e < PB; ++e) {
+            const int idx = tid + RZ_THREADS * e, kk = idx / RZ_COLS, c = idx % RZ_COLS;
+            rb[e] = (k0 + kk < q && col0 + c < q) ? Phibar[(int64_t)(k0 + kk) * q + col0 + c] : 0.0;
+        }
+    };
+    bool sres[5];   // this wave's column tile u has residual columns
+#pragma unroll
+    for (int u = 0; u < 5; ++u) sres[u] = col0 + (wc * 5 + u) * 16 < nres;
+    dbl4 aP[5], aS[5], aM[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) aP[u] = aS[u] = aM[u] = dbl4{0, 0, 0, 0};
+    double num[5] = {0, 0, 0, 0, 0}, den[5] = {0, 0, 0, 0, 0};
+    if (nst > 0) fetch(0);
+    for (int64_t st = 0; st < nst; ++st) {
+#pragma unroll
+        for (int e = 0; e < PA; ++e) {
+            const int idx = tid + RZ_THREADS * e, r = idx / RZ_K, kk = idx % RZ_K;
+            Ps[r][kk] = ra[e];
+            Ss[r][kk] = rs[e];
+            if (HAS_M) Ms[r][kk] = rm[e];
+        }
+#pragma unroll
+        for (int e = 0; e < PB; ++e) {
+            const int idx = tid + RZ_THREADS * e;
+            Bs[idx / RZ_COLS][idx % RZ_COLS] = rb[e];
+        }
+        __syncthreads();
+        if (st + 1 < nst) fetch(st + 1);
+        const int r = wr * 16 + (lane & 15);
+#pragma unroll 2
+        for (int kk = 0; kk < RZ_K; kk += 4) {
+            const int kc = kk + (lane >> 4);
+            const double ap = Ps[r][kc], as = Ss[r][kc];
+            const double am = HAS_M ? Ms[r][kc] : 0.0;
 #pragma unroll
             for (int u = 0; u < 5; ++u) {
-                const int col = col0 + (wc * 5 + u) * 16 + lane % 16;
-                if (col >= q) continue;
-                const double phi = aP[u][v], sphi = aS[u][v];
-                const double mphi = HAS_M ? aM[u][v] : mr * phi;
-                Phi[row * ld + col] = phi;
-                if (MPhi) MPhi[row * ld + col] = mphi;
-                const double res = sphi - lam[col] * mphi;
-                if (minv_norm) {
-                    num[u] += res * res / mr;
-                    den[u] += phi * mphi;
-                } else {
-                    num[u] += res * res;
-                    den[u] += mphi * mphi;
-                }
+                const double b = Bs[kc][(wc * 5 + u) * 16 + (lane & 15)];
+                aP[u] = mfma4(ap, b, aP[u]);
+                if (sres[u]) aS[u] = mfma4(as, b, aS[u]);
+                if (HAS_M) aM[u] = mfma4(am, b, aM[u]);
             }
         }
+        if ((int)(st % nk) == nk - 1) {
+            // block finished: Phi (and M Phi) out, residual sums, accumulators reset
+            const int64_t r0 = (blockIdx.x + (st / nk) * gridDim.x) * RZ_RB;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = r0 + wr * 16 + (lane >> 4) + 4 * v;
+                if (row < n) {
+                    const double mr = HAS_M ? 0.0 : mdiag[row];
+#pragma unroll
+                    for (int u = 0; u < 5; ++u) {
+                        const int col = col0 + (wc * 5 + u) * 16 + (lane & 15);
+                        if (col < q) {
+                            const double phi = aP[u][v];
+                            const double mphi = HAS_M ? aM[u][v] : mr * phi;
+                            Phi[row * ld + col] = phi;
+                            if (MPhi) MPhi[row * ld + col] = mphi;
+                            if (col < nres) {
+                                const double res = aS[u][v] - lam[col] * mphi;
+                                if (minv_norm) {
+                                    num[u] += res * res / mr;
+                                    den[u] += phi * mphi;
+                                } else {
+                                    num[u] += res * res;
+                                    den[u] += mphi * mphi;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 5; ++u) aP[u] = aS[u] = aM[u] = dbl4{0, 0, 0, 0};
+        }
+        __syncthreads();
     }
     // lanes l, l + 16, l + 32, l + 48 hold the same columns
 #pragma unroll
@@ -1719,9 +1845,11 @@ __global__ __launch_bounds__(256) void k_ritz_mfma(const double* __restrict__ Ps
         }
     }
     __syncthreads();
-    if (tid < RCOLS && col0 + tid < q) {
-        partial[(int64_t)blockIdx.x * 2 * q + col0 + tid] = red[0][0][tid] + red[1][0][tid];
-        partial[(int64_t)blockIdx.x * 2 * q + q + col0 + tid] = red[0][1][tid] + red[1][1][tid];
+    if (tid < RZ_COLS && col0 + tid < q) {
+        partial[(int64_t)blockIdx.x * 2 * q + col0 + tid] =
+            (red[0][0][tid] + red[1][0][tid]) + (red[2][0][tid] + red[3][0][tid]);
+        partial[(int64_t)blockIdx.x * 2 * q + q + col0 + tid] =
+            (red[0][1][tid] + red[1][1][tid]) + (red[2][1][tid] + red[3][1][tid]);
     }
 }
 
@@ -1768,31 +1896,41 @@ hipError_t launch_colsum(const double* in, int64_t nrows, int32_t ncols, double*
     return hipGetLastError();
 }
 
-__global__ void k_resid_final(const double* __restrict__ sums, int32_t q, const double* __restrict__ lam,
+__global__ void k_resid_final(const double* __restrict__ sums, int32_t q, int32_t nres, const double* __restrict__ lam,
                               double lam_floor, double* resid) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= q) return;
-    resid[c] = sqrt(sums[c]) / (fmax(fabs(lam[c]), lam_floor) * sqrt(sums[q + c]));
+    resid[c] = c < nres ? sqrt(sums[c]) / (fmax(fabs(lam[c]), lam_floor) * sqrt(sums[q + c])) : NAN;
 }
 
 hipError_t launch_ritz(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag,
                        const double* Phibar, const double* lam, int64_t n, int32_t q, int64_t ld, double* Phi,
                        double* MPhi, double* partial, int64_t /*chunk_rows*/, bool minv_norm, double lam_floor,
-                       double* resid, hipStream_t s) {
-    const int64_t nch = cdiv(n, RITZ_ROWS);
-    const dim3 grid((unsigned)nch, (unsigned)cdiv(q, RCOLS));
-    if (mdiag)
-        k_ritz_mfma<false><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi, MPhi, partial,
-                                                minv_norm ? 1 : 0);
-    else
-        k_ritz_mfma<true><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi, MPhi, partial,
-                                               minv_norm ? 1 : 0);
-    hipError_t e = hipGetLastError();
+                       double* resid, hipStream_t s, int32_t nres) {
+    if (nres < 0 || nres > q) nres = q;
+    const int64_t nblk = cdiv(n, RZ_RB);
+    const int64_t nwg = std::max<int64_t>(1, std::min<int64_t>({(int64_t)device_cus(), nblk, (int64_t)RZ_MAX_WG}));
+    const dim3 grid((unsigned)nwg, (unsigned)cdiv(q, RZ_COLS));
+    hipError_t e;
+    if (mdiag) {
+        constexpr size_t lds = ritz_lds<false>();
+        e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_ritz_mfma<false>), lds, 0);
+        if (e != hipSuccess) return e;
+        k_ritz_mfma<false><<<grid, RZ_THREADS, lds, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi, MPhi,
+                                                         partial, minv_norm ? 1 : 0, nres);
+    } else {
+        constexpr size_t lds = ritz_lds<true>();
+        e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_ritz_mfma<true>), lds, 0);
+        if (e != hipSuccess) return e;
+        k_ritz_mfma<true><<<grid, RZ_THREADS, lds, s>>>(Psi, SPsi, MPsi, mdiag, Phibar, lam, n, q, ld, Phi, MPhi,
+                                                        partial, minv_norm ? 1 : 0, nres);
+    }
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    double* sums = partial + nch * 2 * (int64_t)q;
-    e = launch_colsum(partial, nch, 2 * q, sums + 2 * (int64_t)q, sums, s);
+    double* sums = partial + nwg * 2 * (int64_t)q;
+    e = launch_colsum(partial, nwg, 2 * q, sums + 2 * (int64_t)q, sums, s);
     if (e != hipSuccess) return e;
-    k_resid_final<<<(unsigned)cdiv(q, 256), 256, 0, s>>>(sums, q, lam, lam_floor, resid);
+    k_resid_final<<<(unsigned)cdiv(q, 256), 256, 0, s>>>(sums, q, nres, lam, lam_floor, resid);
     return hipGetLastError();
 }
 
