@@ -139,8 +139,7 @@ struct DenseGEP {
     void setup(int32_t kk) {
         if (k == kk) return;
         k = kk;
-        bj = env_int("HSIM_BJ_B", 16);  // block Jacobi block size
-        if (bj != 16 && bj != 32) bj = 16;
+        bj = 16;                                       // block Jacobi block size
         m = (int32_t)round_up(k, 2 * bj);
         ns_pad = (int32_t)round_up(k, NB);
         Mt = ns_pad / NB;
@@ -242,13 +241,12 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     HIPCHECK(launch_identity(dptr<double>(V), m, s));
     const double tol_rel = 1e-15;
     const int32_t nb = m / bj;
-    const int32_t inner = std::max(1, std::min(3, env_int("HSIM_BJ_INNER", 1)));
     int32_t sweeps = 0;
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
         HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 1, 0, s));
         for (int32_t r = 0; r < nb - 1; ++r)
             HIPCHECK(launch_bj_round(bj, dptr<double>(C), dptr<double>(V), m, r, dptr<double>(Qs), dptr<double>(normf),
-                                     tol_rel, 1e-17, inner, dptr<int32_t>(rot), s));
+                                     tol_rel, 1e-17, 1, dptr<int32_t>(rot), s));
         int32_t nrot = 0;
         HIPCHECK(hipMemcpyAsync(&nrot, rot.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
@@ -666,13 +664,23 @@ static void apply_level(hsim_hierarchy* H, Level& L, int op, const double* X, do
 // FP64 iterative refinement until every column's relative residual
 // ||B - A X|| / ||B|| is at most eta; falls back to the FP64 solve when the
 // refinement stalls.  B is not modified.  Returns the refinement sweeps.
+// est32: backward error of a plain FP32 solve measured on this factor (< 0:
+// not measured yet).  A solve that FP32 cannot meet without refinement is done
+// in FP64 at once; one that it meets by a wide margin skips the residual check.
+// The solve accuracy only steers convergence: every accepted eigenpair is
+// certified by the FP64 residual of an FP64 Rayleigh-Ritz step.
 static int32_t refine_solve(hsim_hierarchy* H, Level& L, const double* B, double* X, int32_t col0, int32_t ncols,
-                            double eta, hipStream_t s, int32_t* escalated) {
+                            double eta, hipStream_t s, int32_t* escalated, double* est32) {
     const int64_t n = L.n;
     const int32_t ld = H->ld;
     double* R = dptr<double>(H->R);
     HIPCHECK(launch_copy2d(B + col0, ld, n, ncols, X + col0, ld, s));
+    if (*est32 >= 0 && *est32 > eta) {
+        solve_level(H, L, X, col0, ncols, false, s, false);
+        return 0;
+    }
     solve_level(H, L, X, col0, ncols, false, s, true);
+    if (*est32 >= 0 && *est32 <= 0.1 * eta) return 0;
     std::vector<double> ratio(ncols);
     double prev = INFINITY;
     int32_t sweeps = 0, stall = 0;
@@ -689,6 +697,7 @@ static int32_t refine_solve(hsim_hierarchy* H, Level& L, const double* B, double
         HIPCHECK(hipStreamSynchronize(s));
         double worst = 0;
         for (double r : ratio) worst = std::max(worst, std::isfinite(r) ? r : INFINITY);
+        if (it == 0) *est32 = std::isfinite(worst) ? worst : 1.0;
         if (worst <= eta) return sweeps;
         if (!(worst < 0.5 * prev)) ++stall;
         if (stall >= 2 || !std::isfinite(worst)) break;
@@ -1081,7 +1090,8 @@ hsim_status hsim_step_solve(hsim_hierarchy* h, int32_t level, int32_t k, const d
         if (!L.factored32) fail(HSIM_E_STATE, "mixed solve needs hsim_step_factor with HSIM_MIXED");
         if (!(refine_tol > 0)) fail(HSIM_E_INVALID, "refine_tol must be positive");
         int32_t esc = 0;
-        refine_solve(h, L, dptr<double>(h->Xc), dptr<double>(h->Btmp), 0, k, refine_tol, s, &esc);
+        double est32 = -1.0;   // always measure and refine on this entry point
+        refine_solve(h, L, dptr<double>(h->Xc), dptr<double>(h->Btmp), 0, k, refine_tol, s, &esc, &est32);
         HIPCHECK(launch_scatter_rows(dptr<double>(h->Btmp), h->ld, dptr<int32_t>(L.dperm), L.n, k, d_X, k, s));
     } else {
         solve_level(h, L, dptr<double>(h->Xc), 0, k, false, s);
@@ -1232,6 +1242,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         bool conv = false;
         double rmax = INFINITY;   // largest residual of the first p pairs after the last Rayleigh-Ritz step
         bool fp64_gram = false;
+        double est32 = -1.0;      // backward error of a plain FP32 solve on this level's factor
         for (it = 1; it <= so.max_iters; ++it) {
             auto a0 = std::chrono::steady_clock::now();
             HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, L.n, q, dptr<double>(h->Psi), h->ld, s));
@@ -1256,7 +1267,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
                     if (mixed) {
                         const double eta = std::min(1e-3, 0.1 * (std::isfinite(rmax) ? rmax : 1e-2));
                         st.refine_steps += refine_solve(h, L, dptr<double>(h->Btmp), dptr<double>(h->Psi), locked, act,
-                                                        eta, s, &st.escalated);
+                                                        eta, s, &st.escalated, &est32);
                     } else {
                         solve_level(h, L, dptr<double>(h->Btmp), locked, act, false, s);
                         HIPCHECK(launch_copy2d(dptr<double>(h->Btmp) + locked, h->ld, L.n, act,
