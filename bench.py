@@ -174,7 +174,9 @@ def main():
             rel = (evm - ev64).abs()[1:] / ev64[1:].abs()
             results["mixed"] = dict(s=dtm, iters=stm["iters"], max_resid=float(rm.max()),
                                     max_eig_rel_diff_vs_fp64=float(rel.max()), stats=stm)
-            value, dtype = dtm, "f32+f64"
+            # headline: the faster of the two precision modes (both reach the tolerance)
+            if dtm < dt64 and float(rm.max()) <= args.tol:
+                value, dtype = dtm, "f32+f64"
         except hs.HsimError as e:
             log(f"mixed precision unavailable: {e}")
             results["mixed"] = dict(error=str(e))
@@ -228,6 +230,7 @@ def main():
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": f"geodesic icosphere nu={args.nu} with 50 bumps + radial noise, "
                                f"{len(V)} vertices, p={args.p}, q={H.q}, T={H.levels}, eps={args.tol}",
+                   "headline_precision": "mixed" if dtype == "f32+f64" else "fp64",
                    "fp64_s": round(dt64, 5), "mixed_s": results.get("mixed", {}).get("s"),
                    "hierarchy_build_s": round(t_build, 3), "factor_nnz": info0["factor_nnz"],
                    "fp64_iters": st64["iters"], "fp64_max_resid": results["fp64"]["max_resid"],

@@ -293,7 +293,8 @@ struct Level {
     DeviceBuffer dS_ptr, dS_idx, dS_val, dM_val, dmdiag, dU_ptr, dU_idx, dU_val, dperm;
     DeviceBuffer dfronts, tiles, linv, D, tiles32, linv32, D32, counters;
     DeviceBuffer tilesT, linvT, tiles32T, linv32T;   // tile-transposed copies for the backward sweeps
-    DeviceBuffer asm_dst, asm_src, it_diag, it_panel, it_upd, it_ea, rel, rows, gptr, gidx;
+    DeviceBuffer asm_dst, asm_src, it_diag, it_panel, it_upd, it_ea, rel, rows, gat;
+    int32_t gw = 0;   // width of the padded gather table
     DeviceBuffer ubuf, big_items;
     double mu = 0;
     bool factored = false, factored32 = false;
@@ -430,8 +431,20 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
     L.it_ea.upload(sy.ea.empty() ? std::vector<int32_t>{0} : sy.ea);
     L.rel.upload(sy.rel.empty() ? std::vector<int32_t>{0} : sy.rel);
     L.rows.upload(sy.rows.empty() ? std::vector<int32_t>{0} : sy.rows);
-    L.gptr.upload(sy.gather_ptr);
-    L.gidx.upload(sy.gather_idx.empty() ? std::vector<int64_t>{0} : sy.gather_idx);
+    // padded gather table: for every (front, local row) its update-buffer source rows, -1 padded
+    int64_t gwid = 0;
+    for (size_t r = 0; r + 1 < sy.gather_ptr.size(); ++r)
+        gwid = std::max<int64_t>(gwid, sy.gather_ptr[r + 1] - sy.gather_ptr[r]);
+    L.gw = (int32_t)gwid;
+    {
+        std::vector<int32_t> gat(std::max<size_t>(1, sy.gather_ptr.size() * (size_t)L.gw), -1);
+        for (size_t r = 0; r + 1 < sy.gather_ptr.size(); ++r)
+            for (int64_t g = sy.gather_ptr[r]; g < sy.gather_ptr[r + 1]; ++g) {
+                if (sy.gather_idx[g] > INT32_MAX) fail(HSIM_E_UNIMPLEMENTED, "update buffer beyond 2^31 rows");
+                gat[r * L.gw + (g - sy.gather_ptr[r])] = (int32_t)sy.gather_idx[g];
+            }
+        L.gat.upload(gat);
+    }
     L.ubuf.alloc((size_t)std::max<int64_t>(1, sy.ubuf_rows) * H->ld * sizeof(double));
     // per tree level launch data
     const int32_t mc = std::max<int32_t>(1, sy.max_children);
@@ -588,7 +601,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
     auto big = [&](int phase, const int64_t* rec, int32_t kb) {
         HIPCHECK(launch_big_solve<TF>(phase, tiles, linv, D, tilesT, linvT, fr, bi + rec[0], rec[1], kb, X, H->ld,
                                       col0, ncols,
-                                      dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr), dptr<int64_t>(L.gidx), md,
+                                      dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
                                       dptr<int32_t>(L.rows), s));
     };
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
@@ -607,7 +620,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         }
         P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
             HIPCHECK(launch_wsolve<TF>(true, tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols,
-                                       dptr<double>(L.ubuf), H->ld, dptr<int64_t>(L.gptr), dptr<int64_t>(L.gidx), md,
+                                       dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
                                        nullptr, false, s));
         });
     }
@@ -627,7 +640,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         }
         P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
             HIPCHECK(launch_wsolve<TF>(false, tilesT, linvT, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols,
-                                       nullptr, H->ld, nullptr, nullptr, nullptr, dptr<int32_t>(L.rows), true, s));
+                                       nullptr, H->ld, nullptr, 0, nullptr, dptr<int32_t>(L.rows), true, s));
         });
     }
 }
@@ -1277,9 +1290,11 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
             }
             HIPCHECK(hipStreamSynchronize(s));
             st.ms_solve += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a0).count();
-            // FP32 Gram only far from convergence: its rounding bounds the Ritz
-            // vectors' accuracy; switch for good once it stops paying off
-            const bool low_gram = mixed && !fp64_gram && rmax > std::max(100.0 * so.tol, 1e-4);
+            // FP32 Gram only far from convergence (its rounding bounds the Ritz
+            // vectors' accuracy; switch for good once it stops paying off), and
+            // only where no single-pass FP64 Gram kernel exists (q > 160)
+            const bool low_gram = mixed && !fp64_gram && q > gram_fp64_single_pass_max_q() &&
+                                  rmax > std::max(100.0 * so.tol, 1e-4);
             rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, low_gram);
             auto check = [&] {
                 conv = true;

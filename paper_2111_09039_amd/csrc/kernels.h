@@ -73,7 +73,8 @@ hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const 
 // counts up to wsolve_max_ns()): one wave per (front, 16 columns), the
 // front's block of the right-hand side in registers.  fwd: forward sweep
 // (mdiag optional pre-scaling, children's updates gathered from ubuf, own
-// updates written to ubuf); !fwd: backward sweep (apply_dinv divides by D),
+// updates written to ubuf; gat: gw update-buffer rows per front row, -1 = none,
+// indexed by (gather_base + local row)); !fwd: backward sweep (apply_dinv divides by D),
 // with tiles and linv the tile-transposed copies (launch_tile_transpose).
 int32_t wsolve_max_ns();
 // every 32 x 32 tile of in[0 .. 1024 ntiles) transposed into the same place of out
@@ -82,7 +83,7 @@ hipError_t launch_tile_transpose(const T* in, T* out, int64_t ntiles, hipStream_
 template <class TF>
 hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
                          int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
-                         double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx, const double* mdiag,
+                         double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw, const double* mdiag,
                          const int32_t* rows, bool apply_dinv, hipStream_t s);
 
 // Block solves of tree levels with wide supernodes, 128-row pivot blocks:
@@ -98,7 +99,7 @@ template <class TF>
 hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
                             const TF* linvT, const DFront* fronts, const int32_t* items, int64_t nitems, int32_t kb,
                             double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf, int64_t ldu,
-                            const int64_t* gptr, const int64_t* gidx, const double* mdiag, const int32_t* rows,
+                            const int32_t* gat, int32_t gw, const double* mdiag, const int32_t* rows,
                             hipStream_t s);
 
 // ------------------------------------------------------------ Rayleigh-Ritz
@@ -108,6 +109,8 @@ hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi
                        int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
                        hipStream_t s, bool fp32 = false);
 int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows);
+// largest q for which the FP64 Gram is one pass over the rows (all tiles per workgroup)
+int32_t gram_fp64_single_pass_max_q();
 
 // Phi = Psi Phibar and residual partial sums; then the residual
 // nres: residuals of the first nres columns only (the rest are set to NaN); -1 = all

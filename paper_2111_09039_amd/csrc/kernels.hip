@@ -29,6 +29,19 @@ __device__ __forceinline__ int64_t tri(int32_t Mt, int32_t I, int32_t J) {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// compute units of the current device (persistent launches)
+int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
 // 16 x 16 x 4 matrix-core products.  Operand layout (lane l of the wave):
 // A (16 x 4) element (l % 16, l / 16), B (4 x 16) element (l / 16, l % 16).
 // Result element v of lane l: FP64 (l / 16 + 4 v, l % 16), FP32
@@ -134,29 +147,52 @@ hipError_t launch_copy2d(const double* in, int64_t ldi, int64_t rows, int32_t k,
 }
 
 // ====================================================================== SpMM
-// one 64-lane wavefront per row, lanes across the k columns
+// Y = (a A + b B) X for CSR A, B on one pattern (B optional): one wave per
+// row, 64 lanes over the columns.  The edges of a row are fetched 8 at a time
+// (index and weight by one lane each, broadcast by shuffles) and the X rows
+// of all 8 are loaded at once (missing edges read the row itself with weight
+// zero).  Workgroups are spread so that each XCD takes one contiguous eighth
+// of the rows: neighbouring rows share their X rows in that XCD's L2.
 __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                               const double* __restrict__ va, const double* __restrict__ vb, double a,
                                               double b, int64_t rows, const double* __restrict__ X, int64_t ldx,
                                               int32_t k, double* __restrict__ Y, int64_t ldy) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t g8 = gridDim.x;   // a multiple of 8
+    const int64_t blk = (blockIdx.x % 8) * (g8 / 8) + blockIdx.x / 8;
+    const int64_t row = blk * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= rows) return;
     const int64_t e0 = ptr[row], e1 = ptr[row + 1];
     for (int c0 = 0; c0 < k; c0 += 256) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t e = e0; e < e1; ++e) {
-            const double w = vb ? a * va[e] + b * vb[e] : a * va[e];
-            const double* xr = X + (int64_t)idx[e] * ldx;
+        for (int64_t eb = e0; eb < e1; eb += 8) {
+            const int cnt = (int)min<int64_t>(8, e1 - eb);
+            int my_col = (int)row;
+            double my_w = 0.0;
+            if (lane < cnt) {
+                my_col = idx[eb + lane];
+                my_w = vb ? a * va[eb + lane] + b * vb[eb + lane] : a * va[eb + lane];
+            }
+            double xv[8][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                int c = c0 + lane + 64 * u;
-                if (c < k) acc[u] += w * xr[c];
+            for (int j = 0; j < 8; ++j) {
+                const double* xr = X + (int64_t)__shfl(my_col, j) * ldx;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = c0 + lane + 64 * u;
+                    xv[j][u] = c < k ? xr[c] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const double w = __shfl(my_w, j);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] += w * xv[j][u];
             }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            int c = c0 + lane + 64 * u;
+            const int c = c0 + lane + 64 * u;
             if (c < k) Y[row * ldy + c] = acc[u];
         }
     }
@@ -164,7 +200,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr, c
 hipError_t launch_spmm(const int64_t* ptr, const int32_t* idx, const double* va, const double* vb, double a, double b,
                        int64_t rows, const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy, hipStream_t s) {
     if (rows <= 0 || k <= 0) return hipSuccess;
-    k_spmm<<<(unsigned)cdiv(rows, 4), 256, 0, s>>>(ptr, idx, va, vb, a, b, rows, X, ldx, k, Y, ldy);
+    k_spmm<<<(unsigned)(cdiv(cdiv(rows, 4), 8) * 8), 256, 0, s>>>(ptr, idx, va, vb, a, b, rows, X, ldx, k, Y, ldy);
     return hipGetLastError();
 }
 
@@ -647,8 +683,8 @@ struct WsolveCols {
 template <class TF, int NT>
 __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
     const TF* __restrict__ tiles, const TF* __restrict__ linv, const DFront* __restrict__ fr, int32_t f0, double* X,
-    int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu, const int64_t* __restrict__ gptr,
-    const int64_t* __restrict__ gidx, const double* __restrict__ mdiag) {
+    int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu, const int32_t* __restrict__ gat,
+    int32_t gw, const double* __restrict__ mdiag) {
     constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
     const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS * CT;
@@ -673,9 +709,12 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
                     val = X[(f.start + r) * ldx + c];
                     if (mdiag) val *= mdiag[f.start + r];
                     if (gath) {
-                        const int64_t g1 = gptr[f.gather_base + r + 1];
-#pragma unroll 1
-                        for (int64_t g = gptr[f.gather_base + r]; g < g1; ++g) val += (double)ubuf[gidx[g] * ldu + c];
+                        const int32_t* gr = gat + (f.gather_base + r) * gw;
+#pragma unroll 2
+                        for (int cg = 0; cg < gw; ++cg) {
+                            const int32_t src = gr[cg];
+                            if (src >= 0) val += (double)ubuf[(int64_t)src * ldu + c];
+                        }
                     }
                 }
                 y[cc][t][v] = val;
@@ -746,14 +785,17 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
 #pragma unroll 1
     for (int rt = 0; rt < mt; ++rt) {
         const int st = rt >> 1, half = rt & 1;
-        int64_t g0[4], g1[4];
+        // first two gather sources of every update row, ahead of the products
+        int32_t s0[4] = {-1, -1, -1, -1}, s1[4] = {-1, -1, -1, -1};
         if (gath) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int sr = 16 * rt + lr + 4 * v;
-                const int64_t gr = f.gather_base + f.ns + min(sr, f.mu - 1);
-                g0[v] = gptr[gr];
-                g1[v] = sr < f.mu ? gptr[gr + 1] : g0[v];
+                if (sr < f.mu) {
+                    const int32_t* gr = gat + (f.gather_base + f.ns + sr) * gw;
+                    if (gw > 0) s0[v] = gr[0];
+                    if (gw > 1) s1[v] = gr[1];
+                }
             }
         }
         dbl4 acc[CT];
@@ -781,8 +823,14 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
                 if (sr < f.mu && c < cend) {
                     double u = 0.0;
                     if (gath) {
+                        if (s0[v] >= 0) u += (double)ubuf[(int64_t)s0[v] * ldu + c];
+                        if (s1[v] >= 0) u += (double)ubuf[(int64_t)s1[v] * ldu + c];
+                        const int32_t* gr = gat + (f.gather_base + f.ns + sr) * gw;
 #pragma unroll 1
-                        for (int64_t g = g0[v]; g < g1[v]; ++g) u += (double)ubuf[gidx[g] * ldu + c];
+                        for (int cg = 2; cg < gw; ++cg) {
+                            const int32_t src = gr[cg];
+                            if (src >= 0) u += (double)ubuf[(int64_t)src * ldu + c];
+                        }
                     }
                     ubuf[(f.ubuf_row + sr) * ldu + c] = (TF)(u - acc[cc][v]);
                 }
@@ -980,7 +1028,7 @@ inline void wsolve_shape(int32_t ncols, int32_t max_waves, int32_t cols_per_wave
 template <class TF>
 hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
                          int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
-                         double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx, const double* mdiag,
+                         double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw, const double* mdiag,
                          const int32_t* rows, bool apply_dinv, hipStream_t s) {
     if (f1 <= f0 || ncols <= 0) return hipSuccess;
     if (ns_pad_max > wsolve_max_ns()) return hipErrorInvalidValue;
@@ -991,7 +1039,7 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
     const dim3 grid((unsigned)(f1 - f0), (unsigned)groups), block((unsigned)(64 * wpg));                          \
     if (fwd)                                                                                                      \
         k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, X, ldx, col0, ncols, wpg, ub, ldu,  \
-                                                    gptr, gidx, mdiag);                                           \
+                                                    gat, gw, mdiag);                                              \
     else                                                                                                          \
         k_wsolve_bwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, D, fronts, f0, X, ldx, col0, ncols, wpg, rows,  \
                                                     apply_dinv ? 1 : 0);
@@ -1004,12 +1052,10 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
 }
 template hipError_t launch_wsolve<double>(bool, const double*, const double*, const double*, const DFront*, int32_t,
                                           int32_t, int32_t, double*, int64_t, int32_t, int32_t, double*, int64_t,
-                                          const int64_t*, const int64_t*, const double*, const int32_t*, bool,
-                                          hipStream_t);
+                                          const int32_t*, int32_t, const double*, const int32_t*, bool, hipStream_t);
 template hipError_t launch_wsolve<float>(bool, const float*, const float*, const float*, const DFront*, int32_t,
                                          int32_t, int32_t, double*, int64_t, int32_t, int32_t, double*, int64_t,
-                                         const int64_t*, const int64_t*, const double*, const int32_t*, bool,
-                                         hipStream_t);
+                                         const int32_t*, int32_t, const double*, const int32_t*, bool, hipStream_t);
 
 namespace {
 template <class T>
@@ -1118,8 +1164,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_big_fwd_init(const DFront* __restrict__ fr, const int32_t* __restrict__ items,
                                                       int32_t nchunks, double* X, int64_t ldx, int32_t col0,
                                                       int32_t ncols, T* ubuf, int64_t ldu,
-                                                      const int64_t* __restrict__ gptr,
-                                                      const int64_t* __restrict__ gidx,
+                                                      const int32_t* __restrict__ gat, int32_t gw,
                                                       const double* __restrict__ mdiag) {
     const int item = blockIdx.x / nchunks;
     const DFront f = fr[items[2 * item]];
@@ -1134,15 +1179,17 @@ __global__ __launch_bounds__(256) void k_big_fwd_init(const DFront* __restrict__
             if (row >= f.ns) continue;
             double v = X[(f.start + row) * ldx + c0 + c];
             if (mdiag) v *= mdiag[f.start + row];
-            for (int64_t g = gptr[f.gather_base + row]; g < gptr[f.gather_base + row + 1]; ++g)
-                v += (double)ubuf[gidx[g] * ldu + c0 + c];
+            const int32_t* gr = gat + (f.gather_base + row) * gw;
+            for (int cg = 0; cg < gw; ++cg)
+                if (gr[cg] >= 0) v += (double)ubuf[(int64_t)gr[cg] * ldu + c0 + c];
             X[(f.start + row) * ldx + c0 + c] = v;
         } else {
             const int s = (tr - f.nsb) * T32 + r;
             if (s >= f.mu) continue;
             double v = 0.0;
-            const int64_t gr = f.gather_base + f.ns + s;
-            for (int64_t g = gptr[gr]; g < gptr[gr + 1]; ++g) v += (double)ubuf[gidx[g] * ldu + c0 + c];
+            const int32_t* gr = gat + (f.gather_base + f.ns + s) * gw;
+            for (int cg = 0; cg < gw; ++cg)
+                if (gr[cg] >= 0) v += (double)ubuf[(int64_t)gr[cg] * ldu + c0 + c];
             ubuf[(f.ubuf_row + s) * ldu + c0 + c] = (T)v;
         }
     }
@@ -1447,14 +1494,14 @@ template <class TF>
 hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
                             const TF* linvT, const DFront* fronts, const int32_t* items, int64_t nitems, int32_t kb,
                             double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf, int64_t ldu,
-                            const int64_t* gptr, const int64_t* gidx, const double* mdiag, const int32_t* rows,
+                            const int32_t* gat, int32_t gw, const double* mdiag, const int32_t* rows,
                             hipStream_t s) {
     if (nitems <= 0 || ncols <= 0) return hipSuccess;
     TF* ub = reinterpret_cast<TF*>(ubuf);
     if (phase == 0) {
         const int32_t nch = (int32_t)cdiv(ncols, BQC);
         k_big_fwd_init<TF><<<(unsigned)(nitems * nch), 256, 0, s>>>(fronts, items, nch, X, ldx, col0, ncols, ub, ldu,
-                                                                    gptr, gidx, mdiag);
+                                                                    gat, gw, mdiag);
         return hipGetLastError();
     }
     int32_t wpg, groups;
@@ -1472,11 +1519,11 @@ hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF
 }
 template hipError_t launch_big_solve<double>(int, const double*, const double*, const double*, const double*,
                                              const double*, const DFront*, const int32_t*, int64_t, int32_t, double*,
-                                             int64_t, int32_t, int32_t, double*, int64_t, const int64_t*,
-                                             const int64_t*, const double*, const int32_t*, hipStream_t);
+                                             int64_t, int32_t, int32_t, double*, int64_t, const int32_t*, int32_t,
+                                             const double*, const int32_t*, hipStream_t);
 template hipError_t launch_big_solve<float>(int, const float*, const float*, const float*, const float*, const float*,
                                             const DFront*, const int32_t*, int64_t, int32_t, double*, int64_t, int32_t,
-                                            int32_t, double*, int64_t, const int64_t*, const int64_t*, const double*,
+                                            int32_t, double*, int64_t, const int32_t*, int32_t, const double*,
                                             const int32_t*, hipStream_t);
 
 // ============================================================ Gram products
@@ -1515,10 +1562,11 @@ static int64_t gram_pairs(int32_t q) {
 }
 
 // per-chunk partial blocks, their sum and the reduction's scratch
+int64_t gram_all_partial_doubles(int32_t q);
 int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) {
     const int64_t nch = cdiv(n, GRAM_CHUNK);
     const int64_t per = gram_pairs(q) * 2 * GT * GT;
-    return nch * per + per + colsum_tmp_doubles(nch, (int32_t)per);
+    return std::max(nch * per + per + colsum_tmp_doubles(nch, (int32_t)per), gram_all_partial_doubles(q));
 }
 
 template <class TA>
@@ -1641,6 +1689,136 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
         }
 }
 
+// FP64 Gram for q <= 160 (nt <= 10 column tiles of 16): persistent, one
+// workgroup of 2 ceil(nt / 2) waves per CU forms every upper 16 x 16 tile of
+// both products for its rows, so Psi is read once.  Wave w takes product
+// w / h (h = ceil(nt / 2); 0: S, 1: M) and the tile rows Ia = w % h and
+// Ib = nt - 1 - Ia with all their upper tiles: nt + 1 tiles per wave.  Rows
+// go through LDS 16 at a time (Psi, S Psi, M Psi or m), the next 16 are
+// loaded into registers meanwhile.  Output: per workgroup and product the
+// upper tiles in row-major tile order, each tile row-major.
+namespace {
+constexpr int GA_R = 16;          // rows per stage
+constexpr int GA_LD = 168;        // LDS row stride (doubles)
+constexpr int GA_MAXT = 10;       // column tiles
+constexpr int GA_THREADS = 640;
+constexpr int GA_MAX_WG = 1024;
+template <bool HAS_M>
+constexpr size_t gram_all_lds() {
+    return ((size_t)(HAS_M ? 3 : 2) * GA_R * GA_LD + GA_R) * sizeof(double);
+}
+}  // namespace
+
+int32_t gram_fp64_single_pass_max_q() { return GA_MAXT * 16; }
+
+int64_t gram_all_partial_doubles(int32_t q) {
+    const int64_t nt = cdiv(q, 16), nup = nt * (nt + 1) / 2, per = 2 * nup * 256;
+    return GA_MAX_WG * per + per + colsum_tmp_doubles(GA_MAX_WG, (int32_t)per);
+}
+
+template <bool HAS_M>
+__global__ __launch_bounds__(GA_THREADS) void k_gram_all(const double* __restrict__ Psi, const double* __restrict__ SPsi,
+                                                         const double* __restrict__ MPsi,
+                                                         const double* __restrict__ mdiag, int64_t n, int32_t q,
+                                                         int64_t ld, double* __restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double(*Ps)[GA_LD] = reinterpret_cast<double(*)[GA_LD]>(smem_raw);
+    double(*Ss)[GA_LD] = Ps + GA_R;
+    double(*Ms)[GA_LD] = Ss + GA_R;   // HAS_M only
+    double* mv = &(HAS_M ? Ms : Ss)[GA_R][0];   // m of the staged rows (finest level)
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nt = (q + 15) >> 4, h = (nt + 1) >> 1;
+    const int64_t nup = (int64_t)nt * (nt + 1) / 2;
+    const bool active = w < 2 * h;
+    const int prod = w / h, Ia = w % h, Ib = nt - 1 - Ia;
+    const int na = nt - Ia;                       // tiles of row Ia
+    const int nb2 = Ib != Ia ? nt - Ib : 0;       // tiles of row Ib
+    const int64_t nblk = (n + GA_R - 1) / GA_R;
+    const int64_t my_blocks = blockIdx.x < nblk ? (nblk - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+    constexpr int PE = (GA_R * GA_MAXT * 16 + GA_THREADS - 1) / GA_THREADS;   // 4
+    double rp[PE], rs[PE], rm[PE], rmd = 0.0;
+    auto fetch = [&](int64_t j) {
+        const int64_t r0 = (blockIdx.x + j * gridDim.x) * GA_R;
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int idx = tid + GA_THREADS * e, r = idx / (GA_MAXT * 16), c = idx % (GA_MAXT * 16);
+            const int64_t row = r0 + r;
+            const bool ok = idx < GA_R * GA_MAXT * 16 && row < n && c < q;
+            rp[e] = ok ? Psi[row * ld + c] : 0.0;
+            rs[e] = ok ? SPsi[row * ld + c] : 0.0;
+            rm[e] = (HAS_M && ok) ? MPsi[row * ld + c] : 0.0;
+        }
+        if (!HAS_M && tid < GA_R) rmd = r0 + tid < n ? mdiag[r0 + tid] : 0.0;
+    };
+    dbl4 acc[GA_MAXT + 1];
+#pragma unroll
+    for (int j = 0; j < GA_MAXT + 1; ++j) acc[j] = dbl4{0, 0, 0, 0};
+    if (my_blocks > 0) fetch(0);
+    for (int64_t jb = 0; jb < my_blocks; ++jb) {
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int idx = tid + GA_THREADS * e;
+            if (idx < GA_R * GA_MAXT * 16) {
+                const int r = idx / (GA_MAXT * 16), c = idx % (GA_MAXT * 16);
+                Ps[r][c] = rp[e];
+                Ss[r][c] = rs[e];
+                if (HAS_M) Ms[r][c] = rm[e];
+            }
+        }
+        if (!HAS_M && tid < GA_R) mv[tid] = rmd;
+        __syncthreads();
+        if (jb + 1 < my_blocks) fetch(jb + 1);
+        if (active) {
+            const double(*Bsrc)[GA_LD] = prod == 0 ? Ss : (HAS_M ? Ms : Ps);
+#pragma unroll 1
+            for (int kk = 0; kk < GA_R; kk += 4) {
+                const int kr = kk + (lane >> 4);
+                const double scale = (prod == 1 && !HAS_M) ? mv[kr] : 1.0;
+                const double aa = Ps[kr][16 * Ia + (lane & 15)];
+                const double ab = Ps[kr][16 * Ib + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < GA_MAXT + 1; ++j) {
+                    const bool first = j < na;
+                    const bool valid = first || j - na < nb2;
+                    if (valid) {
+                        const int J = first ? Ia + j : Ib + (j - na);
+                        const double b = Bsrc[kr][16 * J + (lane & 15)] * scale;
+                        acc[j] = mfma4(first ? aa : ab, b, acc[j]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    double* out = partial + ((int64_t)blockIdx.x * 2 + prod) * nup * 256;
+#pragma unroll
+    for (int j = 0; j < GA_MAXT + 1; ++j) {
+        const bool first = j < na;
+        if (!(first || j - na < nb2)) continue;
+        const int I = first ? Ia : Ib, J = first ? Ia + j : Ib + (j - na);
+        const int64_t t = (int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[t * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[j][v];
+    }
+}
+
+// Sbar, Mbar from the summed upper 16 x 16 tiles of k_gram_all
+__global__ void k_gram_all_scatter(const double* __restrict__ sums, int32_t q, double* Sbar, double* Mbar) {
+    const int32_t nt = (q + 15) >> 4;
+    const int64_t nup = (int64_t)nt * (nt + 1) / 2;
+    const int64_t tot = (int64_t)q * q;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        int32_t i = (int32_t)(e / q), j = (int32_t)(e % q);
+        if (i > j) { const int32_t x = i; i = j; j = x; }
+        const int32_t I = i >> 4, J = j >> 4;
+        const int64_t t = (int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I);
+        const int64_t off = t * 256 + (i & 15) * 16 + (j & 15);
+        Sbar[e] = sums[off];
+        Mbar[e] = sums[nup * 256 + off];
+    }
+}
+
 // Sbar, Mbar (q x q, symmetric) from the summed upper blocks
 __global__ void k_gram_scatter(const double* __restrict__ sums, int32_t q, double* Sbar, double* Mbar) {
     const int32_t nt = (q + GT - 1) / GT;
@@ -1659,6 +1837,31 @@ __global__ void k_gram_scatter(const double* __restrict__ sums, int32_t q, doubl
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
                        int32_t q, int64_t ld, double* partial, int64_t /*chunk_rows*/, double* Sbar, double* Mbar,
                        hipStream_t s, bool fp32) {
+    if (!fp32 && q <= GA_MAXT * 16) {
+        const int32_t nt = (int32_t)cdiv(q, 16);
+        const int64_t nup = (int64_t)nt * (nt + 1) / 2, per = 2 * nup * 256;
+        const int64_t nwg = std::max<int64_t>(1, std::min<int64_t>({(int64_t)device_cus(), cdiv(n, GA_R),
+                                                                    (int64_t)GA_MAX_WG}));
+        hipError_t e;
+        if (mdiag) {
+            constexpr size_t lds = gram_all_lds<false>();
+            e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_gram_all<false>), lds, 0);
+            if (e != hipSuccess) return e;
+            k_gram_all<false><<<(unsigned)nwg, GA_THREADS, lds, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, partial);
+        } else {
+            constexpr size_t lds = gram_all_lds<true>();
+            e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_gram_all<true>), lds, 0);
+            if (e != hipSuccess) return e;
+            k_gram_all<true><<<(unsigned)nwg, GA_THREADS, lds, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, partial);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        double* sums = partial + nwg * per;
+        e = launch_colsum(partial, nwg, (int32_t)per, sums + per, sums, s);
+        if (e != hipSuccess) return e;
+        k_gram_all_scatter<<<grid_for((int64_t)q * q, 256), 256, 0, s>>>(sums, q, Sbar, Mbar);
+        return hipGetLastError();
+    }
     const int64_t npairs = gram_pairs(q);
     const int64_t nch = cdiv(n, GRAM_CHUNK);
     const int64_t per = npairs * 2 * GT * GT;
@@ -1698,17 +1901,6 @@ constexpr int RZ_MAX_WG = 2048;      // persistent workgroups at most (partial-s
 template <bool HAS_M>
 constexpr size_t ritz_lds() {
     return ((size_t)(HAS_M ? 3 : 2) * RZ_RB * RZ_LD + (size_t)RZ_K * RZ_BLD) * sizeof(double);
-}
-int device_cus() {
-    static int cus[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cus[dev]) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
-        cus[dev] = v;
-    }
-    return cus[dev];
 }
 }  // namespace
 
