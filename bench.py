@@ -238,6 +238,14 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels_ms": {k: round(v["ms"], 3) for k, v in kern.items()},
+        # per kernel class: achieved algorithmic HBM rate and flop rate, fractions of the peaks
+        "classes": {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                        "GB_s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None,
+                        "TFLOP_s": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 else None,
+                        "frac_hbm": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if v["ms"] > 0 else None,
+                        "frac_fp64": round(v["flops"] / (v["ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
+                        if v["ms"] > 0 else None}
+                    for k, v in kern.items() if v["launches"] > 0},
     }
     print(json.dumps(line), flush=True)
 

@@ -323,3 +323,59 @@ def test_autograd_function_fd(cuda):
         an = float(np.sum(g * D))
         print(f"[autograd fd] fd {fd:.10e} adjoint {an:.10e}")
         assert abs(fd - an) <= 1e-5 * abs(fd)
+
+
+# ------------------------------------------------------- q above 160 columns
+@pytest.fixture(scope="module")
+def wide(cuda):
+    """p = 120 (q = 180): the Gram and Ritz kernels take their general
+    column tilings (more than 160 columns), the solves more column groups."""
+    import paper_2111_09039_amd as hs
+    rng = np.random.default_rng(21)
+    V, F = synth.icosphere(5)
+    V = synth.radial_jitter(V, 1e-2, rng)
+    S, m = assembly.assemble(V, F)
+    lv = hierarchy.build_hierarchy(V, F, S, m, p=120, levels=3, n_coarsest=400, seed=3)
+    H = hs.Hierarchy(V, F, 120, levels=3, n_coarsest=400, seed=3)
+    print(f"[wide hierarchy] sizes {[len(l['verts']) for l in lv]} q {H.q}", flush=True)
+    assert H.q == 180
+    return V, F, S, m, lv, H
+
+
+def test_wide_gram_and_ritz(wide):
+    V, F, S, m, lv, H = wide
+    rng = np.random.default_rng(8)
+    k = H.q
+    for tau in range(3):
+        n = len(lv[tau]["verts"])
+        Psi = rng.standard_normal((n, k))
+        Sb, Mb = H.gram(tau, _t(Psi))
+        Sr = Psi.T @ (lv[tau]["S"] @ Psi)
+        Mr = Psi.T @ (_mass(lv, tau) @ Psi)
+        assert np.abs(Sb.cpu().numpy() - Sr).max() <= 1e-13 * np.abs(Sr).max(), tau
+        assert np.abs(Mb.cpu().numpy() - Mr).max() <= 1e-13 * np.abs(Mr).max(), tau
+        Pb = rng.standard_normal((k, k))
+        lam = np.sort(rng.uniform(0.5, 20, k))
+        Phi, r = H.ritz(tau, _t(Psi), _t(Pb), _t(lam), 0.5)
+        Phi, r = Phi.cpu().numpy(), r.cpu().numpy()
+        ref = Psi @ Pb
+        assert np.abs(Phi - ref).max() <= 1e-13 * np.abs(ref).max(), tau
+        rr = sim.residual(lv[tau]["S"], lv[tau]["M"] if tau == 0 else _mass(lv, tau), ref, lam, lam_c=0.5,
+                          norm="minv" if tau == 0 else "l2")
+        assert np.abs(r - rr).max() <= 1e-12 * np.abs(rr).max(), tau
+
+
+def test_wide_hsim(wide):
+    V, F, S, m, lv, H = wide
+    p = 120
+    ev, X, r, st = H.solve(tol=1e-9)
+    ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
+    print(f"[wide hsim] iters {st['iters']} total {st['ms_total']:.1f} ms", flush=True)
+    lr, Xr, _, _ = sim.sim_lowest(S, m, p + 10, eps=1e-11)
+    rel = np.abs(ev - lr[:p])[1:] / lr[1:p]
+    assert rel.max() <= 1e-8, rel.max()
+    assert r.max() < 1e-9
+    assert metrics.m_orthonormality(X, m) < 1e-10
+    assert sim.residual(S, m, X, ev).max() < 2e-9
+    err = metrics.eigenvector_err(X, Xr, m, lr)
+    assert err.max() < 1e-5, err.max()
