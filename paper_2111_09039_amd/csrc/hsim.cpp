@@ -239,18 +239,22 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     HIPCHECK(launch_embed_pad(dptr<double>(W), k, m, dptr<double>(C), dptr<double>(normf), dptr<double>(dis),
                               dptr<double>(D), s));
     HIPCHECK(launch_identity(dptr<double>(V), m, s));
-    const double tol_rel = 1e-15;
+    const double tol_rel = 1e-15, tol_abs_rel = 1e-17;
     const int32_t nb = m / bj;
     int32_t sweeps = 0;
+    // a sweep ends the iteration when it rotated nothing or when no entry is
+    // left above the threshold (the next sweep would rotate nothing)
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
-        HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 1, 0, s));
+        HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 2, 0, s));
         for (int32_t r = 0; r < nb - 1; ++r)
             HIPCHECK(launch_bj_round(bj, dptr<double>(C), dptr<double>(V), m, r, dptr<double>(Qs), dptr<double>(normf),
-                                     tol_rel, 1e-17, 1, dptr<int32_t>(rot), s));
-        int32_t nrot = 0;
-        HIPCHECK(hipMemcpyAsync(&nrot, rot.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                                     tol_rel, tol_abs_rel, 1, dptr<int32_t>(rot), s));
+        HIPCHECK(launch_bj_offcount(dptr<double>(C), m, dptr<double>(normf), tol_rel, tol_abs_rel,
+                                    dptr<int32_t>(rot) + 1, s));
+        int32_t cnt[2] = {0, 0};
+        HIPCHECK(hipMemcpyAsync(cnt, rot.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
-        if (nrot == 0) break;
+        if (cnt[0] == 0 || cnt[1] == 0) break;
     }
     // Y = D^-1/2 V (sorted, first kout columns), X' = L^-T Y, X = E X'
     HIPCHECK(launch_sort_eig(dptr<double>(C), m, m, dptr<double>(V), k, dptr<double>(dis), kout, lam_out,

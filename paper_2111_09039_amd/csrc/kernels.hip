@@ -285,46 +285,61 @@ hipError_t launch_extend_add(double* tiles, const DFront* fronts, const int32_t*
 // counts negative pivots (inertia), counters[1] zero/non-finite pivots.
 __global__ __launch_bounds__(256) void k_fac_diag(double* tiles, double* linv, double* D, const DFront* __restrict__ fr,
                                                   const int32_t* __restrict__ items, int32_t k, int32_t* counters) {
+    // Right-looking LDL^T of the 32 x 32 diagonal tile held in registers:
+    // thread (i, c0) owns the entries (i, c0 + 8 e), e < 4, of the tile and of
+    // the inverse of its unit lower factor.  The inverse is accumulated
+    // alongside by applying the same row eliminations to the identity
+    // (L^-1 = E_31 ... E_0 with E_j = I - l_j e_j^T), so both finish after the
+    // 32 pivot steps.  Step j publishes column j of the tile and row j of the
+    // partial inverse through LDS (double-buffered: one barrier per step); the
+    // multipliers l_ij = a_ij / d_j are formed on the fly and the columns are
+    // scaled by 1 / d_j at the end.
     const DFront f = fr[items[blockIdx.x]];
     double* A = tiles + f.tile_base + tri(f.Mt, k, k) * TT;
-    __shared__ double a[T32][T32 + 1];
-    __shared__ double li[T32][T32 + 1];
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < TT; idx += 256) {
-        int r = idx & 31, c = idx >> 5;
-        a[r][c] = r >= c ? A[c * T32 + r] : 0.0;
+    __shared__ double colj[2][T32], lrow[2][T32], dfin[T32];
+    const int tid = threadIdx.x, i = tid & 31, c0 = tid >> 5;
+    double a[4], l[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = c0 + 8 * e;
+        a[e] = i >= c ? A[c * T32 + i] : 0.0;
+        l[e] = i == c ? 1.0 : 0.0;
     }
-    __syncthreads();
+#pragma unroll
     for (int j = 0; j < T32; ++j) {
-        const double inv = 1.0 / a[j][j];
-        for (int idx = tid; idx < TT; idx += 256) {
-            int i = idx & 31, c = idx >> 5;
-            if (c > j && i >= c) a[i][c] -= a[i][j] * a[c][j] * inv;
+        const int b = j & 1;
+        if (c0 == (j & 7)) colj[b][i] = a[j >> 3];
+        if (i == j) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lrow[b][c0 + 8 * e] = l[e];
         }
         __syncthreads();
-        if (tid > j && tid < T32) a[tid][j] *= inv;
-    }
-    __syncthreads();
-    // inverse of the unit lower triangle, one column per thread
-    if (tid < T32) {
-        const int c = tid;
-        for (int i = 0; i < T32; ++i) li[i][c] = 0.0;
-        li[c][c] = 1.0;
-        for (int i = c + 1; i < T32; ++i) {
-            double s = 0.0;
-            for (int t = c; t < i; ++t) s += a[i][t] * li[t][c];
-            li[i][c] = -s;
+        if (i > j) {
+            const double lij = colj[b][i] / colj[b][j];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = c0 + 8 * e;
+                if (c > j) {
+                    if (i >= c) a[e] -= lij * colj[b][c];
+                } else {
+                    l[e] -= lij * lrow[b][c];
+                }
+            }
         }
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (i == c0 + 8 * e) dfin[i] = a[e];
     __syncthreads();
     double* Li = linv + f.linv_base + (int64_t)k * TT;
-    for (int idx = tid; idx < TT; idx += 256) {
-        int r = idx & 31, c = idx >> 5;
-        A[c * T32 + r] = r > c ? a[r][c] : (r == c ? a[r][r] : 0.0);
-        Li[c * T32 + r] = li[r][c];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = c0 + 8 * e;
+        A[c * T32 + i] = i > c ? a[e] / dfin[c] : (i == c ? a[e] : 0.0);
+        Li[c * T32 + i] = l[e];
     }
     if (tid < T32) {
-        const double d = a[tid][tid];
+        const double d = dfin[tid];
         D[f.d_base + k * T32 + tid] = d;
         const int piv = k * T32 + tid;
         if (piv < f.ns) {
@@ -341,6 +356,13 @@ hipError_t launch_fac_diag(double* tiles, double* linv, double* D, const DFront*
 }
 
 // L_Ik = A_Ik L_kk^-T D_k^-1
+// The 32 x 32 tile products of the panel and update steps run on the FP64
+// matrix cores: wave w of the workgroup owns the 16 x 16 block (w / 2, w % 2)
+// of the result and computes its transpose (16x16x4 operands: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16], result item v of lane l is
+// D[l / 16 + 4 v][l % 16]), so that every operand load and every store of
+// the column-major tiles reads or writes 16 consecutive doubles.
+// L_Ik = A_Ik L_kk^-T D_k^-1, in place
 __global__ __launch_bounds__(256) void k_fac_panel(double* tiles, const double* __restrict__ linv,
                                                    const double* __restrict__ D, const DFront* __restrict__ fr,
                                                    const int32_t* __restrict__ items, int32_t k) {
@@ -348,21 +370,20 @@ __global__ __launch_bounds__(256) void k_fac_panel(double* tiles, const double* 
     const int32_t I = items[2 * blockIdx.x + 1];
     double* A = tiles + f.tile_base + tri(f.Mt, I, k) * TT;
     const double* Li = linv + f.linv_base + (int64_t)k * TT;
-    __shared__ double sa[T32][T32 + 1];
-    __shared__ double sl[T32][T32 + 1];
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < TT; idx += 256) {
-        int r = idx & 31, c = idx >> 5;
-        sa[r][c] = A[c * T32 + r];
-        sl[r][c] = Li[c * T32 + r];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int rb = 16 * (w >> 1), cb = 16 * (w & 1);
+    // T[c][r] = sum_j Linv[c][j] A[r][j] for c in cb + [0, 16), r in rb + [0, 16)
+    dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < T32; k0 += 4) {
+        const int j = k0 + lk;
+        acc = mfma4(Li[j * T32 + cb + li], A[j * T32 + rb + li], acc);
     }
-    __syncthreads();
-    const int r = tid & 31;
-    for (int c = tid >> 5; c < T32; c += 8) {
-        double w = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < T32; ++j) w += sa[r][j] * sl[c][j];
-        A[c * T32 + r] = w / D[f.d_base + k * T32 + c];
+    __syncthreads();   // every wave has read its operands before any tile entry is overwritten
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int c = cb + lk + 4 * v;
+        A[c * T32 + rb + li] = acc[v] / D[f.d_base + k * T32 + c];
     }
 }
 hipError_t launch_fac_panel(double* tiles, const double* linv, const double* D, const DFront* fronts,
@@ -381,21 +402,20 @@ __global__ __launch_bounds__(256) void k_fac_update(double* tiles, const double*
     const double* LI = tiles + f.tile_base + tri(f.Mt, I, k) * TT;
     const double* LJ = tiles + f.tile_base + tri(f.Mt, J, k) * TT;
     double* A = tiles + f.tile_base + tri(f.Mt, I, J) * TT;
-    __shared__ double s1[T32][T32 + 1];
-    __shared__ double s2[T32][T32 + 1];
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < TT; idx += 256) {
-        int r = idx & 31, c = idx >> 5;
-        s1[r][c] = LI[c * T32 + r];
-        s2[r][c] = LJ[c * T32 + r] * D[f.d_base + k * T32 + c];
+    const double* Dk = D + f.d_base + k * T32;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int rb = 16 * (w >> 1), cb = 16 * (w & 1);
+    // T[c][r] = sum_j (d_j L_J[c][j]) L_I[r][j]
+    dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < T32; k0 += 4) {
+        const int j = k0 + lk;
+        acc = mfma4(LJ[j * T32 + cb + li] * Dk[j], LI[j * T32 + rb + li], acc);
     }
-    __syncthreads();
-    const int r = tid & 31;
-    for (int c = tid >> 5; c < T32; c += 8) {
-        double w = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < T32; ++j) w += s1[r][j] * s2[c][j];
-        A[c * T32 + r] -= w;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int c = cb + lk + 4 * v;
+        A[c * T32 + rb + li] -= acc[v];
     }
 }
 hipError_t launch_fac_update(double* tiles, const double* D, const DFront* fronts, const int32_t* items,
@@ -2226,104 +2246,118 @@ __device__ __forceinline__ void bj_pair(int k, int r, int nb, int& I, int& J) {
 template <int B>
 __device__ __forceinline__ int bj_index(int l, int I, int J) { return l < B ? I * B + l : J * B + (l - B); }
 
-// one workgroup per block pair; Q (2b x 2b, row-major, Q[l][c]) of every pair to Qs
+// Jacobi rotation annihilating a_pq of the 2 x 2 block [[app, apq], [apq, aqq]]:
+// the angle |theta| <= pi / 4 with tan 2 theta = 2 a_pq / (a_qq - a_pp), from
+// the half-angle identities cos^2 theta = (1 + cos 2 theta) / 2 and
+// sin theta = sin 2 theta / (2 cos theta) with cos 2 theta = |d| / r,
+// sin 2 theta = sign(d) e / r (d = a_qq - a_pp, e = 2 a_pq, r = hypot(d, e)),
+// which needs two reciprocal square roots and no division.  False (and c = 1,
+// s = 0) when |a_pq| <= max(tol_abs, tol_rel sqrt|a_pp a_qq|), compared in
+// squares.  Every thread that needs a rotation computes it itself from the
+// same three values, so all copies agree bit for bit.
+__device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double tol_abs2, double tol_rel2,
+                                                double& c, double& s) {
+    c = 1.0;
+    s = 0.0;
+    if (!(apq * apq > fmax(tol_abs2, tol_rel2 * fabs(app * aqq)))) return false;
+    const double d = aqq - app, e = 2.0 * apq;
+    const double rinv = rsqrt(d * d + e * e);
+    const double u = 0.5 + 0.5 * (fabs(d) * rinv);
+    const double rc = rsqrt(u);
+    c = u * rc;
+    s = (d >= 0 ? 0.5 : -0.5) * e * rinv * rc;
+    return true;
+}
+
+// One workgroup of b^2 threads per block pair; Q (2b x 2b, row-major, Q[l][c])
+// of every pair to Qs.  A round of the inner cyclic sweep rotates the b
+// disjoint index pairs of the tournament order at once; thread (k1, k2) owns
+// the 2 x 2 block {p_k1, q_k1} x {p_k2, q_k2} of A and the entries
+// {k1, k1 + b} x {p_k2, q_k2} of Q.  It computes both rotations it needs from
+// the round's input, so a round needs one barrier: A is double-buffered (every
+// entry is rewritten each round), Q entries have one owner per round.
 template <int B>
-__global__ __launch_bounds__(256) void k_bj_local(const double* __restrict__ C, int32_t m, int32_t r,
-                                                  double* __restrict__ Qs, const double* __restrict__ normf,
-                                                  double tol_rel, double tol_abs_rel, int32_t max_sweeps,
-                                                  int32_t* rot_count) {
+__global__ __launch_bounds__(B * B) void k_bj_local(const double* __restrict__ C, int32_t m, int32_t r,
+                                                    double* __restrict__ Qs, const double* __restrict__ normf,
+                                                    double tol_rel, double tol_abs_rel, int32_t max_sweeps,
+                                                    int32_t* rot_count) {
     constexpr int W = 2 * B;
-    __shared__ double A[W][W + 1];
+    __shared__ double A[2][W][W + 1];
     __shared__ double Q[W][W + 1];
-    __shared__ double cs[B], sn[B];
-    __shared__ int pp[B], qq[B];
-    __shared__ int nrot, total;
+    __shared__ int total;
     const int nb = m / B;
     int I, J;
     bj_pair(blockIdx.x, r, nb, I, J);
-    const double tol_abs = tol_abs_rel * normf[0];
-    for (int idx = threadIdx.x; idx < W * W; idx += 256) {
+    const double tol_abs2 = tol_abs_rel * normf[0] * tol_abs_rel * normf[0];
+    const double tol_rel2 = tol_rel * tol_rel;
+    const int tid = threadIdx.x, k1 = tid / B, k2 = tid % B;
+    for (int idx = tid; idx < W * W; idx += B * B) {
         const int a = idx / W, c = idx % W;
-        A[a][c] = C[(int64_t)bj_index<B>(a, I, J) * m + bj_index<B>(c, I, J)];
+        A[0][a][c] = C[(int64_t)bj_index<B>(a, I, J) * m + bj_index<B>(c, I, J)];
         Q[a][c] = a == c ? 1.0 : 0.0;
     }
-    if (threadIdx.x == 0) total = 0;
+    if (tid == 0) total = 0;
     __syncthreads();
+    int cur = 0, seen = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
-        if (threadIdx.x == 0) nrot = 0;
-        __syncthreads();
+        int mine = 0;
         for (int rr = 0; rr < W - 1; ++rr) {
-            if (threadIdx.x < B) {
-                const int k = threadIdx.x;
-                const int a = jac_player(k, rr, W), c = jac_player(W - 1 - k, rr, W);
-                const int p = min(a, c), q = max(a, c);
-                const double app = A[p][p], aqq = A[q][q], apq = A[p][q];
-                double cc = 1.0, ss = 0.0;
-                if (fabs(apq) > fmax(tol_abs, tol_rel * sqrt(fabs(app * aqq)))) {
-                    const double tau = (aqq - app) / (2.0 * apq);
-                    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    cc = 1.0 / sqrt(1.0 + t * t);
-                    ss = t * cc;
-                    atomicAdd(&nrot, 1);
-                }
-                cs[k] = cc;
-                sn[k] = ss;
-                pp[k] = p;
-                qq[k] = q;
+            const int a1 = jac_player(k1, rr, W), b1 = jac_player(W - 1 - k1, rr, W);
+            const int a2 = jac_player(k2, rr, W), b2 = jac_player(W - 1 - k2, rr, W);
+            const int p1 = min(a1, b1), q1 = max(a1, b1), p2 = min(a2, b2), q2 = max(a2, b2);
+            const double(*Ac)[W + 1] = A[cur];
+            double(*An)[W + 1] = A[cur ^ 1];
+            const double d1p = Ac[p1][p1], d1q = Ac[q1][q1], o1 = Ac[p1][q1];
+            const double d2p = Ac[p2][p2], d2q = Ac[q2][q2], o2 = Ac[p2][q2];
+            const double x00 = Ac[p1][p2], x01 = Ac[p1][q2], x10 = Ac[q1][p2], x11 = Ac[q1][q2];
+            const double u0 = Q[k1][p2], v0 = Q[k1][q2], u1 = Q[k1 + B][p2], v1 = Q[k1 + B][q2];
+            double c1, s1, c2, s2;
+            const bool rot1 = jacobi_rotation(d1p, d1q, o1, tol_abs2, tol_rel2, c1, s1);
+            jacobi_rotation(d2p, d2q, o2, tol_abs2, tol_rel2, c2, s2);
+            const double t00 = c1 * x00 - s1 * x10, t01 = c1 * x01 - s1 * x11;
+            const double t10 = s1 * x00 + c1 * x10, t11 = s1 * x01 + c1 * x11;
+            An[p1][p2] = c2 * t00 - s2 * t01;
+            An[q1][q2] = s2 * t10 + c2 * t11;
+            if (k1 == k2 && rot1) {
+                ++mine;
+                An[p1][q2] = 0.0;
+                An[q1][p2] = 0.0;
+            } else {
+                An[p1][q2] = s2 * t00 + c2 * t01;
+                An[q1][p2] = c2 * t10 - s2 * t11;
             }
-            __syncthreads();
-            // A <- J^T A J: the pairs of one round are disjoint, so every 2 x 2
-            // block {p1, q1} x {p2, q2} is read and written by one thread only
-            for (int blk = threadIdx.x; blk < B * B; blk += 256) {
-                const int k1 = blk / B, k2 = blk % B;
-                const double s1 = sn[k1], s2 = sn[k2];
-                if (s1 == 0.0 && s2 == 0.0) continue;
-                const double c1 = cs[k1], c2 = cs[k2];
-                const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-                const double x00 = A[p1][p2], x01 = A[p1][q2], x10 = A[q1][p2], x11 = A[q1][q2];
-                const double t00 = c1 * x00 - s1 * x10, t01 = c1 * x01 - s1 * x11;
-                const double t10 = s1 * x00 + c1 * x10, t11 = s1 * x01 + c1 * x11;
-                A[p1][p2] = c2 * t00 - s2 * t01;
-                A[q1][q2] = s2 * t10 + c2 * t11;
-                if (k1 == k2) {
-                    A[p1][q2] = 0.0;
-                    A[q1][p2] = 0.0;
-                } else {
-                    A[p1][q2] = s2 * t00 + c2 * t01;
-                    A[q1][p2] = c2 * t10 - s2 * t11;
-                }
-            }
-            // Q <- Q J
-            for (int idx = threadIdx.x; idx < B * W; idx += 256) {
-                const int k = idx % B, a = idx / B;
-                const double ss = sn[k];
-                if (ss == 0.0) continue;
-                const double cc = cs[k];
-                const double u = Q[a][pp[k]], v = Q[a][qq[k]];
-                Q[a][pp[k]] = u * cc - v * ss;
-                Q[a][qq[k]] = u * ss + v * cc;
-            }
+            Q[k1][p2] = u0 * c2 - v0 * s2;
+            Q[k1][q2] = u0 * s2 + v0 * c2;
+            Q[k1 + B][p2] = u1 * c2 - v1 * s2;
+            Q[k1 + B][q2] = u1 * s2 + v1 * c2;
+            cur ^= 1;
             __syncthreads();
         }
-        if (threadIdx.x == 0) total += nrot;
+        if (mine) atomicAdd(&total, mine);
         __syncthreads();
-        if (nrot == 0) break;
+        const int now = total;
+        if (now == seen) break;
+        seen = now;
     }
     double* Qo = Qs + (int64_t)blockIdx.x * W * W;
-    for (int idx = threadIdx.x; idx < W * W; idx += 256) Qo[idx] = Q[idx / W][idx % W];
-    if (threadIdx.x == 0 && total) atomicAdd(rot_count, total);
+    for (int idx = tid; idx < W * W; idx += B * B) Qo[idx] = Q[idx / W][idx % W];
+    if (tid == 0 && seen) atomicAdd(rot_count, seen);
 }
 
 // C <- J^T C J on every (pair, pair') tile (pair <= pair'), V <- V J on row
-// chunks; first npairs*(npairs+1)/2 workgroups do C, the rest V
-template <int B>
+// chunks; first npairs*(npairs+1)/2 workgroups do C, the rest V.  The 2b x 2b
+// products (b = 16) run on the FP64 matrix cores: wave w of the workgroup owns
+// the 16 x 16 output tile (w / 2, w % 2).  16x16x4 operand layout: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result item v of lane l is
+// D[l / 16 + 4 v][l % 16].
 __global__ __launch_bounds__(256) void k_bj_apply(double* C, double* V, int32_t m, int32_t r,
                                                   const double* __restrict__ Qs) {
-    constexpr int W = 2 * B;
-    __shared__ double X[W][W + 1], Q1[W][W + 1], Q2[W][W + 1];
+    constexpr int B = 16, W = 32;
+    __shared__ double X[W][W + 1];
     const int nb = m / B, np = nb / 2;
     const int64_t ctiles = (int64_t)np * (np + 1) / 2;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4, ta = w >> 1, tc = w & 1;
     if (blockIdx.x < ctiles) {
         int t = blockIdx.x, P = 0;
         while (t >= np - P) { t -= np - P; ++P; }
@@ -2333,42 +2367,34 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* C, double* V, int32_t 
         bj_pair(P2, r, nb, I2, J2);
         const double* q1 = Qs + (int64_t)P * W * W;
         const double* q2 = Qs + (int64_t)P2 * W * W;
-        for (int idx = tid; idx < W * W; idx += 256) {
-            const int a = idx / W, c = idx % W;
-            X[a][c] = C[(int64_t)bj_index<B>(a, I1, J1) * m + bj_index<B>(c, I2, J2)];
-            Q1[a][c] = q1[idx];
-            Q2[a][c] = q2[idx];
-        }
-        __syncthreads();
-        // T = Q1^T X  (into registers, then X <- T)
-        constexpr int PER = W * W / 256;
-        double tv[PER];
+        // T = Q1^T X with X the (pair P rows) x (pair P2 columns) block of C
+        const int64_t gcol = bj_index<B>(tc * 16 + li, I2, J2);
+        dbl4 acc = dbl4{0, 0, 0, 0};
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + 256 * e, a = idx / W, c = idx % W;
-            double v = 0;
-            for (int l = 0; l < W; ++l) v += Q1[l][a] * X[l][c];
-            tv[e] = v;
+        for (int ks = 0; ks < W / 4; ++ks) {
+            const int l = 4 * ks + lk;
+            const double a = q1[l * W + ta * 16 + li];
+            const double b = C[(int64_t)bj_index<B>(l, I1, J1) * m + gcol];
+            acc = mfma4(a, b, acc);
         }
-        __syncthreads();
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + 256 * e;
-            X[idx / W][idx % W] = tv[e];
+        for (int v = 0; v < 4; ++v) X[ta * 16 + lk + 4 * v][tc * 16 + li] = acc[v];
+        __syncthreads();
+        // out = T Q2, written to the tile and its mirror
+        acc = dbl4{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < W / 4; ++ks) {
+            const int l = 4 * ks + lk;
+            acc = mfma4(X[ta * 16 + li][l], q2[l * W + tc * 16 + li], acc);
         }
-        __syncthreads();
-        // out = T Q2
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + 256 * e, a = idx / W, c = idx % W;
-            double v = 0;
-            for (int l = 0; l < W; ++l) v += X[a][l] * Q2[l][c];
-            const int gi = bj_index<B>(a, I1, J1), gj = bj_index<B>(c, I2, J2);
-            C[(int64_t)gi * m + gj] = v;
-            C[(int64_t)gj * m + gi] = v;
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gi = bj_index<B>(ta * 16 + lk + 4 * v, I1, J1);
+            C[gi * m + gcol] = acc[v];
+            C[gcol * m + gi] = acc[v];
         }
     } else {
-        // V rows [row0, row0 + W) times Q of pair P
+        // V rows [row0, row0 + W) times Q of pair P (m is a multiple of W)
         const int64_t item = blockIdx.x - ctiles;
         const int P = (int)(item % np);
         const int64_t row0 = (item / np) * W;
@@ -2377,42 +2403,55 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* C, double* V, int32_t 
         const double* q1 = Qs + (int64_t)P * W * W;
         for (int idx = tid; idx < W * W; idx += 256) {
             const int a = idx / W, c = idx % W;
-            const int64_t row = row0 + a;
-            X[a][c] = row < m ? V[row * m + bj_index<B>(c, I1, J1)] : 0.0;
-            Q1[a][c] = q1[idx];
+            X[a][c] = V[(row0 + a) * m + bj_index<B>(c, I1, J1)];
         }
         __syncthreads();
-        constexpr int PER = W * W / 256;
+        dbl4 acc = dbl4{0, 0, 0, 0};
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + 256 * e, a = idx / W, c = idx % W;
-            const int64_t row = row0 + a;
-            double v = 0;
-            for (int l = 0; l < W; ++l) v += X[a][l] * Q1[l][c];
-            if (row < m) V[row * m + bj_index<B>(c, I1, J1)] = v;
+        for (int ks = 0; ks < W / 4; ++ks) {
+            const int l = 4 * ks + lk;
+            acc = mfma4(X[ta * 16 + li][l], q1[l * W + tc * 16 + li], acc);
         }
+        const int64_t gcol = bj_index<B>(tc * 16 + li, I1, J1);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) V[(row0 + ta * 16 + lk + 4 * v) * m + gcol] = acc[v];
     }
+}
+
+// Number of off-diagonal entries of the symmetric m x m matrix C that the
+// rotation threshold of k_bj_local would still act on; zero means that a
+// further sweep would not rotate at all.
+__global__ void k_bj_offcount(const double* __restrict__ C, int32_t m, const double* __restrict__ normf, double tol_rel,
+                              double tol_abs_rel, int32_t* count) {
+    const double tol_abs2 = tol_abs_rel * normf[0] * tol_abs_rel * normf[0];
+    const double tol_rel2 = tol_rel * tol_rel;
+    int n = 0;
+    const int64_t tot = (int64_t)m * m;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = (int32_t)(t / m), q = (int32_t)(t % m);
+        if (p >= q) continue;
+        const double apq = C[t];
+        if (apq * apq > fmax(tol_abs2, tol_rel2 * fabs(C[(int64_t)p * m + p] * C[(int64_t)q * m + q]))) ++n;
+    }
+    if (n) atomicAdd(count, n);
+}
+hipError_t launch_bj_offcount(const double* C, int32_t m, const double* normf, double tol_rel, double tol_abs_rel,
+                              int32_t* count, hipStream_t s) {
+    k_bj_offcount<<<grid_for((int64_t)m * m, 256), 256, 0, s>>>(C, m, normf, tol_rel, tol_abs_rel, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_bj_round(int b, double* C, double* V, int32_t m, int32_t round, double* Qs, const double* normf,
                            double tol_rel, double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count,
                            hipStream_t s) {
+    if (b != 16 || m % (2 * b) != 0) return hipErrorInvalidValue;
     const int nb = m / b, np = nb / 2;
     const int64_t ctiles = (int64_t)np * (np + 1) / 2;
-    const int64_t vitems = cdiv(m, 2 * b) * np;
-    if (b == 32) {
-        k_bj_local<32><<<np, 256, 0, s>>>(C, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        k_bj_apply<32><<<(unsigned)(ctiles + vitems), 256, 0, s>>>(C, V, m, round, Qs);
-    } else if (b == 16) {
-        k_bj_local<16><<<np, 256, 0, s>>>(C, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        k_bj_apply<16><<<(unsigned)(ctiles + vitems), 256, 0, s>>>(C, V, m, round, Qs);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    const int64_t vitems = (int64_t)(m / (2 * b)) * np;
+    k_bj_local<16><<<np, 256, 0, s>>>(C, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_bj_apply<<<(unsigned)(ctiles + vitems), 256, 0, s>>>(C, V, m, round, Qs);
     return hipGetLastError();
 }
 
