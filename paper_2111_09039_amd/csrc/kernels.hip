@@ -22,6 +22,7 @@ namespace hsim {
 namespace {
 constexpr int T32 = 32;
 constexpr int TT = T32 * T32;
+constexpr int NXCD = 8;           // XCDs; workgroups are dispatched round-robin over them
 
 __device__ __forceinline__ int64_t tri(int32_t Mt, int32_t I, int32_t J) {
     return (int64_t)J * Mt - (int64_t)J * (J - 1) / 2 + (I - J);
@@ -685,6 +686,17 @@ __device__ __forceinline__ void frag_mm(const double (&a)[8], const dbl4 (&y)[CT
         }
 }
 
+// workgroup -> (front, column group) of the wave-level solves: workgroups are
+// dispatched round-robin over the 8 XCDs, so the column groups of one front
+// are given ids 8 apart (same XCD, dispatched together) and share the
+// front's factor tiles in that XCD's L2.  False for the padding workgroups.
+__device__ __forceinline__ bool wsolve_item(int32_t nfronts, int32_t groups, int32_t& front, int32_t& grp) {
+    const int32_t b = (int32_t)blockIdx.x, xcd = b & (NXCD - 1), slot = b / NXCD;
+    grp = slot % groups;
+    front = (slot / groups) * NXCD + xcd;
+    return front < nfronts;
+}
+
 // widest workgroup (waves) of the wave-level solves for NT pivot row tiles
 template <int NT>
 struct WsolveWaves {
@@ -702,15 +714,17 @@ struct WsolveCols {
 // column tiles of 16.
 template <class TF, int NT>
 __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
-    const TF* __restrict__ tiles, const TF* __restrict__ linv, const DFront* __restrict__ fr, int32_t f0, double* X,
+    const TF* __restrict__ tiles, const TF* __restrict__ linv, const DFront* __restrict__ fr, int32_t f0, int32_t nfronts, int32_t groups, double* X,
     int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu, const int32_t* __restrict__ gat,
     int32_t gw, const double* __restrict__ mdiag) {
     constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS * CT;
+    int32_t fi, grp;
+    if (!wsolve_item(nfronts, groups, fi, grp)) return;
+    const int32_t cbase = col0 + (grp * wpg + w) * WCOLS * CT;
     const int32_t cend = col0 + ncols;
     if (cbase >= cend) return;
-    const DFront f = fr[f0 + blockIdx.x];
+    const DFront f = fr[f0 + fi];
     const bool gath = (f.flags & DFRONT_GATHER) != 0;
     const int nt = (f.ns + 15) >> 4;
     dbl4 y[CT][NT];
@@ -865,14 +879,16 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
 template <class TF, int NT>
 __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_bwd(
     const TF* __restrict__ tilesT, const TF* __restrict__ linvT, const TF* __restrict__ D,
-    const DFront* __restrict__ fr, int32_t f0, double* X, int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg,
+    const DFront* __restrict__ fr, int32_t f0, int32_t nfronts, int32_t groups, double* X, int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg,
     const int32_t* __restrict__ rows, int apply_dinv) {
     constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS * CT;
+    int32_t fi, grp;
+    if (!wsolve_item(nfronts, groups, fi, grp)) return;
+    const int32_t cbase = col0 + (grp * wpg + w) * WCOLS * CT;
     const int32_t cend = col0 + ncols;
     if (cbase >= cend) return;
-    const DFront f = fr[f0 + blockIdx.x];
+    const DFront f = fr[f0 + fi];
     const int nt = (f.ns + 15) >> 4;
     const int32_t* frows = rows + f.rows_off;
     const int mt = (f.mu + 15) >> 4;
@@ -1056,13 +1072,13 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
     TF* ub = reinterpret_cast<TF*>(ubuf);
 #define HSIM_WS(NT)                                                                                              \
     wsolve_shape(ncols, WsolveWaves<NT>::value, WCOLS * WsolveCols<NT>::value, wpg, groups);                                                     \
-    const dim3 grid((unsigned)(f1 - f0), (unsigned)groups), block((unsigned)(64 * wpg));                          \
+    const dim3 grid((unsigned)(cdiv(f1 - f0, NXCD) * NXCD * groups)), block((unsigned)(64 * wpg));              \
     if (fwd)                                                                                                      \
-        k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, X, ldx, col0, ncols, wpg, ub, ldu,  \
-                                                    gat, gw, mdiag);                                              \
+        k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, f1 - f0, groups, X, ldx, col0,      \
+                                                    ncols, wpg, ub, ldu, gat, gw, mdiag);                         \
     else                                                                                                          \
-        k_wsolve_bwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, D, fronts, f0, X, ldx, col0, ncols, wpg, rows,  \
-                                                    apply_dinv ? 1 : 0);
+        k_wsolve_bwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, D, fronts, f0, f1 - f0, groups, X, ldx, col0,   \
+                                                    ncols, wpg, rows, apply_dinv ? 1 : 0);
     if (ns_pad_max <= 32) { HSIM_WS(2) }
     else if (ns_pad_max <= 64) { HSIM_WS(4) }
     else if (ns_pad_max <= 128) { HSIM_WS(8) }
@@ -1561,7 +1577,6 @@ constexpr int GT = 64;            // output block edge
 constexpr int GRAM_CHUNK = 4096;  // rows per workgroup
 constexpr int GROWS = 32;         // rows per LDS stage
 constexpr int GLD = GT + 8;       // LDS row stride (elements)
-constexpr int NXCD = 8;
 
 
 // workgroup id -> (chunk, pair) with the pairs of a chunk on one XCD
@@ -1710,22 +1725,32 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
 }
 
 // FP64 Gram for q <= 160 (nt <= 10 column tiles of 16): persistent, one
-// workgroup of 2 ceil(nt / 2) waves per CU forms every upper 16 x 16 tile of
-// both products for its rows, so Psi is read once.  Wave w takes product
-// w / h (h = ceil(nt / 2); 0: S, 1: M) and the tile rows Ia = w % h and
-// Ib = nt - 1 - Ia with all their upper tiles: nt + 1 tiles per wave.  Rows
-// go through LDS 16 at a time (Psi, S Psi, M Psi or m), the next 16 are
-// loaded into registers meanwhile.  Output: per workgroup and product the
-// upper tiles in row-major tile order, each tile row-major.
+// workgroup of 8 waves per CU forms every upper 16 x 16 tile of both products
+// for its rows, so Psi is read once.  Waves 0-3 take Psi^T S Psi, waves 4-7
+// Psi^T M Psi; wave slot j of 14 is upper tile 14 (w mod 4) + j in row-major
+// tile order (nup = nt (nt + 1) / 2 <= 55 tiles per product), so the matrix
+// cores of the four SIMDs get equal work.  Rows go through LDS 16 at a time
+// (double-buffered: Psi, S Psi and M Psi or m), the next 16 are loaded into
+// registers meanwhile; within a stage the operands of the next 7 slots are
+// read from LDS while the current 7 products run.  Output: per workgroup and
+// product the upper tiles in row-major tile order, each tile row-major.
 namespace {
 constexpr int GA_R = 16;          // rows per stage
 constexpr int GA_LD = 168;        // LDS row stride (doubles)
 constexpr int GA_MAXT = 10;       // column tiles
-constexpr int GA_THREADS = 640;
+constexpr int GA_W = 8;           // waves
+constexpr int GA_S = 14;          // tile slots per wave
+constexpr int GA_H = GA_S / 2;    // slots per operand batch
+constexpr int GA_THREADS = 64 * GA_W;
 constexpr int GA_MAX_WG = 1024;
+static_assert(GA_W / 2 * GA_S >= GA_MAXT * (GA_MAXT + 1) / 2, "slots must cover the upper tiles");
+template <bool HAS_M>
+constexpr int gram_all_buf() {   // doubles per stage buffer
+    return (HAS_M ? 3 : 2) * GA_R * GA_LD + GA_R;
+}
 template <bool HAS_M>
 constexpr size_t gram_all_lds() {
-    return ((size_t)(HAS_M ? 3 : 2) * GA_R * GA_LD + GA_R) * sizeof(double);
+    return 2 * (size_t)gram_all_buf<HAS_M>() * sizeof(double);
 }
 }  // namespace
 
@@ -1741,21 +1766,34 @@ __global__ __launch_bounds__(GA_THREADS) void k_gram_all(const double* __restric
                                                          const double* __restrict__ MPsi,
                                                          const double* __restrict__ mdiag, int64_t n, int32_t q,
                                                          int64_t ld, double* __restrict__ partial) {
+    constexpr int BUF = gram_all_buf<HAS_M>();
+    constexpr int MAT = GA_R * GA_LD;   // doubles per staged matrix
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double(*Ps)[GA_LD] = reinterpret_cast<double(*)[GA_LD]>(smem_raw);
-    double(*Ss)[GA_LD] = Ps + GA_R;
-    double(*Ms)[GA_LD] = Ss + GA_R;   // HAS_M only
-    double* mv = &(HAS_M ? Ms : Ss)[GA_R][0];   // m of the staged rows (finest level)
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int nt = (q + 15) >> 4, h = (nt + 1) >> 1;
-    const int64_t nup = (int64_t)nt * (nt + 1) / 2;
-    const bool active = w < 2 * h;
-    const int prod = w / h, Ia = w % h, Ib = nt - 1 - Ia;
-    const int na = nt - Ia;                       // tiles of row Ia
-    const int nb2 = Ib != Ia ? nt - Ib : 0;       // tiles of row Ib
+    double* lds = reinterpret_cast<double*>(smem_raw);
+    const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+    const int nt = (q + 15) >> 4, nup = nt * (nt + 1) / 2;
+    const int prod = w >= GA_W / 2;
+    // slot j: LDS offsets of its A (Psi columns of tile row I) and B (S Psi,
+    // M Psi or Psi columns of tile column J) operands
+    int aoff[GA_S], boff[GA_S], valid = 0;
+#pragma unroll
+    for (int j = 0; j < GA_S; ++j) {
+        int t = GA_S * (w - prod * (GA_W / 2)) + j;
+        const bool v = t < nup;
+        t = v ? t : 0;
+        int I = 0;
+        while (t >= nt - I) {
+            t -= nt - I;
+            ++I;
+        }
+        aoff[j] = 16 * I;
+        boff[j] = 16 * (I + t) + (prod == 0 ? MAT : (HAS_M ? 2 * MAT : 0));
+        valid |= (int)v << j;
+    }
     const int64_t nblk = (n + GA_R - 1) / GA_R;
     const int64_t my_blocks = blockIdx.x < nblk ? (nblk - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
-    constexpr int PE = (GA_R * GA_MAXT * 16 + GA_THREADS - 1) / GA_THREADS;   // 4
+    constexpr int PE = (GA_R * GA_MAXT * 16 + GA_THREADS - 1) / GA_THREADS;   // 5
     double rp[PE], rs[PE], rm[PE], rmd = 0.0;
     auto fetch = [&](int64_t j) {
         const int64_t r0 = (blockIdx.x + j * gridDim.x) * GA_R;
@@ -1770,56 +1808,64 @@ __global__ __launch_bounds__(GA_THREADS) void k_gram_all(const double* __restric
         }
         if (!HAS_M && tid < GA_R) rmd = r0 + tid < n ? mdiag[r0 + tid] : 0.0;
     };
-    dbl4 acc[GA_MAXT + 1];
-#pragma unroll
-    for (int j = 0; j < GA_MAXT + 1; ++j) acc[j] = dbl4{0, 0, 0, 0};
-    if (my_blocks > 0) fetch(0);
-    for (int64_t jb = 0; jb < my_blocks; ++jb) {
+    auto stash = [&](int b) {
+        double* P = lds + b * BUF;
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
             const int idx = tid + GA_THREADS * e;
             if (idx < GA_R * GA_MAXT * 16) {
                 const int r = idx / (GA_MAXT * 16), c = idx % (GA_MAXT * 16);
-                Ps[r][c] = rp[e];
-                Ss[r][c] = rs[e];
-                if (HAS_M) Ms[r][c] = rm[e];
+                P[r * GA_LD + c] = rp[e];
+                P[MAT + r * GA_LD + c] = rs[e];
+                if (HAS_M) P[2 * MAT + r * GA_LD + c] = rm[e];
             }
         }
-        if (!HAS_M && tid < GA_R) mv[tid] = rmd;
-        __syncthreads();
-        if (jb + 1 < my_blocks) fetch(jb + 1);
-        if (active) {
-            const double(*Bsrc)[GA_LD] = prod == 0 ? Ss : (HAS_M ? Ms : Ps);
-#pragma unroll 1
-            for (int kk = 0; kk < GA_R; kk += 4) {
-                const int kr = kk + (lane >> 4);
-                const double scale = (prod == 1 && !HAS_M) ? mv[kr] : 1.0;
-                const double aa = Ps[kr][16 * Ia + (lane & 15)];
-                const double ab = Ps[kr][16 * Ib + (lane & 15)];
+        if (!HAS_M && tid < GA_R) P[2 * MAT + tid] = rmd;
+    };
+    dbl4 acc[GA_S];
 #pragma unroll
-                for (int j = 0; j < GA_MAXT + 1; ++j) {
-                    const bool first = j < na;
-                    const bool valid = first || j - na < nb2;
-                    if (valid) {
-                        const int J = first ? Ia + j : Ib + (j - na);
-                        const double b = Bsrc[kr][16 * J + (lane & 15)] * scale;
-                        acc[j] = mfma4(first ? aa : ab, b, acc[j]);
-                    }
-                }
+    for (int j = 0; j < GA_S; ++j) acc[j] = dbl4{0, 0, 0, 0};
+    if (my_blocks > 0) {
+        fetch(0);
+        stash(0);
+    }
+    __syncthreads();
+    for (int64_t jb = 0; jb < my_blocks; ++jb) {
+        if (jb + 1 < my_blocks) fetch(jb + 1);
+        const double* P = lds + (jb & 1) * BUF;
+        // Psi^T M Psi with diagonal M: B operand scaled by m of its row
+        const bool scale = !HAS_M && prod == 1;
+        double a0[GA_H], b0[GA_H], a1[GA_H], b1[GA_H];
+        auto operands = [&](int kk, int h, double(&av)[GA_H], double(&bv)[GA_H]) {
+            const double* Pr = P + (kk + lk) * GA_LD + li;
+#pragma unroll
+            for (int j = 0; j < GA_H; ++j) {
+                av[j] = Pr[aoff[h * GA_H + j]];
+                bv[j] = Pr[boff[h * GA_H + j]];
             }
+        };
+        operands(0, 0, a0, b0);
+#pragma unroll
+        for (int kk = 0; kk < GA_R; kk += 4) {
+            const double sc = scale ? P[2 * MAT + kk + lk] : 1.0;
+            operands(kk, 1, a1, b1);
+#pragma unroll
+            for (int j = 0; j < GA_H; ++j) acc[j] = mfma4(a0[j], b0[j] * sc, acc[j]);
+            if (kk + 4 < GA_R) operands(kk + 4, 0, a0, b0);
+#pragma unroll
+            for (int j = 0; j < GA_H; ++j) acc[GA_H + j] = mfma4(a1[j], b1[j] * sc, acc[GA_H + j]);
         }
+        if (jb + 1 < my_blocks) stash((jb + 1) & 1);
         __syncthreads();
     }
-    if (!active) return;
     double* out = partial + ((int64_t)blockIdx.x * 2 + prod) * nup * 256;
 #pragma unroll
-    for (int j = 0; j < GA_MAXT + 1; ++j) {
-        const bool first = j < na;
-        if (!(first || j - na < nb2)) continue;
-        const int I = first ? Ia : Ib, J = first ? Ia + j : Ib + (j - na);
+    for (int j = 0; j < GA_S; ++j) {
+        if (!((valid >> j) & 1)) continue;
+        const int I = aoff[j] >> 4, J = ((boff[j] - (prod == 0 ? MAT : (HAS_M ? 2 * MAT : 0))) >> 4);
         const int64_t t = (int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) out[t * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[j][v];
+        for (int v = 0; v < 4; ++v) out[t * 256 + (lk + 4 * v) * 16 + li] = acc[j][v];
     }
 }
 
@@ -1905,22 +1951,47 @@ hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi
 // partial sums of the residual numerator and of the normalisation for the
 // first nres columns (S Phi is formed only for those).
 // Persistent grid: one workgroup of 8 waves per CU walks 64-row blocks with
-// stride gridDim.x; wave w takes rows 16 (w / 2) .. +16 and column tiles
-// 5 (w % 2) .. +5 of the 160 columns of blockIdx.y.  The stages (block,
-// 32 contraction columns) go through LDS -- Psi, S Psi, M Psi rows and the
-// Phibar chunk shared by all waves -- and the next stage is loaded into
-// registers while the current one is multiplied.
+// stride gridDim.x; wave w takes rows 16 (w / 2) .. +16 and a set of the
+// 16-column tiles of the 160 columns of blockIdx.y chosen so that both waves
+// of a row tile issue the same number of matrix-core products (a tile with
+// residual columns costs one product more).  The stages (block, 32
+// contraction columns, 16 with M Psi) go through LDS, double-buffered -- Psi, S Psi, M Psi
+// rows and the Phibar chunk shared by all waves -- the next stage is loaded
+// into registers while the current one is multiplied, and within a stage the
+// operands of the next 4 contraction columns are read while the current
+// products run.
 namespace {
 constexpr int RZ_RB = 64;            // rows per block
-constexpr int RZ_K = 32;             // contraction columns per stage
-constexpr int RZ_LD = RZ_K + 4;      // LDS row stride of the row stage
+constexpr int RZ_KMAX = 32;          // contraction columns per stage (16 with M Psi: LDS)
+constexpr int RZ_LD = RZ_KMAX + 1;   // LDS row stride of the row stage (odd: conflict-free A reads)
 constexpr int RZ_COLS = 160;         // output columns per workgroup
-constexpr int RZ_BLD = RZ_COLS + 8;  // LDS row stride of the Phibar stage
+constexpr int RZ_BLD = RZ_COLS;      // LDS row stride of the Phibar stage
 constexpr int RZ_THREADS = 512;
 constexpr int RZ_MAX_WG = 2048;      // persistent workgroups at most (partial-sum rows)
+constexpr int RZ_SL = 5;             // column tiles per wave at most
 template <bool HAS_M>
-constexpr size_t ritz_lds() {
-    return ((size_t)(HAS_M ? 3 : 2) * RZ_RB * RZ_LD + (size_t)RZ_K * RZ_BLD) * sizeof(double);
+constexpr int ritz_k() {             // contraction columns per stage
+    return HAS_M ? 16 : 32;
+}
+template <bool HAS_M>
+constexpr int ritz_buf() {           // doubles per stage buffer
+    return (HAS_M ? 3 : 2) * RZ_RB * RZ_LD + ritz_k<HAS_M>() * RZ_BLD;
+}
+template <bool HAS_M>
+constexpr size_t ritz_lds() {   // two stage buffers + the per-row-tile column sums
+    return (2 * (size_t)ritz_buf<HAS_M>() + 4 * 2 * RZ_COLS) * sizeof(double);
+}
+// column tiles [0, ns) have residual columns; wave half 0 takes tiles
+// [0, a) and [ns, ns + x), half 1 the rest, with x balancing the products
+// (cS per residual tile, cP per other tile).  Returns false when a half would
+// get more than RZ_SL tiles.
+__host__ __device__ inline bool ritz_split(int nt, int ns, bool has_m, int& a, int& x) {
+    const int cS = has_m ? 3 : 2, cP = has_m ? 2 : 1;
+    a = (ns + 1) / 2;
+    const int b = ns - a, po = nt - ns;
+    x = ((b - a) * cS + po * cP + cP) / (2 * cP);
+    x = x < 0 ? 0 : (x > po ? po : x);
+    return a + x <= RZ_SL && b + po - x <= RZ_SL;
 }
 }  // namespace
 
@@ -1935,21 +2006,38 @@ __global__ __launch_bounds__(RZ_THREADS) void k_ritz_mfma(const double* __restri
                                                           int64_t n, int32_t q, int64_t ld, double* __restrict__ Phi,
                                                           double* __restrict__ MPhi, double* __restrict__ partial,
                                                           int minv_norm, int32_t nres) {
+    constexpr int RZ_K = ritz_k<HAS_M>();
+    constexpr int BUF = ritz_buf<HAS_M>();
+    constexpr int AM = RZ_RB * RZ_LD;                      // doubles per staged row matrix
+    constexpr int BOFF = (HAS_M ? 3 : 2) * AM;             // Phibar chunk within a buffer
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double(*Ps)[RZ_LD] = reinterpret_cast<double(*)[RZ_LD]>(smem_raw);
-    double(*Ss)[RZ_LD] = Ps + RZ_RB;
-    double(*Ms)[RZ_LD] = Ss + RZ_RB;   // HAS_M only
-    double(*Bs)[RZ_BLD] = reinterpret_cast<double(*)[RZ_BLD]>(&(HAS_M ? Ms : Ss)[RZ_RB][0]);
-    double(*red)[2][RZ_COLS] = reinterpret_cast<double(*)[2][RZ_COLS]>(smem_raw);   // after the last stage
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double* lds = reinterpret_cast<double*>(smem_raw);
+    // residual numerator / normalisation sums per row tile and column, each
+    // entry owned by one lane
+    double(*red)[2][RZ_COLS] = reinterpret_cast<double(*)[2][RZ_COLS]>(lds + 2 * BUF);
+    const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int wr = w >> 1, wc = w & 1;
+    for (int i = tid; i < 4 * 2 * RZ_COLS; i += RZ_THREADS) (&red[0][0][0])[i] = 0.0;
     const int col0 = blockIdx.y * RZ_COLS;
+    const int ncol = min(RZ_COLS, q - col0);
+    const int nt = (ncol + 15) >> 4;
+    const int ns = nres > col0 ? min(nt, (nres - col0 + 15) >> 4) : 0;
+    int sa, sx;
+    ritz_split(nt, ns, HAS_M, sa, sx);
+    // this wave's column tiles: two runs [t1, t1 + c1) and [t2, t2 + c2)
+    const int t1 = wc ? sa : 0, c1 = wc ? ns - sa : sa;
+    const int t2 = wc ? ns + sx : ns, c2 = wc ? nt - ns - sx : sx;
+    const int ntw = min(RZ_SL, c1 + c2);
+    int tile[RZ_SL];
+#pragma unroll
+    for (int u = 0; u < RZ_SL; ++u) tile[u] = u < c1 ? t1 + u : t2 + (u - c1);
     const int64_t nblk = (n + RZ_RB - 1) / RZ_RB;
     const int nk = (q + RZ_K - 1) / RZ_K;
     const int64_t my_blocks = blockIdx.x < nblk ? (nblk - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
     const int64_t nst = my_blocks * nk;
-    constexpr int PA = RZ_RB * RZ_K / RZ_THREADS;     // 4
-    constexpr int PB = RZ_K * RZ_COLS / RZ_THREADS;   // 10
+    constexpr int PA = RZ_RB * RZ_K / RZ_THREADS;     // row-stage values per thread
+    constexpr int PB = RZ_K * RZ_COLS / RZ_THREADS;   // Phibar values per thread
     double ra[PA], rs[PA], rm[PA], rb[PB];
     auto fetch = [&](int64_t st) {
         const int64_t r0 = (blockIdx.x + (st / nk) * gridDim.x) * RZ_RB;
@@ -1966,98 +2054,118 @@ __global__ __launch_bounds__(RZ_THREADS) void k_ritz_mfma(const double* __restri
 #pragma unroll
         for (int e = 0; e < PB; ++e) {
             const int idx = tid + RZ_THREADS * e, kk = idx / RZ_COLS, c = idx % RZ_COLS;
-            rb[e] = (k0 + kk < q && col0 + c < q) ? Phibar[(int64_t)(k0 + kk) * q + col0 + c] : 0.0;
+            rb[e] = (k0 + kk < q && c < ncol) ? Phibar[(int64_t)(k0 + kk) * q + col0 + c] : 0.0;
         }
     };
-    bool sres[5];   // this wave's column tile u has residual columns
-#pragma unroll
-    for (int u = 0; u < 5; ++u) sres[u] = col0 + (wc * 5 + u) * 16 < nres;
-    dbl4 aP[5], aS[5], aM[5];
-#pragma unroll
-    for (int u = 0; u < 5; ++u) aP[u] = aS[u] = aM[u] = dbl4{0, 0, 0, 0};
-    double num[5] = {0, 0, 0, 0, 0}, den[5] = {0, 0, 0, 0, 0};
-    if (nst > 0) fetch(0);
-    for (int64_t st = 0; st < nst; ++st) {
+    auto stash = [&](int b) {
+        double* L = lds + b * BUF;
 #pragma unroll
         for (int e = 0; e < PA; ++e) {
             const int idx = tid + RZ_THREADS * e, r = idx / RZ_K, kk = idx % RZ_K;
-            Ps[r][kk] = ra[e];
-            Ss[r][kk] = rs[e];
-            if (HAS_M) Ms[r][kk] = rm[e];
+            L[r * RZ_LD + kk] = ra[e];
+            L[AM + r * RZ_LD + kk] = rs[e];
+            if (HAS_M) L[2 * AM + r * RZ_LD + kk] = rm[e];
         }
 #pragma unroll
         for (int e = 0; e < PB; ++e) {
             const int idx = tid + RZ_THREADS * e;
-            Bs[idx / RZ_COLS][idx % RZ_COLS] = rb[e];
+            L[BOFF + (idx / RZ_COLS) * RZ_BLD + idx % RZ_COLS] = rb[e];
         }
-        __syncthreads();
-        if (st + 1 < nst) fetch(st + 1);
-        const int r = wr * 16 + (lane & 15);
-#pragma unroll 2
-        for (int kk = 0; kk < RZ_K; kk += 4) {
-            const int kc = kk + (lane >> 4);
-            const double ap = Ps[r][kc], as = Ss[r][kc];
-            const double am = HAS_M ? Ms[r][kc] : 0.0;
+    };
+    dbl4 aP[RZ_SL], aS[RZ_SL], aM[RZ_SL];
 #pragma unroll
-            for (int u = 0; u < 5; ++u) {
-                const double b = Bs[kc][(wc * 5 + u) * 16 + (lane & 15)];
-                aP[u] = mfma4(ap, b, aP[u]);
-                if (sres[u]) aS[u] = mfma4(as, b, aS[u]);
-                if (HAS_M) aM[u] = mfma4(am, b, aM[u]);
-            }
+    for (int u = 0; u < RZ_SL; ++u) aP[u] = aS[u] = aM[u] = dbl4{0, 0, 0, 0};
+    if (nst > 0) {
+        fetch(0);
+        stash(0);
+    }
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        if (st + 1 < nst) fetch(st + 1);
+        const double* L = lds + (st & 1) * BUF;
+        const double* Ar = L + (wr * 16 + li) * RZ_LD + lk;
+        // operands of 4 contraction columns: A rows of Psi, S Psi (M Psi) and
+        // the B chunk of every tile of this wave
+        struct Ops {
+            double p, s, m, b[RZ_SL];
+        };
+        auto operands = [&](int kk, Ops& o) {
+            o.p = Ar[kk];
+            o.s = Ar[AM + kk];
+            o.m = HAS_M ? Ar[2 * AM + kk] : 0.0;
+            const double* Br = L + BOFF + (kk + lk) * RZ_BLD + li;
+#pragma unroll
+            for (int u = 0; u < RZ_SL; ++u)
+                if (u < ntw) o.b[u] = Br[16 * tile[u]];
+        };
+        auto products = [&](const Ops& o) {
+#pragma unroll
+            for (int u = 0; u < RZ_SL; ++u)
+                if (u < ntw) {
+                    aP[u] = mfma4(o.p, o.b[u], aP[u]);
+                    if (tile[u] < ns) aS[u] = mfma4(o.s, o.b[u], aS[u]);
+                    if (HAS_M) aM[u] = mfma4(o.m, o.b[u], aM[u]);
+                }
+        };
+        Ops o0, o1;
+        operands(0, o0);
+#pragma unroll
+        for (int kk = 0; kk < RZ_K; kk += 8) {
+            operands(kk + 4, o1);
+            products(o0);
+            if (kk + 8 < RZ_K) operands(kk + 8, o0);
+            products(o1);
         }
         if ((int)(st % nk) == nk - 1) {
-            // block finished: Phi (and M Phi) out, residual sums, accumulators reset
-            const int64_t r0 = (blockIdx.x + (st / nk) * gridDim.x) * RZ_RB;
+            // block finished: Phi (and M Phi) out, residual sums (one tile at a
+            // time, reduced over the 4 lanes that share a column), accumulators reset
+            const int64_t r0 = (blockIdx.x + (st / nk) * gridDim.x) * RZ_RB + wr * 16 + lk;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = r0 + wr * 16 + (lane >> 4) + 4 * v;
-                if (row < n) {
-                    const double mr = HAS_M ? 0.0 : mdiag[row];
+            for (int u = 0; u < RZ_SL; ++u) {
+                if (u >= ntw) continue;
+                const int col = col0 + tile[u] * 16 + li;
+                const bool has_res = tile[u] < ns;
+                const double lc = has_res && col < nres ? lam[col] : 0.0;
+                double num = 0.0, den = 0.0;
 #pragma unroll
-                    for (int u = 0; u < 5; ++u) {
-                        const int col = col0 + (wc * 5 + u) * 16 + (lane & 15);
-                        if (col < q) {
-                            const double phi = aP[u][v];
-                            const double mphi = HAS_M ? aM[u][v] : mr * phi;
-                            Phi[row * ld + col] = phi;
-                            if (MPhi) MPhi[row * ld + col] = mphi;
-                            if (col < nres) {
-                                const double res = aS[u][v] - lam[col] * mphi;
-                                if (minv_norm) {
-                                    num[u] += res * res / mr;
-                                    den[u] += phi * mphi;
-                                } else {
-                                    num[u] += res * res;
-                                    den[u] += mphi * mphi;
-                                }
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = r0 + 4 * v;
+                    if (row < n && col < q) {
+                        const double mr = HAS_M ? 0.0 : mdiag[row];
+                        const double phi = aP[u][v];
+                        const double mphi = HAS_M ? aM[u][v] : mr * phi;
+                        Phi[row * ld + col] = phi;
+                        if (MPhi) MPhi[row * ld + col] = mphi;
+                        if (has_res && col < nres) {
+                            const double res = aS[u][v] - lc * mphi;
+                            if (minv_norm) {
+                                num += res * res / mr;
+                                den += phi * mphi;
+                            } else {
+                                num += res * res;
+                                den += mphi * mphi;
                             }
                         }
                     }
                 }
+                if (has_res) {
+                    num += __shfl_xor(num, 16);
+                    num += __shfl_xor(num, 32);
+                    den += __shfl_xor(den, 16);
+                    den += __shfl_xor(den, 32);
+                    if (lane < 16) {
+                        red[wr][0][tile[u] * 16 + lane] += num;
+                        red[wr][1][tile[u] * 16 + lane] += den;
+                    }
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 5; ++u) aP[u] = aS[u] = aM[u] = dbl4{0, 0, 0, 0};
+            for (int u = 0; u < RZ_SL; ++u) aP[u] = aS[u] = aM[u] = dbl4{0, 0, 0, 0};
         }
+        if (st + 1 < nst) stash((st + 1) & 1);
         __syncthreads();
     }
-    // lanes l, l + 16, l + 32, l + 48 hold the same columns
-#pragma unroll
-    for (int u = 0; u < 5; ++u) {
-        num[u] += __shfl_xor(num[u], 16);
-        num[u] += __shfl_xor(num[u], 32);
-        den[u] += __shfl_xor(den[u], 16);
-        den[u] += __shfl_xor(den[u], 32);
-    }
-    if (lane < 16) {
-#pragma unroll
-        for (int u = 0; u < 5; ++u) {
-            red[wr][0][(wc * 5 + u) * 16 + lane] = num[u];
-            red[wr][1][(wc * 5 + u) * 16 + lane] = den[u];
-        }
-    }
-    __syncthreads();
-    if (tid < RZ_COLS && col0 + tid < q) {
+    if (tid < ncol) {
         partial[(int64_t)blockIdx.x * 2 * q + col0 + tid] =
             (red[0][0][tid] + red[1][0][tid]) + (red[2][0][tid] + red[3][0][tid]);
         partial[(int64_t)blockIdx.x * 2 * q + q + col0 + tid] =
@@ -2120,6 +2228,12 @@ hipError_t launch_ritz(const double* Psi, const double* SPsi, const double* MPsi
                        double* MPhi, double* partial, int64_t /*chunk_rows*/, bool minv_norm, double lam_floor,
                        double* resid, hipStream_t s, int32_t nres) {
     if (nres < 0 || nres > q) nres = q;
+    for (int32_t c0 = 0; c0 < q; c0 += RZ_COLS) {
+        const int nt = (int)cdiv(std::min<int32_t>(RZ_COLS, q - c0), 16);
+        const int ns = nres > c0 ? std::min<int>(nt, (int)cdiv(nres - c0, 16)) : 0;
+        int a, x;
+        if (!ritz_split(nt, ns, MPsi != nullptr && !mdiag, a, x)) return hipErrorInvalidValue;
+    }
     const int64_t nblk = cdiv(n, RZ_RB);
     const int64_t nwg = std::max<int64_t>(1, std::min<int64_t>({(int64_t)device_cus(), nblk, (int64_t)RZ_MAX_WG}));
     const dim3 grid((unsigned)nwg, (unsigned)cdiv(q, RZ_COLS));
