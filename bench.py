@@ -49,13 +49,13 @@ def run_solves(H, precision, tol, steps, warmup):
     return dt, out
 
 
-def cpu_baseline(p, nus=(102, 144), cols=30):
+def cpu_baseline(p, nus=(102, 144, 176), cols=30):
     """The oracle as it stands, timed on the host cores on a bounded sample:
     the finest-level work of one subspace iteration (SuperLU factorisation of
     S - mu M, the two block solves of an iteration with q right-hand sides,
-    one oracle Rayleigh-Ritz step) on two smaller meshes of the same recipe;
+    one oracle Rayleigh-Ritz step) on three smaller meshes of the same recipe;
     each component is extrapolated to the benchmark mesh with the power law
-    through the two sizes."""
+    fitted (least squares in log-log) through the three sizes."""
     import numpy as np
     import scipy.sparse as sp
     import synth
@@ -82,9 +82,10 @@ def cpu_baseline(p, nus=(102, 144), cols=30):
 
 
 def extrapolate(res, key, n):
-    (a, b) = res[0], res[1]
-    e = np.log(b[key] / a[key]) / np.log(b["n"] / a["n"])
-    return b[key] * (n / b["n"]) ** e, e
+    x = np.log([r["n"] for r in res])
+    y = np.log([r[key] for r in res])
+    e, c = np.polyfit(x, y, 1)
+    return float(np.exp(c + e * np.log(n))), float(e)
 
 
 def kernel_source_sha(name):
@@ -217,8 +218,8 @@ def main():
         cpu = {"value": round(float(est), 3), "unit": "s", "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
                "sample": (f"finest-level work of the oracle (SuperLU factorisation of S - mu M, q={H.q}-column solve, "
                           f"Rayleigh-Ritz step) timed on meshes of the same recipe with "
-                          f"{res[0]['n']} and {res[1]['n']} vertices, each extrapolated to {n} vertices by the power "
-                          f"law through the two (exponents factor {ef:.2f}, solve {es:.2f}, RR {er:.2f}); value = "
+                          f"{', '.join(str(r['n']) for r in res)} vertices, each extrapolated to {n} vertices by the "
+                          f"power law fitted through them (exponents factor {ef:.2f}, solve {es:.2f}, RR {er:.2f}); value = "
                           f"factor + {it0} finest-level iterations x (2 solves + 1 RR); coarse levels and hierarchy "
                           f"not included; SuperLU single-threaded")}
         log(f"cpu baseline sample took {time.perf_counter() - t:.1f} s")

@@ -596,7 +596,8 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
 // fp32: with the FP32 copy of the factor (FP32 arithmetic, FP64 in and out)
 template <class TF>
 static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
-                         const TF* linvT, double* X, int32_t col0, int32_t ncols, const double* md, hipStream_t s) {
+                         const TF* linvT, double* X, int32_t col0, int32_t ncols, const double* md, hipStream_t s,
+                         const double* Xin = nullptr) {
     const Symbolic& sy = L.sy;
     const DFront* fr = dptr<DFront>(L.dfronts);
     Prof& P = H->prof;
@@ -606,7 +607,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         HIPCHECK(launch_big_solve<TF>(phase, tiles, linv, D, tilesT, linvT, fr, bi + rec[0], rec[1], kb, X, H->ld,
                                       col0, ncols,
                                       dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
-                                      dptr<int32_t>(L.rows), s));
+                                      dptr<int32_t>(L.rows), s, Xin));
     };
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
         const TLev& T = L.tl[t];
@@ -625,7 +626,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
             HIPCHECK(launch_wsolve<TF>(true, tiles, linv, D, fr, T.f0, T.f1, T.ns_pad_max, X, H->ld, col0, ncols,
                                        dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
-                                       nullptr, false, s));
+                                       nullptr, false, s, Xin));
         });
     }
     for (int32_t t = sy.tree_levels - 1; t >= 0; --t) {
@@ -649,16 +650,18 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
     }
 }
 
+// X = (S - mu M)^-1 (M) B on columns [col0, col0 + ncols), in place (B = X)
+// or, with Xin, reading the right-hand side from Xin and writing X
 static void solve_level(hsim_hierarchy* H, Level& L, double* X, int32_t col0, int32_t ncols, bool scale_by_m,
-                        hipStream_t s, bool fp32 = false) {
+                        hipStream_t s, bool fp32 = false, const double* Xin = nullptr) {
     const double* md = scale_by_m ? dptr<double>(L.dmdiag) : nullptr;
     if (fp32) {
         if (!L.factored32) fail(HSIM_E_STATE, "no FP32 factor on level %d", L.tau);
         solve_sweeps<float>(H, L, dptr<float>(L.tiles32), dptr<float>(L.linv32), dptr<float>(L.D32),
-                            dptr<float>(L.tiles32T), dptr<float>(L.linv32T), X, col0, ncols, md, s);
+                            dptr<float>(L.tiles32T), dptr<float>(L.linv32T), X, col0, ncols, md, s, Xin);
     } else {
         solve_sweeps<double>(H, L, dptr<double>(L.tiles), dptr<double>(L.linv), dptr<double>(L.D),
-                             dptr<double>(L.tilesT), dptr<double>(L.linvT), X, col0, ncols, md, s);
+                             dptr<double>(L.tilesT), dptr<double>(L.linvT), X, col0, ncols, md, s, Xin);
     }
 }
 
@@ -1262,33 +1265,34 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         double est32 = -1.0;      // backward error of a plain FP32 solve on this level's factor
         for (it = 1; it <= so.max_iters; ++it) {
             auto a0 = std::chrono::steady_clock::now();
-            HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, L.n, q, dptr<double>(h->Psi), h->ld, s));
             const int32_t act = q - locked;
+            // Psi = Phi on the locked columns (not iterated); the active ones
+            // go from Phi into Psi with the first solve of the iteration
+            if (locked > 0)
+                HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, L.n, locked, dptr<double>(h->Psi), h->ld, s));
             if (act > 0) {
                 for (int rep = 0; rep < 2; ++rep) {
+                    double* src = dptr<double>(rep == 0 ? h->Phi : h->Psi);
                     if (!mixed && tau == 0) {
-                        solve_level(h, L, dptr<double>(h->Psi), locked, act, true, s);
+                        solve_level(h, L, dptr<double>(h->Psi), locked, act, true, s, false, src);
                         continue;
                     }
-                    // B = M Psi
+                    // B = M src
                     if (tau == 0)
-                        HIPCHECK(launch_diag_scale(dptr<double>(L.dmdiag), L.n, dptr<double>(h->Psi) + locked, h->ld,
-                                                   act, dptr<double>(h->Btmp) + locked, h->ld, s));
+                        HIPCHECK(launch_diag_scale(dptr<double>(L.dmdiag), L.n, src + locked, h->ld, act,
+                                                   dptr<double>(h->Btmp) + locked, h->ld, s));
                     else
                         h->prof.run(HSIM_K_SPMM, 12.0 * L.S.nnz() + 16.0 * L.n * act, 2.0 * L.S.nnz() * act, s, [&] {
                             HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx),
-                                                 dptr<double>(L.dM_val), nullptr, 1.0, 0.0, L.n,
-                                                 dptr<double>(h->Psi) + locked, h->ld, act,
-                                                 dptr<double>(h->Btmp) + locked, h->ld, s));
+                                                 dptr<double>(L.dM_val), nullptr, 1.0, 0.0, L.n, src + locked, h->ld,
+                                                 act, dptr<double>(h->Btmp) + locked, h->ld, s));
                         });
                     if (mixed) {
                         const double eta = std::min(1e-3, 0.1 * (std::isfinite(rmax) ? rmax : 1e-2));
                         st.refine_steps += refine_solve(h, L, dptr<double>(h->Btmp), dptr<double>(h->Psi), locked, act,
                                                         eta, s, &st.escalated, &est32);
                     } else {
-                        solve_level(h, L, dptr<double>(h->Btmp), locked, act, false, s);
-                        HIPCHECK(launch_copy2d(dptr<double>(h->Btmp) + locked, h->ld, L.n, act,
-                                               dptr<double>(h->Psi) + locked, h->ld, s));
+                        solve_level(h, L, dptr<double>(h->Psi), locked, act, false, s, false, dptr<double>(h->Btmp));
                     }
                 }
             }

@@ -76,6 +76,8 @@ hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const 
 // updates written to ubuf; gat: gw update-buffer rows per front row, -1 = none,
 // indexed by (gather_base + local row)); !fwd: backward sweep (apply_dinv divides by D),
 // with tiles and linv the tile-transposed copies (launch_tile_transpose).
+// Xin (forward only, null: X): where the right-hand-side rows are read; the
+// solution is written to X either way.
 int32_t wsolve_max_ns();
 // every 32 x 32 tile of in[0 .. 1024 ntiles) transposed into the same place of out
 template <class T>
@@ -84,7 +86,7 @@ template <class TF>
 hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
                          int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
                          double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw, const double* mdiag,
-                         const int32_t* rows, bool apply_dinv, hipStream_t s);
+                         const int32_t* rows, bool apply_dinv, hipStream_t s, const double* Xin = nullptr);
 
 // Block solves of tree levels with wide supernodes, 128-row pivot blocks:
 // phase 0 forward init (items: front, tile row), 1 forward diagonal block kb
@@ -93,14 +95,15 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
 // diagonal block kb (items: front), 5 backward update before block kb
 // (items: front, pivot tile).  Phase 0 in column chunks of 32; the others
 // on the matrix cores, one wave per (item, 16 columns); the backward phases
-// read the tile-transposed copies tilesT, linvT.
+// read the tile-transposed copies tilesT, linvT.  Xin (phase 0 only, null:
+// X): where the right-hand-side rows are read.
 constexpr int BIG_BLOCK_TILES = 4;
 template <class TF>
 hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
                             const TF* linvT, const DFront* fronts, const int32_t* items, int64_t nitems, int32_t kb,
                             double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf, int64_t ldu,
                             const int32_t* gat, int32_t gw, const double* mdiag, const int32_t* rows,
-                            hipStream_t s);
+                            hipStream_t s, const double* Xin = nullptr);
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 // partial Grams over row chunks (pairs of 32-column tiles, upper), then the sum

@@ -716,7 +716,7 @@ template <class TF, int NT>
 __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
     const TF* __restrict__ tiles, const TF* __restrict__ linv, const DFront* __restrict__ fr, int32_t f0, int32_t nfronts, int32_t groups, double* X,
     int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu, const int32_t* __restrict__ gat,
-    int32_t gw, const double* __restrict__ mdiag) {
+    int32_t gw, const double* __restrict__ mdiag, const double* Xin) {
     constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
     int32_t fi, grp;
@@ -740,7 +740,7 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
                 const int r = 16 * t + lr + 4 * v;
                 double val = 0.0;
                 if (r < f.ns && c < cend) {
-                    val = X[(f.start + r) * ldx + c];
+                    val = Xin[(f.start + r) * ldx + c];
                     if (mdiag) val *= mdiag[f.start + r];
                     if (gath) {
                         const int32_t* gr = gat + (f.gather_base + r) * gw;
@@ -1065,8 +1065,9 @@ template <class TF>
 hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
                          int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
                          double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw, const double* mdiag,
-                         const int32_t* rows, bool apply_dinv, hipStream_t s) {
+                         const int32_t* rows, bool apply_dinv, hipStream_t s, const double* Xin) {
     if (f1 <= f0 || ncols <= 0) return hipSuccess;
+    if (!Xin) Xin = X;
     if (ns_pad_max > wsolve_max_ns()) return hipErrorInvalidValue;
     int32_t wpg, groups;
     TF* ub = reinterpret_cast<TF*>(ubuf);
@@ -1075,7 +1076,7 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
     const dim3 grid((unsigned)(cdiv(f1 - f0, NXCD) * NXCD * groups)), block((unsigned)(64 * wpg));              \
     if (fwd)                                                                                                      \
         k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, f1 - f0, groups, X, ldx, col0,      \
-                                                    ncols, wpg, ub, ldu, gat, gw, mdiag);                         \
+                                                    ncols, wpg, ub, ldu, gat, gw, mdiag, Xin);                    \
     else                                                                                                          \
         k_wsolve_bwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, D, fronts, f0, f1 - f0, groups, X, ldx, col0,   \
                                                     ncols, wpg, rows, apply_dinv ? 1 : 0);
@@ -1088,10 +1089,12 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
 }
 template hipError_t launch_wsolve<double>(bool, const double*, const double*, const double*, const DFront*, int32_t,
                                           int32_t, int32_t, double*, int64_t, int32_t, int32_t, double*, int64_t,
-                                          const int32_t*, int32_t, const double*, const int32_t*, bool, hipStream_t);
+                                          const int32_t*, int32_t, const double*, const int32_t*, bool, hipStream_t,
+                                          const double*);
 template hipError_t launch_wsolve<float>(bool, const float*, const float*, const float*, const DFront*, int32_t,
                                          int32_t, int32_t, double*, int64_t, int32_t, int32_t, double*, int64_t,
-                                         const int32_t*, int32_t, const double*, const int32_t*, bool, hipStream_t);
+                                         const int32_t*, int32_t, const double*, const int32_t*, bool, hipStream_t,
+                                         const double*);
 
 namespace {
 template <class T>
@@ -1201,7 +1204,7 @@ __global__ __launch_bounds__(256) void k_big_fwd_init(const DFront* __restrict__
                                                       int32_t nchunks, double* X, int64_t ldx, int32_t col0,
                                                       int32_t ncols, T* ubuf, int64_t ldu,
                                                       const int32_t* __restrict__ gat, int32_t gw,
-                                                      const double* __restrict__ mdiag) {
+                                                      const double* __restrict__ mdiag, const double* Xin) {
     const int item = blockIdx.x / nchunks;
     const DFront f = fr[items[2 * item]];
     const int tr = items[2 * item + 1];
@@ -1213,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_big_fwd_init(const DFront* __restrict__
         if (tr < f.nsb) {
             const int row = tr * T32 + r;
             if (row >= f.ns) continue;
-            double v = X[(f.start + row) * ldx + c0 + c];
+            double v = Xin[(f.start + row) * ldx + c0 + c];
             if (mdiag) v *= mdiag[f.start + row];
             const int32_t* gr = gat + (f.gather_base + row) * gw;
             for (int cg = 0; cg < gw; ++cg)
@@ -1531,13 +1534,13 @@ hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF
                             const TF* linvT, const DFront* fronts, const int32_t* items, int64_t nitems, int32_t kb,
                             double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf, int64_t ldu,
                             const int32_t* gat, int32_t gw, const double* mdiag, const int32_t* rows,
-                            hipStream_t s) {
+                            hipStream_t s, const double* Xin) {
     if (nitems <= 0 || ncols <= 0) return hipSuccess;
     TF* ub = reinterpret_cast<TF*>(ubuf);
     if (phase == 0) {
         const int32_t nch = (int32_t)cdiv(ncols, BQC);
         k_big_fwd_init<TF><<<(unsigned)(nitems * nch), 256, 0, s>>>(fronts, items, nch, X, ldx, col0, ncols, ub, ldu,
-                                                                    gat, gw, mdiag);
+                                                                    gat, gw, mdiag, Xin ? Xin : X);
         return hipGetLastError();
     }
     int32_t wpg, groups;
@@ -1556,11 +1559,11 @@ hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF
 template hipError_t launch_big_solve<double>(int, const double*, const double*, const double*, const double*,
                                              const double*, const DFront*, const int32_t*, int64_t, int32_t, double*,
                                              int64_t, int32_t, int32_t, double*, int64_t, const int32_t*, int32_t,
-                                             const double*, const int32_t*, hipStream_t);
+                                             const double*, const int32_t*, hipStream_t, const double*);
 template hipError_t launch_big_solve<float>(int, const float*, const float*, const float*, const float*, const float*,
                                             const DFront*, const int32_t*, int64_t, int32_t, double*, int64_t, int32_t,
                                             int32_t, double*, int64_t, const int32_t*, int32_t, const double*,
-                                            const int32_t*, hipStream_t);
+                                            const int32_t*, hipStream_t, const double*);
 
 // ============================================================ Gram products
 // Sbar = Psi^T (S Psi), Mbar = Psi^T (M Psi) on the matrix cores.  The q x q
@@ -1729,29 +1732,32 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
 // for its rows, so Psi is read once.  Waves 0-3 take Psi^T S Psi, waves 4-7
 // Psi^T M Psi; wave slot j of 14 is upper tile 14 (w mod 4) + j in row-major
 // tile order (nup = nt (nt + 1) / 2 <= 55 tiles per product), so the matrix
-// cores of the four SIMDs get equal work.  Rows go through LDS 16 at a time
-// (double-buffered: Psi, S Psi and M Psi or m), the next 16 are loaded into
-// registers meanwhile; within a stage the operands of the next 7 slots are
-// read from LDS while the current 7 products run.  Output: per workgroup and
+// cores of the four SIMDs get equal work.  Rows go through LDS 16 at a time,
+// double-buffered, the next 16 loaded into registers meanwhile.  A stage is
+// stored transposed (column-major, GA_TS doubles per column) and the rows are
+// assigned to the products' k index so that k-step s of lane group g takes
+// stage row 4 g + s: a lane's four operands of a tile for the whole stage are
+// contiguous and come in two 16-byte reads.  Output: per workgroup and
 // product the upper tiles in row-major tile order, each tile row-major.
 namespace {
 constexpr int GA_R = 16;          // rows per stage
-constexpr int GA_LD = 168;        // LDS row stride (doubles)
+constexpr int GA_TS = GA_R + 2;   // doubles per column of a transposed stage (16-byte aligned, conflict-free)
 constexpr int GA_MAXT = 10;       // column tiles
+constexpr int GA_MAT = GA_MAXT * 16 * GA_TS;   // doubles per transposed matrix
 constexpr int GA_W = 8;           // waves
-constexpr int GA_S = 14;          // tile slots per wave
-constexpr int GA_H = GA_S / 2;    // slots per operand batch
+constexpr int GA_S = 14;          // tile slots per wave (even: processed in pairs)
 constexpr int GA_THREADS = 64 * GA_W;
 constexpr int GA_MAX_WG = 1024;
 static_assert(GA_W / 2 * GA_S >= GA_MAXT * (GA_MAXT + 1) / 2, "slots must cover the upper tiles");
 template <bool HAS_M>
-constexpr int gram_all_buf() {   // doubles per stage buffer
-    return (HAS_M ? 3 : 2) * GA_R * GA_LD + GA_R;
+constexpr int gram_all_buf() {   // doubles per stage buffer: Psi, S Psi and M Psi or m
+    return (HAS_M ? 3 : 2) * GA_MAT + GA_R;
 }
 template <bool HAS_M>
 constexpr size_t gram_all_lds() {
     return 2 * (size_t)gram_all_buf<HAS_M>() * sizeof(double);
 }
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 }  // namespace
 
 int32_t gram_fp64_single_pass_max_q() { return GA_MAXT * 16; }
@@ -1767,15 +1773,15 @@ __global__ __launch_bounds__(GA_THREADS) void k_gram_all(const double* __restric
                                                          const double* __restrict__ mdiag, int64_t n, int32_t q,
                                                          int64_t ld, double* __restrict__ partial) {
     constexpr int BUF = gram_all_buf<HAS_M>();
-    constexpr int MAT = GA_R * GA_LD;   // doubles per staged matrix
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* lds = reinterpret_cast<double*>(smem_raw);
     const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int nt = (q + 15) >> 4, nup = nt * (nt + 1) / 2;
     const int prod = w >= GA_W / 2;
-    // slot j: LDS offsets of its A (Psi columns of tile row I) and B (S Psi,
-    // M Psi or Psi columns of tile column J) operands
+    const int bmat = prod == 0 ? GA_MAT : (HAS_M ? 2 * GA_MAT : 0);   // B operand matrix
+    // slot j: LDS offsets of its A (Psi, tile row I) and B (S Psi, M Psi or
+    // Psi, tile column J) operand columns
     int aoff[GA_S], boff[GA_S], valid = 0;
 #pragma unroll
     for (int j = 0; j < GA_S; ++j) {
@@ -1787,8 +1793,8 @@ __global__ __launch_bounds__(GA_THREADS) void k_gram_all(const double* __restric
             t -= nt - I;
             ++I;
         }
-        aoff[j] = 16 * I;
-        boff[j] = 16 * (I + t) + (prod == 0 ? MAT : (HAS_M ? 2 * MAT : 0));
+        aoff[j] = 16 * I * GA_TS;
+        boff[j] = 16 * (I + t) * GA_TS + bmat;
         valid |= (int)v << j;
     }
     const int64_t nblk = (n + GA_R - 1) / GA_R;
@@ -1815,12 +1821,12 @@ __global__ __launch_bounds__(GA_THREADS) void k_gram_all(const double* __restric
             const int idx = tid + GA_THREADS * e;
             if (idx < GA_R * GA_MAXT * 16) {
                 const int r = idx / (GA_MAXT * 16), c = idx % (GA_MAXT * 16);
-                P[r * GA_LD + c] = rp[e];
-                P[MAT + r * GA_LD + c] = rs[e];
-                if (HAS_M) P[2 * MAT + r * GA_LD + c] = rm[e];
+                P[c * GA_TS + r] = rp[e];
+                P[GA_MAT + c * GA_TS + r] = rs[e];
+                if (HAS_M) P[2 * GA_MAT + c * GA_TS + r] = rm[e];
             }
         }
-        if (!HAS_M && tid < GA_R) P[2 * MAT + tid] = rmd;
+        if (!HAS_M && tid < GA_R) P[2 * GA_MAT + tid] = rmd;
     };
     dbl4 acc[GA_S];
 #pragma unroll
@@ -1833,27 +1839,47 @@ __global__ __launch_bounds__(GA_THREADS) void k_gram_all(const double* __restric
     for (int64_t jb = 0; jb < my_blocks; ++jb) {
         if (jb + 1 < my_blocks) fetch(jb + 1);
         const double* P = lds + (jb & 1) * BUF;
+        const double* PL = P + li * GA_TS + 4 * lk;   // this lane's column and rows within a tile
         // Psi^T M Psi with diagonal M: B operand scaled by m of its row
-        const bool scale = !HAS_M && prod == 1;
-        double a0[GA_H], b0[GA_H], a1[GA_H], b1[GA_H];
-        auto operands = [&](int kk, int h, double(&av)[GA_H], double(&bv)[GA_H]) {
-            const double* Pr = P + (kk + lk) * GA_LD + li;
-#pragma unroll
-            for (int j = 0; j < GA_H; ++j) {
-                av[j] = Pr[aoff[h * GA_H + j]];
-                bv[j] = Pr[boff[h * GA_H + j]];
-            }
+        dbl4 mk = dbl4{1.0, 1.0, 1.0, 1.0};
+        if (!HAS_M && prod == 1) {
+            const dbl2 m0 = *reinterpret_cast<const dbl2*>(P + 2 * GA_MAT + 4 * lk);
+            const dbl2 m1 = *reinterpret_cast<const dbl2*>(P + 2 * GA_MAT + 4 * lk + 2);
+            mk = dbl4{m0[0], m0[1], m1[0], m1[1]};
+        }
+        // the operands of two slots for the whole stage; the next pair is read
+        // while the current pair's 8 products run
+        struct Pair {
+            dbl2 a0, a1, b0, b1, c0, c1, d0, d1;
         };
-        operands(0, 0, a0, b0);
+        auto operands = [&](int j, Pair& o) {
+            o.a0 = *reinterpret_cast<const dbl2*>(PL + aoff[j]);
+            o.a1 = *reinterpret_cast<const dbl2*>(PL + aoff[j] + 2);
+            o.b0 = *reinterpret_cast<const dbl2*>(PL + boff[j]);
+            o.b1 = *reinterpret_cast<const dbl2*>(PL + boff[j] + 2);
+            o.c0 = *reinterpret_cast<const dbl2*>(PL + aoff[j + 1]);
+            o.c1 = *reinterpret_cast<const dbl2*>(PL + aoff[j + 1] + 2);
+            o.d0 = *reinterpret_cast<const dbl2*>(PL + boff[j + 1]);
+            o.d1 = *reinterpret_cast<const dbl2*>(PL + boff[j + 1] + 2);
+        };
+        auto products = [&](int j, const Pair& o) {
+            acc[j] = mfma4(o.a0[0], o.b0[0] * mk[0], acc[j]);
+            acc[j + 1] = mfma4(o.c0[0], o.d0[0] * mk[0], acc[j + 1]);
+            acc[j] = mfma4(o.a0[1], o.b0[1] * mk[1], acc[j]);
+            acc[j + 1] = mfma4(o.c0[1], o.d0[1] * mk[1], acc[j + 1]);
+            acc[j] = mfma4(o.a1[0], o.b1[0] * mk[2], acc[j]);
+            acc[j + 1] = mfma4(o.c1[0], o.d1[0] * mk[2], acc[j + 1]);
+            acc[j] = mfma4(o.a1[1], o.b1[1] * mk[3], acc[j]);
+            acc[j + 1] = mfma4(o.c1[1], o.d1[1] * mk[3], acc[j + 1]);
+        };
+        Pair p0, p1;
+        operands(0, p0);
 #pragma unroll
-        for (int kk = 0; kk < GA_R; kk += 4) {
-            const double sc = scale ? P[2 * MAT + kk + lk] : 1.0;
-            operands(kk, 1, a1, b1);
-#pragma unroll
-            for (int j = 0; j < GA_H; ++j) acc[j] = mfma4(a0[j], b0[j] * sc, acc[j]);
-            if (kk + 4 < GA_R) operands(kk + 4, 0, a0, b0);
-#pragma unroll
-            for (int j = 0; j < GA_H; ++j) acc[GA_H + j] = mfma4(a1[j], b1[j] * sc, acc[GA_H + j]);
+        for (int j = 0; j < GA_S; j += 4) {
+            if (j + 2 < GA_S) operands(j + 2, p1);
+            products(j, p0);
+            if (j + 4 < GA_S) operands(j + 4, p0);
+            if (j + 2 < GA_S) products(j + 2, p1);
         }
         if (jb + 1 < my_blocks) stash((jb + 1) & 1);
         __syncthreads();
@@ -1862,7 +1888,7 @@ __global__ __launch_bounds__(GA_THREADS) void k_gram_all(const double* __restric
 #pragma unroll
     for (int j = 0; j < GA_S; ++j) {
         if (!((valid >> j) & 1)) continue;
-        const int I = aoff[j] >> 4, J = ((boff[j] - (prod == 0 ? MAT : (HAS_M ? 2 * MAT : 0))) >> 4);
+        const int I = aoff[j] / (16 * GA_TS), J = (boff[j] - bmat) / (16 * GA_TS);
         const int64_t t = (int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I);
 #pragma unroll
         for (int v = 0; v < 4; ++v) out[t * 256 + (lk + 4 * v) * 16 + li] = acc[j][v];
@@ -2396,9 +2422,10 @@ __global__ __launch_bounds__(B * B) void k_bj_local(const double* __restrict__ C
                                                     double tol_rel, double tol_abs_rel, int32_t max_sweeps,
                                                     int32_t* rot_count) {
     constexpr int W = 2 * B;
-    __shared__ double A[2][W][W + 1];
-    __shared__ double Q[W][W + 1];
-    __shared__ int total;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double(*A)[W][W + 1] = reinterpret_cast<double(*)[W][W + 1]>(smem_raw);   // [2][W][W + 1]
+    double(*Q)[W + 1] = reinterpret_cast<double(*)[W + 1]>(smem_raw + 2 * sizeof(double) * W * (W + 1));
+    int& total = *reinterpret_cast<int*>(smem_raw + 3 * sizeof(double) * W * (W + 1));
     const int nb = m / B;
     int I, J;
     bj_pair(blockIdx.x, r, nb, I, J);
@@ -2460,18 +2487,19 @@ __global__ __launch_bounds__(B * B) void k_bj_local(const double* __restrict__ C
 
 // C <- J^T C J on every (pair, pair') tile (pair <= pair'), V <- V J on row
 // chunks; first npairs*(npairs+1)/2 workgroups do C, the rest V.  The 2b x 2b
-// products (b = 16) run on the FP64 matrix cores: wave w of the workgroup owns
-// the 16 x 16 output tile (w / 2, w % 2).  16x16x4 operand layout: lane l holds
+// products run on the FP64 matrix cores: wave w of the workgroup (b^2 / 64
+// waves) owns the 16 x 16 output tile (w / (b / 8), w % (b / 8)).  16x16x4 operand layout: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result item v of lane l is
 // D[l / 16 + 4 v][l % 16].
-__global__ __launch_bounds__(256) void k_bj_apply(double* C, double* V, int32_t m, int32_t r,
-                                                  const double* __restrict__ Qs) {
-    constexpr int B = 16, W = 32;
+template <int B>
+__global__ __launch_bounds__(B * B) void k_bj_apply(double* C, double* V, int32_t m, int32_t r,
+                                                    const double* __restrict__ Qs) {
+    constexpr int W = 2 * B, NT = W / 16;   // NT x NT output tiles of 16 x 16, one per wave
     __shared__ double X[W][W + 1];
     const int nb = m / B, np = nb / 2;
     const int64_t ctiles = (int64_t)np * (np + 1) / 2;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4, ta = w >> 1, tc = w & 1;
+    const int li = lane & 15, lk = lane >> 4, ta = w / NT, tc = w % NT;
     if (blockIdx.x < ctiles) {
         int t = blockIdx.x, P = 0;
         while (t >= np - P) { t -= np - P; ++P; }
@@ -2515,7 +2543,7 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* C, double* V, int32_t 
         int I1, J1;
         bj_pair(P, r, nb, I1, J1);
         const double* q1 = Qs + (int64_t)P * W * W;
-        for (int idx = tid; idx < W * W; idx += 256) {
+        for (int idx = tid; idx < W * W; idx += B * B) {
             const int a = idx / W, c = idx % W;
             X[a][c] = V[(row0 + a) * m + bj_index<B>(c, I1, J1)];
         }
@@ -2555,18 +2583,25 @@ hipError_t launch_bj_offcount(const double* C, int32_t m, const double* normf, d
     return hipGetLastError();
 }
 
+template <int B>
+hipError_t bj_round(double* C, double* V, int32_t m, int32_t round, double* Qs, const double* normf, double tol_rel,
+                    double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, hipStream_t s) {
+    constexpr size_t lds = 3 * sizeof(double) * (2 * B) * (2 * B + 1) + 16;
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_bj_local<B>), lds, 0);
+    if (e != hipSuccess) return e;
+    const int nb = m / B, np = nb / 2;
+    const int64_t ctiles = (int64_t)np * (np + 1) / 2;
+    const int64_t vitems = (int64_t)(m / (2 * B)) * np;
+    k_bj_local<B><<<np, B * B, lds, s>>>(C, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_bj_apply<B><<<(unsigned)(ctiles + vitems), B * B, 0, s>>>(C, V, m, round, Qs);
+    return hipGetLastError();
+}
 hipError_t launch_bj_round(int b, double* C, double* V, int32_t m, int32_t round, double* Qs, const double* normf,
                            double tol_rel, double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count,
                            hipStream_t s) {
     if (b != 16 || m % (2 * b) != 0) return hipErrorInvalidValue;
-    const int nb = m / b, np = nb / 2;
-    const int64_t ctiles = (int64_t)np * (np + 1) / 2;
-    const int64_t vitems = (int64_t)(m / (2 * b)) * np;
-    k_bj_local<16><<<np, 256, 0, s>>>(C, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_bj_apply<<<(unsigned)(ctiles + vitems), 256, 0, s>>>(C, V, m, round, Qs);
-    return hipGetLastError();
+    return bj_round<16>(C, V, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count, s);
 }
 
 // V = identity (m x m)
@@ -3036,39 +3071,45 @@ hipError_t launch_import_cols(const double* in, int64_t nv, const int32_t* perm,
 
 // ============================================================ output
 // per column: the row with the largest |value|, lowest vertex index on ties
-__global__ __launch_bounds__(256) void k_col_argmax(const double* Phi, int64_t ld, int64_t n, int32_t p,
-                                                    const int32_t* perm, int64_t chunk, double* pv, int64_t* pi) {
-    const int c = blockIdx.y;
+// per (chunk of rows, column): the entry of largest magnitude (lowest vertex
+// index on ties).  A workgroup takes one chunk and 128 columns: thread
+// (column lane, row lane) reads rows r0 + row lane + 8 k, so that every row
+// read is 128 consecutive values
+__global__ __launch_bounds__(1024) void k_col_argmax(const double* Phi, int64_t ld, int64_t n, int32_t p,
+                                                     const int32_t* perm, int64_t chunk, double* pv, int64_t* pi) {
+    const int cl = threadIdx.x & 127, rl = threadIdx.x >> 7;
+    const int c = blockIdx.y * 128 + cl;
     const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-    double best = -1.0;
+    double best = -1.0, bv = 0.0;
     int64_t bi = INT64_MAX;
-    double bv = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const double v = Phi[r * ld + c];
-        const int64_t vi = perm ? perm[r] : r;
-        const double a = fabs(v);
-        if (a > best || (a == best && vi < bi)) { best = a; bi = vi; bv = v; }
-    }
-    __shared__ double sb[256], sv[256];
-    __shared__ int64_t si[256];
-    sb[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    sv[threadIdx.x] = bv;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            const int o = threadIdx.x + w;
-            if (sb[o] > sb[threadIdx.x] || (sb[o] == sb[threadIdx.x] && si[o] < si[threadIdx.x])) {
-                sb[threadIdx.x] = sb[o];
-                si[threadIdx.x] = si[o];
-                sv[threadIdx.x] = sv[o];
+    if (c < p) {
+#pragma unroll 4
+        for (int64_t r = r0 + rl; r < r1; r += 8) {
+            const double v = Phi[r * ld + c];
+            const int64_t vi = perm ? perm[r] : r;
+            const double a = fabs(v);
+            if (a > best || (a == best && vi < bi)) {
+                best = a;
+                bi = vi;
+                bv = v;
             }
         }
-        __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        pv[(int64_t)c * gridDim.x + blockIdx.x] = sb[0] >= 0 ? (sv[0] < 0 ? -sb[0] : sb[0]) : 0.0;
-        pi[(int64_t)c * gridDim.x + blockIdx.x] = si[0];
+    __shared__ double sb[8][128], sv[8][128];
+    __shared__ int64_t si[8][128];
+    sb[rl][cl] = best;
+    si[rl][cl] = bi;
+    sv[rl][cl] = bv;
+    __syncthreads();
+    if (rl == 0 && c < p) {
+        for (int k = 1; k < 8; ++k)
+            if (sb[k][cl] > best || (sb[k][cl] == best && si[k][cl] < bi)) {
+                best = sb[k][cl];
+                bi = si[k][cl];
+                bv = sv[k][cl];
+            }
+        pv[(int64_t)c * gridDim.x + blockIdx.x] = best >= 0 ? (bv < 0 ? -best : best) : 0.0;
+        pi[(int64_t)c * gridDim.x + blockIdx.x] = bi;
     }
 }
 __global__ void k_col_sign(const double* pv, const int64_t* pi, int64_t nch, int32_t p, double* sign) {
@@ -3113,7 +3154,7 @@ hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t
     double* pv = work;
     int64_t* pi = reinterpret_cast<int64_t*>(work + nch * p);
     double* sign = work + 2 * nch * p;
-    k_col_argmax<<<dim3((unsigned)nch, (unsigned)p), 256, 0, s>>>(Phi, ld, n, p, perm, chunk, pv, pi);
+    k_col_argmax<<<dim3((unsigned)nch, (unsigned)cdiv(p, 128)), 1024, 0, s>>>(Phi, ld, n, p, perm, chunk, pv, pi);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_col_sign<<<(unsigned)cdiv(p, 256), 256, 0, s>>>(pv, pi, nch, p, sign);
