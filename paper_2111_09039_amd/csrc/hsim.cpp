@@ -268,11 +268,15 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
 // tree levels whose widest supernode has at least this many (padded) pivots
 // use the multi-workgroup block solve
 constexpr int32_t BIG_NS = 256;
+// the backward sweep switches to the multi-workgroup solve earlier (its
+// wave-level form reduces over all struct rows of a front in one wave)
+constexpr int32_t BIG_NS_BWD = 128;
 
 struct TLev {
     int32_t f0 = 0, f1 = 0, ns_pad_max = 0;
-    // wide supernodes: multi-workgroup block solve (item lists in Level::big_items)
-    bool big = false;
+    // wide supernodes: multi-workgroup block solve (item lists in Level::big_items,
+    // built when either sweep uses it)
+    bool big = false, big_fwd = false, big_bwd = false;
     int32_t nblk = 0;
     int64_t fwd_init[2] = {0, 0}, bwd_init[2] = {0, 0};   // [offset (ints), count]
     std::vector<int64_t> fdiag, fupd, bdiag, bupd;       // per block: offset, count pairs
@@ -464,7 +468,10 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
             T.l_entries += (double)f.ns * (f.ns + 1) / 2 + (double)f.ns * f.mu;
             T.pivots += f.ns;
         }
-        T.big = T.ns_pad_max > wsolve_max_ns() || T.ns_pad_max >= env_int("HSIM_BIG_NS", BIG_NS);
+        const bool wide = T.ns_pad_max > wsolve_max_ns();
+        T.big_fwd = wide || T.ns_pad_max >= env_int("HSIM_BIG_NS", BIG_NS);
+        T.big_bwd = wide || T.ns_pad_max >= env_int("HSIM_BIG_NS_BWD", BIG_NS_BWD);
+        T.big = T.big_fwd || T.big_bwd;
         if (T.big) {
             // item lists of the multi-workgroup block solve
             auto push = [&](int32_t a, int32_t b) { big.push_back(a); big.push_back(b); };
@@ -613,7 +620,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         const TLev& T = L.tl[t];
         const double bytes = bL * T.l_entries + 2.0 * 8.0 * T.pivots * ncols;
         const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
-        if (T.big) {
+        if (T.big_fwd) {
             P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
                 big(0, T.fwd_init, 0);
                 for (int32_t kb = 0; kb < T.nblk; ++kb) {
@@ -633,7 +640,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         const TLev& T = L.tl[t];
         const double bytes = bL * T.l_entries + 2.0 * 8.0 * T.pivots * ncols;
         const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
-        if (T.big) {
+        if (T.big_bwd) {
             P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
                 big(3, T.bwd_init, 0);
                 for (int32_t kb = T.nblk - 1; kb >= 0; --kb) {
@@ -665,18 +672,23 @@ static void solve_level(hsim_hierarchy* H, Level& L, double* X, int32_t col0, in
     }
 }
 
+// Y = (a A + b M) X on the level's S / M pattern, A = S (a_is_s) or M; the
+// M term only with with_m
+static void pattern_spmm(Level& L, bool a_is_s, bool with_m, double a, double b, const double* X, int64_t ldx,
+                         int32_t k, double* Y, int64_t ldy, hipStream_t s) {
+    HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), dptr<double>(a_is_s ? L.dS_val : L.dM_val),
+                         with_m ? dptr<double>(L.dM_val) : nullptr, a, b, L.n, X, ldx, k, Y, ldy, s));
+}
+
 static void apply_level(hsim_hierarchy* H, Level& L, int op, const double* X, double* Y, int32_t k, hipStream_t s) {
     // op 0: S, 1: M, 2: S - mu M
     if (op == 1 && L.tau == 0) {
         HIPCHECK(launch_diag_scale(dptr<double>(L.dmdiag), L.n, X, H->ld, k, Y, H->ld, s));
         return;
     }
-    const double* va = op == 1 ? dptr<double>(L.dM_val) : dptr<double>(L.dS_val);
-    const double* vb = op == 2 ? dptr<double>(L.dM_val) : nullptr;
     const double nnz = (double)L.S.nnz();
     H->prof.run(HSIM_K_SPMM, nnz * (op == 2 ? 20.0 : 12.0) + 16.0 * L.n * k, 2.0 * nnz * k, s, [&] {
-        HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), va, vb, 1.0, op == 2 ? -L.mu : 0.0, L.n,
-                             X, H->ld, k, Y, H->ld, s));
+        pattern_spmm(L, op != 1, op == 2, 1.0, op == 2 ? -L.mu : 0.0, X, H->ld, k, Y, H->ld, s);
     });
 }
 
@@ -708,8 +720,7 @@ static int32_t refine_solve(hsim_hierarchy* H, Level& L, const double* B, double
     for (int it = 0; it < 12; ++it) {
         // R = B - (S - mu M) X
         H->prof.run(HSIM_K_SPMM, nnz * 20.0 + 16.0 * n * ncols, 2.0 * nnz * ncols, s, [&] {
-            HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx), dptr<double>(L.dS_val),
-                                 dptr<double>(L.dM_val), 1.0, -L.mu, n, X + col0, ld, ncols, R + col0, ld, s));
+            pattern_spmm(L, true, true, 1.0, -L.mu, X + col0, ld, ncols, R + col0, ld, s);
         });
         HIPCHECK(launch_axpby(1.0, B + col0, ld, -1.0, R + col0, ld, n, ncols, s));
         HIPCHECK(launch_colnorm_ratio(R, B, n, ld, col0, ncols, dptr<double>(H->cn_part), dptr<double>(H->cn_ratio), s));
@@ -740,6 +751,11 @@ static void prolong_level(hsim_hierarchy* H, Level& L, const double* Xc, double*
         HIPCHECK(launch_spmm(dptr<int64_t>(L.dU_ptr), dptr<int32_t>(L.dU_idx), dptr<double>(L.dU_val), nullptr, 1.0, 0.0,
                              L.n, Xc, H->ld, k, Xf, H->ld, s));
     });
+}
+
+static void swap_buffers(DeviceBuffer& a, DeviceBuffer& b) {
+    std::swap(a.p, b.p);
+    std::swap(a.bytes, b.bytes);
 }
 
 static void alloc_workspace(hsim_hierarchy* H) {
@@ -1266,26 +1282,26 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         for (it = 1; it <= so.max_iters; ++it) {
             auto a0 = std::chrono::steady_clock::now();
             const int32_t act = q - locked;
-            // Psi = Phi on the locked columns (not iterated); the active ones
-            // go from Phi into Psi with the first solve of the iteration
-            if (locked > 0)
-                HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, L.n, locked, dptr<double>(h->Psi), h->ld, s));
+            // the active columns go from Phi into Psi with the two solves of the
+            // iteration; the locked ones (not iterated) are copied from Phi after
             if (act > 0) {
-                for (int rep = 0; rep < 2; ++rep) {
+                if (!mixed && tau == 0) {
+                    // Phi -> Psi -> Btmp, out of place (lets the forward sweep split
+                    // narrow tree levels), then Btmp becomes Psi
+                    solve_level(h, L, dptr<double>(h->Psi), locked, act, true, s, false, dptr<double>(h->Phi));
+                    solve_level(h, L, dptr<double>(h->Btmp), locked, act, true, s, false, dptr<double>(h->Psi));
+                    swap_buffers(h->Psi, h->Btmp);
+                }
+                for (int rep = 0; rep < 2 && (mixed || tau > 0); ++rep) {
                     double* src = dptr<double>(rep == 0 ? h->Phi : h->Psi);
-                    if (!mixed && tau == 0) {
-                        solve_level(h, L, dptr<double>(h->Psi), locked, act, true, s, false, src);
-                        continue;
-                    }
                     // B = M src
                     if (tau == 0)
                         HIPCHECK(launch_diag_scale(dptr<double>(L.dmdiag), L.n, src + locked, h->ld, act,
                                                    dptr<double>(h->Btmp) + locked, h->ld, s));
                     else
                         h->prof.run(HSIM_K_SPMM, 12.0 * L.S.nnz() + 16.0 * L.n * act, 2.0 * L.S.nnz() * act, s, [&] {
-                            HIPCHECK(launch_spmm(dptr<int64_t>(L.dS_ptr), dptr<int32_t>(L.dS_idx),
-                                                 dptr<double>(L.dM_val), nullptr, 1.0, 0.0, L.n, src + locked, h->ld,
-                                                 act, dptr<double>(h->Btmp) + locked, h->ld, s));
+                            pattern_spmm(L, false, false, 1.0, 0.0, src + locked, h->ld, act,
+                                         dptr<double>(h->Btmp) + locked, h->ld, s);
                         });
                     if (mixed) {
                         const double eta = std::min(1e-3, 0.1 * (std::isfinite(rmax) ? rmax : 1e-2));
@@ -1296,6 +1312,8 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
                     }
                 }
             }
+            if (locked > 0)
+                HIPCHECK(launch_copy2d(dptr<double>(h->Phi), h->ld, L.n, locked, dptr<double>(h->Psi), h->ld, s));
             HIPCHECK(hipStreamSynchronize(s));
             st.ms_solve += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a0).count();
             // FP32 Gram only far from convergence (its rounding bounds the Ritz

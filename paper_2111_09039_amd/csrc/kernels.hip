@@ -696,7 +696,24 @@ __device__ __forceinline__ bool wsolve_item(int32_t nfronts, int32_t groups, int
     front = (slot / groups) * NXCD + xcd;
     return front < nfronts;
 }
+// the same with the update rows of a front split over `splits` workgroups
+// (all of one front on one XCD)
+__device__ __forceinline__ bool wsolve_item_split(int32_t nfronts, int32_t groups, int32_t splits, int32_t& front,
+                                                  int32_t& grp, int32_t& split) {
+    const int32_t b = (int32_t)blockIdx.x, xcd = b & (NXCD - 1), slot = b / NXCD;
+    grp = slot % groups;
+    const int32_t rem = slot / groups;
+    split = rem % splits;
+    front = (rem / splits) * NXCD + xcd;
+    return front < nfronts;
+}
 
+// a forward sweep over a tree level with fewer waves than this splits the
+// update rows of every front over several workgroups (each repeats the pivot
+// block solve), so that narrow levels near the top of the tree fill the chip;
+// only when the right-hand side is read from a separate block (in place, one
+// workgroup's solution would overwrite another one's input)
+constexpr int64_t WSOLVE_MIN_WAVES = 1024;
 // widest workgroup (waves) of the wave-level solves for NT pivot row tiles
 template <int NT>
 struct WsolveWaves {
@@ -714,13 +731,13 @@ struct WsolveCols {
 // column tiles of 16.
 template <class TF, int NT>
 __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
-    const TF* __restrict__ tiles, const TF* __restrict__ linv, const DFront* __restrict__ fr, int32_t f0, int32_t nfronts, int32_t groups, double* X,
+    const TF* __restrict__ tiles, const TF* __restrict__ linv, const DFront* __restrict__ fr, int32_t f0, int32_t nfronts, int32_t groups, int32_t splits, double* X,
     int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu, const int32_t* __restrict__ gat,
     int32_t gw, const double* __restrict__ mdiag, const double* Xin) {
     constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    int32_t fi, grp;
-    if (!wsolve_item(nfronts, groups, fi, grp)) return;
+    int32_t fi, grp, split;
+    if (!wsolve_item_split(nfronts, groups, splits, fi, grp, split)) return;
     const int32_t cbase = col0 + (grp * wpg + w) * WCOLS * CT;
     const int32_t cend = col0 + ncols;
     if (cbase >= cend) return;
@@ -806,18 +823,20 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = 16 * t + lr + 4 * v;
-                if (r < f.ns && c < cend) X[(f.start + r) * ldx + c] = y[cc][t][v];
+                if (split == 0 && r < f.ns && c < cend) X[(f.start + r) * ldx + c] = y[cc][t][v];
             }
     }
     // update rows, 16 at a time; the fragments of the next (row tile, pivot
     // block) pair are loaded while the current one is applied
+    // (this workgroup's share [rt0, rt1) of the row tiles when they are split)
     const int mt = (f.mu + 15) >> 4;
-    if (mt == 0) return;
+    const int rt0 = split * mt / splits, rt1 = (split + 1) * mt / splits;
+    if (rt0 >= rt1) return;
     const int nkb = (nt + 1) >> 1;
     double a[8];
-    frag_rows(tiles + f.tile_base + tri(f.Mt, f.nsb, 0) * TT, 0, false, a);
+    frag_rows(tiles + f.tile_base + tri(f.Mt, f.nsb + (rt0 >> 1), 0) * TT, rt0 & 1, false, a);
 #pragma unroll 1
-    for (int rt = 0; rt < mt; ++rt) {
+    for (int rt = rt0; rt < rt1; ++rt) {
         const int st = rt >> 1, half = rt & 1;
         // first two gather sources of every update row, ahead of the products
         int32_t s0[4] = {-1, -1, -1, -1}, s1[4] = {-1, -1, -1, -1};
@@ -840,7 +859,7 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
             if (kb < nkb) {
                 double an[8];
                 const bool last = kb + 1 == nkb;
-                if (!last || rt + 1 < mt) {
+                if (!last || rt + 1 < rt1) {
                     const int rn = last ? rt + 1 : rt, kn = last ? 0 : kb + 1;
                     frag_rows(tiles + f.tile_base + tri(f.Mt, f.nsb + (rn >> 1), kn) * TT, rn & 1, false, an);
                 }
@@ -1073,10 +1092,14 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
     TF* ub = reinterpret_cast<TF*>(ubuf);
 #define HSIM_WS(NT)                                                                                              \
     wsolve_shape(ncols, WsolveWaves<NT>::value, WCOLS * WsolveCols<NT>::value, wpg, groups);                                                     \
-    const dim3 grid((unsigned)(cdiv(f1 - f0, NXCD) * NXCD * groups)), block((unsigned)(64 * wpg));              \
+    const int64_t waves = (int64_t)(f1 - f0) * groups * wpg;                                                      \
+    const int32_t splits = fwd && Xin != X                                                                      \
+                               ? (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, WSOLVE_MIN_WAVES / waves))   \
+                               : 1;                                                                              \
+    const dim3 grid((unsigned)(cdiv(f1 - f0, NXCD) * NXCD * groups * splits)), block((unsigned)(64 * wpg));     \
     if (fwd)                                                                                                      \
-        k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, f1 - f0, groups, X, ldx, col0,      \
-                                                    ncols, wpg, ub, ldu, gat, gw, mdiag, Xin);                    \
+        k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, f1 - f0, groups, splits, X, ldx,    \
+                                                    col0, ncols, wpg, ub, ldu, gat, gw, mdiag, Xin);              \
     else                                                                                                          \
         k_wsolve_bwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, D, fronts, f0, f1 - f0, groups, X, ldx, col0,   \
                                                     ncols, wpg, rows, apply_dinv ? 1 : 0);
