@@ -240,15 +240,13 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
                               dptr<double>(D), s));
     HIPCHECK(launch_identity(dptr<double>(V), m, s));
     const double tol_rel = 1e-15, tol_abs_rel = 1e-17;
-    const int32_t nb = m / bj;
     int32_t sweeps = 0;
     // a sweep ends the iteration when it rotated nothing or when no entry is
     // left above the threshold (the next sweep would rotate nothing)
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
         HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 2, 0, s));
-        for (int32_t r = 0; r < nb - 1; ++r)
-            HIPCHECK(launch_bj_round(bj, dptr<double>(C), dptr<double>(V), m, r, dptr<double>(Qs), dptr<double>(normf),
-                                     tol_rel, tol_abs_rel, 1, dptr<int32_t>(rot), s));
+        HIPCHECK(launch_bj_sweep(bj, dptr<double>(C), dptr<double>(V), m, dptr<double>(Qs), dptr<double>(normf),
+                                 tol_rel, tol_abs_rel, 1, dptr<int32_t>(rot), s));
         HIPCHECK(launch_bj_offcount(dptr<double>(C), m, dptr<double>(normf), tol_rel, tol_abs_rel,
                                     dptr<int32_t>(rot) + 1, s));
         int32_t cnt[2] = {0, 0};

@@ -134,16 +134,17 @@ hipError_t launch_dense_to_front(const double* A, int32_t k, double* tiles, int3
 hipError_t launch_transpose(const double* A, int32_t k, double* B, hipStream_t s);
 // C[i, j] = 0.5 (A[i,j] + A[j,i]) * w[i] * w[j] with w = D^-1/2 (k x k)
 hipError_t launch_sym_scale(const double* A, const double* D, int32_t k, double* C, hipStream_t s);
-// Block Jacobi round (block size b = 16, m a multiple of 2b): local
-// 2b x 2b diagonalisations of every block pair (at most inner_sweeps cyclic
-// sweeps; rotation threshold max(tol_abs_rel * normf[0], tol_rel * sqrt(|c_pp c_qq|)),
-// rotations counted into rot_count), then C <- J^T C J and V <- V J.
-// Qs holds (m / 2b) x (2b)^2 doubles.
-hipError_t launch_bj_round(int b, double* C, double* V, int32_t m, int32_t round, double* Qs, const double* normf,
-                           double tol_rel, double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count,
-                           hipStream_t s);
+// One block Jacobi sweep (block size b = 16, m a positive multiple of 2b):
+// m / b - 1 rounds in tournament order; in each, every block
+// pair's 2b x 2b principal submatrix is diagonalised (at most inner_sweeps
+// cyclic sweeps; rotation threshold max(tol_abs_rel * normf[0],
+// tol_rel * sqrt(|c_pp c_qq|)), rotations counted into rot_count), then
+// C <- J^T C J and V <- V J.  Qs: (m / 2b) (2b)^2 doubles (the pairs'
+// orthogonal factors of a round).
+hipError_t launch_bj_sweep(int b, double* C, double* V, int32_t m, double* Qs, const double* normf, double tol_rel,
+                           double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, hipStream_t s);
 // count += number of entries c_pq (p < q) of the symmetric m x m C above the
-// rotation threshold of launch_bj_round (0: another sweep would not rotate)
+// rotation threshold of launch_bj_sweep (0: another sweep would not rotate)
 hipError_t launch_bj_offcount(const double* C, int32_t m, const double* normf, double tol_rel, double tol_abs_rel,
                               int32_t* count, hipStream_t s);
 hipError_t launch_identity(double* V, int32_t m, hipStream_t s);

@@ -837,7 +837,6 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
     frag_rows(tiles + f.tile_base + tri(f.Mt, f.nsb + (rt0 >> 1), 0) * TT, rt0 & 1, false, a);
 #pragma unroll 1
     for (int rt = rt0; rt < rt1; ++rt) {
-        const int st = rt >> 1, half = rt & 1;
         // first two gather sources of every update row, ahead of the products
         int32_t s0[4] = {-1, -1, -1, -1}, s1[4] = {-1, -1, -1, -1};
         if (gath) {
@@ -2440,18 +2439,20 @@ __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double a
 // the round's input, so a round needs one barrier: A is double-buffered (every
 // entry is rewritten each round), Q entries have one owner per round.
 template <int B>
-__global__ __launch_bounds__(B * B) void k_bj_local(const double* __restrict__ C, int32_t m, int32_t r,
-                                                    double* __restrict__ Qs, const double* __restrict__ normf,
-                                                    double tol_rel, double tol_abs_rel, int32_t max_sweeps,
-                                                    int32_t* rot_count) {
+constexpr size_t bj_local_lds() {   // A (double-buffered), Q and a counter
+    return 3 * sizeof(double) * (2 * B) * (2 * B + 1) + 16;
+}
+template <int B>
+__device__ void bj_local_solve(const double* C, int32_t m, int32_t r, int32_t P, double* __restrict__ Qs,
+                               const double* __restrict__ normf, double tol_rel, double tol_abs_rel,
+                               int32_t max_sweeps, int32_t* rot_count, unsigned char* smem_raw) {
     constexpr int W = 2 * B;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     double(*A)[W][W + 1] = reinterpret_cast<double(*)[W][W + 1]>(smem_raw);   // [2][W][W + 1]
     double(*Q)[W + 1] = reinterpret_cast<double(*)[W + 1]>(smem_raw + 2 * sizeof(double) * W * (W + 1));
     int& total = *reinterpret_cast<int*>(smem_raw + 3 * sizeof(double) * W * (W + 1));
     const int nb = m / B;
     int I, J;
-    bj_pair(blockIdx.x, r, nb, I, J);
+    bj_pair(P, r, nb, I, J);
     const double tol_abs2 = tol_abs_rel * normf[0] * tol_abs_rel * normf[0];
     const double tol_rel2 = tol_rel * tol_rel;
     const int tid = threadIdx.x, k1 = tid / B, k2 = tid % B;
@@ -2503,9 +2504,18 @@ __global__ __launch_bounds__(B * B) void k_bj_local(const double* __restrict__ C
         if (now == seen) break;
         seen = now;
     }
-    double* Qo = Qs + (int64_t)blockIdx.x * W * W;
+    double* Qo = Qs + (int64_t)P * W * W;
     for (int idx = tid; idx < W * W; idx += B * B) Qo[idx] = Q[idx / W][idx % W];
     if (tid == 0 && seen) atomicAdd(rot_count, seen);
+    __syncthreads();   // LDS free for the caller
+}
+template <int B>
+__global__ __launch_bounds__(B * B) void k_bj_local(const double* __restrict__ C, int32_t m, int32_t r,
+                                                    double* __restrict__ Qs, const double* __restrict__ normf,
+                                                    double tol_rel, double tol_abs_rel, int32_t max_sweeps,
+                                                    int32_t* rot_count) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    bj_local_solve<B>(C, m, r, blockIdx.x, Qs, normf, tol_rel, tol_abs_rel, max_sweeps, rot_count, smem_raw);
 }
 
 // C <- J^T C J on every (pair, pair') tile (pair <= pair'), V <- V J on row
@@ -2515,10 +2525,9 @@ __global__ __launch_bounds__(B * B) void k_bj_local(const double* __restrict__ C
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result item v of lane l is
 // D[l / 16 + 4 v][l % 16].
 template <int B>
-__global__ __launch_bounds__(B * B) void k_bj_apply(double* C, double* V, int32_t m, int32_t r,
-                                                    const double* __restrict__ Qs) {
+__device__ void bj_apply_item(double* C, double* V, int32_t m, int32_t r, const double* __restrict__ Qs,
+                              double (*X)[2 * B + 1]) {
     constexpr int W = 2 * B, NT = W / 16;   // NT x NT output tiles of 16 x 16, one per wave
-    __shared__ double X[W][W + 1];
     const int nb = m / B, np = nb / 2;
     const int64_t ctiles = (int64_t)np * (np + 1) / 2;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -2582,6 +2591,12 @@ __global__ __launch_bounds__(B * B) void k_bj_apply(double* C, double* V, int32_
         for (int v = 0; v < 4; ++v) V[(row0 + ta * 16 + lk + 4 * v) * m + gcol] = acc[v];
     }
 }
+template <int B>
+__global__ __launch_bounds__(B * B) void k_bj_apply(double* C, double* V, int32_t m, int32_t r,
+                                                    const double* __restrict__ Qs) {
+    __shared__ double X[2 * B][2 * B + 1];
+    bj_apply_item<B>(C, V, m, r, Qs, X);
+}
 
 // Number of off-diagonal entries of the symmetric m x m matrix C that the
 // rotation threshold of k_bj_local would still act on; zero means that a
@@ -2607,24 +2622,26 @@ hipError_t launch_bj_offcount(const double* C, int32_t m, const double* normf, d
 }
 
 template <int B>
-hipError_t bj_round(double* C, double* V, int32_t m, int32_t round, double* Qs, const double* normf, double tol_rel,
+hipError_t bj_sweep(double* C, double* V, int32_t m, double* Qs, const double* normf, double tol_rel,
                     double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, hipStream_t s) {
-    constexpr size_t lds = 3 * sizeof(double) * (2 * B) * (2 * B + 1) + 16;
+    constexpr size_t lds = bj_local_lds<B>();
     hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_bj_local<B>), lds, 0);
     if (e != hipSuccess) return e;
     const int nb = m / B, np = nb / 2;
     const int64_t ctiles = (int64_t)np * (np + 1) / 2;
     const int64_t vitems = (int64_t)(m / (2 * B)) * np;
-    k_bj_local<B><<<np, B * B, lds, s>>>(C, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_bj_apply<B><<<(unsigned)(ctiles + vitems), B * B, 0, s>>>(C, V, m, round, Qs);
-    return hipGetLastError();
+    for (int32_t r = 0; r + 1 < nb; ++r) {
+        k_bj_local<B><<<np, B * B, lds, s>>>(C, m, r, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_bj_apply<B><<<(unsigned)(ctiles + vitems), B * B, 0, s>>>(C, V, m, r, Qs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
-hipError_t launch_bj_round(int b, double* C, double* V, int32_t m, int32_t round, double* Qs, const double* normf,
-                           double tol_rel, double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count,
-                           hipStream_t s) {
-    if (b != 16 || m % (2 * b) != 0) return hipErrorInvalidValue;
-    return bj_round<16>(C, V, m, round, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count, s);
+hipError_t launch_bj_sweep(int b, double* C, double* V, int32_t m, double* Qs, const double* normf, double tol_rel,
+                           double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, hipStream_t s) {
+    if (b != 16 || m % (2 * b) != 0 || m < 2 * b) return hipErrorInvalidValue;
+    return bj_sweep<16>(C, V, m, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count, s);
 }
 
 // V = identity (m x m)
