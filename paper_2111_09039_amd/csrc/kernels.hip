@@ -1290,6 +1290,7 @@ __device__ __forceinline__ void store_rows(const dbl4 (&y)[NTL], double* X, int6
 
 namespace {
 constexpr int BNT = 2 * KBT;   // 16-row tiles of a pivot block
+constexpr int BWI_WAVES = 8;   // waves sharing the struct rows of one backward-init item
 }
 
 // forward diagonal block kb of every listed front: y_blk = L_blk^-1 y_blk (in X)
@@ -1403,14 +1404,16 @@ __global__ __launch_bounds__(512) void k_big_fwd_update(const T* __restrict__ ti
 
 // backward start: z_jb = D^-1 y_jb - sum over struct tiles L(st, jb)^T x_st, in X.  items: (front, jb)
 template <class T>
-__global__ __launch_bounds__(512) void k_big_bwd_init(const T* __restrict__ tilesT, const T* __restrict__ D,
-                                                      const DFront* __restrict__ fr, const int32_t* __restrict__ items,
-                                                      int32_t wpg, double* X, int64_t ldx, int32_t col0, int32_t ncols,
-                                                      const int32_t* __restrict__ rows) {
+__global__ __launch_bounds__(64 * BWI_WAVES) void k_big_bwd_init(const T* __restrict__ tilesT, const T* __restrict__ D,
+                                                                const DFront* __restrict__ fr,
+                                                                const int32_t* __restrict__ items, double* X,
+                                                                int64_t ldx, int32_t col0, int32_t ncols,
+                                                                const int32_t* __restrict__ rows) {
+    // workgroup: (item, 16 columns); wave w sums over its share of the struct
+    // row tiles, the shares are added in wave order through LDS
+    __shared__ dbl4 red[BWI_WAVES][2][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
-    if (cbase >= col0 + ncols) return;
-    const int32_t c = cbase + (lane & 15);
+    const int32_t c = col0 + blockIdx.y * WCOLS + (lane & 15);
     const bool cok = c < col0 + ncols;
     const DFront f = fr[items[2 * blockIdx.x]];
     const int jb = items[2 * blockIdx.x + 1];
@@ -1419,25 +1422,21 @@ __global__ __launch_bounds__(512) void k_big_bwd_init(const T* __restrict__ tile
     const bool two = nrow > 16;
     const int32_t* frows = rows + f.rows_off;
     const int stiles = (f.mu + T32 - 1) / T32;
-    dbl4 z[2];
-    load_rows<2>(z, X, ldx, f.start, r0, r0 + nrow, c, cok);
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + 16 * t + lr + 4 * v;
-            if (r < r0 + nrow) z[t][v] /= (double)D[f.d_base + r];
-        }
+    const int chunk = (stiles + BWI_WAVES - 1) / BWI_WAVES;
+    const int st0 = min(stiles, w * chunk), st1 = min(stiles, st0 + chunk);
+    dbl4 z[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
     // x of the struct rows, eight k-steps of 4 rows per 32-row tile, one tile ahead
     double xs[8], xn[8];
+    if (st0 < st1) {
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-        const int sr = 4 * ks + lr;
-        xs[ks] = (sr < f.mu && cok) ? X[(int64_t)frows[sr] * ldx + c] : 0.0;
+        for (int ks = 0; ks < 8; ++ks) {
+            const int sr = st0 * T32 + 4 * ks + lr;
+            xs[ks] = (sr < f.mu && cok) ? X[(int64_t)frows[sr] * ldx + c] : 0.0;
+        }
     }
 #pragma unroll 1
-    for (int st = 0; st < stiles; ++st) {
-        if (st + 1 < stiles) {
+    for (int st = st0; st < st1; ++st) {
+        if (st + 1 < st1) {
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks) {
                 const int sr = (st + 1) * T32 + 4 * ks + lr;
@@ -1459,7 +1458,25 @@ __global__ __launch_bounds__(512) void k_big_bwd_init(const T* __restrict__ tile
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) xs[ks] = xn[ks];
     }
-    store_rows<2>(z, X, ldx, f.start, r0, r0 + nrow, c, cok);
+    red[w][0][lane] = z[0];
+    red[w][1][lane] = z[1];
+    __syncthreads();
+    if (w != 0) return;
+    // z = D^-1 y - sum of the shares
+    dbl4 y[2];
+    load_rows<2>(y, X, ldx, f.start, r0, r0 + nrow, c, cok);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        dbl4 acc = red[0][t][lane];
+#pragma unroll
+        for (int k = 1; k < BWI_WAVES; ++k) acc += red[k][t][lane];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * t + lr + 4 * v;
+            y[t][v] = r < r0 + nrow ? y[t][v] / (double)D[f.d_base + r] + acc[v] : 0.0;
+        }
+    }
+    store_rows<2>(y, X, ldx, f.start, r0, r0 + nrow, c, cok);
 }
 
 // backward diagonal block kb: x_blk = L_blk^-T z_blk (in X)
@@ -1571,7 +1588,10 @@ hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF
     switch (phase) {
         case 1: k_big_fwd_diag<TF><<<grid, block, 0, s>>>(tiles, linv, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
         case 2: k_big_fwd_update<TF><<<grid, block, 0, s>>>(tiles, fronts, items, wpg, kb, X, ldx, col0, ncols, ub, ldu); break;
-        case 3: k_big_bwd_init<TF><<<grid, block, 0, s>>>(tilesT, D, fronts, items, wpg, X, ldx, col0, ncols, rows); break;
+        case 3:
+            k_big_bwd_init<TF><<<dim3((unsigned)nitems, (unsigned)cdiv(ncols, WCOLS)), 64 * BWI_WAVES, 0, s>>>(
+                tilesT, D, fronts, items, X, ldx, col0, ncols, rows);
+            break;
         case 4: k_big_bwd_diag<TF><<<grid, block, 0, s>>>(tilesT, linvT, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
         case 5: k_big_bwd_update<TF><<<grid, block, 0, s>>>(tilesT, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
         default: return hipErrorInvalidValue;
