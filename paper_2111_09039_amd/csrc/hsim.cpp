@@ -134,6 +134,12 @@ struct DenseGEP {
     int32_t k = 0, m = 0, ns_pad = 0, Mt = 0, bj = 16;
     std::vector<int64_t> diag_ptr, panel_ptr, upd_ptr;
     DeviceBuffer front, tiles, linv, D, items_diag, items_panel, items_upd, gptr, counters;
+    // large problems: triangular solves by the multi-workgroup block solve over
+    // 128-row pivot blocks (transposed tile copies for the backward sweep)
+    bool big = false;
+    int32_t nblk = 0;
+    std::vector<int64_t> fupd_off, fupd_cnt, bupd_off, bupd_cnt;
+    DeviceBuffer tilesT, linvT, big_items;
     DeviceBuffer S2, M2, e, W, W2, C, V, Qs, rot, dis, normf;
 
     void setup(int32_t kk) {
@@ -169,6 +175,34 @@ struct DenseGEP {
         items_diag.upload(dg);
         items_panel.upload(pn.empty() ? std::vector<int32_t>{0, 0} : pn);
         items_upd.upload(up.empty() ? std::vector<int32_t>{0, 0, 0} : up);
+        big = ns_pad >= env_int("HSIM_DENSE_BIG_MIN", 512);
+        if (big) {
+            // items: [0] the front (diagonal phases), then per pivot block the
+            // (front, tile row) pairs below it (forward) and above it (backward)
+            nblk = (Mt + BIG_BLOCK_TILES - 1) / BIG_BLOCK_TILES;
+            std::vector<int32_t> bi{0, 0};
+            fupd_off.assign(nblk, 0);
+            fupd_cnt.assign(nblk, 0);
+            bupd_off.assign(nblk, 0);
+            bupd_cnt.assign(nblk, 0);
+            for (int32_t kb = 0; kb < nblk; ++kb) {
+                fupd_off[kb] = (int64_t)bi.size();
+                for (int32_t r = std::min(Mt, (kb + 1) * BIG_BLOCK_TILES); r < Mt; ++r) {
+                    bi.push_back(0);
+                    bi.push_back(r);
+                }
+                fupd_cnt[kb] = ((int64_t)bi.size() - fupd_off[kb]) / 2;
+                bupd_off[kb] = (int64_t)bi.size();
+                for (int32_t r = 0; r < kb * BIG_BLOCK_TILES; ++r) {
+                    bi.push_back(0);
+                    bi.push_back(r);
+                }
+                bupd_cnt[kb] = ((int64_t)bi.size() - bupd_off[kb]) / 2;
+            }
+            big_items.upload(bi);
+            tilesT.alloc((size_t)Mt * (Mt + 1) / 2 * NB * NB * sizeof(double));
+            linvT.alloc((size_t)Mt * NB * NB * sizeof(double));
+        }
         gptr.upload(std::vector<int64_t>((size_t)k + 1, 0));
         counters.alloc(4 * sizeof(int32_t));
         const size_t kk2 = (size_t)k * k * sizeof(double);
@@ -199,6 +233,11 @@ struct DenseGEP {
             HIPCHECK(launch_fac_update(dptr<double>(tiles), dptr<double>(D), fr,
                                        dptr<int32_t>(items_upd) + 3 * upd_ptr[st], upd_ptr[st + 1] - upd_ptr[st], st, s));
         }
+        if (big) {
+            HIPCHECK(launch_tile_transpose<double>(dptr<double>(tiles), dptr<double>(tilesT),
+                                                   (int64_t)Mt * (Mt + 1) / 2, s));
+            HIPCHECK(launch_tile_transpose<double>(dptr<double>(linv), dptr<double>(linvT), Mt, s));
+        }
     }
 
     int32_t qc_for(int32_t ncols) const {
@@ -207,12 +246,43 @@ struct DenseGEP {
         return qc;
     }
 
+    // the multi-workgroup block solve of the dense front: forward L^-1 X, or
+    // backward L^-T X (no D^-1: the caller scales)
+    void big_sweep(bool forward, double* X, int32_t ncols, int64_t ld, hipStream_t s) {
+        const DFront* fr = dptr<DFront>(front);
+        const int32_t* bi = dptr<int32_t>(big_items);
+        auto run = [&](int phase, int64_t off, int64_t cnt, int32_t kb) {
+            HIPCHECK(launch_big_solve<double>(phase, dptr<double>(tiles), dptr<double>(linv), dptr<double>(D),
+                                              dptr<double>(tilesT), dptr<double>(linvT), fr, bi + off, cnt, kb, X, ld,
+                                              0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s));
+        };
+        if (forward) {
+            for (int32_t kb = 0; kb < nblk; ++kb) {
+                run(1, 0, 1, kb);
+                run(2, fupd_off[kb], fupd_cnt[kb], kb);
+            }
+        } else {
+            for (int32_t kb = nblk - 1; kb >= 0; --kb) {
+                run(4, 0, 1, kb);
+                run(5, bupd_off[kb], bupd_cnt[kb], kb);
+            }
+        }
+    }
+
     void fwd(double* X, int32_t ncols, hipStream_t s) {
+        if (big) {
+            big_sweep(true, X, ncols, k, s);
+            return;
+        }
         const int32_t qc = qc_for(ncols);
         HIPCHECK(launch_solve_fwd<double>(dptr<double>(tiles), dptr<double>(linv), dptr<DFront>(front), 0, 1, ns_pad, X,
                                           ncols, 0, ncols, qc, nullptr, 0, dptr<int64_t>(gptr), nullptr, nullptr, s));
     }
     void bwd(double* X, int32_t ncols, int64_t ld, hipStream_t s) {
+        if (big) {
+            big_sweep(false, X, ncols, ld, s);
+            return;
+        }
         const int32_t qc = qc_for(ncols);
         HIPCHECK(launch_solve_bwd<double>(dptr<double>(tiles), dptr<double>(linv), dptr<double>(D), dptr<DFront>(front),
                                           0, 1, ns_pad, X, ld, 0, ncols, qc, nullptr, false, s));

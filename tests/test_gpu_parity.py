@@ -124,6 +124,15 @@ def test_reduced_eigenproblem(cuda, k):
     _check_reduced_eigenproblem(k)
 
 
+@pytest.mark.parametrize("k", [96, 130])
+def test_reduced_eigenproblem_block_solves(cuda, k, monkeypatch):
+    """Dense problems from 512 unknowns on solve their triangular systems with
+    the multi-workgroup block solve; the switch point is lowered here so that
+    the oracle's dense Jacobi stays quick."""
+    monkeypatch.setenv("HSIM_DENSE_BIG_MIN", "64")
+    _check_reduced_eigenproblem(k)
+
+
 def test_coarsest_dense_solve(small):
     V, F, S, m, lv, H = small
     k = H.q
