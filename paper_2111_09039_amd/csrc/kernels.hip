@@ -2466,7 +2466,12 @@ template <int B>
 __device__ void bj_local_solve(const double* C, int32_t m, int32_t r, int32_t P, double* __restrict__ Qs,
                                const double* __restrict__ normf, double tol_rel, double tol_abs_rel,
                                int32_t max_sweeps, int32_t* rot_count, unsigned char* smem_raw) {
-    constexpr int W = 2 * B;
+    // 2 b^2 threads: thread (k1, k2) < b^2 owns the 2 x 2 block {p_k1, q_k1} x
+    // {p_k2, q_k2} of A, thread b^2 + (k1, k2) the entries {k1, k1 + b} x
+    // {p_k2, q_k2} of Q; both compute the rotations they need from the step's
+    // input, so a step needs one barrier (A double-buffered, Q entries with one
+    // owner per step)
+    constexpr int W = 2 * B, NT = B * B;
     double(*A)[W][W + 1] = reinterpret_cast<double(*)[W][W + 1]>(smem_raw);   // [2][W][W + 1]
     double(*Q)[W + 1] = reinterpret_cast<double(*)[W + 1]>(smem_raw + 2 * sizeof(double) * W * (W + 1));
     int& total = *reinterpret_cast<int*>(smem_raw + 3 * sizeof(double) * W * (W + 1));
@@ -2475,8 +2480,10 @@ __device__ void bj_local_solve(const double* C, int32_t m, int32_t r, int32_t P,
     bj_pair(P, r, nb, I, J);
     const double tol_abs2 = tol_abs_rel * normf[0] * tol_abs_rel * normf[0];
     const double tol_rel2 = tol_rel * tol_rel;
-    const int tid = threadIdx.x, k1 = tid / B, k2 = tid % B;
-    for (int idx = tid; idx < W * W; idx += B * B) {
+    const int tid = threadIdx.x;
+    const bool qthread = tid >= NT;
+    const int tt = qthread ? tid - NT : tid, k1 = tt / B, k2 = tt % B;
+    for (int idx = tid; idx < W * W; idx += 2 * NT) {
         const int a = idx / W, c = idx % W;
         A[0][a][c] = C[(int64_t)bj_index<B>(a, I, J) * m + bj_index<B>(c, I, J)];
         Q[a][c] = a == c ? 1.0 : 0.0;
@@ -2487,34 +2494,43 @@ __device__ void bj_local_solve(const double* C, int32_t m, int32_t r, int32_t P,
     for (int sw = 0; sw < max_sweeps; ++sw) {
         int mine = 0;
         for (int rr = 0; rr < W - 1; ++rr) {
-            const int a1 = jac_player(k1, rr, W), b1 = jac_player(W - 1 - k1, rr, W);
             const int a2 = jac_player(k2, rr, W), b2 = jac_player(W - 1 - k2, rr, W);
-            const int p1 = min(a1, b1), q1 = max(a1, b1), p2 = min(a2, b2), q2 = max(a2, b2);
+            const int p2 = min(a2, b2), q2 = max(a2, b2);
             const double(*Ac)[W + 1] = A[cur];
-            double(*An)[W + 1] = A[cur ^ 1];
-            const double d1p = Ac[p1][p1], d1q = Ac[q1][q1], o1 = Ac[p1][q1];
-            const double d2p = Ac[p2][p2], d2q = Ac[q2][q2], o2 = Ac[p2][q2];
-            const double x00 = Ac[p1][p2], x01 = Ac[p1][q2], x10 = Ac[q1][p2], x11 = Ac[q1][q2];
-            const double u0 = Q[k1][p2], v0 = Q[k1][q2], u1 = Q[k1 + B][p2], v1 = Q[k1 + B][q2];
-            double c1, s1, c2, s2;
-            const bool rot1 = jacobi_rotation(d1p, d1q, o1, tol_abs2, tol_rel2, c1, s1);
-            jacobi_rotation(d2p, d2q, o2, tol_abs2, tol_rel2, c2, s2);
-            const double t00 = c1 * x00 - s1 * x10, t01 = c1 * x01 - s1 * x11;
-            const double t10 = s1 * x00 + c1 * x10, t11 = s1 * x01 + c1 * x11;
-            An[p1][p2] = c2 * t00 - s2 * t01;
-            An[q1][q2] = s2 * t10 + c2 * t11;
-            if (k1 == k2 && rot1) {
-                ++mine;
-                An[p1][q2] = 0.0;
-                An[q1][p2] = 0.0;
+            if (qthread) {
+                // Q <- Q J on rows k1 and k1 + b
+                const double d2p = Ac[p2][p2], d2q = Ac[q2][q2], o2 = Ac[p2][q2];
+                const double u0 = Q[k1][p2], v0 = Q[k1][q2], u1 = Q[k1 + B][p2], v1 = Q[k1 + B][q2];
+                double c2, s2;
+                jacobi_rotation(d2p, d2q, o2, tol_abs2, tol_rel2, c2, s2);
+                Q[k1][p2] = u0 * c2 - v0 * s2;
+                Q[k1][q2] = u0 * s2 + v0 * c2;
+                Q[k1 + B][p2] = u1 * c2 - v1 * s2;
+                Q[k1 + B][q2] = u1 * s2 + v1 * c2;
             } else {
-                An[p1][q2] = s2 * t00 + c2 * t01;
-                An[q1][p2] = c2 * t10 - s2 * t11;
+                // A <- J^T A J on the 2 x 2 block of pairs k1, k2
+                const int a1 = jac_player(k1, rr, W), b1 = jac_player(W - 1 - k1, rr, W);
+                const int p1 = min(a1, b1), q1 = max(a1, b1);
+                double(*An)[W + 1] = A[cur ^ 1];
+                const double d1p = Ac[p1][p1], d1q = Ac[q1][q1], o1 = Ac[p1][q1];
+                const double d2p = Ac[p2][p2], d2q = Ac[q2][q2], o2 = Ac[p2][q2];
+                const double x00 = Ac[p1][p2], x01 = Ac[p1][q2], x10 = Ac[q1][p2], x11 = Ac[q1][q2];
+                double c1, s1, c2, s2;
+                const bool rot1 = jacobi_rotation(d1p, d1q, o1, tol_abs2, tol_rel2, c1, s1);
+                jacobi_rotation(d2p, d2q, o2, tol_abs2, tol_rel2, c2, s2);
+                const double t00 = c1 * x00 - s1 * x10, t01 = c1 * x01 - s1 * x11;
+                const double t10 = s1 * x00 + c1 * x10, t11 = s1 * x01 + c1 * x11;
+                An[p1][p2] = c2 * t00 - s2 * t01;
+                An[q1][q2] = s2 * t10 + c2 * t11;
+                if (k1 == k2 && rot1) {
+                    ++mine;
+                    An[p1][q2] = 0.0;
+                    An[q1][p2] = 0.0;
+                } else {
+                    An[p1][q2] = s2 * t00 + c2 * t01;
+                    An[q1][p2] = c2 * t10 - s2 * t11;
+                }
             }
-            Q[k1][p2] = u0 * c2 - v0 * s2;
-            Q[k1][q2] = u0 * s2 + v0 * c2;
-            Q[k1 + B][p2] = u1 * c2 - v1 * s2;
-            Q[k1 + B][q2] = u1 * s2 + v1 * c2;
             cur ^= 1;
             __syncthreads();
         }
@@ -2525,12 +2541,12 @@ __device__ void bj_local_solve(const double* C, int32_t m, int32_t r, int32_t P,
         seen = now;
     }
     double* Qo = Qs + (int64_t)P * W * W;
-    for (int idx = tid; idx < W * W; idx += B * B) Qo[idx] = Q[idx / W][idx % W];
+    for (int idx = tid; idx < W * W; idx += 2 * NT) Qo[idx] = Q[idx / W][idx % W];
     if (tid == 0 && seen) atomicAdd(rot_count, seen);
     __syncthreads();   // LDS free for the caller
 }
 template <int B>
-__global__ __launch_bounds__(B * B) void k_bj_local(const double* __restrict__ C, int32_t m, int32_t r,
+__global__ __launch_bounds__(2 * B * B) void k_bj_local(const double* __restrict__ C, int32_t m, int32_t r,
                                                     double* __restrict__ Qs, const double* __restrict__ normf,
                                                     double tol_rel, double tol_abs_rel, int32_t max_sweeps,
                                                     int32_t* rot_count) {
@@ -2651,7 +2667,7 @@ hipError_t bj_sweep(double* C, double* V, int32_t m, double* Qs, const double* n
     const int64_t ctiles = (int64_t)np * (np + 1) / 2;
     const int64_t vitems = (int64_t)(m / (2 * B)) * np;
     for (int32_t r = 0; r + 1 < nb; ++r) {
-        k_bj_local<B><<<np, B * B, lds, s>>>(C, m, r, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
+        k_bj_local<B><<<np, 2 * B * B, lds, s>>>(C, m, r, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_bj_apply<B><<<(unsigned)(ctiles + vitems), B * B, 0, s>>>(C, V, m, r, Qs);
         if ((e = hipGetLastError()) != hipSuccess) return e;
