@@ -148,12 +148,15 @@ hipError_t launch_copy2d(const double* in, int64_t ldi, int64_t rows, int32_t k,
 }
 
 // ====================================================================== SpMM
-// Y = (a A + b B) X for CSR A, B on one pattern (B optional): one wave per
-// row, 64 lanes over the columns.  The edges of a row are fetched 8 at a time
-// (index and weight by one lane each, broadcast by shuffles) and the X rows
-// of all 8 are loaded at once (missing edges read the row itself with weight
-// zero).  Workgroups are spread so that each XCD takes one contiguous eighth
-// of the rows: neighbouring rows share their X rows in that XCD's L2.
+// Y = (a A + b B) X for CSR A, B on one pattern (B optional; A may be
+// rectangular): one wave per row, 64 lanes over the columns.  The edges of a
+// row are fetched 8 at a time (index and weight by one lane each, broadcast by
+// shuffles) and the X rows of the batch are loaded at once.  The edge count of
+// a batch is the same for the whole wave; slots past it load nothing and add
+// nothing, so only X rows named by the pattern are ever read (a zero weight
+// times an unrelated row would still turn a non-finite value there into NaN).
+// Workgroups are spread so that each XCD takes one contiguous eighth of the
+// rows: neighbouring rows share their X rows in that XCD's L2.
 __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                               const double* __restrict__ va, const double* __restrict__ vb, double a,
                                               double b, int64_t rows, const double* __restrict__ X, int64_t ldx,
@@ -167,8 +170,8 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr, c
     for (int c0 = 0; c0 < k; c0 += 256) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t eb = e0; eb < e1; eb += 8) {
-            const int cnt = (int)min<int64_t>(8, e1 - eb);
-            int my_col = (int)row;
+            const int cnt = (int)min<int64_t>(8, e1 - eb);   // wave-uniform
+            int my_col = 0;
             double my_w = 0.0;
             if (lane < cnt) {
                 my_col = idx[eb + lane];
@@ -177,18 +180,21 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr, c
             double xv[8][4];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const double* xr = X + (int64_t)__shfl(my_col, j) * ldx;
+                const int col = __shfl(my_col, j);
+                const double* xr = X + (int64_t)col * ldx;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int c = c0 + lane + 64 * u;
-                    xv[j][u] = c < k ? xr[c] : 0.0;
+                    xv[j][u] = j < cnt && c < k ? xr[c] : 0.0;
                 }
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const double w = __shfl(my_w, j);
+                if (j < cnt) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc[u] += w * xv[j][u];
+                    for (int u = 0; u < 4; ++u) acc[u] += w * xv[j][u];
+                }
             }
         }
 #pragma unroll
@@ -2691,6 +2697,14 @@ hipError_t launch_identity(double* V, int32_t m, hipStream_t s) {
     return hipGetLastError();
 }
 
+// (a, i) before (b, j) in ascending order of value, NaN after every number,
+// ties by index: a strict total order, so the ranks below are a permutation
+// of 0 .. kvalid - 1 whatever the values (every order[j] gets written)
+__device__ __forceinline__ bool sort_before(double a, int i, double b, int j) {
+    const bool na = a != a, nb = b != b;
+    if (na || nb) return na && nb ? i < j : nb;
+    return a < b || (a == b && i < j);
+}
 // ascending order of the diagonal of C (ties by index); X[r, j] = scale[r] Y[r, order[j]]
 __global__ __launch_bounds__(1024) void k_sort_eig(const double* C, int32_t m, int32_t kvalid, const double* Y,
                                                    int32_t rows, const double* scale, int32_t kout, double* lam_out,
@@ -2700,10 +2714,7 @@ __global__ __launch_bounds__(1024) void k_sort_eig(const double* C, int32_t m, i
     for (int i = threadIdx.x; i < kvalid; i += blockDim.x) {
         const double li = C[(int64_t)i * m + i];
         int rank = 0;
-        for (int j = 0; j < kvalid; ++j) {
-            const double lj = C[(int64_t)j * m + j];
-            rank += (lj < li) || (lj == li && j < i);
-        }
+        for (int j = 0; j < kvalid; ++j) rank += sort_before(C[(int64_t)j * m + j], j, li, i);
         if (rank < kout) {
             order[rank] = i;
             lam_out[rank] = li;
@@ -2719,6 +2730,7 @@ __global__ __launch_bounds__(1024) void k_sort_eig(const double* C, int32_t m, i
 }
 hipError_t launch_sort_eig(const double* C, int32_t m, int32_t kvalid, const double* Y, int32_t rows,
                            const double* scale, int32_t kout, double* lam_out, double* X, int64_t ldx, hipStream_t s) {
+    if (kout <= 0 || kout > kvalid || kvalid > m) return hipErrorInvalidValue;   // every order[j] must have a source
     k_sort_eig<<<1, 1024, (size_t)kout * sizeof(int), s>>>(C, m, kvalid, Y, rows, scale, kout, lam_out, X, ldx);
     return hipGetLastError();
 }

@@ -51,6 +51,24 @@ def test_prolongation(small):
             assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max(), (tau, k)
 
 
+def test_prolongation_ignores_stale_workspace_rows(small):
+    # the coarse block occupies only the first n_coarse rows of the shared
+    # workspace; rows past it hold whatever an earlier call left there
+    # (here +inf from a level-0 product), and the prolongation must not touch
+    # them (a zero weight times inf would be NaN)
+    V, F, S, m, lv, H = small
+    rng = np.random.default_rng(3)
+    for tau in range(2):
+        n, nc = len(lv[tau]["verts"]), len(lv[tau + 1]["verts"])
+        k = 13
+        H.apply(0, 1, _t(np.full((len(lv[0]["verts"]), k), np.inf)))
+        Xc = rng.standard_normal((nc, k))
+        Y = H.prolong(tau, _t(Xc)).cpu().numpy()
+        assert np.isfinite(Y).all(), tau
+        ref = lv[tau]["U"] @ Xc
+        assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max(), tau
+
+
 def test_operator_products(small):
     V, F, S, m, lv, H = small
     rng = np.random.default_rng(1)
