@@ -2037,7 +2037,7 @@ hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi
 namespace {
 constexpr int RZ_RB = 64;            // rows per block
 constexpr int RZ_KMAX = 32;          // contraction columns per stage (16 with M Psi: LDS)
-constexpr int RZ_LD = RZ_KMAX + 1;   // LDS row stride of the row stage (odd: conflict-free A reads)
+constexpr int RZ_LD = RZ_KMAX + 2;   // LDS row stride of the row stage (16-byte rows, conflict-free 16-byte reads)
 constexpr int RZ_COLS = 160;         // output columns per workgroup
 constexpr int RZ_BLD = RZ_COLS;      // LDS row stride of the Phibar stage
 constexpr int RZ_THREADS = 512;
@@ -2157,38 +2157,43 @@ __global__ __launch_bounds__(RZ_THREADS) void k_ritz_mfma(const double* __restri
     for (int64_t st = 0; st < nst; ++st) {
         if (st + 1 < nst) fetch(st + 1);
         const double* L = lds + (st & 1) * BUF;
-        const double* Ar = L + (wr * 16 + li) * RZ_LD + lk;
-        // operands of 4 contraction columns: A rows of Psi, S Psi (M Psi) and
-        // the B chunk of every tile of this wave
-        struct Ops {
-            double p, s, m, b[RZ_SL];
+        // contraction column k of step s of 16-column chunk h is 16 h + 4 g + s
+        // for lane group g, so the A operands of a lane for a whole chunk are
+        // 4 consecutive values of its row (two 16-byte reads per matrix)
+        const double* Ar = L + (wr * 16 + li) * RZ_LD + 4 * lk;
+        auto apair = [&](int h, int j, int mat) {
+            return *reinterpret_cast<const dbl2*>(Ar + mat * AM + 16 * h + 2 * j);
         };
-        auto operands = [&](int kk, Ops& o) {
-            o.p = Ar[kk];
-            o.s = Ar[AM + kk];
-            o.m = HAS_M ? Ar[2 * AM + kk] : 0.0;
-            const double* Br = L + BOFF + (kk + lk) * RZ_BLD + li;
+        auto bops = [&](int k, double(&b)[RZ_SL]) {
+            const double* Br = L + BOFF + k * RZ_BLD + li;
 #pragma unroll
             for (int u = 0; u < RZ_SL; ++u)
-                if (u < ntw) o.b[u] = Br[16 * tile[u]];
+                if (u < ntw) b[u] = Br[16 * tile[u]];
         };
-        auto products = [&](const Ops& o) {
+        auto products = [&](double p, double q, double mm, const double(&b)[RZ_SL]) {
 #pragma unroll
             for (int u = 0; u < RZ_SL; ++u)
                 if (u < ntw) {
-                    aP[u] = mfma4(o.p, o.b[u], aP[u]);
-                    if (tile[u] < ns) aS[u] = mfma4(o.s, o.b[u], aS[u]);
-                    if (HAS_M) aM[u] = mfma4(o.m, o.b[u], aM[u]);
+                    aP[u] = mfma4(p, b[u], aP[u]);
+                    if (tile[u] < ns) aS[u] = mfma4(q, b[u], aS[u]);
+                    if (HAS_M) aM[u] = mfma4(mm, b[u], aM[u]);
                 }
         };
-        Ops o0, o1;
-        operands(0, o0);
 #pragma unroll
-        for (int kk = 0; kk < RZ_K; kk += 8) {
-            operands(kk + 4, o1);
-            products(o0);
-            if (kk + 8 < RZ_K) operands(kk + 8, o0);
-            products(o1);
+        for (int h = 0; h < RZ_K / 16; ++h) {
+            const dbl2 pa = apair(h, 0, 0), sa = apair(h, 0, 1);
+            const dbl2 ma = HAS_M ? apair(h, 0, 2) : dbl2{0, 0};
+            double b0[RZ_SL], b1[RZ_SL];
+            bops(16 * h + 4 * lk, b0);
+            bops(16 * h + 4 * lk + 1, b1);
+            const dbl2 pc = apair(h, 1, 0), sc = apair(h, 1, 1);
+            const dbl2 mc = HAS_M ? apair(h, 1, 2) : dbl2{0, 0};
+            products(pa[0], sa[0], ma[0], b0);
+            bops(16 * h + 4 * lk + 2, b0);
+            products(pa[1], sa[1], ma[1], b1);
+            bops(16 * h + 4 * lk + 3, b1);
+            products(pc[0], sc[0], mc[0], b0);
+            products(pc[1], sc[1], mc[1], b1);
         }
         if ((int)(st % nk) == nk - 1) {
             // block finished: Phi (and M Phi) out, residual sums (one tile at a
