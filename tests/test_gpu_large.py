@@ -101,3 +101,42 @@ def test_sphere1m_bench_configuration(cuda):
             ev64 = ev
         else:
             assert np.abs(ev - ev64)[1:].max() <= 1e-6 * ev64[1:].min()
+
+
+def test_large_p_hsim(cuda):
+    """p = 1000 (q = 1500; three levels by the paper's rule for p > 200; a
+    1500-vertex coarsest level): the large-p regime.  The 5,000-vertex noisy
+    torus keeps the dense FP64 reference (LAPACK, lowest 1000 pairs) at about
+    15 s of CPU; its spectrum has near-degenerate pairs (relative gaps down to
+    1e-4), so eigenvectors are compared cluster by cluster."""
+    import time
+
+    import scipy.linalg as sla
+    import torch
+
+    import paper_2111_09039_amd as hs
+    rng = np.random.default_rng(21)
+    V, F = synth.torus(100, 50)
+    V = synth.isotropic_noise(V, F, 0.2 * synth.mean_edge_length(V, F), rng)
+    S, m = assembly.assemble(V, F)
+    p = 1000
+    H = hs.Hierarchy(V, F, p)
+    sizes = [H.level_info(t)["n"] for t in range(H.levels)]
+    assert H.levels == 3 and sizes[-1] == 1500, sizes
+    t0 = time.perf_counter()
+    ev, X, r, st = H.solve(tol=1e-9)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[large p] levels {sizes} q {st['q']} iters {st['iters']} solve {dt * 1e3:.1f} ms", flush=True)
+    ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
+    lr, Xr = sla.eigh(S.toarray(), np.diag(m), subset_by_index=[0, p + 99], driver="gvx")
+    rel = np.abs(ev - lr[:p])[1:] / lr[1:p]
+    assert rel.max() <= 1e-9, rel.max()
+    assert abs(ev[0]) <= 1e-9 * lr[1]
+    assert r.max() < 1e-9
+    assert metrics.m_orthonormality(X, m) < 1e-10
+    assert sim.residual(S, m, X, ev).max() < 2e-9
+    # clusters: relative gaps below 1e-4; a residual of 1e-9 bounds the error of
+    # a pair separated by more than that by about 1e-5
+    err = metrics.eigenvector_err(X, Xr, m, lr, gap=1e-4)
+    assert err.max() < 1e-4, err.max()
