@@ -131,6 +131,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nu", type=int, default=324, help="geodesic frequency (324 -> 1,049,762 vertices)")
     ap.add_argument("--p", type=int, default=100)
+    ap.add_argument("--levels", type=int, default=0, help="T; 0 = the paper's rule (2 for p <= 200, else 3)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -151,7 +152,7 @@ def main():
     V, F, dens = synth.config_mesh("sphere1m", seed=0, nu=args.nu)
     log(f"mesh {len(V)} vertices, {len(F)} triangles ({time.perf_counter() - t:.1f} s)")
     t = time.perf_counter()
-    H = hs.Hierarchy(V, F, args.p, density=dens, levels=2)
+    H = hs.Hierarchy(V, F, args.p, density=dens, levels=args.levels or (2 if args.p <= 200 else 3))
     t_build = time.perf_counter() - t
     log(f"hierarchy built in {t_build:.1f} s: levels {H.levels}, q {H.q}")
     info0 = H.level_info(0)
