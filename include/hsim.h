@@ -63,7 +63,12 @@ typedef struct {
     double support_sigma;  /* sigma of eq. (radius); default 7                                     */
     uint64_t seed;         /* start vertex of Algorithm 3 = seed mod n                              */
     int32_t flags;         /* HSIM_BUILD_HOST_ONLY: build on the host only (inspection; no solve)   */
-    int32_t reserved;
+    int32_t boundary;      /* mesh boundary (edges of one triangle): 0 natural (Neumann) condition;
+                              1 Dirichlet: boundary vertices held at zero, dropped from level 0 (its
+                              S, lumped M and the rows of U^0); the coarser levels are sampled and
+                              built as without boundary and get their operators from the restricted
+                              level 0 (the paper's surfaces-with-boundary experiments use the same
+                              hierarchy and basis construction)                                   */
 } hsim_build_opts;
 
 enum { HSIM_BUILD_HOST_ONLY = 1 };
@@ -173,7 +178,8 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
  *   d_evals  device, [p] ascending eigenvalues
  *   d_evecs  device, [nv x p] column-major (eigenvector k contiguous), mesh
  *            vertex order, M-orthonormal; each column's largest-magnitude
- *            entry is positive (lowest index on ties)
+ *            entry is positive (lowest index on ties); with the Dirichlet
+ *            boundary option the boundary vertices' entries are zero
  *   d_resid  device, [p] final relative residuals (finest level), or NULL
  *   stats    host, or NULL
  * HSIM_E_NOCONV still fills evals/evecs/resid with the last iterate.
@@ -193,6 +199,8 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
  *   d_grad_evals  device, [p] dL/dlambda, or NULL
  *   d_grad_evecs  device, [nv x p] column-major dL/dX, or NULL
  *   d_grad_V      device, [nv x 3] row-major, overwritten with dL/dV
+ * HSIM_E_UNIMPLEMENTED for a hierarchy built with the Dirichlet boundary
+ * option or with circumcentric lumping.
  */
 hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals,
                                 const double* d_grad_evecs, double* d_grad_V, void* stream);

@@ -17,6 +17,11 @@ Readings
   m_i = sum_t (|e_ij|^2 cot(theta_k) + |e_ik|^2 cot(theta_j)) / 8, exact for the
   flat grid pin (it assumes non-obtuse triangles).
 * An optional per-vertex density multiplies m_i.
+* Surfaces with boundary (Section 5, paragraph "Surface with boundary"): the
+  natural (Neumann) condition needs nothing beyond the assembly above; the
+  Dirichlet condition u = 0 on the boundary keeps the interior vertices only,
+  i.e. the principal submatrix of S and the lumped masses there.  Boundary
+  vertices are the endpoints of edges that belong to exactly one triangle.
 """
 from __future__ import annotations
 
@@ -114,3 +119,22 @@ def consistent_mass(V, F):
             vals.append(A / 6.0 if a == b else A / 12.0)
     return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(n, n)).tocsr()
+
+
+def boundary_vertices(F, nv):
+    """Boolean mask of the vertices on the mesh boundary (endpoints of edges
+    that belong to exactly one triangle)."""
+    F = np.asarray(F, dtype=np.int64)
+    E = np.sort(np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]]), axis=1)
+    edges, count = np.unique(E, axis=0, return_counts=True)
+    on = np.zeros(nv, dtype=bool)
+    on[edges[count == 1].ravel()] = True
+    return on
+
+
+def dirichlet(S, m, F):
+    """(S_II, m_I, interior): the Dirichlet problem on the interior vertices
+    (ascending mesh indices) of the mesh with triangles F."""
+    interior = np.flatnonzero(~boundary_vertices(F, S.shape[0]))
+    S = sp.csr_matrix(S)
+    return S[interior][:, interior].tocsr(), np.asarray(m)[interior], interior

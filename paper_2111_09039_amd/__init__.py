@@ -51,7 +51,7 @@ class Hierarchy:
     current device."""
 
     def __init__(self, V, F, p, density=None, levels=0, n_coarsest=0, growth_mode=0, lumping=0,
-                 support_sigma=7.0, seed=0, host_only=False):
+                 support_sigma=7.0, seed=0, host_only=False, boundary="neumann"):
         lib = _lib.load()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -65,6 +65,10 @@ class Hierarchy:
         o.p, o.levels, o.n_coarsest, o.growth_mode = int(p), int(levels), int(n_coarsest), int(growth_mode)
         o.lumping, o.support_sigma, o.seed = int(lumping), float(support_sigma), int(seed)
         o.flags = 1 if host_only else 0
+        bc = {"neumann": 0, "natural": 0, "dirichlet": 1}
+        if boundary not in bc:
+            raise ValueError("boundary must be 'neumann' or 'dirichlet'")
+        o.boundary = bc[boundary]
         h = C.c_void_p()
         _lib.check(lib.hsim_build_hierarchy(V.ctypes.data_as(C.c_void_p), len(V), F.ctypes.data_as(C.c_void_p),
                                             len(F), None if d is None else d.ctypes.data_as(C.c_void_p),

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libhsim.so")
 class BuildOpts(C.Structure):
     _fields_ = [("p", C.c_int32), ("levels", C.c_int32), ("n_coarsest", C.c_int32), ("growth_mode", C.c_int32),
                 ("lumping", C.c_int32), ("support_sigma", C.c_double), ("seed", C.c_uint64),
-                ("flags", C.c_int32), ("reserved", C.c_int32)]
+                ("flags", C.c_int32), ("boundary", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

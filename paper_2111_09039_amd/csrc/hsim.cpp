@@ -367,6 +367,7 @@ struct Level {
     std::vector<TLev> tl;
     // device, internal (elimination) order
     DeviceBuffer dS_ptr, dS_idx, dS_val, dM_val, dmdiag, dU_ptr, dU_idx, dU_val, dperm;
+    DeviceBuffer dmeshmap;   // level 0: mesh vertex of every internal row
     DeviceBuffer dfronts, tiles, linv, D, tiles32, linv32, D32, counters;
     DeviceBuffer tilesT, linvT, tiles32T, linv32T;   // tile-transposed copies for the backward sweeps
     DeviceBuffer asm_dst, asm_src, it_diag, it_panel, it_upd, it_ea, rel, rows, gat;
@@ -439,6 +440,11 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
     L.dS_val.upload(sv);
     L.dM_val.upload(mv);
     L.dperm.upload(perm);
+    if (L.tau == 0) {
+        std::vector<int32_t> mm(n);
+        for (int64_t k = 0; k < n; ++k) mm[k] = L.verts[perm[k]];
+        L.dmeshmap.upload(mm);
+    }
     if (!L.mdiag.empty()) {
         std::vector<double> md(n);
         for (int64_t k = 0; k < n; ++k) md[k] = L.mdiag[perm[k]];
@@ -1002,14 +1008,24 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
     }
     validate_mesh(m);
     Graph g = edge_graph(m);
+    if (bo.boundary != 0 && bo.boundary != 1) fail(HSIM_E_INVALID, "boundary must be 0 (natural) or 1 (Dirichlet)");
+    // level-0 unknowns: every vertex, or (Dirichlet) the vertices off the boundary
+    std::vector<int32_t> dofs;
+    {
+        const std::vector<char> onb = bo.boundary == 1 ? boundary_vertex_flags(m) : std::vector<char>(nv, 0);
+        for (int64_t i = 0; i < nv; ++i)
+            if (!onb[i]) dofs.push_back((int32_t)i);
+    }
+    const int64_t n0 = (int64_t)dofs.size();
+    const bool restricted = n0 < nv;
     const int32_t p = bo.p;
     if (p < 1) fail(HSIM_E_INVALID, "p must be >= 1");
     const int32_t q = std::max<int32_t>((int32_t)std::ceil(1.5 * p), p + 8);
-    if (q >= nv) fail(HSIM_E_INVALID, "subspace size q=%d must be below the vertex count %lld", q, (long long)nv);
+    if (q >= n0) fail(HSIM_E_INVALID, "subspace size q=%d must be below the unknown count %lld", q, (long long)n0);
     int T = bo.levels ? bo.levels : (p <= 200 ? 2 : 3);
     if (T < 2 || T > HSIM_MAX_LEVELS) fail(HSIM_E_INVALID, "levels must be in [2, %d]", HSIM_MAX_LEVELS);
     int64_t nc = bo.n_coarsest ? bo.n_coarsest : std::max<int64_t>((int64_t)std::ceil(1.5 * p), 1000);
-    nc = std::min<int64_t>(nc, nv);
+    nc = std::min<int64_t>(nc, n0);
     if (nc < q) fail(HSIM_E_INVALID, "coarsest level (%lld) smaller than the subspace size %d", (long long)nc, q);
     if (!(bo.support_sigma > 0)) fail(HSIM_E_INVALID, "support_sigma must be positive");
     if (bo.lumping != 0 && bo.lumping != 1) fail(HSIM_E_INVALID, "lumping must be 0 or 1");
@@ -1018,7 +1034,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
     H->T = T;
     H->ld = (int32_t)round_up(q, 8);
     H->area = surface_area(m);
-    std::vector<int64_t> sizes = level_sizes(nv, T, nc, bo.growth_mode);
+    std::vector<int64_t> sizes = level_sizes(n0, T, nc, bo.growth_mode);
     for (int t = 1; t < T; ++t)
         if (sizes[t] >= sizes[t - 1]) fail(HSIM_E_INVALID, "level %d is not smaller than level %d (too many levels for this mesh)", t, t - 1);
     std::vector<int32_t> order = farthest_point_sampling(g, nv, sizes[1], bo.seed);
@@ -1029,8 +1045,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         L->n = sizes[t];
         L->coarsest = t == T - 1;
         if (t == 0) {
-            L->verts.resize(nv);
-            std::iota(L->verts.begin(), L->verts.end(), 0);
+            L->verts = dofs;
         } else {
             L->verts.assign(order.begin(), order.begin() + sizes[t]);
         }
@@ -1040,15 +1055,46 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         Level& L0 = *H->lv[0];
         L0.S = cotan_stiffness(m);
         L0.mdiag = lumped_mass(m, bo.lumping, density);
+        if (restricted) {
+            // Dirichlet: the principal submatrix of S and the lumped masses on the unknowns
+            std::vector<int32_t> pos(nv, -1);
+            for (int64_t k = 0; k < n0; ++k) pos[dofs[k]] = (int32_t)k;
+            Csr R;
+            R.rows = R.cols = n0;
+            R.ptr.assign(n0 + 1, 0);
+            std::vector<double> md(n0);
+            for (int64_t k = 0; k < n0; ++k) {
+                const int32_t v = dofs[k];
+                for (int64_t e = L0.S.ptr[v]; e < L0.S.ptr[v + 1]; ++e)
+                    if (pos[L0.S.idx[e]] >= 0) {
+                        R.idx.push_back(pos[L0.S.idx[e]]);
+                        R.val.push_back(L0.S.val[e]);
+                    }
+                R.ptr[k + 1] = (int64_t)R.idx.size();
+                md[k] = L0.mdiag[v];
+            }
+            L0.S = std::move(R);
+            L0.mdiag = std::move(md);
+        }
         L0.Mval.assign(L0.S.nnz(), 0.0);
-        for (int64_t i = 0; i < nv; ++i)
+        for (int64_t i = 0; i < n0; ++i)
             for (int64_t e = L0.S.ptr[i]; e < L0.S.ptr[i + 1]; ++e)
                 if (L0.S.idx[e] == i) L0.Mval[e] = L0.mdiag[i];
     }
     for (int t = 0; t + 1 < T; ++t) {
         Level& L = *H->lv[t];
         Level& C = *H->lv[t + 1];
-        L.U = prolongation(g, nv, L.verts, t == 0, C.verts, bo.support_sigma, H->area, &L.rho);
+        L.U = prolongation(g, nv, L.verts, t == 0 && !restricted, C.verts, bo.support_sigma, H->area, &L.rho);
+        if (t == 0 && restricted) {
+            // a coarse basis function with no unknown in its support would make the
+            // Galerkin operators singular
+            std::vector<char> hit(C.n, 0);
+            for (int32_t c : L.U.idx) hit[c] = 1;
+            for (int64_t c = 0; c < C.n; ++c)
+                if (!hit[c])
+                    fail(HSIM_E_INVALID, "coarse vertex %d has no interior vertex within its support radius",
+                         C.verts[c]);
+        }
         galerkin(L.U, L.S, L.Mval, C.S, C.Mval);
     }
     for (int t = 0; t + 1 < T; ++t) {
@@ -1420,7 +1466,8 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     Level& L0 = *h->lv[0];
     HIPCHECK(hipMemcpyAsync(d_evals, h->lam.p, p * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (d_resid) HIPCHECK(hipMemcpyAsync(d_resid, h->resid.p, p * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHECK(launch_export_evecs(dptr<double>(h->Phi), h->ld, L0.n, p, dptr<int32_t>(L0.dperm), d_evecs,
+    if (L0.n < h->mesh.nv) HIPCHECK(launch_fill(d_evecs, (int64_t)p * h->mesh.nv, 0.0, s));   // Dirichlet boundary rows
+    HIPCHECK(launch_export_evecs(dptr<double>(h->Phi), h->ld, L0.n, p, dptr<int32_t>(L0.dmeshmap), h->mesh.nv, d_evecs,
                                  dptr<double>(h->exportw), s));
     HIPCHECK(hipStreamSynchronize(s));
     h->last_lam = lam;
@@ -1471,6 +1518,7 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
     if (h->host_only) fail(HSIM_E_STATE, "hierarchy was built host-only");
     if (!h->solved) fail(HSIM_E_STATE, "hsim_solve_backward before a successful hsim_solve");
     if (h->bo.lumping != 0) fail(HSIM_E_UNIMPLEMENTED, "the adjoint supports the barycentric lumping only");
+    if (h->lv[0]->n < h->mesh.nv) fail(HSIM_E_UNIMPLEMENTED, "the adjoint of the Dirichlet problem is not implemented");
     hipStream_t s = S_(stream);
     backward_setup(h);
     Level& L0 = *h->lv[0];

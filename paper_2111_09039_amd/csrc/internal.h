@@ -50,6 +50,8 @@ struct Mesh {
 void validate_mesh(const Mesh& m);
 Graph edge_graph(const Mesh& m);
 double surface_area(const Mesh& m);
+// per vertex: 1 if it lies on an edge that belongs to exactly one triangle
+std::vector<char> boundary_vertex_flags(const Mesh& m);
 Csr cotan_stiffness(const Mesh& m);
 std::vector<double> lumped_mass(const Mesh& m, int lumping, const double* density);
 

@@ -198,9 +198,10 @@ hipError_t launch_import_cols(const double* in, int64_t nv, const int32_t* perm,
                               int64_t ld, hipStream_t s, const double* sign = nullptr);
 
 // ------------------------------------------------------------ output
-// evecs[c * nv + vertex(r)] = sign_c * Phi[r, c] for c < p, largest-magnitude
-// entry positive (lowest vertex index on ties)
+// evecs[c * nout + vertex(r)] = sign_c * Phi[r, c] for r < n, c < p (vertex(r) =
+// perm[r] < nout; rows of evecs that no r names are left as they are),
+// largest-magnitude entry positive (lowest vertex index on ties)
 hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t p, const int32_t* perm,
-                               double* evecs, double* work, hipStream_t s);
+                               int64_t nout, double* evecs, double* work, hipStream_t s);
 
 }  // namespace hsim

@@ -3218,9 +3218,10 @@ __global__ void k_col_sign(const double* pv, const int64_t* pi, int64_t nch, int
     }
     sign[c] = bv < 0 ? -1.0 : 1.0;
 }
-// evecs[c * n + perm[r]] = sign[c] * Phi[r, c]: tiles of 32 rows x 32 columns through LDS
+// evecs[c * nout + perm[r]] = sign[c] * Phi[r, c]: tiles of 32 rows x 32 columns through LDS
 __global__ __launch_bounds__(256) void k_export(const double* Phi, int64_t ld, int64_t n, int32_t p,
-                                                const int32_t* perm, const double* sign, double* evecs) {
+                                                const int32_t* perm, int64_t nout, const double* sign,
+                                                double* evecs) {
     __shared__ double t[T32][T32 + 1];
     const int64_t r0 = blockIdx.x * (int64_t)T32;
     const int c0 = blockIdx.y * T32;
@@ -3236,12 +3237,12 @@ __global__ __launch_bounds__(256) void k_export(const double* Phi, int64_t ld, i
         const int64_t r = r0 + tx;
         if (r < n && c < p) {
             const int64_t v = perm ? perm[r] : r;
-            evecs[(int64_t)c * n + v] = sign[c] * t[tx][yy];
+            evecs[(int64_t)c * nout + v] = sign[c] * t[tx][yy];
         }
     }
 }
 hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t p, const int32_t* perm,
-                               double* evecs, double* work, hipStream_t s) {
+                               int64_t nout, double* evecs, double* work, hipStream_t s) {
     const int64_t chunk = 8192;
     const int64_t nch = cdiv(n, chunk);
     double* pv = work;
@@ -3252,7 +3253,8 @@ hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t
     if (e != hipSuccess) return e;
     k_col_sign<<<(unsigned)cdiv(p, 256), 256, 0, s>>>(pv, pi, nch, p, sign);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_export<<<dim3((unsigned)cdiv(n, T32), (unsigned)cdiv(p, T32)), 256, 0, s>>>(Phi, ld, n, p, perm, sign, evecs);
+    k_export<<<dim3((unsigned)cdiv(n, T32), (unsigned)cdiv(p, T32)), 256, 0, s>>>(Phi, ld, n, p, perm, nout, sign,
+                                                                                   evecs);
     return hipGetLastError();
 }
 

@@ -8,6 +8,25 @@
 
 namespace hsim {
 
+std::vector<char> boundary_vertex_flags(const Mesh& m) {
+    std::vector<std::pair<int32_t, int32_t>> e;
+    e.reserve(3 * (size_t)m.nf);
+    for (int64_t t = 0; t < m.nf; ++t)
+        for (int k = 0; k < 3; ++k) {
+            const int32_t a = m.F[3 * t + k], b = m.F[3 * t + (k + 1) % 3];
+            e.push_back({std::min(a, b), std::max(a, b)});
+        }
+    std::sort(e.begin(), e.end());
+    std::vector<char> on(m.nv, 0);
+    for (size_t i = 0; i < e.size();) {
+        size_t j = i;
+        while (j < e.size() && e[j] == e[i]) ++j;
+        if (j - i == 1) on[e[i].first] = on[e[i].second] = 1;
+        i = j;
+    }
+    return on;
+}
+
 void validate_mesh(const Mesh& m) {
     if (m.nv < 3 || m.nf < 1) fail(HSIM_E_MESH, "mesh needs >= 3 vertices and >= 1 triangle");
     for (int64_t i = 0; i < 3 * m.nv; ++i)

@@ -7,6 +7,7 @@ import math
 
 import numpy as np
 import pytest
+import scipy.linalg as sl
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
@@ -213,6 +214,39 @@ def test_hsim_end_to_end(cuda, case):
     # sign convention: largest-magnitude entry positive
     idx = np.argmax(np.abs(X), axis=0)
     assert (X[idx, np.arange(p)] > 0).all()
+
+
+def test_hsim_dirichlet_end_to_end(cuda):
+    # surface with boundary, Dirichlet condition: HSIM on the interior unknowns
+    # against the dense generalized eigenproblem of the oracle's restriction
+    import paper_2111_09039_amd as hs
+    rng = np.random.default_rng(8)
+    V, F = synth.rectangle_grid(60, 40, 0.05)
+    V = synth.isotropic_noise(V, F, 0.2 * synth.mean_edge_length(V, F), rng)
+    S, m = assembly.assemble(V, F)
+    Si, mi, interior = assembly.dirichlet(S, m, F)
+    p = 20
+    H = hs.Hierarchy(V, F, p, levels=3, n_coarsest=200, boundary="dirichlet")
+    print(f"[dirichlet] n={len(V)} interior={len(interior)} levels {[H.level_info(t)['n'] for t in range(3)]}",
+          flush=True)
+    ev, X, r, st = H.solve(tol=1e-10)
+    ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
+    lr, Xr = sl.eigh(Si.toarray(), np.diag(mi), subset_by_index=[0, p + 9])
+    assert np.abs(ev - lr[:p]).max() <= 1e-9 * lr[p - 1], np.abs(ev - lr[:p]).max()
+    boundary = np.setdiff1d(np.arange(len(V)), interior)
+    assert (X[boundary] == 0).all()
+    Xi = X[interior]
+    assert r.max() < 1e-10
+    assert metrics.m_orthonormality(Xi, mi) < 1e-10
+    assert sim.residual(Si, mi, Xi, ev).max() < 2e-10
+    assert metrics.eigenvector_err(Xi, Xr, mi, lr).max() < 1e-6
+    with pytest.raises(Exception, match="UNIMPLEMENTED"):
+        H.backward(grad_evals=torch_ones(p))
+
+
+def torch_ones(k):
+    import torch
+    return torch.ones(k, dtype=torch.float64, device="cuda")
 
 
 # ---------------------------------------------------------------- mixed precision

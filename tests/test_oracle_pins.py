@@ -169,6 +169,34 @@ def test_neumann_rectangle_P3(nx, ny):
     assert np.abs(lb - exact).max() > 1e-3 * exact.max()
 
 
+@pytest.mark.parametrize("nx,ny", [(9, 6), (13, 10)])
+def test_dirichlet_rectangle(nx, ny):
+    # Dirichlet on the flat grid: the interior block of the cotangent matrix is
+    # the 5-point Laplacian and the circumcentric masses are h^2, so the
+    # spectrum is (4/h^2)(sin^2(k pi / 2(nx-1)) + sin^2(l pi / 2(ny-1))),
+    # k = 1..nx-2, l = 1..ny-2, with eigenvectors sin(k pi i/(nx-1)) sin(l pi j/(ny-1))
+    h = 0.37
+    V, F = synth.rectangle_grid(nx, ny, h)
+    S, m = assembly.assemble(V, F, lumping="voronoi")
+    on = assembly.boundary_vertices(F, len(V))
+    assert on.sum() == 2 * (nx + ny) - 4
+    Si, mi, interior = assembly.dirichlet(S, m, F)
+    assert len(interior) == (nx - 2) * (ny - 2) and not on[interior].any()
+    k, l = np.arange(1, nx - 1), np.arange(1, ny - 1)
+    exact = np.sort(((4 / h ** 2) * (np.sin(k[:, None] * np.pi / (2 * (nx - 1))) ** 2
+                                     + np.sin(l[None, :] * np.pi / (2 * (ny - 1))) ** 2)).ravel())
+    lam, X = jacobi.jacobi_gep_diag(Si, mi)
+    assert np.abs(lam - exact).max() < 1e-12 * exact.max()
+    # the lowest mode is the product of the two lowest sines on the interior
+    xy = V[interior, :2] / h
+    mode = np.sin(np.pi * np.round(xy[:, 0]) / (nx - 1)) * np.sin(np.pi * np.round(xy[:, 1]) / (ny - 1))
+    c = abs(mode @ (mi * X[:, 0])) / np.sqrt(mode @ (mi * mode))
+    assert abs(c - 1.0) < 1e-12
+    # a closed surface has no boundary
+    Vs, Fs = synth.icosphere(2)
+    assert not assembly.boundary_vertices(Fs, len(Vs)).any()
+
+
 # ---------------------------------------------------------- SIM / residual
 def test_sim_matches_dense_and_residual_forms():
     V, F = synth.torus(24, 14)
