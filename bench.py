@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--nu", type=int, default=324, help="geodesic frequency (324 -> 1,049,762 vertices)")
     ap.add_argument("--p", type=int, default=100)
     ap.add_argument("--levels", type=int, default=0, help="T; 0 = the paper's rule (2 for p <= 200, else 3)")
+    ap.add_argument("--mesh", choices=["sphere", "sheet"], default="sphere",
+                    help="sphere: the benchmark mesh; sheet: a noisy 700 x 530 grid (371,000 vertices, with boundary)")
+    ap.add_argument("--boundary", choices=["neumann", "dirichlet"], default="neumann")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -149,10 +152,16 @@ def main():
 
     torch.cuda.set_device(0)
     t = time.perf_counter()
-    V, F, dens = synth.config_mesh("sphere1m", seed=0, nu=args.nu)
+    if args.mesh == "sphere":
+        V, F, dens = synth.config_mesh("sphere1m", seed=0, nu=args.nu)
+    else:
+        V, F = synth.rectangle_grid(700, 530, 1.0 / 700)
+        V = synth.isotropic_noise(V, F, 0.2 * synth.mean_edge_length(V, F), np.random.default_rng(0))
+        dens = None
     log(f"mesh {len(V)} vertices, {len(F)} triangles ({time.perf_counter() - t:.1f} s)")
     t = time.perf_counter()
-    H = hs.Hierarchy(V, F, args.p, density=dens, levels=args.levels or (2 if args.p <= 200 else 3))
+    H = hs.Hierarchy(V, F, args.p, density=dens, levels=args.levels or (2 if args.p <= 200 else 3),
+                     boundary=args.boundary)
     t_build = time.perf_counter() - t
     log(f"hierarchy built in {t_build:.1f} s: levels {H.levels}, q {H.q}")
     info0 = H.level_info(0)
@@ -197,7 +206,7 @@ def main():
     else:
         achieved = kd["bytes"] / max(1, kd["launches"]) / (avg_ms * 1e-3) / 1e9
         peak = HBM_PEAK_GBS
-    traffic = stored_traffic(dom, args.nu, args.p)
+    traffic = stored_traffic(dom, args.nu, args.p) if args.mesh == "sphere" else None
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4),
                 "traffic": None if traffic is None else round(traffic), "traffic_unit": "bytes per launch",
@@ -207,7 +216,7 @@ def main():
                 "algorithmic_flops_per_launch": kd["flops"] / max(1, kd["launches"])}
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.mesh == "sphere":
         t = time.perf_counter()
         res = cpu_baseline(args.p)
         n = len(V)
@@ -230,8 +239,10 @@ def main():
         "value": round(value, 5), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(value * 1e3, 3), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-        "config": {"workload": f"geodesic icosphere nu={args.nu} with 50 bumps + radial noise, "
-                               f"{len(V)} vertices, p={args.p}, q={H.q}, T={H.levels}, eps={args.tol}",
+        "config": {"workload": (f"geodesic icosphere nu={args.nu} with 50 bumps + radial noise, "
+                                if args.mesh == "sphere" else
+                                f"noisy 700 x 530 grid sheet, {args.boundary} boundary, ")
+                               + f"{len(V)} vertices, p={args.p}, q={H.q}, T={H.levels}, eps={args.tol}",
                    "headline_precision": "mixed" if dtype == "f32+f64" else "fp64",
                    "fp64_s": round(dt64, 5), "mixed_s": results.get("mixed", {}).get("s"),
                    "hierarchy_build_s": round(t_build, 3), "factor_nnz": info0["factor_nnz"],
