@@ -140,7 +140,7 @@ struct DenseGEP {
     int32_t nblk = 0;
     std::vector<int64_t> fupd_off, fupd_cnt, bupd_off, bupd_cnt;
     DeviceBuffer tilesT, linvT, big_items;
-    DeviceBuffer S2, M2, e, W, W2, C, V, Qs, rot, dis, normf;
+    DeviceBuffer S2, M2, e, W, W2, C, V, Qs, qrot, rot, dis, normf;
 
     void setup(int32_t kk) {
         if (k == kk) return;
@@ -215,6 +215,7 @@ struct DenseGEP {
         C.alloc((size_t)m * m * sizeof(double));
         V.alloc((size_t)m * m * sizeof(double));
         Qs.alloc((size_t)(m / (2 * bj)) * (2 * bj) * (2 * bj) * sizeof(double));
+        qrot.alloc((size_t)(m / (2 * bj)) * sizeof(int32_t));
         rot.alloc(4 * sizeof(int32_t));
         normf.alloc(2 * sizeof(double));
     }
@@ -316,7 +317,7 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
         HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 2, 0, s));
         HIPCHECK(launch_bj_sweep(bj, dptr<double>(C), dptr<double>(V), m, dptr<double>(Qs), dptr<double>(normf),
-                                 tol_rel, tol_abs_rel, 1, dptr<int32_t>(rot), s));
+                                 tol_rel, tol_abs_rel, 1, dptr<int32_t>(rot), dptr<int32_t>(qrot), s));
         HIPCHECK(launch_bj_offcount(dptr<double>(C), m, dptr<double>(normf), tol_rel, tol_abs_rel,
                                     dptr<int32_t>(rot) + 1, s));
         int32_t cnt[2] = {0, 0};

@@ -140,9 +140,12 @@ hipError_t launch_sym_scale(const double* A, const double* D, int32_t k, double*
 // cyclic sweeps; rotation threshold max(tol_abs_rel * normf[0],
 // tol_rel * sqrt(|c_pp c_qq|)), rotations counted into rot_count), then
 // C <- J^T C J and V <- V J.  Qs: (m / 2b) (2b)^2 doubles (the pairs'
-// orthogonal factors of a round).
+// orthogonal factors of a round); qrot: m / 2b ints (per pair of the round:
+// 0 when no entry was above the threshold, so its factor is the identity and
+// the update skips it).
 hipError_t launch_bj_sweep(int b, double* C, double* V, int32_t m, double* Qs, const double* normf, double tol_rel,
-                           double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, hipStream_t s);
+                           double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, int32_t* qrot,
+                           hipStream_t s);
 // count += number of entries c_pq (p < q) of the symmetric m x m C above the
 // rotation threshold of launch_bj_sweep (0: another sweep would not rotate)
 hipError_t launch_bj_offcount(const double* C, int32_t m, const double* normf, double tol_rel, double tol_abs_rel,

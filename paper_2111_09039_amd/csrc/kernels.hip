@@ -2476,7 +2476,8 @@ constexpr size_t bj_local_lds() {   // A (double-buffered), Q and a counter
 template <int B>
 __device__ void bj_local_solve(const double* C, int32_t m, int32_t r, int32_t P, double* __restrict__ Qs,
                                const double* __restrict__ normf, double tol_rel, double tol_abs_rel,
-                               int32_t max_sweeps, int32_t* rot_count, unsigned char* smem_raw) {
+                               int32_t max_sweeps, int32_t* rot_count, int32_t* __restrict__ qrot,
+                               unsigned char* smem_raw) {
     // 2 b^2 threads: thread (k1, k2) < b^2 owns the 2 x 2 block {p_k1, q_k1} x
     // {p_k2, q_k2} of A, thread b^2 + (k1, k2) the entries {k1, k1 + b} x
     // {p_k2, q_k2} of Q; both compute the rotations they need from the step's
@@ -2501,6 +2502,21 @@ __device__ void bj_local_solve(const double* C, int32_t m, int32_t r, int32_t P,
     }
     if (tid == 0) total = 0;
     __syncthreads();
+    // no entry above the threshold: a sweep would rotate nothing (the test only
+    // reads entries that nothing changes), so Q is the identity and the apply
+    // launch skips this pair
+    int pred = 0;
+    for (int idx = tid; idx < W * W; idx += 2 * NT) {
+        const int a = idx / W, c = idx % W;
+        const double apq = A[0][a][c];
+        pred |= a < c && apq * apq > fmax(tol_abs2, tol_rel2 * fabs(A[0][a][a] * A[0][c][c]));
+    }
+    double* Qo = Qs + (int64_t)P * W * W;
+    if (!__syncthreads_or(pred)) {
+        for (int idx = tid; idx < W * W; idx += 2 * NT) Qo[idx] = idx / W == idx % W ? 1.0 : 0.0;
+        if (tid == 0) qrot[P] = 0;
+        return;
+    }
     int cur = 0, seen = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         int mine = 0;
@@ -2551,8 +2567,8 @@ __device__ void bj_local_solve(const double* C, int32_t m, int32_t r, int32_t P,
         if (now == seen) break;
         seen = now;
     }
-    double* Qo = Qs + (int64_t)P * W * W;
     for (int idx = tid; idx < W * W; idx += 2 * NT) Qo[idx] = Q[idx / W][idx % W];
+    if (tid == 0) qrot[P] = 1;
     if (tid == 0 && seen) atomicAdd(rot_count, seen);
     __syncthreads();   // LDS free for the caller
 }
@@ -2560,9 +2576,9 @@ template <int B>
 __global__ __launch_bounds__(2 * B * B) void k_bj_local(const double* __restrict__ C, int32_t m, int32_t r,
                                                     double* __restrict__ Qs, const double* __restrict__ normf,
                                                     double tol_rel, double tol_abs_rel, int32_t max_sweeps,
-                                                    int32_t* rot_count) {
+                                                    int32_t* rot_count, int32_t* __restrict__ qrot) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    bj_local_solve<B>(C, m, r, blockIdx.x, Qs, normf, tol_rel, tol_abs_rel, max_sweeps, rot_count, smem_raw);
+    bj_local_solve<B>(C, m, r, blockIdx.x, Qs, normf, tol_rel, tol_abs_rel, max_sweeps, rot_count, qrot, smem_raw);
 }
 
 // C <- J^T C J on every (pair, pair') tile (pair <= pair'), V <- V J on row
@@ -2573,7 +2589,7 @@ __global__ __launch_bounds__(2 * B * B) void k_bj_local(const double* __restrict
 // D[l / 16 + 4 v][l % 16].
 template <int B>
 __device__ void bj_apply_item(double* C, double* V, int32_t m, int32_t r, const double* __restrict__ Qs,
-                              double (*X)[2 * B + 1]) {
+                              const int32_t* __restrict__ qrot, double (*X)[2 * B + 1]) {
     constexpr int W = 2 * B, NT = W / 16;   // NT x NT output tiles of 16 x 16, one per wave
     const int nb = m / B, np = nb / 2;
     const int64_t ctiles = (int64_t)np * (np + 1) / 2;
@@ -2583,6 +2599,7 @@ __device__ void bj_apply_item(double* C, double* V, int32_t m, int32_t r, const 
         int t = blockIdx.x, P = 0;
         while (t >= np - P) { t -= np - P; ++P; }
         const int P2 = P + t;
+        if (!qrot[P] && !qrot[P2]) return;   // both factors are the identity
         int I1, J1, I2, J2;
         bj_pair(P, r, nb, I1, J1);
         bj_pair(P2, r, nb, I2, J2);
@@ -2618,6 +2635,7 @@ __device__ void bj_apply_item(double* C, double* V, int32_t m, int32_t r, const 
         // V rows [row0, row0 + W) times Q of pair P (m is a multiple of W)
         const int64_t item = blockIdx.x - ctiles;
         const int P = (int)(item % np);
+        if (!qrot[P]) return;
         const int64_t row0 = (item / np) * W;
         int I1, J1;
         bj_pair(P, r, nb, I1, J1);
@@ -2640,9 +2658,9 @@ __device__ void bj_apply_item(double* C, double* V, int32_t m, int32_t r, const 
 }
 template <int B>
 __global__ __launch_bounds__(B * B) void k_bj_apply(double* C, double* V, int32_t m, int32_t r,
-                                                    const double* __restrict__ Qs) {
+                                                    const double* __restrict__ Qs, const int32_t* __restrict__ qrot) {
     __shared__ double X[2 * B][2 * B + 1];
-    bj_apply_item<B>(C, V, m, r, Qs, X);
+    bj_apply_item<B>(C, V, m, r, Qs, qrot, X);
 }
 
 // Number of off-diagonal entries of the symmetric m x m matrix C that the
@@ -2670,7 +2688,7 @@ hipError_t launch_bj_offcount(const double* C, int32_t m, const double* normf, d
 
 template <int B>
 hipError_t bj_sweep(double* C, double* V, int32_t m, double* Qs, const double* normf, double tol_rel,
-                    double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, hipStream_t s) {
+                    double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, int32_t* qrot, hipStream_t s) {
     constexpr size_t lds = bj_local_lds<B>();
     hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_bj_local<B>), lds, 0);
     if (e != hipSuccess) return e;
@@ -2678,17 +2696,19 @@ hipError_t bj_sweep(double* C, double* V, int32_t m, double* Qs, const double* n
     const int64_t ctiles = (int64_t)np * (np + 1) / 2;
     const int64_t vitems = (int64_t)(m / (2 * B)) * np;
     for (int32_t r = 0; r + 1 < nb; ++r) {
-        k_bj_local<B><<<np, 2 * B * B, lds, s>>>(C, m, r, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count);
+        k_bj_local<B><<<np, 2 * B * B, lds, s>>>(C, m, r, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count,
+                                                 qrot);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        k_bj_apply<B><<<(unsigned)(ctiles + vitems), B * B, 0, s>>>(C, V, m, r, Qs);
+        k_bj_apply<B><<<(unsigned)(ctiles + vitems), B * B, 0, s>>>(C, V, m, r, Qs, qrot);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 hipError_t launch_bj_sweep(int b, double* C, double* V, int32_t m, double* Qs, const double* normf, double tol_rel,
-                           double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, hipStream_t s) {
+                           double tol_abs_rel, int32_t inner_sweeps, int32_t* rot_count, int32_t* qrot,
+                           hipStream_t s) {
     if (b != 16 || m % (2 * b) != 0 || m < 2 * b) return hipErrorInvalidValue;
-    return bj_sweep<16>(C, V, m, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count, s);
+    return bj_sweep<16>(C, V, m, Qs, normf, tol_rel, tol_abs_rel, inner_sweeps, rot_count, qrot, s);
 }
 
 // V = identity (m x m)
