@@ -720,10 +720,12 @@ __device__ __forceinline__ bool wsolve_item_split(int32_t nfronts, int32_t group
 // only when the right-hand side is read from a separate block (in place, one
 // workgroup's solution would overwrite another one's input)
 constexpr int64_t WSOLVE_MIN_WAVES = 1024;
-// widest workgroup (waves) of the wave-level solves for NT pivot row tiles
+// waves per workgroup of the wave-level solves for NT pivot row tiles: one
+// (the waves never synchronise, and single-wave workgroups let the dispatcher
+// fill the CUs at the finest granularity; measured faster than 2, 4 or 8)
 template <int NT>
 struct WsolveWaves {
-    static constexpr int value = NT >= 16 ? 4 : 8;
+    static constexpr int value = 1;
 };
 // 16-column tiles per wave (one: many independent waves hide latency better
 // than fewer, wider ones on these solves)
