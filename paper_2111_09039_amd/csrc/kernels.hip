@@ -1591,7 +1591,7 @@ hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF
         return hipGetLastError();
     }
     int32_t wpg, groups;
-    wsolve_shape(ncols, 8, WCOLS, wpg, groups);
+    wsolve_shape(ncols, 2, WCOLS, wpg, groups);
     const dim3 grid((unsigned)nitems, (unsigned)groups), block((unsigned)(64 * wpg));
     switch (phase) {
         case 1: k_big_fwd_diag<TF><<<grid, block, 0, s>>>(tiles, linv, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
