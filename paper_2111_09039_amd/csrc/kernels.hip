@@ -843,21 +843,41 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
     const int nkb = (nt + 1) >> 1;
     double a[8];
     frag_rows(tiles + f.tile_base + tri(f.Mt, f.nsb + (rt0 >> 1), 0) * TT, rt0 & 1, false, a);
-#pragma unroll 1
-    for (int rt = rt0; rt < rt1; ++rt) {
-        // first two gather sources of every update row, ahead of the products
-        int32_t s0[4] = {-1, -1, -1, -1}, s1[4] = {-1, -1, -1, -1};
-        if (gath) {
+    // gather sources of the update rows: the indices of row tile rt + 1 and the
+    // gathered values of row tile rt are in flight while the products of rt run
+    // (every update row has at most gw sources; the first two are pipelined)
+    auto gather_idx = [&](int rt, int32_t (&i0)[4], int32_t (&i1)[4]) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int sr = 16 * rt + lr + 4 * v;
-                if (sr < f.mu) {
-                    const int32_t* gr = gat + (f.gather_base + f.ns + sr) * gw;
-                    if (gw > 0) s0[v] = gr[0];
-                    if (gw > 1) s1[v] = gr[1];
-                }
+        for (int v = 0; v < 4; ++v) {
+            i0[v] = -1;
+            i1[v] = -1;
+            const int sr = 16 * rt + lr + 4 * v;
+            if (gath && sr < f.mu) {
+                const int32_t* gr = gat + (f.gather_base + f.ns + sr) * gw;
+                if (gw > 0) i0[v] = gr[0];
+                if (gw > 1) i1[v] = gr[1];
             }
         }
+    };
+    int32_t n0[4], n1[4];
+    gather_idx(rt0, n0, n1);
+#pragma unroll 1
+    for (int rt = rt0; rt < rt1; ++rt) {
+        double g[CT][4];
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc) {
+            const int32_t c = cbase + 16 * cc + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double u = 0.0;
+                if (c < cend) {
+                    if (n0[v] >= 0) u += (double)ubuf[(int64_t)n0[v] * ldu + c];
+                    if (n1[v] >= 0) u += (double)ubuf[(int64_t)n1[v] * ldu + c];
+                }
+                g[cc][v] = u;
+            }
+        }
+        if (rt + 1 < rt1) gather_idx(rt + 1, n0, n1);
         dbl4 acc[CT];
 #pragma unroll
         for (int cc = 0; cc < CT; ++cc) acc[cc] = dbl4{0, 0, 0, 0};
@@ -881,10 +901,8 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
             for (int v = 0; v < 4; ++v) {
                 const int sr = 16 * rt + lr + 4 * v;
                 if (sr < f.mu && c < cend) {
-                    double u = 0.0;
+                    double u = g[cc][v];
                     if (gath) {
-                        if (s0[v] >= 0) u += (double)ubuf[(int64_t)s0[v] * ldu + c];
-                        if (s1[v] >= 0) u += (double)ubuf[(int64_t)s1[v] * ldu + c];
                         const int32_t* gr = gat + (f.gather_base + f.ns + sr) * gw;
 #pragma unroll 1
                         for (int cg = 2; cg < gw; ++cg) {
