@@ -289,7 +289,8 @@ struct DenseGEP {
                                           0, 1, ns_pad, X, ld, 0, ncols, qc, nullptr, false, s));
     }
 
-    // returns the Jacobi sweeps used
+    // returns the Jacobi sweeps used, or -1 when dM is not numerically
+    // positive definite (nothing else is computed then)
     int32_t run(const double* dS, const double* dM, int32_t kout, double* lam_out, double* X, int64_t ldx,
                 hipStream_t s, int32_t max_sweeps = 40);
 };
@@ -300,6 +301,15 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     HIPCHECK(launch_equilibrate(dS, dM, k, dptr<double>(S2), dptr<double>(M2), dptr<double>(e), s));
     HIPCHECK(launch_dense_to_front(dptr<double>(M2), k, dptr<double>(tiles), Mt, s));
     factor(s);
+    {
+        // the (equilibrated) mass matrix must be positive definite: a negative,
+        // zero or non-finite pivot is reported to the caller (-1) instead of
+        // turning into NaN through D^-1/2
+        int32_t piv[2] = {0, 0};
+        HIPCHECK(hipMemcpyAsync(piv, counters.p, sizeof(piv), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (piv[0] > 0 || piv[1] > 0) return -1;
+    }
     // W = L^-1 S', W2 = W^T, W2 <- L^-1 W2 = L^-1 S' L^-T
     HIPCHECK(launch_copy2d(dptr<double>(S2), k, k, k, dptr<double>(W), k, s));
     fwd(dptr<double>(W), k, s);
@@ -880,7 +890,9 @@ static double choose_shift(const std::vector<double>& lam, int32_t p, double alp
 
 // one Rayleigh-Ritz step on level L from the basis in Psi (already inverse
 // iterated); leaves Phi, lam (device) and returns lam/resid on the host
-static void rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam, std::vector<double>& res,
+// false (and Phi untouched) when the FP32 Gram left the reduced mass matrix
+// without a positive definite factor; the caller repeats the step in FP64
+static bool rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam, std::vector<double>& res,
                           hipStream_t s, double* ms_gram, double* ms_rr, double* ms_ritz, bool fp32_gram = false) {
     const int32_t q = H->q;
     const bool fin = L.tau == 0;
@@ -896,9 +908,16 @@ static void rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam,
     HIPCHECK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     H->rr.setup(q);
+    int32_t sweeps = 0;
     H->prof.run(HSIM_K_JACOBI, 0.0, 0.0, s, [&] {
-        H->rr.run(dptr<double>(H->Sbar), dptr<double>(H->Mbar), q, dptr<double>(H->lam), dptr<double>(H->Phibar), q, s);
+        sweeps = H->rr.run(dptr<double>(H->Sbar), dptr<double>(H->Mbar), q, dptr<double>(H->lam),
+                           dptr<double>(H->Phibar), q, s);
     });
+    if (sweeps < 0) {
+        if (fp32_gram) return false;
+        fail(HSIM_E_FACTOR, "Rayleigh-Ritz step on level %d: the reduced mass matrix is not positive definite "
+             "(the iterated basis has lost rank)", L.tau);
+    }
     lam.resize(q);
     HIPCHECK(hipMemcpyAsync(lam.data(), H->lam.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
@@ -922,6 +941,7 @@ static void rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam,
     *ms_gram += std::chrono::duration<double, std::milli>(t1 - t0).count();
     *ms_rr += std::chrono::duration<double, std::milli>(t2 - t1).count();
     *ms_ritz += std::chrono::duration<double, std::milli>(t3 - t2).count();
+    return true;
 }
 
 static Level& level_at(hsim_hierarchy* H, int32_t level) {
@@ -1278,6 +1298,7 @@ hsim_status hsim_step_rr(int32_t k, const double* d_Sbar, const double* d_Mbar, 
     if (!g) g.reset(new DenseGEP());
     g->setup(k);
     int32_t sw = g->run(d_Sbar, d_Mbar, k, d_lam, d_Phibar, k, S_(stream));
+    if (sw < 0) fail(HSIM_E_FACTOR, "the reduced mass matrix is not positive definite");
     if (sweeps) *sweeps = sw;
     API_END
 }
@@ -1310,6 +1331,7 @@ static void coarse_solve(hsim_hierarchy* h, int32_t k, double* d_lam, double* d_
                             dptr<double>(h->coarseM), s));
     h->coarse.setup((int32_t)nc);
     int32_t sw = h->coarse.run(dptr<double>(h->coarseS), dptr<double>(h->coarseM), k, d_lam, d_Phi, ldphi, s);
+    if (sw < 0) fail(HSIM_E_FACTOR, "coarsest level: the mass matrix is not positive definite");
     if (sweeps) *sweeps = sw;
 }
 
@@ -1434,9 +1456,15 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
             // FP32 Gram only far from convergence (its rounding bounds the Ritz
             // vectors' accuracy; switch for good once it stops paying off), and
             // only where no single-pass FP64 Gram kernel exists (q > 160)
-            const bool low_gram = mixed && !fp64_gram && q > gram_fp64_single_pass_max_q() &&
-                                  rmax > std::max(100.0 * so.tol, 1e-4);
-            rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, low_gram);
+            bool low_gram = mixed && !fp64_gram && q > gram_fp64_single_pass_max_q() &&
+                            rmax > std::max(100.0 * so.tol, 1e-4);
+            if (!rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, low_gram)) {
+                // the FP32 Gram lost the definiteness of the reduced mass matrix
+                // (an ill-conditioned basis): this step and the rest of the level in FP64
+                fp64_gram = true;
+                low_gram = false;
+                rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, false);
+            }
             auto check = [&] {
                 conv = true;
                 rmax = 0;

@@ -140,3 +140,11 @@ def test_large_p_hsim(cuda):
     # a pair separated by more than that by about 1e-5
     err = metrics.eigenvector_err(X, Xr, m, lr, gap=1e-4)
     assert err.max() < 1e-4, err.max()
+    # mixed precision: FP32 solves and, above 160 columns, the FP32 interim Gram
+    # while far from convergence; the returned pairs come from an FP64 step
+    evm, Xm, rm, stm = H.solve(tol=1e-9, precision=hs.MIXED)
+    evm, rm = evm.cpu().numpy(), rm.cpu().numpy()
+    print(f"[large p] mixed iters {stm['iters']} refine steps {stm.get('refine_steps')}", flush=True)
+    relm = np.abs(evm - lr[:p])[1:] / lr[1:p]
+    assert relm.max() <= 1e-9, relm.max()
+    assert rm.max() < 1e-9

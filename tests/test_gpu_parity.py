@@ -240,6 +240,11 @@ def test_hsim_dirichlet_end_to_end(cuda):
     assert metrics.m_orthonormality(Xi, mi) < 1e-10
     assert sim.residual(Si, mi, Xi, ev).max() < 2e-10
     assert metrics.eigenvector_err(Xi, Xr, mi, lr).max() < 1e-6
+    # mixed precision (FP32 solves with FP64 refinement) reaches the same pairs
+    evm, Xm, rm, stm = H.solve(tol=1e-10, precision=hs.MIXED)
+    evm, Xm = evm.cpu().numpy(), Xm.cpu().numpy()
+    assert np.abs(evm - lr[:p]).max() <= 1e-9 * lr[p - 1], np.abs(evm - lr[:p]).max()
+    assert (Xm[boundary] == 0).all() and rm.max().item() < 1e-10
     with pytest.raises(Exception, match="UNIMPLEMENTED"):
         H.backward(grad_evals=torch_ones(p))
 
