@@ -394,6 +394,7 @@ struct Level {
 struct hsim_hierarchy {
     int device = 0;
     int32_t p = 0, q = 0, T = 0, ld = 0;
+    int64_t gram_chunk = 1024;   // rows per workgroup of the multi-pass Gram
     hsim_build_opts bo{};
     hsim::Mesh mesh;
     std::vector<double> density;
@@ -856,7 +857,8 @@ static void alloc_workspace(hsim_hierarchy* H) {
     H->cn_part.alloc((size_t)colnorm_partial_doubles(n0, H->ld) * sizeof(double));
     H->cn_ratio.alloc((size_t)H->ld * sizeof(double));
     const int64_t chunk = 4096;
-    H->gram_part.alloc((size_t)gram_partial_doubles(n0, H->q, chunk) * sizeof(double));
+    H->gram_chunk = gram_chunk_rows(n0, H->q);   // fixed here: every later Gram call fits the buffer
+    H->gram_part.alloc((size_t)gram_partial_doubles(n0, H->q, H->gram_chunk) * sizeof(double));
     H->ritz_part.alloc((size_t)ritz_partial_doubles(n0, H->q, chunk) * sizeof(double));
     H->Sbar.alloc((size_t)H->q * H->q * sizeof(double));
     H->Mbar.alloc((size_t)H->q * H->q * sizeof(double));
@@ -902,7 +904,7 @@ static bool rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam,
     const double nq = (double)L.n * q;
     H->prof.run(HSIM_K_GRAM, 8.0 * nq * (fin ? 2.0 : 3.0) + 8.0 * (fin ? L.n : 0), 2.0 * nq * q, s, [&] {
         HIPCHECK(launch_gram(dptr<double>(H->Psi), dptr<double>(H->SPsi), fin ? nullptr : dptr<double>(H->MPsi),
-                             fin ? dptr<double>(L.dmdiag) : nullptr, L.n, q, H->ld, dptr<double>(H->gram_part), 4096,
+                             fin ? dptr<double>(L.dmdiag) : nullptr, L.n, q, H->ld, dptr<double>(H->gram_part), H->gram_chunk,
                              dptr<double>(H->Sbar), dptr<double>(H->Mbar), s, fp32_gram));
     });
     HIPCHECK(hipStreamSynchronize(s));
@@ -1284,7 +1286,7 @@ hsim_status hsim_step_gram(hsim_hierarchy* h, int32_t level, int32_t k, const do
     const bool fin = L.tau == 0;
     if (!fin) apply_level(h, L, 1, dptr<double>(h->Psi), dptr<double>(h->MPsi), k, s);
     HIPCHECK(launch_gram(dptr<double>(h->Psi), dptr<double>(h->SPsi), fin ? nullptr : dptr<double>(h->MPsi),
-                         fin ? dptr<double>(L.dmdiag) : nullptr, L.n, k, h->ld, dptr<double>(h->gram_part), 4096, d_Sbar,
+                         fin ? dptr<double>(L.dmdiag) : nullptr, L.n, k, h->ld, dptr<double>(h->gram_part), h->gram_chunk, d_Sbar,
                          d_Mbar, s, precision == HSIM_MIXED));
     API_END
 }

@@ -106,12 +106,14 @@ hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF
                             hipStream_t s, const double* Xin = nullptr);
 
 // ------------------------------------------------------------ Rayleigh-Ritz
-// partial Grams over row chunks (pairs of 32-column tiles, upper), then the sum
+// partial Grams over row chunks of chunk_rows rows (gram_chunk_rows of the
+// largest n the partial buffer is sized for), then the sum
 // fp32: operands rounded to FP32, FP32 accumulation over runs of 256 rows, FP64 sum of the runs
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
                        int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
                        hipStream_t s, bool fp32 = false);
 int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows);
+int64_t gram_chunk_rows(int64_t n, int32_t q);
 // largest q for which the FP64 Gram is one pass over the rows (all tiles per workgroup)
 int32_t gram_fp64_single_pass_max_q();
 

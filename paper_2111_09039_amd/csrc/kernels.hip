@@ -1636,7 +1636,7 @@ template hipError_t launch_big_solve<float>(int, const float*, const float*, con
 // ============================================================ Gram products
 // Sbar = Psi^T (S Psi), Mbar = Psi^T (M Psi) on the matrix cores.  The q x q
 // upper triangle is covered by 64 x 64 block pairs (a <= b); a workgroup takes
-// one block pair and GRAM_CHUNK rows, its four waves one 32 x 32 quarter each
+// one block pair and one chunk of rows (gram_chunk_rows), its four waves one 32 x 32 quarter each
 // (2 x 2 tiles of the 16 x 16 x 4 MFMA, both products).  Rows are staged
 // through LDS 32 at a time, the next 32 prefetched into registers.
 // TA = double: FP64 MFMA.  TA = float: operands rounded to FP32, FP32 MFMA
@@ -1645,7 +1645,6 @@ template hipError_t launch_big_solve<float>(int, const float*, const float*, con
 // XCD (dispatch is round-robin over the 8 XCDs) and share its L2.
 namespace {
 constexpr int GT = 64;            // output block edge
-constexpr int GRAM_CHUNK = 4096;  // rows per workgroup
 constexpr int GROWS = 32;         // rows per LDS stage
 constexpr int GLD = GT + 8;       // LDS row stride (elements)
 
@@ -1667,10 +1666,20 @@ static int64_t gram_pairs(int32_t q) {
     return nt * (nt + 1) / 2;
 }
 
+// rows per workgroup of the multi-pass Gram for up to n rows: short chunks
+// (more workgroups per block pair) as long as the per-chunk partial blocks
+// stay within 2^32 doubles
+int64_t gram_chunk_rows(int64_t n, int32_t q) {
+    const int64_t per = gram_pairs(q) * 2 * GT * GT;
+    int64_t c = 1024;
+    while (c < (int64_t(1) << 24) && cdiv(n, c) * per > (int64_t(1) << 32)) c *= 2;
+    return c;
+}
+
 // per-chunk partial blocks, their sum and the reduction's scratch
 int64_t gram_all_partial_doubles(int32_t q);
-int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t /*chunk_rows*/) {
-    const int64_t nch = cdiv(n, GRAM_CHUNK);
+int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows) {
+    const int64_t nch = cdiv(n, chunk_rows);
     const int64_t per = gram_pairs(q) * 2 * GT * GT;
     return std::max(nch * per + per + colsum_tmp_doubles(nch, (int32_t)per), gram_all_partial_doubles(q));
 }
@@ -1679,7 +1688,7 @@ template <class TA>
 __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Psi, const double* __restrict__ SPsi,
                                                    const double* __restrict__ MPsi, const double* __restrict__ mdiag,
                                                    int64_t n, int32_t q, int64_t ld, int64_t nchunks,
-                                                   double* __restrict__ partial) {
+                                                   int64_t chunk_rows, double* __restrict__ partial) {
     using V4 = typename std::conditional<std::is_same<TA, double>::value, dbl4, flt4>::type;
     const int32_t nt = (q + GT - 1) / GT;
     const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
@@ -1689,8 +1698,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
     int32_t pair = (int32_t)(item % npairs), a = 0;
     while (pair >= nt - a) { pair -= nt - a; ++a; }
     const int32_t b = a + pair;
-    const int64_t r0 = chunk * GRAM_CHUNK;
-    const int64_t r1 = min(n, r0 + GRAM_CHUNK);
+    const int64_t r0 = chunk * chunk_rows;
+    const int64_t r1 = min(n, r0 + chunk_rows);
 
     __shared__ TA P[GROWS][GLD], Q[GROWS][GLD], R[GROWS][GLD];
     const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
@@ -1995,7 +2004,7 @@ __global__ void k_gram_scatter(const double* __restrict__ sums, int32_t q, doubl
 }
 
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
-                       int32_t q, int64_t ld, double* partial, int64_t /*chunk_rows*/, double* Sbar, double* Mbar,
+                       int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
                        hipStream_t s, bool fp32) {
     if (!fp32 && q <= GA_MAXT * 16) {
         const int32_t nt = (int32_t)cdiv(q, 16);
@@ -2022,14 +2031,15 @@ hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi
         k_gram_all_scatter<<<grid_for((int64_t)q * q, 256), 256, 0, s>>>(sums, q, Sbar, Mbar);
         return hipGetLastError();
     }
+    if (chunk_rows < 1) return hipErrorInvalidValue;
     const int64_t npairs = gram_pairs(q);
-    const int64_t nch = cdiv(n, GRAM_CHUNK);
+    const int64_t nch = cdiv(n, chunk_rows);
     const int64_t per = npairs * 2 * GT * GT;
     const unsigned grid = (unsigned)(cdiv(nch * npairs, NXCD) * NXCD);
     if (fp32)
-        k_gram_mfma<float><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, partial);
+        k_gram_mfma<float><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, chunk_rows, partial);
     else
-        k_gram_mfma<double><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, partial);
+        k_gram_mfma<double><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, chunk_rows, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     double* sums = partial + nch * per;
