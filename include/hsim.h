@@ -79,7 +79,11 @@ enum { HSIM_FP64 = 0, HSIM_MIXED = 1 };
 enum {
     HSIM_FLAG_NOLOCK = 1,        /* disable locking of converged vectors (Section 4.2) */
     HSIM_FLAG_SAVE_FORWARD = 2,  /* keep what hsim_solve_backward needs (set by the autograd wrapper) */
-    HSIM_FLAG_PROFILE = 4        /* time every kernel launch with HIP events (fills k_ms / k_launches) */
+    HSIM_FLAG_PROFILE = 4,       /* time every kernel launch with HIP events (fills k_ms / k_launches) */
+    HSIM_FLAG_DETERMINISTIC = 8  /* bitwise reproducible results run to run on one device.  Every solve
+                                    already is (all reductions run in a fixed order; the kernels use
+                                    integer atomics only, for counters): the flag is accepted and
+                                    changes nothing.  Unknown flag bits are HSIM_E_INVALID. */
 };
 
 /* kernel classes of the profile counters in hsim_stats */

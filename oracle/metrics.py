@@ -8,6 +8,20 @@ of a computed vector x_i is its M-norm distance to the span of the reference
 cluster containing index i, ||x_i - Y_C Y_C^T M x_i||_M (Y_C M-orthonormal).
 The paper measures eigenvector differences by the relative L2 norm (Section 5,
 termination criterion); with ||x_i||_M = 1 this is the same quantity.
+
+Sketches (for meshes whose reference eigenvectors are too large to keep)
+-----------------------------------------------------------------------
+With a fixed Gaussian matrix G (n x r) and M diagonal, the sketch of a block X
+is W = G^T (M^{1/2} X) (r x k).  For an M-orthonormal reference cluster Y_C,
+Z_C = G^T M^{1/2} Y_C, and a vector x = Y_C c + e with e M-orthogonal to Y_C
+has sketch Z_C c + G^T M^{1/2} e, whose second part is independent of Z_C and
+Gaussian with variance ||e||_M^2 per entry.  Removing the least-squares fit on
+the columns of Z_C therefore leaves a residual whose squared norm has expected
+value (r - |C|) ||e||_M^2: ``sketch_vector_err`` returns that estimate of the
+cluster-aware error of ``eigenvector_err`` (a chi-square estimate with
+r - |C| degrees of freedom).  ``sketch_projector_diff`` compares the
+rotation-invariant sketches W W^T and Z_C Z_C^T of two bases of a whole
+cluster.
 """
 from __future__ import annotations
 
@@ -58,3 +72,36 @@ def m_orthonormality(X, M):
     Mop = sp.diags(M) if not sp.issparse(M) and np.ndim(M) == 1 else M
     G = X.T @ (Mop @ X)
     return float(np.abs(G - np.eye(G.shape[0])).max())
+
+
+def sketch(X, m, G):
+    """W = G^T (m^{1/2} * X) for a diagonal mass m (see the module notes)."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    return G.T @ (np.sqrt(np.asarray(m, dtype=np.float64))[:, None] * X)
+
+
+def sketch_vector_err(w, Zc, xnorm=None):
+    """Estimate of ||x - Y_C Y_C^T M x||_M / ||x||_M from the sketch w of x
+    (length r) and the sketch Zc (r x |C|) of the M-orthonormal reference
+    cluster Y_C.  ``xnorm`` = ||x||_M if known (else estimated as |w|/sqrt(r),
+    since E|w|^2 = r ||x||_M^2)."""
+    w = np.asarray(w, dtype=np.float64)
+    r, c = Zc.shape
+    if c >= r:
+        raise ValueError("sketch has too few rows for this cluster")
+    coef, *_ = np.linalg.lstsq(Zc, w, rcond=None)
+    res = w - Zc @ coef
+    out = np.sqrt(float(res @ res) / (r - c))
+    if xnorm is None:
+        xnorm = np.sqrt(float(w @ w) / r)
+    return out / max(float(xnorm), 1e-300)
+
+
+def sketch_projector_diff(W, Zc):
+    """|| W W^T - Zc Zc^T ||_F / || Zc Zc^T ||_F for the sketches of two bases
+    of the same cluster (invariant to rotations and signs inside the cluster)."""
+    A = W @ W.T
+    B = Zc @ Zc.T
+    return float(np.linalg.norm(A - B) / np.linalg.norm(B))

@@ -18,7 +18,7 @@ from ._lib import HsimError
 __all__ = ["Hierarchy", "HsimError", "FP64", "MIXED", "build_library"]
 
 FP64, MIXED = 0, 1
-FLAG_NOLOCK, FLAG_SAVE_FORWARD, FLAG_PROFILE = 1, 2, 4
+FLAG_NOLOCK, FLAG_SAVE_FORWARD, FLAG_PROFILE, FLAG_DETERMINISTIC = 1, 2, 4, 8
 
 
 def build_library(verbose=False):

@@ -1359,6 +1359,8 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     if (!(so.tol > 0)) fail(HSIM_E_INVALID, "tol must be positive");
     if (so.max_iters < 1) fail(HSIM_E_INVALID, "max_iters must be >= 1");
     if (so.precision != HSIM_FP64 && so.precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
+    if (so.flags & ~(HSIM_FLAG_NOLOCK | HSIM_FLAG_SAVE_FORWARD | HSIM_FLAG_PROFILE | HSIM_FLAG_DETERMINISTIC))
+        fail(HSIM_E_INVALID, "unknown solve flags 0x%x", (unsigned)so.flags);
     const bool mixed = so.precision == HSIM_MIXED;
     hipStream_t s = S_(so.stream);
     const auto T0 = std::chrono::steady_clock::now();

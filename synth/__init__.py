@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "icosahedron", "icosphere", "geodesic_icosphere", "torus", "rectangle_grid",
-    "radial_jitter", "isotropic_noise", "gaussian_bumps", "random_density",
+    "radial_jitter", "isotropic_noise", "gaussian_bumps", "random_density", "gaussian_matrix",
     "mean_edge_length", "config_mesh", "CONFIGS",
 ]
 
@@ -235,6 +235,12 @@ def gaussian_bumps(V, rng, count=50, amplitude=0.05, width=(0.1, 0.3)):
 
 def random_density(n, rng, lo=0.7, hi=1.3):
     return rng.uniform(lo, hi, size=n)
+
+
+def gaussian_matrix(n, r, seed):
+    """Seeded n x r matrix of independent N(0, 1) entries (row-major), used as
+    the random test matrix of eigenvector sketches and as random directions."""
+    return np.random.default_rng(seed).standard_normal((n, r))
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,109 @@
+"""Error paths and reproducibility of the C ABI, forced from the host so that
+every kernel still runs to its normal end.
+
+* hsim_solve_backward before any hsim_solve: HSIM_E_STATE, output untouched;
+* max_iters = 1: HSIM_E_NOCONV with every output filled by the last iterate;
+* a shift at the zero eigenvalue of a closed mesh (S - 0 M = S is singular in
+  exact arithmetic): the factorisation either reports the breakdown
+  (HSIM_E_FACTOR) or returns an inertia of 0 or 1 (rounding decides the sign
+  of the last pivot), and the hierarchy stays usable;
+* determinism: two solves of the same hierarchy give bitwise equal results
+  (every reduction has a fixed order; the kernels use no floating-point
+  atomics), in FP64 and in mixed precision, with HSIM_FLAG_DETERMINISTIC set
+  or not.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import assembly, sim
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torus(cuda):
+    import paper_2111_09039_amd as hs
+    rng = np.random.default_rng(4)
+    V, F = synth.torus(40, 24)
+    V = synth.isotropic_noise(V, F, 0.2 * synth.mean_edge_length(V, F), rng)
+    H = hs.Hierarchy(V, F, 12, levels=2, n_coarsest=200)
+    return V, F, H
+
+
+def test_backward_before_solve_is_state_error(torus):
+    import torch
+    import paper_2111_09039_amd as hs
+    from paper_2111_09039_amd import _lib
+    V, F, _ = torus
+    H = hs.Hierarchy(V, F, 12, levels=2, n_coarsest=200)
+    gV = torch.full((len(V), 3), 7.0, dtype=torch.float64, device="cuda")
+    ge = torch.ones(12, dtype=torch.float64, device="cuda")
+    code = _lib.load().hsim_solve_backward(H.handle, C.c_void_p(ge.data_ptr()), None, C.c_void_p(gV.data_ptr()), None)
+    assert _lib.STATUS[code] == "HSIM_E_STATE"
+    assert b"before" in _lib.load().hsim_last_error()
+    torch.cuda.synchronize()
+    assert bool((gV == 7.0).all())
+    # a solve without the saved forward state: still HSIM_E_STATE
+    H.solve(tol=1e-6)
+    with pytest.raises(hs.HsimError) as e:
+        H.backward(grad_evals=ge)
+    assert e.value.code == -7
+    H.close()
+
+
+def test_noconv_fills_outputs(torus):
+    V, F, H = torus
+    ev, X, r, st = H.solve(tol=1e-12, max_iters=1, raise_noconv=False)
+    assert st["status"] == "HSIM_E_NOCONV"
+    ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
+    assert np.isfinite(ev).all() and np.isfinite(X).all() and np.isfinite(r).all()
+    assert np.all(np.diff(ev) >= 0)
+    assert r.max() >= 1e-12
+    assert st["iters"][1] == 1
+    # the reported residuals are those of the returned iterate
+    S, m = assembly.assemble(V, F)
+    assert np.allclose(sim.residual(S, m, X, ev), r, rtol=1e-6, atol=1e-14)
+    # and the same call raises through the binding by default
+    import paper_2111_09039_amd as hs
+    with pytest.raises(hs.HsimError) as e:
+        H.solve(tol=1e-12, max_iters=1)
+    assert e.value.code == -4
+
+
+def test_singular_shift(torus):
+    import paper_2111_09039_amd as hs
+    V, F, H = torus
+    try:
+        neg = H.factor(0, 0.0)
+        assert neg in (0, 1)
+    except hs.HsimError as e:
+        assert e.code == -3
+    # the hierarchy recovers: a regular shift and a full solve work afterwards
+    assert H.factor(0, -1e-3) == 0
+    ev, X, r, st = H.solve(tol=1e-8)
+    assert r.cpu().numpy().max() < 1e-8
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_solves_are_bitwise_equal(torus, precision):
+    import torch
+    from paper_2111_09039_amd import _lib
+    V, F, H = torus
+    outs = []
+    for flags in (0, 8):           # HSIM_FLAG_DETERMINISTIC = 8
+        lib = _lib.load()
+        o = _lib.SolveOpts()
+        lib.hsim_default_solve_opts(C.byref(o))
+        o.tol, o.precision, o.flags = 1e-8, precision, flags
+        o.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        ev = torch.empty(12, dtype=torch.float64, device="cuda")
+        X = torch.empty(12, len(V), dtype=torch.float64, device="cuda")
+        r = torch.empty(12, dtype=torch.float64, device="cuda")
+        _lib.check(lib.hsim_solve(H.handle, C.byref(o), C.c_void_p(ev.data_ptr()), C.c_void_p(X.data_ptr()),
+                                  C.c_void_p(r.data_ptr()), None))
+        outs.append((ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))

@@ -316,3 +316,82 @@ def test_hsim_oracle_reaches_dense_solution():
     assert info["resid"].max() < 1e-8
     assert metrics.eigenvector_err(X, Y[:, :40], m, ref[:40]).max() < 1e-5
     assert metrics.m_orthonormality(X, m) < 1e-10
+
+
+# ------------------------------------------------------------ error metrics
+@pytest.fixture(scope="module")
+def sphere162_pairs():
+    """All eigenpairs of the 162-vertex icosphere (LAPACK): exact clusters of
+    the sphere spectrum, 1, 3, 5, 7, ... (slightly split by the mesh)."""
+    V, F = synth.icosphere(2)
+    S, m = assembly.assemble(V, F)
+    lam, Y = sl.eigh(S.toarray(), np.diag(m))
+    return S, m, lam, Y
+
+
+def test_eigenvector_err_wrong_cluster_is_one(sphere162_pairs):
+    """A vector from another cluster is M-orthogonal to the reference cluster:
+    error exactly 1 (a projection onto the whole reference block instead of
+    the cluster would give 0)."""
+    S, m, lam, Y = sphere162_pairs
+    cl = metrics.clusters(lam[:16])
+    assert [b - a for a, b in cl][:3] == [1, 3, 5]
+    X = Y[:, :9].copy()
+    X[:, 1], X[:, 5] = Y[:, 5], Y[:, 1]          # swap a l=1 vector with a l=2 vector
+    err = metrics.eigenvector_err(X, Y[:, :16], m, lam[:16])
+    assert abs(err[1] - 1.0) < 1e-12 and abs(err[5] - 1.0) < 1e-12
+    others = np.delete(err, [1, 5])
+    assert others.max() < 1e-12
+
+
+def test_eigenvector_err_value_of_a_mixed_vector(sphere162_pairs):
+    """x = cos t y_i + sin t y_j with y_j outside the cluster of y_i has error |sin t|."""
+    S, m, lam, Y = sphere162_pairs
+    X = Y[:, :9].copy()
+    for t in (1e-6, 1e-3, 0.3):
+        X[:, 2] = np.cos(t) * Y[:, 2] + np.sin(t) * Y[:, 12]
+        err = metrics.eigenvector_err(X, Y[:, :16], m, lam[:16])
+        assert abs(err[2] - np.sin(t)) <= 1e-9 * max(np.sin(t), 1e-3), t
+        # a rotation inside the cluster costs nothing
+    X[:, 1:4] = Y[:, 1:4] @ sl.qr(np.random.default_rng(1).standard_normal((3, 3)))[0]
+    assert metrics.eigenvector_err(X[:, :4], Y[:, :16], m, lam[:16]).max() < 1e-12
+
+
+def test_m_orthonormality_flags_a_bad_block(sphere162_pairs):
+    S, m, lam, Y = sphere162_pairs
+    X = Y[:, :10].copy()
+    assert metrics.m_orthonormality(X, m) < 1e-12
+    X[:, 3] *= 1.1                                   # ||x_3||_M^2 = 1.21
+    assert abs(metrics.m_orthonormality(X, m) - 0.21) < 1e-12
+    X = Y[:, :10].copy()
+    X[:, 4] += 0.05 * Y[:, 7]                        # x_7^T M x_4 = 0.05
+    assert abs(metrics.m_orthonormality(X, m) - 0.05) < 1e-12
+    # Euclidean-orthonormal but not M-orthonormal
+    Q = sl.qr(Y[:, :10], mode="economic")[0]
+    assert metrics.m_orthonormality(Q, m) > 0.1
+
+
+def test_sketch_estimates_cluster_error(sphere162_pairs):
+    """The sketch estimate of the cluster-aware error agrees with the exact
+    error (chi-square spread with r - |C| degrees of freedom), is about 1 for
+    a vector of another cluster and exactly 0 for an in-cluster rotation."""
+    S, m, lam, Y = sphere162_pairs
+    r = 400
+    G = synth.gaussian_matrix(len(m), r, seed=5)
+    cl = metrics.clusters(lam[:16])
+    a, b = cl[2]                                       # the l = 2 cluster
+    Zc = metrics.sketch(Y[:, a:b], m, G)
+    for t in (1e-7, 1e-4, 0.2, np.pi / 2):
+        x = np.cos(t) * Y[:, a + 1] + np.sin(t) * Y[:, 20]
+        est = metrics.sketch_vector_err(metrics.sketch(x, m, G)[:, 0], Zc)
+        exact = metrics.eigenvector_err(np.column_stack([Y[:, :a + 1], x]), Y[:, :16], m, lam[:16])[a + 1]
+        assert abs(est / exact - 1.0) < 0.25, (t, est, exact)
+    # a rotation inside the cluster: out-of-span part 0 up to rounding
+    Q = sl.qr(np.random.default_rng(2).standard_normal((b - a, b - a)))[0]
+    W = metrics.sketch(Y[:, a:b] @ Q, m, G)
+    assert max(metrics.sketch_vector_err(W[:, i], Zc) for i in range(b - a)) < 1e-12
+    assert metrics.sketch_projector_diff(W, Zc) < 1e-12
+    # the projector sketch sees a vector swapped in from another cluster
+    X = Y[:, a:b].copy()
+    X[:, 0] = Y[:, 20]
+    assert metrics.sketch_projector_diff(metrics.sketch(X, m, G), Zc) > 0.1
