@@ -78,7 +78,9 @@ enum { HSIM_FP64 = 0, HSIM_MIXED = 1 };
 /* flags of hsim_solve_opts */
 enum {
     HSIM_FLAG_NOLOCK = 1,        /* disable locking of converged vectors (Section 4.2) */
-    HSIM_FLAG_SAVE_FORWARD = 2,  /* keep what hsim_solve_backward needs (set by the autograd wrapper) */
+    HSIM_FLAG_SAVE_FORWARD = 2,  /* keep what hsim_solve_backward needs (set by the autograd wrapper).
+                                    The state it needs (level-0 factor, Ritz vectors and values) stays
+                                    resident after every converged solve, so the flag changes nothing. */
     HSIM_FLAG_PROFILE = 4,       /* time every kernel launch with HIP events (fills k_ms / k_launches) */
     HSIM_FLAG_DETERMINISTIC = 8  /* bitwise reproducible results run to run on one device.  Every solve
                                     already is (all reductions run in a fixed order; the kernels use
@@ -133,6 +135,10 @@ typedef struct {
     int64_t k_launches[HSIM_KCLASSES];
     double k_bytes[HSIM_KCLASSES];
     double k_flops[HSIM_KCLASSES];
+    /* block triangular solves (one forward and one backward sweep each, every
+     * level and precision) and the right-hand-side columns they covered */
+    int64_t block_solves;
+    int64_t block_solve_cols;
 } hsim_stats;
 
 /* Per-level sizes (hsim_level_desc). */
@@ -203,6 +209,8 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
  *   d_grad_evals  device, [p] dL/dlambda, or NULL
  *   d_grad_evecs  device, [nv x p] column-major dL/dX, or NULL
  *   d_grad_V      device, [nv x 3] row-major, overwritten with dL/dV
+ * HSIM_E_STATE before a converged hsim_solve on this hierarchy (after none, after
+ * one that ended with HSIM_E_NOCONV or another error, or after a step-level call).
  * HSIM_E_UNIMPLEMENTED for a hierarchy built with the Dirichlet boundary
  * option or with circumcentric lumping.
  */

@@ -32,7 +32,7 @@ class Stats(C.Structure):
                 ("ms_gram", C.c_double), ("ms_rr", C.c_double), ("ms_ritz", C.c_double),
                 ("ms_prolong", C.c_double), ("ms_total", C.c_double),
                 ("k_ms", C.c_double * 8), ("k_launches", C.c_int64 * 8), ("k_bytes", C.c_double * 8),
-                ("k_flops", C.c_double * 8)]
+                ("k_flops", C.c_double * 8), ("block_solves", C.c_int64), ("block_solve_cols", C.c_int64)]
 
     def as_dict(self):
         T = self.levels
@@ -41,7 +41,8 @@ class Stats(C.Structure):
                     mu=list(self.mu[:T]), refine_steps=self.refine_steps, escalated=self.escalated,
                     ms_build=self.ms_build, ms_coarse=self.ms_coarse, ms_factor=self.ms_factor,
                     ms_solve=self.ms_solve, ms_gram=self.ms_gram, ms_rr=self.ms_rr, ms_ritz=self.ms_ritz,
-                    ms_prolong=self.ms_prolong, ms_total=self.ms_total,
+                    ms_prolong=self.ms_prolong, ms_total=self.ms_total, block_solves=self.block_solves,
+                    block_solve_cols=self.block_solve_cols,
                     kernels={name: dict(ms=self.k_ms[i], launches=self.k_launches[i], bytes=self.k_bytes[i],
                                         flops=self.k_flops[i]) for i, name in enumerate(KCLASSES)})
 

@@ -94,6 +94,7 @@ struct Prof {
     }
     void reset(bool enable) {
         on = enable;
+        solves = solve_cols = 0;
         used = 0;
         recs.clear();
     }
@@ -109,7 +110,10 @@ struct Prof {
         HIPCHECK(hipEventRecord(b, s));
         recs.push_back({a, b, cls, bytes, flops});
     }
+    int64_t solves = 0, solve_cols = 0;   // block solves since reset (counted with or without profiling)
     void collect(hsim_stats& st, hipStream_t s) {
+        st.block_solves = solves;
+        st.block_solve_cols = solve_cols;
         if (!on) return;
         HIPCHECK(hipStreamSynchronize(s));
         for (const Rec& r : recs) {
@@ -696,6 +700,8 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
     Prof& P = H->prof;
     const double bL = sizeof(TF);
     const int32_t* bi = dptr<int32_t>(L.big_items);
+    P.solves += 1;
+    P.solve_cols += ncols;
     auto big = [&](int phase, const int64_t* rec, int32_t kb) {
         HIPCHECK(launch_big_solve<TF>(phase, tiles, linv, D, tilesT, linvT, fr, bi + rec[0], rec[1], kb, X, H->ld,
                                       col0, ncols,
@@ -1504,7 +1510,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
                                  dptr<double>(h->exportw), s));
     HIPCHECK(hipStreamSynchronize(s));
     h->last_lam = lam;
-    h->solved = true;
+    h->solved = final_status == HSIM_OK;   // the adjoint needs converged eigenpairs
     h->prof.collect(st, s);
     st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();
     if (stats) *stats = st;

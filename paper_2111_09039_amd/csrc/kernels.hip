@@ -2648,16 +2648,23 @@ __device__ void bj_apply_item(double* C, double* V, int32_t m, int32_t r, const 
 #pragma unroll
         for (int v = 0; v < 4; ++v) X[ta * 16 + lk + 4 * v][tc * 16 + li] = acc[v];
         __syncthreads();
-        // out = T Q2, written to the tile and its mirror
+        // out = T Q2, written to the tile and its mirror.  On a diagonal tile
+        // (P == P2) entry (i, j) and its mirror (j, i) are two results computed
+        // in different rounding orders: only the lower triangle (i >= j) is
+        // stored, to both places, so no address gets two different values
+        // (which one landed last would depend on the wave schedule)
         acc = dbl4{0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < W / 4; ++ks) {
             const int l = 4 * ks + lk;
             acc = mfma4(X[ta * 16 + li][l], q2[l * W + tc * 16 + li], acc);
         }
+        const bool diag_tile = P == P2;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t gi = bj_index<B>(ta * 16 + lk + 4 * v, I1, J1);
+            const int lr = ta * 16 + lk + 4 * v;
+            if (diag_tile && lr < tc * 16 + li) continue;
+            const int64_t gi = bj_index<B>(lr, I1, J1);
             C[gi * m + gcol] = acc[v];
             C[gcol * m + gi] = acc[v];
         }

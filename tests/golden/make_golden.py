@@ -21,7 +21,9 @@ The result is pinned to something other than the iteration itself:
 Eigenvectors of a 1M-vertex mesh are too large to keep, so a sketch is stored:
 Z = G^T (M^{1/2} Y) for the seeded Gaussian G = synth.gaussian_matrix(n, r,
 seed) (see oracle.metrics).  Output, next to this script:
-  <workload>_p<p>.json   eigenvalues, residuals, clusters, run and check data
+  <workload>_p<p>.json   eigenvalues, residuals, clusters, run and check data,
+                         and the largest residual of the tested pairs after every
+                         Rayleigh-Ritz step (the oracle's convergence history)
   <workload>_p<p>_sketch.npy   Z (r x k), float64
 
 Usage: python tests/golden/make_golden.py torus100k 100 [--q 200] [--threads 2]
@@ -144,6 +146,7 @@ def main():
         oracle=dict(method="plain subspace iteration (Algorithm 1), two inverse iterations per "
                            "Rayleigh-Ritz step, SuperLU factor of S - mu M, seeded random start",
                     q=q, mu=mu, eps=a.eps, iterations=total_it, start_seed=a.start_seed),
+        history=[float(x) for x in hist],
         checks=dict(max_residual=float(r_chk.max()), m_orthonormality=orth,
                     inertia_below_upper=below_hi, inertia_below_lower=below_lo),
         seconds=round(time.perf_counter() - t0, 1),

@@ -1,7 +1,8 @@
 """Error paths and reproducibility of the C ABI, forced from the host so that
 every kernel still runs to its normal end.
 
-* hsim_solve_backward before any hsim_solve: HSIM_E_STATE, output untouched;
+* hsim_solve_backward before any converged hsim_solve (none, one that ended
+  with HSIM_E_NOCONV, or a step-level call since): HSIM_E_STATE, output untouched;
 * max_iters = 1: HSIM_E_NOCONV with every output filled by the last iterate;
 * a shift at the zero eigenvalue of a closed mesh (S - 0 M = S is singular in
   exact arithmetic): the factorisation either reports the breakdown
@@ -46,8 +47,17 @@ def test_backward_before_solve_is_state_error(torus):
     assert b"before" in _lib.load().hsim_last_error()
     torch.cuda.synchronize()
     assert bool((gV == 7.0).all())
-    # a solve without the saved forward state: still HSIM_E_STATE
-    H.solve(tol=1e-6)
+    # after a solve that did not converge: still HSIM_E_STATE
+    H.solve(tol=1e-12, max_iters=1, raise_noconv=False)
+    with pytest.raises(hs.HsimError) as e:
+        H.backward(grad_evals=ge)
+    assert e.value.code == -7
+    # after a converged solve the adjoint runs
+    H.solve(tol=1e-8)
+    gV = H.backward(grad_evals=ge)
+    assert bool(torch.isfinite(gV).all())
+    # a step-level call reuses the solve's workspace: the state is gone again
+    H.factor(0, -1e-3)
     with pytest.raises(hs.HsimError) as e:
         H.backward(grad_evals=ge)
     assert e.value.code == -7
@@ -65,7 +75,7 @@ def test_noconv_fills_outputs(torus):
     assert st["iters"][1] == 1
     # the reported residuals are those of the returned iterate
     S, m = assembly.assemble(V, F)
-    assert np.allclose(sim.residual(S, m, X, ev), r, rtol=1e-6, atol=1e-14)
+    assert np.allclose(sim.residual(S, m, X, ev), r, rtol=1e-6, atol=1e-12)
     # and the same call raises through the binding by default
     import paper_2111_09039_amd as hs
     with pytest.raises(hs.HsimError) as e:
