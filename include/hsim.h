@@ -287,6 +287,23 @@ hsim_status hsim_step_gram(hsim_hierarchy* h, int32_t level, int32_t k, const do
 hsim_status hsim_step_rr(int32_t k, const double* d_Sbar, const double* d_Mbar, double* d_lam,
                          double* d_Phibar, int32_t* sweeps, void* stream);
 
+/*
+ * hsim_step_rr_noalloc -- hsim_step_rr for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * hsim_step_rr (the same kernels run), for k <= HSIM_RR_NOALLOC_MAX_K; larger
+ * k is HSIM_E_INVALID.  It calls no hipMalloc or hipFree: its work arrays
+ * live in one fixed 4 MiB device region per GPU that the library holds until
+ * the process ends (looked up on the first call on each device).  Every call
+ * on a device shares that region and overwrites it, so calls that overlap on
+ * one device (two host threads, or two streams of one device without
+ * ordering) race; calls on different devices do not.  The call synchronizes
+ * the stream (it reads pivot and rotation counts back to the host).
+ */
+#define HSIM_RR_NOALLOC_MAX_K 256
+hsim_status hsim_step_rr_noalloc(int32_t k, const double* d_Sbar, const double* d_Mbar, double* d_lam,
+                                 double* d_Phibar, int32_t* sweeps, void* stream);
+
 /* Ritz update and residual: Phi = Psi Phibar (the update of Algorithm 1) and the floored relative
  * residual of every column (eq. conv2 in the M^-1 norm on level 0, the
  * Euclidean norm on coarser levels, Section 5), with lam_floor the lambda_c

@@ -76,6 +76,7 @@ SIGNATURES = {
     "hsim_step_solve": (C.c_int, [_P, _I32, _I32, _P, _P, _I32, _D, _P]),
     "hsim_step_gram": (C.c_int, [_P, _I32, _I32, _P, _P, _P, _I32, _P]),
     "hsim_step_rr": (C.c_int, [_I32, _P, _P, _P, _P, C.POINTER(_I32), _P]),
+    "hsim_step_rr_noalloc": (C.c_int, [_I32, _P, _P, _P, _P, C.POINTER(_I32), _P]),
     "hsim_step_ritz": (C.c_int, [_P, _I32, _I32, _P, _P, _P, _D, _P, _P, _P]),
     "hsim_step_coarse": (C.c_int, [_P, _I32, _P, _P, C.POINTER(_I32), _P]),
 }

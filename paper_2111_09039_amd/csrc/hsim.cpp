@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "internal.h"
@@ -137,54 +138,48 @@ struct Prof {
 struct DenseGEP {
     int32_t k = 0, m = 0, ns_pad = 0, Mt = 0, bj = 16;
     std::vector<int64_t> diag_ptr, panel_ptr, upd_ptr;
-    DeviceBuffer front, tiles, linv, D, items_diag, items_panel, items_upd, gptr, counters;
     // large problems: triangular solves by the multi-workgroup block solve over
     // 128-row pivot blocks (transposed tile copies for the backward sweep)
     bool big = false;
     int32_t nblk = 0;
     std::vector<int64_t> fupd_off, fupd_cnt, bupd_off, bupd_cnt;
-    DeviceBuffer tilesT, linvT, big_items;
-    DeviceBuffer S2, M2, e, W, W2, C, V, Qs, qrot, rot, dis, normf;
+    // device work arrays: owned (setup) or carved from a caller's region (setup_in)
+    DeviceBuffer store;
+    DFront* front = nullptr;
+    double *tiles = nullptr, *linv = nullptr, *D = nullptr, *tilesT = nullptr, *linvT = nullptr;
+    double *S2 = nullptr, *M2 = nullptr, *e = nullptr, *W = nullptr, *W2 = nullptr, *C = nullptr, *V = nullptr,
+           *Qs = nullptr, *dis = nullptr, *normf = nullptr;
+    int32_t *items_diag = nullptr, *items_panel = nullptr, *items_upd = nullptr, *counters = nullptr,
+            *qrot = nullptr, *rot = nullptr, *big_items = nullptr;
+    int64_t* gptr = nullptr;
+    bool owned = false;
 
-    void setup(int32_t kk) {
-        if (k == kk) return;
+    // host-side shape: sizes, work-list offsets and (big problems) the block-solve item list
+    std::vector<int32_t> shape(int32_t kk) {
         k = kk;
         bj = 16;                                       // block Jacobi block size
         m = (int32_t)round_up(k, 2 * bj);
         ns_pad = (int32_t)round_up(k, NB);
         Mt = ns_pad / NB;
-        DFront f{};
-        f.ns = k;
-        f.ns_pad = ns_pad;
-        f.Mt = Mt;
-        f.nsb = Mt;
-        f.parent = -1;
-        front.upload(std::vector<DFront>{f});
-        tiles.alloc((size_t)Mt * (Mt + 1) / 2 * NB * NB * sizeof(double));
-        linv.alloc((size_t)Mt * NB * NB * sizeof(double));
-        D.alloc((size_t)ns_pad * sizeof(double));
-        std::vector<int32_t> dg, pn, up;
         diag_ptr = {0};
         panel_ptr = {0};
         upd_ptr = {0};
-        for (int32_t s = 0; s < Mt; ++s) {
-            dg.push_back(0);
-            for (int32_t I = s + 1; I < Mt; ++I) { pn.push_back(0); pn.push_back(I); }
-            for (int32_t J = s + 1; J < Mt; ++J)
-                for (int32_t I = J; I < Mt; ++I) { up.push_back(0); up.push_back(I); up.push_back(J); }
-            diag_ptr.push_back((int64_t)dg.size());
-            panel_ptr.push_back((int64_t)pn.size() / 2);
-            upd_ptr.push_back((int64_t)up.size() / 3);
+        int64_t nd = 0, np = 0, nu = 0;
+        for (int32_t st = 0; st < Mt; ++st) {
+            nd += 1;
+            np += Mt - 1 - st;
+            for (int32_t J = st + 1; J < Mt; ++J) nu += Mt - J;
+            diag_ptr.push_back(nd);
+            panel_ptr.push_back(np);
+            upd_ptr.push_back(nu);
         }
-        items_diag.upload(dg);
-        items_panel.upload(pn.empty() ? std::vector<int32_t>{0, 0} : pn);
-        items_upd.upload(up.empty() ? std::vector<int32_t>{0, 0, 0} : up);
         big = ns_pad >= env_int("HSIM_DENSE_BIG_MIN", 512);
+        std::vector<int32_t> bi;
         if (big) {
             // items: [0] the front (diagonal phases), then per pivot block the
             // (front, tile row) pairs below it (forward) and above it (backward)
             nblk = (Mt + BIG_BLOCK_TILES - 1) / BIG_BLOCK_TILES;
-            std::vector<int32_t> bi{0, 0};
+            bi = {0, 0};
             fupd_off.assign(nblk, 0);
             fupd_cnt.assign(nblk, 0);
             bupd_off.assign(nblk, 0);
@@ -203,45 +198,95 @@ struct DenseGEP {
                 }
                 bupd_cnt[kb] = ((int64_t)bi.size() - bupd_off[kb]) / 2;
             }
-            big_items.upload(bi);
-            tilesT.alloc((size_t)Mt * (Mt + 1) / 2 * NB * NB * sizeof(double));
-            linvT.alloc((size_t)Mt * NB * NB * sizeof(double));
         }
-        gptr.upload(std::vector<int64_t>((size_t)k + 1, 0));
-        counters.alloc(4 * sizeof(int32_t));
-        const size_t kk2 = (size_t)k * k * sizeof(double);
-        S2.alloc(kk2);
-        M2.alloc(kk2);
-        W.alloc(kk2);
-        W2.alloc(kk2);
-        e.alloc((size_t)k * sizeof(double));
-        dis.alloc((size_t)m * sizeof(double));
-        C.alloc((size_t)m * m * sizeof(double));
-        V.alloc((size_t)m * m * sizeof(double));
-        Qs.alloc((size_t)(m / (2 * bj)) * (2 * bj) * (2 * bj) * sizeof(double));
-        qrot.alloc((size_t)(m / (2 * bj)) * sizeof(int32_t));
-        rot.alloc(4 * sizeof(int32_t));
-        normf.alloc(2 * sizeof(double));
+        return bi;
+    }
+
+    // carve the work arrays out of [base, base + cap) (256-byte aligned pieces);
+    // returns the bytes used (also when base is null: sizing only)
+    size_t carve(char* base, size_t cap, size_t big_ints) {
+        size_t off = 0;
+        auto take = [&](size_t bytes) -> char* {
+            char* q = base ? base + off : nullptr;
+            off += (bytes + 255) / 256 * 256;
+            return q;
+        };
+        const size_t d8 = sizeof(double), kk2 = (size_t)k * k * d8, mm2 = (size_t)m * m * d8;
+        const size_t tile_bytes = (size_t)Mt * (Mt + 1) / 2 * NB * NB * d8;
+        front = reinterpret_cast<DFront*>(take(sizeof(DFront)));
+        tiles = reinterpret_cast<double*>(take(tile_bytes));
+        linv = reinterpret_cast<double*>(take((size_t)Mt * NB * NB * d8));
+        D = reinterpret_cast<double*>(take((size_t)ns_pad * d8));
+        S2 = reinterpret_cast<double*>(take(kk2));
+        M2 = reinterpret_cast<double*>(take(kk2));
+        W = reinterpret_cast<double*>(take(kk2));
+        W2 = reinterpret_cast<double*>(take(kk2));
+        e = reinterpret_cast<double*>(take((size_t)k * d8));
+        dis = reinterpret_cast<double*>(take((size_t)m * d8));
+        C = reinterpret_cast<double*>(take(mm2));
+        V = reinterpret_cast<double*>(take(mm2));
+        Qs = reinterpret_cast<double*>(take((size_t)(m / (2 * bj)) * (2 * bj) * (2 * bj) * d8));
+        normf = reinterpret_cast<double*>(take(2 * d8));
+        gptr = reinterpret_cast<int64_t*>(take((size_t)(k + 1) * sizeof(int64_t)));
+        items_diag = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, diag_ptr.back()) * 4));
+        items_panel = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, panel_ptr.back()) * 2 * 4));
+        items_upd = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, upd_ptr.back()) * 3 * 4));
+        counters = reinterpret_cast<int32_t*>(take(4 * 4));
+        qrot = reinterpret_cast<int32_t*>(take((size_t)(m / (2 * bj)) * 4));
+        rot = reinterpret_cast<int32_t*>(take(4 * 4));
+        if (big) {
+            tilesT = reinterpret_cast<double*>(take(tile_bytes));
+            linvT = reinterpret_cast<double*>(take((size_t)Mt * NB * NB * d8));
+            big_items = reinterpret_cast<int32_t*>(take(big_ints * 4));
+        } else {
+            tilesT = linvT = nullptr;
+            big_items = nullptr;
+        }
+        if (base && off > cap) fail(HSIM_E_INVALID, "dense eigenproblem work arrays need %zu bytes, %zu available", off, cap);
+        return off;
+    }
+
+    // owned work arrays (allocated here, kept for the next call of the same size)
+    void setup(int32_t kk, hipStream_t s) {
+        if (k == kk && owned) return;
+        std::vector<int32_t> bi = shape(kk);
+        const size_t need = carve(nullptr, 0, bi.size());
+        store.alloc(need);
+        carve(static_cast<char*>(store.p), store.bytes, bi.size());
+        owned = true;
+        fill_lists(bi, s);
+    }
+
+    // work arrays in the caller's device region [base, base + cap): allocates nothing
+    void setup_in(int32_t kk, char* base, size_t cap, hipStream_t s) {
+        std::vector<int32_t> bi = shape(kk);
+        if (big) fail(HSIM_E_INVALID, "dense eigenproblems of %d unknowns need the allocating entry point", kk);
+        carve(base, cap, 0);
+        owned = false;
+        fill_lists(bi, s);
+    }
+
+    // the front descriptor, the tile work lists and the (empty) gather pointers,
+    // written on the device; the block-solve item list of big problems is copied
+    void fill_lists(const std::vector<int32_t>& bi, hipStream_t s) {
+        HIPCHECK(launch_dense_lists(front, k, ns_pad, Mt, items_diag, items_panel, items_upd, gptr, s));
+        if (big) HIPCHECK(hipMemcpyAsync(big_items, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipStreamSynchronize(s));
     }
 
     void factor(hipStream_t s) {
-        int32_t* cnt = dptr<int32_t>(counters);
-        HIPCHECK(launch_fill_i32(cnt, 4, 0, s));
-        const DFront* fr = dptr<DFront>(front);
+        HIPCHECK(launch_fill_i32(counters, 4, 0, s));
         for (int32_t st = 0; st < Mt; ++st) {
-            HIPCHECK(launch_fac_diag(dptr<double>(tiles), dptr<double>(linv), dptr<double>(D), fr,
-                                     dptr<int32_t>(items_diag) + diag_ptr[st], diag_ptr[st + 1] - diag_ptr[st], st,
-                                     cnt, s));
-            HIPCHECK(launch_fac_panel(dptr<double>(tiles), dptr<double>(linv), dptr<double>(D), fr,
-                                      dptr<int32_t>(items_panel) + 2 * panel_ptr[st], panel_ptr[st + 1] - panel_ptr[st],
-                                      st, s));
-            HIPCHECK(launch_fac_update(dptr<double>(tiles), dptr<double>(D), fr,
-                                       dptr<int32_t>(items_upd) + 3 * upd_ptr[st], upd_ptr[st + 1] - upd_ptr[st], st, s));
+            HIPCHECK(launch_fac_diag(tiles, linv, D, front, items_diag + diag_ptr[st], diag_ptr[st + 1] - diag_ptr[st],
+                                     st, counters, s));
+            HIPCHECK(launch_fac_panel(tiles, linv, D, front, items_panel + 2 * panel_ptr[st],
+                                      panel_ptr[st + 1] - panel_ptr[st], st, s));
+            HIPCHECK(launch_fac_update(tiles, D, front, items_upd + 3 * upd_ptr[st], upd_ptr[st + 1] - upd_ptr[st], st,
+                                       s));
         }
         if (big) {
-            HIPCHECK(launch_tile_transpose<double>(dptr<double>(tiles), dptr<double>(tilesT),
-                                                   (int64_t)Mt * (Mt + 1) / 2, s));
-            HIPCHECK(launch_tile_transpose<double>(dptr<double>(linv), dptr<double>(linvT), Mt, s));
+            HIPCHECK(launch_tile_transpose<double>(tiles, tilesT, (int64_t)Mt * (Mt + 1) / 2, s));
+            HIPCHECK(launch_tile_transpose<double>(linv, linvT, Mt, s));
         }
     }
 
@@ -254,12 +299,9 @@ struct DenseGEP {
     // the multi-workgroup block solve of the dense front: forward L^-1 X, or
     // backward L^-T X (no D^-1: the caller scales)
     void big_sweep(bool forward, double* X, int32_t ncols, int64_t ld, hipStream_t s) {
-        const DFront* fr = dptr<DFront>(front);
-        const int32_t* bi = dptr<int32_t>(big_items);
         auto run = [&](int phase, int64_t off, int64_t cnt, int32_t kb) {
-            HIPCHECK(launch_big_solve<double>(phase, dptr<double>(tiles), dptr<double>(linv), dptr<double>(D),
-                                              dptr<double>(tilesT), dptr<double>(linvT), fr, bi + off, cnt, kb, X, ld,
-                                              0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s));
+            HIPCHECK(launch_big_solve<double>(phase, tiles, linv, D, tilesT, linvT, front, big_items + off, cnt, kb, X,
+                                              ld, 0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s));
         };
         if (forward) {
             for (int32_t kb = 0; kb < nblk; ++kb) {
@@ -280,8 +322,8 @@ struct DenseGEP {
             return;
         }
         const int32_t qc = qc_for(ncols);
-        HIPCHECK(launch_solve_fwd<double>(dptr<double>(tiles), dptr<double>(linv), dptr<DFront>(front), 0, 1, ns_pad, X,
-                                          ncols, 0, ncols, qc, nullptr, 0, dptr<int64_t>(gptr), nullptr, nullptr, s));
+        HIPCHECK(launch_solve_fwd<double>(tiles, linv, front, 0, 1, ns_pad, X, ncols, 0, ncols, qc, nullptr, 0, gptr,
+                                          nullptr, nullptr, s));
     }
     void bwd(double* X, int32_t ncols, int64_t ld, hipStream_t s) {
         if (big) {
@@ -289,8 +331,7 @@ struct DenseGEP {
             return;
         }
         const int32_t qc = qc_for(ncols);
-        HIPCHECK(launch_solve_bwd<double>(dptr<double>(tiles), dptr<double>(linv), dptr<double>(D), dptr<DFront>(front),
-                                          0, 1, ns_pad, X, ld, 0, ncols, qc, nullptr, false, s));
+        HIPCHECK(launch_solve_bwd<double>(tiles, linv, D, front, 0, 1, ns_pad, X, ld, 0, ncols, qc, nullptr, false, s));
     }
 
     // returns the Jacobi sweeps used, or -1 when dM is not numerically
@@ -302,49 +343,72 @@ struct DenseGEP {
 
 int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* lam_out, double* X, int64_t ldx,
                       hipStream_t s, int32_t max_sweeps) {
-    HIPCHECK(launch_equilibrate(dS, dM, k, dptr<double>(S2), dptr<double>(M2), dptr<double>(e), s));
-    HIPCHECK(launch_dense_to_front(dptr<double>(M2), k, dptr<double>(tiles), Mt, s));
+    HIPCHECK(launch_equilibrate(dS, dM, k, S2, M2, e, s));
+    HIPCHECK(launch_dense_to_front(M2, k, tiles, Mt, s));
     factor(s);
     {
         // the (equilibrated) mass matrix must be positive definite: a negative,
         // zero or non-finite pivot is reported to the caller (-1) instead of
         // turning into NaN through D^-1/2
         int32_t piv[2] = {0, 0};
-        HIPCHECK(hipMemcpyAsync(piv, counters.p, sizeof(piv), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(piv, counters, sizeof(piv), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         if (piv[0] > 0 || piv[1] > 0) return -1;
     }
     // W = L^-1 S', W2 = W^T, W2 <- L^-1 W2 = L^-1 S' L^-T
-    HIPCHECK(launch_copy2d(dptr<double>(S2), k, k, k, dptr<double>(W), k, s));
-    fwd(dptr<double>(W), k, s);
-    HIPCHECK(launch_transpose(dptr<double>(W), k, dptr<double>(W2), s));
-    fwd(dptr<double>(W2), k, s);
+    HIPCHECK(launch_copy2d(S2, k, k, k, W, k, s));
+    fwd(W, k, s);
+    HIPCHECK(launch_transpose(W, k, W2, s));
+    fwd(W2, k, s);
     // C = D^-1/2 W2 D^-1/2 (symmetrised) embedded in m x m; dis = D^-1/2
-    HIPCHECK(launch_sym_scale(dptr<double>(W2), dptr<double>(D), k, dptr<double>(W), s));
-    HIPCHECK(launch_embed_pad(dptr<double>(W), k, m, dptr<double>(C), dptr<double>(normf), dptr<double>(dis),
-                              dptr<double>(D), s));
-    HIPCHECK(launch_identity(dptr<double>(V), m, s));
+    HIPCHECK(launch_sym_scale(W2, D, k, W, s));
+    HIPCHECK(launch_embed_pad(W, k, m, C, normf, dis, D, s));
+    HIPCHECK(launch_identity(V, m, s));
     const double tol_rel = 1e-15, tol_abs_rel = 1e-17;
     int32_t sweeps = 0;
     // a sweep ends the iteration when it rotated nothing or when no entry is
     // left above the threshold (the next sweep would rotate nothing)
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
-        HIPCHECK(launch_fill_i32(dptr<int32_t>(rot), 2, 0, s));
-        HIPCHECK(launch_bj_sweep(bj, dptr<double>(C), dptr<double>(V), m, dptr<double>(Qs), dptr<double>(normf),
-                                 tol_rel, tol_abs_rel, 1, dptr<int32_t>(rot), dptr<int32_t>(qrot), s));
-        HIPCHECK(launch_bj_offcount(dptr<double>(C), m, dptr<double>(normf), tol_rel, tol_abs_rel,
-                                    dptr<int32_t>(rot) + 1, s));
+        HIPCHECK(launch_fill_i32(rot, 2, 0, s));
+        HIPCHECK(launch_bj_sweep(bj, C, V, m, Qs, normf, tol_rel, tol_abs_rel, 1, rot, qrot, s));
+        HIPCHECK(launch_bj_offcount(C, m, normf, tol_rel, tol_abs_rel, rot + 1, s));
         int32_t cnt[2] = {0, 0};
-        HIPCHECK(hipMemcpyAsync(cnt, rot.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(cnt, rot, sizeof(cnt), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         if (cnt[0] == 0 || cnt[1] == 0) break;
     }
     // Y = D^-1/2 V (sorted, first kout columns), X' = L^-T Y, X = E X'
-    HIPCHECK(launch_sort_eig(dptr<double>(C), m, m, dptr<double>(V), k, dptr<double>(dis), kout, lam_out,
-                             dptr<double>(W), kout, s));
-    bwd(dptr<double>(W), kout, kout, s);
-    HIPCHECK(launch_diag_scale(dptr<double>(e), k, dptr<double>(W), kout, kout, X, ldx, s));
+    HIPCHECK(launch_sort_eig(C, m, m, V, k, dis, kout, lam_out, W, kout, s));
+    bwd(W, kout, kout, s);
+    HIPCHECK(launch_diag_scale(e, k, W, kout, kout, X, ldx, s));
     return std::min(sweeps, max_sweeps);
+}
+
+// ============================== reduced eigenproblem without allocation
+// Work arrays of hsim_step_rr_noalloc: one fixed region per device, sized
+// for HSIM_RR_NOALLOC_MAX_K unknowns (3.6 MB used of 4 MiB), held until the
+// process ends.  Host code never names the array in a kernel argument or a
+// copy: it takes the device address from hipGetSymbolAddress, once per
+// device, with that device current.
+constexpr size_t RR_SCRATCH_BYTES = size_t(4) << 20;
+static __device__ __align__(256) char scratch[RR_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::vector<char*> g_scratch_ptr;   // per device ordinal
+
+static char* rr_scratch_ptr() {
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            fail(HSIM_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    return g_scratch_ptr[dev];
 }
 
 // ================================================================ levels
@@ -915,7 +979,7 @@ static bool rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam,
     });
     HIPCHECK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
-    H->rr.setup(q);
+    H->rr.setup(q, s);
     int32_t sweeps = 0;
     H->prof.run(HSIM_K_JACOBI, 0.0, 0.0, s, [&] {
         sweeps = H->rr.run(dptr<double>(H->Sbar), dptr<double>(H->Mbar), q, dptr<double>(H->lam),
@@ -1304,8 +1368,25 @@ hsim_status hsim_step_rr(int32_t k, const double* d_Sbar, const double* d_Mbar, 
     if (!d_Sbar || !d_Mbar || !d_lam || !d_Phibar) fail(HSIM_E_INVALID, "null argument");
     static thread_local std::unique_ptr<DenseGEP> g;
     if (!g) g.reset(new DenseGEP());
-    g->setup(k);
+    g->setup(k, S_(stream));
     int32_t sw = g->run(d_Sbar, d_Mbar, k, d_lam, d_Phibar, k, S_(stream));
+    if (sw < 0) fail(HSIM_E_FACTOR, "the reduced mass matrix is not positive definite");
+    if (sweeps) *sweeps = sw;
+    API_END
+}
+
+hsim_status hsim_step_rr_noalloc(int32_t k, const double* d_Sbar, const double* d_Mbar, double* d_lam,
+                                 double* d_Phibar, int32_t* sweeps, void* stream) {
+    API_BEGIN
+    if (k < 1 || k > HSIM_RR_NOALLOC_MAX_K)
+        fail(HSIM_E_INVALID, "k = %d outside [1, %d] of the allocation-free reduced eigenproblem", k,
+             HSIM_RR_NOALLOC_MAX_K);
+    if (!d_Sbar || !d_Mbar || !d_lam || !d_Phibar) fail(HSIM_E_INVALID, "null argument");
+    hipStream_t s = S_(stream);
+    char* base = rr_scratch_ptr();
+    static thread_local DenseGEP g;   // host bookkeeping only; its device arrays are carved from the scratch region
+    g.setup_in(k, base, RR_SCRATCH_BYTES, s);
+    int32_t sw = g.run(d_Sbar, d_Mbar, k, d_lam, d_Phibar, k, s);
     if (sw < 0) fail(HSIM_E_FACTOR, "the reduced mass matrix is not positive definite");
     if (sweeps) *sweeps = sw;
     API_END
@@ -1337,7 +1418,7 @@ static void coarse_solve(hsim_hierarchy* h, int32_t k, double* d_lam, double* d_
                             dptr<double>(h->coarseS), s));
     HIPCHECK(launch_densify(dptr<int64_t>(C.dS_ptr), dptr<int32_t>(C.dS_idx), dptr<double>(C.dM_val), nc,
                             dptr<double>(h->coarseM), s));
-    h->coarse.setup((int32_t)nc);
+    h->coarse.setup((int32_t)nc, s);
     int32_t sw = h->coarse.run(dptr<double>(h->coarseS), dptr<double>(h->coarseM), k, d_lam, d_Phi, ldphi, s);
     if (sw < 0) fail(HSIM_E_FACTOR, "coarsest level: the mass matrix is not positive definite");
     if (sweeps) *sweeps = sw;

@@ -131,6 +131,9 @@ hipError_t launch_equilibrate(const double* S, const double* M, int32_t k, doubl
                               hipStream_t s);
 // copy the lower triangle of the k x k row-major A into one dense front (tile
 // storage, Mt tiles per side); dummy pivots beyond k get 1 on the diagonal
+// descriptor, factorisation work lists and zero gather pointers of a dense k x k problem as one front
+hipError_t launch_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t Mt, int32_t* diag, int32_t* panel,
+                              int32_t* upd, int64_t* gptr, hipStream_t s);
 hipError_t launch_dense_to_front(const double* A, int32_t k, double* tiles, int32_t Mt, hipStream_t s);
 // B = A^T (k x k, row-major, ld = k)
 hipError_t launch_transpose(const double* A, int32_t k, double* B, hipStream_t s);

@@ -2386,6 +2386,45 @@ hipError_t launch_equilibrate(const double* S, const double* M, int32_t k, doubl
     return hipGetLastError();
 }
 
+// Descriptor and factorisation work lists of a dense k x k problem held as one
+// front of Mt x Mt tiles: per pivot tile step st the diagonal item (front 0),
+// the panel items (0, I) for I > st and the update items (0, I, J) for
+// st < J <= I; the solve's row-gather pointers are all zero.  One thread
+// writes them (at most a few hundred integers).
+__global__ void k_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t Mt, int32_t* diag, int32_t* panel,
+                              int32_t* upd, int64_t* gptr) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    DFront f{};
+    f.ns = k;
+    f.ns_pad = ns_pad;
+    f.Mt = Mt;
+    f.nsb = Mt;
+    f.parent = -1;
+    *front = f;
+    int64_t nd = 0, np = 0, nu = 0;
+    for (int32_t st = 0; st < Mt; ++st) {
+        diag[nd++] = 0;
+        for (int32_t I = st + 1; I < Mt; ++I) {
+            panel[2 * np] = 0;
+            panel[2 * np + 1] = I;
+            ++np;
+        }
+        for (int32_t J = st + 1; J < Mt; ++J)
+            for (int32_t I = J; I < Mt; ++I) {
+                upd[3 * nu] = 0;
+                upd[3 * nu + 1] = I;
+                upd[3 * nu + 2] = J;
+                ++nu;
+            }
+    }
+    for (int32_t i = 0; i <= k; ++i) gptr[i] = 0;
+}
+hipError_t launch_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t Mt, int32_t* diag, int32_t* panel,
+                              int32_t* upd, int64_t* gptr, hipStream_t s) {
+    k_dense_lists<<<1, 64, 0, s>>>(front, k, ns_pad, Mt, diag, panel, upd, gptr);
+    return hipGetLastError();
+}
+
 __global__ void k_dense_to_front(const double* A, int32_t k, double* tiles, int32_t Mt) {
     const int64_t np = (int64_t)Mt * T32;
     const int64_t tot = np * np;
