@@ -37,20 +37,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_solves(H, precision, tol, steps, warmup):
+def run_solves(H, precision, tol, steps, warmup, **kw):
     import torch
-    from paper_2111_09039_amd import FP64
     for i in range(warmup):
-        H.solve(tol=tol, precision=precision)
-        log(f"warmup {i + 1}/{warmup} precision={precision}")
+        H.solve(tol=tol, precision=precision, **kw)
+        log(f"warmup {i + 1}/{warmup} precision={precision} {kw}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = None
     for i in range(steps):
-        out = H.solve(tol=tol, precision=precision)
+        out = H.solve(tol=tol, precision=precision, **kw)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    log(f"timed {steps} solves precision={precision}: {dt * 1e3:.1f} ms/solve, iters {out[3]['iters']}")
+    log(f"timed {steps} solves precision={precision} {kw}: {dt * 1e3:.1f} ms/solve, iters {out[3]['iters']}")
     return dt, out
 
 
@@ -245,7 +244,7 @@ def main():
             rel = (evm - ev64).abs()[1:] / ev64[1:].abs()
             results["mixed"] = dict(s=dtm, iters=stm["iters"], max_resid=float(rm.max()),
                                     max_eig_rel_diff_vs_fp64=float(rel.max()), refine_steps=stm["refine_steps"],
-                                    escalated=stm["escalated"], stats=stm)
+                                    escalated=stm["escalated"], gram_steps=stm["gram_steps"], stats=stm)
             outs["mixed"] = (evm, Xm)
             # headline: the faster of the two precision modes (both reach the tolerance)
             if dtm < dt64 and float(rm.max()) <= args.tol:
@@ -253,6 +252,17 @@ def main():
         except hs.HsimError as e:
             log(f"mixed precision unavailable: {e}")
             results["mixed"] = dict(error=str(e))
+        # the other Gram forms of the mixed solve (not headline candidates):
+        # FP32 interim Gram at any q, compensated FP32 Gram near convergence
+        for name, kw in (("mixed_fp32_gram", dict(fp32_gram=True)), ("mixed_compensated_gram",
+                                                                      dict(compensated_gram=True))):
+            try:
+                dtv, (evv, Xv, rv, stv) = run_solves(H, hs.MIXED, args.tol, min(args.steps, 5), 1, **kw)
+                results[name] = dict(s=dtv, iters=stv["iters"], max_resid=float(rv.max()),
+                                     gram_steps=stv["gram_steps"], refine_steps=stv["refine_steps"])
+                outs[name] = (evv, Xv)
+            except hs.HsimError as e:
+                results[name] = dict(error=str(e))
 
     # per-eigenpair errors against the stored oracle result of this workload
     errors = None
@@ -327,6 +337,8 @@ def main():
                    "hierarchy_build_s": round(t_build, 3), "factor_nnz": info0["factor_nnz"],
                    "fp64_iters": st64["iters"], "fp64_max_resid": results["fp64"]["max_resid"],
                    "mixed": {k: v for k, v in results.get("mixed", {}).items() if k != "stats"},
+                   "mixed_forms": {k: results[k] for k in ("mixed_fp32_gram", "mixed_compensated_gram")
+                                   if k in results},
                    "errors_vs_oracle": errors},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -73,8 +73,8 @@ typedef struct {
 
 enum { HSIM_BUILD_HOST_ONLY = 1 };
 
-/* precision forms of the solve */
-enum { HSIM_FP64 = 0, HSIM_MIXED = 1 };
+/* precision forms of the solve; HSIM_GRAM_COMPENSATED only for hsim_step_gram */
+enum { HSIM_FP64 = 0, HSIM_MIXED = 1, HSIM_GRAM_COMPENSATED = 2 };
 /* flags of hsim_solve_opts */
 enum {
     HSIM_FLAG_NOLOCK = 1,        /* disable locking of converged vectors (Section 4.2) */
@@ -82,10 +82,19 @@ enum {
                                     The state it needs (level-0 factor, Ritz vectors and values) stays
                                     resident after every converged solve, so the flag changes nothing. */
     HSIM_FLAG_PROFILE = 4,       /* time every kernel launch with HIP events (fills k_ms / k_launches) */
-    HSIM_FLAG_DETERMINISTIC = 8  /* bitwise reproducible results run to run on one device.  Every solve
+    HSIM_FLAG_DETERMINISTIC = 8, /* bitwise reproducible results run to run on one device.  Every solve
                                     already is (all reductions run in a fixed order; the kernels use
                                     integer atomics only, for counters): the flag is accepted and
                                     changes nothing.  Unknown flag bits are HSIM_E_INVALID. */
+    HSIM_FLAG_COMPENSATED_GRAM = 16, /* HSIM_MIXED: the Rayleigh-Ritz steps that do not use the FP32 Gram
+                                    use the compensated FP32 Gram (hi/lo split, three FP32 products,
+                                    FP64 sums) instead of the FP64 one; a step whose reduced mass
+                                    matrix then has no positive definite factor is redone in FP64 */
+    HSIM_FLAG_NO_FP32_GRAM = 32, /* HSIM_MIXED: no FP32 Gram in the iterations far from convergence */
+    HSIM_FLAG_FP32_GRAM = 64     /* HSIM_MIXED: the FP32 Gram in the iterations far from convergence at
+                                    any q (by default only for q > 160, where the FP64 Gram is a
+                                    multi-pass product as well; below, the single-pass FP64 product is
+                                    the faster one on the FP64 matrix cores) */
 };
 
 /* kernel classes of the profile counters in hsim_stats */
@@ -139,6 +148,8 @@ typedef struct {
      * level and precision) and the right-hand-side columns they covered */
     int64_t block_solves;
     int64_t block_solve_cols;
+    /* Rayleigh-Ritz Gram products by form: FP64, FP32, compensated FP32 */
+    int32_t gram_steps[3];
 } hsim_stats;
 
 /* Per-level sizes (hsim_level_desc). */
@@ -276,7 +287,10 @@ hsim_status hsim_step_solve(hsim_hierarchy* h, int32_t level, int32_t k, const d
  * (the reduced stiffness and mass matrices of Algorithm 1).
  * d_Psi [n^tau x k]; d_Sbar, d_Mbar [k x k] row-major, symmetric.
  * precision HSIM_MIXED takes the low-precision Gram (FP32 MFMA products of
- * rounded copies, FP32 accumulation within 256-row chunks). */
+ * rounded copies, FP32 accumulation within 256-row chunks, FP64 sums of the
+ * chunks); HSIM_GRAM_COMPENSATED the compensated one (every FP64 operand split
+ * into FP32 hi = fl(x) and lo = fl(x - hi), the products hi*hi + hi*lo + lo*hi
+ * on the FP32 matrix cores, FP64 sums of every 32 rows). */
 hsim_status hsim_step_gram(hsim_hierarchy* h, int32_t level, int32_t k, const double* d_Psi,
                            double* d_Sbar, double* d_Mbar, int32_t precision, void* stream);
 

@@ -17,8 +17,9 @@ from ._lib import HsimError
 
 __all__ = ["Hierarchy", "HsimError", "FP64", "MIXED", "build_library"]
 
-FP64, MIXED = 0, 1
+FP64, MIXED, GRAM_COMPENSATED = 0, 1, 2
 FLAG_NOLOCK, FLAG_SAVE_FORWARD, FLAG_PROFILE, FLAG_DETERMINISTIC = 1, 2, 4, 8
+FLAG_COMPENSATED_GRAM, FLAG_NO_FP32_GRAM, FLAG_FP32_GRAM = 16, 32, 64
 
 
 def build_library(verbose=False):
@@ -99,16 +100,20 @@ class Hierarchy:
 
     # ----------------------------------------------------------- solve
     def solve(self, tol=1e-2, shift_alpha=0.1, precision=FP64, max_iters=100, lock=True, save_forward=False,
-              stream=None, raise_noconv=True, profile=False):
+              stream=None, raise_noconv=True, profile=False, compensated_gram=False, fp32_gram=None):
         """Returns (evals [p], evecs [nv, p], resid [p], stats dict) with CUDA
-        float64 tensors; evecs is the transpose view of a (p, nv) buffer."""
+        float64 tensors; evecs is the transpose view of a (p, nv) buffer.
+        fp32_gram (mixed precision): None = the library's rule (FP32 interim
+        Gram above q = 160), True = at any q, False = never; compensated_gram:
+        the compensated FP32 Gram instead of the FP64 one near convergence."""
         torch = _torch()
         lib = _lib.load()
         o = _lib.SolveOpts()
         lib.hsim_default_solve_opts(C.byref(o))
         o.tol, o.shift_alpha, o.precision, o.max_iters = float(tol), float(shift_alpha), int(precision), int(max_iters)
         o.flags = ((0 if lock else FLAG_NOLOCK) | (FLAG_SAVE_FORWARD if save_forward else 0)
-                   | (FLAG_PROFILE if profile else 0))
+                   | (FLAG_PROFILE if profile else 0) | (FLAG_COMPENSATED_GRAM if compensated_gram else 0)
+                   | {None: 0, True: FLAG_FP32_GRAM, False: FLAG_NO_FP32_GRAM}[fp32_gram])
         o.stream = _stream_ptr(stream)
         dev = torch.device("cuda", torch.cuda.current_device())
         ev = torch.empty(self.p, dtype=torch.float64, device=dev)

@@ -32,7 +32,8 @@ class Stats(C.Structure):
                 ("ms_gram", C.c_double), ("ms_rr", C.c_double), ("ms_ritz", C.c_double),
                 ("ms_prolong", C.c_double), ("ms_total", C.c_double),
                 ("k_ms", C.c_double * 8), ("k_launches", C.c_int64 * 8), ("k_bytes", C.c_double * 8),
-                ("k_flops", C.c_double * 8), ("block_solves", C.c_int64), ("block_solve_cols", C.c_int64)]
+                ("k_flops", C.c_double * 8), ("block_solves", C.c_int64), ("block_solve_cols", C.c_int64),
+                ("gram_steps", C.c_int32 * 3)]
 
     def as_dict(self):
         T = self.levels
@@ -42,7 +43,7 @@ class Stats(C.Structure):
                     ms_build=self.ms_build, ms_coarse=self.ms_coarse, ms_factor=self.ms_factor,
                     ms_solve=self.ms_solve, ms_gram=self.ms_gram, ms_rr=self.ms_rr, ms_ritz=self.ms_ritz,
                     ms_prolong=self.ms_prolong, ms_total=self.ms_total, block_solves=self.block_solves,
-                    block_solve_cols=self.block_solve_cols,
+                    block_solve_cols=self.block_solve_cols, gram_steps=list(self.gram_steps),
                     kernels={name: dict(ms=self.k_ms[i], launches=self.k_launches[i], bytes=self.k_bytes[i],
                                         flops=self.k_flops[i]) for i, name in enumerate(KCLASSES)})
 

@@ -478,6 +478,7 @@ struct hsim_hierarchy {
     bool bw_ready = false;
     int32_t cg_iters = 0;
     bool solved = false, host_only = false;
+    int32_t gram_steps[3] = {0, 0, 0};   // Rayleigh-Ritz Gram products per form in the last solve
     std::vector<double> last_lam;
     hsim::Prof prof;
 };
@@ -962,10 +963,12 @@ static double choose_shift(const std::vector<double>& lam, int32_t p, double alp
 
 // one Rayleigh-Ritz step on level L from the basis in Psi (already inverse
 // iterated); leaves Phi, lam (device) and returns lam/resid on the host
-// false (and Phi untouched) when the FP32 Gram left the reduced mass matrix
-// without a positive definite factor; the caller repeats the step in FP64
+// false (and Phi untouched) when a low-precision or compensated Gram
+// (gram_mode != GRAM_FP64) left the reduced mass matrix without a positive
+// definite factor; the caller repeats the step in FP64
 static bool rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam, std::vector<double>& res,
-                          hipStream_t s, double* ms_gram, double* ms_rr, double* ms_ritz, bool fp32_gram = false) {
+                          hipStream_t s, double* ms_gram, double* ms_rr, double* ms_ritz,
+                          int gram_mode = GRAM_FP64) {
     const int32_t q = H->q;
     const bool fin = L.tau == 0;
     auto t0 = std::chrono::steady_clock::now();
@@ -975,8 +978,9 @@ static bool rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam,
     H->prof.run(HSIM_K_GRAM, 8.0 * nq * (fin ? 2.0 : 3.0) + 8.0 * (fin ? L.n : 0), 2.0 * nq * q, s, [&] {
         HIPCHECK(launch_gram(dptr<double>(H->Psi), dptr<double>(H->SPsi), fin ? nullptr : dptr<double>(H->MPsi),
                              fin ? dptr<double>(L.dmdiag) : nullptr, L.n, q, H->ld, dptr<double>(H->gram_part), H->gram_chunk,
-                             dptr<double>(H->Sbar), dptr<double>(H->Mbar), s, fp32_gram));
+                             dptr<double>(H->Sbar), dptr<double>(H->Mbar), s, gram_mode));
     });
+    H->gram_steps[gram_mode] += 1;
     HIPCHECK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     H->rr.setup(q, s);
@@ -986,7 +990,7 @@ static bool rayleigh_ritz(hsim_hierarchy* H, Level& L, std::vector<double>& lam,
                            dptr<double>(H->Phibar), q, s);
     });
     if (sweeps < 0) {
-        if (fp32_gram) return false;
+        if (gram_mode != GRAM_FP64) return false;
         fail(HSIM_E_FACTOR, "Rayleigh-Ritz step on level %d: the reduced mass matrix is not positive definite "
              "(the iterated basis has lost rank)", L.tau);
     }
@@ -1349,7 +1353,8 @@ hsim_status hsim_step_gram(hsim_hierarchy* h, int32_t level, int32_t k, const do
     Level& L = level_at(h, level);
     if (k < 1 || k > h->q) fail(HSIM_E_INVALID, "k must be in [1, %d]", h->q);
     if (!d_Psi || !d_Sbar || !d_Mbar) fail(HSIM_E_INVALID, "null argument");
-    if (precision != HSIM_FP64 && precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
+    if (precision != HSIM_FP64 && precision != HSIM_MIXED && precision != HSIM_GRAM_COMPENSATED)
+        fail(HSIM_E_INVALID, "unknown precision");
     hipStream_t s = S_(stream);
     HIPCHECK(launch_gather_rows(d_Psi, k, dptr<int32_t>(L.dperm), L.n, k, dptr<double>(h->Psi), h->ld, s));
     apply_level(h, L, 0, dptr<double>(h->Psi), dptr<double>(h->SPsi), k, s);
@@ -1357,7 +1362,9 @@ hsim_status hsim_step_gram(hsim_hierarchy* h, int32_t level, int32_t k, const do
     if (!fin) apply_level(h, L, 1, dptr<double>(h->Psi), dptr<double>(h->MPsi), k, s);
     HIPCHECK(launch_gram(dptr<double>(h->Psi), dptr<double>(h->SPsi), fin ? nullptr : dptr<double>(h->MPsi),
                          fin ? dptr<double>(L.dmdiag) : nullptr, L.n, k, h->ld, dptr<double>(h->gram_part), h->gram_chunk, d_Sbar,
-                         d_Mbar, s, precision == HSIM_MIXED));
+                         d_Mbar, s,
+                         precision == HSIM_MIXED ? GRAM_FP32
+                                                 : (precision == HSIM_GRAM_COMPENSATED ? GRAM_COMPENSATED : GRAM_FP64)));
     API_END
 }
 
@@ -1446,9 +1453,17 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     if (!(so.tol > 0)) fail(HSIM_E_INVALID, "tol must be positive");
     if (so.max_iters < 1) fail(HSIM_E_INVALID, "max_iters must be >= 1");
     if (so.precision != HSIM_FP64 && so.precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
-    if (so.flags & ~(HSIM_FLAG_NOLOCK | HSIM_FLAG_SAVE_FORWARD | HSIM_FLAG_PROFILE | HSIM_FLAG_DETERMINISTIC))
+    if (so.flags & ~(HSIM_FLAG_NOLOCK | HSIM_FLAG_SAVE_FORWARD | HSIM_FLAG_PROFILE | HSIM_FLAG_DETERMINISTIC |
+                     HSIM_FLAG_COMPENSATED_GRAM | HSIM_FLAG_NO_FP32_GRAM | HSIM_FLAG_FP32_GRAM))
         fail(HSIM_E_INVALID, "unknown solve flags 0x%x", (unsigned)so.flags);
     const bool mixed = so.precision == HSIM_MIXED;
+    // Gram forms of a mixed solve: FP32 far from convergence (unless switched
+    // off), then FP64 or, when asked for, compensated FP32
+    // (by default only above q = 160, where the FP64 Gram is the multi-pass kernel too: below,
+    // the single-pass FP64 kernel is faster than the multi-pass FP32 one)
+    const bool gram32 = (so.flags & HSIM_FLAG_FP32_GRAM) != 0 ||
+                        (!(so.flags & HSIM_FLAG_NO_FP32_GRAM) && h->q > gram_fp64_single_pass_max_q());
+    const int hi_gram = (mixed && (so.flags & HSIM_FLAG_COMPENSATED_GRAM)) ? GRAM_COMPENSATED : GRAM_FP64;
     hipStream_t s = S_(so.stream);
     const auto T0 = std::chrono::steady_clock::now();
     hsim_stats st;
@@ -1459,6 +1474,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     const int32_t q = h->q, p = h->p, T = h->T;
     h->solved = false;
     h->prof.reset((so.flags & HSIM_FLAG_PROFILE) != 0);
+    h->gram_steps[0] = h->gram_steps[1] = h->gram_steps[2] = 0;
     // coarsest level: dense solve, Phi in the coarsest level's order (= its internal order)
     std::vector<double> lam(q), res(q);
     {
@@ -1545,16 +1561,17 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
             HIPCHECK(hipStreamSynchronize(s));
             st.ms_solve += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a0).count();
             // FP32 Gram only far from convergence (its rounding bounds the Ritz
-            // vectors' accuracy; switch for good once it stops paying off), and
-            // only where no single-pass FP64 Gram kernel exists (q > 160)
-            bool low_gram = mixed && !fp64_gram && q > gram_fp64_single_pass_max_q() &&
-                            rmax > std::max(100.0 * so.tol, 1e-4);
-            if (!rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, low_gram)) {
-                // the FP32 Gram lost the definiteness of the reduced mass matrix
+            // vectors' accuracy; switch for good once it stops paying off); the
+            // other steps of a mixed solve take the FP64 Gram, or the compensated
+            // one when asked for
+            bool low_gram = mixed && !fp64_gram && gram32 && rmax > std::max(100.0 * so.tol, 1e-4);
+            const int mode = low_gram ? GRAM_FP32 : (fp64_gram ? GRAM_FP64 : hi_gram);
+            if (!rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, mode)) {
+                // the low-precision Gram lost the definiteness of the reduced mass matrix
                 // (an ill-conditioned basis): this step and the rest of the level in FP64
                 fp64_gram = true;
                 low_gram = false;
-                rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, false);
+                rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, GRAM_FP64);
             }
             auto check = [&] {
                 conv = true;
@@ -1566,10 +1583,16 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
             };
             const double rprev = rmax;
             check();
-            if (low_gram && !(rmax < 0.5 * rprev)) fp64_gram = true;
-            // the returned basis always comes from an FP64 Gram (M-orthonormal to FP64 accuracy)
+            // a low-precision or compensated step that does not halve the largest residual
+            // has reached the accuracy of its Gram: the rest of the level in FP64
+            if ((low_gram || mode == GRAM_COMPENSATED) && !(rmax < 0.5 * rprev)) fp64_gram = true;
+            // the returned basis never comes from the FP32 Gram (FP64 or compensated)
             if (conv && low_gram) {
-                rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, false);
+                if (!rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz,
+                                   fp64_gram ? GRAM_FP64 : hi_gram)) {
+                    fp64_gram = true;
+                    rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, GRAM_FP64);
+                }
                 check();
             }
             if (conv) break;
@@ -1593,6 +1616,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     h->last_lam = lam;
     h->solved = final_status == HSIM_OK;   // the adjoint needs converged eigenpairs
     h->prof.collect(st, s);
+    for (int g = 0; g < 3; ++g) st.gram_steps[g] = h->gram_steps[g];
     st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();
     if (stats) *stats = st;
     if (final_status != HSIM_OK) {

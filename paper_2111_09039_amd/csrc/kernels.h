@@ -108,10 +108,12 @@ hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF
 // ------------------------------------------------------------ Rayleigh-Ritz
 // partial Grams over row chunks of chunk_rows rows (gram_chunk_rows of the
 // largest n the partial buffer is sized for), then the sum
-// fp32: operands rounded to FP32, FP32 accumulation over runs of 256 rows, FP64 sum of the runs
+// mode 0: FP64; 1: operands rounded to FP32, FP32 accumulation over runs of 256 rows, FP64 sum of
+// the runs; 2: compensated (hi/lo FP32 split of every operand, three FP32 products, FP64 stage sums)
+enum { GRAM_FP64 = 0, GRAM_FP32 = 1, GRAM_COMPENSATED = 2 };
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
                        int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
-                       hipStream_t s, bool fp32 = false);
+                       hipStream_t s, int mode = GRAM_FP64);
 int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows);
 int64_t gram_chunk_rows(int64_t n, int32_t q);
 // largest q for which the FP64 Gram is one pass over the rows (all tiles per workgroup)

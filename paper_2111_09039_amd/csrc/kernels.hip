@@ -1684,12 +1684,22 @@ int64_t gram_partial_doubles(int64_t n, int32_t q, int64_t chunk_rows) {
     return std::max(nch * per + per + colsum_tmp_doubles(nch, (int32_t)per), gram_all_partial_doubles(q));
 }
 
-template <class TA>
+// MODE 0: FP64 operands and MFMA.  MODE 1: operands rounded to FP32, FP32
+// MFMA accumulation over runs of 256 rows, FP64 sum of the runs.  MODE 2
+// (compensated): every FP64 operand split into hi = fl32(x) and lo =
+// fl32(x - hi) (together 48 significant bits), three FP32 products per pair
+// (hi*hi, hi*lo, lo*hi; lo*lo is below the FP64 rounding of the result),
+// the hi*hi run and the cross-term run summed in FP32 over one 32-row stage
+// each and added in FP64.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Psi, const double* __restrict__ SPsi,
                                                    const double* __restrict__ MPsi, const double* __restrict__ mdiag,
                                                    int64_t n, int32_t q, int64_t ld, int64_t nchunks,
                                                    int64_t chunk_rows, double* __restrict__ partial) {
-    using V4 = typename std::conditional<std::is_same<TA, double>::value, dbl4, flt4>::type;
+    using TA = typename std::conditional<MODE == 0, double, float>::type;
+    using V4 = typename std::conditional<MODE == 0, dbl4, flt4>::type;
+    constexpr bool COMP = MODE == 2;
+    constexpr int LOW = COMP ? GROWS : 1;          // rows of the lo arrays (1: unused)
     const int32_t nt = (q + GT - 1) / GT;
     const int64_t npairs = (int64_t)nt * (nt + 1) / 2;
     int64_t item;
@@ -1702,6 +1712,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
     const int64_t r1 = min(n, r0 + chunk_rows);
 
     __shared__ TA P[GROWS][GLD], Q[GROWS][GLD], R[GROWS][GLD];
+    __shared__ TA Pl[LOW][GLD], Ql[LOW][GLD], Rl[LOW][GLD];
     const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
     const int wi = w / 2, wj = w % 2;              // quarter of the 64 x 64 block pair
     const bool active = !(a == b && wi > wj);      // strictly lower quarter of a diagonal block
@@ -1713,13 +1724,13 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
             tile_on[t][u] = active && a * GT + wi * 32 + t * 16 < q && b * GT + wj * 32 + u * 16 < q;
 
     dbl4 accS[2][2], accM[2][2];
-    V4 runS[2][2], runM[2][2];
+    V4 runS[2][2], runM[2][2], corS[2][2], corM[2][2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             accS[t][u] = accM[t][u] = dbl4{0, 0, 0, 0};
-            runS[t][u] = runM[t][u] = V4{0, 0, 0, 0};
+            runS[t][u] = runM[t][u] = corS[t][u] = corM[t][u] = V4{0, 0, 0, 0};
         }
 
     // staging: thread -> 8 elements of each array (rows tid / 8 + 32 j / 8 ...)
@@ -1737,15 +1748,33 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
             rv[e] = (ok && cb < q) ? (mdiag ? mdiag[row] * Psi[row * ld + cb] : MPsi[row * ld + cb]) : 0.0;
         }
     };
+    auto fold = [&] {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    accS[t][u][v] += (double)runS[t][u][v] + (double)corS[t][u][v];
+                    accM[t][u][v] += (double)runM[t][u][v] + (double)corM[t][u][v];
+                    runS[t][u][v] = runM[t][u][v] = corS[t][u][v] = corM[t][u][v] = 0;
+                }
+    };
     fetch(r0);
     int steps = 0;
     for (int64_t row0 = r0; row0 < r1; row0 += GROWS) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + 256 * e, i = idx / GT, c = idx % GT;
-            P[i][c] = (TA)pv[e];
-            Q[i][c] = (TA)qv[e];
-            R[i][c] = (TA)rv[e];
+            const TA ph = (TA)pv[e], qh = (TA)qv[e], rh = (TA)rv[e];
+            P[i][c] = ph;
+            Q[i][c] = qh;
+            R[i][c] = rh;
+            if (COMP) {
+                Pl[i][c] = (TA)(pv[e] - (double)ph);
+                Ql[i][c] = (TA)(qv[e] - (double)qh);
+                Rl[i][c] = (TA)(rv[e] - (double)rh);
+            }
         }
         __syncthreads();
         if (row0 + GROWS < r1) fetch(row0 + GROWS);
@@ -1753,13 +1782,20 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
 #pragma unroll
             for (int kk = 0; kk < GROWS; kk += 4) {
                 const int kr = kk + lane / 16;
-                TA av[2], sv[2], mv[2];
+                TA av[2], sv[2], mv[2], al[2], sl[2], ml[2];
 #pragma unroll
-                for (int t = 0; t < 2; ++t) av[t] = P[kr][wi * 32 + t * 16 + lane % 16];
+                for (int t = 0; t < 2; ++t) {
+                    av[t] = P[kr][wi * 32 + t * 16 + lane % 16];
+                    if (COMP) al[t] = Pl[kr][wi * 32 + t * 16 + lane % 16];
+                }
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     sv[u] = Q[kr][wj * 32 + u * 16 + lane % 16];
                     mv[u] = R[kr][wj * 32 + u * 16 + lane % 16];
+                    if (COMP) {
+                        sl[u] = Ql[kr][wj * 32 + u * 16 + lane % 16];
+                        ml[u] = Rl[kr][wj * 32 + u * 16 + lane % 16];
+                    }
                 }
 #pragma unroll
                 for (int t = 0; t < 2; ++t)
@@ -1768,21 +1804,20 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ Ps
                         if (tile_on[t][u]) {
                             runS[t][u] = mfma4(av[t], sv[u], runS[t][u]);
                             runM[t][u] = mfma4(av[t], mv[u], runM[t][u]);
+                            if (COMP) {
+                                corS[t][u] = mfma4(av[t], sl[u], corS[t][u]);
+                                corS[t][u] = mfma4(al[t], sv[u], corS[t][u]);
+                                corM[t][u] = mfma4(av[t], ml[u], corM[t][u]);
+                                corM[t][u] = mfma4(al[t], mv[u], corM[t][u]);
+                            }
                         }
             }
         }
         __syncthreads();
-        if (!std::is_same<TA, double>::value && ++steps == 8) {   // FP32: fold a run of 256 rows into FP64
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        accS[t][u][v] += (double)runS[t][u][v];
-                        accM[t][u][v] += (double)runM[t][u][v];
-                        runS[t][u][v] = runM[t][u][v] = 0;
-                    }
+        if (COMP) {
+            fold();                                            // FP64 sum of every 32-row stage
+        } else if (MODE == 1 && ++steps == 8) {                // FP32: fold a run of 256 rows into FP64
+            fold();
             steps = 0;
         }
     }
@@ -2005,8 +2040,8 @@ __global__ void k_gram_scatter(const double* __restrict__ sums, int32_t q, doubl
 
 hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi, const double* mdiag, int64_t n,
                        int32_t q, int64_t ld, double* partial, int64_t chunk_rows, double* Sbar, double* Mbar,
-                       hipStream_t s, bool fp32) {
-    if (!fp32 && q <= GA_MAXT * 16) {
+                       hipStream_t s, int mode) {
+    if (mode == 0 && q <= GA_MAXT * 16) {
         const int32_t nt = (int32_t)cdiv(q, 16);
         const int64_t nup = (int64_t)nt * (nt + 1) / 2, per = 2 * nup * 256;
         const int64_t nwg = std::max<int64_t>(1, std::min<int64_t>({(int64_t)device_cus(), cdiv(n, GA_R),
@@ -2036,10 +2071,12 @@ hipError_t launch_gram(const double* Psi, const double* SPsi, const double* MPsi
     const int64_t nch = cdiv(n, chunk_rows);
     const int64_t per = npairs * 2 * GT * GT;
     const unsigned grid = (unsigned)(cdiv(nch * npairs, NXCD) * NXCD);
-    if (fp32)
-        k_gram_mfma<float><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, chunk_rows, partial);
+    if (mode == 2)
+        k_gram_mfma<2><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, chunk_rows, partial);
+    else if (mode == 1)
+        k_gram_mfma<1><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, chunk_rows, partial);
     else
-        k_gram_mfma<double><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, chunk_rows, partial);
+        k_gram_mfma<0><<<grid, 256, 0, s>>>(Psi, SPsi, MPsi, mdiag, n, q, ld, nch, chunk_rows, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     double* sums = partial + nch * per;

@@ -7,8 +7,9 @@ Sylvester inertia counts).
 * 1M bumpy sphere, p = 100 and p = 200, two levels (the paper's rule), eps = 1e-6.
 
 Every returned eigenvalue is compared with the oracle's (relative error, the
-lambda = 0 mode against lambda_1): <= 1e-9 for FP64, <= 1e-6 for mixed
-precision.  Every returned eigenvector is compared with the oracle's cluster
+lambda = 0 mode against lambda_1): <= 1e-9 for FP64, <= 1e-6 for each mixed
+precision form (the library's Gram rule, the FP32 interim Gram at any q, the
+compensated Gram near convergence).  Every returned eigenvector is compared with the oracle's cluster
 (relative gaps < 1e-2) through the stored sketch (oracle.metrics): its
 M-norm distance to the cluster's span must stay below the Davis-Kahan bound
 of its residual, tol * lambda / gap with the gap of the cluster to the rest
@@ -107,17 +108,20 @@ def _run(mesh, name, p, levels, capsys=None):
     G = synth.gaussian_matrix(len(V), g["sketch"]["rows"], g["sketch"]["seed"])
     H = hs.Hierarchy(V, F, p, density=d, levels=levels)
     out = {}
-    for prec, bar in ((hs.FP64, 1e-9), (hs.MIXED, 1e-6)):
-        ev, X, r, st = H.solve(tol=TOL, precision=prec)
+    forms = ((hs.FP64, {}, 1e-9), (hs.MIXED, {}, 1e-6), (hs.MIXED, dict(fp32_gram=True), 1e-6),
+             (hs.MIXED, dict(compensated_gram=True), 1e-6))
+    for prec, kw, bar in forms:
+        ev, X, r, st = H.solve(tol=TOL, precision=prec, **kw)
         ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
         assert r.max() < TOL
         assert sim.residual(S, m, X, ev).max() < 1.5 * TOL
         assert metrics.m_orthonormality(X, m) < (1e-10 if prec == hs.FP64 else 1e-8)
         e_val, e_vec, diffs = compare(g, ev, X, m, G, TOL, bar)
-        print(f"[{name} p={p} precision={prec}] iters {st['iters']}: eigenvalue error max {e_val.max():.2e} "
+        print(f"[{name} p={p} precision={prec} {kw}] iters {st['iters']} Gram forms {st['gram_steps']}: "
+              f"eigenvalue error max {e_val.max():.2e} "
               f"median {np.median(e_val):.2e}; eigenvector error max {e_vec.max():.2e} median "
               f"{np.median(e_vec):.2e}; cluster sketch max {diffs.max() if len(diffs) else 0:.2e}", flush=True)
-        out[prec] = (e_val, e_vec)
+        out[(prec, tuple(kw))] = (e_val, e_vec)
     H.close()
     return out
 

@@ -289,6 +289,27 @@ def test_mixed_gram(small):
         assert np.abs(Sb.cpu().numpy() - Sr).max() > 0      # really the low-precision path
 
 
+def test_compensated_gram(small):
+    """Compensated Gram (hi/lo FP32 split of the FP64 operands, three FP32
+    matrix-core products, FP64 sums of 32-row stages): more accurate than the
+    FP32 Gram, bounded by the FP32 rounding of the matrix cores' accumulation
+    (a 4-term sum per instruction), far above FP64 rounding."""
+    import paper_2111_09039_amd as hs
+    V, F, S, m, lv, H = small
+    rng = np.random.default_rng(8)
+    for tau in range(3):
+        n = len(lv[tau]["verts"])
+        Psi = rng.standard_normal((n, 30))
+        Sr = Psi.T @ (lv[tau]["S"] @ Psi)
+        Mr = Psi.T @ (_mass(lv, tau) @ Psi)
+        Sc, Mc = (x.cpu().numpy() for x in H.gram(tau, _t(Psi), precision=hs.GRAM_COMPENSATED))
+        S32, M32 = (x.cpu().numpy() for x in H.gram(tau, _t(Psi), precision=hs.MIXED))
+        ec = max(np.abs(Sc - Sr).max() / np.abs(Sr).max(), np.abs(Mc - Mr).max() / np.abs(Mr).max())
+        e32 = max(np.abs(S32 - Sr).max() / np.abs(Sr).max(), np.abs(M32 - Mr).max() / np.abs(Mr).max())
+        print(f"[compensated gram] level {tau}: rel err {ec:.2e} (FP32 {e32:.2e})")
+        assert ec <= 2e-7 and ec < 0.5 * e32 and ec > 0
+
+
 def test_hsim_mixed_end_to_end(cuda):
     import paper_2111_09039_amd as hs
     V, F, d = synth.config_mesh("sphere2k", seed=0)
