@@ -91,10 +91,15 @@ enum {
                                     FP64 sums) instead of the FP64 one; a step whose reduced mass
                                     matrix then has no positive definite factor is redone in FP64 */
     HSIM_FLAG_NO_FP32_GRAM = 32, /* HSIM_MIXED: no FP32 Gram in the iterations far from convergence */
-    HSIM_FLAG_FP32_GRAM = 64     /* HSIM_MIXED: the FP32 Gram in the iterations far from convergence at
+    HSIM_FLAG_FP32_GRAM = 64,    /* HSIM_MIXED: the FP32 Gram in the iterations far from convergence at
                                     any q (by default only for q > 160, where the FP64 Gram is a
                                     multi-pass product as well; below, the single-pass FP64 product is
                                     the faster one on the FP64 matrix cores) */
+    HSIM_FLAG_GRAPH = 128        /* HSIM_FP64: the two inverse iterations of a subspace iteration
+                                    (every block-solve launch, and the M products on coarse levels) are
+                                    captured once per (level, locked columns, buffers) into a HIP graph
+                                    kept by the hierarchy and replayed; same results bit for bit.
+                                    Ignored with HSIM_FLAG_PROFILE. */
 };
 
 /* kernel classes of the profile counters in hsim_stats */
@@ -209,6 +214,50 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
                        double* d_evecs, double* d_resid, hsim_stats* stats);
 
 /*
+ * hsim_solve_batch -- hsim_solve for many hierarchies (meshes of uneven
+ * size) at once: the solves are spread over `streams` worker streams of the
+ * current device (0 = 8), one host thread each, largest meshes first, so the
+ * small meshes' latency-bound launches overlap on the GPU.  Every mesh gets
+ * exactly the result hsim_solve would give it (same kernels, same order).
+ *
+ *   hs        host array [count] of hierarchies built on the current device
+ *   opts      as for hsim_solve (opts->stream: the workers start after the
+ *             caller's stream reaches this call)
+ *   d_evals, d_evecs, d_resid  host arrays [count] of device pointers as for
+ *             hsim_solve (d_resid may be NULL, or hold NULL entries)
+ *   stats     host [count] or NULL; status: host [count] per-mesh status or NULL
+ * Returns HSIM_OK when every mesh converged, else the status of the first
+ * failing mesh (hsim_last_error names it); all outputs of the other meshes
+ * are complete either way.  The call returns when every worker has finished.
+ * Two calls that share a hierarchy must not overlap.
+ */
+hsim_status hsim_solve_batch(hsim_hierarchy* const* hs, int32_t count, const hsim_solve_opts* opts,
+                             double* const* d_evals, double* const* d_evecs, double* const* d_resid,
+                             hsim_stats* stats, int32_t* status, int32_t streams);
+
+/*
+ * hsim_autotune -- choose the launch plan of the block triangular solves of
+ * one level (the widest-supernode thresholds, in padded pivots, from which a
+ * tree level's forward and backward sweeps use the multi-workgroup block
+ * solve instead of the wave-level matrix-core solve) by timing a q-column
+ * block solve of each candidate (forward 128/256/512 x backward 64/128/256)
+ * on a factor of S - mu M with mu below the spectrum, and keep the fastest
+ * for the following solves of this hierarchy.  With the environment variable
+ * HSIM_TUNE_CACHE naming a file, the choice is looked up there first (keyed
+ * by subspace size, tree height, widest front and level size class) and
+ * appended after tuning.  Overwrites the level's factor (the next hsim_solve
+ * factors again).  out (host, may be NULL) receives the choice.
+ */
+typedef struct {
+    int32_t big_ns, big_ns_bwd;   /* chosen thresholds                                   */
+    double ms;                    /* measured time of one q-column block solve           */
+    int32_t from_cache;           /* 1: taken from HSIM_TUNE_CACHE without timing        */
+} hsim_tune_result;
+hsim_status hsim_autotune(hsim_hierarchy* h, int32_t level, void* stream, hsim_tune_result* out);
+
+/*
+ * hsim_solve_backward -- vector-Jacobian product/*
+ * hsim_solve_backward -- vector-Jacobian product/*
  * hsim_solve_backward -- vector-Jacobian product of the last hsim_solve
  * (run with HSIM_FLAG_SAVE_FORWARD) with respect to the vertex positions.
  * Eigenvalue part: d lambda_k = x_k^T (dS - lambda_k dM) x_k.  Eigenvector

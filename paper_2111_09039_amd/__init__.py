@@ -15,11 +15,12 @@ import numpy as np
 from . import _lib
 from ._lib import HsimError
 
-__all__ = ["Hierarchy", "HsimError", "FP64", "MIXED", "build_library"]
+__all__ = ["Hierarchy", "HsimError", "FP64", "MIXED", "GRAM_COMPENSATED", "build_library", "solve_batch",
+           "rayleigh_ritz_dense"]
 
 FP64, MIXED, GRAM_COMPENSATED = 0, 1, 2
 FLAG_NOLOCK, FLAG_SAVE_FORWARD, FLAG_PROFILE, FLAG_DETERMINISTIC = 1, 2, 4, 8
-FLAG_COMPENSATED_GRAM, FLAG_NO_FP32_GRAM, FLAG_FP32_GRAM = 16, 32, 64
+FLAG_COMPENSATED_GRAM, FLAG_NO_FP32_GRAM, FLAG_FP32_GRAM, FLAG_GRAPH = 16, 32, 64, 128
 
 
 def build_library(verbose=False):
@@ -100,7 +101,7 @@ class Hierarchy:
 
     # ----------------------------------------------------------- solve
     def solve(self, tol=1e-2, shift_alpha=0.1, precision=FP64, max_iters=100, lock=True, save_forward=False,
-              stream=None, raise_noconv=True, profile=False, compensated_gram=False, fp32_gram=None):
+              stream=None, raise_noconv=True, profile=False, compensated_gram=False, fp32_gram=None, graph=False):
         """Returns (evals [p], evecs [nv, p], resid [p], stats dict) with CUDA
         float64 tensors; evecs is the transpose view of a (p, nv) buffer.
         fp32_gram (mixed precision): None = the library's rule (FP32 interim
@@ -113,7 +114,8 @@ class Hierarchy:
         o.tol, o.shift_alpha, o.precision, o.max_iters = float(tol), float(shift_alpha), int(precision), int(max_iters)
         o.flags = ((0 if lock else FLAG_NOLOCK) | (FLAG_SAVE_FORWARD if save_forward else 0)
                    | (FLAG_PROFILE if profile else 0) | (FLAG_COMPENSATED_GRAM if compensated_gram else 0)
-                   | {None: 0, True: FLAG_FP32_GRAM, False: FLAG_NO_FP32_GRAM}[fp32_gram])
+                   | {None: 0, True: FLAG_FP32_GRAM, False: FLAG_NO_FP32_GRAM}[fp32_gram]
+                   | (FLAG_GRAPH if graph else 0))
         o.stream = _stream_ptr(stream)
         dev = torch.device("cuda", torch.cuda.current_device())
         ev = torch.empty(self.p, dtype=torch.float64, device=dev)
@@ -138,6 +140,13 @@ class Hierarchy:
         gx = None if grad_evecs is None else grad_evecs.detach().to(dev, torch.float64).t().contiguous()
         _lib.check(lib.hsim_solve_backward(self.handle, _dptr(ge), _dptr(gx), _dptr(gV), _stream_ptr(stream)))
         return gV
+
+    def autotune(self, level=0, stream=None):
+        """hsim_autotune: pick and keep the fastest block-solve launch plan of a
+        level; returns dict(big_ns, big_ns_bwd, ms, from_cache)."""
+        r = _lib.TuneResult()
+        _lib.check(_lib.load().hsim_autotune(self.handle, int(level), _stream_ptr(stream), C.byref(r)))
+        return {k: getattr(r, k) for k, _ in _lib.TuneResult._fields_}
 
     # ---------------------------------------------------------- inspection
     def level_info(self, level):
@@ -216,6 +225,35 @@ class Hierarchy:
         sw = C.c_int32()
         _lib.check(_lib.load().hsim_step_coarse(self.handle, int(k), _dptr(lam), _dptr(X), C.byref(sw), _stream_ptr()))
         return lam, X, sw.value
+
+
+def solve_batch(hierarchies, tol=1e-2, shift_alpha=0.1, precision=FP64, max_iters=100, lock=True, streams=0,
+                graph=False, stream=None):
+    """hsim_solve_batch: solve many hierarchies at once over `streams` worker
+    streams.  Returns a list of (evals [p], evecs [nv, p], resid [p], stats)
+    per hierarchy and the list of per-mesh status names."""
+    torch = _torch()
+    lib = _lib.load()
+    o = _lib.SolveOpts()
+    lib.hsim_default_solve_opts(C.byref(o))
+    o.tol, o.shift_alpha, o.precision, o.max_iters = float(tol), float(shift_alpha), int(precision), int(max_iters)
+    o.flags = (0 if lock else FLAG_NOLOCK) | (FLAG_GRAPH if graph else 0)
+    o.stream = _stream_ptr(stream)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    n = len(hierarchies)
+    evs = [torch.empty(H.p, dtype=torch.float64, device=dev) for H in hierarchies]
+    Xs = [torch.empty(H.p, H.nv, dtype=torch.float64, device=dev) for H in hierarchies]
+    rs = [torch.empty(H.p, dtype=torch.float64, device=dev) for H in hierarchies]
+    P = C.c_void_p * n
+    hs = P(*[H.handle for H in hierarchies])
+    pe, px, pr = P(*[t.data_ptr() for t in evs]), P(*[t.data_ptr() for t in Xs]), P(*[t.data_ptr() for t in rs])
+    stats = (_lib.Stats * n)()
+    status = (C.c_int32 * n)()
+    code = lib.hsim_solve_batch(hs, n, C.byref(o), pe, px, pr, stats, status, int(streams))
+    if code not in (0, -4):
+        _lib.check(code)
+    out = [(evs[i], Xs[i].t(), rs[i], stats[i].as_dict()) for i in range(n)]
+    return out, [_lib.STATUS.get(c, c) for c in status]
 
 
 def rayleigh_ritz_dense(Sbar, Mbar):

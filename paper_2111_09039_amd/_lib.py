@@ -48,6 +48,10 @@ class Stats(C.Structure):
                                         flops=self.k_flops[i]) for i, name in enumerate(KCLASSES)})
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("big_ns", C.c_int32), ("big_ns_bwd", C.c_int32), ("ms", C.c_double), ("from_cache", C.c_int32)]
+
+
 class LevelDesc(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("nnz_u", C.c_int64), ("fronts", C.c_int64),
                 ("tree_levels", C.c_int64), ("factor_entries", C.c_int64), ("rho", C.c_double),
@@ -78,6 +82,8 @@ SIGNATURES = {
     "hsim_step_gram": (C.c_int, [_P, _I32, _I32, _P, _P, _P, _I32, _P]),
     "hsim_step_rr": (C.c_int, [_I32, _P, _P, _P, _P, C.POINTER(_I32), _P]),
     "hsim_step_rr_noalloc": (C.c_int, [_I32, _P, _P, _P, _P, C.POINTER(_I32), _P]),
+    "hsim_autotune": (C.c_int, [_P, _I32, _P, C.POINTER(TuneResult)]),
+    "hsim_solve_batch": (C.c_int, [_P, _I32, C.POINTER(SolveOpts), _P, _P, _P, C.POINTER(Stats), _P, _I32]),
     "hsim_step_ritz": (C.c_int, [_P, _I32, _I32, _P, _P, _P, _D, _P, _P, _P]),
     "hsim_step_coarse": (C.c_int, [_P, _I32, _P, _P, C.POINTER(_I32), _P]),
 }

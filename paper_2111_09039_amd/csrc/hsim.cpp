@@ -7,6 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
+#include <thread>
+#include <array>
+#include <map>
 #include <mutex>
 #include <numeric>
 
@@ -452,6 +456,7 @@ struct Level {
     DeviceBuffer asm_dst, asm_src, it_diag, it_panel, it_upd, it_ea, rel, rows, gat;
     int32_t gw = 0;   // width of the padded gather table
     DeviceBuffer ubuf, big_items;
+    int32_t big_ns = 0, big_ns_bwd = 0;   // thresholds of the current block-solve plan
     double mu = 0;
     bool factored = false, factored32 = false;
     int32_t neg_pivots = 0;
@@ -481,11 +486,97 @@ struct hsim_hierarchy {
     int32_t gram_steps[3] = {0, 0, 0};   // Rayleigh-Ritz Gram products per form in the last solve
     std::vector<double> last_lam;
     hsim::Prof prof;
+    // HSIM_FLAG_GRAPH: instantiated graphs of the block solves of one subspace
+    // iteration, keyed by level, locked columns and the buffers they read and write
+    std::map<std::array<intptr_t, 5>, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;   // capture stream of those graphs
+    ~hsim_hierarchy() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace hsim {
 
 // ----------------------------------------------------------- build helpers
+// Launch plan of the block solves on one level: per tree level the fronts,
+// the tile and pivot counts, and whether the forward / backward sweep of the
+// level uses the multi-workgroup block solve (widest front at least big_ns /
+// big_ns_bwd padded pivots, or wider than the wave-level solve holds) with its
+// item lists.  Re-planned by the autotuner.
+static void plan_solve(Level& L, int32_t big_ns, int32_t big_ns_bwd) {
+    const Symbolic& sy = L.sy;
+    const int32_t mc = std::max<int32_t>(1, sy.max_children);
+    L.tl.assign(sy.tree_levels, TLev());
+    L.big_ns = big_ns;
+    L.big_ns_bwd = big_ns_bwd;
+    std::vector<int32_t> big;
+    for (int32_t t = 0; t < sy.tree_levels; ++t) {
+        TLev& T = L.tl[t];
+        T.f0 = sy.tlev_ptr[t];
+        T.f1 = sy.tlev_ptr[t + 1];
+        for (int32_t i = T.f0; i < T.f1; ++i) {
+            const Front& f = sy.fronts[i];
+            T.ns_pad_max = std::max(T.ns_pad_max, f.ns_pad);
+            T.l_entries += (double)f.ns * (f.ns + 1) / 2 + (double)f.ns * f.mu;
+            T.pivots += f.ns;
+        }
+        const bool wide = T.ns_pad_max > wsolve_max_ns();
+        T.big_fwd = wide || T.ns_pad_max >= big_ns;
+        T.big_bwd = wide || T.ns_pad_max >= big_ns_bwd;
+        T.big = T.big_fwd || T.big_bwd;
+        if (T.big) {
+            // item lists of the multi-workgroup block solve
+            auto push = [&](int32_t a, int32_t b) { big.push_back(a); big.push_back(b); };
+            int32_t maxnsb = 0;
+            for (int32_t i = T.f0; i < T.f1; ++i) maxnsb = std::max(maxnsb, sy.fronts[i].nsb);
+            T.nblk = (maxnsb + BIG_BLOCK_TILES - 1) / BIG_BLOCK_TILES;
+            T.fwd_init[0] = (int64_t)big.size();
+            for (int32_t i = T.f0; i < T.f1; ++i) {
+                const Front& f = sy.fronts[i];
+                const int32_t st = (f.mu + NB - 1) / NB;
+                for (int32_t r = 0; r < f.nsb + st; ++r) push(i, r);
+            }
+            T.fwd_init[1] = ((int64_t)big.size() - T.fwd_init[0]) / 2;
+            T.bwd_init[0] = (int64_t)big.size();
+            for (int32_t i = T.f0; i < T.f1; ++i)
+                for (int32_t r = 0; r < sy.fronts[i].nsb; ++r) push(i, r);
+            T.bwd_init[1] = ((int64_t)big.size() - T.bwd_init[0]) / 2;
+            for (int32_t kb = 0; kb < T.nblk; ++kb) {
+                int64_t o = (int64_t)big.size();
+                for (int32_t i = T.f0; i < T.f1; ++i)
+                    if (sy.fronts[i].nsb > kb * BIG_BLOCK_TILES) big.push_back(i);
+                const int64_t cnt = (int64_t)big.size() - o;
+                T.fdiag.push_back(o); T.fdiag.push_back(cnt);
+                T.bdiag.push_back(o); T.bdiag.push_back(cnt);
+                o = (int64_t)big.size();
+                for (int32_t i = T.f0; i < T.f1; ++i) {
+                    const Front& f = sy.fronts[i];
+                    if (f.nsb <= kb * BIG_BLOCK_TILES) continue;
+                    const int32_t t1 = std::min(f.nsb, (kb + 1) * BIG_BLOCK_TILES);
+                    const int32_t st = (f.mu + NB - 1) / NB;
+                    for (int32_t r = t1; r < f.nsb + st; ++r) push(i, r);
+                }
+                T.fupd.push_back(o); T.fupd.push_back(((int64_t)big.size() - o) / 2);
+                o = (int64_t)big.size();
+                for (int32_t i = T.f0; i < T.f1; ++i) {
+                    const Front& f = sy.fronts[i];
+                    if (f.nsb <= kb * BIG_BLOCK_TILES) continue;
+                    for (int32_t r = 0; r < kb * BIG_BLOCK_TILES; ++r) push(i, r);
+                }
+                T.bupd.push_back(o); T.bupd.push_back(((int64_t)big.size() - o) / 2);
+            }
+        }
+        T.step0 = sy.step_ptr[t];
+        T.step1 = sy.step_ptr[t + 1];
+        T.ea_tile_cols.assign(mc, 0);
+        for (int32_t c = 0; c < mc; ++c)
+            for (int64_t e = sy.ea_ptr[(int64_t)t * mc + c]; e < sy.ea_ptr[(int64_t)t * mc + c + 1]; ++e)
+                T.ea_tile_cols[c] = std::max<int32_t>(T.ea_tile_cols[c], (sy.fronts[sy.ea[e]].mu + NB - 1) / NB);
+    }
+    L.big_items.upload(big.empty() ? std::vector<int32_t>{0, 0} : big);
+}
+
 static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<int32_t>* coarse_iperm) {
     const int64_t n = L.n;
     std::vector<int32_t> perm, iperm;
@@ -609,74 +700,7 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
         L.gat.upload(gat);
     }
     L.ubuf.alloc((size_t)std::max<int64_t>(1, sy.ubuf_rows) * H->ld * sizeof(double));
-    // per tree level launch data
-    const int32_t mc = std::max<int32_t>(1, sy.max_children);
-    L.tl.resize(sy.tree_levels);
-    std::vector<int32_t> big;
-    for (int32_t t = 0; t < sy.tree_levels; ++t) {
-        TLev& T = L.tl[t];
-        T.f0 = sy.tlev_ptr[t];
-        T.f1 = sy.tlev_ptr[t + 1];
-        for (int32_t i = T.f0; i < T.f1; ++i) {
-            const Front& f = sy.fronts[i];
-            T.ns_pad_max = std::max(T.ns_pad_max, f.ns_pad);
-            T.l_entries += (double)f.ns * (f.ns + 1) / 2 + (double)f.ns * f.mu;
-            T.pivots += f.ns;
-        }
-        const bool wide = T.ns_pad_max > wsolve_max_ns();
-        T.big_fwd = wide || T.ns_pad_max >= env_int("HSIM_BIG_NS", BIG_NS);
-        T.big_bwd = wide || T.ns_pad_max >= env_int("HSIM_BIG_NS_BWD", BIG_NS_BWD);
-        T.big = T.big_fwd || T.big_bwd;
-        if (T.big) {
-            // item lists of the multi-workgroup block solve
-            auto push = [&](int32_t a, int32_t b) { big.push_back(a); big.push_back(b); };
-            int32_t maxnsb = 0;
-            for (int32_t i = T.f0; i < T.f1; ++i) maxnsb = std::max(maxnsb, sy.fronts[i].nsb);
-            T.nblk = (maxnsb + BIG_BLOCK_TILES - 1) / BIG_BLOCK_TILES;
-            T.fwd_init[0] = (int64_t)big.size();
-            for (int32_t i = T.f0; i < T.f1; ++i) {
-                const Front& f = sy.fronts[i];
-                const int32_t st = (f.mu + NB - 1) / NB;
-                for (int32_t r = 0; r < f.nsb + st; ++r) push(i, r);
-            }
-            T.fwd_init[1] = ((int64_t)big.size() - T.fwd_init[0]) / 2;
-            T.bwd_init[0] = (int64_t)big.size();
-            for (int32_t i = T.f0; i < T.f1; ++i)
-                for (int32_t r = 0; r < sy.fronts[i].nsb; ++r) push(i, r);
-            T.bwd_init[1] = ((int64_t)big.size() - T.bwd_init[0]) / 2;
-            for (int32_t kb = 0; kb < T.nblk; ++kb) {
-                int64_t o = (int64_t)big.size();
-                for (int32_t i = T.f0; i < T.f1; ++i)
-                    if (sy.fronts[i].nsb > kb * BIG_BLOCK_TILES) big.push_back(i);
-                const int64_t cnt = (int64_t)big.size() - o;
-                T.fdiag.push_back(o); T.fdiag.push_back(cnt);
-                T.bdiag.push_back(o); T.bdiag.push_back(cnt);
-                o = (int64_t)big.size();
-                for (int32_t i = T.f0; i < T.f1; ++i) {
-                    const Front& f = sy.fronts[i];
-                    if (f.nsb <= kb * BIG_BLOCK_TILES) continue;
-                    const int32_t t1 = std::min(f.nsb, (kb + 1) * BIG_BLOCK_TILES);
-                    const int32_t st = (f.mu + NB - 1) / NB;
-                    for (int32_t r = t1; r < f.nsb + st; ++r) push(i, r);
-                }
-                T.fupd.push_back(o); T.fupd.push_back(((int64_t)big.size() - o) / 2);
-                o = (int64_t)big.size();
-                for (int32_t i = T.f0; i < T.f1; ++i) {
-                    const Front& f = sy.fronts[i];
-                    if (f.nsb <= kb * BIG_BLOCK_TILES) continue;
-                    for (int32_t r = 0; r < kb * BIG_BLOCK_TILES; ++r) push(i, r);
-                }
-                T.bupd.push_back(o); T.bupd.push_back(((int64_t)big.size() - o) / 2);
-            }
-        }
-        T.step0 = sy.step_ptr[t];
-        T.step1 = sy.step_ptr[t + 1];
-        T.ea_tile_cols.assign(mc, 0);
-        for (int32_t c = 0; c < mc; ++c)
-            for (int64_t e = sy.ea_ptr[(int64_t)t * mc + c]; e < sy.ea_ptr[(int64_t)t * mc + c + 1]; ++e)
-                T.ea_tile_cols[c] = std::max<int32_t>(T.ea_tile_cols[c], (sy.fronts[sy.ea[e]].mu + NB - 1) / NB);
-    }
-    L.big_items.upload(big.empty() ? std::vector<int32_t>{0, 0} : big);
+    plan_solve(L, env_int("HSIM_BIG_NS", BIG_NS), env_int("HSIM_BIG_NS_BWD", BIG_NS_BWD));
 }
 
 // ----------------------------------------------------------- factor / solve
@@ -1454,9 +1478,11 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
     if (so.max_iters < 1) fail(HSIM_E_INVALID, "max_iters must be >= 1");
     if (so.precision != HSIM_FP64 && so.precision != HSIM_MIXED) fail(HSIM_E_INVALID, "unknown precision");
     if (so.flags & ~(HSIM_FLAG_NOLOCK | HSIM_FLAG_SAVE_FORWARD | HSIM_FLAG_PROFILE | HSIM_FLAG_DETERMINISTIC |
-                     HSIM_FLAG_COMPENSATED_GRAM | HSIM_FLAG_NO_FP32_GRAM | HSIM_FLAG_FP32_GRAM))
+                     HSIM_FLAG_COMPENSATED_GRAM | HSIM_FLAG_NO_FP32_GRAM | HSIM_FLAG_FP32_GRAM | HSIM_FLAG_GRAPH))
         fail(HSIM_E_INVALID, "unknown solve flags 0x%x", (unsigned)so.flags);
     const bool mixed = so.precision == HSIM_MIXED;
+    // replayed graphs of the FP64 iteration body (not while every launch is timed)
+    const bool use_graph = (so.flags & HSIM_FLAG_GRAPH) && !(so.flags & HSIM_FLAG_PROFILE);
     // Gram forms of a mixed solve: FP32 far from convergence (unless switched
     // off), then FP64 or, when asked for, compensated FP32
     // (by default only above q = 160, where the FP64 Gram is the multi-pass kernel too: below,
@@ -1528,15 +1554,64 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
             const int32_t act = q - locked;
             // the active columns go from Phi into Psi with the two solves of the
             // iteration; the locked ones (not iterated) are copied from Phi after
-            if (act > 0) {
-                if (!mixed && tau == 0) {
-                    // Phi -> Psi -> Btmp, out of place (lets the forward sweep split
-                    // narrow tree levels), then Btmp becomes Psi
-                    solve_level(h, L, dptr<double>(h->Psi), locked, act, true, s, false, dptr<double>(h->Phi));
-                    solve_level(h, L, dptr<double>(h->Btmp), locked, act, true, s, false, dptr<double>(h->Psi));
-                    swap_buffers(h->Psi, h->Btmp);
+            if (act > 0 && !mixed) {
+                // FP64: the two inverse iterations of the step (kernels only, no host
+                // synchronisation), as one replayed graph with HSIM_FLAG_GRAPH
+                auto body = [&](hipStream_t ss) {
+                    if (tau == 0) {
+                        // Phi -> Psi -> Btmp, out of place (lets the forward sweep split
+                        // narrow tree levels); Btmp becomes Psi after the step
+                        solve_level(h, L, dptr<double>(h->Psi), locked, act, true, ss, false, dptr<double>(h->Phi));
+                        solve_level(h, L, dptr<double>(h->Btmp), locked, act, true, ss, false, dptr<double>(h->Psi));
+                    } else {
+                        for (int rep = 0; rep < 2; ++rep) {
+                            double* src = dptr<double>(rep == 0 ? h->Phi : h->Psi);
+                            h->prof.run(HSIM_K_SPMM, 12.0 * L.S.nnz() + 16.0 * L.n * act, 2.0 * L.S.nnz() * act, ss,
+                                        [&] {
+                                            pattern_spmm(L, false, false, 1.0, 0.0, src + locked, h->ld, act,
+                                                         dptr<double>(h->Btmp) + locked, h->ld, ss);
+                                        });
+                            solve_level(h, L, dptr<double>(h->Psi), locked, act, false, ss, false,
+                                        dptr<double>(h->Btmp));
+                        }
+                    }
+                };
+                if (use_graph) {
+                    const std::array<intptr_t, 5> key{tau, locked, (intptr_t)h->Phi.p, (intptr_t)h->Psi.p,
+                                                      (intptr_t)h->Btmp.p};
+                    auto g = h->graphs.find(key);
+                    if (g == h->graphs.end()) {
+                        hipGraph_t graph = nullptr;
+                        // captured on the hierarchy's own stream (the caller's may be the
+                        // null stream, which cannot capture), replayed on the caller's
+                        if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+                        HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+                        try {
+                            body(h->cap_stream);
+                        } catch (...) {
+                            hipGraph_t dead = nullptr;
+                            (void)hipStreamEndCapture(h->cap_stream, &dead);
+                            if (dead) (void)hipGraphDestroy(dead);
+                            throw;
+                        }
+                        HIPCHECK(hipStreamEndCapture(h->cap_stream, &graph));
+                        hipGraphExec_t exec = nullptr;
+                        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                        (void)hipGraphDestroy(graph);
+                        HIPCHECK(e);
+                        g = h->graphs.emplace(key, exec).first;
+                    } else {
+                        h->prof.solves += 2;   // counted by the host code of the capture otherwise
+                        h->prof.solve_cols += 2 * (int64_t)act;
+                    }
+                    HIPCHECK(hipGraphLaunch(g->second, s));
+                } else {
+                    body(s);
                 }
-                for (int rep = 0; rep < 2 && (mixed || tau > 0); ++rep) {
+                if (tau == 0) swap_buffers(h->Psi, h->Btmp);
+            }
+            if (act > 0 && mixed) {
+                for (int rep = 0; rep < 2; ++rep) {
                     double* src = dptr<double>(rep == 0 ? h->Phi : h->Psi);
                     // B = M src
                     if (tau == 0)
@@ -1547,13 +1622,9 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
                             pattern_spmm(L, false, false, 1.0, 0.0, src + locked, h->ld, act,
                                          dptr<double>(h->Btmp) + locked, h->ld, s);
                         });
-                    if (mixed) {
-                        const double eta = std::min(1e-3, 0.1 * (std::isfinite(rmax) ? rmax : 1e-2));
-                        st.refine_steps += refine_solve(h, L, dptr<double>(h->Btmp), dptr<double>(h->Psi), locked, act,
-                                                        eta, s, &st.escalated, &est32);
-                    } else {
-                        solve_level(h, L, dptr<double>(h->Psi), locked, act, false, s, false, dptr<double>(h->Btmp));
-                    }
+                    const double eta = std::min(1e-3, 0.1 * (std::isfinite(rmax) ? rmax : 1e-2));
+                    st.refine_steps += refine_solve(h, L, dptr<double>(h->Btmp), dptr<double>(h->Psi), locked, act,
+                                                    eta, s, &st.escalated, &est32);
                 }
             }
             if (locked > 0)
@@ -1623,6 +1694,177 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         set_last_error("subspace iterations did not converge within max_iters");
         return final_status;
     }
+    API_END
+}
+
+hsim_status hsim_solve_batch(hsim_hierarchy* const* hs, int32_t count, const hsim_solve_opts* opts,
+                             double* const* d_evals, double* const* d_evecs, double* const* d_resid,
+                             hsim_stats* stats, int32_t* status, int32_t streams) {
+    API_BEGIN
+    if (count < 0 || (count > 0 && (!hs || !d_evals || !d_evecs))) fail(HSIM_E_INVALID, "null argument");
+    if (count == 0) return HSIM_OK;
+    for (int32_t i = 0; i < count; ++i)
+        if (!hs[i] || !d_evals[i] || !d_evecs[i]) fail(HSIM_E_INVALID, "null argument for mesh %d", i);
+    hsim_solve_opts so;
+    if (opts) so = *opts;
+    else hsim_default_solve_opts(&so);
+    const int32_t nw = std::max(1, std::min(count, streams > 0 ? streams : 8));
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    // the workers' streams start after the caller's stream has reached this call
+    hipEvent_t start;
+    HIPCHECK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(start, S_(so.stream)));
+    // largest meshes first: the queue ends with the short solves
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return hs[a]->lv[0]->n > hs[b]->lv[0]->n; });
+    std::atomic<int32_t> next{0};
+    std::vector<int32_t> st(count, HSIM_OK);
+    std::vector<std::string> msg(count);
+    std::vector<std::string> werr(nw);
+    auto worker = [&](int w) {
+        hipStream_t ws = nullptr;
+        if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamWaitEvent(ws, start, 0) != hipSuccess) {
+            werr[w] = "worker stream set-up failed";
+            if (ws) (void)hipStreamDestroy(ws);
+            return;
+        }
+        hsim_solve_opts o = so;
+        o.stream = ws;
+        for (;;) {
+            const int32_t k = next.fetch_add(1);
+            if (k >= count) break;
+            const int32_t i = order[k];
+            st[i] = hsim_solve(hs[i], &o, d_evals[i], d_evecs[i], d_resid ? d_resid[i] : nullptr,
+                               stats ? &stats[i] : nullptr);
+            if (st[i] != HSIM_OK) msg[i] = hsim_last_error();
+        }
+        if (hipStreamSynchronize(ws) != hipSuccess) werr[w] = "worker stream failed";
+        (void)hipStreamDestroy(ws);
+    };
+    std::vector<std::thread> pool;
+    for (int w = 1; w < nw; ++w) pool.emplace_back(worker, w);
+    worker(0);
+    for (auto& t : pool) t.join();
+    (void)hipEventDestroy(start);
+    for (int w = 0; w < nw; ++w)
+        if (!werr[w].empty()) fail(HSIM_E_DEVICE, "%s", werr[w].c_str());
+    if (status)
+        for (int32_t i = 0; i < count; ++i) status[i] = st[i];
+    for (int32_t i = 0; i < count; ++i)
+        if (st[i] != HSIM_OK) {
+            set_last_error("mesh " + std::to_string(i) + ": " + msg[i]);
+            return (hsim_status)st[i];
+        }
+    API_END
+}
+
+// ------------------------------------------------------------- autotuning
+// Candidate launch plans of the block solves: the widest-front thresholds
+// (padded pivots) from which a tree level's forward / backward sweep uses the
+// multi-workgroup block solve instead of the wave-level one.
+static const int32_t kTuneFwd[] = {128, 256, 512};
+static const int32_t kTuneBwd[] = {64, 128, 256};
+static std::mutex g_tune_mu;
+
+static std::string tune_key(const hsim_hierarchy* h, const Level& L) {
+    int32_t top = 0;
+    for (const TLev& T : L.tl) top = std::max(top, T.ns_pad_max);
+    // meshes with the same subspace size, tree height, widest front and size
+    // class share a plan (size class: the level size to two significant binary digits)
+    int64_t n = L.n, sc = 0;
+    while (n >= 4) { n >>= 1; ++sc; }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "solve-plan q=%d tree=%d top=%d size=%lld.%lld", h->q, (int)L.tl.size(), top,
+                  (long long)sc, (long long)n);
+    return buf;
+}
+
+static bool tune_cache_lookup(const std::string& key, int32_t* f, int32_t* b, double* ms) {
+    const char* path = std::getenv("HSIM_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, fp)) {
+        const char* bar = std::strchr(line, '|');
+        if (!bar || std::string(line, bar - line) != key) continue;
+        int32_t ff, bb;
+        double mm;
+        if (std::sscanf(bar + 1, "%d %d %lf", &ff, &bb, &mm) == 3) {
+            *f = ff, *b = bb, *ms = mm;
+            found = true;   // the last entry of a key wins
+        }
+    }
+    std::fclose(fp);
+    return found;
+}
+
+static void tune_cache_store(const std::string& key, int32_t f, int32_t b, double ms) {
+    const char* path = std::getenv("HSIM_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    FILE* fp = std::fopen(path, "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s|%d %d %.6f\n", key.c_str(), f, b, ms);
+    std::fclose(fp);
+}
+
+hsim_status hsim_autotune(hsim_hierarchy* h, int32_t level, void* stream, hsim_tune_result* out) {
+    API_BEGIN
+    Level& L = level_at(h, level);
+    if (L.coarsest) fail(HSIM_E_INVALID, "the coarsest level is solved densely");
+    hipStream_t s = S_(stream);
+    const std::string key = tune_key(h, L);
+    hsim_tune_result r{};
+    int32_t f = 0, b = 0;
+    double ms = 0;
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);   // they hold the old plan's launches
+    h->graphs.clear();
+    if (tune_cache_lookup(key, &f, &b, &ms)) {
+        plan_solve(L, f, b);
+        r.big_ns = f, r.big_ns_bwd = b, r.ms = ms, r.from_cache = 1;
+    } else {
+        // time the q-column block solve of every plan on a factor of S - mu M
+        // with mu below the spectrum (the times do not depend on the values)
+        const double mu = -1e-3;
+        factor_level(h, L, mu, s, false);
+        double* X = dptr<double>(h->Psi);
+        double* B = dptr<double>(h->Btmp);
+        HIPCHECK(launch_fill(B, L.n * h->ld, 1.0, s));
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        double best = INFINITY;
+        int32_t bf = L.big_ns, bb = L.big_ns_bwd;
+        for (int32_t cf : kTuneFwd)
+            for (int32_t cb : kTuneBwd) {
+                plan_solve(L, cf, cb);
+                solve_level(h, L, X, 0, h->q, false, s, false, B);   // warm-up
+                double t = INFINITY;
+                for (int rep = 0; rep < 3; ++rep) {
+                    HIPCHECK(hipEventRecord(e0, s));
+                    solve_level(h, L, X, 0, h->q, false, s, false, B);
+                    HIPCHECK(hipEventRecord(e1, s));
+                    HIPCHECK(hipEventSynchronize(e1));
+                    float m = 0;
+                    HIPCHECK(hipEventElapsedTime(&m, e0, e1));
+                    t = std::min(t, (double)m);
+                }
+                if (t < best) best = t, bf = cf, bb = cb;
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        plan_solve(L, bf, bb);
+        tune_cache_store(key, bf, bb, best);
+        r.big_ns = bf, r.big_ns_bwd = bb, r.ms = best, r.from_cache = 0;
+    }
+    if (out) *out = r;
     API_END
 }
 

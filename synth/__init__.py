@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "icosahedron", "icosphere", "geodesic_icosphere", "torus", "rectangle_grid",
-    "radial_jitter", "isotropic_noise", "gaussian_bumps", "random_density", "gaussian_matrix",
+    "radial_jitter", "isotropic_noise", "gaussian_bumps", "random_density", "gaussian_matrix", "batch_mesh",
     "mean_edge_length", "config_mesh", "CONFIGS",
 ]
 
@@ -241,6 +241,27 @@ def gaussian_matrix(n, r, seed):
     """Seeded n x r matrix of independent N(0, 1) entries (row-major), used as
     the random test matrix of eigenvector sketches and as random directions."""
     return np.random.default_rng(seed).standard_normal((n, r))
+
+
+def batch_mesh(i, seed=0, count=256, lo=2000, hi=50000):
+    """Mesh i of a batch of ``count`` seeded meshes (noisy geodesic spheres for
+    even i, noisy tori for odd i) whose vertex counts are log-uniform in
+    [lo, hi].  Each mesh has its own generator (seed, i), so any subset of the
+    batch can be made on its own."""
+    if not 0 <= i < count:
+        raise IndexError(i)
+    rng = np.random.default_rng([seed, i])
+    n = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+    if i % 2 == 0:
+        nu = max(4, int(round(np.sqrt((n - 2) / 10))))
+        V, F = geodesic_icosphere(nu)
+        V = radial_jitter(V, 0.05 / nu, rng)
+    else:
+        a = max(8, int(round(np.sqrt(1.6 * n))))
+        b = max(6, int(round(n / a)))
+        V, F = torus(a, b)
+        V = isotropic_noise(V, F, 0.2 * mean_edge_length(V, F), rng)
+    return V, F
 
 
 # ---------------------------------------------------------------------------

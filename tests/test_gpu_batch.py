@@ -1,0 +1,98 @@
+"""Batched solves of meshes of uneven size (hsim_solve_batch), replayed
+graphs of the iteration bodies (HSIM_FLAG_GRAPH) and the block-solve
+autotuner (hsim_autotune with HSIM_TUNE_CACHE), through the C ABI.
+
+* 24 meshes of the seeded batch workload (noisy spheres and tori, the
+  smallest of the 256 so that the oracle stays quick), p = 50: the batched
+  result equals the per-mesh sequential result bit for bit, and every mesh's
+  eigenvalues match the oracle's (dense FP64 eigenproblem of the mesh) to
+  1e-9 (FP64) / 1e-6 (FP32 solves with refinement), residuals below tol;
+* graphs: three solves with graphs, with ordinary eager solves and host
+  synchronisations between them, each bitwise equal to the eager result;
+* autotuner: the chosen plan is written to the cache and read back without
+  timing; the re-planned solve gives the same eigenvalues.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+import synth
+from oracle import assembly
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def batch(cuda):
+    import paper_2111_09039_amd as hs
+    sizes = [(len(synth.batch_mesh(i)[0]), i) for i in range(256)]
+    pick = [i for _, i in sorted(sizes)[:24]]
+    meshes = [synth.batch_mesh(i) for i in pick]
+    Hs = [hs.Hierarchy(V, F, 50, levels=2) for V, F in meshes]
+    print(f"[batch] meshes {pick}, sizes {[len(V) for V, _ in meshes]}", flush=True)
+    return meshes, Hs
+
+
+def _dense(V, F, p):
+    S, m = assembly.assemble(V, F)
+    return sl.eigh(S.toarray(), np.diag(m), eigvals_only=True, subset_by_index=[0, p - 1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_sequential_and_oracle(batch, precision):
+    import paper_2111_09039_amd as hs
+    meshes, Hs = batch
+    seq = [H.solve(tol=TOL, precision=precision) for H in Hs]
+    out, status = hs.solve_batch(Hs, tol=TOL, precision=precision, streams=6)
+    assert all(s == "HSIM_OK" for s in status)
+    bar = 1e-9 if precision == 0 else 1e-6
+    worst = 0.0
+    for (V, F), (ev0, X0, r0, _), (ev, X, r, st) in zip(meshes, seq, out):
+        assert np.array_equal(ev.cpu().numpy(), ev0.cpu().numpy())
+        assert np.array_equal(X.cpu().numpy(), X0.cpu().numpy())
+        assert r.cpu().numpy().max() < TOL
+        ref = _dense(V, F, 50)
+        e = np.abs(ev.cpu().numpy() - ref)[1:] / ref[1:]
+        worst = max(worst, e.max())
+        assert e.max() <= bar, e.max()
+    print(f"[batch precision={precision}] worst eigenvalue error against the oracle {worst:.2e}", flush=True)
+
+
+def test_graph_replays_match_eager(batch):
+    import torch
+    meshes, Hs = batch
+    H = Hs[-1]
+    ev0, X0, r0, _ = H.solve(tol=TOL)
+    ref = (ev0.cpu().numpy(), X0.cpu().numpy())
+    for rep in range(3):
+        ev, X, r, st = H.solve(tol=TOL, graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(ev.cpu().numpy(), ref[0]) and np.array_equal(X.cpu().numpy(), ref[1]), rep
+        # ordinary eager work and a synchronisation between the replays
+        e2, _, _, _ = H.solve(tol=TOL)
+        torch.cuda.synchronize()
+        assert np.array_equal(e2.cpu().numpy(), ref[0])
+    # batched with graphs as well
+    import paper_2111_09039_amd as hs
+    out, status = hs.solve_batch(Hs[-4:], tol=TOL, graph=True, streams=2)
+    for H2, (ev, X, r, st) in zip(Hs[-4:], out):
+        e1 = H2.solve(tol=TOL)[0].cpu().numpy()
+        assert np.array_equal(ev.cpu().numpy(), e1)
+
+
+def test_autotune_and_cache(batch, tmp_path, monkeypatch):
+    meshes, Hs = batch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HSIM_TUNE_CACHE", str(cache))
+    H = Hs[-2]
+    before = H.solve(tol=TOL)[0].cpu().numpy()
+    r1 = H.autotune(0)
+    assert r1["from_cache"] == 0 and r1["ms"] > 0
+    assert r1["big_ns"] in (128, 256, 512) and r1["big_ns_bwd"] in (64, 128, 256)
+    assert cache.exists() and "solve-plan" in cache.read_text()
+    r2 = H.autotune(0)
+    assert r2["from_cache"] == 1 and (r2["big_ns"], r2["big_ns_bwd"]) == (r1["big_ns"], r1["big_ns_bwd"])
+    after = H.solve(tol=TOL)[0].cpu().numpy()
+    assert np.abs(after - before)[1:].max() <= 1e-12 * before[-1]
