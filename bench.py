@@ -290,6 +290,11 @@ def main():
     t_build = time.perf_counter() - t
     log(f"hierarchy built in {t_build:.1f} s: levels {H.levels}, q {H.q}")
     info0 = H.level_info(0)
+    # launch plan of the block solves chosen by the library's autotuner (part of the set-up)
+    t = time.perf_counter()
+    tune = [H.autotune(lv) for lv in range(H.levels - 1)]
+    t_tune = time.perf_counter() - t
+    log(f"autotuned in {t_tune:.2f} s: {[(r['big_ns'], r['big_ns_bwd']) for r in tune]}")
 
     if args.profile_only:
         copy_calibration()
@@ -402,7 +407,8 @@ def main():
         "config": {"workload": f"{desc}, {len(V)} vertices, p={args.p}, q={H.q}, T={H.levels}, eps={args.tol}",
                    "headline_precision": "mixed" if dtype == "f32+f64" else "fp64",
                    "fp64_s": round(dt64, 5), "mixed_s": results.get("mixed", {}).get("s"),
-                   "hierarchy_build_s": round(t_build, 3), "factor_nnz": info0["factor_nnz"],
+                   "hierarchy_build_s": round(t_build, 3), "autotune_s": round(t_tune, 3),
+                   "solve_plans": [(r["big_ns"], r["big_ns_bwd"]) for r in tune], "factor_nnz": info0["factor_nnz"],
                    "fp64_iters": st64["iters"], "fp64_max_resid": results["fp64"]["max_resid"],
                    "mixed": {k: v for k, v in results.get("mixed", {}).items() if k != "stats"},
                    "mixed_forms": {k: results[k] for k in ("mixed_fp32_gram", "mixed_compensated_gram")

@@ -1103,6 +1103,41 @@ const char* hsim_last_error(void) { return g_last_error.c_str(); }
 
 void hsim_free(hsim_hierarchy* h) { delete h; }
 
+// Finest-level S (values on the pattern of the edge graph plus the diagonal)
+// and barycentric lumped M assembled on the current device.
+static void device_assembly(const Mesh& m, const Graph& g, const double* density, Csr& S, std::vector<double>& md) {
+    AssemblyMaps a = assembly_maps(m, g);
+    const int64_t n = m.nv, nf = m.nf, nnz = a.S.nnz();
+    DeviceBuffer dV, dF, bptr, bidx, bcorner, bdptr, bdcorner, dvptr, dvtri, ddens, dw, da3, dval, dm;
+    dV.upload(m.V);
+    dF.upload(m.F);
+    bptr.upload(a.S.ptr);
+    bidx.upload(a.S.idx);
+    bcorner.upload(a.corner);
+    bdptr.upload(a.dptr);
+    bdcorner.upload(a.dcorner);
+    dvptr.upload(a.vptr);
+    dvtri.upload(a.vtri);
+    if (density) {
+        ddens.alloc((size_t)n * sizeof(double));
+        ddens.copy_in(density, (size_t)n * sizeof(double));
+    }
+    dw.alloc((size_t)3 * nf * sizeof(double));
+    da3.alloc((size_t)nf * sizeof(double));
+    dval.alloc((size_t)nnz * sizeof(double));
+    dm.alloc((size_t)n * sizeof(double));
+    HIPCHECK(launch_assemble_mesh(dptr<double>(dV), dptr<int32_t>(dF), nf, n, dptr<int64_t>(bptr),
+                                  dptr<int32_t>(bidx), dptr<int64_t>(bcorner), dptr<int64_t>(bdptr),
+                                  dptr<int64_t>(bdcorner), dptr<int64_t>(dvptr), dptr<int32_t>(dvtri),
+                                  density ? dptr<double>(ddens) : nullptr, dptr<double>(dw), dptr<double>(da3),
+                                  dptr<double>(dval), dptr<double>(dm), nullptr));
+    S = std::move(a.S);
+    S.val.resize(nnz);
+    md.resize(n);
+    HIPCHECK(hipMemcpy(S.val.data(), dval.p, (size_t)nnz * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(md.data(), dm.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost));
+}
+
 hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, int64_t nf, const double* density,
                                  const hsim_build_opts* opts, hsim_hierarchy** out) {
     API_BEGIN
@@ -1174,8 +1209,16 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
     }
     {
         Level& L0 = *H->lv[0];
-        L0.S = cotan_stiffness(m);
-        L0.mdiag = lumped_mass(m, bo.lumping, density);
+        if (!H->host_only && bo.lumping == 0 && env_int("HSIM_HOST_ASSEMBLY", 0) == 0) {
+            // cotangent stiffness and lumped mass assembled on the device (same values as the host
+            // assembly, term for term in the same order), downloaded for the rest of the build
+            device_assembly(m, g, density, L0.S, L0.mdiag);
+            for (int64_t i = 0; i < nv; ++i)
+                if (!(L0.mdiag[i] > 0)) fail(HSIM_E_MESH, "lumped mass of vertex %lld is not positive", (long long)i);
+        } else {
+            L0.S = cotan_stiffness(m);
+            L0.mdiag = lumped_mass(m, bo.lumping, density);
+        }
         if (restricted) {
             // Dirichlet: the principal submatrix of S and the lumped masses on the unknowns
             std::vector<int32_t> pos(nv, -1);

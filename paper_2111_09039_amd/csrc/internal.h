@@ -54,6 +54,16 @@ double surface_area(const Mesh& m);
 std::vector<char> boundary_vertex_flags(const Mesh& m);
 Csr cotan_stiffness(const Mesh& m);
 std::vector<double> lumped_mass(const Mesh& m, int lumping, const double* density);
+// index structures of the device assembly of S (pattern, corner lists) and the lumped M
+struct AssemblyMaps {
+    Csr S;                        // pattern only (val empty), sorted columns, diagonal included
+    std::vector<int64_t> corner;  // [2 nnz]: corners 3t + k opposite the entry's edge, -1 padded
+    std::vector<int64_t> dptr;    // [n + 1]: each vertex's diagonal corners in dcorner
+    std::vector<int64_t> dcorner;
+    std::vector<int64_t> vptr;    // [n + 1]: each vertex's triangles in vtri (ascending)
+    std::vector<int32_t> vtri;
+};
+AssemblyMaps assembly_maps(const Mesh& m, const Graph& g);
 
 // hierarchy.cpp
 std::vector<int64_t> level_sizes(int64_t n0, int T, int64_t n_coarsest, int growth_mode);

@@ -133,6 +133,14 @@ hipError_t launch_equilibrate(const double* S, const double* M, int32_t k, doubl
                               hipStream_t s);
 // copy the lower triangle of the k x k row-major A into one dense front (tile
 // storage, Mt tiles per side); dummy pivots beyond k get 1 on the diagonal
+// finest-level cotangent stiffness values on a given CSR pattern and barycentric lumped mass
+// (corner lists: per entry its <= 2 opposite corners 3t + k, -1 padded; per vertex the corners
+// whose weights its diagonal sums; per vertex its triangles); w [3 nf], a3 [nf] scratch
+hipError_t launch_assemble_mesh(const double* V, const int32_t* F, int64_t nf, int64_t n, const int64_t* ptr,
+                                const int32_t* idx, const int64_t* corner, const int64_t* dptr,
+                                const int64_t* dcorner, const int64_t* vptr, const int32_t* vtri,
+                                const double* density, double* w, double* a3, double* sval, double* mdiag,
+                                hipStream_t s);
 // descriptor, factorisation work lists and zero gather pointers of a dense k x k problem as one front
 hipError_t launch_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t Mt, int32_t* diag, int32_t* panel,
                               int32_t* upd, int64_t* gptr, hipStream_t s);

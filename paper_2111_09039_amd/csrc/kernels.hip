@@ -2423,6 +2423,83 @@ hipError_t launch_equilibrate(const double* S, const double* M, int32_t k, doubl
     return hipGetLastError();
 }
 
+// ============================================================ device assembly
+// Cotangent stiffness and lumped mass of the finest level (eq. massStiffMatrices)
+// on the device, for the pattern the host derived from the triangles.  Plain
+// IEEE arithmetic without contraction, in the host assembly's order, so the
+// values equal the host's bit for bit.
+#pragma clang fp contract(off)
+// per triangle t: w[3t + k] = -cot(angle at corner k) / 2, a3[t] = area / 3
+__global__ void k_tri_weights(const double* __restrict__ V, const int32_t* __restrict__ F, int64_t nf,
+                              double* __restrict__ w, double* __restrict__ a3) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t f[3] = {F[3 * t], F[3 * t + 1], F[3 * t + 2]};
+        for (int k = 0; k < 3; ++k) {
+            const double* P = V + 3 * (int64_t)f[k];
+            const double* Q = V + 3 * (int64_t)f[(k + 1) % 3];
+            const double* R = V + 3 * (int64_t)f[(k + 2) % 3];
+            const double ux = Q[0] - P[0], uy = Q[1] - P[1], uz = Q[2] - P[2];
+            const double vx = R[0] - P[0], vy = R[1] - P[1], vz = R[2] - P[2];
+            const double dot = ux * vx + uy * vy + uz * vz;
+            const double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+            w[3 * t + k] = -0.5 * (dot / sqrt(cx * cx + cy * cy + cz * cz));
+        }
+        const double* a = V + 3 * (int64_t)f[0];
+        const double* b = V + 3 * (int64_t)f[1];
+        const double* c = V + 3 * (int64_t)f[2];
+        const double e1x = b[0] - a[0], e1y = b[1] - a[1], e1z = b[2] - a[2];
+        const double e2x = c[0] - a[0], e2y = c[1] - a[1], e2z = c[2] - a[2];
+        const double cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
+        a3[t] = 0.5 * sqrt(cx * cx + cy * cy + cz * cz) / 3.0;
+    }
+}
+// S values on the pattern: an off-diagonal entry sums the weights of the (at
+// most two) corners opposite its edge, in triangle order; the diagonal entry
+// sums the negated weights of every corner opposite an edge at the vertex,
+// in triangle order (corner lists prepared by the host)
+__global__ void k_assemble_stiffness(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                                     const int64_t* __restrict__ corner, int64_t n, const int64_t* __restrict__ dptr,
+                                     const int64_t* __restrict__ dcorner, const double* __restrict__ w,
+                                     double* __restrict__ val) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+            double v = 0.0;
+            if (idx[e] == i) {
+                for (int64_t c = dptr[i]; c < dptr[i + 1]; ++c) v += -w[dcorner[c]];
+            } else {
+                if (corner[2 * e] >= 0) v += w[corner[2 * e]];
+                if (corner[2 * e + 1] >= 0) v += w[corner[2 * e + 1]];
+            }
+            val[e] = v;
+        }
+    }
+}
+// m_i = density_i * sum over the triangles at i (ascending) of area / 3
+__global__ void k_assemble_mass(const int64_t* __restrict__ vptr, const int32_t* __restrict__ vtri, int64_t n,
+                                const double* __restrict__ a3, const double* __restrict__ density,
+                                double* __restrict__ m) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int64_t k = vptr[i]; k < vptr[i + 1]; ++k) v += a3[vtri[k]];
+        m[i] = density ? v * density[i] : v;
+    }
+}
+#pragma clang fp contract(on)
+hipError_t launch_assemble_mesh(const double* V, const int32_t* F, int64_t nf, int64_t n, const int64_t* ptr,
+                                const int32_t* idx, const int64_t* corner, const int64_t* dptr,
+                                const int64_t* dcorner, const int64_t* vptr, const int32_t* vtri,
+                                const double* density, double* w, double* a3, double* sval, double* mdiag,
+                                hipStream_t s) {
+    if (nf <= 0 || n <= 0) return hipErrorInvalidValue;
+    k_tri_weights<<<grid_for(nf, 256), 256, 0, s>>>(V, F, nf, w, a3);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_assemble_stiffness<<<grid_for(n, 256), 256, 0, s>>>(ptr, idx, corner, n, dptr, dcorner, w, sval);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_assemble_mass<<<grid_for(n, 256), 256, 0, s>>>(vptr, vtri, n, a3, density, mdiag);
+    return hipGetLastError();
+}
+
 // Descriptor and factorisation work lists of a dense k x k problem held as one
 // front of Mt x Mt tiles: per pivot tile step st the diagonal item (front 0),
 // the panel items (0, I) for I > st and the update items (0, I, J) for

@@ -213,4 +213,71 @@ std::vector<double> lumped_mass(const Mesh& m, int lumping, const double* densit
     return mass;
 }
 
+
+// Index structures of the device assembly (cotangent stiffness on the
+// pattern of the edge graph plus the diagonal, barycentric lumped mass): per
+// CSR entry the <= 2 triangle corners opposite its edge, per vertex the
+// corners whose weights its diagonal sums and its triangles, every list in
+// triangle order and, within a triangle, corner order -- the order in which
+// the host assembly sums the same terms.
+AssemblyMaps assembly_maps(const Mesh& m, const Graph& g) {
+    AssemblyMaps a;
+    const int64_t n = m.nv;
+    a.S.rows = a.S.cols = n;
+    a.S.ptr.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) a.S.ptr[i + 1] = a.S.ptr[i] + (g.ptr[i + 1] - g.ptr[i]) + 1;
+    a.S.idx.resize(a.S.ptr[n]);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t o = a.S.ptr[i];
+        bool put = false;
+        for (int64_t e = g.ptr[i]; e < g.ptr[i + 1]; ++e) {
+            if (!put && g.nbr[e] > i) {
+                a.S.idx[o++] = (int32_t)i;
+                put = true;
+            }
+            a.S.idx[o++] = g.nbr[e];
+        }
+        if (!put) a.S.idx[o++] = (int32_t)i;
+    }
+    a.corner.assign(2 * a.S.ptr[n], -1);
+    auto find = [&](int32_t i, int32_t j) -> int64_t {
+        const int32_t* b = a.S.idx.data() + a.S.ptr[i];
+        const int32_t* e = a.S.idx.data() + a.S.ptr[i + 1];
+        const int32_t* q = std::lower_bound(b, e, j);
+        if (q == e || *q != j) fail(HSIM_E_MESH, "edge (%d, %d) missing from the edge graph", i, j);
+        return a.S.ptr[i] + (q - b);
+    };
+    for (int64_t t = 0; t < m.nf; ++t) {
+        const int32_t* f = &m.F[3 * t];
+        for (int k = 0; k < 3; ++k) {
+            const int32_t i = f[(k + 1) % 3], j = f[(k + 2) % 3];
+            for (int64_t e : {find(i, j), find(j, i)}) {
+                int64_t* c = &a.corner[2 * e];
+                if (c[0] < 0) c[0] = 3 * t + k;
+                else if (c[1] < 0) c[1] = 3 * t + k;
+                else fail(HSIM_E_MESH, "edge (%d, %d) belongs to more than two triangles", i, j);
+            }
+        }
+    }
+    // vertex -> triangles (ascending), and the two corners of each that face an edge at the vertex
+    a.vptr.assign(n + 1, 0);
+    for (int64_t t = 0; t < m.nf; ++t)
+        for (int k = 0; k < 3; ++k) a.vptr[m.F[3 * t + k] + 1]++;
+    for (int64_t i = 0; i < n; ++i) a.vptr[i + 1] += a.vptr[i];
+    a.vtri.resize(a.vptr[n]);
+    a.dcorner.resize(2 * a.vptr[n]);
+    std::vector<int64_t> fill(a.vptr.begin(), a.vptr.end() - 1);
+    for (int64_t t = 0; t < m.nf; ++t)
+        for (int k = 0; k < 3; ++k) {
+            const int64_t o = fill[m.F[3 * t + k]]++;
+            a.vtri[o] = (int32_t)t;
+            a.dcorner[2 * o] = 3 * t + (k == 0 ? 1 : 0);
+            a.dcorner[2 * o + 1] = 3 * t + (k == 2 ? 1 : 2);
+        }
+    a.dptr.resize(n + 1);
+    for (int64_t i = 0; i <= n; ++i) a.dptr[i] = 2 * a.vptr[i];
+    return a;
+}
+
 }  // namespace hsim

@@ -87,6 +87,50 @@ int main(int argc, char** argv) {
         }
         std::printf("S_nnz %lld\nS_max_abs_rowsum %.3e\narea %.17g\nmass_sum %.17g\n", (long long)S.nnz(), rowsum,
                     area, msum);
+        {
+            // the device assembly's index structures, evaluated on the host with the
+            // device kernels' formulas, must reproduce the host assembly bit for bit
+            AssemblyMaps a = assembly_maps(m, g);
+            std::vector<double> w(3 * nf), a3(nf);
+            for (int64_t t = 0; t < nf; ++t) {
+                const int32_t* f = &m.F[3 * t];
+                for (int k = 0; k < 3; ++k) {
+                    const double* P = &m.V[3 * (int64_t)f[k]];
+                    const double* Q = &m.V[3 * (int64_t)f[(k + 1) % 3]];
+                    const double* R = &m.V[3 * (int64_t)f[(k + 2) % 3]];
+                    const double ux = Q[0] - P[0], uy = Q[1] - P[1], uz = Q[2] - P[2];
+                    const double vx = R[0] - P[0], vy = R[1] - P[1], vz = R[2] - P[2];
+                    const double dot = ux * vx + uy * vy + uz * vz;
+                    const double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+                    w[3 * t + k] = -0.5 * (dot / std::sqrt(cx * cx + cy * cy + cz * cz));
+                }
+                const double* A = &m.V[3 * (int64_t)f[0]];
+                const double* B = &m.V[3 * (int64_t)f[1]];
+                const double* C = &m.V[3 * (int64_t)f[2]];
+                const double e1x = B[0] - A[0], e1y = B[1] - A[1], e1z = B[2] - A[2];
+                const double e2x = C[0] - A[0], e2y = C[1] - A[1], e2z = C[2] - A[2];
+                const double cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
+                a3[t] = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz) / 3.0;
+            }
+            bool same = a.S.ptr == S.ptr && a.S.idx == S.idx;
+            for (int64_t i = 0; same && i < nv; ++i)
+                for (int64_t e = a.S.ptr[i]; e < a.S.ptr[i + 1]; ++e) {
+                    double v = 0.0;
+                    if (a.S.idx[e] == i) {
+                        for (int64_t c = a.dptr[i]; c < a.dptr[i + 1]; ++c) v += -w[a.dcorner[c]];
+                    } else {
+                        if (a.corner[2 * e] >= 0) v += w[a.corner[2 * e]];
+                        if (a.corner[2 * e + 1] >= 0) v += w[a.corner[2 * e + 1]];
+                    }
+                    same &= v == S.val[e];
+                }
+            for (int64_t i = 0; same && i < nv; ++i) {
+                double v = 0.0;
+                for (int64_t k = a.vptr[i]; k < a.vptr[i + 1]; ++k) v += a3[a.vtri[k]];
+                same &= v == md[i];
+            }
+            std::printf("assembly_maps_match %d\n", (int)same);
+        }
         std::vector<int64_t> sizes = level_sizes(nv, T, nc, 0);
         std::printf("levels");
         for (int64_t s : sizes) std::printf(" %lld", (long long)s);

@@ -470,3 +470,28 @@ def test_wide_hsim(wide):
     assert sim.residual(S, m, X, ev).max() < 2e-9
     err = metrics.eigenvector_err(X, Xr, m, lr)
     assert err.max() < 1e-5, err.max()
+
+
+def test_device_assembly_equals_host(cuda, monkeypatch):
+    """The finest level's cotangent stiffness and lumped mass assembled on the
+    device (the default build) equal the host assembly bit for bit (same
+    terms, same order, no contraction), and the oracle's to rounding."""
+    import paper_2111_09039_amd as hs
+    rng = np.random.default_rng(5)
+    V, F = synth.torus(60, 40)
+    V = synth.isotropic_noise(V, F, 0.2 * synth.mean_edge_length(V, F), rng)
+    d = synth.random_density(len(V), rng)
+    Hd = hs.Hierarchy(V, F, 10, density=d, levels=2, n_coarsest=200)
+    monkeypatch.setenv("HSIM_HOST_ASSEMBLY", "1")
+    Hh = hs.Hierarchy(V, F, 10, density=d, levels=2, n_coarsest=200)
+    ed, eh = Hd.export(0), Hh.export(0)
+    for k in ("S_indptr", "S_indices", "S_data", "M_data", "U_data", "perm"):
+        assert np.array_equal(ed[k], eh[k]), k
+    S, m = assembly.assemble(V, F, density=d)
+    Sd = sp.csr_matrix((ed["S_data"], ed["S_indices"], ed["S_indptr"]), shape=S.shape)
+    assert abs(Sd - S).max() <= 1e-13 * abs(S).max()
+    diag = np.zeros(len(V))
+    rows = np.repeat(np.arange(len(V)), np.diff(ed["S_indptr"]))
+    on = ed["S_indices"] == rows
+    diag[rows[on]] = ed["M_data"][on]
+    assert np.abs(diag - m).max() <= 1e-14 * m.max()

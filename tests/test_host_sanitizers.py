@@ -70,6 +70,8 @@ def test_host_build_under_sanitizers(driver, tmp_path, name):
         T, nc = 2, 150
     out = run(driver, tmp_path, V, F, 10, T, nc)
     assert out["ok"] == [[]]
+    # the device assembly's index structures reproduce the host assembly term for term
+    assert out["assembly_maps_match"] == [["1"]]
     S, m = assembly.assemble(V, F)
     assert int(out["S_nnz"][0][0]) == S.nnz
     assert float(out["S_max_abs_rowsum"][0][0]) < 1e-12
