@@ -168,6 +168,10 @@ typedef struct {
     double rho;            /* support radius of U^tau (eq. radius); 0 on the coarsest */
     double factor_flops;   /* flops of one numeric factorisation                      */
     int64_t factor_nnz;    /* nonzeros of L (unpadded supernodal panels, incl. diagonal) */
+    int64_t qpanel_tree_levels; /* tree levels whose fronts also get inverse panels
+                              Q = [L11^-1; -L21 L11^-1] in every factorisation (the block
+                              solves may multiply by them instead of substituting)    */
+    int64_t qpanel_entries;/* stored inverse-panel values (padded tiles)              */
 } hsim_level_desc;
 
 void hsim_default_build_opts(hsim_build_opts* opts);
@@ -238,9 +242,10 @@ hsim_status hsim_solve_batch(hsim_hierarchy* const* hs, int32_t count, const hsi
 /*
  * hsim_autotune -- choose the launch plan of the block triangular solves of
  * one level (the widest-supernode thresholds, in padded pivots, from which a
- * tree level's forward and backward sweeps use the multi-workgroup block
- * solve instead of the wave-level matrix-core solve) by timing a q-column
- * block solve of each candidate (forward 128/256/512 x backward 64/128/256)
+ * tree level's forward and backward sweeps multiply by the inverse panels of
+ * its fronts, Q = [L11^-1; -L21 L11^-1], instead of running the wave-level
+ * matrix-core solve) by timing a q-column block solve of each candidate
+ * (forward 128/256/512 x backward 128/256/512)
  * on a factor of S - mu M with mu below the spectrum, and keep the fastest
  * for the following solves of this hierarchy.  With the environment variable
  * HSIM_TUNE_CACHE naming a file, the choice is looked up there first (keyed
@@ -256,8 +261,6 @@ typedef struct {
 hsim_status hsim_autotune(hsim_hierarchy* h, int32_t level, void* stream, hsim_tune_result* out);
 
 /*
- * hsim_solve_backward -- vector-Jacobian product/*
- * hsim_solve_backward -- vector-Jacobian product/*
  * hsim_solve_backward -- vector-Jacobian product of the last hsim_solve
  * (run with HSIM_FLAG_SAVE_FORWARD) with respect to the vertex positions.
  * Eigenvalue part: d lambda_k = x_k^T (dS - lambda_k dM) x_k.  Eigenvector

@@ -55,7 +55,8 @@ class TuneResult(C.Structure):
 class LevelDesc(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("nnz_u", C.c_int64), ("fronts", C.c_int64),
                 ("tree_levels", C.c_int64), ("factor_entries", C.c_int64), ("rho", C.c_double),
-                ("factor_flops", C.c_double), ("factor_nnz", C.c_int64)]
+                ("factor_flops", C.c_double), ("factor_nnz", C.c_int64), ("qpanel_tree_levels", C.c_int64),
+                ("qpanel_entries", C.c_int64)]
 
 
 STATUS = {0: "HSIM_OK", -1: "HSIM_E_INVALID", -2: "HSIM_E_MESH", -3: "HSIM_E_FACTOR", -4: "HSIM_E_NOCONV",

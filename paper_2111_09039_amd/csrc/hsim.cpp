@@ -137,29 +137,26 @@ struct Prof {
 // ====================================================== dense eigenproblem
 // First kout eigenpairs of S x = lambda M x for k x k dense symmetric S and SPD M
 // (row-major, device): equilibration E = diag(M)^-1/2, LDL^T of E M E by the
-// tiled front kernels, C = D^-1/2 L^-1 (E S E) L^-T D^-1/2, cyclic Jacobi on C,
-// X = E L^-T D^-1/2 V.
+// tiled front kernels (with the inverse panel P = L^-1 of the one front),
+// C = D^-1/2 P (E S E) P^T D^-1/2 by two products, cyclic Jacobi on C,
+// X = E P^T D^-1/2 V by a third.
 struct DenseGEP {
     int32_t k = 0, m = 0, ns_pad = 0, Mt = 0, bj = 16;
-    std::vector<int64_t> diag_ptr, panel_ptr, upd_ptr;
-    // large problems: triangular solves by the multi-workgroup block solve over
-    // 128-row pivot blocks (transposed tile copies for the backward sweep)
-    bool big = false;
-    int32_t nblk = 0;
-    std::vector<int64_t> fupd_off, fupd_cnt, bupd_off, bupd_cnt;
+    std::vector<int64_t> diag_ptr, panel_ptr, upd_ptr, qrow_ptr, qupd_ptr;
+    int64_t nprod = 0;   // product items (0, o): 16-row tiles of the k rows
     // device work arrays: owned (setup) or carved from a caller's region (setup_in)
     DeviceBuffer store;
     DFront* front = nullptr;
-    double *tiles = nullptr, *linv = nullptr, *D = nullptr, *tilesT = nullptr, *linvT = nullptr;
+    double *tiles = nullptr, *linv = nullptr, *D = nullptr, *qinvT = nullptr, *qinv = nullptr;
     double *S2 = nullptr, *M2 = nullptr, *e = nullptr, *W = nullptr, *W2 = nullptr, *C = nullptr, *V = nullptr,
            *Qs = nullptr, *dis = nullptr, *normf = nullptr;
-    int32_t *items_diag = nullptr, *items_panel = nullptr, *items_upd = nullptr, *counters = nullptr,
-            *qrot = nullptr, *rot = nullptr, *big_items = nullptr;
+    int32_t *items_diag = nullptr, *items_panel = nullptr, *items_upd = nullptr, *items_qrow = nullptr,
+            *items_qupd = nullptr, *items_prod = nullptr, *counters = nullptr, *qrot = nullptr, *rot = nullptr;
     int64_t* gptr = nullptr;
     bool owned = false;
 
-    // host-side shape: sizes, work-list offsets and (big problems) the block-solve item list
-    std::vector<int32_t> shape(int32_t kk) {
+    // host-side shape: sizes and work-list offsets
+    void shape(int32_t kk) {
         k = kk;
         bj = 16;                                       // block Jacobi block size
         m = (int32_t)round_up(k, 2 * bj);
@@ -168,47 +165,27 @@ struct DenseGEP {
         diag_ptr = {0};
         panel_ptr = {0};
         upd_ptr = {0};
-        int64_t nd = 0, np = 0, nu = 0;
+        qrow_ptr = {0};
+        qupd_ptr = {0};
+        int64_t nd = 0, np = 0, nu = 0, nqr = 0, nqu = 0;
         for (int32_t st = 0; st < Mt; ++st) {
             nd += 1;
             np += Mt - 1 - st;
             for (int32_t J = st + 1; J < Mt; ++J) nu += Mt - J;
+            nqr += st + 1;
+            nqu += (int64_t)(Mt - 1 - st) * (st + 1);
             diag_ptr.push_back(nd);
             panel_ptr.push_back(np);
             upd_ptr.push_back(nu);
+            qrow_ptr.push_back(nqr);
+            qupd_ptr.push_back(nqu);
         }
-        big = ns_pad >= env_int("HSIM_DENSE_BIG_MIN", 512);
-        std::vector<int32_t> bi;
-        if (big) {
-            // items: [0] the front (diagonal phases), then per pivot block the
-            // (front, tile row) pairs below it (forward) and above it (backward)
-            nblk = (Mt + BIG_BLOCK_TILES - 1) / BIG_BLOCK_TILES;
-            bi = {0, 0};
-            fupd_off.assign(nblk, 0);
-            fupd_cnt.assign(nblk, 0);
-            bupd_off.assign(nblk, 0);
-            bupd_cnt.assign(nblk, 0);
-            for (int32_t kb = 0; kb < nblk; ++kb) {
-                fupd_off[kb] = (int64_t)bi.size();
-                for (int32_t r = std::min(Mt, (kb + 1) * BIG_BLOCK_TILES); r < Mt; ++r) {
-                    bi.push_back(0);
-                    bi.push_back(r);
-                }
-                fupd_cnt[kb] = ((int64_t)bi.size() - fupd_off[kb]) / 2;
-                bupd_off[kb] = (int64_t)bi.size();
-                for (int32_t r = 0; r < kb * BIG_BLOCK_TILES; ++r) {
-                    bi.push_back(0);
-                    bi.push_back(r);
-                }
-                bupd_cnt[kb] = ((int64_t)bi.size() - bupd_off[kb]) / 2;
-            }
-        }
-        return bi;
+        nprod = (k + 15) / 16;
     }
 
     // carve the work arrays out of [base, base + cap) (256-byte aligned pieces);
     // returns the bytes used (also when base is null: sizing only)
-    size_t carve(char* base, size_t cap, size_t big_ints) {
+    size_t carve(char* base, size_t cap) {
         size_t off = 0;
         auto take = [&](size_t bytes) -> char* {
             char* q = base ? base + off : nullptr;
@@ -221,6 +198,8 @@ struct DenseGEP {
         tiles = reinterpret_cast<double*>(take(tile_bytes));
         linv = reinterpret_cast<double*>(take((size_t)Mt * NB * NB * d8));
         D = reinterpret_cast<double*>(take((size_t)ns_pad * d8));
+        qinvT = reinterpret_cast<double*>(take(tile_bytes));
+        qinv = reinterpret_cast<double*>(take(tile_bytes));
         S2 = reinterpret_cast<double*>(take(kk2));
         M2 = reinterpret_cast<double*>(take(kk2));
         W = reinterpret_cast<double*>(take(kk2));
@@ -235,17 +214,12 @@ struct DenseGEP {
         items_diag = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, diag_ptr.back()) * 4));
         items_panel = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, panel_ptr.back()) * 2 * 4));
         items_upd = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, upd_ptr.back()) * 3 * 4));
+        items_qrow = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, qrow_ptr.back()) * 2 * 4));
+        items_qupd = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, qupd_ptr.back()) * 3 * 4));
+        items_prod = reinterpret_cast<int32_t*>(take((size_t)std::max<int64_t>(1, nprod) * 2 * 4));
         counters = reinterpret_cast<int32_t*>(take(4 * 4));
         qrot = reinterpret_cast<int32_t*>(take((size_t)(m / (2 * bj)) * 4));
         rot = reinterpret_cast<int32_t*>(take(4 * 4));
-        if (big) {
-            tilesT = reinterpret_cast<double*>(take(tile_bytes));
-            linvT = reinterpret_cast<double*>(take((size_t)Mt * NB * NB * d8));
-            big_items = reinterpret_cast<int32_t*>(take(big_ints * 4));
-        } else {
-            tilesT = linvT = nullptr;
-            big_items = nullptr;
-        }
         if (base && off > cap) fail(HSIM_E_INVALID, "dense eigenproblem work arrays need %zu bytes, %zu available", off, cap);
         return off;
     }
@@ -253,89 +227,54 @@ struct DenseGEP {
     // owned work arrays (allocated here, kept for the next call of the same size)
     void setup(int32_t kk, hipStream_t s) {
         if (k == kk && owned) return;
-        std::vector<int32_t> bi = shape(kk);
-        const size_t need = carve(nullptr, 0, bi.size());
+        shape(kk);
+        const size_t need = carve(nullptr, 0);
         store.alloc(need);
-        carve(static_cast<char*>(store.p), store.bytes, bi.size());
+        carve(static_cast<char*>(store.p), store.bytes);
         owned = true;
-        fill_lists(bi, s);
+        fill_lists(s);
     }
 
     // work arrays in the caller's device region [base, base + cap): allocates nothing
     void setup_in(int32_t kk, char* base, size_t cap, hipStream_t s) {
-        std::vector<int32_t> bi = shape(kk);
-        if (big) fail(HSIM_E_INVALID, "dense eigenproblems of %d unknowns need the allocating entry point", kk);
-        carve(base, cap, 0);
+        shape(kk);
+        carve(base, cap);
         owned = false;
-        fill_lists(bi, s);
+        fill_lists(s);
     }
 
-    // the front descriptor, the tile work lists and the (empty) gather pointers,
-    // written on the device; the block-solve item list of big problems is copied
-    void fill_lists(const std::vector<int32_t>& bi, hipStream_t s) {
-        HIPCHECK(launch_dense_lists(front, k, ns_pad, Mt, items_diag, items_panel, items_upd, gptr, s));
-        if (big) HIPCHECK(hipMemcpyAsync(big_items, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, s));
+    // the front descriptor, the tile work lists (factorisation, inverse panel,
+    // products) and the (empty) gather pointers, written on the device
+    void fill_lists(hipStream_t s) {
+        HIPCHECK(launch_dense_lists(front, k, ns_pad, Mt, items_diag, items_panel, items_upd, items_qrow, items_qupd,
+                                    items_prod, gptr, s));
         HIPCHECK(hipStreamSynchronize(s));
     }
 
     void factor(hipStream_t s) {
         HIPCHECK(launch_fill_i32(counters, 4, 0, s));
+        HIPCHECK(launch_fill(qinvT, (int64_t)Mt * (Mt + 1) / 2 * NB * NB, 0.0, s));
         for (int32_t st = 0; st < Mt; ++st) {
             HIPCHECK(launch_fac_diag(tiles, linv, D, front, items_diag + diag_ptr[st], diag_ptr[st + 1] - diag_ptr[st],
                                      st, counters, s));
             HIPCHECK(launch_fac_panel(tiles, linv, D, front, items_panel + 2 * panel_ptr[st],
-                                      panel_ptr[st + 1] - panel_ptr[st], st, s));
+                                      panel_ptr[st + 1] - panel_ptr[st], st, s, qinvT,
+                                      items_qrow + 2 * qrow_ptr[st], qrow_ptr[st + 1] - qrow_ptr[st]));
             HIPCHECK(launch_fac_update(tiles, D, front, items_upd + 3 * upd_ptr[st], upd_ptr[st + 1] - upd_ptr[st], st,
-                                       s));
+                                       s, qinvT, items_qupd + 3 * qupd_ptr[st], qupd_ptr[st + 1] - qupd_ptr[st]));
         }
-        if (big) {
-            HIPCHECK(launch_tile_transpose<double>(tiles, tilesT, (int64_t)Mt * (Mt + 1) / 2, s));
-            HIPCHECK(launch_tile_transpose<double>(linv, linvT, Mt, s));
-        }
+        HIPCHECK(launch_tile_transpose<double>(qinvT, qinv, (int64_t)Mt * (Mt + 1) / 2, s));
     }
 
-    int32_t qc_for(int32_t ncols) const {
-        const int32_t qc = solve_chunk_width(ns_pad, ncols, false);
-        if (!qc) fail(HSIM_E_UNIMPLEMENTED, "dense problem of size %d exceeds the solve kernels' LDS", k);
-        return qc;
+    // Y = L^-1 X (forward) or Y = L^-T X (backward; no D^-1: the caller
+    // scales), X and Y n x ncols row-major with leading dimension ld, X != Y
+    void fwd(const double* X, double* Y, int32_t ncols, int64_t ld, hipStream_t s) {
+        HIPCHECK(launch_qsolve<double>(1, qinv, qinvT, D, front, items_prod, nprod, const_cast<double*>(X), ld, Y, ld,
+                                       0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s));
     }
-
-    // the multi-workgroup block solve of the dense front: forward L^-1 X, or
-    // backward L^-T X (no D^-1: the caller scales)
-    void big_sweep(bool forward, double* X, int32_t ncols, int64_t ld, hipStream_t s) {
-        auto run = [&](int phase, int64_t off, int64_t cnt, int32_t kb) {
-            HIPCHECK(launch_big_solve<double>(phase, tiles, linv, D, tilesT, linvT, front, big_items + off, cnt, kb, X,
-                                              ld, 0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s));
-        };
-        if (forward) {
-            for (int32_t kb = 0; kb < nblk; ++kb) {
-                run(1, 0, 1, kb);
-                run(2, fupd_off[kb], fupd_cnt[kb], kb);
-            }
-        } else {
-            for (int32_t kb = nblk - 1; kb >= 0; --kb) {
-                run(4, 0, 1, kb);
-                run(5, bupd_off[kb], bupd_cnt[kb], kb);
-            }
-        }
-    }
-
-    void fwd(double* X, int32_t ncols, hipStream_t s) {
-        if (big) {
-            big_sweep(true, X, ncols, k, s);
-            return;
-        }
-        const int32_t qc = qc_for(ncols);
-        HIPCHECK(launch_solve_fwd<double>(tiles, linv, front, 0, 1, ns_pad, X, ncols, 0, ncols, qc, nullptr, 0, gptr,
-                                          nullptr, nullptr, s));
-    }
-    void bwd(double* X, int32_t ncols, int64_t ld, hipStream_t s) {
-        if (big) {
-            big_sweep(false, X, ncols, ld, s);
-            return;
-        }
-        const int32_t qc = qc_for(ncols);
-        HIPCHECK(launch_solve_bwd<double>(tiles, linv, D, front, 0, 1, ns_pad, X, ld, 0, ncols, qc, nullptr, false, s));
+    void bwd(const double* X, double* Y, int32_t ncols, int64_t ld, hipStream_t s) {
+        HIPCHECK(launch_qsolve<double>(3, qinv, qinvT, D, front, items_prod, nprod, const_cast<double*>(X), ld, Y, ld,
+                                       0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s));
     }
 
     // returns the Jacobi sweeps used, or -1 when dM is not numerically
@@ -359,14 +298,13 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
         HIPCHECK(hipStreamSynchronize(s));
         if (piv[0] > 0 || piv[1] > 0) return -1;
     }
-    // W = L^-1 S', W2 = W^T, W2 <- L^-1 W2 = L^-1 S' L^-T
-    HIPCHECK(launch_copy2d(S2, k, k, k, W, k, s));
-    fwd(W, k, s);
+    // W = L^-1 S', W2 = W^T, W = L^-1 W2 = L^-1 S' L^-T
+    fwd(S2, W, k, k, s);
     HIPCHECK(launch_transpose(W, k, W2, s));
-    fwd(W2, k, s);
-    // C = D^-1/2 W2 D^-1/2 (symmetrised) embedded in m x m; dis = D^-1/2
-    HIPCHECK(launch_sym_scale(W2, D, k, W, s));
-    HIPCHECK(launch_embed_pad(W, k, m, C, normf, dis, D, s));
+    fwd(W2, W, k, k, s);
+    // C = D^-1/2 W D^-1/2 (symmetrised) embedded in m x m; dis = D^-1/2
+    HIPCHECK(launch_sym_scale(W, D, k, W2, s));
+    HIPCHECK(launch_embed_pad(W2, k, m, C, normf, dis, D, s));
     HIPCHECK(launch_identity(V, m, s));
     const double tol_rel = 1e-15, tol_abs_rel = 1e-17;
     int32_t sweeps = 0;
@@ -383,8 +321,8 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     }
     // Y = D^-1/2 V (sorted, first kout columns), X' = L^-T Y, X = E X'
     HIPCHECK(launch_sort_eig(C, m, m, V, k, dis, kout, lam_out, W, kout, s));
-    bwd(W, kout, kout, s);
-    HIPCHECK(launch_diag_scale(e, k, W, kout, kout, X, ldx, s));
+    bwd(W, W2, kout, kout, s);
+    HIPCHECK(launch_diag_scale(e, k, W2, kout, kout, X, ldx, s));
     return std::min(sweeps, max_sweeps);
 }
 
@@ -417,20 +355,23 @@ static char* rr_scratch_ptr() {
 
 // ================================================================ levels
 // tree levels whose widest supernode has at least this many (padded) pivots
-// use the multi-workgroup block solve
+// solve through the inverse panels of their fronts (forward sweep)
 constexpr int32_t BIG_NS = 256;
-// the backward sweep switches to the multi-workgroup solve earlier (its
-// wave-level form reduces over all struct rows of a front in one wave)
+// the backward sweep switches earlier (its wave-level form reduces over all
+// struct rows of a front in one wave)
 constexpr int32_t BIG_NS_BWD = 128;
+// tree levels whose widest supernode has at least this many padded pivots
+// get inverse panels in every factorisation (the plans choose among them)
+constexpr int32_t QPANEL_MIN_NS = 128;
 
 struct TLev {
     int32_t f0 = 0, f1 = 0, ns_pad_max = 0;
-    // wide supernodes: multi-workgroup block solve (item lists in Level::big_items,
-    // built when either sweep uses it)
-    bool big = false, big_fwd = false, big_bwd = false;
-    int32_t nblk = 0;
-    int64_t fwd_init[2] = {0, 0}, bwd_init[2] = {0, 0};   // [offset (ints), count]
-    std::vector<int64_t> fdiag, fupd, bdiag, bupd;       // per block: offset, count pairs
+    // inverse panels: q (the level's fronts have them), and whether the
+    // forward / backward sweep uses them in the current plan; item lists in
+    // Level::q_items: gather (front, 32-row tile), forward product (front,
+    // 16-row tile), backward product (front, 16-row pivot tile)
+    bool q = false, big_fwd = false, big_bwd = false;
+    int64_t q_gather[2] = {0, 0}, q_fprod[2] = {0, 0}, q_bprod[2] = {0, 0};   // [offset (ints), count]
     double l_entries = 0, pivots = 0;    // unpadded L entries and pivot rows of the level's fronts
     int32_t step0 = 0, step1 = 0;
     std::vector<int32_t> ea_tile_cols;   // per child slot: max tile columns of the children's update blocks
@@ -453,9 +394,15 @@ struct Level {
     DeviceBuffer dmeshmap;   // level 0: mesh vertex of every internal row
     DeviceBuffer dfronts, tiles, linv, D, tiles32, linv32, D32, counters;
     DeviceBuffer tilesT, linvT, tiles32T, linv32T;   // tile-transposed copies for the backward sweeps
+    // inverse panels of the fronts on tree levels with TLev::q: transposed
+    // tiles (written by the factorisation), column-major tiles, FP32 mirrors;
+    // their work items per factorisation step; the solves' scratch block
+    DeviceBuffer qinvT, qinv, qinv32, qinv32T, it_qrow, it_qupd, q_items, qrhs;
+    int64_t q_doubles = 0, qrhs_rows = 0;
+    std::vector<int64_t> qrow_ptr, qupd_ptr;   // per step: row items (pairs), update items (triples)
     DeviceBuffer asm_dst, asm_src, it_diag, it_panel, it_upd, it_ea, rel, rows, gat;
     int32_t gw = 0;   // width of the padded gather table
-    DeviceBuffer ubuf, big_items;
+    DeviceBuffer ubuf;
     int32_t big_ns = 0, big_ns_bwd = 0;   // thresholds of the current block-solve plan
     double mu = 0;
     bool factored = false, factored32 = false;
@@ -501,16 +448,31 @@ namespace hsim {
 // ----------------------------------------------------------- build helpers
 // Launch plan of the block solves on one level: per tree level the fronts,
 // the tile and pivot counts, and whether the forward / backward sweep of the
-// level uses the multi-workgroup block solve (widest front at least big_ns /
-// big_ns_bwd padded pivots, or wider than the wave-level solve holds) with its
-// item lists.  Re-planned by the autotuner.
+// level goes through the inverse panels (widest front at least big_ns /
+// big_ns_bwd padded pivots, or wider than the wave-level solve holds; only
+// levels that have inverse panels).  Re-planned by the autotuner.
 static void plan_solve(Level& L, int32_t big_ns, int32_t big_ns_bwd) {
+    L.big_ns = big_ns;
+    L.big_ns_bwd = big_ns_bwd;
+    for (TLev& T : L.tl) {
+        const bool wide = T.ns_pad_max > wsolve_max_ns();
+        T.big_fwd = T.q && (wide || T.ns_pad_max >= big_ns);
+        T.big_bwd = T.q && (wide || T.ns_pad_max >= big_ns_bwd);
+    }
+}
+
+// Tree levels, inverse-panel layout (q_base, qrow of every front, the
+// factorisation's row and update items per step, the solves' item lists) of
+// one level; df: the device front descriptors being built.
+static void setup_tree_levels(hsim_hierarchy* H, Level& L, std::vector<DFront>& df) {
     const Symbolic& sy = L.sy;
     const int32_t mc = std::max<int32_t>(1, sy.max_children);
     L.tl.assign(sy.tree_levels, TLev());
-    L.big_ns = big_ns;
-    L.big_ns_bwd = big_ns_bwd;
-    std::vector<int32_t> big;
+    int64_t qoff = 0;
+    std::vector<int32_t> qrow_it, qupd_it, qitems;
+    L.qrow_ptr.assign(1, 0);
+    L.qupd_ptr.assign(1, 0);
+    L.qrhs_rows = 0;
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
         TLev& T = L.tl[t];
         T.f0 = sy.tlev_ptr[t];
@@ -521,60 +483,78 @@ static void plan_solve(Level& L, int32_t big_ns, int32_t big_ns_bwd) {
             T.l_entries += (double)f.ns * (f.ns + 1) / 2 + (double)f.ns * f.mu;
             T.pivots += f.ns;
         }
-        const bool wide = T.ns_pad_max > wsolve_max_ns();
-        T.big_fwd = wide || T.ns_pad_max >= big_ns;
-        T.big_bwd = wide || T.ns_pad_max >= big_ns_bwd;
-        T.big = T.big_fwd || T.big_bwd;
-        if (T.big) {
-            // item lists of the multi-workgroup block solve
-            auto push = [&](int32_t a, int32_t b) { big.push_back(a); big.push_back(b); };
-            int32_t maxnsb = 0;
-            for (int32_t i = T.f0; i < T.f1; ++i) maxnsb = std::max(maxnsb, sy.fronts[i].nsb);
-            T.nblk = (maxnsb + BIG_BLOCK_TILES - 1) / BIG_BLOCK_TILES;
-            T.fwd_init[0] = (int64_t)big.size();
-            for (int32_t i = T.f0; i < T.f1; ++i) {
-                const Front& f = sy.fronts[i];
-                const int32_t st = (f.mu + NB - 1) / NB;
-                for (int32_t r = 0; r < f.nsb + st; ++r) push(i, r);
-            }
-            T.fwd_init[1] = ((int64_t)big.size() - T.fwd_init[0]) / 2;
-            T.bwd_init[0] = (int64_t)big.size();
-            for (int32_t i = T.f0; i < T.f1; ++i)
-                for (int32_t r = 0; r < sy.fronts[i].nsb; ++r) push(i, r);
-            T.bwd_init[1] = ((int64_t)big.size() - T.bwd_init[0]) / 2;
-            for (int32_t kb = 0; kb < T.nblk; ++kb) {
-                int64_t o = (int64_t)big.size();
-                for (int32_t i = T.f0; i < T.f1; ++i)
-                    if (sy.fronts[i].nsb > kb * BIG_BLOCK_TILES) big.push_back(i);
-                const int64_t cnt = (int64_t)big.size() - o;
-                T.fdiag.push_back(o); T.fdiag.push_back(cnt);
-                T.bdiag.push_back(o); T.bdiag.push_back(cnt);
-                o = (int64_t)big.size();
-                for (int32_t i = T.f0; i < T.f1; ++i) {
-                    const Front& f = sy.fronts[i];
-                    if (f.nsb <= kb * BIG_BLOCK_TILES) continue;
-                    const int32_t t1 = std::min(f.nsb, (kb + 1) * BIG_BLOCK_TILES);
-                    const int32_t st = (f.mu + NB - 1) / NB;
-                    for (int32_t r = t1; r < f.nsb + st; ++r) push(i, r);
-                }
-                T.fupd.push_back(o); T.fupd.push_back(((int64_t)big.size() - o) / 2);
-                o = (int64_t)big.size();
-                for (int32_t i = T.f0; i < T.f1; ++i) {
-                    const Front& f = sy.fronts[i];
-                    if (f.nsb <= kb * BIG_BLOCK_TILES) continue;
-                    for (int32_t r = 0; r < kb * BIG_BLOCK_TILES; ++r) push(i, r);
-                }
-                T.bupd.push_back(o); T.bupd.push_back(((int64_t)big.size() - o) / 2);
-            }
-        }
+        T.q = T.ns_pad_max >= QPANEL_MIN_NS || T.ns_pad_max > wsolve_max_ns();
         T.step0 = sy.step_ptr[t];
         T.step1 = sy.step_ptr[t + 1];
+        int64_t qrow = 0;
+        for (int32_t i = T.f0; i < T.f1; ++i) {
+            const Front& f = sy.fronts[i];
+            df[i].q_base = -1;
+            df[i].qrow = 0;
+            if (!T.q) continue;
+            df[i].q_base = qoff;
+            df[i].qrow = qrow;
+            qoff += ((int64_t)f.nsb * f.Mt - (int64_t)f.nsb * (f.nsb - 1) / 2) * NB * NB;
+            qrow += (int64_t)NB * f.Mt;
+        }
+        L.qrhs_rows = std::max(L.qrhs_rows, qrow);
+        // factorisation items of the inverse panels, per pivot tile step k
+        for (int32_t k = 0; k < T.step1 - T.step0; ++k) {
+            if (T.q)
+                for (int32_t i = T.f0; i < T.f1; ++i) {
+                    const Front& f = sy.fronts[i];
+                    if (f.nsb <= k) continue;
+                    for (int32_t j = 0; j <= k; ++j) {
+                        qrow_it.push_back(i);
+                        qrow_it.push_back(j);
+                    }
+                    for (int32_t I = k + 1; I < f.Mt; ++I)
+                        for (int32_t j = 0; j <= k; ++j) {
+                            qupd_it.push_back(i);
+                            qupd_it.push_back(I);
+                            qupd_it.push_back(j);
+                        }
+                }
+            L.qrow_ptr.push_back((int64_t)qrow_it.size() / 2);
+            L.qupd_ptr.push_back((int64_t)qupd_it.size() / 3);
+        }
+        if (T.q) {
+            auto push = [&](int32_t a, int32_t b) { qitems.push_back(a); qitems.push_back(b); };
+            T.q_gather[0] = (int64_t)qitems.size();
+            for (int32_t i = T.f0; i < T.f1; ++i)
+                for (int32_t r = 0; r < sy.fronts[i].Mt; ++r) push(i, r);
+            T.q_gather[1] = ((int64_t)qitems.size() - T.q_gather[0]) / 2;
+            T.q_fprod[0] = (int64_t)qitems.size();
+            for (int32_t i = T.f0; i < T.f1; ++i) {
+                const Front& f = sy.fronts[i];
+                for (int32_t o = 0; o < 2 * f.nsb; ++o)
+                    if (16 * o < f.ns) push(i, o);
+                for (int32_t o = 2 * f.nsb; o < 2 * f.Mt; ++o)
+                    if (16 * (o - 2 * f.nsb) < f.mu) push(i, o);
+            }
+            T.q_fprod[1] = ((int64_t)qitems.size() - T.q_fprod[0]) / 2;
+            T.q_bprod[0] = (int64_t)qitems.size();
+            for (int32_t i = T.f0; i < T.f1; ++i)
+                for (int32_t o = 0; 16 * o < sy.fronts[i].ns; ++o) push(i, o);
+            T.q_bprod[1] = ((int64_t)qitems.size() - T.q_bprod[0]) / 2;
+        }
         T.ea_tile_cols.assign(mc, 0);
         for (int32_t c = 0; c < mc; ++c)
             for (int64_t e = sy.ea_ptr[(int64_t)t * mc + c]; e < sy.ea_ptr[(int64_t)t * mc + c + 1]; ++e)
                 T.ea_tile_cols[c] = std::max<int32_t>(T.ea_tile_cols[c], (sy.fronts[sy.ea[e]].mu + NB - 1) / NB);
     }
-    L.big_items.upload(big.empty() ? std::vector<int32_t>{0, 0} : big);
+    if (L.qrow_ptr.size() != (size_t)sy.step_ptr[sy.tree_levels] + 1)
+        fail(HSIM_E_INVALID, "inverse-panel items: %zu steps for %d", L.qrow_ptr.size() - 1,
+             sy.step_ptr[sy.tree_levels]);
+    L.q_doubles = qoff;
+    L.it_qrow.upload(qrow_it.empty() ? std::vector<int32_t>{0, 0} : qrow_it);
+    L.it_qupd.upload(qupd_it.empty() ? std::vector<int32_t>{0, 0, 0} : qupd_it);
+    L.q_items.upload(qitems.empty() ? std::vector<int32_t>{0, 0} : qitems);
+    if (L.q_doubles > 0) {
+        L.qinvT.alloc((size_t)L.q_doubles * sizeof(double));
+        L.qinv.alloc((size_t)L.q_doubles * sizeof(double));
+        L.qrhs.alloc((size_t)L.qrhs_rows * H->ld * sizeof(double));
+    }
 }
 
 static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<int32_t>* coarse_iperm) {
@@ -667,6 +647,7 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
         const int64_t gb = f.gather_base, m = (int64_t)f.ns + f.mu;
         d.flags = sy.gather_ptr[gb + m] > sy.gather_ptr[gb] ? DFRONT_GATHER : 0;
     }
+    setup_tree_levels(H, L, df);
     L.dfronts.upload(df);
     L.tiles.alloc((size_t)sy.tile_doubles * sizeof(double));
     L.linv.alloc((size_t)sy.linv_doubles * sizeof(double));
@@ -713,6 +694,8 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
     double* tiles = dptr<double>(L.tiles);
     Prof& P = H->prof;
     const double lvflops = sy.flops / std::max(1, sy.tree_levels);
+    double* qT = L.q_doubles > 0 ? dptr<double>(L.qinvT) : nullptr;
+    if (qT) HIPCHECK(launch_fill(qT, L.q_doubles, 0.0, s));   // the update items accumulate
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
       P.run(HSIM_K_FACTOR, 8.0 * L.tl[t].l_entries, lvflops, s, [&] {
         const TLev& T = L.tl[t];
@@ -737,9 +720,13 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
                                      k, cnt, s));
             HIPCHECK(launch_fac_panel(tiles, dptr<double>(L.linv), dptr<double>(L.D), fr,
                                       dptr<int32_t>(L.it_panel) + 2 * sy.panel_ptr[st],
-                                      sy.panel_ptr[st + 1] - sy.panel_ptr[st], k, s));
+                                      sy.panel_ptr[st + 1] - sy.panel_ptr[st], k, s, qT,
+                                      dptr<int32_t>(L.it_qrow) + 2 * L.qrow_ptr[st],
+                                      L.qrow_ptr[st + 1] - L.qrow_ptr[st]));
             HIPCHECK(launch_fac_update(tiles, dptr<double>(L.D), fr, dptr<int32_t>(L.it_upd) + 3 * sy.upd_ptr[st],
-                                       sy.upd_ptr[st + 1] - sy.upd_ptr[st], k, s));
+                                       sy.upd_ptr[st + 1] - sy.upd_ptr[st], k, s, qT,
+                                       dptr<int32_t>(L.it_qupd) + 3 * L.qupd_ptr[st],
+                                       L.qupd_ptr[st + 1] - L.qupd_ptr[st]));
         }
       });
     }
@@ -757,6 +744,7 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
         HIPCHECK(launch_tile_transpose<double>(tiles, dptr<double>(L.tilesT), sy.tile_doubles / (NB * NB), s));
         HIPCHECK(launch_tile_transpose<double>(dptr<double>(L.linv), dptr<double>(L.linvT), sy.linv_doubles / (NB * NB),
                                                s));
+        if (qT) HIPCHECK(launch_tile_transpose<double>(qT, dptr<double>(L.qinv), L.q_doubles / (NB * NB), s));
     });
     if (mixed) {
         // FP32 copy of the FP64 factor for the low-precision solves
@@ -773,6 +761,12 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
                                                   sy.tile_doubles / (NB * NB), s));
             HIPCHECK(launch_tile_transpose<float>(dptr<float>(L.linv32), dptr<float>(L.linv32T),
                                                   sy.linv_doubles / (NB * NB), s));
+            if (L.q_doubles > 0) {
+                L.qinv32.alloc((size_t)L.q_doubles * sizeof(float));
+                L.qinv32T.alloc((size_t)L.q_doubles * sizeof(float));
+                HIPCHECK(launch_to_float(dptr<double>(L.qinv), dptr<float>(L.qinv32), L.q_doubles, s));
+                HIPCHECK(launch_to_float(dptr<double>(L.qinvT), dptr<float>(L.qinv32T), L.q_doubles, s));
+            }
         });
         L.factored32 = true;
     }
@@ -782,20 +776,19 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
 // fp32: with the FP32 copy of the factor (FP32 arithmetic, FP64 in and out)
 template <class TF>
 static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
-                         const TF* linvT, double* X, int32_t col0, int32_t ncols, const double* md, hipStream_t s,
-                         const double* Xin = nullptr) {
+                         const TF* linvT, const TF* qinv, const TF* qinvT, double* X, int32_t col0, int32_t ncols,
+                         const double* md, hipStream_t s, const double* Xin = nullptr) {
     const Symbolic& sy = L.sy;
     const DFront* fr = dptr<DFront>(L.dfronts);
     Prof& P = H->prof;
     const double bL = sizeof(TF);
-    const int32_t* bi = dptr<int32_t>(L.big_items);
+    const int32_t* qi = dptr<int32_t>(L.q_items);
     P.solves += 1;
     P.solve_cols += ncols;
-    auto big = [&](int phase, const int64_t* rec, int32_t kb) {
-        HIPCHECK(launch_big_solve<TF>(phase, tiles, linv, D, tilesT, linvT, fr, bi + rec[0], rec[1], kb, X, H->ld,
-                                      col0, ncols,
-                                      dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
-                                      dptr<int32_t>(L.rows), s, Xin));
+    auto qsolve = [&](int phase, const int64_t* rec) {
+        HIPCHECK(launch_qsolve<TF>(phase, qinv, qinvT, D, fr, qi + rec[0], rec[1], dptr<double>(L.qrhs), H->ld, X,
+                                   H->ld, col0, ncols, dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
+                                   dptr<int32_t>(L.rows), s, Xin));
     };
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
         const TLev& T = L.tl[t];
@@ -803,11 +796,8 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
         if (T.big_fwd) {
             P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
-                big(0, T.fwd_init, 0);
-                for (int32_t kb = 0; kb < T.nblk; ++kb) {
-                    big(1, &T.fdiag[2 * kb], kb);
-                    big(2, &T.fupd[2 * kb], kb);
-                }
+                qsolve(0, T.q_gather);
+                qsolve(1, T.q_fprod);
             });
             continue;
         }
@@ -823,11 +813,8 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
         if (T.big_bwd) {
             P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
-                big(3, T.bwd_init, 0);
-                for (int32_t kb = T.nblk - 1; kb >= 0; --kb) {
-                    big(4, &T.bdiag[2 * kb], kb);
-                    big(5, &T.bupd[2 * kb], kb);
-                }
+                qsolve(2, T.q_gather);
+                qsolve(3, T.q_bprod);
             });
             continue;
         }
@@ -846,10 +833,12 @@ static void solve_level(hsim_hierarchy* H, Level& L, double* X, int32_t col0, in
     if (fp32) {
         if (!L.factored32) fail(HSIM_E_STATE, "no FP32 factor on level %d", L.tau);
         solve_sweeps<float>(H, L, dptr<float>(L.tiles32), dptr<float>(L.linv32), dptr<float>(L.D32),
-                            dptr<float>(L.tiles32T), dptr<float>(L.linv32T), X, col0, ncols, md, s, Xin);
+                            dptr<float>(L.tiles32T), dptr<float>(L.linv32T), dptr<float>(L.qinv32),
+                            dptr<float>(L.qinv32T), X, col0, ncols, md, s, Xin);
     } else {
         solve_sweeps<double>(H, L, dptr<double>(L.tiles), dptr<double>(L.linv), dptr<double>(L.D),
-                             dptr<double>(L.tilesT), dptr<double>(L.linvT), X, col0, ncols, md, s, Xin);
+                             dptr<double>(L.tilesT), dptr<double>(L.linvT), dptr<double>(L.qinv),
+                             dptr<double>(L.qinvT), X, col0, ncols, md, s, Xin);
     }
 }
 
@@ -1318,6 +1307,8 @@ hsim_status hsim_level_info(const hsim_hierarchy* h, int32_t level, hsim_level_d
     info->rho = L.rho;
     info->factor_flops = L.coarsest ? 0 : L.sy.flops;
     info->factor_nnz = L.coarsest ? 0 : L.sy.factor_nnz;
+    for (const TLev& T : L.tl) info->qpanel_tree_levels += T.q ? 1 : 0;
+    info->qpanel_entries = L.q_doubles;
     API_END
 }
 
@@ -1807,10 +1798,10 @@ hsim_status hsim_solve_batch(hsim_hierarchy* const* hs, int32_t count, const hsi
 
 // ------------------------------------------------------------- autotuning
 // Candidate launch plans of the block solves: the widest-front thresholds
-// (padded pivots) from which a tree level's forward / backward sweep uses the
-// multi-workgroup block solve instead of the wave-level one.
+// (padded pivots) from which a tree level's forward / backward sweep
+// multiplies by the inverse panels instead of running the wave-level solve.
 static const int32_t kTuneFwd[] = {128, 256, 512};
-static const int32_t kTuneBwd[] = {64, 128, 256};
+static const int32_t kTuneBwd[] = {128, 256, 512};
 static std::mutex g_tune_mu;
 
 static std::string tune_key(const hsim_hierarchy* h, const Level& L) {
@@ -1821,7 +1812,7 @@ static std::string tune_key(const hsim_hierarchy* h, const Level& L) {
     int64_t n = L.n, sc = 0;
     while (n >= 4) { n >>= 1; ++sc; }
     char buf[160];
-    std::snprintf(buf, sizeof buf, "solve-plan q=%d tree=%d top=%d size=%lld.%lld", h->q, (int)L.tl.size(), top,
+    std::snprintf(buf, sizeof buf, "qpanel-plan q=%d tree=%d top=%d size=%lld.%lld", h->q, (int)L.tl.size(), top,
                   (long long)sc, (long long)n);
     return buf;
 }

@@ -11,8 +11,11 @@ namespace hsim {
 // Device copy of a front's geometry (see Front in internal.h).
 // DFront::flags bit: some row of the front gathers children's update rows
 constexpr int32_t DFRONT_GATHER = 1;
+// q_base: offset of the front's inverse-panel tiles (qinv / qinvT), -1 if it
+// has none; qrow: first row of the front in the scratch block of the
+// inverse-panel solves of its tree level.
 struct DFront {
-    int64_t start, tile_base, linv_base, d_base, ubuf_row, gather_base, rows_off;
+    int64_t start, tile_base, linv_base, d_base, ubuf_row, gather_base, rows_off, q_base, qrow;
     int32_t ns, mu, ns_pad, mu_pad, Mt, nsb, parent, flags;   // flags: DFRONT_GATHER
 };
 
@@ -48,27 +51,18 @@ hipError_t launch_extend_add(double* tiles, const DFront* fronts, const int32_t*
                              const int32_t* rel, int32_t max_tile_cols, hipStream_t s);
 hipError_t launch_fac_diag(double* tiles, double* linv, double* D, const DFront* fronts, const int32_t* items,
                            int64_t nitems, int32_t k, int32_t* counters, hipStream_t s);
+// panel / update launches of pivot tile step k; with qT, the same launches
+// also run the row items (front, j) / update items (front, I, j) of the
+// inverse panels (qT: transposed tiles of Q = [L11^-1; -L21 L11^-1] at each
+// front's q_base, zero before step 0)
 hipError_t launch_fac_panel(double* tiles, const double* linv, const double* D, const DFront* fronts,
-                            const int32_t* items, int64_t nitems, int32_t k, hipStream_t s);
+                            const int32_t* items, int64_t nitems, int32_t k, hipStream_t s, double* qT = nullptr,
+                            const int32_t* qitems = nullptr, int64_t nq = 0);
 hipError_t launch_fac_update(double* tiles, const double* D, const DFront* fronts, const int32_t* items,
-                             int64_t nitems, int32_t k, hipStream_t s);
+                             int64_t nitems, int32_t k, hipStream_t s, double* qT = nullptr,
+                             const int32_t* qitems = nullptr, int64_t nq = 0);
 
 // ------------------------------------------------------------ block solves
-// widest supported column chunk (8..160) whose LDS footprint fits a workgroup
-// for fronts of ns_pad_max pivots; 0 if none fits
-int32_t solve_chunk_width(int32_t ns_pad_max, int32_t ncols, bool fp32);
-// Forward L^-1 (and optional diagonal pre-scaling by mdiag) over the fronts
-// [f0, f1) of one tree level, columns [col0, col0 + ncols) in chunks of qc.
-template <class TF>
-hipError_t launch_solve_fwd(const TF* tiles, const TF* linv, const DFront* fronts, int32_t f0, int32_t f1,
-                            int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols, int32_t qc,
-                            double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx,
-                            const double* mdiag, hipStream_t s);
-template <class TF>
-hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
-                            int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
-                            int32_t qc, const int32_t* rows, bool apply_dinv, hipStream_t s);
-
 // Wave-level matrix-core solves of one tree level (fronts [f0, f1), pivot
 // counts up to wsolve_max_ns()): one wave per (front, 16 columns), the
 // front's block of the right-hand side in registers.  fwd: forward sweep
@@ -88,22 +82,20 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
                          double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw, const double* mdiag,
                          const int32_t* rows, bool apply_dinv, hipStream_t s, const double* Xin = nullptr);
 
-// Block solves of tree levels with wide supernodes, 128-row pivot blocks:
-// phase 0 forward init (items: front, tile row), 1 forward diagonal block kb
-// (items: front), 2 forward update below block kb (items: front, tile row),
-// 3 backward init with the struct rows (items: front, pivot tile), 4 backward
-// diagonal block kb (items: front), 5 backward update before block kb
-// (items: front, pivot tile).  Phase 0 in column chunks of 32; the others
-// on the matrix cores, one wave per (item, 16 columns); the backward phases
-// read the tile-transposed copies tilesT, linvT.  Xin (phase 0 only, null:
-// X): where the right-hand-side rows are read.
-constexpr int BIG_BLOCK_TILES = 4;
+// Block solves through the inverse panels (fronts with q_base >= 0):
+// phase 0 forward gather (items: front, 32-row tile of [0, Mt)): right-hand
+// side of the pivots (Xin times mdiag plus the children's updates) into the
+// scratch block R, children's updates of the struct rows into the front's
+// update rows; 1 forward product (items: front, 16-row tile of [0, 2 Mt)):
+// pivot rows of X = Q_piv R, update rows += Q_struct R; 2 backward gather
+// (items as phase 0): R = [D^-1 X(pivots); X(struct rows)]; 3 backward
+// product (items: front, 16-row tile of the pivots): X(pivots) = Q^T R.
+// qinv: column-major Q tiles (phase 1), qinvT: transposed tiles (phase 3).
 template <class TF>
-hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
-                            const TF* linvT, const DFront* fronts, const int32_t* items, int64_t nitems, int32_t kb,
-                            double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf, int64_t ldu,
-                            const int32_t* gat, int32_t gw, const double* mdiag, const int32_t* rows,
-                            hipStream_t s, const double* Xin = nullptr);
+hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D, const DFront* fronts,
+                         const int32_t* items, int64_t nitems, double* R, int64_t ldr, double* X, int64_t ldx,
+                         int32_t col0, int32_t ncols, double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw,
+                         const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin = nullptr);
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 // partial Grams over row chunks of chunk_rows rows (gram_chunk_rows of the
@@ -141,9 +133,11 @@ hipError_t launch_assemble_mesh(const double* V, const int32_t* F, int64_t nf, i
                                 const int64_t* dcorner, const int64_t* vptr, const int32_t* vtri,
                                 const double* density, double* w, double* a3, double* sval, double* mdiag,
                                 hipStream_t s);
-// descriptor, factorisation work lists and zero gather pointers of a dense k x k problem as one front
+// descriptor, factorisation and inverse-panel work lists, product items and
+// zero gather pointers of a dense k x k problem as one front
 hipError_t launch_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t Mt, int32_t* diag, int32_t* panel,
-                              int32_t* upd, int64_t* gptr, hipStream_t s);
+                              int32_t* upd, int32_t* qrow, int32_t* qupd, int32_t* prod, int64_t* gptr,
+                              hipStream_t s);
 hipError_t launch_dense_to_front(const double* A, int32_t k, double* tiles, int32_t Mt, hipStream_t s);
 // B = A^T (k x k, row-major, ld = k)
 hipError_t launch_transpose(const double* A, int32_t k, double* B, hipStream_t s);

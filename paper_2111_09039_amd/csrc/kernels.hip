@@ -368,11 +368,78 @@ hipError_t launch_fac_diag(double* tiles, double* linv, double* D, const DFront*
 // of the result and computes its transpose (16x16x4 operands: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16], result item v of lane l is
 // D[l / 16 + 4 v][l % 16]), so that every operand load and every store of
-// the column-major tiles reads or writes 16 consecutive doubles.
-// L_Ik = A_Ik L_kk^-T D_k^-1, in place
+// the column-major tiles reads or writes 16 consecutive doubles.  In that
+// form a wave computes Z(r, c) = sum_j Y(r, j) X(c, j), i.e. Z = Y X^T, for
+// column-major tiles X (A operand), Y (B operand) and Z.
+//
+// Inverse panels.  For the fronts of the tree levels with wide supernodes
+// (and for the dense problems) the factorisation also forms Q, the pivot
+// columns of E^-1 where E = [L11 0; L21 I] is the unit lower factor of the
+// front extended by the identity on its struct rows: Q = [L11^-1; -L21 L11^-1].
+// A front's forward solve step is then one product, [y; u - g] = Q b', and its
+// backward step another, x = Q^T [D^-1 y; x_struct] (see the solves below).
+// E^-1 = E_{nsb-1}^-1 ... E_0^-1 with E_k the identity plus pivot tile column
+// k of E.  Applying E_k^-1 from the left replaces tile row k of the product so
+// far by Linv_k times itself and subtracts L(I, k) times the new row from every
+// tile row I > k; row k has non-zero tiles in the columns j <= k only (tile
+// (k, k) starts as the identity).  So the panel launch of step k also forms
+// tile row k of Q (row items (front, j), j <= k: they need Linv_k) and the
+// update launch the subtractions (items (front, I, j), I > k, j <= k: they need
+// L(I, k) and the new row k).  Tiles are written transposed, qT tile (I, J)
+// = Q(I, J)^T column-major: then both steps are the coalesced Z (+)= Y X^T.
+namespace {
+// tile row k of Q: Q(k, j) <- Linv_k Q(k, j) (j < k), Q(k, k) = Linv_k; in
+// transposed tiles Z <- Z Linv_k^T, resp. Z = Linv_k^T
+__device__ __forceinline__ void q_row_item(double* __restrict__ qT, const double* __restrict__ linv, const DFront& f,
+                                           int32_t j, int32_t k) {
+    double* Z = qT + f.q_base + tri(f.Mt, k, j) * TT;
+    const double* Li = linv + f.linv_base + (int64_t)k * TT;
+    if (j == k) {
+        for (int e = threadIdx.x; e < TT; e += 256) Z[e] = Li[(e % T32) * T32 + e / T32];
+        return;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int rb = 16 * (w >> 1), cb = 16 * (w & 1);
+    dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < T32; k0 += 4) {
+        const int jj = k0 + lk;
+        acc = mfma4(Li[jj * T32 + cb + li], Z[jj * T32 + rb + li], acc);
+    }
+    __syncthreads();   // every wave has read its operands before the tile is overwritten
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Z[(cb + lk + 4 * v) * T32 + rb + li] = acc[v];
+}
+// Q(I, j) -= L(I, k) Q(k, j); transposed: Z_Ij -= Z_kj L(I, k)^T
+__device__ __forceinline__ void q_update_item(double* __restrict__ qT, const double* __restrict__ tiles,
+                                              const DFront& f, int32_t I, int32_t j, int32_t k) {
+    const double* X = tiles + f.tile_base + tri(f.Mt, I, k) * TT;
+    const double* Y = qT + f.q_base + tri(f.Mt, k, j) * TT;
+    double* Z = qT + f.q_base + tri(f.Mt, I, j) * TT;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int rb = 16 * (w >> 1), cb = 16 * (w & 1);
+    dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < T32; k0 += 4) {
+        const int jj = k0 + lk;
+        acc = mfma4(X[jj * T32 + cb + li], Y[jj * T32 + rb + li], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Z[(cb + lk + 4 * v) * T32 + rb + li] -= acc[v];
+}
+}  // namespace
+
+// L_Ik = A_Ik L_kk^-T D_k^-1, in place (workgroups [0, nitems)); then the
+// row items (front, j) of the inverse panels (workgroups from nitems on)
 __global__ __launch_bounds__(256) void k_fac_panel(double* tiles, const double* __restrict__ linv,
                                                    const double* __restrict__ D, const DFront* __restrict__ fr,
-                                                   const int32_t* __restrict__ items, int32_t k) {
+                                                   const int32_t* __restrict__ items, int32_t nitems, int32_t k,
+                                                   double* qT, const int32_t* __restrict__ qitems) {
+    if ((int32_t)blockIdx.x >= nitems) {
+        const int32_t q = (int32_t)blockIdx.x - nitems;
+        q_row_item(qT, linv, fr[qitems[2 * q]], qitems[2 * q + 1], k);
+        return;
+    }
     const DFront f = fr[items[2 * blockIdx.x]];
     const int32_t I = items[2 * blockIdx.x + 1];
     double* A = tiles + f.tile_base + tri(f.Mt, I, k) * TT;
@@ -394,16 +461,25 @@ __global__ __launch_bounds__(256) void k_fac_panel(double* tiles, const double* 
     }
 }
 hipError_t launch_fac_panel(double* tiles, const double* linv, const double* D, const DFront* fronts,
-                            const int32_t* items, int64_t nitems, int32_t k, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    k_fac_panel<<<(unsigned)nitems, 256, 0, s>>>(tiles, linv, D, fronts, items, k);
+                            const int32_t* items, int64_t nitems, int32_t k, hipStream_t s, double* qT,
+                            const int32_t* qitems, int64_t nq) {
+    if (!qT) nq = 0;
+    if (nitems + nq <= 0) return hipSuccess;
+    k_fac_panel<<<(unsigned)(nitems + nq), 256, 0, s>>>(tiles, linv, D, fronts, items, (int32_t)nitems, k, qT, qitems);
     return hipGetLastError();
 }
 
-// A_IJ -= L_Ik D_k L_Jk^T
+// A_IJ -= L_Ik D_k L_Jk^T (workgroups [0, nitems)); then the update items
+// (front, I, j) of the inverse panels
 __global__ __launch_bounds__(256) void k_fac_update(double* tiles, const double* __restrict__ D,
                                                     const DFront* __restrict__ fr, const int32_t* __restrict__ items,
-                                                    int32_t k) {
+                                                    int32_t nitems, int32_t k, double* qT,
+                                                    const int32_t* __restrict__ qitems) {
+    if ((int32_t)blockIdx.x >= nitems) {
+        const int32_t q = (int32_t)blockIdx.x - nitems;
+        q_update_item(qT, tiles, fr[qitems[3 * q]], qitems[3 * q + 1], qitems[3 * q + 2], k);
+        return;
+    }
     const DFront f = fr[items[3 * blockIdx.x]];
     const int32_t I = items[3 * blockIdx.x + 1], J = items[3 * blockIdx.x + 2];
     const double* LI = tiles + f.tile_base + tri(f.Mt, I, k) * TT;
@@ -426,226 +502,11 @@ __global__ __launch_bounds__(256) void k_fac_update(double* tiles, const double*
     }
 }
 hipError_t launch_fac_update(double* tiles, const double* D, const DFront* fronts, const int32_t* items,
-                             int64_t nitems, int32_t k, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    k_fac_update<<<(unsigned)nitems, 256, 0, s>>>(tiles, D, fronts, items, k);
+                             int64_t nitems, int32_t k, hipStream_t s, double* qT, const int32_t* qitems, int64_t nq) {
+    if (!qT) nq = 0;
+    if (nitems + nq <= 0) return hipSuccess;
+    k_fac_update<<<(unsigned)(nitems + nq), 256, 0, s>>>(tiles, D, fronts, items, (int32_t)nitems, k, qT, qitems);
     return hipGetLastError();
-}
-
-// ============================================================ block solves
-// One workgroup per (front, chunk of QC right-hand-side columns) of a tree
-// level.  The front's pivot rows of the block live in LDS; every 32 x 32
-// factor tile is staged in LDS once and applied to all QC columns by a
-// register-blocked micro-kernel: out[row][col] += sum_k A[k][row] * B[k][col].
-namespace {
-template <int QC>
-struct SolveMap {
-    static constexpr int RR = QC >= 32 ? 4 : (QC == 16 ? 2 : 1);   // rows per thread
-    static constexpr int RL = 32 / RR;                              // row lanes
-    static constexpr int CL = 256 / RL;                             // column lanes
-    static constexpr int CC = QC / CL > 0 ? QC / CL : 1;            // columns per thread
-    static_assert(RR * CC * 256 == 32 * QC, "thread map must cover a 32 x QC block");
-};
-constexpr int TS = T32 + 1;   // LDS stride of a staged tile (no bank conflicts on transposed stores)
-
-// stage a 32 x 32 column-major tile into As[k * TS + row] as A(row, k) (trans = false)
-// or A(k, row) (trans = true)
-template <class T>
-__device__ __forceinline__ void stage_tile(T* As, const T* __restrict__ tile, bool trans) {
-    for (int idx = threadIdx.x; idx < TT; idx += 256) {
-        const int a = idx & 31, b = idx >> 5;    // tile element (row a, col b)
-        if (!trans) As[b * TS + a] = tile[idx];  // A(row = a, k = b)
-        else As[a * TS + b] = tile[idx];         // A(row = b, k = a)
-    }
-}
-
-// acc[i][j] += sum_k As[k * TS + row_i] * B[(k) * ldb + col_j]
-template <class T, int QC>
-__device__ __forceinline__ void micro(T (&acc)[SolveMap<QC>::RR][SolveMap<QC>::CC], const T* As, const T* B) {
-    using M = SolveMap<QC>;
-    const int rl = threadIdx.x % M::RL, cl = threadIdx.x / M::RL;
-#pragma unroll 4
-    for (int k = 0; k < T32; ++k) {
-        T a[M::RR], b[M::CC];
-#pragma unroll
-        for (int i = 0; i < M::RR; ++i) a[i] = As[k * TS + rl + M::RL * i];
-#pragma unroll
-        for (int j = 0; j < M::CC; ++j) b[j] = B[k * QC + cl + M::CL * j];
-#pragma unroll
-        for (int i = 0; i < M::RR; ++i)
-#pragma unroll
-            for (int j = 0; j < M::CC; ++j) acc[i][j] += a[i] * b[j];
-    }
-}
-}  // namespace
-
-// Forward sweep over one tree level: y = L11^-1 (b_J + children's updates)
-// and u_J = (children's updates for the struct rows) - L21 y.
-template <class T, int QC>
-__global__ __launch_bounds__(256) void k_solve_fwd(const T* __restrict__ tiles, const T* __restrict__ linv,
-                                                   const DFront* __restrict__ fr, int32_t f0, int32_t nchunks,
-                                                   double* X, int64_t ldx, int32_t col0, int32_t ncols, T* ubuf,
-                                                   int64_t ldu, const int64_t* __restrict__ gptr,
-                                                   const int64_t* __restrict__ gidx, const double* __restrict__ mdiag) {
-    using M = SolveMap<QC>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* As = reinterpret_cast<T*>(smem_raw);   // 32 x TS staged tile
-    T* y = As + T32 * TS;                     // ns_pad x QC
-    const DFront f = fr[f0 + blockIdx.x / nchunks];
-    const int32_t c0 = col0 + (blockIdx.x % nchunks) * QC;
-    const int32_t cw = min(QC, col0 + ncols - c0);
-    const int tid = threadIdx.x;
-    const int rl = tid % M::RL, cl = tid / M::RL;
-    // 1. pivot rows of the right-hand side plus the children's updates
-    for (int idx = tid; idx < f.ns_pad * QC; idx += 256) {
-        const int r = idx / QC, c = idx % QC;
-        double v = 0.0;
-        if (r < f.ns && c < cw) {
-            v = X[(f.start + r) * ldx + c0 + c];
-            if (mdiag) v *= mdiag[f.start + r];
-            for (int64_t g = gptr[f.gather_base + r]; g < gptr[f.gather_base + r + 1]; ++g)
-                v += (double)ubuf[gidx[g] * ldu + c0 + c];
-        }
-        y[idx] = (T)v;
-    }
-    // 2. blocked forward substitution with the unit lower L11
-    for (int kb = 0; kb < f.nsb; ++kb) {
-        T* ykb = y + kb * T32 * QC;
-        __syncthreads();
-        stage_tile(As, linv + f.linv_base + (int64_t)kb * TT, false);
-        __syncthreads();
-        T acc[M::RR][M::CC] = {};
-        micro<T, QC>(acc, As, ykb);
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < M::RR; ++i)
-#pragma unroll
-            for (int j = 0; j < M::CC; ++j) ykb[(rl + M::RL * i) * QC + cl + M::CL * j] = acc[i][j];
-        for (int ib = kb + 1; ib < f.nsb; ++ib) {
-            __syncthreads();
-            stage_tile(As, tiles + f.tile_base + tri(f.Mt, ib, kb) * TT, false);
-            __syncthreads();
-            T a2[M::RR][M::CC] = {};
-            micro<T, QC>(a2, As, ykb);
-            T* yib = y + ib * T32 * QC;
-#pragma unroll
-            for (int i = 0; i < M::RR; ++i)
-#pragma unroll
-                for (int j = 0; j < M::CC; ++j) yib[(rl + M::RL * i) * QC + cl + M::CL * j] -= a2[i][j];
-        }
-    }
-    __syncthreads();
-    // 3. pivot rows out
-    for (int idx = tid; idx < f.ns * QC; idx += 256) {
-        const int r = idx / QC, c = idx % QC;
-        if (c < cw) X[(f.start + r) * ldx + c0 + c] = (double)y[idx];
-    }
-    // 4. update rows: u = gathered - L21 y, one 32-row tile at a time
-    const int stiles = (f.mu + T32 - 1) / T32;
-    for (int st = 0; st < stiles; ++st) {
-        T acc[M::RR][M::CC] = {};
-        for (int kb = 0; kb < f.nsb; ++kb) {
-            __syncthreads();
-            stage_tile(As, tiles + f.tile_base + tri(f.Mt, f.nsb + st, kb) * TT, false);
-            __syncthreads();
-            micro<T, QC>(acc, As, y + kb * T32 * QC);
-        }
-#pragma unroll
-        for (int i = 0; i < M::RR; ++i) {
-            const int s = st * T32 + rl + M::RL * i;
-            if (s >= f.mu) continue;
-            const int64_t gr = f.gather_base + f.ns + s;
-            const int64_t g0 = gptr[gr], g1 = gptr[gr + 1];
-#pragma unroll
-            for (int j = 0; j < M::CC; ++j) {
-                const int c = cl + M::CL * j;
-                if (c >= cw) continue;
-                double v = 0.0;
-                for (int64_t g = g0; g < g1; ++g) v += (double)ubuf[gidx[g] * ldu + c0 + c];
-                ubuf[(f.ubuf_row + s) * ldu + c0 + c] = (T)(v - (double)acc[i][j]);
-            }
-        }
-    }
-}
-
-// Backward sweep over one tree level: z = D^-1 y - L21^T x_struct, then
-// x_J = L11^-T z (right-looking over the pivot tiles, last tile first).
-template <class T, int QC>
-__global__ __launch_bounds__(256) void k_solve_bwd(const T* __restrict__ tiles, const T* __restrict__ linv,
-                                                   const T* __restrict__ D, const DFront* __restrict__ fr, int32_t f0,
-                                                   int32_t nchunks, double* X, int64_t ldx, int32_t col0,
-                                                   int32_t ncols, const int32_t* __restrict__ rows, int apply_dinv) {
-    using M = SolveMap<QC>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* As = reinterpret_cast<T*>(smem_raw);   // 32 x TS staged tile
-    T* xs = As + T32 * TS;                    // 32 x QC struct-row solution values
-    T* z = xs + T32 * QC;                     // ns_pad x QC
-    const DFront f = fr[f0 + blockIdx.x / nchunks];
-    const int32_t c0 = col0 + (blockIdx.x % nchunks) * QC;
-    const int32_t cw = min(QC, col0 + ncols - c0);
-    const int tid = threadIdx.x;
-    const int rl = tid % M::RL, cl = tid / M::RL;
-    for (int idx = tid; idx < f.ns_pad * QC; idx += 256) {
-        const int r = idx / QC, c = idx % QC;
-        double v = 0.0;
-        if (r < f.ns && c < cw) {
-            v = X[(f.start + r) * ldx + c0 + c];
-            if (apply_dinv) v /= (double)D[f.d_base + r];
-        }
-        z[idx] = (T)v;
-    }
-    const int32_t* frows = rows + f.rows_off;
-    const int stiles = (f.mu + T32 - 1) / T32;
-    for (int st = 0; st < stiles; ++st) {
-        __syncthreads();
-        for (int idx = tid; idx < T32 * QC; idx += 256) {
-            const int s = idx / QC, c = idx % QC;
-            const int sr = st * T32 + s;
-            xs[idx] = (sr < f.mu && c < cw) ? (T)X[(int64_t)frows[sr] * ldx + c0 + c] : (T)0;
-        }
-        for (int jb = 0; jb < f.nsb; ++jb) {
-            __syncthreads();
-            stage_tile(As, tiles + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT, true);
-            __syncthreads();
-            T acc[M::RR][M::CC] = {};
-            micro<T, QC>(acc, As, xs);
-            T* zjb = z + jb * T32 * QC;
-#pragma unroll
-            for (int i = 0; i < M::RR; ++i)
-#pragma unroll
-                for (int j = 0; j < M::CC; ++j) zjb[(rl + M::RL * i) * QC + cl + M::CL * j] -= acc[i][j];
-        }
-    }
-    for (int kb = f.nsb - 1; kb >= 0; --kb) {
-        T* zkb = z + kb * T32 * QC;
-        __syncthreads();
-        stage_tile(As, linv + f.linv_base + (int64_t)kb * TT, true);
-        __syncthreads();
-        T acc[M::RR][M::CC] = {};
-        micro<T, QC>(acc, As, zkb);
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < M::RR; ++i)
-#pragma unroll
-            for (int j = 0; j < M::CC; ++j) zkb[(rl + M::RL * i) * QC + cl + M::CL * j] = acc[i][j];
-        for (int ib = 0; ib < kb; ++ib) {
-            __syncthreads();
-            stage_tile(As, tiles + f.tile_base + tri(f.Mt, kb, ib) * TT, true);
-            __syncthreads();
-            T a2[M::RR][M::CC] = {};
-            micro<T, QC>(a2, As, zkb);
-            T* zib = z + ib * T32 * QC;
-#pragma unroll
-            for (int i = 0; i < M::RR; ++i)
-#pragma unroll
-                for (int j = 0; j < M::CC; ++j) zib[(rl + M::RL * i) * QC + cl + M::CL * j] -= a2[i][j];
-        }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < f.ns * QC; idx += 256) {
-        const int r = idx / QC, c = idx % QC;
-        if (c < cw) X[(f.start + r) * ldx + c0 + c] = (double)z[idx];
-    }
 }
 
 // ------------------------------------------------------------ wave-level solves
@@ -1144,494 +1005,228 @@ template hipError_t launch_wsolve<float>(bool, const float*, const float*, const
                                          const int32_t*, int32_t, const double*, const int32_t*, bool, hipStream_t,
                                          const double*);
 
-namespace {
-template <class T>
-size_t fwd_lds(int32_t ns_pad, int qc) { return ((size_t)T32 * TS + (size_t)ns_pad * qc) * sizeof(T); }
-template <class T>
-size_t bwd_lds(int32_t ns_pad, int qc) { return ((size_t)T32 * TS + (size_t)T32 * qc + (size_t)ns_pad * qc) * sizeof(T); }
-}  // namespace
-
-int32_t solve_chunk_width(int32_t ns_pad_max, int32_t ncols, bool fp32) {
-    static const int opts[] = {160, 128, 96, 64, 32, 16, 8};
-    static const int cap = [] {
-        const char* e = getenv("HSIM_SOLVE_QC_MAX");   // tuning cap on the column chunk
-        return e ? atoi(e) : 160;
-    }();
-    for (int qc : opts) {
-        if (qc > cap && qc > 8) continue;
-        if (qc > 32 && qc >= ncols + 32) continue;   // narrower chunk covers all columns
-        const size_t b = fp32 ? bwd_lds<float>(ns_pad_max, qc) : bwd_lds<double>(ns_pad_max, qc);
-        if (b <= LDS_PER_WG) return qc;
-    }
-    return 0;
-}
-
-template <class TF, int QC>
-static hipError_t fwd_qc(const TF* tiles, const TF* linv, const DFront* fronts, int32_t f0, int32_t f1,
-                         int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf,
-                         int64_t ldu, const int64_t* gptr, const int64_t* gidx, const double* mdiag, hipStream_t s) {
-    const int32_t nchunks = (int32_t)cdiv(ncols, QC);
-    const size_t lds = fwd_lds<TF>(ns_pad_max, QC);
-    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_solve_fwd<TF, QC>), lds, 0);
-    if (e != hipSuccess) return e;
-    k_solve_fwd<TF, QC><<<(unsigned)((f1 - f0) * nchunks), 256, lds, s>>>(
-        tiles, linv, fronts, f0, nchunks, X, ldx, col0, ncols, reinterpret_cast<TF*>(ubuf), ldu, gptr, gidx, mdiag);
-    return hipGetLastError();
-}
-template <class TF, int QC>
-static hipError_t bwd_qc(const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0, int32_t f1,
-                         int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols, const int32_t* rows,
-                         bool apply_dinv, hipStream_t s) {
-    const int32_t nchunks = (int32_t)cdiv(ncols, QC);
-    const size_t lds = bwd_lds<TF>(ns_pad_max, QC);
-    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_solve_bwd<TF, QC>), lds, 0);
-    if (e != hipSuccess) return e;
-    k_solve_bwd<TF, QC><<<(unsigned)((f1 - f0) * nchunks), 256, lds, s>>>(tiles, linv, D, fronts, f0, nchunks, X, ldx,
-                                                                           col0, ncols, rows, apply_dinv ? 1 : 0);
-    return hipGetLastError();
-}
-
-template <class TF>
-hipError_t launch_solve_fwd(const TF* tiles, const TF* linv, const DFront* fronts, int32_t f0, int32_t f1,
-                            int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols, int32_t qc,
-                            double* ubuf, int64_t ldu, const int64_t* gptr, const int64_t* gidx, const double* mdiag,
-                            hipStream_t s) {
-    if (f1 <= f0 || ncols <= 0) return hipSuccess;
-    switch (qc) {
-#define HSIM_FWD(Q) \
-    case Q: return fwd_qc<TF, Q>(tiles, linv, fronts, f0, f1, ns_pad_max, X, ldx, col0, ncols, ubuf, ldu, gptr, gidx, mdiag, s);
-        HSIM_FWD(8) HSIM_FWD(16) HSIM_FWD(32) HSIM_FWD(64) HSIM_FWD(96) HSIM_FWD(128) HSIM_FWD(160)
-#undef HSIM_FWD
-        default: return hipErrorInvalidValue;
-    }
-}
-template <class TF>
-hipError_t launch_solve_bwd(const TF* tiles, const TF* linv, const TF* D, const DFront* fronts, int32_t f0,
-                            int32_t f1, int32_t ns_pad_max, double* X, int64_t ldx, int32_t col0, int32_t ncols,
-                            int32_t qc, const int32_t* rows, bool apply_dinv, hipStream_t s) {
-    if (f1 <= f0 || ncols <= 0) return hipSuccess;
-    switch (qc) {
-#define HSIM_BWD(Q) \
-    case Q: return bwd_qc<TF, Q>(tiles, linv, D, fronts, f0, f1, ns_pad_max, X, ldx, col0, ncols, rows, apply_dinv, s);
-        HSIM_BWD(8) HSIM_BWD(16) HSIM_BWD(32) HSIM_BWD(64) HSIM_BWD(96) HSIM_BWD(128) HSIM_BWD(160)
-#undef HSIM_BWD
-        default: return hipErrorInvalidValue;
-    }
-}
-template hipError_t launch_solve_fwd<double>(const double*, const double*, const DFront*, int32_t, int32_t, int32_t,
-                                             double*, int64_t, int32_t, int32_t, int32_t, double*, int64_t,
-                                             const int64_t*, const int64_t*, const double*, hipStream_t);
-template hipError_t launch_solve_fwd<float>(const float*, const float*, const DFront*, int32_t, int32_t, int32_t,
-                                            double*, int64_t, int32_t, int32_t, int32_t, double*, int64_t,
-                                            const int64_t*, const int64_t*, const double*, hipStream_t);
-template hipError_t launch_solve_bwd<double>(const double*, const double*, const double*, const DFront*, int32_t,
-                                             int32_t, int32_t, double*, int64_t, int32_t, int32_t, int32_t,
-                                             const int32_t*, bool, hipStream_t);
-template hipError_t launch_solve_bwd<float>(const float*, const float*, const float*, const DFront*, int32_t,
-                                            int32_t, int32_t, double*, int64_t, int32_t, int32_t, int32_t,
-                                            const int32_t*, bool, hipStream_t);
-
 // ---------------------------------------------------------------------------
-// Block solves for tree levels with wide supernodes.  The pivots of a front
-// are processed in blocks of KBT = 4 tiles (128 rows): one launch solves the
-// diagonal block of every front (one workgroup per front and column chunk),
-// the next launch applies it to every 32-row tile outside the block (one
-// workgroup per front, tile and column chunk), so the large fronts near the
-// root use the whole chip.  The right-hand side lives in X (pivot rows) and
-// in the update buffer (struct rows) between launches.
-namespace {
-constexpr int KBT = 4;
-constexpr int BQC = 32;
-using BM = SolveMap<BQC>;
-}  // namespace
+// Block solves through the inverse panels Q = [L11^-1; -L21 L11^-1] of the
+// factorisation.  Per tree level and direction two launches:
+//   forward:  gather  R(pivots) = mdiag b + children's updates, update rows =
+//                     children's updates of the struct rows;
+//             product y = Q_piv R -> X, update rows += Q_struct R
+//                     (u = g - L21 L11^-1 b' = g + Q_struct b');
+//   backward: gather  R = [D^-1 y; x at the struct rows];
+//             product x = Q^T R -> X (= L11^-T (D^-1 y - L21^T x_struct)).
+// R is a scratch block whose rows follow each front's local index space
+// (pivot r at qrow + r, struct row s at qrow + ns_pad + s; padding rows are
+// written as zeros).  The products run on the FP64 matrix cores, one wave per
+// (16-row output tile, 16 columns), the Q fragments straight from the tiles
+// (forward: the column-major tiles; backward: the transposed ones, so both
+// load 16 consecutive values per lane group), the next tile's operands loaded
+// while the current one is applied.  Nothing depends on anything else within
+// a launch, so a wide front is no longer a chain of launches.
 
-// rows [0, ns) of the front from B (times mdiag) plus children's updates into X;
-// struct rows: the children's updates into the front's update rows.  items: (front, tile row)
-template <class T>
-__global__ __launch_bounds__(256) void k_big_fwd_init(const DFront* __restrict__ fr, const int32_t* __restrict__ items,
-                                                      int32_t nchunks, double* X, int64_t ldx, int32_t col0,
-                                                      int32_t ncols, T* ubuf, int64_t ldu,
-                                                      const int32_t* __restrict__ gat, int32_t gw,
-                                                      const double* __restrict__ mdiag, const double* Xin) {
-    const int item = blockIdx.x / nchunks;
-    const DFront f = fr[items[2 * item]];
-    const int tr = items[2 * item + 1];
-    const int32_t c0 = col0 + (blockIdx.x % nchunks) * BQC;
-    const int32_t cw = min(BQC, col0 + ncols - c0);
-    for (int idx = threadIdx.x; idx < T32 * BQC; idx += 256) {
-        const int r = idx / BQC, c = idx % BQC;
-        if (c >= cw) continue;
-        if (tr < f.nsb) {
-            const int row = tr * T32 + r;
-            if (row >= f.ns) continue;
-            double v = Xin[(f.start + row) * ldx + c0 + c];
-            if (mdiag) v *= mdiag[f.start + row];
-            const int32_t* gr = gat + (f.gather_base + row) * gw;
-            for (int cg = 0; cg < gw; ++cg)
-                if (gr[cg] >= 0) v += (double)ubuf[(int64_t)gr[cg] * ldu + c0 + c];
-            X[(f.start + row) * ldx + c0 + c] = v;
-        } else {
-            const int s = (tr - f.nsb) * T32 + r;
-            if (s >= f.mu) continue;
+// items: (front, 32-row tile of [0, nsb + struct tiles)); 64 columns per blockIdx.y
+template <class TF>
+__global__ __launch_bounds__(256) void k_qsolve_gather(int fwd, const DFront* __restrict__ fr,
+                                                       const int32_t* __restrict__ items, double* R, int64_t ldr,
+                                                       const double* Xin, double* X, int64_t ldx, int32_t col0,
+                                                       int32_t ncols, TF* ubuf, int64_t ldu,
+                                                       const int32_t* __restrict__ gat, int32_t gw,
+                                                       const double* __restrict__ mdiag, const TF* __restrict__ D,
+                                                       const int32_t* __restrict__ rows) {
+    const DFront f = fr[items[2 * blockIdx.x]];
+    const int tr = items[2 * blockIdx.x + 1];
+    const int32_t c = col0 + 64 * blockIdx.y + (threadIdx.x & 63);
+    if (c >= col0 + ncols) return;
+    const bool piv = tr < f.nsb;
+    for (int i = threadIdx.x >> 6; i < T32; i += 4) {
+        if (piv) {
+            const int p = tr * T32 + i;
             double v = 0.0;
-            const int32_t* gr = gat + (f.gather_base + f.ns + s) * gw;
-            for (int cg = 0; cg < gw; ++cg)
-                if (gr[cg] >= 0) v += (double)ubuf[(int64_t)gr[cg] * ldu + c0 + c];
-            ubuf[(f.ubuf_row + s) * ldu + c0 + c] = (T)v;
-        }
-    }
-}
-
-// The diagonal-block, update and backward phases run on the matrix cores in
-// the wave-level layout of the small-front solves: one wave per (item, 16
-// right-hand-side columns), the 128 rows of a pivot block as eight 16 x 16
-// FP64 MFMA results in registers, factor fragments straight from the tiles
-// (backward phases: from the tile-transposed copy).
-
-// rows r0 + 16 t .. of X (t < nt16, rows below rmax), column c, as MFMA results
-template <int NTL>
-__device__ __forceinline__ void load_rows(dbl4 (&y)[NTL], const double* X, int64_t ldx, int64_t base, int r0,
-                                          int rmax, int32_t c, bool cok) {
-    const int lr = (threadIdx.x & 63) >> 4;
-#pragma unroll
-    for (int t = 0; t < NTL; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + 16 * t + lr + 4 * v;
-            y[t][v] = (r < rmax && cok) ? X[(base + r) * ldx + c] : 0.0;
-        }
-}
-template <int NTL>
-__device__ __forceinline__ void store_rows(const dbl4 (&y)[NTL], double* X, int64_t ldx, int64_t base, int r0, int rmax,
-                                           int32_t c, bool cok) {
-    const int lr = (threadIdx.x & 63) >> 4;
-#pragma unroll
-    for (int t = 0; t < NTL; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + 16 * t + lr + 4 * v;
-            if (r < rmax && cok) X[(base + r) * ldx + c] = y[t][v];
-        }
-}
-
-namespace {
-constexpr int BNT = 2 * KBT;   // 16-row tiles of a pivot block
-constexpr int BWI_WAVES = 8;   // waves sharing the struct rows of one backward-init item
-}
-
-// forward diagonal block kb of every listed front: y_blk = L_blk^-1 y_blk (in X)
-template <class T>
-__global__ __launch_bounds__(512) void k_big_fwd_diag(const T* __restrict__ tiles, const T* __restrict__ linv,
-                                                      const DFront* __restrict__ fr, const int32_t* __restrict__ items,
-                                                      int32_t wpg, int32_t kb, double* X, int64_t ldx, int32_t col0,
-                                                      int32_t ncols) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
-    if (cbase >= col0 + ncols) return;
-    const int32_t c = cbase + (lane & 15);
-    const bool cok = c < col0 + ncols;
-    const DFront f = fr[items[blockIdx.x]];
-    const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
-    const int rbase = t0 * T32, nrow = min(f.ns - rbase, (t1 - t0) * T32);   // real rows of the block
-    const int nt = (nrow + 15) >> 4;
-    dbl4 y[BNT];
-    load_rows<BNT>(y, X, ldx, f.start, rbase, rbase + nrow, c, cok);
-    // rows of y are relative to the block: local row r = global row - rbase
-#pragma unroll
-    for (int lk = 0; lk < KBT; ++lk) {
-        if (2 * lk < nt) {
-            const int kmax = min(32, nrow - 32 * lk);
-            const bool two = 2 * lk + 1 < nt;
-            const T* Li = linv + f.linv_base + (int64_t)(t0 + lk) * TT;
-            double a0[8], a1[8];
-            frag_rows(Li, 0, false, a0);
-            if (two) frag_rows(Li, 1, false, a1);
-            dbl4 n0[1] = {{0, 0, 0, 0}}, n1[1] = {{0, 0, 0, 0}};
-            dbl4 yy[1][BNT];
-#pragma unroll
-            for (int t = 0; t < BNT; ++t) yy[0][t] = y[t];
-            frag_mm<BNT, 1>(a0, yy, lk, kmax, n0, false);
-            if (two) frag_mm<BNT, 1>(a1, yy, lk, kmax, n1, false);
-            y[2 * lk] = n0[0];
-            if (two) y[2 * lk + 1] = n1[0];
-#pragma unroll
-            for (int li = lk + 1; li < KBT; ++li)
-                if (2 * li < nt) {
-                    const T* Lt = tiles + f.tile_base + tri(f.Mt, t0 + li, t0 + lk) * TT;
-                    const bool two_i = 2 * li + 1 < nt;
-                    frag_rows(Lt, 0, false, a0);
-                    if (two_i) frag_rows(Lt, 1, false, a1);
-#pragma unroll
-                    for (int t = 0; t < BNT; ++t) yy[0][t] = y[t];
-                    dbl4 t0v[1] = {y[2 * li]}, t1v[1] = {y[2 * li + 1]};
-                    frag_mm<BNT, 1>(a0, yy, lk, kmax, t0v, true);
-                    if (two_i) frag_mm<BNT, 1>(a1, yy, lk, kmax, t1v, true);
-                    y[2 * li] = t0v[0];
-                    y[2 * li + 1] = t1v[0];
-                }
-        }
-    }
-    store_rows<BNT>(y, X, ldx, f.start, rbase, rbase + nrow, c, cok);
-}
-
-// forward update of one 32-row tile ib below block kb: rows -= L(ib, blk) y_blk
-// (pivot tile: rows of X; struct tile: the front's update rows).  items: (front, ib)
-template <class T>
-__global__ __launch_bounds__(512) void k_big_fwd_update(const T* __restrict__ tiles, const DFront* __restrict__ fr,
-                                                        const int32_t* __restrict__ items, int32_t wpg, int32_t kb,
-                                                        double* X, int64_t ldx, int32_t col0, int32_t ncols, T* ubuf,
-                                                        int64_t ldu) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
-    if (cbase >= col0 + ncols) return;
-    const int32_t c = cbase + (lane & 15);
-    const bool cok = c < col0 + ncols;
-    const DFront f = fr[items[2 * blockIdx.x]];
-    const int ib = items[2 * blockIdx.x + 1];
-    const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
-    const int rbase = t0 * T32, nrow = min(f.ns - rbase, (t1 - t0) * T32);
-    // rows of the target tile that exist
-    const bool piv = ib < f.nsb;
-    const int tr0 = piv ? ib * T32 : (ib - f.nsb) * T32;
-    const int tlim = piv ? f.ns : f.mu;
-    const int trows = min(T32, tlim - tr0);
-    if (trows <= 0) return;
-    dbl4 yy[1][BNT];
-    load_rows<BNT>(yy[0], X, ldx, f.start, rbase, rbase + nrow, c, cok);
-    dbl4 acc0[1] = {{0, 0, 0, 0}}, acc1[1] = {{0, 0, 0, 0}};
-    const bool two = trows > 16;
-#pragma unroll
-    for (int lk = 0; lk < KBT; ++lk)
-        if (32 * lk < nrow) {
-            const T* Lt = tiles + f.tile_base + tri(f.Mt, ib, t0 + lk) * TT;
-            double a0[8], a1[8];
-            frag_rows(Lt, 0, false, a0);
-            if (two) frag_rows(Lt, 1, false, a1);
-            const int kmax = min(32, nrow - 32 * lk);
-            frag_mm<BNT, 1>(a0, yy, lk, kmax, acc0, false);
-            if (two) frag_mm<BNT, 1>(a1, yy, lk, kmax, acc1, false);
-        }
-#pragma unroll
-    for (int it = 0; it < 2; ++it)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = 16 * it + lr + 4 * v;
-            if (r < trows && cok) {
-                const double a = it ? acc1[0][v] : acc0[0][v];
-                if (piv) {
-                    X[(f.start + tr0 + r) * ldx + c] -= a;
+            if (p < f.ns) {
+                if (fwd) {
+                    v = Xin[(f.start + p) * ldx + c];
+                    if (mdiag) v *= mdiag[f.start + p];
+                    if (f.flags & DFRONT_GATHER) {
+                        const int32_t* gr = gat + (f.gather_base + p) * gw;
+                        for (int cg = 0; cg < gw; ++cg)
+                            if (gr[cg] >= 0) v += (double)ubuf[(int64_t)gr[cg] * ldu + c];
+                    }
                 } else {
-                    T* u = ubuf + (f.ubuf_row + tr0 + r) * ldu + c;
-                    *u = (T)((double)*u - a);
+                    v = X[(f.start + p) * ldx + c] / (double)D[f.d_base + p];
                 }
             }
-        }
-}
-
-// backward start: z_jb = D^-1 y_jb - sum over struct tiles L(st, jb)^T x_st, in X.  items: (front, jb)
-template <class T>
-__global__ __launch_bounds__(64 * BWI_WAVES) void k_big_bwd_init(const T* __restrict__ tilesT, const T* __restrict__ D,
-                                                                const DFront* __restrict__ fr,
-                                                                const int32_t* __restrict__ items, double* X,
-                                                                int64_t ldx, int32_t col0, int32_t ncols,
-                                                                const int32_t* __restrict__ rows) {
-    // workgroup: (item, 16 columns); wave w sums over its share of the struct
-    // row tiles, the shares are added in wave order through LDS
-    __shared__ dbl4 red[BWI_WAVES][2][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t c = col0 + blockIdx.y * WCOLS + (lane & 15);
-    const bool cok = c < col0 + ncols;
-    const DFront f = fr[items[2 * blockIdx.x]];
-    const int jb = items[2 * blockIdx.x + 1];
-    const int r0 = jb * T32, nrow = min(T32, f.ns - r0);
-    if (nrow <= 0) return;
-    const bool two = nrow > 16;
-    const int32_t* frows = rows + f.rows_off;
-    const int stiles = (f.mu + T32 - 1) / T32;
-    const int chunk = (stiles + BWI_WAVES - 1) / BWI_WAVES;
-    const int st0 = min(stiles, w * chunk), st1 = min(stiles, st0 + chunk);
-    dbl4 z[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
-    // x of the struct rows, eight k-steps of 4 rows per 32-row tile, one tile ahead
-    double xs[8], xn[8];
-    if (st0 < st1) {
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const int sr = st0 * T32 + 4 * ks + lr;
-            xs[ks] = (sr < f.mu && cok) ? X[(int64_t)frows[sr] * ldx + c] : 0.0;
-        }
-    }
-#pragma unroll 1
-    for (int st = st0; st < st1; ++st) {
-        if (st + 1 < st1) {
-#pragma unroll
-            for (int ks = 0; ks < 8; ++ks) {
-                const int sr = (st + 1) * T32 + 4 * ks + lr;
-                xn[ks] = (sr < f.mu && cok) ? X[(int64_t)frows[sr] * ldx + c] : 0.0;
+            R[(f.qrow + p) * ldr + c] = v;
+        } else {
+            const int sr = (tr - f.nsb) * T32 + i;
+            if (fwd) {
+                if (sr >= f.mu) continue;
+                double v = 0.0;
+                if (f.flags & DFRONT_GATHER) {
+                    const int32_t* gr = gat + (f.gather_base + f.ns + sr) * gw;
+                    for (int cg = 0; cg < gw; ++cg)
+                        if (gr[cg] >= 0) v += (double)ubuf[(int64_t)gr[cg] * ldu + c];
+                }
+                ubuf[(f.ubuf_row + sr) * ldu + c] = (TF)v;
+            } else {
+                const double v = sr < f.mu ? X[(int64_t)rows[f.rows_off + sr] * ldx + c] : 0.0;
+                R[(f.qrow + f.ns_pad + sr) * ldr + c] = v;
             }
         }
-        // A(i, k) = L(k, i): element (i, k) of the transposed tile (nsb + st, jb)
-        const T* Lt = tilesT + f.tile_base + tri(f.Mt, f.nsb + st, jb) * TT;
-        double a0[8], a1[8];
-        frag_rows(Lt, 0, false, a0);
-        if (two) frag_rows(Lt, 1, false, a1);
-        const int kmax = min(32, f.mu - st * T32);
+    }
+}
+
+// 16 rows of column c of R starting at row r0 of the front's index space, as
+// the B operands of the eight k-steps of one tile (rows at or past kmax: 0)
+__device__ __forceinline__ void q_rhs(const double* __restrict__ R, int64_t ldr, int64_t r0, int kmax, int32_t c,
+                                      bool cok, double (&b)[8]) {
+    const int lr = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        const int r = 4 * ks + lr;
+        b[ks] = (r < kmax && cok) ? R[(r0 + r) * ldr + c] : 0.0;
+    }
+}
+
+// forward product; items (front, o): output rows 16 o .. 16 o + 15 of the
+// front's index space (tile I = o / 2, half h = o % 2)
+template <class TF>
+__global__ __launch_bounds__(64) void k_qsolve_fwd(const TF* __restrict__ qinv, const DFront* __restrict__ fr,
+                                                   const int32_t* __restrict__ items, int32_t nitems, int32_t groups,
+                                                   const double* __restrict__ R, int64_t ldr, double* X, int64_t ldx,
+                                                   int32_t col0, int32_t ncols, TF* ubuf, int64_t ldu) {
+    int32_t it, grp;
+    if (!wsolve_item(nitems, groups, it, grp)) return;
+    const int lane = threadIdx.x & 63, lr = lane >> 4;
+    const int32_t c = col0 + WCOLS * grp + (lane & 15);
+    const bool cok = c < col0 + ncols;
+    const DFront f = fr[items[2 * it]];
+    const int o = items[2 * it + 1], I = o >> 1, h = o & 1;
+    const int J1 = min(I, f.nsb - 1);
+    const TF* Q = qinv + f.q_base;
+    double a[8], b[8];
+    frag_rows(Q + tri(f.Mt, I, 0) * TT, h, false, a);
+    q_rhs(R, ldr, f.qrow, min(T32, f.ns), c, cok, b);
+    dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll 1
+    for (int J = 0; J <= J1; ++J) {
+        double an[8], bn[8];
+        if (J < J1) {
+            frag_rows(Q + tri(f.Mt, I, J + 1) * TT, h, false, an);
+            q_rhs(R, ldr, f.qrow + T32 * (J + 1), min(T32, f.ns - T32 * (J + 1)), c, cok, bn);
+        }
+        // the diagonal tile of Q is lower triangular
+        const int kmax = J == I ? min(16 * h + 16, f.ns - T32 * J) : min(T32, f.ns - T32 * J);
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks)
-            if (4 * ks < kmax) {
-                z[0] = mfma4(-a0[ks], xs[ks], z[0]);
-                if (two) z[1] = mfma4(-a1[ks], xs[ks], z[1]);
-            }
+            if (4 * ks < kmax) acc = mfma4(a[ks], b[ks], acc);
+        if (J < J1) {
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) xs[ks] = xn[ks];
-    }
-    red[w][0][lane] = z[0];
-    red[w][1][lane] = z[1];
-    __syncthreads();
-    if (w != 0) return;
-    // z = D^-1 y - sum of the shares
-    dbl4 y[2];
-    load_rows<2>(y, X, ldx, f.start, r0, r0 + nrow, c, cok);
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        dbl4 acc = red[0][t][lane];
-#pragma unroll
-        for (int k = 1; k < BWI_WAVES; ++k) acc += red[k][t][lane];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + 16 * t + lr + 4 * v;
-            y[t][v] = r < r0 + nrow ? y[t][v] / (double)D[f.d_base + r] + acc[v] : 0.0;
-        }
-    }
-    store_rows<2>(y, X, ldx, f.start, r0, r0 + nrow, c, cok);
-}
-
-// backward diagonal block kb: x_blk = L_blk^-T z_blk (in X)
-template <class T>
-__global__ __launch_bounds__(512) void k_big_bwd_diag(const T* __restrict__ tilesT, const T* __restrict__ linvT,
-                                                      const DFront* __restrict__ fr, const int32_t* __restrict__ items,
-                                                      int32_t wpg, int32_t kb, double* X, int64_t ldx, int32_t col0,
-                                                      int32_t ncols) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
-    if (cbase >= col0 + ncols) return;
-    const int32_t c = cbase + (lane & 15);
-    const bool cok = c < col0 + ncols;
-    const DFront f = fr[items[blockIdx.x]];
-    const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
-    const int rbase = t0 * T32, nrow = min(f.ns - rbase, (t1 - t0) * T32);
-    const int nt = (nrow + 15) >> 4;
-    dbl4 zz[1][BNT];
-    load_rows<BNT>(zz[0], X, ldx, f.start, rbase, rbase + nrow, c, cok);
-#pragma unroll
-    for (int lk = KBT - 1; lk >= 0; --lk) {
-        if (2 * lk < nt) {
-            const int kmax = min(32, nrow - 32 * lk);
-            const bool two = 2 * lk + 1 < nt;
-            const T* Li = linvT + f.linv_base + (int64_t)(t0 + lk) * TT;
-            double a0[8], a1[8];
-            frag_rows(Li, 0, false, a0);
-            if (two) frag_rows(Li, 1, false, a1);
-            dbl4 n0[1] = {{0, 0, 0, 0}}, n1[1] = {{0, 0, 0, 0}};
-            frag_mm<BNT, 1>(a0, zz, lk, kmax, n0, false);
-            if (two) frag_mm<BNT, 1>(a1, zz, lk, kmax, n1, false);
-            zz[0][2 * lk] = n0[0];
-            if (two) zz[0][2 * lk + 1] = n1[0];
-#pragma unroll
-            for (int li = 0; li < lk; ++li) {
-                const T* Lt = tilesT + f.tile_base + tri(f.Mt, t0 + lk, t0 + li) * TT;
-                frag_rows(Lt, 0, false, a0);
-                frag_rows(Lt, 1, false, a1);
-                dbl4 t0v[1] = {zz[0][2 * li]}, t1v[1] = {zz[0][2 * li + 1]};
-                frag_mm<BNT, 1>(a0, zz, lk, kmax, t0v, true);
-                frag_mm<BNT, 1>(a1, zz, lk, kmax, t1v, true);
-                zz[0][2 * li] = t0v[0];
-                zz[0][2 * li + 1] = t1v[0];
+            for (int ks = 0; ks < 8; ++ks) {
+                a[ks] = an[ks];
+                b[ks] = bn[ks];
             }
         }
     }
-    store_rows<BNT>(zz[0], X, ldx, f.start, rbase, rbase + nrow, c, cok);
+    if (!cok) return;
+    const bool piv = I < f.nsb;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 16 * h + lr + 4 * v;
+        if (piv) {
+            const int p = I * T32 + r;
+            if (p < f.ns) X[(f.start + p) * ldx + c] = acc[v];
+        } else {
+            const int sr = (I - f.nsb) * T32 + r;
+            if (sr < f.mu) {
+                TF* u = ubuf + (f.ubuf_row + sr) * ldu + c;
+                *u = (TF)((double)*u + acc[v]);
+            }
+        }
+    }
 }
 
-// backward update of pivot tile jb (before block kb): z_jb -= sum_{k in blk} L(k, jb)^T x_k.  items: (front, jb)
-template <class T>
-__global__ __launch_bounds__(512) void k_big_bwd_update(const T* __restrict__ tilesT, const DFront* __restrict__ fr,
-                                                        const int32_t* __restrict__ items, int32_t wpg, int32_t kb,
-                                                        double* X, int64_t ldx, int32_t col0, int32_t ncols) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int32_t cbase = col0 + (blockIdx.y * wpg + w) * WCOLS;
-    if (cbase >= col0 + ncols) return;
-    const int32_t c = cbase + (lane & 15);
+// backward product; items (front, o): pivot rows 16 o .. 16 o + 15 of x,
+// x(C, h) = sum over tile rows I >= C of Q(I, C)^T R(I)
+template <class TF>
+__global__ __launch_bounds__(64) void k_qsolve_bwd(const TF* __restrict__ qinvT, const DFront* __restrict__ fr,
+                                                   const int32_t* __restrict__ items, int32_t nitems, int32_t groups,
+                                                   const double* __restrict__ R, int64_t ldr, double* X, int64_t ldx,
+                                                   int32_t col0, int32_t ncols) {
+    int32_t it, grp;
+    if (!wsolve_item(nitems, groups, it, grp)) return;
+    const int lane = threadIdx.x & 63, lr = lane >> 4;
+    const int32_t c = col0 + WCOLS * grp + (lane & 15);
     const bool cok = c < col0 + ncols;
-    const DFront f = fr[items[2 * blockIdx.x]];
-    const int jb = items[2 * blockIdx.x + 1];
-    const int t0 = kb * KBT, t1 = min(f.nsb, t0 + KBT);
-    const int rbase = t0 * T32, nrow = min(f.ns - rbase, (t1 - t0) * T32);
-    const int r0 = jb * T32, trows = min(T32, f.ns - r0);
-    if (trows <= 0) return;
-    const bool two = trows > 16;
-    dbl4 xx[1][BNT];
-    load_rows<BNT>(xx[0], X, ldx, f.start, rbase, rbase + nrow, c, cok);
-    dbl4 z0[1], z1[1];
-    {
-        dbl4 zt[2];
-        load_rows<2>(zt, X, ldx, f.start, r0, r0 + trows, c, cok);
-        z0[0] = zt[0];
-        z1[0] = zt[1];
-    }
-#pragma unroll
-    for (int lk = 0; lk < KBT; ++lk)
-        if (32 * lk < nrow) {
-            // A(i, k) = L(k, i): tile (t0 + lk, jb) transposed
-            const T* Lt = tilesT + f.tile_base + tri(f.Mt, t0 + lk, jb) * TT;
-            double a0[8], a1[8];
-            frag_rows(Lt, 0, false, a0);
-            if (two) frag_rows(Lt, 1, false, a1);
-            const int kmax = min(32, nrow - 32 * lk);
-            frag_mm<BNT, 1>(a0, xx, lk, kmax, z0, true);
-            if (two) frag_mm<BNT, 1>(a1, xx, lk, kmax, z1, true);
+    const DFront f = fr[items[2 * it]];
+    const int o = items[2 * it + 1], C = o >> 1, h = o & 1;
+    const TF* Q = qinvT + f.q_base;
+    auto rows_of = [&](int I) { return I < f.nsb ? min(T32, f.ns - T32 * I) : min(T32, f.mu - T32 * (I - f.nsb)); };
+    double a[8], b[8];
+    frag_rows(Q + tri(f.Mt, C, C) * TT, h, false, a);
+    q_rhs(R, ldr, f.qrow + T32 * C, rows_of(C), c, cok, b);
+    dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll 1
+    for (int I = C; I < f.Mt; ++I) {
+        double an[8], bn[8];
+        const bool more = I + 1 < f.Mt;
+        if (more) {
+            frag_rows(Q + tri(f.Mt, I + 1, C) * TT, h, false, an);
+            q_rhs(R, ldr, f.qrow + T32 * (I + 1), rows_of(I + 1), c, cok, bn);
         }
-    dbl4 zt[2] = {z0[0], z1[0]};
-    store_rows<2>(zt, X, ldx, f.start, r0, r0 + trows, c, cok);
+        // Q(C, C) is lower triangular: its rows above 16 h do not reach columns 16 h ..
+        const int ks0 = I == C ? 4 * h : 0;
+        const int kmax = rows_of(I);
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+            if (ks >= ks0 && 4 * ks < kmax) acc = mfma4(a[ks], b[ks], acc);
+        if (more) {
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                a[ks] = an[ks];
+                b[ks] = bn[ks];
+            }
+        }
+    }
+    if (!cok) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int p = C * T32 + 16 * h + lr + 4 * v;
+        if (p < f.ns) X[(f.start + p) * ldx + c] = acc[v];
+    }
 }
 
 template <class TF>
-hipError_t launch_big_solve(int phase, const TF* tiles, const TF* linv, const TF* D, const TF* tilesT,
-                            const TF* linvT, const DFront* fronts, const int32_t* items, int64_t nitems, int32_t kb,
-                            double* X, int64_t ldx, int32_t col0, int32_t ncols, double* ubuf, int64_t ldu,
-                            const int32_t* gat, int32_t gw, const double* mdiag, const int32_t* rows,
-                            hipStream_t s, const double* Xin) {
+hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D, const DFront* fronts,
+                         const int32_t* items, int64_t nitems, double* R, int64_t ldr, double* X, int64_t ldx,
+                         int32_t col0, int32_t ncols, double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw,
+                         const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin) {
     if (nitems <= 0 || ncols <= 0) return hipSuccess;
     TF* ub = reinterpret_cast<TF*>(ubuf);
-    if (phase == 0) {
-        const int32_t nch = (int32_t)cdiv(ncols, BQC);
-        k_big_fwd_init<TF><<<(unsigned)(nitems * nch), 256, 0, s>>>(fronts, items, nch, X, ldx, col0, ncols, ub, ldu,
-                                                                    gat, gw, mdiag, Xin ? Xin : X);
+    if (phase == 0 || phase == 2) {
+        const dim3 grid((unsigned)nitems, (unsigned)cdiv(ncols, 64));
+        k_qsolve_gather<TF><<<grid, 256, 0, s>>>(phase == 0 ? 1 : 0, fronts, items, R, ldr, Xin ? Xin : X, X, ldx,
+                                                 col0, ncols, ub, ldu, gat, gw, mdiag, D, rows);
         return hipGetLastError();
     }
-    int32_t wpg, groups;
-    wsolve_shape(ncols, 2, WCOLS, wpg, groups);
-    const dim3 grid((unsigned)nitems, (unsigned)groups), block((unsigned)(64 * wpg));
-    switch (phase) {
-        case 1: k_big_fwd_diag<TF><<<grid, block, 0, s>>>(tiles, linv, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
-        case 2: k_big_fwd_update<TF><<<grid, block, 0, s>>>(tiles, fronts, items, wpg, kb, X, ldx, col0, ncols, ub, ldu); break;
-        case 3:
-            k_big_bwd_init<TF><<<dim3((unsigned)nitems, (unsigned)cdiv(ncols, WCOLS)), 64 * BWI_WAVES, 0, s>>>(
-                tilesT, D, fronts, items, X, ldx, col0, ncols, rows);
-            break;
-        case 4: k_big_bwd_diag<TF><<<grid, block, 0, s>>>(tilesT, linvT, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
-        case 5: k_big_bwd_update<TF><<<grid, block, 0, s>>>(tilesT, fronts, items, wpg, kb, X, ldx, col0, ncols); break;
-        default: return hipErrorInvalidValue;
-    }
+    const int32_t groups = (int32_t)cdiv(ncols, WCOLS);
+    const unsigned grid = (unsigned)(cdiv(nitems, NXCD) * NXCD * groups);
+    if (phase == 1)
+        k_qsolve_fwd<TF><<<grid, 64, 0, s>>>(qinv, fronts, items, (int32_t)nitems, groups, R, ldr, X, ldx, col0, ncols,
+                                            ub, ldu);
+    else if (phase == 3)
+        k_qsolve_bwd<TF><<<grid, 64, 0, s>>>(qinvT, fronts, items, (int32_t)nitems, groups, R, ldr, X, ldx, col0,
+                                            ncols);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
-template hipError_t launch_big_solve<double>(int, const double*, const double*, const double*, const double*,
-                                             const double*, const DFront*, const int32_t*, int64_t, int32_t, double*,
-                                             int64_t, int32_t, int32_t, double*, int64_t, const int32_t*, int32_t,
-                                             const double*, const int32_t*, hipStream_t, const double*);
-template hipError_t launch_big_solve<float>(int, const float*, const float*, const float*, const float*, const float*,
-                                            const DFront*, const int32_t*, int64_t, int32_t, double*, int64_t, int32_t,
-                                            int32_t, double*, int64_t, const int32_t*, int32_t, const double*,
-                                            const int32_t*, hipStream_t, const double*);
+template hipError_t launch_qsolve<double>(int, const double*, const double*, const double*, const DFront*,
+                                          const int32_t*, int64_t, double*, int64_t, double*, int64_t, int32_t, int32_t,
+                                          double*, int64_t, const int32_t*, int32_t, const double*, const int32_t*,
+                                          hipStream_t, const double*);
+template hipError_t launch_qsolve<float>(int, const float*, const float*, const float*, const DFront*, const int32_t*,
+                                         int64_t, double*, int64_t, double*, int64_t, int32_t, int32_t, double*,
+                                         int64_t, const int32_t*, int32_t, const double*, const int32_t*, hipStream_t,
+                                         const double*);
 
 // ============================================================ Gram products
 // Sbar = Psi^T (S Psi), Mbar = Psi^T (M Psi) on the matrix cores.  The q x q
@@ -2502,11 +2097,14 @@ hipError_t launch_assemble_mesh(const double* V, const int32_t* F, int64_t nf, i
 
 // Descriptor and factorisation work lists of a dense k x k problem held as one
 // front of Mt x Mt tiles: per pivot tile step st the diagonal item (front 0),
-// the panel items (0, I) for I > st and the update items (0, I, J) for
-// st < J <= I; the solve's row-gather pointers are all zero.  One thread
-// writes them (at most a few hundred integers).
+// the panel items (0, I) for I > st, the update items (0, I, J) for
+// st < J <= I, the inverse-panel row items (0, j) for j <= st and update
+// items (0, I, j) for I > st, j <= st; the product items (0, o) of the
+// 16-row tiles of the k rows; the solve's row-gather pointers are all zero.
+// The front's inverse panel P = L^-1 starts at offset 0 of its own arrays.
+// One thread writes them (a few thousand integers at most for k = 1000).
 __global__ void k_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t Mt, int32_t* diag, int32_t* panel,
-                              int32_t* upd, int64_t* gptr) {
+                              int32_t* upd, int32_t* qrow, int32_t* qupd, int32_t* prod, int64_t* gptr) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     DFront f{};
     f.ns = k;
@@ -2514,8 +2112,10 @@ __global__ void k_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t 
     f.Mt = Mt;
     f.nsb = Mt;
     f.parent = -1;
+    f.q_base = 0;
+    f.qrow = 0;
     *front = f;
-    int64_t nd = 0, np = 0, nu = 0;
+    int64_t nd = 0, np = 0, nu = 0, nqr = 0, nqu = 0;
     for (int32_t st = 0; st < Mt; ++st) {
         diag[nd++] = 0;
         for (int32_t I = st + 1; I < Mt; ++I) {
@@ -2530,12 +2130,29 @@ __global__ void k_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t 
                 upd[3 * nu + 2] = J;
                 ++nu;
             }
+        for (int32_t j = 0; j <= st; ++j) {
+            qrow[2 * nqr] = 0;
+            qrow[2 * nqr + 1] = j;
+            ++nqr;
+        }
+        for (int32_t I = st + 1; I < Mt; ++I)
+            for (int32_t j = 0; j <= st; ++j) {
+                qupd[3 * nqu] = 0;
+                qupd[3 * nqu + 1] = I;
+                qupd[3 * nqu + 2] = j;
+                ++nqu;
+            }
+    }
+    for (int32_t o = 0; 16 * o < k; ++o) {
+        prod[2 * o] = 0;
+        prod[2 * o + 1] = o;
     }
     for (int32_t i = 0; i <= k; ++i) gptr[i] = 0;
 }
 hipError_t launch_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t Mt, int32_t* diag, int32_t* panel,
-                              int32_t* upd, int64_t* gptr, hipStream_t s) {
-    k_dense_lists<<<1, 64, 0, s>>>(front, k, ns_pad, Mt, diag, panel, upd, gptr);
+                              int32_t* upd, int32_t* qrow, int32_t* qupd, int32_t* prod, int64_t* gptr,
+                              hipStream_t s) {
+    k_dense_lists<<<1, 64, 0, s>>>(front, k, ns_pad, Mt, diag, panel, upd, qrow, qupd, prod, gptr);
     return hipGetLastError();
 }
 

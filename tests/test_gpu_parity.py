@@ -143,12 +143,10 @@ def test_reduced_eigenproblem(cuda, k):
     _check_reduced_eigenproblem(k)
 
 
-@pytest.mark.parametrize("k", [96, 130])
-def test_reduced_eigenproblem_block_solves(cuda, k, monkeypatch):
-    """Dense problems from 512 unknowns on solve their triangular systems with
-    the multi-workgroup block solve; the switch point is lowered here so that
-    the oracle's dense Jacobi stays quick."""
-    monkeypatch.setenv("HSIM_DENSE_BIG_MIN", "64")
+@pytest.mark.parametrize("k", [96, 130, 200])
+def test_reduced_eigenproblem_wide(cuda, k):
+    """Several 32-row tiles of the dense factor and its inverse panel, the last
+    one ragged (130, 200), and several 16-column groups of the products."""
     _check_reduced_eigenproblem(k)
 
 
