@@ -143,7 +143,7 @@ struct Prof {
 struct DenseGEP {
     int32_t k = 0, m = 0, ns_pad = 0, Mt = 0, bj = 16;
     std::vector<int64_t> diag_ptr, panel_ptr, upd_ptr, qrow_ptr, qupd_ptr;
-    int64_t nprod = 0;   // product items (0, o): 16-row tiles of the k rows
+    int64_t nprod = 0;   // product items (0, I): the 32-row tiles of the k rows
     // device work arrays: owned (setup) or carved from a caller's region (setup_in)
     DeviceBuffer store;
     DFront* front = nullptr;
@@ -180,7 +180,7 @@ struct DenseGEP {
             qrow_ptr.push_back(nqr);
             qupd_ptr.push_back(nqu);
         }
-        nprod = (k + 15) / 16;
+        nprod = Mt;
     }
 
     // carve the work arrays out of [base, base + cap) (256-byte aligned pieces);
@@ -270,11 +270,11 @@ struct DenseGEP {
     // scales), X and Y n x ncols row-major with leading dimension ld, X != Y
     void fwd(const double* X, double* Y, int32_t ncols, int64_t ld, hipStream_t s) {
         HIPCHECK(launch_qsolve<double>(1, qinv, qinvT, D, front, items_prod, nprod, const_cast<double*>(X), ld, Y, ld,
-                                       0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s));
+                                       0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s, nullptr, Mt));
     }
     void bwd(const double* X, double* Y, int32_t ncols, int64_t ld, hipStream_t s) {
         HIPCHECK(launch_qsolve<double>(3, qinv, qinvT, D, front, items_prod, nprod, const_cast<double*>(X), ld, Y, ld,
-                                       0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s));
+                                       0, ncols, nullptr, 0, nullptr, 0, nullptr, nullptr, s, nullptr, Mt));
     }
 
     // returns the Jacobi sweeps used, or -1 when dM is not numerically
@@ -372,6 +372,7 @@ struct TLev {
     // 16-row tile), backward product (front, 16-row pivot tile)
     bool q = false, big_fwd = false, big_bwd = false;
     int64_t q_gather[2] = {0, 0}, q_fprod[2] = {0, 0}, q_bprod[2] = {0, 0};   // [offset (ints), count]
+    int32_t q_kf = 0, q_kb = 0;   // longest contraction (tiles) of the forward / backward products
     double l_entries = 0, pivots = 0;    // unpadded L entries and pivot rows of the level's fronts
     int32_t step0 = 0, step1 = 0;
     std::vector<int32_t> ea_tile_cols;   // per child slot: max tile columns of the children's update blocks
@@ -525,18 +526,17 @@ static void setup_tree_levels(hsim_hierarchy* H, Level& L, std::vector<DFront>& 
                 for (int32_t r = 0; r < sy.fronts[i].Mt; ++r) push(i, r);
             T.q_gather[1] = ((int64_t)qitems.size() - T.q_gather[0]) / 2;
             T.q_fprod[0] = (int64_t)qitems.size();
-            for (int32_t i = T.f0; i < T.f1; ++i) {
-                const Front& f = sy.fronts[i];
-                for (int32_t o = 0; o < 2 * f.nsb; ++o)
-                    if (16 * o < f.ns) push(i, o);
-                for (int32_t o = 2 * f.nsb; o < 2 * f.Mt; ++o)
-                    if (16 * (o - 2 * f.nsb) < f.mu) push(i, o);
-            }
+            for (int32_t i = T.f0; i < T.f1; ++i)
+                for (int32_t I = 0; I < sy.fronts[i].Mt; ++I) push(i, I);
             T.q_fprod[1] = ((int64_t)qitems.size() - T.q_fprod[0]) / 2;
             T.q_bprod[0] = (int64_t)qitems.size();
             for (int32_t i = T.f0; i < T.f1; ++i)
-                for (int32_t o = 0; 16 * o < sy.fronts[i].ns; ++o) push(i, o);
+                for (int32_t C = 0; C < sy.fronts[i].nsb; ++C) push(i, C);
             T.q_bprod[1] = ((int64_t)qitems.size() - T.q_bprod[0]) / 2;
+            for (int32_t i = T.f0; i < T.f1; ++i) {
+                T.q_kf = std::max(T.q_kf, sy.fronts[i].nsb);
+                T.q_kb = std::max(T.q_kb, sy.fronts[i].Mt);
+            }
         }
         T.ea_tile_cols.assign(mc, 0);
         for (int32_t c = 0; c < mc; ++c)
@@ -785,10 +785,10 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
     const int32_t* qi = dptr<int32_t>(L.q_items);
     P.solves += 1;
     P.solve_cols += ncols;
-    auto qsolve = [&](int phase, const int64_t* rec) {
+    auto qsolve = [&](int phase, const int64_t* rec, int32_t kmax) {
         HIPCHECK(launch_qsolve<TF>(phase, qinv, qinvT, D, fr, qi + rec[0], rec[1], dptr<double>(L.qrhs), H->ld, X,
                                    H->ld, col0, ncols, dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
-                                   dptr<int32_t>(L.rows), s, Xin));
+                                   dptr<int32_t>(L.rows), s, Xin, kmax));
     };
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
         const TLev& T = L.tl[t];
@@ -796,8 +796,8 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
         if (T.big_fwd) {
             P.run(HSIM_K_SOLVE_FWD, bytes, flops, s, [&] {
-                qsolve(0, T.q_gather);
-                qsolve(1, T.q_fprod);
+                qsolve(0, T.q_gather, 0);
+                qsolve(1, T.q_fprod, T.q_kf);
             });
             continue;
         }
@@ -813,8 +813,8 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
         const double flops = 2.0 * (2.0 * T.l_entries - T.pivots) * ncols;
         if (T.big_bwd) {
             P.run(HSIM_K_SOLVE_BWD, bytes, flops, s, [&] {
-                qsolve(2, T.q_gather);
-                qsolve(3, T.q_bprod);
+                qsolve(2, T.q_gather, 0);
+                qsolve(3, T.q_bprod, T.q_kb);
             });
             continue;
         }

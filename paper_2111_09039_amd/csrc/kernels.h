@@ -86,16 +86,20 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
 // phase 0 forward gather (items: front, 32-row tile of [0, Mt)): right-hand
 // side of the pivots (Xin times mdiag plus the children's updates) into the
 // scratch block R, children's updates of the struct rows into the front's
-// update rows; 1 forward product (items: front, 16-row tile of [0, 2 Mt)):
+// update rows; 1 forward product (items: front, 32-row tile I < Mt):
 // pivot rows of X = Q_piv R, update rows += Q_struct R; 2 backward gather
 // (items as phase 0): R = [D^-1 X(pivots); X(struct rows)]; 3 backward
-// product (items: front, 16-row tile of the pivots): X(pivots) = Q^T R.
+// product (items: front, 32-row pivot tile C < nsb): X(pivots) = Q^T R.
 // qinv: column-major Q tiles (phase 1), qinvT: transposed tiles (phase 3).
+// kmax (products): the longest contraction of the items in tiles (forward:
+// the largest nsb, backward: the largest Mt); it sets the waves that share
+// one output tile.
 template <class TF>
 hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D, const DFront* fronts,
                          const int32_t* items, int64_t nitems, double* R, int64_t ldr, double* X, int64_t ldx,
                          int32_t col0, int32_t ncols, double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw,
-                         const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin = nullptr);
+                         const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin = nullptr,
+                         int32_t kmax = 1);
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 // partial Grams over row chunks of chunk_rows rows (gram_chunk_rows of the

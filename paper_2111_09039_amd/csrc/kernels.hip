@@ -1074,131 +1074,199 @@ __global__ __launch_bounds__(256) void k_qsolve_gather(int fwd, const DFront* __
     }
 }
 
-// 16 rows of column c of R starting at row r0 of the front's index space, as
-// the B operands of the eight k-steps of one tile (rows at or past kmax: 0)
+// 32 rows of columns c and c + 16 of R starting at row r0 of the front's index
+// space, as the B operands of the eight k-steps of one tile (rows at or past
+// kmax, and columns past the block: 0)
 __device__ __forceinline__ void q_rhs(const double* __restrict__ R, int64_t ldr, int64_t r0, int kmax, int32_t c,
-                                      bool cok, double (&b)[8]) {
+                                      bool ok0, bool ok1, double (&b)[2][8]) {
     const int lr = (threadIdx.x & 63) >> 4;
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
         const int r = 4 * ks + lr;
-        b[ks] = (r < kmax && cok) ? R[(r0 + r) * ldr + c] : 0.0;
+        const double* p = R + (r0 + r) * ldr + c;
+        b[0][ks] = (r < kmax && ok0) ? p[0] : 0.0;
+        b[1][ks] = (r < kmax && ok1) ? p[16] : 0.0;
     }
 }
 
-// forward product; items (front, o): output rows 16 o .. 16 o + 15 of the
-// front's index space (tile I = o / 2, half h = o % 2)
+// acc[h][ct] += Q fragment rows (half h) times the B operands of column tile
+// ct over the contraction rows [4 ks0_h, kmax_h) (whole k-steps)
+__device__ __forceinline__ void q_mm(const double (&a)[2][8], const double (&b)[2][8], int kmax0, int kmax1,
+                                     int ks0h1, dbl4 (&acc)[2][2]) {
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            if (4 * ks < kmax0) acc[0][ct] = mfma4(a[0][ks], b[ct][ks], acc[0][ct]);
+            if (4 * ks < kmax1 && ks >= ks0h1) acc[1][ct] = mfma4(a[1][ks], b[ct][ks], acc[1][ct]);
+        }
+    }
+}
+
+// the partial sums of the nw waves of a workgroup added in wave order (wave 0
+// returns true and holds the sum); red: nw x 4 x 64 dbl4 of dynamic LDS
+__device__ __forceinline__ bool q_reduce(dbl4 (&acc)[2][2], int nw, dbl4* red) {
+    if (nw == 1) return true;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) red[(w * 4 + 2 * h + ct) * 64 + lane] = acc[h][ct];
+    __syncthreads();
+    if (w != 0) return false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            dbl4 s = red[(2 * h + ct) * 64 + lane];
+            for (int k = 1; k < nw; ++k) s += red[(k * 4 + 2 * h + ct) * 64 + lane];
+            acc[h][ct] = s;
+        }
+    return true;
+}
+
+// Both products: a workgroup of nw waves per (item, 32 columns); the item is
+// a 32-row output tile of one front, the wave owns its two 16-row halves times
+// two 16-column tiles (four accumulators), the nw waves take every nw-th tile
+// of the contraction and add their sums in wave order.  The next tile's
+// operands are loaded while the current one is applied.
+// Forward, items (front, I), I < Mt: rows of tile I of Q R (J <= min(I, nsb - 1)).
 template <class TF>
-__global__ __launch_bounds__(64) void k_qsolve_fwd(const TF* __restrict__ qinv, const DFront* __restrict__ fr,
-                                                   const int32_t* __restrict__ items, int32_t nitems, int32_t groups,
-                                                   const double* __restrict__ R, int64_t ldr, double* X, int64_t ldx,
-                                                   int32_t col0, int32_t ncols, TF* ubuf, int64_t ldu) {
+__global__ __launch_bounds__(512) void k_qsolve_fwd(const TF* __restrict__ qinv, const DFront* __restrict__ fr,
+                                                    const int32_t* __restrict__ items, int32_t nitems, int32_t groups,
+                                                    int32_t nw, const double* __restrict__ R, int64_t ldr, double* X,
+                                                    int64_t ldx, int32_t col0, int32_t ncols, TF* ubuf, int64_t ldu) {
+    extern __shared__ dbl4 qred[];
     int32_t it, grp;
     if (!wsolve_item(nitems, groups, it, grp)) return;
-    const int lane = threadIdx.x & 63, lr = lane >> 4;
-    const int32_t c = col0 + WCOLS * grp + (lane & 15);
-    const bool cok = c < col0 + ncols;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
+    const int32_t c = col0 + 32 * grp + (lane & 15);
+    const bool ok0 = c < col0 + ncols, ok1 = c + 16 < col0 + ncols;
     const DFront f = fr[items[2 * it]];
-    const int o = items[2 * it + 1], I = o >> 1, h = o & 1;
+    const int I = items[2 * it + 1];
     const int J1 = min(I, f.nsb - 1);
     const TF* Q = qinv + f.q_base;
-    double a[8], b[8];
-    frag_rows(Q + tri(f.Mt, I, 0) * TT, h, false, a);
-    q_rhs(R, ldr, f.qrow, min(T32, f.ns), c, cok, b);
-    dbl4 acc = dbl4{0, 0, 0, 0};
+    dbl4 acc[2][2] = {{dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}}, {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}}};
+    double a[2][8], b[2][8];
+    int J = w;
+    if (J <= J1) {
+        frag_rows(Q + tri(f.Mt, I, J) * TT, 0, false, a[0]);
+        frag_rows(Q + tri(f.Mt, I, J) * TT, 1, false, a[1]);
+        q_rhs(R, ldr, f.qrow + T32 * J, min(T32, f.ns - T32 * J), c, ok0, ok1, b);
+    }
 #pragma unroll 1
-    for (int J = 0; J <= J1; ++J) {
-        double an[8], bn[8];
-        if (J < J1) {
-            frag_rows(Q + tri(f.Mt, I, J + 1) * TT, h, false, an);
-            q_rhs(R, ldr, f.qrow + T32 * (J + 1), min(T32, f.ns - T32 * (J + 1)), c, cok, bn);
+    for (; J <= J1; J += nw) {
+        double an[2][8], bn[2][8];
+        const int Jn = J + nw;
+        if (Jn <= J1) {
+            frag_rows(Q + tri(f.Mt, I, Jn) * TT, 0, false, an[0]);
+            frag_rows(Q + tri(f.Mt, I, Jn) * TT, 1, false, an[1]);
+            q_rhs(R, ldr, f.qrow + T32 * Jn, min(T32, f.ns - T32 * Jn), c, ok0, ok1, bn);
         }
-        // the diagonal tile of Q is lower triangular
-        const int kmax = J == I ? min(16 * h + 16, f.ns - T32 * J) : min(T32, f.ns - T32 * J);
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks)
-            if (4 * ks < kmax) acc = mfma4(a[ks], b[ks], acc);
-        if (J < J1) {
+        // the diagonal tile of Q is lower triangular: rows 0..15 end at column 15
+        const int km = min(T32, f.ns - T32 * J);
+        q_mm(a, b, J == I ? min(km, 16) : km, km, 0, acc);
+        if (Jn <= J1) {
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks) {
-                a[ks] = an[ks];
-                b[ks] = bn[ks];
+                a[0][ks] = an[0][ks];
+                a[1][ks] = an[1][ks];
+                b[0][ks] = bn[0][ks];
+                b[1][ks] = bn[1][ks];
             }
         }
     }
-    if (!cok) return;
+    if (!q_reduce(acc, nw, qred)) return;
     const bool piv = I < f.nsb;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = 16 * h + lr + 4 * v;
-        if (piv) {
-            const int p = I * T32 + r;
-            if (p < f.ns) X[(f.start + p) * ldx + c] = acc[v];
-        } else {
-            const int sr = (I - f.nsb) * T32 + r;
-            if (sr < f.mu) {
-                TF* u = ubuf + (f.ubuf_row + sr) * ldu + c;
-                *u = (TF)((double)*u + acc[v]);
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            if (!(ct ? ok1 : ok0)) continue;
+            const int32_t cc = c + 16 * ct;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * h + lr + 4 * v;
+                if (piv) {
+                    const int p = I * T32 + r;
+                    if (p < f.ns) X[(f.start + p) * ldx + cc] = acc[h][ct][v];
+                } else {
+                    const int sr = (I - f.nsb) * T32 + r;
+                    if (sr < f.mu) {
+                        TF* u = ubuf + (f.ubuf_row + sr) * ldu + cc;
+                        *u = (TF)((double)*u + acc[h][ct][v]);
+                    }
+                }
             }
         }
-    }
 }
 
-// backward product; items (front, o): pivot rows 16 o .. 16 o + 15 of x,
-// x(C, h) = sum over tile rows I >= C of Q(I, C)^T R(I)
+// Backward, items (front, C), C < nsb: pivot rows of tile C of Q^T R, the sum
+// over tile rows I >= C of Q(I, C)^T R(I)
 template <class TF>
-__global__ __launch_bounds__(64) void k_qsolve_bwd(const TF* __restrict__ qinvT, const DFront* __restrict__ fr,
-                                                   const int32_t* __restrict__ items, int32_t nitems, int32_t groups,
-                                                   const double* __restrict__ R, int64_t ldr, double* X, int64_t ldx,
-                                                   int32_t col0, int32_t ncols) {
+__global__ __launch_bounds__(512) void k_qsolve_bwd(const TF* __restrict__ qinvT, const DFront* __restrict__ fr,
+                                                    const int32_t* __restrict__ items, int32_t nitems, int32_t groups,
+                                                    int32_t nw, const double* __restrict__ R, int64_t ldr, double* X,
+                                                    int64_t ldx, int32_t col0, int32_t ncols) {
+    extern __shared__ dbl4 qred[];
     int32_t it, grp;
     if (!wsolve_item(nitems, groups, it, grp)) return;
-    const int lane = threadIdx.x & 63, lr = lane >> 4;
-    const int32_t c = col0 + WCOLS * grp + (lane & 15);
-    const bool cok = c < col0 + ncols;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
+    const int32_t c = col0 + 32 * grp + (lane & 15);
+    const bool ok0 = c < col0 + ncols, ok1 = c + 16 < col0 + ncols;
     const DFront f = fr[items[2 * it]];
-    const int o = items[2 * it + 1], C = o >> 1, h = o & 1;
+    const int C = items[2 * it + 1];
     const TF* Q = qinvT + f.q_base;
     auto rows_of = [&](int I) { return I < f.nsb ? min(T32, f.ns - T32 * I) : min(T32, f.mu - T32 * (I - f.nsb)); };
-    double a[8], b[8];
-    frag_rows(Q + tri(f.Mt, C, C) * TT, h, false, a);
-    q_rhs(R, ldr, f.qrow + T32 * C, rows_of(C), c, cok, b);
-    dbl4 acc = dbl4{0, 0, 0, 0};
+    dbl4 acc[2][2] = {{dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}}, {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}}};
+    double a[2][8], b[2][8];
+    int I = C + w;
+    if (I < f.Mt) {
+        frag_rows(Q + tri(f.Mt, I, C) * TT, 0, false, a[0]);
+        frag_rows(Q + tri(f.Mt, I, C) * TT, 1, false, a[1]);
+        q_rhs(R, ldr, f.qrow + T32 * I, rows_of(I), c, ok0, ok1, b);
+    }
 #pragma unroll 1
-    for (int I = C; I < f.Mt; ++I) {
-        double an[8], bn[8];
-        const bool more = I + 1 < f.Mt;
-        if (more) {
-            frag_rows(Q + tri(f.Mt, I + 1, C) * TT, h, false, an);
-            q_rhs(R, ldr, f.qrow + T32 * (I + 1), rows_of(I + 1), c, cok, bn);
+    for (; I < f.Mt; I += nw) {
+        double an[2][8], bn[2][8];
+        const int In = I + nw;
+        if (In < f.Mt) {
+            frag_rows(Q + tri(f.Mt, In, C) * TT, 0, false, an[0]);
+            frag_rows(Q + tri(f.Mt, In, C) * TT, 1, false, an[1]);
+            q_rhs(R, ldr, f.qrow + T32 * In, rows_of(In), c, ok0, ok1, bn);
         }
-        // Q(C, C) is lower triangular: its rows above 16 h do not reach columns 16 h ..
-        const int ks0 = I == C ? 4 * h : 0;
-        const int kmax = rows_of(I);
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks)
-            if (ks >= ks0 && 4 * ks < kmax) acc = mfma4(a[ks], b[ks], acc);
-        if (more) {
+        // Q(C, C) is lower triangular: columns 16..31 start at row 16
+        const int km = rows_of(I);
+        q_mm(a, b, km, km, I == C ? 4 : 0, acc);
+        if (In < f.Mt) {
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks) {
-                a[ks] = an[ks];
-                b[ks] = bn[ks];
+                a[0][ks] = an[0][ks];
+                a[1][ks] = an[1][ks];
+                b[0][ks] = bn[0][ks];
+                b[1][ks] = bn[1][ks];
             }
         }
     }
-    if (!cok) return;
+    if (!q_reduce(acc, nw, qred)) return;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int p = C * T32 + 16 * h + lr + 4 * v;
-        if (p < f.ns) X[(f.start + p) * ldx + c] = acc[v];
-    }
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            if (!(ct ? ok1 : ok0)) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int p = C * T32 + 16 * h + lr + 4 * v;
+                if (p < f.ns) X[(f.start + p) * ldx + c + 16 * ct] = acc[h][ct][v];
+            }
+        }
 }
 
 template <class TF>
 hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D, const DFront* fronts,
                          const int32_t* items, int64_t nitems, double* R, int64_t ldr, double* X, int64_t ldx,
                          int32_t col0, int32_t ncols, double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw,
-                         const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin) {
+                         const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin, int32_t kmax) {
     if (nitems <= 0 || ncols <= 0) return hipSuccess;
     TF* ub = reinterpret_cast<TF*>(ubuf);
     if (phase == 0 || phase == 2) {
@@ -1207,14 +1275,17 @@ hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D
                                                  col0, ncols, ub, ldu, gat, gw, mdiag, D, rows);
         return hipGetLastError();
     }
-    const int32_t groups = (int32_t)cdiv(ncols, WCOLS);
+    // waves per workgroup: every wave takes about eight tiles of the longest contraction
+    const int32_t nw = kmax > 32 ? 8 : kmax > 16 ? 4 : kmax > 8 ? 2 : 1;
+    const size_t lds = nw > 1 ? (size_t)nw * 4 * 64 * sizeof(double) * 4 : 0;
+    const int32_t groups = (int32_t)cdiv(ncols, 32);
     const unsigned grid = (unsigned)(cdiv(nitems, NXCD) * NXCD * groups);
     if (phase == 1)
-        k_qsolve_fwd<TF><<<grid, 64, 0, s>>>(qinv, fronts, items, (int32_t)nitems, groups, R, ldr, X, ldx, col0, ncols,
-                                            ub, ldu);
+        k_qsolve_fwd<TF><<<grid, 64 * nw, lds, s>>>(qinv, fronts, items, (int32_t)nitems, groups, nw, R, ldr, X, ldx,
+                                                   col0, ncols, ub, ldu);
     else if (phase == 3)
-        k_qsolve_bwd<TF><<<grid, 64, 0, s>>>(qinvT, fronts, items, (int32_t)nitems, groups, R, ldr, X, ldx, col0,
-                                            ncols);
+        k_qsolve_bwd<TF><<<grid, 64 * nw, lds, s>>>(qinvT, fronts, items, (int32_t)nitems, groups, nw, R, ldr, X, ldx,
+                                                   col0, ncols);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1222,11 +1293,11 @@ hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D
 template hipError_t launch_qsolve<double>(int, const double*, const double*, const double*, const DFront*,
                                           const int32_t*, int64_t, double*, int64_t, double*, int64_t, int32_t, int32_t,
                                           double*, int64_t, const int32_t*, int32_t, const double*, const int32_t*,
-                                          hipStream_t, const double*);
+                                          hipStream_t, const double*, int32_t);
 template hipError_t launch_qsolve<float>(int, const float*, const float*, const float*, const DFront*, const int32_t*,
                                          int64_t, double*, int64_t, double*, int64_t, int32_t, int32_t, double*,
                                          int64_t, const int32_t*, int32_t, const double*, const int32_t*, hipStream_t,
-                                         const double*);
+                                         const double*, int32_t);
 
 // ============================================================ Gram products
 // Sbar = Psi^T (S Psi), Mbar = Psi^T (M Psi) on the matrix cores.  The q x q
@@ -2099,8 +2170,8 @@ hipError_t launch_assemble_mesh(const double* V, const int32_t* F, int64_t nf, i
 // front of Mt x Mt tiles: per pivot tile step st the diagonal item (front 0),
 // the panel items (0, I) for I > st, the update items (0, I, J) for
 // st < J <= I, the inverse-panel row items (0, j) for j <= st and update
-// items (0, I, j) for I > st, j <= st; the product items (0, o) of the
-// 16-row tiles of the k rows; the solve's row-gather pointers are all zero.
+// items (0, I, j) for I > st, j <= st; the product items (0, I) of the
+// 32-row tiles of the k rows; the solve's row-gather pointers are all zero.
 // The front's inverse panel P = L^-1 starts at offset 0 of its own arrays.
 // One thread writes them (a few thousand integers at most for k = 1000).
 __global__ void k_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t Mt, int32_t* diag, int32_t* panel,
@@ -2143,7 +2214,7 @@ __global__ void k_dense_lists(DFront* front, int32_t k, int32_t ns_pad, int32_t 
                 ++nqu;
             }
     }
-    for (int32_t o = 0; 16 * o < k; ++o) {
+    for (int32_t o = 0; o < Mt; ++o) {
         prod[2 * o] = 0;
         prod[2 * o + 1] = o;
     }
