@@ -315,9 +315,13 @@ def main():
         try:
             dtm, (evm, Xm, rm, stm) = run_solves(H, hs.MIXED, args.tol, args.steps, args.warmup)
             rel = (evm - ev64).abs()[1:] / ev64[1:].abs()
+            _, _, _, profm = H.solve(tol=args.tol, precision=hs.MIXED, profile=True)
             results["mixed"] = dict(s=dtm, iters=stm["iters"], max_resid=float(rm.max()),
                                     max_eig_rel_diff_vs_fp64=float(rel.max()), refine_steps=stm["refine_steps"],
-                                    escalated=stm["escalated"], gram_steps=stm["gram_steps"], stats=stm)
+                                    escalated=stm["escalated"], gram_steps=stm["gram_steps"],
+                                    block_solves=stm["block_solves"], block_solves_fp32=stm["block_solves_fp32"],
+                                    kernels_ms={k: round(v["ms"], 3) for k, v in profm["kernels"].items()},
+                                    stats=stm)
             outs["mixed"] = (evm, Xm)
             # headline: the faster of the two precision modes (both reach the tolerance)
             if dtm < dt64 and float(rm.max()) <= args.tol:

@@ -155,6 +155,8 @@ typedef struct {
     int64_t block_solve_cols;
     /* Rayleigh-Ritz Gram products by form: FP64, FP32, compensated FP32 */
     int32_t gram_steps[3];
+    /* of block_solves: those that ran with the FP32 copy of the factor */
+    int64_t block_solves_fp32;
 } hsim_stats;
 
 /* Per-level sizes (hsim_level_desc). */

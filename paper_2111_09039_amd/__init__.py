@@ -159,10 +159,11 @@ class Hierarchy:
         U (CSR, rows = this level, cols = next coarser), perm."""
         info = self.level_info(level)
         n, nnz, nu = info["n"], info["nnz"], info["nnz_u"]
-        out = dict(verts=np.empty(n, np.int64), S_indptr=np.empty(n + 1, np.int64), S_indices=np.empty(nnz, np.int32),
-                   S_data=np.empty(nnz), M_data=np.empty(nnz), U_indptr=np.empty(n + 1, np.int64),
-                   U_indices=np.empty(max(nu, 1), np.int32), U_data=np.empty(max(nu, 1)),
-                   perm=np.empty(n, np.int32))
+        # zero-filled: the coarsest level has no U and no elimination order
+        out = dict(verts=np.zeros(n, np.int64), S_indptr=np.zeros(n + 1, np.int64), S_indices=np.zeros(nnz, np.int32),
+                   S_data=np.zeros(nnz), M_data=np.zeros(nnz), U_indptr=np.zeros(n + 1, np.int64),
+                   U_indices=np.zeros(max(nu, 1), np.int32), U_data=np.zeros(max(nu, 1)),
+                   perm=np.zeros(n, np.int32))
         ptr = {k: v.ctypes.data_as(C.c_void_p) for k, v in out.items()}
         _lib.check(_lib.load().hsim_level_export(self.handle, int(level), ptr["verts"], ptr["S_indptr"],
                                                  ptr["S_indices"], ptr["S_data"], ptr["M_data"], ptr["U_indptr"],

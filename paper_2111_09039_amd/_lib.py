@@ -33,7 +33,7 @@ class Stats(C.Structure):
                 ("ms_prolong", C.c_double), ("ms_total", C.c_double),
                 ("k_ms", C.c_double * 8), ("k_launches", C.c_int64 * 8), ("k_bytes", C.c_double * 8),
                 ("k_flops", C.c_double * 8), ("block_solves", C.c_int64), ("block_solve_cols", C.c_int64),
-                ("gram_steps", C.c_int32 * 3)]
+                ("gram_steps", C.c_int32 * 3), ("block_solves_fp32", C.c_int64)]
 
     def as_dict(self):
         T = self.levels
@@ -44,6 +44,7 @@ class Stats(C.Structure):
                     ms_solve=self.ms_solve, ms_gram=self.ms_gram, ms_rr=self.ms_rr, ms_ritz=self.ms_ritz,
                     ms_prolong=self.ms_prolong, ms_total=self.ms_total, block_solves=self.block_solves,
                     block_solve_cols=self.block_solve_cols, gram_steps=list(self.gram_steps),
+                    block_solves_fp32=self.block_solves_fp32,
                     kernels={name: dict(ms=self.k_ms[i], launches=self.k_launches[i], bytes=self.k_bytes[i],
                                         flops=self.k_flops[i]) for i, name in enumerate(KCLASSES)})
 

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libhsim.so")
 ARCH = os.environ.get("HSIM_OFFLOAD_ARCH", "gfx950")
 
 HOST_SOURCES = ["mesh.cpp", "hierarchy.cpp", "order.cpp"]        # plain C++ (no HIP)
-DEVICE_SOURCES = ["hsim.cpp", "kernels.hip"]                     # HIP runtime / kernels
+DEVICE_SOURCES = ["hsim.cpp", "kernels.hip", "build_dev.hip"]    # HIP runtime / kernels
 
 
 def _hipcc():

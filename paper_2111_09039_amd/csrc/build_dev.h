@@ -1,0 +1,30 @@
+// Device parts of the hierarchy build (Algorithm 3 and the mesh topology it
+// runs on).  Host declarations only; the kernels live in build_dev.hip.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+
+namespace hsim {
+
+// Device copies of the mesh and of its edge graph, kept while the hierarchy
+// is built.
+struct DevMesh {
+    DeviceBuffer V, F, gptr, gnbr, gw;
+    int64_t nv = 0, nf = 0;
+};
+
+// validate_mesh followed by edge_graph, on the device: the same checks in the
+// same order with the same messages (HSIM_E_MESH), and the same graph (the
+// neighbours of a vertex ascending, the same Euclidean edge lengths bit for
+// bit).  Leaves the device copies of V, F and the graph in dm.
+void device_mesh_graph(const Mesh& m, DevMesh& dm, Graph& g);
+
+// farthest_point_sampling on the device graph of dm: the same insertion
+// order bit for bit (the same distances: the fixpoint of the relaxations does
+// not depend on their order; farthest ties to the lowest vertex index).
+std::vector<int32_t> device_fps(const DevMesh& dm, int64_t count, uint64_t seed);
+
+}  // namespace hsim

@@ -1,0 +1,483 @@
+// Device parts of the hierarchy build for gfx950: the mesh checks and the
+// edge graph that the geodesic distances of Algorithm 3 run on, and the
+// farthest point sampling of Algorithm 3 itself.
+//
+// The results equal the host build's bit for bit.  Floating-point values are
+// formed with the host's operations in the host's order (no contraction in
+// this file), and the only order-dependent choices are resolved by index: the
+// neighbours of a vertex are sorted, and farthest-point ties go to the lowest
+// vertex index.  The sampling's distances are the least fixpoint of
+// d(u) = min(d(u), d(v) + w(v, u)) from the new sample: a value that every
+// order of relaxations reaches (rounding is monotone and w >= 0), so the
+// parallel relaxation below gives the host Dijkstra's distances exactly.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <limits>
+
+#include "build_dev.h"
+
+#pragma clang fp contract(off)
+
+namespace hsim {
+
+namespace {
+#define BDCHECK(x)                                                                                  \
+    do {                                                                                            \
+        const hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) fail(HSIM_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_));             \
+    } while (0)
+
+constexpr unsigned long long NONE = ~0ull;
+
+inline unsigned grid_of(int64_t n, int block) {
+    const int64_t g = (n + block - 1) / block;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, int64_t(1) << 20));
+}
+template <class T>
+T* dp(const DeviceBuffer& b) {
+    return static_cast<T*>(b.p);
+}
+}  // namespace
+
+// ------------------------------------------------------------ prefix sums
+// out[i] = sum of in[j], j < i, for i < n (2048 values per workgroup of 1024
+// threads); sums[b] = the workgroup's total.  in and out may alias (every
+// value is read before the barrier and written after it by the same thread).
+__global__ __launch_bounds__(1024) void k_scan_block(const int64_t* in, int64_t n, int64_t* out, int64_t* sums) {
+    __shared__ int64_t s[1024];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * 2048 + 2 * t;
+    const int64_t a = i0 < n ? in[i0] : 0, b = i0 + 1 < n ? in[i0 + 1] : 0;
+    s[t] = a + b;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    const int64_t excl = s[t] - (a + b);
+    if (i0 < n) out[i0] = excl;
+    if (i0 + 1 < n) out[i0 + 1] = excl + a;
+    if (t == 1023) sums[blockIdx.x] = s[1023];
+}
+__global__ void k_scan_add(int64_t* out, int64_t n, const int64_t* __restrict__ offs) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] += offs[i / 2048];
+}
+__global__ void k_copy1(int64_t* dst, const int64_t* src) { *dst = *src; }
+
+// out[0 .. n] = exclusive prefix sums of in[0 .. n) and the total (out may be in)
+static void dev_scan(const int64_t* in, int64_t* out, int64_t n) {
+    const int64_t nb = std::max<int64_t>(1, (n + 2047) / 2048);
+    DeviceBuffer sums;
+    sums.alloc((size_t)(nb + 1) * sizeof(int64_t));
+    k_scan_block<<<(unsigned)nb, 1024>>>(in, n, out, dp<int64_t>(sums));
+    BDCHECK(hipGetLastError());
+    if (nb > 1) {
+        dev_scan(dp<int64_t>(sums), dp<int64_t>(sums), nb);
+        k_scan_add<<<grid_of(n, 256), 256>>>(out, n, dp<int64_t>(sums));
+        BDCHECK(hipGetLastError());
+        k_copy1<<<1, 1>>>(out + n, dp<int64_t>(sums) + nb);
+    } else {
+        k_copy1<<<1, 1>>>(out + n, dp<int64_t>(sums));
+    }
+    BDCHECK(hipGetLastError());
+    BDCHECK(hipDeviceSynchronize());   // sums is freed on return
+}
+
+// ------------------------------------------------------------ mesh checks
+// first vertex with a non-finite coordinate
+__global__ void k_check_coords(const double* __restrict__ V, int64_t nv, unsigned long long* first) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * nv; i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(V[i])) atomicMin(first, (unsigned long long)(i / 3));
+}
+// first triangle with an index out of range or a repeated vertex; first
+// degenerate triangle among the others (the host's area test, same operations)
+__global__ void k_check_tris(const double* __restrict__ V, const int32_t* __restrict__ F, int64_t nf, int64_t nv,
+                             unsigned long long* first_bad, unsigned long long* first_degen) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t f0 = F[3 * t], f1 = F[3 * t + 1], f2 = F[3 * t + 2];
+        const bool range = f0 >= 0 && f0 < nv && f1 >= 0 && f1 < nv && f2 >= 0 && f2 < nv;
+        if (!range || f0 == f1 || f1 == f2 || f2 == f0) {
+            atomicMin(first_bad, (unsigned long long)t);
+            continue;
+        }
+        const double* a = V + 3 * (int64_t)f0;
+        const double* b = V + 3 * (int64_t)f1;
+        const double* c = V + 3 * (int64_t)f2;
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        const double e3[3] = {c[0] - b[0], c[1] - b[1], c[2] - b[2]};
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+        const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+        const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double a2 = cx * cx + cy * cy + cz * cz;
+        const double l1 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+        const double lb = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+        const double lc = e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2];
+        double l2 = l1;
+        if (l2 < lb) l2 = lb;
+        if (l2 < lc) l2 = lc;
+        if (!(a2 > 1e-24 * l2 * l2)) atomicMin(first_degen, (unsigned long long)t);
+    }
+}
+// triangles per vertex
+__global__ void k_count_tri(const int32_t* __restrict__ F, int64_t nf, unsigned long long* cnt) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 3 * nf; e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[F[e]], 1ull);
+}
+__global__ void k_check_used(const int64_t* __restrict__ cnt, int64_t nv, unsigned long long* first) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+        if (cnt[i] == 0) atomicMin(first, (unsigned long long)i);
+}
+// triangles of every vertex into its segment of vtri (any order; sorted next)
+__global__ void k_fill_tri(const int32_t* __restrict__ F, int64_t nf, unsigned long long* cursor, int32_t* vtri) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 3 * nf; e += (int64_t)gridDim.x * blockDim.x)
+        vtri[atomicAdd(&cursor[F[e]], 1ull)] = (int32_t)(e / 3);
+}
+// per vertex: its triangles ascending; the other two corners of each as
+// candidate neighbours, sorted, made unique in place (count in ucnt), and the
+// first neighbour u > v whose edge lies in more than two triangles
+__global__ void k_neighbours(const int32_t* __restrict__ F, const int64_t* __restrict__ vptr, int32_t* vtri,
+                             int64_t nv, int32_t* cand, int64_t* ucnt, unsigned long long* first_nm) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t0 = vptr[v], d = vptr[v + 1] - t0;
+        int32_t* T = vtri + t0;
+        for (int64_t i = 1; i < d; ++i) {
+            const int32_t x = T[i];
+            int64_t j = i - 1;
+            while (j >= 0 && T[j] > x) {
+                T[j + 1] = T[j];
+                --j;
+            }
+            T[j + 1] = x;
+        }
+        int32_t* C = cand + 2 * t0;
+        for (int64_t i = 0; i < d; ++i) {
+            const int32_t* f = F + 3 * (int64_t)T[i];
+            const int k = f[0] == v ? 0 : (f[1] == v ? 1 : 2);
+            C[2 * i] = f[(k + 1) % 3];
+            C[2 * i + 1] = f[(k + 2) % 3];
+        }
+        for (int64_t i = 1; i < 2 * d; ++i) {
+            const int32_t x = C[i];
+            int64_t j = i - 1;
+            while (j >= 0 && C[j] > x) {
+                C[j + 1] = C[j];
+                --j;
+            }
+            C[j + 1] = x;
+        }
+        int64_t u = 0;
+        bool flagged = false;
+        for (int64_t i = 0; i < 2 * d;) {
+            int64_t j = i;
+            while (j < 2 * d && C[j] == C[i]) ++j;
+            if (!flagged && j - i > 2 && C[i] > v) {
+                atomicMin(first_nm, ((unsigned long long)v << 32) | (unsigned long long)(uint32_t)C[i]);
+                flagged = true;
+            }
+            C[u++] = C[i];
+            i = j;
+        }
+        ucnt[v] = u;
+    }
+}
+// CSR of the edge graph: neighbours ascending, Euclidean lengths (squared
+// differences summed x, y, z in order, then the square root)
+__global__ void k_graph_fill(const int64_t* __restrict__ vptr, const int32_t* __restrict__ cand,
+                             const int64_t* __restrict__ gptr, int64_t nv, const double* __restrict__ V,
+                             int32_t* __restrict__ nbr, double* __restrict__ w) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* C = cand + 2 * vptr[v];
+        const int64_t o = gptr[v], d = gptr[v + 1] - o;
+        for (int64_t i = 0; i < d; ++i) {
+            const int32_t j = C[i];
+            nbr[o + i] = j;
+            const double dx = V[3 * v] - V[3 * (int64_t)j];
+            const double dy = V[3 * v + 1] - V[3 * (int64_t)j + 1];
+            const double dz = V[3 * v + 2] - V[3 * (int64_t)j + 2];
+            w[o + i] = sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    }
+}
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+static unsigned long long read_u64(const DeviceBuffer& b, size_t i) {
+    unsigned long long v = 0;
+    BDCHECK(hipMemcpy(&v, static_cast<const unsigned long long*>(b.p) + i, sizeof v, hipMemcpyDeviceToHost));
+    return v;
+}
+
+void device_mesh_graph(const Mesh& m, DevMesh& dm, Graph& g) {
+    if (m.nv < 3 || m.nf < 1) fail(HSIM_E_MESH, "mesh needs >= 3 vertices and >= 1 triangle");
+    const int64_t nv = m.nv, nf = m.nf;
+    dm.nv = nv;
+    dm.nf = nf;
+    dm.V.upload(m.V);
+    dm.F.upload(m.F);
+    DeviceBuffer flags;   // first non-finite vertex, bad triangle, degenerate triangle, unused vertex, non-manifold edge
+    flags.alloc(5 * sizeof(unsigned long long));
+    unsigned long long* fl = dp<unsigned long long>(flags);
+    k_fill_u64<<<1, 64>>>(fl, 5, NONE);
+    k_check_coords<<<grid_of(3 * nv, 256), 256>>>(dp<double>(dm.V), nv, fl);
+    k_check_tris<<<grid_of(nf, 256), 256>>>(dp<double>(dm.V), dp<int32_t>(dm.F), nf, nv, fl + 1, fl + 2);
+    BDCHECK(hipGetLastError());
+    BDCHECK(hipDeviceSynchronize());
+    // the host's order of checks and messages
+    unsigned long long bad = read_u64(flags, 0);
+    if (bad != NONE) fail(HSIM_E_MESH, "vertex %lld has a non-finite coordinate", (long long)bad);
+    bad = read_u64(flags, 1);
+    if (bad != NONE) {
+        const int32_t* f = &m.F[3 * bad];
+        for (int k = 0; k < 3; ++k)
+            if (f[k] < 0 || f[k] >= nv)
+                fail(HSIM_E_MESH, "triangle %lld references vertex %d out of range", (long long)bad, f[k]);
+        fail(HSIM_E_MESH, "triangle %lld repeats a vertex", (long long)bad);
+    }
+    // every index is in range from here on
+    DeviceBuffer cnt, vptr, cursor, vtri, cand, ucnt;
+    cnt.alloc((size_t)nv * sizeof(int64_t));
+    vptr.alloc((size_t)(nv + 1) * sizeof(int64_t));
+    k_fill_u64<<<grid_of(nv, 256), 256>>>(dp<unsigned long long>(cnt), nv, 0ull);
+    k_count_tri<<<grid_of(3 * nf, 256), 256>>>(dp<int32_t>(dm.F), nf, dp<unsigned long long>(cnt));
+    k_check_used<<<grid_of(nv, 256), 256>>>(dp<int64_t>(cnt), nv, fl + 3);
+    BDCHECK(hipGetLastError());
+    BDCHECK(hipDeviceSynchronize());
+    bad = read_u64(flags, 3);
+    if (bad != NONE) fail(HSIM_E_MESH, "vertex %lld belongs to no triangle", (long long)bad);
+    bad = read_u64(flags, 2);
+    if (bad != NONE) fail(HSIM_E_MESH, "triangle %lld is degenerate", (long long)bad);
+    dev_scan(dp<int64_t>(cnt), dp<int64_t>(vptr), nv);
+    cursor.alloc((size_t)nv * sizeof(int64_t));
+    BDCHECK(hipMemcpy(cursor.p, vptr.p, (size_t)nv * sizeof(int64_t), hipMemcpyDeviceToDevice));
+    vtri.alloc((size_t)3 * nf * sizeof(int32_t));
+    cand.alloc((size_t)6 * nf * sizeof(int32_t));
+    ucnt.alloc((size_t)(nv + 1) * sizeof(int64_t));
+    k_fill_tri<<<grid_of(3 * nf, 256), 256>>>(dp<int32_t>(dm.F), nf, dp<unsigned long long>(cursor), dp<int32_t>(vtri));
+    k_neighbours<<<grid_of(nv, 256), 256>>>(dp<int32_t>(dm.F), dp<int64_t>(vptr), dp<int32_t>(vtri), nv,
+                                            dp<int32_t>(cand), dp<int64_t>(ucnt), fl + 4);
+    BDCHECK(hipGetLastError());
+    BDCHECK(hipDeviceSynchronize());
+    bad = read_u64(flags, 4);
+    if (bad != NONE) {
+        const int64_t a = (int64_t)(bad >> 32), b = (int64_t)(bad & 0xffffffffull);
+        size_t c = 0;
+        for (int64_t t = 0; t < nf; ++t)
+            for (int k = 0; k < 3; ++k) {
+                const int64_t u = m.F[3 * t + k], v = m.F[3 * t + (k + 1) % 3];
+                c += std::min(u, v) == a && std::max(u, v) == b;
+            }
+        fail(HSIM_E_MESH, "edge (%lld,%lld) is shared by %zu triangles", (long long)a, (long long)b, c);
+    }
+    dm.gptr.alloc((size_t)(nv + 1) * sizeof(int64_t));
+    dev_scan(dp<int64_t>(ucnt), dp<int64_t>(dm.gptr), nv);
+    g.ptr.resize(nv + 1);
+    BDCHECK(hipMemcpy(g.ptr.data(), dm.gptr.p, (size_t)(nv + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    const int64_t ne = g.ptr[nv];
+    dm.gnbr.alloc((size_t)std::max<int64_t>(1, ne) * sizeof(int32_t));
+    dm.gw.alloc((size_t)std::max<int64_t>(1, ne) * sizeof(double));
+    k_graph_fill<<<grid_of(nv, 256), 256>>>(dp<int64_t>(vptr), dp<int32_t>(cand), dp<int64_t>(dm.gptr), nv,
+                                            dp<double>(dm.V), dp<int32_t>(dm.gnbr), dp<double>(dm.gw));
+    BDCHECK(hipGetLastError());
+    g.nbr.resize(ne);
+    g.w.resize(ne);
+    BDCHECK(hipMemcpy(g.nbr.data(), dm.gnbr.p, (size_t)ne * sizeof(int32_t), hipMemcpyDeviceToHost));
+    BDCHECK(hipMemcpy(g.w.data(), dm.gw.p, (size_t)ne * sizeof(double), hipMemcpyDeviceToHost));
+    check_connected(g, nv);
+}
+
+// ------------------------------------------------------------ farthest point sampling
+// One workgroup runs the whole sampling (it is sequential over the samples):
+// after each new sample, rounds of relaxation over a frontier (queues and
+// in-queue flags double-buffered: a vertex improved while it waits in the
+// current round goes to the next one), then the farthest vertex from the
+// per-block maxima of the distances (blocks of 1024 vertices; only blocks
+// with an improved vertex are rescanned).  Distances are non-negative
+// doubles, so their bit patterns order like the values and atomicMin on the
+// 64-bit patterns is an exact minimum.  Every hand-over of global data
+// between threads (queues, flags, block maxima) crosses an agent-scope fence
+// and a barrier, so the readers' first-level cache holds no stale line; a
+// distance read in the middle of a round may miss an improvement made in the
+// same round, but the improved vertex is queued again for the next round.
+namespace {
+constexpr int FPS_T = 1024;
+// (value, index) pairs: larger value wins, ties to the lower index
+__device__ __forceinline__ bool better(double a, int32_t ia, double b, int32_t ib) {
+    return a > b || (a == b && ia < ib);
+}
+__device__ __forceinline__ void fence_sync() {
+    __threadfence();
+    __syncthreads();
+}
+}  // namespace
+
+__global__ void k_fps_init(int64_t n, unsigned long long* dist, unsigned int* f0, unsigned int* f1,
+                           unsigned int* dirty, int64_t nb) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        dist[i] = 0x7ff0000000000000ull;   // +inf
+        f0[i] = 0;
+        f1[i] = 0;
+        if (i < nb) dirty[i] = 1;
+    }
+}
+
+__global__ __launch_bounds__(FPS_T) void k_fps(const int64_t* __restrict__ gptr, const int32_t* __restrict__ nbr,
+                                               const double* __restrict__ w, int64_t n, int64_t count, int32_t start,
+                                               unsigned long long* dist, int32_t* q0, int32_t* q1,
+                                               unsigned int* f0, unsigned int* f1, double* bmax, int32_t* bidx,
+                                               unsigned int* dirty, int32_t* dlist, int32_t* order, int32_t* status) {
+    __shared__ int32_t qn[2];
+    __shared__ int32_t nd_;
+    __shared__ double rv[FPS_T];
+    __shared__ int32_t ri[FPS_T];
+    __shared__ int32_t sel, stop;
+    const int t = threadIdx.x;
+    const int64_t nb = (n + FPS_T - 1) / FPS_T;
+    int32_t* Q[2] = {q0, q1};
+    unsigned int* FL[2] = {f0, f1};
+    if (t == 0) {
+        sel = start;
+        stop = 0;
+    }
+    __syncthreads();
+    for (int64_t k = 0; k < count; ++k) {
+        const int32_t s = sel;
+        if (t == 0) order[k] = s;
+        if (k + 1 == count) break;   // the last sample's distances choose nothing
+        // relaxation from s
+        if (t == 0) {
+            atomicMin(&dist[s], 0ull);
+            atomicOr(&dirty[s / FPS_T], 1u);
+            Q[0][0] = s;
+            FL[0][s] = 1;
+            qn[0] = 1;
+            qn[1] = 0;
+        }
+        fence_sync();
+        int cur = 0;
+        while (true) {
+            const int32_t len = qn[cur];
+            if (len == 0) break;
+            int32_t* qo = Q[cur ^ 1];
+            unsigned int* fo = FL[cur ^ 1];
+            for (int32_t e = t; e < len; e += FPS_T) {
+                const int32_t v = Q[cur][e];
+                FL[cur][v] = 0;
+                const double dv = __longlong_as_double((long long)dist[v]);
+                for (int64_t kk = gptr[v]; kk < gptr[v + 1]; ++kk) {
+                    const int32_t u = nbr[kk];
+                    const double ndist = dv + w[kk];
+                    const unsigned long long nbits = (unsigned long long)__double_as_longlong(ndist);
+                    if (nbits < atomicMin(&dist[u], nbits)) {
+                        atomicOr(&dirty[u / FPS_T], 1u);
+                        if (atomicExch(&fo[u], 1u) == 0u) qo[atomicAdd(&qn[cur ^ 1], 1)] = u;
+                    }
+                }
+            }
+            fence_sync();
+            if (t == 0) qn[cur] = 0;
+            __syncthreads();
+            cur ^= 1;
+        }
+        // maxima of the blocks that changed
+        if (t == 0) nd_ = 0;
+        __syncthreads();
+        for (int64_t b = t; b < nb; b += FPS_T)
+            if (dirty[b]) {
+                dirty[b] = 0;
+                dlist[atomicAdd(&nd_, 1)] = (int32_t)b;
+            }
+        fence_sync();
+        const int32_t ndirty = nd_;
+        for (int32_t j = 0; j < ndirty; ++j) {
+            const int64_t b = dlist[j];
+            const int64_t i = b * FPS_T + t;
+            rv[t] = i < n ? __longlong_as_double((long long)dist[i]) : -1.0;
+            ri[t] = (int32_t)i;
+            __syncthreads();
+            for (int off = FPS_T / 2; off > 0; off >>= 1) {
+                if (t < off && better(rv[t + off], ri[t + off], rv[t], ri[t])) {
+                    rv[t] = rv[t + off];
+                    ri[t] = ri[t + off];
+                }
+                __syncthreads();
+            }
+            if (t == 0) {
+                bmax[b] = rv[0];
+                bidx[b] = ri[0];
+            }
+            __syncthreads();
+        }
+        fence_sync();
+        // farthest vertex over the blocks
+        double bv = -1.0;
+        int32_t bi = INT32_MAX;
+        for (int64_t b = t; b < nb; b += FPS_T)
+            if (better(bmax[b], bidx[b], bv, bi)) {
+                bv = bmax[b];
+                bi = bidx[b];
+            }
+        rv[t] = bv;
+        ri[t] = bi;
+        __syncthreads();
+        for (int off = FPS_T / 2; off > 0; off >>= 1) {
+            if (t < off && better(rv[t + off], ri[t + off], rv[t], ri[t])) {
+                rv[t] = rv[t + off];
+                ri[t] = ri[t + off];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            if (!(rv[0] > 0)) stop = 1;   // no vertex left at a positive distance
+            sel = ri[0];
+        }
+        __syncthreads();
+        if (stop) {
+            if (t == 0) *status = 1;
+            return;
+        }
+    }
+}
+
+std::vector<int32_t> device_fps(const DevMesh& dm, int64_t count, uint64_t seed) {
+    const int64_t n = dm.nv;
+    const int64_t nb = (n + FPS_T - 1) / FPS_T;
+    DeviceBuffer dist, q0, q1, f0, f1, bmax, bidx, dirty, dlist, order, status;
+    dist.alloc((size_t)n * sizeof(unsigned long long));
+    q0.alloc((size_t)n * sizeof(int32_t));
+    q1.alloc((size_t)n * sizeof(int32_t));
+    f0.alloc((size_t)n * sizeof(unsigned int));
+    f1.alloc((size_t)n * sizeof(unsigned int));
+    bmax.alloc((size_t)nb * sizeof(double));
+    bidx.alloc((size_t)nb * sizeof(int32_t));
+    dirty.alloc((size_t)nb * sizeof(unsigned int));
+    dlist.alloc((size_t)nb * sizeof(int32_t));
+    order.alloc((size_t)count * sizeof(int32_t));
+    status.alloc(sizeof(int32_t));
+    BDCHECK(hipMemset(status.p, 0, sizeof(int32_t)));
+    const int32_t start = (int32_t)(seed % (uint64_t)n);
+    k_fps_init<<<grid_of(n, 256), 256>>>(n, dp<unsigned long long>(dist), dp<unsigned int>(f0), dp<unsigned int>(f1),
+                                         dp<unsigned int>(dirty), nb);
+    BDCHECK(hipGetLastError());
+    k_fps<<<1, FPS_T>>>(dp<int64_t>(dm.gptr), dp<int32_t>(dm.gnbr), dp<double>(dm.gw), n, count, start,
+                        dp<unsigned long long>(dist), dp<int32_t>(q0), dp<int32_t>(q1), dp<unsigned int>(f0),
+                        dp<unsigned int>(f1), dp<double>(bmax), dp<int32_t>(bidx), dp<unsigned int>(dirty),
+                        dp<int32_t>(dlist), dp<int32_t>(order), dp<int32_t>(status));
+    BDCHECK(hipGetLastError());
+    BDCHECK(hipDeviceSynchronize());
+    int32_t st = 0;
+    BDCHECK(hipMemcpy(&st, status.p, sizeof st, hipMemcpyDeviceToHost));
+    if (st) fail(HSIM_E_MESH, "farthest point sampling ran out of distinct vertices");
+    std::vector<int32_t> out(count);
+    BDCHECK(hipMemcpy(out.data(), order.p, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return out;
+}
+
+}  // namespace hsim

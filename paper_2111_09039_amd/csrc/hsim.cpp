@@ -15,6 +15,7 @@
 #include <numeric>
 
 #include "internal.h"
+#include "build_dev.h"
 #include "kernels.h"
 
 namespace hsim {
@@ -99,7 +100,7 @@ struct Prof {
     }
     void reset(bool enable) {
         on = enable;
-        solves = solve_cols = 0;
+        solves = solve_cols = solves32 = 0;
         used = 0;
         recs.clear();
     }
@@ -115,10 +116,12 @@ struct Prof {
         HIPCHECK(hipEventRecord(b, s));
         recs.push_back({a, b, cls, bytes, flops});
     }
-    int64_t solves = 0, solve_cols = 0;   // block solves since reset (counted with or without profiling)
+    // block solves since reset (counted with or without profiling), those with the FP32 factor
+    int64_t solves = 0, solve_cols = 0, solves32 = 0;
     void collect(hsim_stats& st, hipStream_t s) {
         st.block_solves = solves;
         st.block_solve_cols = solve_cols;
+        st.block_solves_fp32 = solves32;
         if (!on) return;
         HIPCHECK(hipStreamSynchronize(s));
         for (const Rec& r : recs) {
@@ -785,6 +788,7 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
     const int32_t* qi = dptr<int32_t>(L.q_items);
     P.solves += 1;
     P.solve_cols += ncols;
+    if (sizeof(TF) == sizeof(float)) P.solves32 += 1;
     auto qsolve = [&](int phase, const int64_t* rec, int32_t kmax) {
         HIPCHECK(launch_qsolve<TF>(phase, qinv, qinvT, D, fr, qi + rec[0], rec[1], dptr<double>(L.qrhs), H->ld, X,
                                    H->ld, col0, ncols, dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
@@ -1151,8 +1155,17 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         for (int64_t i = 0; i < nv; ++i)
             if (!(H->density[i] > 0) || !std::isfinite(H->density[i])) fail(HSIM_E_INVALID, "density must be positive");
     }
-    validate_mesh(m);
-    Graph g = edge_graph(m);
+    // mesh checks, edge graph and farthest point sampling on the device (the
+    // host build's results bit for bit), or on the host for host-only builds
+    const bool dev_build = !H->host_only && env_int("HSIM_HOST_HIERARCHY", 0) == 0;
+    DevMesh dm;
+    Graph g;
+    if (dev_build) {
+        device_mesh_graph(m, dm, g);
+    } else {
+        validate_mesh(m);
+        g = edge_graph(m);
+    }
     if (bo.boundary != 0 && bo.boundary != 1) fail(HSIM_E_INVALID, "boundary must be 0 (natural) or 1 (Dirichlet)");
     // level-0 unknowns: every vertex, or (Dirichlet) the vertices off the boundary
     std::vector<int32_t> dofs;
@@ -1182,7 +1195,8 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
     std::vector<int64_t> sizes = level_sizes(n0, T, nc, bo.growth_mode);
     for (int t = 1; t < T; ++t)
         if (sizes[t] >= sizes[t - 1]) fail(HSIM_E_INVALID, "level %d is not smaller than level %d (too many levels for this mesh)", t, t - 1);
-    std::vector<int32_t> order = farthest_point_sampling(g, nv, sizes[1], bo.seed);
+    std::vector<int32_t> order =
+        dev_build ? device_fps(dm, sizes[1], bo.seed) : farthest_point_sampling(g, nv, sizes[1], bo.seed);
     // levels
     for (int t = 0; t < T; ++t) {
         auto L = std::make_unique<Level>();

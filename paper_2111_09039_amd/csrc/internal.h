@@ -49,6 +49,7 @@ struct Mesh {
 // mesh.cpp
 void validate_mesh(const Mesh& m);
 Graph edge_graph(const Mesh& m);
+void check_connected(const Graph& g, int64_t nv);   // HSIM_E_MESH unless every vertex is reachable from 0
 double surface_area(const Mesh& m);
 // per vertex: 1 if it lies on an edge that belongs to exactly one triangle
 std::vector<char> boundary_vertex_flags(const Mesh& m);

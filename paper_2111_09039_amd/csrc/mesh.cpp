@@ -103,8 +103,12 @@ Graph edge_graph(const Mesh& m) {
         double dz = m.V[3 * i + 2] - m.V[3 * j + 2];
         g.w[k] = std::sqrt(dx * dx + dy * dy + dz * dz);
     }
-    // connectivity
-    std::vector<char> seen(m.nv, 0);
+    check_connected(g, m.nv);
+    return g;
+}
+
+void check_connected(const Graph& g, int64_t nv) {
+    std::vector<char> seen(nv, 0);
     std::vector<int32_t> stack{0};
     seen[0] = 1;
     int64_t count = 1;
@@ -118,8 +122,7 @@ Graph edge_graph(const Mesh& m) {
                 stack.push_back(g.nbr[k]);
             }
     }
-    if (count != m.nv) fail(HSIM_E_MESH, "mesh is not connected (%lld of %lld vertices reachable)", (long long)count, (long long)m.nv);
-    return g;
+    if (count != nv) fail(HSIM_E_MESH, "mesh is not connected (%lld of %lld vertices reachable)", (long long)count, (long long)nv);
 }
 
 static inline double tri_area(const Mesh& m, int64_t t) {
