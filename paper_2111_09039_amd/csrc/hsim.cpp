@@ -1140,6 +1140,16 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
     if (opts) bo = *opts;
     else hsim_default_build_opts(&bo);
     auto t0 = std::chrono::steady_clock::now();
+    // HSIM_VERBOSE=1: the time of every build phase on stderr
+    const bool verbose = env_int("HSIM_VERBOSE", 0) != 0;
+    auto tlast = t0;
+    auto phase = [&](const char* name) {
+        const auto now = std::chrono::steady_clock::now();
+        if (verbose)
+            std::fprintf(stderr, "[hsim build] %-28s %8.1f ms\n", name,
+                         std::chrono::duration<double, std::milli>(now - tlast).count());
+        tlast = now;
+    };
     std::unique_ptr<hsim_hierarchy> H(new hsim_hierarchy());
     H->host_only = (bo.flags & HSIM_BUILD_HOST_ONLY) != 0;
     if (!H->host_only) HIPCHECK(hipGetDevice(&H->device));
@@ -1166,6 +1176,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         validate_mesh(m);
         g = edge_graph(m);
     }
+    phase(dev_build ? "mesh checks + graph (device)" : "mesh checks + graph (host)");
     if (bo.boundary != 0 && bo.boundary != 1) fail(HSIM_E_INVALID, "boundary must be 0 (natural) or 1 (Dirichlet)");
     // level-0 unknowns: every vertex, or (Dirichlet) the vertices off the boundary
     std::vector<int32_t> dofs;
@@ -1197,6 +1208,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         if (sizes[t] >= sizes[t - 1]) fail(HSIM_E_INVALID, "level %d is not smaller than level %d (too many levels for this mesh)", t, t - 1);
     std::vector<int32_t> order =
         dev_build ? device_fps(dm, sizes[1], bo.seed) : farthest_point_sampling(g, nv, sizes[1], bo.seed);
+    phase(dev_build ? "farthest points (device)" : "farthest points (host)");
     // levels
     for (int t = 0; t < T; ++t) {
         auto L = std::make_unique<Level>();
@@ -1248,6 +1260,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
             for (int64_t e = L0.S.ptr[i]; e < L0.S.ptr[i + 1]; ++e)
                 if (L0.S.idx[e] == i) L0.Mval[e] = L0.mdiag[i];
     }
+    phase("assembly");
     for (int t = 0; t + 1 < T; ++t) {
         Level& L = *H->lv[t];
         Level& C = *H->lv[t + 1];
@@ -1264,6 +1277,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         }
         galerkin(L.U, L.S, L.Mval, C.S, C.Mval);
     }
+    phase("prolongation + Galerkin");
     for (int t = 0; t + 1 < T; ++t) {
         Level& L = *H->lv[t];
         std::vector<double> X(3 * L.n);
@@ -1271,6 +1285,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
             for (int c = 0; c < 3; ++c) X[3 * i + c] = m.V[3 * (int64_t)L.verts[i] + c];
         L.sy = analyse(L.S, X.data(), L.n);
     }
+    phase("ordering + symbolic");
     // device
     for (int t = H->host_only ? -1 : T - 1; t >= 0; --t) {
         Level& L = *H->lv[t];
@@ -1292,6 +1307,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         alloc_workspace(H.get());
         HIPCHECK(hipDeviceSynchronize());
     }
+    phase("device levels + workspace");
     H->ms_build = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = H.release();
     API_END

@@ -22,74 +22,107 @@ namespace hsim {
 namespace {
 
 constexpr int LEAF = 64;
+// subsets at least this large are split in their own OpenMP task
+constexpr size_t TASK_MIN = 16384;
 
+// Nested dissection.  Every call owns a distinct vertex subset; its marks in
+// `tag` carry the call's id (unique in the recursion tree), so concurrent
+// calls on disjoint subsets never read each other's sides.  The elimination
+// order of a subset is its first part, then its second part, then the
+// separator (ascending): the same in every schedule.
 struct ND {
     const Csr& G;
     const double* X;
-    std::vector<int32_t> side;     // scratch: -1 outside the current set
-    std::vector<int32_t> order;    // elimination order being built
-    std::vector<std::pair<int64_t, int32_t>> snodes;  // (start, size)
+    // per axis: (call id << 2) | side (0, 1: halves, 2: separator); -1 unmarked
+    std::vector<int64_t> tag[3];
 
-    ND(const Csr& g, const double* x, int64_t n) : G(g), X(x), side(n, -1) { order.reserve(n); }
-
-    void emit(const std::vector<int32_t>& W) {
-        if (W.empty()) return;
-        snodes.push_back({(int64_t)order.size(), (int32_t)W.size()});
-        order.insert(order.end(), W.begin(), W.end());
+    ND(const Csr& g, const double* x, int64_t n) : G(g), X(x) {
+        for (auto& t : tag) t.assign(n, -1);
     }
 
-    void run(std::vector<int32_t> W) {
+    // the split of W at the median plane of one axis: its separator (the
+    // smaller of the two boundary layers) and the two remaining halves
+    void split(const std::vector<int32_t>& W, int64_t id, int axis, std::vector<int32_t>& sep,
+               std::vector<int32_t>& left, std::vector<int32_t>& right) {
+        const size_t n = W.size(), half = n / 2;
+        std::vector<int64_t>& tg = tag[axis];
+        const int64_t mine = id << 2;
+        auto side_of = [&](int32_t u) -> int { return (tg[u] >> 2) == id ? (int)(tg[u] & 3) : -1; };
+        std::vector<int32_t> S(W);
+        std::nth_element(S.begin(), S.begin() + half, S.end(), [&](int32_t a, int32_t b) {
+            double xa = X[3 * a + axis], xb = X[3 * b + axis];
+            return xa < xb || (xa == xb && a < b);
+        });
+        for (size_t i = 0; i < n; ++i) tg[S[i]] = mine | (i < half ? 0 : 1);
+        std::vector<int32_t> bl, br;
+        for (size_t i = 0; i < n; ++i) {
+            int32_t v = S[i];
+            const int sv = side_of(v);
+            bool cross = false;
+            for (int64_t k = G.ptr[v]; k < G.ptr[v + 1] && !cross; ++k) {
+                const int su = side_of(G.idx[k]);
+                cross = su >= 0 && su != sv;
+            }
+            if (cross) (sv == 0 ? bl : br).push_back(v);
+        }
+        sep = bl.size() <= br.size() ? std::move(bl) : std::move(br);
+        for (int32_t v : sep) tg[v] = mine | 2;
+        left.clear();
+        right.clear();
+        for (size_t i = 0; i < n; ++i) {
+            const int sv = side_of(S[i]);
+            if (sv == 0) left.push_back(S[i]);
+            else if (sv == 1) right.push_back(S[i]);
+        }
+    }
+
+    // order: the subset's vertices in elimination order; sizes: its supernodes in order
+    void run(std::vector<int32_t> W, int64_t id, std::vector<int32_t>& order, std::vector<int32_t>& sizes) {
         if ((int)W.size() <= LEAF) {
-            emit(W);
+            order = std::move(W);
+            sizes.assign(1, (int32_t)order.size());
+            if (order.empty()) sizes.clear();
             return;
         }
-        const size_t n = W.size(), half = n / 2;
-        std::vector<int32_t> best_sep, best_l, best_r;
-        bool have = false;
+        const bool big = W.size() >= TASK_MIN;
+        std::vector<int32_t> sep[3], lft[3], rgt[3];
         for (int axis = 0; axis < 3; ++axis) {
-            std::vector<int32_t> S(W);
-            std::nth_element(S.begin(), S.begin() + half, S.end(), [&](int32_t a, int32_t b) {
-                double xa = X[3 * a + axis], xb = X[3 * b + axis];
-                return xa < xb || (xa == xb && a < b);
-            });
-            for (size_t i = 0; i < n; ++i) side[S[i]] = i < half ? 0 : 1;
-            std::vector<int32_t> bl, br;
-            for (size_t i = 0; i < n; ++i) {
-                int32_t v = S[i];
-                bool cross = false;
-                for (int64_t k = G.ptr[v]; k < G.ptr[v + 1] && !cross; ++k) {
-                    int32_t u = G.idx[k];
-                    cross = side[u] >= 0 && side[u] != side[v];
-                }
-                if (cross) (side[v] == 0 ? bl : br).push_back(v);
-            }
-            const bool use_left = bl.size() <= br.size();
-            const std::vector<int32_t>& sep = use_left ? bl : br;
-            if (!have || sep.size() < best_sep.size()) {
-                have = true;
-                best_sep = sep;
-                best_l.clear();
-                best_r.clear();
-                for (int32_t v : sep) side[v] = 2;
-                for (size_t i = 0; i < n; ++i) {
-                    int32_t v = S[i];
-                    if (side[v] == 0) best_l.push_back(v);
-                    else if (side[v] == 1) best_r.push_back(v);
-                }
-            }
-            for (size_t i = 0; i < n; ++i) side[S[i]] = -1;
+#pragma omp task shared(W, sep, lft, rgt) if (big)
+            split(W, id, axis, sep[axis], lft[axis], rgt[axis]);
+        }
+#pragma omp taskwait
+        // the smallest separator, the first axis on ties
+        int best = 0;
+        for (int axis = 1; axis < 3; ++axis)
+            if (sep[axis].size() < sep[best].size()) best = axis;
+        std::vector<int32_t> best_sep = std::move(sep[best]), best_l = std::move(lft[best]),
+                             best_r = std::move(rgt[best]);
+        for (int axis = 0; axis < 3; ++axis) {
+            sep[axis].clear();
+            lft[axis].clear();
+            rgt[axis].clear();
         }
         // a split that separates nothing: stop here
         if (best_l.empty() || best_r.empty()) {
-            emit(W);
+            order = std::move(W);
+            sizes.assign(1, (int32_t)order.size());
             return;
         }
         W.clear();
         W.shrink_to_fit();
-        run(std::move(best_l));
-        run(std::move(best_r));
-        std::sort(best_sep.begin(), best_sep.end(), [&](int32_t a, int32_t b) { return a < b; });
-        emit(best_sep);
+        std::vector<int32_t> ol, sl, orr, sr;
+#pragma omp task shared(ol, sl, best_l) if (big)
+        run(std::move(best_l), 2 * id, ol, sl);
+#pragma omp task shared(orr, sr, best_r) if (big)
+        run(std::move(best_r), 2 * id + 1, orr, sr);
+#pragma omp taskwait
+        std::sort(best_sep.begin(), best_sep.end());
+        order = std::move(ol);
+        order.insert(order.end(), orr.begin(), orr.end());
+        order.insert(order.end(), best_sep.begin(), best_sep.end());
+        sizes = std::move(sl);
+        sizes.insert(sizes.end(), sr.begin(), sr.end());
+        if (!best_sep.empty()) sizes.push_back((int32_t)best_sep.size());
     }
 };
 
@@ -99,21 +132,32 @@ inline int32_t round_up(int64_t x, int64_t m) { return (int32_t)((x + m - 1) / m
 
 Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
     Symbolic sy;
-    ND nd(S, coords, n);
+    std::vector<int32_t> order, sizes;
     {
+        ND nd(S, coords, n);
         std::vector<int32_t> all(n);
         std::iota(all.begin(), all.end(), 0);
-        nd.run(std::move(all));
+#pragma omp parallel
+#pragma omp single
+        nd.run(std::move(all), 1, order, sizes);
     }
-    if ((int64_t)nd.order.size() != n) fail(HSIM_E_INVALID, "ordering lost vertices");
-    sy.perm = nd.order;
+    if ((int64_t)order.size() != n) fail(HSIM_E_INVALID, "ordering lost vertices");
+    std::vector<std::pair<int64_t, int32_t>> snodes;   // (start, size) in elimination order
+    {
+        int64_t at = 0;
+        for (int32_t sz : sizes) {
+            snodes.push_back({at, sz});
+            at += sz;
+        }
+    }
+    sy.perm = std::move(order);
     sy.iperm.assign(n, 0);
     for (int64_t k = 0; k < n; ++k) sy.iperm[sy.perm[k]] = (int32_t)k;
 
-    const int64_t ns_count = (int64_t)nd.snodes.size();
+    const int64_t ns_count = (int64_t)snodes.size();
     std::vector<int32_t> snode_of(n);
     for (int64_t s = 0; s < ns_count; ++s)
-        for (int64_t c = nd.snodes[s].first; c < nd.snodes[s].first + nd.snodes[s].second; ++c) snode_of[c] = (int32_t)s;
+        for (int64_t c = snodes[s].first; c < snodes[s].first + snodes[s].second; ++c) snode_of[c] = (int32_t)s;
 
     // column structures, in elimination order (children before parents)
     std::vector<std::vector<int32_t>> st(ns_count);
@@ -121,7 +165,7 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
     std::vector<int32_t> parent(ns_count, -1), tlev(ns_count, 0);
     std::vector<int64_t> mark(n, -1);
     for (int64_t s = 0; s < ns_count; ++s) {
-        const int64_t a = nd.snodes[s].first, e = a + nd.snodes[s].second;
+        const int64_t a = snodes[s].first, e = a + snodes[s].second;
         std::vector<int32_t>& R = st[s];
         for (int64_t c = a; c < e; ++c) {
             int32_t v = sy.perm[c];
@@ -153,8 +197,8 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
     for (int64_t i = 0; i < ns_count; ++i) {
         int32_t s = byid[i];
         Front& f = sy.fronts[i];
-        f.start = nd.snodes[s].first;
-        f.ns = nd.snodes[s].second;
+        f.start = snodes[s].first;
+        f.ns = snodes[s].second;
         f.mu = (int32_t)st[s].size();
         f.ns_pad = round_up(f.ns, NB);
         f.mu_pad = round_up(f.mu, NB);
