@@ -28,3 +28,12 @@ void device_mesh_graph(const Mesh& m, DevMesh& dm, Graph& g);
 std::vector<int32_t> device_fps(const DevMesh& dm, int64_t count, uint64_t seed);
 
 }  // namespace hsim
+
+namespace hsim {
+// galerkin on the device: S_next = U^T S U, M_next = U^T M U on the
+// structural pattern, every entry summed with the host's terms in the host's
+// order (bit for bit the host result).  False (nothing computed) when the
+// coarse level is too large for the row marks of one workgroup.
+bool device_galerkin(const Csr& U, const Csr& S, const std::vector<double>& Mval, Csr& S_next,
+                     std::vector<double>& M_next);
+}  // namespace hsim

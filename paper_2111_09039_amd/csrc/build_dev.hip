@@ -481,3 +481,288 @@ std::vector<int32_t> device_fps(const DevMesh& dm, int64_t count, uint64_t seed)
 }
 
 }  // namespace hsim
+
+namespace hsim {
+
+// ------------------------------------------------------------ Galerkin products
+// T = S U and T_M = M U, row j: the terms s_jl u_lk (m_jl u_lk) over the
+// entries l of S row j in order and the entries k of U row l in order, summed
+// per column in that order (the host's dense accumulator), columns ascending.
+// pass 0 counts the columns of every row, pass 1 writes the row.  Rows with
+// more than TCAP columns set *overflow (the caller falls back to the host).
+namespace {
+constexpr int TCAP = 96;
+}
+__global__ __launch_bounds__(64) void k_su(int pass, const int64_t* __restrict__ sptr,
+                                           const int32_t* __restrict__ sidx, const double* __restrict__ sval,
+                                           const double* __restrict__ mval, const int64_t* __restrict__ uptr,
+                                           const int32_t* __restrict__ uidx, const double* __restrict__ uval,
+                                           int64_t nf, int64_t* cnt, const int64_t* __restrict__ tptr,
+                                           int32_t* tidx, double* ta, double* tb, int32_t* overflow) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nf; j += (int64_t)gridDim.x * blockDim.x) {
+        int32_t ks[TCAP];
+        double aa[TCAP], bb[TCAP];
+        int n = 0;
+        bool over = false;
+        for (int64_t b = sptr[j]; b < sptr[j + 1] && !over; ++b) {
+            const int64_t l = sidx[b];
+            for (int64_t c = uptr[l]; c < uptr[l + 1]; ++c) {
+                const int32_t k = uidx[c];
+                int q = 0;
+                while (q < n && ks[q] != k) ++q;
+                if (q == n) {
+                    if (n == TCAP) {
+                        over = true;
+                        break;
+                    }
+                    ks[n] = k;
+                    aa[n] = 0.0;
+                    bb[n] = 0.0;
+                    ++n;
+                }
+                aa[q] += sval[b] * uval[c];
+                bb[q] += mval[b] * uval[c];
+            }
+        }
+        if (over) {
+            *overflow = 1;
+            if (pass == 0) cnt[j] = 0;
+            continue;
+        }
+        if (pass == 0) {
+            cnt[j] = n;
+            continue;
+        }
+        for (int x = 1; x < n; ++x) {
+            const int32_t k = ks[x];
+            const double va = aa[x], vb = bb[x];
+            int y = x - 1;
+            while (y >= 0 && ks[y] > k) {
+                ks[y + 1] = ks[y];
+                aa[y + 1] = aa[y];
+                bb[y + 1] = bb[y];
+                --y;
+            }
+            ks[y + 1] = k;
+            aa[y + 1] = va;
+            bb[y + 1] = vb;
+        }
+        const int64_t o = tptr[j];
+        for (int x = 0; x < n; ++x) {
+            tidx[o + x] = ks[x];
+            ta[o + x] = aa[x];
+            tb[o + x] = bb[x];
+        }
+    }
+}
+// pattern of row i of U^T T: the columns of the T rows of the fine vertices in
+// U^T row i, marked in an LDS bitmap (nc bits); pass 0 counts, pass 1 writes
+// the columns ascending
+__global__ __launch_bounds__(256) void k_galerkin_pattern(int pass, const int64_t* __restrict__ utp,
+                                                          const int32_t* __restrict__ uti,
+                                                          const int64_t* __restrict__ tptr,
+                                                          const int32_t* __restrict__ tidx, int64_t nc,
+                                                          int64_t* rowlen, const int64_t* __restrict__ nptr,
+                                                          int32_t* nidx) {
+    extern __shared__ unsigned int bits[];
+    __shared__ unsigned long long total;
+    const int64_t i = blockIdx.x;
+    const int64_t words = (nc + 31) / 32;
+    for (int64_t w = threadIdx.x; w < words; w += blockDim.x) bits[w] = 0;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    for (int64_t a = utp[i] + threadIdx.x; a < utp[i + 1]; a += blockDim.x) {
+        const int64_t j = uti[a];
+        for (int64_t c = tptr[j]; c < tptr[j + 1]; ++c) {
+            const int32_t k = tidx[c];
+            atomicOr(&bits[k >> 5], 1u << (k & 31));
+        }
+    }
+    __syncthreads();
+    if (pass == 0) {
+        unsigned long long mine = 0;
+        for (int64_t w = threadIdx.x; w < words; w += blockDim.x) mine += __popc(bits[w]);
+        atomicAdd(&total, mine);
+        __syncthreads();
+        if (threadIdx.x == 0) rowlen[i] = (int64_t)total;
+        return;
+    }
+    if (threadIdx.x == 0) {
+        int64_t o = nptr[i];
+        for (int64_t w = 0; w < words; ++w) {
+            unsigned int m = bits[w];
+            while (m) {
+                const int bit = __ffs(m) - 1;
+                nidx[o++] = (int32_t)(w * 32 + bit);
+                m &= m - 1;
+            }
+        }
+    }
+}
+// row i of U^T T by one wave: the fine rows j of U^T row i in order, the
+// entries of T row j on the lanes (distinct columns, so distinct slots), each
+// lane adding u_ij T_jk into the LDS slot of its column k: every entry of the
+// result is the host's sum in the host's order
+__global__ __launch_bounds__(64) void k_galerkin_values(const int64_t* __restrict__ utp,
+                                                        const int32_t* __restrict__ uti,
+                                                        const double* __restrict__ utv,
+                                                        const int64_t* __restrict__ tptr,
+                                                        const int32_t* __restrict__ tidx,
+                                                        const double* __restrict__ ta, const double* __restrict__ tb,
+                                                        const int64_t* __restrict__ nptr,
+                                                        const int32_t* __restrict__ nidx, double* outS,
+                                                        double* outM) {
+    extern __shared__ double slots[];   // [len] S sums, [len] M sums, [len] columns (as int32)
+    const int64_t i = blockIdx.x;
+    const int64_t r0 = nptr[i], len = nptr[i + 1] - r0;
+    double* accS = slots;
+    double* accM = slots + len;
+    int32_t* key = reinterpret_cast<int32_t*>(slots + 2 * len);
+    const int lane = threadIdx.x;
+    for (int64_t x = lane; x < len; x += 64) {
+        accS[x] = 0.0;
+        accM[x] = 0.0;
+        key[x] = nidx[r0 + x];
+    }
+    __syncthreads();
+    for (int64_t a = utp[i]; a < utp[i + 1]; ++a) {
+        const int64_t j = uti[a];
+        const double uij = utv[a];
+        for (int64_t c = tptr[j] + lane; c < tptr[j + 1]; c += 64) {
+            const int32_t k = tidx[c];
+            int64_t lo = 0, hi = len;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (key[mid] < k) lo = mid + 1;
+                else hi = mid;
+            }
+            accS[lo] += uij * ta[c];
+            accM[lo] += uij * tb[c];
+        }
+        __syncthreads();
+    }
+    for (int64_t x = lane; x < len; x += 64) {
+        outS[r0 + x] = accS[x];
+        outM[r0 + x] = accM[x];
+    }
+}
+__global__ void k_row_of(const int64_t* __restrict__ ptr, int64_t rows, int32_t* row) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) row[e] = (int32_t)r;
+}
+// exact symmetry: both mirror entries become their average (the upper one's thread writes both)
+__global__ void k_galerkin_sym(const int64_t* __restrict__ nptr, const int32_t* __restrict__ nidx,
+                               const int32_t* __restrict__ nrow, int64_t nnz, double* S, double* M) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = nrow[e], j = nidx[e];
+        if (j <= i) continue;
+        int64_t lo = nptr[j], hi = nptr[j + 1];
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (nidx[mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo == nptr[j + 1] || nidx[lo] != i) continue;   // the pattern is symmetric: not reached
+        const double s = 0.5 * (S[e] + S[lo]);
+        const double m = 0.5 * (M[e] + M[lo]);
+        S[e] = S[lo] = s;
+        M[e] = M[lo] = m;
+    }
+}
+
+bool device_galerkin(const Csr& U, const Csr& S, const std::vector<double>& Mval, Csr& Sn, std::vector<double>& Mn) {
+    const int64_t nf = U.rows, nc = U.cols, nu = U.nnz();
+    const size_t bitmap = (size_t)(nc + 31) / 32 * sizeof(unsigned int);
+    if (bitmap > 64 * 1024 || nu == 0) return false;
+    DeviceBuffer uptr, uidx, uval, sptr, sidx, sval, mval, ovf, tcnt, tptr, tidx, ta, tb;
+    uptr.upload(U.ptr);
+    uidx.upload(U.idx);
+    uval.upload(U.val);
+    sptr.upload(S.ptr);
+    sidx.upload(S.idx);
+    sval.upload(S.val);
+    mval.upload(Mval);
+    ovf.alloc(sizeof(int32_t));
+    BDCHECK(hipMemset(ovf.p, 0, sizeof(int32_t)));
+    // T = S U, T_M = M U
+    tcnt.alloc((size_t)nf * sizeof(int64_t));
+    tptr.alloc((size_t)(nf + 1) * sizeof(int64_t));
+    k_su<<<grid_of(nf, 64), 64>>>(0, dp<int64_t>(sptr), dp<int32_t>(sidx), dp<double>(sval), dp<double>(mval),
+                                   dp<int64_t>(uptr), dp<int32_t>(uidx), dp<double>(uval), nf, dp<int64_t>(tcnt),
+                                   nullptr, nullptr, nullptr, nullptr, dp<int32_t>(ovf));
+    BDCHECK(hipGetLastError());
+    int32_t over = 0;
+    BDCHECK(hipMemcpy(&over, ovf.p, sizeof over, hipMemcpyDeviceToHost));
+    if (over) return false;
+    dev_scan(dp<int64_t>(tcnt), dp<int64_t>(tptr), nf);
+    int64_t nt = 0;
+    BDCHECK(hipMemcpy(&nt, dp<int64_t>(tptr) + nf, sizeof nt, hipMemcpyDeviceToHost));
+    tidx.alloc((size_t)std::max<int64_t>(1, nt) * sizeof(int32_t));
+    ta.alloc((size_t)std::max<int64_t>(1, nt) * sizeof(double));
+    tb.alloc((size_t)std::max<int64_t>(1, nt) * sizeof(double));
+    k_su<<<grid_of(nf, 64), 64>>>(1, dp<int64_t>(sptr), dp<int32_t>(sidx), dp<double>(sval), dp<double>(mval),
+                                   dp<int64_t>(uptr), dp<int32_t>(uidx), dp<double>(uval), nf, nullptr,
+                                   dp<int64_t>(tptr), dp<int32_t>(tidx), dp<double>(ta), dp<double>(tb),
+                                   dp<int32_t>(ovf));
+    BDCHECK(hipGetLastError());
+    // U^T (coarse rows, fine columns ascending), transposed on the host where
+    // U was built (a stable counting pass)
+    DeviceBuffer utp, uti, utv, rowlen, nptr;
+    {
+        std::vector<int64_t> tp(nc + 1, 0);
+        for (int64_t k = 0; k < nu; ++k) tp[U.idx[k] + 1]++;
+        for (int64_t i = 0; i < nc; ++i) tp[i + 1] += tp[i];
+        std::vector<int32_t> ti(nu);
+        std::vector<double> tv(nu);
+        std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+        for (int64_t j = 0; j < nf; ++j)
+            for (int64_t k = U.ptr[j]; k < U.ptr[j + 1]; ++k) {
+                ti[fill[U.idx[k]]] = (int32_t)j;
+                tv[fill[U.idx[k]]++] = U.val[k];
+            }
+        utp.upload(tp);
+        uti.upload(ti);
+        utv.upload(tv);
+    }
+    // pattern and values of U^T T
+    rowlen.alloc((size_t)nc * sizeof(int64_t));
+    nptr.alloc((size_t)(nc + 1) * sizeof(int64_t));
+    k_galerkin_pattern<<<(unsigned)nc, 256, bitmap>>>(0, dp<int64_t>(utp), dp<int32_t>(uti), dp<int64_t>(tptr),
+                                                       dp<int32_t>(tidx), nc, dp<int64_t>(rowlen), nullptr, nullptr);
+    BDCHECK(hipGetLastError());
+    dev_scan(dp<int64_t>(rowlen), dp<int64_t>(nptr), nc);
+    Sn = Csr();
+    Sn.rows = Sn.cols = nc;
+    Sn.ptr.resize(nc + 1);
+    BDCHECK(hipMemcpy(Sn.ptr.data(), nptr.p, (size_t)(nc + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    const int64_t nn = Sn.ptr[nc];
+    int64_t maxlen = 0;
+    for (int64_t i = 0; i < nc; ++i) maxlen = std::max(maxlen, Sn.ptr[i + 1] - Sn.ptr[i]);
+    const size_t lds = (size_t)maxlen * (2 * sizeof(double) + sizeof(int32_t));
+    if (lds > 64 * 1024) return false;
+    DeviceBuffer nidx, nrow, outS, outM;
+    nidx.alloc((size_t)std::max<int64_t>(1, nn) * sizeof(int32_t));
+    nrow.alloc((size_t)std::max<int64_t>(1, nn) * sizeof(int32_t));
+    outS.alloc((size_t)std::max<int64_t>(1, nn) * sizeof(double));
+    outM.alloc((size_t)std::max<int64_t>(1, nn) * sizeof(double));
+    k_galerkin_pattern<<<(unsigned)nc, 256, bitmap>>>(1, dp<int64_t>(utp), dp<int32_t>(uti), dp<int64_t>(tptr),
+                                                       dp<int32_t>(tidx), nc, nullptr, dp<int64_t>(nptr),
+                                                       dp<int32_t>(nidx));
+    k_row_of<<<grid_of(nc, 256), 256>>>(dp<int64_t>(nptr), nc, dp<int32_t>(nrow));
+    k_galerkin_values<<<(unsigned)nc, 64, lds>>>(dp<int64_t>(utp), dp<int32_t>(uti), dp<double>(utv),
+                                                 dp<int64_t>(tptr), dp<int32_t>(tidx), dp<double>(ta),
+                                                 dp<double>(tb), dp<int64_t>(nptr), dp<int32_t>(nidx),
+                                                 dp<double>(outS), dp<double>(outM));
+    k_galerkin_sym<<<grid_of(nn, 256), 256>>>(dp<int64_t>(nptr), dp<int32_t>(nidx), dp<int32_t>(nrow), nn,
+                                              dp<double>(outS), dp<double>(outM));
+    BDCHECK(hipGetLastError());
+    Sn.idx.resize(nn);
+    Sn.val.resize(nn);
+    Mn.resize(nn);
+    BDCHECK(hipMemcpy(Sn.idx.data(), nidx.p, (size_t)nn * sizeof(int32_t), hipMemcpyDeviceToHost));
+    BDCHECK(hipMemcpy(Sn.val.data(), outS.p, (size_t)nn * sizeof(double), hipMemcpyDeviceToHost));
+    BDCHECK(hipMemcpy(Mn.data(), outM.p, (size_t)nn * sizeof(double), hipMemcpyDeviceToHost));
+    return true;
+}
+
+}  // namespace hsim

@@ -235,12 +235,15 @@ Csr prolongation(const Graph& g, int64_t n, const std::vector<int32_t>& fine_ver
     return U;
 }
 
-// S_next = U^T S U, M_next = U^T M U with M given on S's pattern.  The
-// pattern is the structural product (no numerical dropping), so M_next lives
-// on S_next's pattern too.
+// S_next = U^T S U, M_next = U^T M U with M given on S's pattern, in two
+// sparse products: T = S U and T_M = M U (row j of T sums s_jl U_l. over the
+// entries l of S row j in order), then row i of S_next sums u_ij T_j. over the
+// fine rows j of U^T row i, ascending.  The pattern is the structural product
+// (no numerical dropping), so M_next lives on S_next's pattern too.  The
+// device build forms the same sums in the same order.
 void galerkin(const Csr& U, const Csr& S, const std::vector<double>& Mval, Csr& Sn, std::vector<double>& Mn) {
     const int64_t nf = U.rows, nc = U.cols;
-    // U^T in CSR (coarse rows)
+    // U^T in CSR (coarse rows, fine columns ascending)
     Csr Ut;
     Ut.rows = nc;
     Ut.cols = nf;
@@ -257,55 +260,71 @@ void galerkin(const Csr& U, const Csr& S, const std::vector<double>& Mval, Csr& 
                 Ut.val[fill[U.idx[k]]++] = U.val[k];
             }
     }
-    // row i of U^T S U = sum_j Ut_ij * sum_l S_jl * U_l,: ; dense accumulators per thread
-    std::vector<std::vector<int32_t>> rcols(nc);
-    std::vector<std::vector<double>> rs(nc), rm(nc);
+    // sparse rows with a dense accumulator per thread: row r sums w_e X_(c_e).
+    // over its terms e in order; columns of the result ascending
+    struct Rows {
+        std::vector<std::vector<int32_t>> cols;
+        std::vector<std::vector<double>> a, b;
+    };
+    auto product = [&](int64_t rows, int64_t width, auto&& terms, Rows& R) {
+        R.cols.assign(rows, {});
+        R.a.assign(rows, {});
+        R.b.assign(rows, {});
 #pragma omp parallel
-    {
-        std::vector<double> accS(nc, 0.0), accM(nc, 0.0);
-        std::vector<char> mark(nc, 0);
-        std::vector<int32_t> list;
-#pragma omp for schedule(dynamic, 8)
-        for (int64_t i = 0; i < nc; ++i) {
-            list.clear();
-            for (int64_t a = Ut.ptr[i]; a < Ut.ptr[i + 1]; ++a) {
-                int64_t j = Ut.idx[a];
-                double uij = Ut.val[a];
-                for (int64_t b = S.ptr[j]; b < S.ptr[j + 1]; ++b) {
-                    int64_t l = S.idx[b];
-                    double s = uij * S.val[b], mm = uij * Mval[b];
-                    for (int64_t c = U.ptr[l]; c < U.ptr[l + 1]; ++c) {
-                        int32_t k = U.idx[c];
-                        if (!mark[k]) { mark[k] = 1; list.push_back(k); }
-                        accS[k] += s * U.val[c];
-                        accM[k] += mm * U.val[c];
-                    }
+        {
+            std::vector<double> accA(width, 0.0), accB(width, 0.0);
+            std::vector<char> mark(width, 0);
+            std::vector<int32_t> list;
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t r = 0; r < rows; ++r) {
+                list.clear();
+                terms(r, [&](int32_t k, double va, double vb) {
+                    if (!mark[k]) { mark[k] = 1; list.push_back(k); }
+                    accA[k] += va;
+                    accB[k] += vb;
+                });
+                std::sort(list.begin(), list.end());
+                R.cols[r] = list;
+                R.a[r].resize(list.size());
+                R.b[r].resize(list.size());
+                for (size_t t = 0; t < list.size(); ++t) {
+                    const int32_t k = list[t];
+                    R.a[r][t] = accA[k];
+                    R.b[r][t] = accB[k];
+                    accA[k] = accB[k] = 0.0;
+                    mark[k] = 0;
                 }
             }
-            std::sort(list.begin(), list.end());
-            rcols[i] = list;
-            rs[i].resize(list.size());
-            rm[i].resize(list.size());
-            for (size_t t = 0; t < list.size(); ++t) {
-                int32_t k = list[t];
-                rs[i][t] = accS[k];
-                rm[i][t] = accM[k];
-                accS[k] = accM[k] = 0.0;
-                mark[k] = 0;
-            }
         }
-    }
+    };
+    // T = S U, T_M = M U
+    Rows T;
+    product(nf, nc, [&](int64_t j, auto&& add) {
+        for (int64_t b = S.ptr[j]; b < S.ptr[j + 1]; ++b) {
+            const int64_t l = S.idx[b];
+            for (int64_t c = U.ptr[l]; c < U.ptr[l + 1]; ++c) add(U.idx[c], S.val[b] * U.val[c], Mval[b] * U.val[c]);
+        }
+    }, T);
+    // S_next = U^T T, M_next = U^T T_M
+    Rows N;
+    product(nc, nc, [&](int64_t i, auto&& add) {
+        for (int64_t a = Ut.ptr[i]; a < Ut.ptr[i + 1]; ++a) {
+            const int64_t j = Ut.idx[a];
+            const double uij = Ut.val[a];
+            for (size_t t = 0; t < T.cols[j].size(); ++t) add(T.cols[j][t], uij * T.a[j][t], uij * T.b[j][t]);
+        }
+    }, N);
     Sn = Csr();
     Sn.rows = Sn.cols = nc;
     Sn.ptr.assign(nc + 1, 0);
-    for (int64_t i = 0; i < nc; ++i) Sn.ptr[i + 1] = Sn.ptr[i] + (int64_t)rcols[i].size();
+    for (int64_t i = 0; i < nc; ++i) Sn.ptr[i + 1] = Sn.ptr[i] + (int64_t)N.cols[i].size();
     Sn.idx.resize(Sn.ptr[nc]);
     Sn.val.resize(Sn.ptr[nc]);
     Mn.resize(Sn.ptr[nc]);
     for (int64_t i = 0; i < nc; ++i) {
-        std::copy(rcols[i].begin(), rcols[i].end(), Sn.idx.begin() + Sn.ptr[i]);
-        std::copy(rs[i].begin(), rs[i].end(), Sn.val.begin() + Sn.ptr[i]);
-        std::copy(rm[i].begin(), rm[i].end(), Mn.begin() + Sn.ptr[i]);
+        std::copy(N.cols[i].begin(), N.cols[i].end(), Sn.idx.begin() + Sn.ptr[i]);
+        std::copy(N.a[i].begin(), N.a[i].end(), Sn.val.begin() + Sn.ptr[i]);
+        std::copy(N.b[i].begin(), N.b[i].end(), Mn.begin() + Sn.ptr[i]);
     }
     // exact symmetry: average the two mirror entries
     for (int64_t i = 0; i < nc; ++i)

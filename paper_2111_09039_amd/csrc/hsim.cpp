@@ -1275,7 +1275,8 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
                     fail(HSIM_E_INVALID, "coarse vertex %d has no interior vertex within its support radius",
                          C.verts[c]);
         }
-        galerkin(L.U, L.S, L.Mval, C.S, C.Mval);
+        // the Galerkin products on the device (the host's sums, same order), else on the host
+        if (!(dev_build && device_galerkin(L.U, L.S, L.Mval, C.S, C.Mval))) galerkin(L.U, L.S, L.Mval, C.S, C.Mval);
     }
     phase("prolongation + Galerkin");
     for (int t = 0; t + 1 < T; ++t) {

@@ -36,6 +36,12 @@ pytestmark = pytest.mark.gpu
 
 P = 64
 TOL = 1e-10
+# The floored residual of the constant mode (eq. conv2 with lambda_c = lambda_1)
+# cannot fall below about u lambda_max / lambda_1 in FP64: a rounding-level
+# error of the constant vector is multiplied by S.  On the 200k torus that is
+# 2.2e-16 * 2.52e6 / 0.968 = 5.7e-10, so its forward solve asks for 2e-9
+# (the 2k copy's floor is far below 1e-10).
+TOL_200K = 2e-9
 
 
 def _loss_parts(lam0, n, seed=11):
@@ -123,9 +129,9 @@ def test_adjoint_fd_200k(cuda):
     n = len(V)
     Ft = torch.tensor(F, dtype=torch.int64)
     Vt = torch.tensor(V, requires_grad=True)
-    ev, X = eigs(Vt, torch.tensor(F), P, levels=2, tol=TOL)
+    ev, X = eigs(Vt, torch.tensor(F), P, levels=2, tol=TOL_200K)
     Hx = hs.Hierarchy(V, F, P + 8, levels=2)
-    lam_ext = Hx.solve(tol=TOL)[0].cpu().numpy()
+    lam_ext = Hx.solve(tol=TOL_200K)[0].cpu().numpy()
     Hx.close()
     w, lhat, full, T = _loss_parts(lam_ext, n)
     assert sum(len(i) for i in full) >= P - 4
@@ -144,7 +150,7 @@ def test_adjoint_fd_200k(cuda):
     # smooth function of V); the count exceeds the converged solve's, so the
     # iterate is at least as accurate (residual at the FP64 floor).
     H0 = hs.Hierarchy(V, F, P, levels=2)
-    it0 = H0.solve(tol=TOL)[3]["iters"][-1]
+    it0 = H0.solve(tol=TOL_200K)[3]["iters"][-1]
     H0.close()
     n_it = it0 + 6
 
