@@ -37,3 +37,13 @@ namespace hsim {
 bool device_galerkin(const Csr& U, const Csr& S, const std::vector<double>& Mval, Csr& S_next,
                      std::vector<double>& M_next);
 }  // namespace hsim
+
+namespace hsim {
+// prolongation on the device graph of dm (eq. radius, eq. basis, row
+// normalisation): the same U bit for bit (exact bounded distances, the same
+// weights and sums).  False (nothing computed) when a ball outgrows its work
+// arrays or a fine row would be empty (the host then builds U).
+bool device_prolongation(const DevMesh& dm, const std::vector<int32_t>& fine_verts, bool fine_is_all,
+                         const std::vector<int32_t>& coarse_verts, double sigma, double area, Csr& U,
+                         double* rho_out);
+}  // namespace hsim

@@ -766,3 +766,222 @@ bool device_galerkin(const Csr& U, const Csr& S, const std::vector<double>& Mval
 }
 
 }  // namespace hsim
+
+namespace hsim {
+
+// ------------------------------------------------------------ prolongation
+// Workgroup b owns the distance array dist + b n (all +inf between balls) and
+// takes the coarse vertices b, b + gridDim.x, ...: for each, rounds of
+// relaxation from its vertex that keep only distances below rho (the host's
+// bounded Dijkstra reaches exactly these vertices with exactly these
+// distances), then an entry (fine row, coarse column, 1 - d / rho) for every
+// reached fine vertex with a positive weight, and the touched distances reset.
+// Hand-overs between threads cross an agent-scope fence and a barrier.
+namespace {
+constexpr int PB_T = 256;
+}
+__global__ __launch_bounds__(PB_T) void k_prolong_balls(const int64_t* __restrict__ gptr,
+                                                        const int32_t* __restrict__ nbr,
+                                                        const double* __restrict__ w, int64_t n,
+                                                        const int32_t* __restrict__ coarse, int64_t nc,
+                                                        const int32_t* __restrict__ pos, double rho,
+                                                        unsigned long long* dist_all, unsigned int* flag_all,
+                                                        int32_t* q_all, int32_t* touched_all, int32_t cap,
+                                                        int32_t* erow, int32_t* ecol, double* ewt, int64_t ecap,
+                                                        unsigned long long* ecount, int32_t* overflow) {
+    __shared__ int32_t qn[2], nt, stop;
+    const int t = threadIdx.x;
+    unsigned long long* dist = dist_all + (int64_t)blockIdx.x * n;
+    unsigned int* flag = flag_all + (int64_t)blockIdx.x * n;
+    int32_t* Q[2] = {q_all + (int64_t)blockIdx.x * 2 * cap, q_all + (int64_t)blockIdx.x * 2 * cap + cap};
+    int32_t* touched = touched_all + (int64_t)blockIdx.x * cap;
+    const unsigned long long rbits = (unsigned long long)__double_as_longlong(rho);
+    for (int64_t ci = blockIdx.x; ci < nc; ci += gridDim.x) {
+        const int32_t src = coarse[ci];
+        if (t == 0) {
+            dist[src] = 0ull;
+            touched[0] = src;
+            nt = 1;
+            Q[0][0] = src;
+            qn[0] = 1;
+            qn[1] = 0;
+            stop = 0;
+        }
+        fence_sync();
+        int cur = 0;
+        while (true) {
+            const int32_t len = qn[cur];
+            if (len == 0 || stop) break;
+            for (int32_t e = t; e < len; e += PB_T) {
+                const int32_t v = Q[cur][e];
+                flag[v] = 0;
+                const double dv = __longlong_as_double((long long)dist[v]);
+                for (int64_t kk = gptr[v]; kk < gptr[v + 1]; ++kk) {
+                    const int32_t u = nbr[kk];
+                    const double nd = dv + w[kk];
+                    const unsigned long long nb = (unsigned long long)__double_as_longlong(nd);
+                    if (nb >= rbits) continue;
+                    const unsigned long long old = atomicMin(&dist[u], nb);
+                    if (nb < old) {
+                        if (old == 0x7ff0000000000000ull) {
+                            const int32_t p = atomicAdd(&nt, 1);
+                            if (p < cap) touched[p] = u;
+                            else stop = 1;
+                        }
+                        if (atomicExch(&flag[u], 1u) == 0u) {
+                            const int32_t p = atomicAdd(&qn[cur ^ 1], 1);
+                            if (p < cap) Q[cur ^ 1][p] = u;
+                            else stop = 1;
+                        }
+                    }
+                }
+            }
+            fence_sync();
+            if (t == 0) qn[cur] = 0;
+            __syncthreads();
+            cur ^= 1;
+        }
+        if (stop) {
+            if (t == 0) *overflow = 1;
+            return;
+        }
+        const int32_t cnt = nt;
+        for (int32_t e = t; e < cnt; e += PB_T) {
+            const int32_t v = touched[e];
+            const double d = __longlong_as_double((long long)dist[v]);
+            const int32_t row = pos[v];
+            if (row >= 0) {
+                const double wt = 1.0 - d / rho;
+                if (wt > 0.0) {
+                    const unsigned long long o = atomicAdd(ecount, 1ull);
+                    if ((int64_t)o < ecap) {
+                        erow[o] = row;
+                        ecol[o] = (int32_t)ci;
+                        ewt[o] = wt;
+                    } else {
+                        *overflow = 1;
+                    }
+                }
+            }
+            dist[v] = 0x7ff0000000000000ull;
+            flag[v] = 0;
+        }
+        fence_sync();
+    }
+}
+__global__ void k_fill_u32(unsigned int* p, int64_t n, unsigned int v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_count_rows(const int32_t* __restrict__ erow, int64_t ne, unsigned long long* cnt) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[erow[e]], 1ull);
+}
+__global__ void k_scatter_rows(const int32_t* __restrict__ erow, const int32_t* __restrict__ ecol,
+                               const double* __restrict__ ewt, int64_t ne, unsigned long long* cursor, int32_t* idx,
+                               double* val) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long o = atomicAdd(&cursor[erow[e]], 1ull);
+        idx[o] = ecol[e];
+        val[o] = ewt[e];
+    }
+}
+// every row: columns ascending, then U_jk = (1 / sum_k U_jk) * U_jk with the
+// sum taken in column order (the host's normalisation)
+__global__ void k_sort_normalise(const int64_t* __restrict__ ptr, int64_t rows, int32_t* idx, double* val) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = ptr[r], b = ptr[r + 1];
+        for (int64_t i = a + 1; i < b; ++i) {
+            const int32_t x = idx[i];
+            const double v = val[i];
+            int64_t j = i - 1;
+            while (j >= a && idx[j] > x) {
+                idx[j + 1] = idx[j];
+                val[j + 1] = val[j];
+                --j;
+            }
+            idx[j + 1] = x;
+            val[j + 1] = v;
+        }
+        double s = 0.0;
+        for (int64_t i = a; i < b; ++i) s += val[i];
+        const double inv = 1.0 / s;
+        for (int64_t i = a; i < b; ++i) val[i] = inv * val[i];
+    }
+}
+
+bool device_prolongation(const DevMesh& dm, const std::vector<int32_t>& fine_verts, bool fine_is_all,
+                         const std::vector<int32_t>& coarse_verts, double sigma, double area, Csr& U,
+                         double* rho_out) {
+    const int64_t n = dm.nv, nc = (int64_t)coarse_verts.size();
+    const int64_t nf = fine_is_all ? n : (int64_t)fine_verts.size();
+    const double rho = std::sqrt(sigma * area / ((double)nc * M_PI));
+    if (rho_out) *rho_out = rho;
+    std::vector<int32_t> pos(n, -1);
+    if (fine_is_all)
+        for (int64_t i = 0; i < n; ++i) pos[i] = (int32_t)i;
+    else
+        for (int64_t j = 0; j < nf; ++j) pos[fine_verts[j]] = (int32_t)j;
+    // work arrays: one distance array per workgroup (about 2 GB of them at most)
+    const int64_t slots = std::max<int64_t>(16, std::min<int64_t>(256, (int64_t(2) << 30) / (12 * std::max<int64_t>(1, n))));
+    const int32_t cap = (int32_t)std::min<int64_t>(n, 1 << 17);
+    const int64_t ecap = 16 * nf + 1024;
+    DeviceBuffer dpos, dcoarse, dist, flag, q, touched, erow, ecol, ewt, ecount, ovf;
+    dpos.upload(pos);
+    dcoarse.upload(coarse_verts);
+    dist.alloc((size_t)slots * n * sizeof(unsigned long long));
+    flag.alloc((size_t)slots * n * sizeof(unsigned int));
+    q.alloc((size_t)slots * 2 * cap * sizeof(int32_t));
+    touched.alloc((size_t)slots * cap * sizeof(int32_t));
+    erow.alloc((size_t)ecap * sizeof(int32_t));
+    ecol.alloc((size_t)ecap * sizeof(int32_t));
+    ewt.alloc((size_t)ecap * sizeof(double));
+    ecount.alloc(sizeof(unsigned long long));
+    ovf.alloc(sizeof(int32_t));
+    BDCHECK(hipMemset(ecount.p, 0, sizeof(unsigned long long)));
+    BDCHECK(hipMemset(ovf.p, 0, sizeof(int32_t)));
+    k_fill_u64<<<grid_of(slots * n, 256), 256>>>(dp<unsigned long long>(dist), slots * n, 0x7ff0000000000000ull);
+    k_fill_u32<<<grid_of(slots * n, 256), 256>>>(dp<unsigned int>(flag), slots * n, 0u);
+    k_prolong_balls<<<(unsigned)slots, PB_T>>>(dp<int64_t>(dm.gptr), dp<int32_t>(dm.gnbr), dp<double>(dm.gw), n,
+                                               dp<int32_t>(dcoarse), nc, dp<int32_t>(dpos), rho,
+                                               dp<unsigned long long>(dist), dp<unsigned int>(flag), dp<int32_t>(q),
+                                               dp<int32_t>(touched), cap, dp<int32_t>(erow), dp<int32_t>(ecol),
+                                               dp<double>(ewt), ecap, dp<unsigned long long>(ecount),
+                                               dp<int32_t>(ovf));
+    BDCHECK(hipGetLastError());
+    BDCHECK(hipDeviceSynchronize());
+    int32_t over = 0;
+    unsigned long long ne = 0;
+    BDCHECK(hipMemcpy(&over, ovf.p, sizeof over, hipMemcpyDeviceToHost));
+    BDCHECK(hipMemcpy(&ne, ecount.p, sizeof ne, hipMemcpyDeviceToHost));
+    if (over) return false;
+    DeviceBuffer cnt, ptr, cur, idx, val;
+    cnt.alloc((size_t)nf * sizeof(int64_t));
+    ptr.alloc((size_t)(nf + 1) * sizeof(int64_t));
+    k_fill_u64<<<grid_of(nf, 256), 256>>>(dp<unsigned long long>(cnt), nf, 0ull);
+    k_count_rows<<<grid_of((int64_t)ne, 256), 256>>>(dp<int32_t>(erow), (int64_t)ne, dp<unsigned long long>(cnt));
+    BDCHECK(hipGetLastError());
+    dev_scan(dp<int64_t>(cnt), dp<int64_t>(ptr), nf);
+    U = Csr();
+    U.rows = nf;
+    U.cols = nc;
+    U.ptr.resize(nf + 1);
+    BDCHECK(hipMemcpy(U.ptr.data(), ptr.p, (size_t)(nf + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < nf; ++j)
+        if (U.ptr[j + 1] == U.ptr[j]) return false;   // a fine vertex with no coarse vertex within rho
+    cur.alloc((size_t)nf * sizeof(int64_t));
+    BDCHECK(hipMemcpy(cur.p, ptr.p, (size_t)nf * sizeof(int64_t), hipMemcpyDeviceToDevice));
+    idx.alloc((size_t)std::max<unsigned long long>(1, ne) * sizeof(int32_t));
+    val.alloc((size_t)std::max<unsigned long long>(1, ne) * sizeof(double));
+    k_scatter_rows<<<grid_of((int64_t)ne, 256), 256>>>(dp<int32_t>(erow), dp<int32_t>(ecol), dp<double>(ewt),
+                                                        (int64_t)ne, dp<unsigned long long>(cur), dp<int32_t>(idx),
+                                                        dp<double>(val));
+    k_sort_normalise<<<grid_of(nf, 64), 64>>>(dp<int64_t>(ptr), nf, dp<int32_t>(idx), dp<double>(val));
+    BDCHECK(hipGetLastError());
+    U.idx.resize(ne);
+    U.val.resize(ne);
+    BDCHECK(hipMemcpy(U.idx.data(), idx.p, (size_t)ne * sizeof(int32_t), hipMemcpyDeviceToHost));
+    BDCHECK(hipMemcpy(U.val.data(), val.p, (size_t)ne * sizeof(double), hipMemcpyDeviceToHost));
+    return true;
+}
+
+}  // namespace hsim

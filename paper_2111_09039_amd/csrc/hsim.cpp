@@ -1264,7 +1264,10 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
     for (int t = 0; t + 1 < T; ++t) {
         Level& L = *H->lv[t];
         Level& C = *H->lv[t + 1];
-        L.U = prolongation(g, nv, L.verts, t == 0 && !restricted, C.verts, bo.support_sigma, H->area, &L.rho);
+        // U on the device (the host's U bit for bit), else on the host
+        if (!(dev_build && device_prolongation(dm, L.verts, t == 0 && !restricted, C.verts, bo.support_sigma, H->area,
+                                               L.U, &L.rho)))
+            L.U = prolongation(g, nv, L.verts, t == 0 && !restricted, C.verts, bo.support_sigma, H->area, &L.rho);
         if (t == 0 && restricted) {
             // a coarse basis function with no unknown in its support would make the
             // Galerkin operators singular
