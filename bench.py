@@ -413,6 +413,8 @@ def main():
                    "fp64_s": round(dt64, 5), "mixed_s": results.get("mixed", {}).get("s"),
                    "hierarchy_build_s": round(t_build, 3), "autotune_s": round(t_tune, 3),
                    "solve_plans": [(r["big_ns"], r["big_ns_bwd"]) for r in tune], "factor_nnz": info0["factor_nnz"],
+                   "inverse_panels": {"tree_levels": info0["qpanel_tree_levels"],
+                                      "stored_doubles": info0["qpanel_entries"]},
                    "fp64_iters": st64["iters"], "fp64_max_resid": results["fp64"]["max_resid"],
                    "mixed": {k: v for k, v in results.get("mixed", {}).items() if k != "stats"},
                    "mixed_forms": {k: results[k] for k in ("mixed_fp32_gram", "mixed_compensated_gram")

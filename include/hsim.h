@@ -246,8 +246,10 @@ hsim_status hsim_solve_batch(hsim_hierarchy* const* hs, int32_t count, const hsi
  * one level (the widest-supernode thresholds, in padded pivots, from which a
  * tree level's forward and backward sweeps multiply by the inverse panels of
  * its fronts, Q = [L11^-1; -L21 L11^-1], instead of running the wave-level
- * matrix-core solve) by timing a q-column block solve of each candidate
- * (forward 128/256/512 x backward 128/256/512)
+ * matrix-core solve) by timing a q-column block solve of the candidates
+ * 64/96/128/256/512 (the forward threshold with the backward one at 128, then
+ * the backward threshold with the chosen forward one; tree levels above the
+ * leaves whose widest front has at least 64 padded pivots have inverse panels)
  * on a factor of S - mu M with mu below the spectrum, and keep the fastest
  * for the following solves of this hierarchy.  With the environment variable
  * HSIM_TUNE_CACHE naming a file, the choice is looked up there first (keyed

@@ -316,6 +316,18 @@ __device__ __forceinline__ void fence_sync() {
     __threadfence();
     __syncthreads();
 }
+// the better (value, index) pair of the 64 lanes, in every lane
+__device__ __forceinline__ void wave_best(double& v, int32_t& i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o);
+        const int32_t oi = __shfl_xor(i, o);
+        if (better(ov, oi, v, i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+}
 }  // namespace
 
 __global__ void k_fps_init(int64_t n, unsigned long long* dist, unsigned int* f0, unsigned int* f1,
@@ -335,8 +347,8 @@ __global__ __launch_bounds__(FPS_T) void k_fps(const int64_t* __restrict__ gptr,
                                                unsigned int* dirty, int32_t* dlist, int32_t* order, int32_t* status) {
     __shared__ int32_t qn[2];
     __shared__ int32_t nd_;
-    __shared__ double rv[FPS_T];
-    __shared__ int32_t ri[FPS_T];
+    __shared__ double rv[FPS_T / 64];
+    __shared__ int32_t ri[FPS_T / 64];
     __shared__ int32_t sel, stop;
     const int t = threadIdx.x;
     const int64_t nb = (n + FPS_T - 1) / FPS_T;
@@ -371,14 +383,31 @@ __global__ __launch_bounds__(FPS_T) void k_fps(const int64_t* __restrict__ gptr,
                 const int32_t v = Q[cur][e];
                 FL[cur][v] = 0;
                 const double dv = __longlong_as_double((long long)dist[v]);
-                for (int64_t kk = gptr[v]; kk < gptr[v + 1]; ++kk) {
-                    const int32_t u = nbr[kk];
-                    const double ndist = dv + w[kk];
-                    const unsigned long long nbits = (unsigned long long)__double_as_longlong(ndist);
-                    if (nbits < atomicMin(&dist[u], nbits)) {
-                        atomicOr(&dirty[u / FPS_T], 1u);
-                        if (atomicExch(&fo[u], 1u) == 0u) qo[atomicAdd(&qn[cur ^ 1], 1)] = u;
+                const int64_t k0 = gptr[v], k1 = gptr[v + 1];
+                // up to eight edges at a time: their minima are independent
+                // atomics, issued together so that the round trips overlap
+                for (int64_t kb = k0; kb < k1; kb += 8) {
+                    int32_t uu[8];
+                    unsigned long long nb[8], old[8];
+                    unsigned int was[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        uu[j] = kb + j < k1 ? nbr[kb + j] : 0;
+                        nb[j] = kb + j < k1 ? (unsigned long long)__double_as_longlong(dv + w[kb + j]) : 0ull;
                     }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) old[j] = kb + j < k1 ? atomicMin(&dist[uu[j]], nb[j]) : 0ull;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        was[j] = 1u;
+                        if (kb + j < k1 && nb[j] < old[j]) {
+                            atomicOr(&dirty[uu[j] / FPS_T], 1u);
+                            was[j] = atomicExch(&fo[uu[j]], 1u);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (was[j] == 0u) qo[atomicAdd(&qn[cur ^ 1], 1)] = uu[j];
                 }
             }
             fence_sync();
@@ -395,28 +424,32 @@ __global__ __launch_bounds__(FPS_T) void k_fps(const int64_t* __restrict__ gptr,
                 dlist[atomicAdd(&nd_, 1)] = (int32_t)b;
             }
         fence_sync();
+        // a wave per changed block: 16 entries per lane, then the wave's
+        // shuffle reduction (the farthest vertex under a total order, so the
+        // order of the comparisons does not matter)
         const int32_t ndirty = nd_;
-        for (int32_t j = 0; j < ndirty; ++j) {
+        const int lane = t & 63, wv = t >> 6;
+        for (int32_t j = wv; j < ndirty; j += FPS_T / 64) {
             const int64_t b = dlist[j];
-            const int64_t i = b * FPS_T + t;
-            rv[t] = i < n ? __longlong_as_double((long long)dist[i]) : -1.0;
-            ri[t] = (int32_t)i;
-            __syncthreads();
-            for (int off = FPS_T / 2; off > 0; off >>= 1) {
-                if (t < off && better(rv[t + off], ri[t + off], rv[t], ri[t])) {
-                    rv[t] = rv[t + off];
-                    ri[t] = ri[t + off];
+            double bv = -1.0;
+            int32_t bi = INT32_MAX;
+#pragma unroll 4
+            for (int k = 0; k < FPS_T / 64; ++k) {
+                const int64_t i = b * FPS_T + k * 64 + lane;
+                const double d = i < n ? __longlong_as_double((long long)dist[i]) : -1.0;
+                if (better(d, (int32_t)i, bv, bi)) {
+                    bv = d;
+                    bi = (int32_t)i;
                 }
-                __syncthreads();
             }
-            if (t == 0) {
-                bmax[b] = rv[0];
-                bidx[b] = ri[0];
+            wave_best(bv, bi);
+            if (lane == 0) {
+                bmax[b] = bv;
+                bidx[b] = bi;
             }
-            __syncthreads();
         }
         fence_sync();
-        // farthest vertex over the blocks
+        // farthest vertex over the blocks: per thread, per wave, then wave 0
         double bv = -1.0;
         int32_t bi = INT32_MAX;
         for (int64_t b = t; b < nb; b += FPS_T)
@@ -424,19 +457,20 @@ __global__ __launch_bounds__(FPS_T) void k_fps(const int64_t* __restrict__ gptr,
                 bv = bmax[b];
                 bi = bidx[b];
             }
-        rv[t] = bv;
-        ri[t] = bi;
-        __syncthreads();
-        for (int off = FPS_T / 2; off > 0; off >>= 1) {
-            if (t < off && better(rv[t + off], ri[t + off], rv[t], ri[t])) {
-                rv[t] = rv[t + off];
-                ri[t] = ri[t + off];
-            }
-            __syncthreads();
+        wave_best(bv, bi);
+        if (lane == 0) {
+            rv[wv] = bv;
+            ri[wv] = bi;
         }
-        if (t == 0) {
-            if (!(rv[0] > 0)) stop = 1;   // no vertex left at a positive distance
-            sel = ri[0];
+        __syncthreads();
+        if (wv == 0) {
+            bv = lane < FPS_T / 64 ? rv[lane] : -1.0;
+            bi = lane < FPS_T / 64 ? ri[lane] : INT32_MAX;
+            wave_best(bv, bi);
+            if (lane == 0) {
+                if (!(bv > 0)) stop = 1;   // no vertex left at a positive distance
+                sel = bi;
+            }
         }
         __syncthreads();
         if (stop) {

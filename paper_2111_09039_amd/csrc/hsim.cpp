@@ -331,7 +331,7 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
 
 // ============================== reduced eigenproblem without allocation
 // Work arrays of hsim_step_rr_noalloc: one fixed region per device, sized
-// for HSIM_RR_NOALLOC_MAX_K unknowns (3.6 MB used of 4 MiB), held until the
+// for HSIM_RR_NOALLOC_MAX_K unknowns (4.17 MB used of 4 MiB), held until the
 // process ends.  Host code never names the array in a kernel argument or a
 // copy: it takes the device address from hipGetSymbolAddress, once per
 // device, with that device current.
@@ -363,9 +363,11 @@ constexpr int32_t BIG_NS = 256;
 // the backward sweep switches earlier (its wave-level form reduces over all
 // struct rows of a front in one wave)
 constexpr int32_t BIG_NS_BWD = 128;
-// tree levels whose widest supernode has at least this many padded pivots
-// get inverse panels in every factorisation (the plans choose among them)
-constexpr int32_t QPANEL_MIN_NS = 128;
+// tree levels above the leaves whose widest supernode has at least this many
+// padded pivots get inverse panels in every factorisation (the plans choose
+// among them); the leaf level holds the largest share of the factor and keeps
+// the wave-level solves unless its fronts are too wide for them
+constexpr int32_t QPANEL_MIN_NS = 64;
 
 struct TLev {
     int32_t f0 = 0, f1 = 0, ns_pad_max = 0;
@@ -487,7 +489,7 @@ static void setup_tree_levels(hsim_hierarchy* H, Level& L, std::vector<DFront>& 
             T.l_entries += (double)f.ns * (f.ns + 1) / 2 + (double)f.ns * f.mu;
             T.pivots += f.ns;
         }
-        T.q = T.ns_pad_max >= QPANEL_MIN_NS || T.ns_pad_max > wsolve_max_ns();
+        T.q = (t > 0 && T.ns_pad_max >= QPANEL_MIN_NS) || T.ns_pad_max > wsolve_max_ns();
         T.step0 = sy.step_ptr[t];
         T.step1 = sy.step_ptr[t + 1];
         int64_t qrow = 0;
@@ -789,10 +791,13 @@ static void solve_sweeps(hsim_hierarchy* H, Level& L, const TF* tiles, const TF*
     P.solves += 1;
     P.solve_cols += ncols;
     if (sizeof(TF) == sizeof(float)) P.solves32 += 1;
+    // the forward products gather the children's updates of the struct rows
+    // themselves (each update row written once)
+    constexpr bool fuse = true;
     auto qsolve = [&](int phase, const int64_t* rec, int32_t kmax) {
         HIPCHECK(launch_qsolve<TF>(phase, qinv, qinvT, D, fr, qi + rec[0], rec[1], dptr<double>(L.qrhs), H->ld, X,
                                    H->ld, col0, ncols, dptr<double>(L.ubuf), H->ld, dptr<int32_t>(L.gat), L.gw, md,
-                                   dptr<int32_t>(L.rows), s, Xin, kmax));
+                                   dptr<int32_t>(L.rows), s, Xin, kmax, fuse));
     };
     for (int32_t t = 0; t < sy.tree_levels; ++t) {
         const TLev& T = L.tl[t];
@@ -1834,8 +1839,7 @@ hsim_status hsim_solve_batch(hsim_hierarchy* const* hs, int32_t count, const hsi
 // Candidate launch plans of the block solves: the widest-front thresholds
 // (padded pivots) from which a tree level's forward / backward sweep
 // multiplies by the inverse panels instead of running the wave-level solve.
-static const int32_t kTuneFwd[] = {128, 256, 512};
-static const int32_t kTuneBwd[] = {128, 256, 512};
+static const int32_t kTuneNs[] = {64, 96, 128, 256, 512};
 static std::mutex g_tune_mu;
 
 static std::string tune_key(const hsim_hierarchy* h, const Level& L) {
@@ -1846,7 +1850,7 @@ static std::string tune_key(const hsim_hierarchy* h, const Level& L) {
     int64_t n = L.n, sc = 0;
     while (n >= 4) { n >>= 1; ++sc; }
     char buf[160];
-    std::snprintf(buf, sizeof buf, "qpanel-plan q=%d tree=%d top=%d size=%lld.%lld", h->q, (int)L.tl.size(), top,
+    std::snprintf(buf, sizeof buf, "inverse-panel-plan q=%d tree=%d top=%d size=%lld.%lld", h->q, (int)L.tl.size(), top,
                   (long long)sc, (long long)n);
     return buf;
 }
@@ -1908,24 +1912,35 @@ hsim_status hsim_autotune(hsim_hierarchy* h, int32_t level, void* stream, hsim_t
         hipEvent_t e0, e1;
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
-        double best = INFINITY;
-        int32_t bf = L.big_ns, bb = L.big_ns_bwd;
-        for (int32_t cf : kTuneFwd)
-            for (int32_t cb : kTuneBwd) {
-                plan_solve(L, cf, cb);
-                solve_level(h, L, X, 0, h->q, false, s, false, B);   // warm-up
-                double t = INFINITY;
-                for (int rep = 0; rep < 3; ++rep) {
-                    HIPCHECK(hipEventRecord(e0, s));
-                    solve_level(h, L, X, 0, h->q, false, s, false, B);
-                    HIPCHECK(hipEventRecord(e1, s));
-                    HIPCHECK(hipEventSynchronize(e1));
-                    float m = 0;
-                    HIPCHECK(hipEventElapsedTime(&m, e0, e1));
-                    t = std::min(t, (double)m);
-                }
-                if (t < best) best = t, bf = cf, bb = cb;
+        auto time_plan = [&](int32_t cf, int32_t cb) {
+            plan_solve(L, cf, cb);
+            solve_level(h, L, X, 0, h->q, false, s, false, B);   // warm-up
+            double t = INFINITY;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIPCHECK(hipEventRecord(e0, s));
+                solve_level(h, L, X, 0, h->q, false, s, false, B);
+                HIPCHECK(hipEventRecord(e1, s));
+                HIPCHECK(hipEventSynchronize(e1));
+                float m = 0;
+                HIPCHECK(hipEventElapsedTime(&m, e0, e1));
+                t = std::min(t, (double)m);
             }
+            return t;
+        };
+        // the forward and backward sweeps add up: the forward threshold is
+        // chosen with the backward one at 128, then the backward threshold
+        // with that forward one
+        double best = INFINITY;
+        int32_t bf = 128, bb = 128;
+        for (int32_t cf : kTuneNs) {
+            const double t = time_plan(cf, bb);
+            if (t < best) best = t, bf = cf;
+        }
+        for (int32_t cb : kTuneNs) {
+            if (cb == 128) continue;   // timed above
+            const double t = time_plan(bf, cb);
+            if (t < best) best = t, bb = cb;
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         plan_solve(L, bf, bb);

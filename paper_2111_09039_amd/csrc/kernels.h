@@ -93,13 +93,16 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
 // qinv: column-major Q tiles (phase 1), qinvT: transposed tiles (phase 3).
 // kmax (products): the longest contraction of the items in tiles (forward:
 // the largest nsb, backward: the largest Mt); it sets the waves that share
-// one output tile.
+// one output tile.  fuse (phases 0 and 1 of one forward sweep, both with the
+// same value): the gather fills only the pivot rows of R and the product
+// gathers the children's updates of the struct rows itself, writing each
+// update row once.
 template <class TF>
 hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D, const DFront* fronts,
                          const int32_t* items, int64_t nitems, double* R, int64_t ldr, double* X, int64_t ldx,
                          int32_t col0, int32_t ncols, double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw,
                          const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin = nullptr,
-                         int32_t kmax = 1);
+                         int32_t kmax = 1, bool fuse = false);
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 // partial Grams over row chunks of chunk_rows rows (gram_chunk_rows of the

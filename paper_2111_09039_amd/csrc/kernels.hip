@@ -589,7 +589,8 @@ struct WsolveWaves {
     static constexpr int value = 1;
 };
 // 16-column tiles per wave (one: many independent waves hide latency better
-// than fewer, wider ones on these solves)
+// than fewer, wider ones on these solves; two at the levels of up to 64
+// pivots measured 6 % slower for the whole solve)
 template <int NT>
 struct WsolveCols {
     static constexpr int value = 1;
@@ -598,12 +599,11 @@ struct WsolveCols {
 // forward sweep over one tree level: y = L11^-1 (b_J + children's updates),
 // u_J = (children's updates of the struct rows) - L21 y.  A wave takes CT
 // column tiles of 16.
-template <class TF, int NT>
+template <class TF, int NT, int CT>
 __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
     const TF* __restrict__ tiles, const TF* __restrict__ linv, const DFront* __restrict__ fr, int32_t f0, int32_t nfronts, int32_t groups, int32_t splits, double* X,
     int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg, TF* ubuf, int64_t ldu, const int32_t* __restrict__ gat,
     int32_t gw, const double* __restrict__ mdiag, const double* Xin) {
-    constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
     int32_t fi, grp, split;
     if (!wsolve_item_split(nfronts, groups, splits, fi, grp, split)) return;
@@ -781,12 +781,11 @@ __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_fwd(
 // backward sweep over one tree level: z = D^-1 y - L21^T x_struct, then
 // x_J = L11^-T z (last pivot block first); tilesT, linvT are the factor
 // tiles transposed one by one, so that L^T fragments load like L fragments
-template <class TF, int NT>
+template <class TF, int NT, int CT>
 __global__ __launch_bounds__(64 * WsolveWaves<NT>::value) void k_wsolve_bwd(
     const TF* __restrict__ tilesT, const TF* __restrict__ linvT, const TF* __restrict__ D,
     const DFront* __restrict__ fr, int32_t f0, int32_t nfronts, int32_t groups, double* X, int64_t ldx, int32_t col0, int32_t ncols, int32_t wpg,
     const int32_t* __restrict__ rows, int apply_dinv) {
-    constexpr int CT = WsolveCols<NT>::value;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
     int32_t fi, grp;
     if (!wsolve_item(nfronts, groups, fi, grp)) return;
@@ -976,23 +975,23 @@ hipError_t launch_wsolve(bool fwd, const TF* tiles, const TF* linv, const TF* D,
     if (ns_pad_max > wsolve_max_ns()) return hipErrorInvalidValue;
     int32_t wpg, groups;
     TF* ub = reinterpret_cast<TF*>(ubuf);
-#define HSIM_WS(NT)                                                                                              \
-    wsolve_shape(ncols, WsolveWaves<NT>::value, WCOLS * WsolveCols<NT>::value, wpg, groups);                                                     \
+#define HSIM_WS(NT, CT)                                                                                          \
+    wsolve_shape(ncols, WsolveWaves<NT>::value, WCOLS * CT, wpg, groups);                                         \
     const int64_t waves = (int64_t)(f1 - f0) * groups * wpg;                                                      \
     const int32_t splits = fwd && Xin != X                                                                      \
                                ? (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, WSOLVE_MIN_WAVES / waves))   \
                                : 1;                                                                              \
     const dim3 grid((unsigned)(cdiv(f1 - f0, NXCD) * NXCD * groups * splits)), block((unsigned)(64 * wpg));     \
     if (fwd)                                                                                                      \
-        k_wsolve_fwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, f1 - f0, groups, splits, X, ldx,    \
-                                                    col0, ncols, wpg, ub, ldu, gat, gw, mdiag, Xin);              \
+        k_wsolve_fwd<TF, NT, CT><<<grid, block, 0, s>>>(tiles, linv, fronts, f0, f1 - f0, groups, splits, X, ldx, \
+                                                        col0, ncols, wpg, ub, ldu, gat, gw, mdiag, Xin);          \
     else                                                                                                          \
-        k_wsolve_bwd<TF, NT><<<grid, block, 0, s>>>(tiles, linv, D, fronts, f0, f1 - f0, groups, X, ldx, col0,   \
-                                                    ncols, wpg, rows, apply_dinv ? 1 : 0);
-    if (ns_pad_max <= 32) { HSIM_WS(2) }
-    else if (ns_pad_max <= 64) { HSIM_WS(4) }
-    else if (ns_pad_max <= 128) { HSIM_WS(8) }
-    else { HSIM_WS(16) }
+        k_wsolve_bwd<TF, NT, CT><<<grid, block, 0, s>>>(tiles, linv, D, fronts, f0, f1 - f0, groups, X, ldx,     \
+                                                        col0, ncols, wpg, rows, apply_dinv ? 1 : 0);
+    if (ns_pad_max <= 32) { HSIM_WS(2, WsolveCols<2>::value) }
+    else if (ns_pad_max <= 64) { HSIM_WS(4, WsolveCols<4>::value) }
+    else if (ns_pad_max <= 128) { HSIM_WS(8, WsolveCols<8>::value) }
+    else { HSIM_WS(16, WsolveCols<16>::value) }
 #undef HSIM_WS
     return hipGetLastError();
 }
@@ -1008,20 +1007,22 @@ template hipError_t launch_wsolve<float>(bool, const float*, const float*, const
 // ---------------------------------------------------------------------------
 // Block solves through the inverse panels Q = [L11^-1; -L21 L11^-1] of the
 // factorisation.  Per tree level and direction two launches:
-//   forward:  gather  R(pivots) = mdiag b + children's updates, update rows =
-//                     children's updates of the struct rows;
-//             product y = Q_piv R -> X, update rows += Q_struct R
+//   forward:  gather  R(pivots) = mdiag b + children's updates (and, unless
+//                     the product does it, update rows = children's updates
+//                     g of the struct rows);
+//             product y = Q_piv R -> X, update rows = g + Q_struct R
 //                     (u = g - L21 L11^-1 b' = g + Q_struct b');
 //   backward: gather  R = [D^-1 y; x at the struct rows];
 //             product x = Q^T R -> X (= L11^-T (D^-1 y - L21^T x_struct)).
 // R is a scratch block whose rows follow each front's local index space
 // (pivot r at qrow + r, struct row s at qrow + ns_pad + s; padding rows are
-// written as zeros).  The products run on the FP64 matrix cores, one wave per
-// (16-row output tile, 16 columns), the Q fragments straight from the tiles
-// (forward: the column-major tiles; backward: the transposed ones, so both
-// load 16 consecutive values per lane group), the next tile's operands loaded
-// while the current one is applied.  Nothing depends on anything else within
-// a launch, so a wide front is no longer a chain of launches.
+// written as zeros).  The products run on the FP64 matrix cores, a workgroup
+// per (32-row output tile, 32 columns) whose waves split the contraction, the
+// Q fragments straight from the tiles (forward: the column-major tiles;
+// backward: the transposed ones, so both load 16 consecutive values per lane
+// group), the next tile's operands loaded while the current one is applied.
+// Nothing depends on anything else within a launch, so a wide front is not a
+// chain of launches.
 
 // items: (front, 32-row tile of [0, nsb + struct tiles)); 64 columns per blockIdx.y
 template <class TF>
@@ -1031,12 +1032,13 @@ __global__ __launch_bounds__(256) void k_qsolve_gather(int fwd, const DFront* __
                                                        int32_t ncols, TF* ubuf, int64_t ldu,
                                                        const int32_t* __restrict__ gat, int32_t gw,
                                                        const double* __restrict__ mdiag, const TF* __restrict__ D,
-                                                       const int32_t* __restrict__ rows) {
+                                                       const int32_t* __restrict__ rows, int pivots_only) {
     const DFront f = fr[items[2 * blockIdx.x]];
     const int tr = items[2 * blockIdx.x + 1];
     const int32_t c = col0 + 64 * blockIdx.y + (threadIdx.x & 63);
     if (c >= col0 + ncols) return;
     const bool piv = tr < f.nsb;
+    if (!piv && pivots_only) return;   // the forward product gathers the struct rows itself
     for (int i = threadIdx.x >> 6; i < T32; i += 4) {
         if (piv) {
             const int p = tr * T32 + i;
@@ -1074,29 +1076,33 @@ __global__ __launch_bounds__(256) void k_qsolve_gather(int fwd, const DFront* __
     }
 }
 
-// 32 rows of columns c and c + 16 of R starting at row r0 of the front's index
-// space, as the B operands of the eight k-steps of one tile (rows at or past
-// kmax, and columns past the block: 0)
+// 32 rows of the CT column tiles c + 16 ct of R starting at row r0 of the
+// front's index space, as the B operands of the eight k-steps of one tile
+// (rows at or past kmax, and column tiles past the block: 0)
+template <int CT>
 __device__ __forceinline__ void q_rhs(const double* __restrict__ R, int64_t ldr, int64_t r0, int kmax, int32_t c,
-                                      bool ok0, bool ok1, double (&b)[2][8]) {
+                                      int ctn, double (&b)[CT][8]) {
     const int lr = (threadIdx.x & 63) >> 4;
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
         const int r = 4 * ks + lr;
         const double* p = R + (r0 + r) * ldr + c;
-        b[0][ks] = (r < kmax && ok0) ? p[0] : 0.0;
-        b[1][ks] = (r < kmax && ok1) ? p[16] : 0.0;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) b[ct][ks] = (r < kmax && ct < ctn) ? p[16 * ct] : 0.0;
     }
 }
 
 // acc[h][ct] += Q fragment rows (half h) times the B operands of column tile
-// ct over the contraction rows [4 ks0_h, kmax_h) (whole k-steps)
-__device__ __forceinline__ void q_mm(const double (&a)[2][8], const double (&b)[2][8], int kmax0, int kmax1,
-                                     int ks0h1, dbl4 (&acc)[2][2]) {
+// ct over the contraction rows [4 ks0_h, kmax_h) (whole k-steps); column
+// tiles at or past ctn (wave-uniform) are skipped
+template <int CT>
+__device__ __forceinline__ void q_mm(const double (&a)[2][8], const double (&b)[CT][8], int kmax0, int kmax1,
+                                     int ks0h1, int ctn, dbl4 (&acc)[2][CT]) {
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
+        for (int ct = 0; ct < CT; ++ct) {
+            if (ct >= ctn) continue;
             if (4 * ks < kmax0) acc[0][ct] = mfma4(a[0][ks], b[ct][ks], acc[0][ct]);
             if (4 * ks < kmax1 && ks >= ks0h1) acc[1][ct] = mfma4(a[1][ks], b[ct][ks], acc[1][ct]);
         }
@@ -1104,86 +1110,123 @@ __device__ __forceinline__ void q_mm(const double (&a)[2][8], const double (&b)[
 }
 
 // the partial sums of the nw waves of a workgroup added in wave order (wave 0
-// returns true and holds the sum); red: nw x 4 x 64 dbl4 of dynamic LDS
-__device__ __forceinline__ bool q_reduce(dbl4 (&acc)[2][2], int nw, dbl4* red) {
+// returns true and holds the sum), two column tiles at a time; red: nw x 4 x
+// 64 dbl4 of dynamic LDS
+template <int CT>
+__device__ __forceinline__ bool q_reduce(dbl4 (&acc)[2][CT], int nw, dbl4* red) {
     if (nw == 1) return true;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int c0 = 0; c0 < CT; c0 += 2) {
+        if (c0 > 0) __syncthreads();   // wave 0 has read the previous pair
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) red[(w * 4 + 2 * h + ct) * 64 + lane] = acc[h][ct];
-    __syncthreads();
-    if (w != 0) return false;
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+            for (int ct = 0; ct < 2; ++ct) red[(w * 4 + 2 * h + ct) * 64 + lane] = acc[h][c0 + ct];
+        __syncthreads();
+        if (w == 0) {
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            dbl4 s = red[(2 * h + ct) * 64 + lane];
-            for (int k = 1; k < nw; ++k) s += red[(k * 4 + 2 * h + ct) * 64 + lane];
-            acc[h][ct] = s;
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    dbl4 sum = red[(2 * h + ct) * 64 + lane];
+                    for (int k = 1; k < nw; ++k) sum += red[(k * 4 + 2 * h + ct) * 64 + lane];
+                    acc[h][c0 + ct] = sum;
+                }
         }
-    return true;
+    }
+    return w == 0;
 }
 
-// Both products: a workgroup of nw waves per (item, 32 columns); the item is
-// a 32-row output tile of one front, the wave owns its two 16-row halves times
-// two 16-column tiles (four accumulators), the nw waves take every nw-th tile
-// of the contraction and add their sums in wave order.  The next tile's
-// operands are loaded while the current one is applied.
+// Both products: a workgroup of nw waves per (item, 16 CT columns); the item
+// is a 32-row output tile of one front, the wave owns its two 16-row halves
+// times CT 16-column tiles, the nw waves take every nw-th tile of the
+// contraction and add their sums in wave order.  The next tile's operands are
+// loaded while the current one is applied.
 // Forward, items (front, I), I < Mt: rows of tile I of Q R (J <= min(I, nsb - 1)).
-template <class TF>
+template <class TF, int CT>
 __global__ __launch_bounds__(512) void k_qsolve_fwd(const TF* __restrict__ qinv, const DFront* __restrict__ fr,
                                                     const int32_t* __restrict__ items, int32_t nitems, int32_t groups,
                                                     int32_t nw, const double* __restrict__ R, int64_t ldr, double* X,
-                                                    int64_t ldx, int32_t col0, int32_t ncols, TF* ubuf, int64_t ldu) {
+                                                    int64_t ldx, int32_t col0, int32_t ncols, TF* ubuf, int64_t ldu,
+                                                    const int32_t* __restrict__ gat, int32_t gw) {
     extern __shared__ dbl4 qred[];
     int32_t it, grp;
     if (!wsolve_item(nitems, groups, it, grp)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t c = col0 + 32 * grp + (lane & 15);
-    const bool ok0 = c < col0 + ncols, ok1 = c + 16 < col0 + ncols;
+    const int32_t cw = col0 + 16 * CT * grp;   // first column of the wave's block
+    const int32_t c = cw + (lane & 15);
+    const int ctn = min(CT, (int)((col0 + ncols - cw + 15) >> 4));   // column tiles that hold columns
+    const int32_t cend = col0 + ncols;
     const DFront f = fr[items[2 * it]];
     const int I = items[2 * it + 1];
     const int J1 = min(I, f.nsb - 1);
     const TF* Q = qinv + f.q_base;
-    dbl4 acc[2][2] = {{dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}}, {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}}};
-    double a[2][8], b[2][8];
+    // gat given: the children's updates g of this tile's struct rows are
+    // gathered here (wave 0, loaded before the products) instead of by the
+    // gather launch, and the update rows are written once as g + Q_struct b'
+    const bool own_g = gat != nullptr && I >= f.nsb;
+    double g[2][CT][4];
+    if (own_g && w == 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int sr = (I - f.nsb) * T32 + 16 * h + lr + 4 * v;
+                const int32_t* gr = gat + (f.gather_base + f.ns + sr) * gw;
+                const bool live = sr < f.mu && (f.flags & DFRONT_GATHER);
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) g[h][ct][v] = 0.0;
+                if (!live) continue;
+                for (int cg = 0; cg < gw; ++cg) {
+                    const int32_t src = gr[cg];
+                    if (src < 0) continue;
+#pragma unroll
+                    for (int ct = 0; ct < CT; ++ct)
+                        if (ct < ctn && c + 16 * ct < cend) g[h][ct][v] += (double)ubuf[(int64_t)src * ldu + c + 16 * ct];
+                }
+            }
+    }
+    dbl4 acc[2][CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[0][ct] = acc[1][ct] = dbl4{0, 0, 0, 0};
+    double a[2][8], b[CT][8];
     int J = w;
     if (J <= J1) {
         frag_rows(Q + tri(f.Mt, I, J) * TT, 0, false, a[0]);
         frag_rows(Q + tri(f.Mt, I, J) * TT, 1, false, a[1]);
-        q_rhs(R, ldr, f.qrow + T32 * J, min(T32, f.ns - T32 * J), c, ok0, ok1, b);
+        q_rhs<CT>(R, ldr, f.qrow + T32 * J, min(T32, f.ns - T32 * J), c, ctn, b);
     }
 #pragma unroll 1
     for (; J <= J1; J += nw) {
-        double an[2][8], bn[2][8];
+        double an[2][8], bn[CT][8];
         const int Jn = J + nw;
         if (Jn <= J1) {
             frag_rows(Q + tri(f.Mt, I, Jn) * TT, 0, false, an[0]);
             frag_rows(Q + tri(f.Mt, I, Jn) * TT, 1, false, an[1]);
-            q_rhs(R, ldr, f.qrow + T32 * Jn, min(T32, f.ns - T32 * Jn), c, ok0, ok1, bn);
+            q_rhs<CT>(R, ldr, f.qrow + T32 * Jn, min(T32, f.ns - T32 * Jn), c, ctn, bn);
         }
         // the diagonal tile of Q is lower triangular: rows 0..15 end at column 15
         const int km = min(T32, f.ns - T32 * J);
-        q_mm(a, b, J == I ? min(km, 16) : km, km, 0, acc);
+        q_mm<CT>(a, b, J == I ? min(km, 16) : km, km, 0, ctn, acc);
         if (Jn <= J1) {
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks) {
                 a[0][ks] = an[0][ks];
                 a[1][ks] = an[1][ks];
-                b[0][ks] = bn[0][ks];
-                b[1][ks] = bn[1][ks];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) b[ct][ks] = bn[ct][ks];
             }
         }
     }
-    if (!q_reduce(acc, nw, qred)) return;
+    if (!q_reduce<CT>(acc, nw, qred)) return;
     const bool piv = I < f.nsb;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            if (!(ct ? ok1 : ok0)) continue;
+        for (int ct = 0; ct < CT; ++ct) {
             const int32_t cc = c + 16 * ct;
+            if (ct >= ctn || cc >= cend) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = 16 * h + lr + 4 * v;
@@ -1194,7 +1237,7 @@ __global__ __launch_bounds__(512) void k_qsolve_fwd(const TF* __restrict__ qinv,
                     const int sr = (I - f.nsb) * T32 + r;
                     if (sr < f.mu) {
                         TF* u = ubuf + (f.ubuf_row + sr) * ldu + cc;
-                        *u = (TF)((double)*u + acc[h][ct][v]);
+                        *u = own_g ? (TF)(g[h][ct][v] + acc[h][ct][v]) : (TF)((double)*u + acc[h][ct][v]);
                     }
                 }
             }
@@ -1203,7 +1246,7 @@ __global__ __launch_bounds__(512) void k_qsolve_fwd(const TF* __restrict__ qinv,
 
 // Backward, items (front, C), C < nsb: pivot rows of tile C of Q^T R, the sum
 // over tile rows I >= C of Q(I, C)^T R(I)
-template <class TF>
+template <class TF, int CT>
 __global__ __launch_bounds__(512) void k_qsolve_bwd(const TF* __restrict__ qinvT, const DFront* __restrict__ fr,
                                                     const int32_t* __restrict__ items, int32_t nitems, int32_t groups,
                                                     int32_t nw, const double* __restrict__ R, int64_t ldr, double* X,
@@ -1212,52 +1255,57 @@ __global__ __launch_bounds__(512) void k_qsolve_bwd(const TF* __restrict__ qinvT
     int32_t it, grp;
     if (!wsolve_item(nitems, groups, it, grp)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane >> 4;
-    const int32_t c = col0 + 32 * grp + (lane & 15);
-    const bool ok0 = c < col0 + ncols, ok1 = c + 16 < col0 + ncols;
+    const int32_t cw = col0 + 16 * CT * grp;
+    const int32_t c = cw + (lane & 15);
+    const int ctn = min(CT, (int)((col0 + ncols - cw + 15) >> 4));
+    const int32_t cend = col0 + ncols;
     const DFront f = fr[items[2 * it]];
     const int C = items[2 * it + 1];
     const TF* Q = qinvT + f.q_base;
     auto rows_of = [&](int I) { return I < f.nsb ? min(T32, f.ns - T32 * I) : min(T32, f.mu - T32 * (I - f.nsb)); };
-    dbl4 acc[2][2] = {{dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}}, {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}}};
-    double a[2][8], b[2][8];
+    dbl4 acc[2][CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[0][ct] = acc[1][ct] = dbl4{0, 0, 0, 0};
+    double a[2][8], b[CT][8];
     int I = C + w;
     if (I < f.Mt) {
         frag_rows(Q + tri(f.Mt, I, C) * TT, 0, false, a[0]);
         frag_rows(Q + tri(f.Mt, I, C) * TT, 1, false, a[1]);
-        q_rhs(R, ldr, f.qrow + T32 * I, rows_of(I), c, ok0, ok1, b);
+        q_rhs<CT>(R, ldr, f.qrow + T32 * I, rows_of(I), c, ctn, b);
     }
 #pragma unroll 1
     for (; I < f.Mt; I += nw) {
-        double an[2][8], bn[2][8];
+        double an[2][8], bn[CT][8];
         const int In = I + nw;
         if (In < f.Mt) {
             frag_rows(Q + tri(f.Mt, In, C) * TT, 0, false, an[0]);
             frag_rows(Q + tri(f.Mt, In, C) * TT, 1, false, an[1]);
-            q_rhs(R, ldr, f.qrow + T32 * In, rows_of(In), c, ok0, ok1, bn);
+            q_rhs<CT>(R, ldr, f.qrow + T32 * In, rows_of(In), c, ctn, bn);
         }
         // Q(C, C) is lower triangular: columns 16..31 start at row 16
         const int km = rows_of(I);
-        q_mm(a, b, km, km, I == C ? 4 : 0, acc);
+        q_mm<CT>(a, b, km, km, I == C ? 4 : 0, ctn, acc);
         if (In < f.Mt) {
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks) {
                 a[0][ks] = an[0][ks];
                 a[1][ks] = an[1][ks];
-                b[0][ks] = bn[0][ks];
-                b[1][ks] = bn[1][ks];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) b[ct][ks] = bn[ct][ks];
             }
         }
     }
-    if (!q_reduce(acc, nw, qred)) return;
+    if (!q_reduce<CT>(acc, nw, qred)) return;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            if (!(ct ? ok1 : ok0)) continue;
+        for (int ct = 0; ct < CT; ++ct) {
+            const int32_t cc = c + 16 * ct;
+            if (ct >= ctn || cc >= cend) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int p = C * T32 + 16 * h + lr + 4 * v;
-                if (p < f.ns) X[(f.start + p) * ldx + c + 16 * ct] = acc[h][ct][v];
+                if (p < f.ns) X[(f.start + p) * ldx + cc] = acc[h][ct][v];
             }
         }
 }
@@ -1266,26 +1314,30 @@ template <class TF>
 hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D, const DFront* fronts,
                          const int32_t* items, int64_t nitems, double* R, int64_t ldr, double* X, int64_t ldx,
                          int32_t col0, int32_t ncols, double* ubuf, int64_t ldu, const int32_t* gat, int32_t gw,
-                         const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin, int32_t kmax) {
+                         const double* mdiag, const int32_t* rows, hipStream_t s, const double* Xin, int32_t kmax,
+                         bool fuse) {
     if (nitems <= 0 || ncols <= 0) return hipSuccess;
     TF* ub = reinterpret_cast<TF*>(ubuf);
     if (phase == 0 || phase == 2) {
         const dim3 grid((unsigned)nitems, (unsigned)cdiv(ncols, 64));
         k_qsolve_gather<TF><<<grid, 256, 0, s>>>(phase == 0 ? 1 : 0, fronts, items, R, ldr, Xin ? Xin : X, X, ldx,
-                                                 col0, ncols, ub, ldu, gat, gw, mdiag, D, rows);
+                                                 col0, ncols, ub, ldu, gat, gw, mdiag, D, rows,
+                                                 phase == 0 && fuse ? 1 : 0);
         return hipGetLastError();
     }
     // waves per workgroup: every wave takes about eight tiles of the longest contraction
     const int32_t nw = kmax > 32 ? 8 : kmax > 16 ? 4 : kmax > 8 ? 2 : 1;
     const size_t lds = nw > 1 ? (size_t)nw * 4 * 64 * sizeof(double) * 4 : 0;
-    const int32_t groups = (int32_t)cdiv(ncols, 32);
+    // two 16-column tiles per wave (four: one wave per SIMD for registers, measured slower)
+    constexpr int CT = 2;
+    const int32_t groups = (int32_t)cdiv(ncols, 16 * CT);
     const unsigned grid = (unsigned)(cdiv(nitems, NXCD) * NXCD * groups);
     if (phase == 1)
-        k_qsolve_fwd<TF><<<grid, 64 * nw, lds, s>>>(qinv, fronts, items, (int32_t)nitems, groups, nw, R, ldr, X, ldx,
-                                                   col0, ncols, ub, ldu);
+        k_qsolve_fwd<TF, CT><<<grid, 64 * nw, lds, s>>>(qinv, fronts, items, (int32_t)nitems, groups, nw, R, ldr, X,
+                                                       ldx, col0, ncols, ub, ldu, fuse ? gat : nullptr, gw);
     else if (phase == 3)
-        k_qsolve_bwd<TF><<<grid, 64 * nw, lds, s>>>(qinvT, fronts, items, (int32_t)nitems, groups, nw, R, ldr, X, ldx,
-                                                   col0, ncols);
+        k_qsolve_bwd<TF, CT><<<grid, 64 * nw, lds, s>>>(qinvT, fronts, items, (int32_t)nitems, groups, nw, R, ldr, X,
+                                                       ldx, col0, ncols);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1293,11 +1345,11 @@ hipError_t launch_qsolve(int phase, const TF* qinv, const TF* qinvT, const TF* D
 template hipError_t launch_qsolve<double>(int, const double*, const double*, const double*, const DFront*,
                                           const int32_t*, int64_t, double*, int64_t, double*, int64_t, int32_t, int32_t,
                                           double*, int64_t, const int32_t*, int32_t, const double*, const int32_t*,
-                                          hipStream_t, const double*, int32_t);
+                                          hipStream_t, const double*, int32_t, bool);
 template hipError_t launch_qsolve<float>(int, const float*, const float*, const float*, const DFront*, const int32_t*,
                                          int64_t, double*, int64_t, double*, int64_t, int32_t, int32_t, double*,
                                          int64_t, const int32_t*, int32_t, const double*, const int32_t*, hipStream_t,
-                                         const double*, int32_t);
+                                         const double*, int32_t, bool);
 
 // ============================================================ Gram products
 // Sbar = Psi^T (S Psi), Mbar = Psi^T (M Psi) on the matrix cores.  The q x q
@@ -2544,23 +2596,35 @@ __global__ __launch_bounds__(B * B) void k_bj_apply(double* C, double* V, int32_
 // Number of off-diagonal entries of the symmetric m x m matrix C that the
 // rotation threshold of k_bj_local would still act on; zero means that a
 // further sweep would not rotate at all.
-__global__ void k_bj_offcount(const double* __restrict__ C, int32_t m, const double* __restrict__ normf, double tol_rel,
-                              double tol_abs_rel, int32_t* count) {
+__global__ __launch_bounds__(256) void k_bj_offcount(const double* __restrict__ C, int32_t m,
+                                                     const double* __restrict__ normf, double tol_rel,
+                                                     double tol_abs_rel, int32_t* count) {
+    __shared__ int part[4];
     const double tol_abs2 = tol_abs_rel * normf[0] * tol_abs_rel * normf[0];
     const double tol_rel2 = tol_rel * tol_rel;
     int n = 0;
-    const int64_t tot = (int64_t)m * m;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t p = (int32_t)(t / m), q = (int32_t)(t % m);
-        if (p >= q) continue;
-        const double apq = C[t];
-        if (apq * apq > fmax(tol_abs2, tol_rel2 * fabs(C[(int64_t)p * m + p] * C[(int64_t)q * m + q]))) ++n;
+    // one row p per workgroup at a time, entries q > p over the threads
+    for (int32_t p = blockIdx.x; p < m; p += gridDim.x) {
+        const double* row = C + (int64_t)p * m;
+        const double app = row[p];
+        for (int32_t q = p + 1 + (int32_t)threadIdx.x; q < m; q += (int32_t)blockDim.x) {
+            const double apq = row[q];
+            if (apq * apq > fmax(tol_abs2, tol_rel2 * fabs(app * C[(int64_t)q * m + q]))) ++n;
+        }
     }
-    if (n) atomicAdd(count, n);
+    // one atomic per workgroup
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(count, t);
+    }
 }
 hipError_t launch_bj_offcount(const double* C, int32_t m, const double* normf, double tol_rel, double tol_abs_rel,
                               int32_t* count, hipStream_t s) {
-    k_bj_offcount<<<grid_for((int64_t)m * m, 256), 256, 0, s>>>(C, m, normf, tol_rel, tol_abs_rel, count);
+    if (m <= 0) return hipSuccess;
+    k_bj_offcount<<<(unsigned)std::min<int32_t>(m, 1024), 256, 0, s>>>(C, m, normf, tol_rel, tol_abs_rel, count);
     return hipGetLastError();
 }
 

@@ -148,3 +148,8 @@ def test_large_p_hsim(cuda):
     relm = np.abs(evm - lr[:p])[1:] / lr[1:p]
     assert relm.max() <= 1e-9, relm.max()
     assert rm.max() < 1e-9
+    # the FP32 Gram path is the one that could degrade the basis
+    Xm = Xm.cpu().numpy()
+    assert metrics.m_orthonormality(Xm, m) < 1e-10
+    errm = metrics.eigenvector_err(Xm, Xr, m, lr, gap=1e-4)
+    assert errm.max() < 1e-4, errm.max()

@@ -102,7 +102,9 @@ def test_factor_inertia_and_solve(small, tau):
         # normwise backward error per column (infinity norms)
         Ainf = np.abs(A).sum(axis=1).max()
         bw = (np.abs(A @ X - B).max(axis=0) / (Ainf * np.abs(X).max(axis=0) + np.abs(B).max(axis=0))).max()
-        # bound c n u of a backward-stable solve (n = 642)
+        # bound c n u of a backward-stable solve (n = 642: n u = 1.4e-13; a
+        # constant c of order one, the measured values are printed)
+        print(f"[factor/solve tau={tau} mu={mu:.3g}] normwise backward error {bw:.2e}", flush=True)
         assert bw < 1e-13, bw
 
 
@@ -462,7 +464,7 @@ def test_wide_hsim(wide):
     print(f"[wide hsim] iters {st['iters']} total {st['ms_total']:.1f} ms", flush=True)
     lr, Xr, _, _ = sim.sim_lowest(S, m, p + 10, eps=1e-11)
     rel = np.abs(ev - lr[:p])[1:] / lr[1:p]
-    assert rel.max() <= 1e-8, rel.max()
+    assert rel.max() <= 1e-9, rel.max()
     assert r.max() < 1e-9
     assert metrics.m_orthonormality(X, m) < 1e-10
     assert sim.residual(S, m, X, ev).max() < 2e-9

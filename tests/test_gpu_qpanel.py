@@ -1,7 +1,7 @@
 """Block solves through the inverse panels of wide fronts, through the C ABI.
 
-The tree levels whose widest supernode has at least 128 padded pivots get, in
-every factorisation, the inverse panels Q = [L11^-1; -L21 L11^-1] of their
+The tree levels above the leaves whose widest supernode has at least 64
+padded pivots get, in every factorisation, the inverse panels Q = [L11^-1; -L21 L11^-1] of their
 fronts, and the block solves may multiply by them instead of substituting
 (which levels do is the launch plan, set here through HSIM_BIG_NS /
 HSIM_BIG_NS_BWD as the autotuner would).  A 20,000-vertex noisy torus has
@@ -27,7 +27,7 @@ from oracle import assembly
 
 pytestmark = pytest.mark.gpu
 
-PLANS = [(128, 128), (256, 128), (512, 512), (1 << 20, 1 << 20)]
+PLANS = [(64, 64), (96, 128), (128, 128), (256, 128), (512, 512), (1 << 20, 1 << 20)]
 
 
 def _t(a):
