@@ -56,7 +56,8 @@ def build(verbose=False, jobs=None):
         objs.append(obj)
     for src in DEVICE_SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmds.append([hipcc, *common, "-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+        omp = ["-fopenmp"] if src == "hsim.cpp" else []   # host loops of the level set-up
+        cmds.append([hipcc, *common, *omp, "-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
                      "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                      "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

@@ -3,7 +3,10 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "internal.h"
 
@@ -26,6 +29,23 @@ void device_mesh_graph(const Mesh& m, DevMesh& dm, Graph& g);
 // order bit for bit (the same distances: the fixpoint of the relaxations does
 // not depend on their order; farthest ties to the lowest vertex index).
 std::vector<int32_t> device_fps(const DevMesh& dm, int64_t count, uint64_t seed);
+
+// The same in two halves: start launches the sampling on a stream of its own
+// (non-blocking: work on the null stream neither waits for it nor holds it
+// up) and returns at once; finish waits for it and returns the order.  The
+// run owns its work arrays; destroying it waits for the kernel first.  dm
+// must outlive the run.
+struct FpsRun {
+    DeviceBuffer dist, q0, q1, f0, f1, bmax, bidx, dirty, dlist, order, status;
+    hipStream_t stream = nullptr;
+    int64_t count = 0;
+    FpsRun() = default;
+    FpsRun(const FpsRun&) = delete;
+    FpsRun& operator=(const FpsRun&) = delete;
+    ~FpsRun();
+};
+std::unique_ptr<FpsRun> device_fps_start(const DevMesh& dm, int64_t count, uint64_t seed);
+std::vector<int32_t> device_fps_finish(FpsRun& r);
 
 }  // namespace hsim
 

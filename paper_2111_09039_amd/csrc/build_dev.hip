@@ -480,38 +480,59 @@ __global__ __launch_bounds__(FPS_T) void k_fps(const int64_t* __restrict__ gptr,
     }
 }
 
-std::vector<int32_t> device_fps(const DevMesh& dm, int64_t count, uint64_t seed) {
+FpsRun::~FpsRun() {
+    if (stream) {
+        (void)hipStreamSynchronize(stream);   // the buffers outlive the kernel, also on an error path
+        (void)hipStreamDestroy(stream);
+    }
+}
+
+std::unique_ptr<FpsRun> device_fps_start(const DevMesh& dm, int64_t count, uint64_t seed) {
+    BDCHECK(hipDeviceSynchronize());   // the graph in dm is complete
+    std::unique_ptr<FpsRun> r(new FpsRun());
     const int64_t n = dm.nv;
     const int64_t nb = (n + FPS_T - 1) / FPS_T;
-    DeviceBuffer dist, q0, q1, f0, f1, bmax, bidx, dirty, dlist, order, status;
-    dist.alloc((size_t)n * sizeof(unsigned long long));
-    q0.alloc((size_t)n * sizeof(int32_t));
-    q1.alloc((size_t)n * sizeof(int32_t));
-    f0.alloc((size_t)n * sizeof(unsigned int));
-    f1.alloc((size_t)n * sizeof(unsigned int));
-    bmax.alloc((size_t)nb * sizeof(double));
-    bidx.alloc((size_t)nb * sizeof(int32_t));
-    dirty.alloc((size_t)nb * sizeof(unsigned int));
-    dlist.alloc((size_t)nb * sizeof(int32_t));
-    order.alloc((size_t)count * sizeof(int32_t));
-    status.alloc(sizeof(int32_t));
-    BDCHECK(hipMemset(status.p, 0, sizeof(int32_t)));
+    r->count = count;
+    r->dist.alloc((size_t)n * sizeof(unsigned long long));
+    r->q0.alloc((size_t)n * sizeof(int32_t));
+    r->q1.alloc((size_t)n * sizeof(int32_t));
+    r->f0.alloc((size_t)n * sizeof(unsigned int));
+    r->f1.alloc((size_t)n * sizeof(unsigned int));
+    r->bmax.alloc((size_t)nb * sizeof(double));
+    r->bidx.alloc((size_t)nb * sizeof(int32_t));
+    r->dirty.alloc((size_t)nb * sizeof(unsigned int));
+    r->dlist.alloc((size_t)nb * sizeof(int32_t));
+    r->order.alloc((size_t)count * sizeof(int32_t));
+    r->status.alloc(sizeof(int32_t));
+    // its own stream, which does not wait for (or hold up) the null stream
+    BDCHECK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
+    BDCHECK(hipMemsetAsync(r->status.p, 0, sizeof(int32_t), r->stream));
     const int32_t start = (int32_t)(seed % (uint64_t)n);
-    k_fps_init<<<grid_of(n, 256), 256>>>(n, dp<unsigned long long>(dist), dp<unsigned int>(f0), dp<unsigned int>(f1),
-                                         dp<unsigned int>(dirty), nb);
+    k_fps_init<<<grid_of(n, 256), 256, 0, r->stream>>>(n, dp<unsigned long long>(r->dist), dp<unsigned int>(r->f0),
+                                                       dp<unsigned int>(r->f1), dp<unsigned int>(r->dirty), nb);
     BDCHECK(hipGetLastError());
-    k_fps<<<1, FPS_T>>>(dp<int64_t>(dm.gptr), dp<int32_t>(dm.gnbr), dp<double>(dm.gw), n, count, start,
-                        dp<unsigned long long>(dist), dp<int32_t>(q0), dp<int32_t>(q1), dp<unsigned int>(f0),
-                        dp<unsigned int>(f1), dp<double>(bmax), dp<int32_t>(bidx), dp<unsigned int>(dirty),
-                        dp<int32_t>(dlist), dp<int32_t>(order), dp<int32_t>(status));
+    k_fps<<<1, FPS_T, 0, r->stream>>>(dp<int64_t>(dm.gptr), dp<int32_t>(dm.gnbr), dp<double>(dm.gw), n, count, start,
+                                      dp<unsigned long long>(r->dist), dp<int32_t>(r->q0), dp<int32_t>(r->q1),
+                                      dp<unsigned int>(r->f0), dp<unsigned int>(r->f1), dp<double>(r->bmax),
+                                      dp<int32_t>(r->bidx), dp<unsigned int>(r->dirty), dp<int32_t>(r->dlist),
+                                      dp<int32_t>(r->order), dp<int32_t>(r->status));
     BDCHECK(hipGetLastError());
-    BDCHECK(hipDeviceSynchronize());
+    return r;
+}
+
+std::vector<int32_t> device_fps_finish(FpsRun& r) {
+    BDCHECK(hipStreamSynchronize(r.stream));
     int32_t st = 0;
-    BDCHECK(hipMemcpy(&st, status.p, sizeof st, hipMemcpyDeviceToHost));
+    BDCHECK(hipMemcpy(&st, r.status.p, sizeof st, hipMemcpyDeviceToHost));
     if (st) fail(HSIM_E_MESH, "farthest point sampling ran out of distinct vertices");
-    std::vector<int32_t> out(count);
-    BDCHECK(hipMemcpy(out.data(), order.p, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> out(r.count);
+    BDCHECK(hipMemcpy(out.data(), r.order.p, (size_t)r.count * sizeof(int32_t), hipMemcpyDeviceToHost));
     return out;
+}
+
+std::vector<int32_t> device_fps(const DevMesh& dm, int64_t count, uint64_t seed) {
+    std::unique_ptr<FpsRun> r = device_fps_start(dm, count, seed);
+    return device_fps_finish(*r);
 }
 
 }  // namespace hsim

@@ -578,18 +578,23 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
     std::vector<int32_t> idx(L.S.nnz());
     std::vector<double> sv(L.S.nnz()), mv(L.S.nnz());
     std::vector<int64_t> newpos(L.S.nnz());   // CSR entry (level order) -> entry of the permuted CSR
-    std::vector<std::pair<int32_t, int64_t>> rowbuf;
-    for (int64_t k = 0; k < n; ++k) {
-        const int32_t v = perm[k];
-        rowbuf.clear();
-        for (int64_t e = L.S.ptr[v]; e < L.S.ptr[v + 1]; ++e) rowbuf.push_back({iperm[L.S.idx[e]], e});
-        std::sort(rowbuf.begin(), rowbuf.end());
-        ptr[k + 1] = ptr[k] + (int64_t)rowbuf.size();
-        for (size_t t = 0; t < rowbuf.size(); ++t) {
-            idx[ptr[k] + t] = rowbuf[t].first;
-            sv[ptr[k] + t] = L.S.val[rowbuf[t].second];
-            mv[ptr[k] + t] = L.Mval[rowbuf[t].second];
-            newpos[rowbuf[t].second] = ptr[k] + (int64_t)t;
+    for (int64_t k = 0; k < n; ++k) ptr[k + 1] = ptr[k] + (L.S.ptr[perm[k] + 1] - L.S.ptr[perm[k]]);
+    // rows are independent once their offsets are known
+#pragma omp parallel
+    {
+        std::vector<std::pair<int32_t, int64_t>> rowbuf;
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < n; ++k) {
+            const int32_t v = perm[k];
+            rowbuf.clear();
+            for (int64_t e = L.S.ptr[v]; e < L.S.ptr[v + 1]; ++e) rowbuf.push_back({iperm[L.S.idx[e]], e});
+            std::sort(rowbuf.begin(), rowbuf.end());
+            for (size_t t = 0; t < rowbuf.size(); ++t) {
+                idx[ptr[k] + t] = rowbuf[t].first;
+                sv[ptr[k] + t] = L.S.val[rowbuf[t].second];
+                mv[ptr[k] + t] = L.Mval[rowbuf[t].second];
+                newpos[rowbuf[t].second] = ptr[k] + (int64_t)t;
+            }
         }
     }
     L.dS_ptr.upload(ptr);
@@ -613,16 +618,21 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
         std::vector<int64_t> up(n + 1, 0);
         std::vector<int32_t> ui(L.U.nnz());
         std::vector<double> uv(L.U.nnz());
-        std::vector<std::pair<int32_t, double>> rb;
-        for (int64_t k = 0; k < n; ++k) {
-            const int32_t v = perm[k];
-            rb.clear();
-            for (int64_t e = L.U.ptr[v]; e < L.U.ptr[v + 1]; ++e) rb.push_back({(*coarse_iperm)[L.U.idx[e]], L.U.val[e]});
-            std::sort(rb.begin(), rb.end());
-            up[k + 1] = up[k] + (int64_t)rb.size();
-            for (size_t t = 0; t < rb.size(); ++t) {
-                ui[up[k] + t] = rb[t].first;
-                uv[up[k] + t] = rb[t].second;
+        for (int64_t k = 0; k < n; ++k) up[k + 1] = up[k] + (L.U.ptr[perm[k] + 1] - L.U.ptr[perm[k]]);
+#pragma omp parallel
+        {
+            std::vector<std::pair<int32_t, double>> rb;
+#pragma omp for schedule(static)
+            for (int64_t k = 0; k < n; ++k) {
+                const int32_t v = perm[k];
+                rb.clear();
+                for (int64_t e = L.U.ptr[v]; e < L.U.ptr[v + 1]; ++e)
+                    rb.push_back({(*coarse_iperm)[L.U.idx[e]], L.U.val[e]});
+                std::sort(rb.begin(), rb.end());
+                for (size_t t = 0; t < rb.size(); ++t) {
+                    ui[up[k] + t] = rb[t].first;
+                    uv[up[k] + t] = rb[t].second;
+                }
             }
         }
         L.dU_ptr.upload(up);
@@ -1103,10 +1113,24 @@ void hsim_free(hsim_hierarchy* h) { delete h; }
 
 // Finest-level S (values on the pattern of the edge graph plus the diagonal)
 // and barycentric lumped M assembled on the current device.
-static void device_assembly(const Mesh& m, const Graph& g, const double* density, Csr& S, std::vector<double>& md) {
+// work arrays of the device assembly, kept by the caller until the sampling
+// that runs beside it has finished (freeing device memory waits for the device)
+struct AssemblyBuffers {
+    DeviceBuffer dV, dF, bptr, bidx, bcorner, bdptr, bdcorner, dvptr, dvtri, ddens, dw, da3, dval, dm;
+    void release() {
+        for (DeviceBuffer* b : {&dV, &dF, &bptr, &bidx, &bcorner, &bdptr, &bdcorner, &dvptr, &dvtri, &ddens, &dw,
+                                &da3, &dval, &dm})
+            b->release();
+    }
+};
+
+static void device_assembly(const Mesh& m, const Graph& g, const double* density, Csr& S, std::vector<double>& md,
+                            AssemblyBuffers& B) {
     AssemblyMaps a = assembly_maps(m, g);
     const int64_t n = m.nv, nf = m.nf, nnz = a.S.nnz();
-    DeviceBuffer dV, dF, bptr, bidx, bcorner, bdptr, bdcorner, dvptr, dvtri, ddens, dw, da3, dval, dm;
+    DeviceBuffer &dV = B.dV, &dF = B.dF, &bptr = B.bptr, &bidx = B.bidx, &bcorner = B.bcorner, &bdptr = B.bdptr,
+                 &bdcorner = B.bdcorner, &dvptr = B.dvptr, &dvtri = B.dvtri, &ddens = B.ddens, &dw = B.dw,
+                 &da3 = B.da3, &dval = B.dval, &dm = B.dm;
     dV.upload(m.V);
     dF.upload(m.F);
     bptr.upload(a.S.ptr);
@@ -1211,20 +1235,18 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
     std::vector<int64_t> sizes = level_sizes(n0, T, nc, bo.growth_mode);
     for (int t = 1; t < T; ++t)
         if (sizes[t] >= sizes[t - 1]) fail(HSIM_E_INVALID, "level %d is not smaller than level %d (too many levels for this mesh)", t, t - 1);
-    std::vector<int32_t> order =
-        dev_build ? device_fps(dm, sizes[1], bo.seed) : farthest_point_sampling(g, nv, sizes[1], bo.seed);
-    phase(dev_build ? "farthest points (device)" : "farthest points (host)");
-    // levels
+    // the sampling runs on the device (a stream of its own) while the host and
+    // the rest of the device assemble the finest level and analyse it
+    std::unique_ptr<FpsRun> fps;
+    if (dev_build) fps = device_fps_start(dm, sizes[1], bo.seed);
+    AssemblyBuffers asm_buf;
+    // levels (the vertices of the coarser ones follow from the sampling)
     for (int t = 0; t < T; ++t) {
         auto L = std::make_unique<Level>();
         L->tau = t;
         L->n = sizes[t];
         L->coarsest = t == T - 1;
-        if (t == 0) {
-            L->verts = dofs;
-        } else {
-            L->verts.assign(order.begin(), order.begin() + sizes[t]);
-        }
+        if (t == 0) L->verts = dofs;
         H->lv.push_back(std::move(L));
     }
     {
@@ -1232,7 +1254,7 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         if (!H->host_only && bo.lumping == 0 && env_int("HSIM_HOST_ASSEMBLY", 0) == 0) {
             // cotangent stiffness and lumped mass assembled on the device (same values as the host
             // assembly, term for term in the same order), downloaded for the rest of the build
-            device_assembly(m, g, density, L0.S, L0.mdiag);
+            device_assembly(m, g, density, L0.S, L0.mdiag, asm_buf);
             for (int64_t i = 0; i < nv; ++i)
                 if (!(L0.mdiag[i] > 0)) fail(HSIM_E_MESH, "lumped mass of vertex %lld is not positive", (long long)i);
         } else {
@@ -1266,6 +1288,24 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
                 if (L0.S.idx[e] == i) L0.Mval[e] = L0.mdiag[i];
     }
     phase("assembly");
+    // elimination order and symbolic analysis of a level (host, OpenMP)
+    auto analyse_level = [&](int t) {
+        Level& L = *H->lv[t];
+        std::vector<double> X(3 * L.n);
+        for (int64_t i = 0; i < L.n; ++i)
+            for (int c = 0; c < 3; ++c) X[3 * i + c] = m.V[3 * (int64_t)L.verts[i] + c];
+        L.sy = analyse(L.S, X.data(), L.n);
+    };
+    // the finest level's pattern and coordinates are known now: the host
+    // analyses it while the device samples
+    analyse_level(0);
+    phase("ordering + symbolic (finest)");
+    std::vector<int32_t> order =
+        dev_build ? device_fps_finish(*fps) : farthest_point_sampling(g, nv, sizes[1], bo.seed);
+    fps.reset();
+    asm_buf.release();
+    for (int t = 1; t < T; ++t) H->lv[t]->verts.assign(order.begin(), order.begin() + sizes[t]);
+    phase(dev_build ? "farthest points (device, rest)" : "farthest points (host)");
     for (int t = 0; t + 1 < T; ++t) {
         Level& L = *H->lv[t];
         Level& C = *H->lv[t + 1];
@@ -1287,14 +1327,8 @@ hsim_status hsim_build_hierarchy(const double* V, int64_t nv, const int32_t* F, 
         if (!(dev_build && device_galerkin(L.U, L.S, L.Mval, C.S, C.Mval))) galerkin(L.U, L.S, L.Mval, C.S, C.Mval);
     }
     phase("prolongation + Galerkin");
-    for (int t = 0; t + 1 < T; ++t) {
-        Level& L = *H->lv[t];
-        std::vector<double> X(3 * L.n);
-        for (int64_t i = 0; i < L.n; ++i)
-            for (int c = 0; c < 3; ++c) X[3 * i + c] = m.V[3 * (int64_t)L.verts[i] + c];
-        L.sy = analyse(L.S, X.data(), L.n);
-    }
-    phase("ordering + symbolic");
+    for (int t = 1; t + 1 < T; ++t) analyse_level(t);
+    phase("ordering + symbolic (rest)");
     // device
     for (int t = H->host_only ? -1 : T - 1; t >= 0; --t) {
         Level& L = *H->lv[t];
