@@ -144,6 +144,7 @@ struct Prof {
 // C = D^-1/2 P (E S E) P^T D^-1/2 by two products, cyclic Jacobi on C,
 // X = E P^T D^-1/2 V by a third.
 struct DenseGEP {
+    static constexpr int32_t MAX_SWEEPS = 40;   // at most this many Jacobi sweeps
     int32_t k = 0, m = 0, ns_pad = 0, Mt = 0, bj = 16;
     std::vector<int64_t> diag_ptr, panel_ptr, upd_ptr, qrow_ptr, qupd_ptr;
     int64_t nprod = 0;   // product items (0, I): the 32-row tiles of the k rows
@@ -307,10 +308,11 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     fwd(W2, W, k, k, s);
     // C = D^-1/2 W D^-1/2 (symmetrised) embedded in m x m; dis = D^-1/2
     HIPCHECK(launch_sym_scale(W, D, k, W2, s));
-    HIPCHECK(launch_embed_pad(W2, k, m, C, normf, dis, D, s));
+    HIPCHECK(launch_embed_pad(W2, k, m, C, normf, dis, D, Qs, s));   // Qs (>= 1024 doubles) free until the sweeps
     HIPCHECK(launch_identity(V, m, s));
     const double tol_rel = 1e-15, tol_abs_rel = 1e-17;
     int32_t sweeps = 0;
+    max_sweeps = std::min(max_sweeps, MAX_SWEEPS);
     // a sweep ends the iteration when it rotated nothing or when no entry is
     // left above the threshold (the next sweep would rotate nothing)
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
@@ -700,7 +702,9 @@ static void build_device_level(hsim_hierarchy* H, Level& L, const std::vector<in
 }
 
 // ----------------------------------------------------------- factor / solve
-static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, bool mixed = false) {
+// the factorisation's launches (nothing waited for); factor_finish reads the
+// pivot counts and writes the transposed and FP32 copies
+static void factor_launch(hsim_hierarchy* H, Level& L, double mu, hipStream_t s) {
     const Symbolic& sy = L.sy;
     const int32_t mc = std::max<int32_t>(1, sy.max_children);
     int32_t* cnt = dptr<int32_t>(L.counters);
@@ -745,14 +749,17 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
         }
       });
     }
-    int32_t hc[2] = {0, 0};
-    HIPCHECK(hipMemcpyAsync(hc, cnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    L.mu = mu;
-    L.neg_pivots = hc[0];
-    L.factored = hc[1] == 0;
-    L.factored32 = false;
-    if (hc[1] != 0) fail(HSIM_E_FACTOR, "LDL^T of S - mu M (level %d, mu=%g): %d zero or non-finite pivots", L.tau, mu, hc[1]);
+}
+
+static void factor_finish(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, bool mixed) {
+    const Symbolic& sy = L.sy;
+    int32_t* cnt = dptr<int32_t>(L.counters);
+    double* tiles = dptr<double>(L.tiles);
+    double* qT = L.q_doubles > 0 ? dptr<double>(L.qinvT) : nullptr;
+    Prof& P = H->prof;
+    // the transposed copies are queued before the pivot counts are read back,
+    // so the device works through the host's round trip (wasted only when the
+    // factorisation fails)
     L.tilesT.alloc((size_t)sy.tile_doubles * sizeof(double));
     L.linvT.alloc((size_t)std::max<int64_t>(1, sy.linv_doubles) * sizeof(double));
     P.run(HSIM_K_FACTOR, 16.0 * (sy.tile_doubles + sy.linv_doubles), 0.0, s, [&] {
@@ -761,6 +768,14 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
                                                s));
         if (qT) HIPCHECK(launch_tile_transpose<double>(qT, dptr<double>(L.qinv), L.q_doubles / (NB * NB), s));
     });
+    int32_t hc[2] = {0, 0};
+    HIPCHECK(hipMemcpyAsync(hc, cnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    L.mu = mu;
+    L.neg_pivots = hc[0];
+    L.factored = hc[1] == 0;
+    L.factored32 = false;
+    if (hc[1] != 0) fail(HSIM_E_FACTOR, "LDL^T of S - mu M (level %d, mu=%g): %d zero or non-finite pivots", L.tau, mu, hc[1]);
     if (mixed) {
         // FP32 copy of the FP64 factor for the low-precision solves
         L.tiles32.alloc((size_t)sy.tile_doubles * sizeof(float));
@@ -785,6 +800,11 @@ static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, 
         });
         L.factored32 = true;
     }
+}
+
+static void factor_level(hsim_hierarchy* H, Level& L, double mu, hipStream_t s, bool mixed = false) {
+    factor_launch(H, L, mu, s);
+    factor_finish(H, L, mu, s, mixed);
 }
 
 // X (internal order, leading dim ld) <- (S - mu M)^-1 (mdiag ? m*X : X) on columns [col0, col0 + ncols);

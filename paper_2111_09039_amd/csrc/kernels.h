@@ -167,9 +167,10 @@ hipError_t launch_bj_sweep(int b, double* C, double* V, int32_t m, double* Qs, c
 hipError_t launch_bj_offcount(const double* C, int32_t m, const double* normf, double tol_rel, double tol_abs_rel,
                               int32_t* count, hipStream_t s);
 hipError_t launch_identity(double* V, int32_t m, hipStream_t s);
-// C (m x m) = Ck (k x k) plus decoupled dummies (m > k), normf = ||Ck||_F, dis = D^-1/2
+// C (m x m) = Ck (k x k) plus decoupled dummies (m > k), normf = ||Ck||_F, dis = D^-1/2;
+// part: 256 doubles of scratch (partial sums of squares)
 hipError_t launch_embed_pad(const double* Ck, int32_t k, int32_t m, double* C, double* normf, double* dis,
-                            const double* D, hipStream_t s);
+                            const double* D, double* part, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // A (n x n row-major) = dense copy of a CSR matrix
 hipError_t launch_densify(const int64_t* ptr, const int32_t* idx, const double* val, int64_t n, double* A,

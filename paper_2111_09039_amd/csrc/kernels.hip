@@ -2673,15 +2673,23 @@ __device__ __forceinline__ bool sort_before(double a, int i, double b, int j) {
     return a < b || (a == b && i < j);
 }
 // ascending order of the diagonal of C (ties by index); X[r, j] = scale[r] Y[r, order[j]]
+constexpr int SORT_LDS_MAX = 8192;
 __global__ __launch_bounds__(1024) void k_sort_eig(const double* C, int32_t m, int32_t kvalid, const double* Y,
                                                    int32_t rows, const double* scale, int32_t kout, double* lam_out,
                                                    double* X, int64_t ldx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    int* order = reinterpret_cast<int*>(smem_raw);
+    // the diagonal staged in LDS when it fits (kvalid <= SORT_LDS_MAX)
+    const bool staged = kvalid <= SORT_LDS_MAX;
+    double* diag = reinterpret_cast<double*>(smem_raw);
+    int* order = reinterpret_cast<int*>(smem_raw + (staged ? sizeof(double) * kvalid : 0));   // kout entries
+    if (staged)
+        for (int i = threadIdx.x; i < kvalid; i += blockDim.x) diag[i] = C[(int64_t)i * m + i];
+    __syncthreads();
+    auto dg = [&](int j) { return staged ? diag[j] : C[(int64_t)j * m + j]; };
     for (int i = threadIdx.x; i < kvalid; i += blockDim.x) {
-        const double li = C[(int64_t)i * m + i];
+        const double li = dg(i);
         int rank = 0;
-        for (int j = 0; j < kvalid; ++j) rank += sort_before(C[(int64_t)j * m + j], j, li, i);
+        for (int j = 0; j < kvalid; ++j) rank += sort_before(dg(j), j, li, i);
         if (rank < kout) {
             order[rank] = i;
             lam_out[rank] = li;
@@ -2698,29 +2706,44 @@ __global__ __launch_bounds__(1024) void k_sort_eig(const double* C, int32_t m, i
 hipError_t launch_sort_eig(const double* C, int32_t m, int32_t kvalid, const double* Y, int32_t rows,
                            const double* scale, int32_t kout, double* lam_out, double* X, int64_t ldx, hipStream_t s) {
     if (kout <= 0 || kout > kvalid || kvalid > m) return hipErrorInvalidValue;   // every order[j] must have a source
-    k_sort_eig<<<1, 1024, (size_t)kout * sizeof(int), s>>>(C, m, kvalid, Y, rows, scale, kout, lam_out, X, ldx);
+    const size_t lds = (kvalid <= SORT_LDS_MAX ? (size_t)kvalid * sizeof(double) : 0) + (size_t)kout * sizeof(int);
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_sort_eig), lds, 0);
+    if (e != hipSuccess) return e;
+    k_sort_eig<<<1, 1024, lds, s>>>(C, m, kvalid, Y, rows, scale, kout, lam_out, X, ldx);
     return hipGetLastError();
 }
 
 // C (m x m) = Ck (k x k) padded with decoupled dummy rows/columns whose
 // diagonal exceeds every eigenvalue; normf[0] = ||Ck||_F; dis = D^-1/2
-// (1 on the dummies)
-__global__ void k_embed_copy(const double* Ck, int32_t k, int32_t m, double* C) {
-    const int64_t tot = (int64_t)m * m;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+// (1 on the dummies).  The squares are summed in a fixed order: workgroup b
+// over its own range of C's entries (strided over its threads, then a fixed
+// tree), the EMBED_WG partial sums by one workgroup.
+constexpr int EMBED_WG = 256;
+__global__ __launch_bounds__(256) void k_embed_copy(const double* Ck, int32_t k, int32_t m, double* C, double* part) {
+    __shared__ double red[256];
+    const int64_t tot = (int64_t)m * m, chunk = (tot + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = blockIdx.x * chunk, t1 = min(tot, t0 + chunk);
+    double sq = 0.0;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
         const int32_t i = (int32_t)(t / m), j = (int32_t)(t % m);
-        C[t] = (i < k && j < k) ? Ck[(int64_t)i * k + j] : 0.0;
+        const double v = (i < k && j < k) ? Ck[(int64_t)i * k + j] : 0.0;
+        C[t] = v;
+        sq += v * v;
     }
-}
-__global__ __launch_bounds__(1024) void k_embed_finish(const double* Ck, int32_t k, int32_t m, double* C,
-                                                       double* normf, double* dis, const double* D) {
-    __shared__ double red[1024];
-    double s = 0.0;
-    const int64_t tot = (int64_t)k * k;
-    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) s += Ck[t] * Ck[t];
-    red[threadIdx.x] = s;
+    red[threadIdx.x] = sq;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(256) void k_embed_finish(const double* part, int32_t k, int32_t m, double* C,
+                                                      double* normf, double* dis, const double* D) {
+    __shared__ double red[256];
+    red[threadIdx.x] = part[threadIdx.x];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -2730,11 +2753,11 @@ __global__ __launch_bounds__(1024) void k_embed_finish(const double* Ck, int32_t
     for (int i = threadIdx.x; i < m; i += blockDim.x) dis[i] = i < k ? 1.0 / sqrt(D[i]) : 1.0;
 }
 hipError_t launch_embed_pad(const double* Ck, int32_t k, int32_t m, double* C, double* normf, double* dis,
-                            const double* D, hipStream_t s) {
-    k_embed_copy<<<grid_for((int64_t)m * m, 256), 256, 0, s>>>(Ck, k, m, C);
+                            const double* D, double* part, hipStream_t s) {
+    k_embed_copy<<<EMBED_WG, 256, 0, s>>>(Ck, k, m, C, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_embed_finish<<<1, 1024, 0, s>>>(Ck, k, m, C, normf, dis, D);
+    k_embed_finish<<<1, 256, 0, s>>>(part, k, m, C, normf, dis, D);
     return hipGetLastError();
 }
 
