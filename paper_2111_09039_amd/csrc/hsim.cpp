@@ -1679,9 +1679,14 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         for (it = 1; it <= so.max_iters; ++it) {
             auto a0 = std::chrono::steady_clock::now();
             const int32_t act = q - locked;
+            // mixed precision: the solves' target accuracy for this step; once a
+            // plain FP32 solve on this factor is known to miss it, the step runs
+            // the FP64 solves (the same launches as an FP64 solve, no probing)
+            const double eta = std::min(1e-3, 0.1 * (std::isfinite(rmax) ? rmax : 1e-2));
+            const bool fp64_solves = !mixed || (est32 >= 0 && est32 > eta);
             // the active columns go from Phi into Psi with the two solves of the
             // iteration; the locked ones (not iterated) are copied from Phi after
-            if (act > 0 && !mixed) {
+            if (act > 0 && fp64_solves) {
                 // FP64: the two inverse iterations of the step (kernels only, no host
                 // synchronisation), as one replayed graph with HSIM_FLAG_GRAPH
                 auto body = [&](hipStream_t ss) {
@@ -1737,7 +1742,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
                 }
                 if (tau == 0) swap_buffers(h->Psi, h->Btmp);
             }
-            if (act > 0 && mixed) {
+            if (act > 0 && !fp64_solves) {
                 for (int rep = 0; rep < 2; ++rep) {
                     double* src = dptr<double>(rep == 0 ? h->Phi : h->Psi);
                     // B = M src
@@ -1749,7 +1754,6 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
                             pattern_spmm(L, false, false, 1.0, 0.0, src + locked, h->ld, act,
                                          dptr<double>(h->Btmp) + locked, h->ld, s);
                         });
-                    const double eta = std::min(1e-3, 0.1 * (std::isfinite(rmax) ? rmax : 1e-2));
                     st.refine_steps += refine_solve(h, L, dptr<double>(h->Btmp), dptr<double>(h->Psi), locked, act,
                                                     eta, s, &st.escalated, &est32);
                 }
