@@ -183,12 +183,16 @@ def test_ritz_update_and_residual(small):
         assert np.abs(r - rr).max() <= 1e-12 * np.abs(rr).max()
 
 
-@pytest.mark.parametrize("case", ["sphere2k", "torus"])
+@pytest.mark.parametrize("case", ["sphere2k", "sphere2k-default-coarsest", "torus"])
 def test_hsim_end_to_end(cuda, case):
     import paper_2111_09039_amd as hs
     if case == "sphere2k":
         V, F, d = synth.config_mesh("sphere2k", seed=0)
         p, T, nc = 20, 3, 300
+    elif case == "sphere2k-default-coarsest":
+        # the small configuration exactly as the library sizes it: levels 2562, 1601, 1000
+        V, F, d = synth.config_mesh("sphere2k", seed=0)
+        p, T, nc = 20, 3, 0
     else:
         rng = np.random.default_rng(11)
         V, F = synth.torus(60, 30)
@@ -198,6 +202,8 @@ def test_hsim_end_to_end(cuda, case):
     print(f"[end-to-end {case}] n={len(V)} p={p}", flush=True)
     S, m = assembly.assemble(V, F, density=d)
     H = hs.Hierarchy(V, F, p, density=d, levels=T, n_coarsest=nc)
+    if nc == 0:
+        assert [H.level_info(t)["n"] for t in range(H.levels)] == [2562, 1601, 1000]
     ev, X, r, st = H.solve(tol=1e-10)
     ev, X, r = ev.cpu().numpy(), X.cpu().numpy(), r.cpu().numpy()
     lr, Xr, _, _ = sim.sim_lowest(S, m, p + 10, eps=1e-12)
