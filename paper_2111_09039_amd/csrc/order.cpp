@@ -13,7 +13,9 @@
 // children's structures below it (so every child's update block fits inside
 // its parent's front).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <numeric>
 
 #include "internal.h"
@@ -133,6 +135,15 @@ inline int32_t round_up(int64_t x, int64_t m) { return (int32_t)((x + m - 1) / m
 Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
     Symbolic sy;
     std::vector<int32_t> order, sizes;
+    const bool verbose = env_int("HSIM_VERBOSE", 0) != 0;
+    auto t0 = std::chrono::steady_clock::now();
+    auto phase_done = [&](const char* what) {
+        if (!verbose) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[hsim analyse] %-26s %8.1f ms (n = %lld)\n", what,
+                     std::chrono::duration<double, std::milli>(now - t0).count(), (long long)n);
+        t0 = now;
+    };
     {
         ND nd(S, coords, n);
         std::vector<int32_t> all(n);
@@ -141,6 +152,7 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
 #pragma omp single
         nd.run(std::move(all), 1, order, sizes);
     }
+    phase_done("nested dissection");
     if ((int64_t)order.size() != n) fail(HSIM_E_INVALID, "ordering lost vertices");
     std::vector<std::pair<int64_t, int32_t>> snodes;   // (start, size) in elimination order
     {
@@ -185,6 +197,7 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
             kids[parent[s]].push_back((int32_t)s);
         }
     }
+    phase_done("column structures");
     // renumber fronts by (tree level, elimination start)
     std::vector<int32_t> newid(ns_count), byid(ns_count);
     std::iota(byid.begin(), byid.end(), 0);
@@ -215,6 +228,7 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
         std::copy(st[byid[i]].begin(), st[byid[i]].end(), sy.rows.begin() + sy.rows_ptr[i]);
     st.clear();
 
+    phase_done("renumbering");
     // offsets, child slots, flops
     std::vector<std::vector<int32_t>> children(ns_count);
     for (int64_t i = 0; i < ns_count; ++i)
@@ -246,6 +260,7 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
     sy.d_doubles = db;
     sy.ubuf_rows = ub;
 
+    phase_done("offsets and flops");
     // relative indices of struct rows in the parent's local index space
     sy.rel.resize(sy.rows.size());
     for (int64_t i = 0; i < ns_count; ++i) {
@@ -268,59 +283,86 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
             }
         }
     }
+    phase_done("relative indices");
     // gather lists of the solve: compact local row (pivot r -> r, struct k -> ns + k)
     {
-        std::vector<std::vector<int64_t>> lists(gb);
+        // counted, then filled in front order (children in front order, which
+        // is slot order within a parent)
+        auto list_of = [&](int64_t i, int64_t k) {
+            const Front& P = sy.fronts[sy.fronts[i].parent];
+            const int32_t lr = sy.rel[k];
+            return P.gather_base + (lr < P.ns_pad ? lr : P.ns + (lr - P.ns_pad));
+        };
+        sy.gather_ptr.assign(gb + 1, 0);
+        for (int64_t i = 0; i < ns_count; ++i)
+            if (sy.fronts[i].parent >= 0)
+                for (int64_t k = sy.rows_ptr[i]; k < sy.rows_ptr[i + 1]; ++k) ++sy.gather_ptr[list_of(i, k) + 1];
+        for (int64_t r = 0; r < gb; ++r) sy.gather_ptr[r + 1] += sy.gather_ptr[r];
+        sy.gather_idx.assign(sy.gather_ptr[gb], 0);
+        std::vector<int64_t> fill(sy.gather_ptr.begin(), sy.gather_ptr.end() - 1);
         for (int64_t i = 0; i < ns_count; ++i) {
             const Front& f = sy.fronts[i];
             if (f.parent < 0) continue;
-            const Front& P = sy.fronts[f.parent];
-            for (int64_t k = sy.rows_ptr[i]; k < sy.rows_ptr[i + 1]; ++k) {
-                int32_t lr = sy.rel[k];
-                int64_t compact = lr < P.ns_pad ? lr : P.ns + (lr - P.ns_pad);
-                lists[P.gather_base + compact].push_back(f.ubuf_row + (k - sy.rows_ptr[i]));
-            }
+            for (int64_t k = sy.rows_ptr[i]; k < sy.rows_ptr[i + 1]; ++k)
+                sy.gather_idx[fill[list_of(i, k)]++] = f.ubuf_row + (k - sy.rows_ptr[i]);
         }
-        // children are visited in front order, which is slot order within a parent
-        sy.gather_ptr.assign(gb + 1, 0);
-        for (int64_t r = 0; r < gb; ++r) sy.gather_ptr[r + 1] = sy.gather_ptr[r] + (int64_t)lists[r].size();
-        sy.gather_idx.reserve(sy.gather_ptr[gb]);
-        for (auto& l : lists) sy.gather_idx.insert(sy.gather_idx.end(), l.begin(), l.end());
     }
+    phase_done("gather lists");
     // assembly map of A = S - mu M (lower triangle) into the front tiles
+    // (fronts in order, each front's entries counted, then written into its own
+    // range by the threads; the same map as one pass in front order)
     sy.asm_tlev_ptr.assign(sy.tree_levels + 1, 0);
-    for (int64_t i = 0; i < ns_count; ++i) {
-        const Front& f = sy.fronts[i];
-        const int32_t* fr = sy.rows.data() + sy.rows_ptr[i];
-        for (int32_t lc = 0; lc < f.ns_pad; ++lc) {
-            if (lc >= f.ns) {   // dummy pivot: identity
-                int64_t off = f.tile_base + tri_tile(f.Mt, lc / NB, lc / NB) * NB * NB + (lc % NB) * NB + lc % NB;
-                sy.asm_dst.push_back(off);
-                sy.asm_src.push_back(-1);
-                continue;
+    {
+        std::vector<int64_t> aptr(ns_count + 1, 0);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < ns_count; ++i) {
+            const Front& f = sy.fronts[i];
+            int64_t cnt = f.ns_pad - f.ns;   // dummy pivots
+            for (int32_t lc = 0; lc < f.ns; ++lc) {
+                const int64_t c = f.start + lc;
+                const int32_t v = sy.perm[c];
+                for (int64_t k = S.ptr[v]; k < S.ptr[v + 1]; ++k) cnt += sy.iperm[S.idx[k]] >= c;
             }
-            const int64_t c = f.start + lc;
-            const int32_t v = sy.perm[c];
-            for (int64_t k = S.ptr[v]; k < S.ptr[v + 1]; ++k) {
-                const int64_t r = sy.iperm[S.idx[k]];
-                if (r < c) continue;
-                int32_t lr;
-                if (r < f.start + f.ns) {
-                    lr = (int32_t)(r - f.start);
-                } else {
-                    const int32_t* it = std::lower_bound(fr, fr + f.mu, (int32_t)r);
-                    lr = f.ns_pad + (int32_t)(it - fr);
+            aptr[i + 1] = cnt;
+        }
+        for (int64_t i = 0; i < ns_count; ++i) aptr[i + 1] += aptr[i];
+        sy.asm_dst.assign(aptr[ns_count], 0);
+        sy.asm_src.assign(aptr[ns_count], 0);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < ns_count; ++i) {
+            const Front& f = sy.fronts[i];
+            const int32_t* fr = sy.rows.data() + sy.rows_ptr[i];
+            int64_t o = aptr[i];
+            for (int32_t lc = 0; lc < f.ns_pad; ++lc) {
+                if (lc >= f.ns) {   // dummy pivot: identity
+                    sy.asm_dst[o] = f.tile_base + tri_tile(f.Mt, lc / NB, lc / NB) * NB * NB + (lc % NB) * NB + lc % NB;
+                    sy.asm_src[o++] = -1;
+                    continue;
                 }
-                int64_t off = f.tile_base + tri_tile(f.Mt, lr / NB, lc / NB) * NB * NB + (lc % NB) * NB + lr % NB;
-                sy.asm_dst.push_back(off);
-                sy.asm_src.push_back(k);
+                const int64_t c = f.start + lc;
+                const int32_t v = sy.perm[c];
+                for (int64_t k = S.ptr[v]; k < S.ptr[v + 1]; ++k) {
+                    const int64_t r = sy.iperm[S.idx[k]];
+                    if (r < c) continue;
+                    int32_t lr;
+                    if (r < f.start + f.ns) {
+                        lr = (int32_t)(r - f.start);
+                    } else {
+                        const int32_t* it = std::lower_bound(fr, fr + f.mu, (int32_t)r);
+                        lr = f.ns_pad + (int32_t)(it - fr);
+                    }
+                    sy.asm_dst[o] = f.tile_base + tri_tile(f.Mt, lr / NB, lc / NB) * NB * NB + (lc % NB) * NB + lr % NB;
+                    sy.asm_src[o++] = k;
+                }
             }
         }
-        sy.asm_tlev_ptr[f.tlev + 1] = (int64_t)sy.asm_dst.size();
+        for (int64_t i = 0; i < ns_count; ++i)
+            sy.asm_tlev_ptr[sy.fronts[i].tlev + 1] = std::max(sy.asm_tlev_ptr[sy.fronts[i].tlev + 1], aptr[i + 1]);
     }
     for (int t = 0; t < sy.tree_levels; ++t)
         sy.asm_tlev_ptr[t + 1] = std::max(sy.asm_tlev_ptr[t + 1], sy.asm_tlev_ptr[t]);
 
+    phase_done("assembly map");
     // factorisation work lists
     sy.step_ptr.assign(sy.tree_levels + 1, 0);
     sy.diag_ptr.push_back(0);
@@ -353,6 +395,7 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
         }
         sy.step_ptr[t + 1] = nsteps;
     }
+    phase_done("work lists");
     // extend-add passes: (tree level of the parent, child slot)
     const int32_t mc = std::max<int32_t>(1, sy.max_children);
     sy.ea_ptr.assign((int64_t)sy.tree_levels * mc + 1, 0);
@@ -369,6 +412,7 @@ Symbolic analyse(const Csr& S, const double* coords, int64_t n) {
         }
     }
     check_symbolic(sy, n, S.nnz());
+    phase_done("extend-add passes");
     return sy;
 }
 
