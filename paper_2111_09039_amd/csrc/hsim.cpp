@@ -13,6 +13,8 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <memory>
+#include <random>
 
 #include "internal.h"
 #include "build_dev.h"
@@ -282,14 +284,39 @@ struct DenseGEP {
     }
 
     // returns the Jacobi sweeps used, or -1 when dM is not numerically
-    // positive definite (nothing else is computed then)
+    // positive definite (nothing else is computed then).  sigma > 0 (owned
+    // work arrays, k >= PROJ_MIN_K, kout <= k / 2): an estimate of an
+    // eigenvalue a little above the kout-th, for the spectral projection
     int32_t run(const double* dS, const double* dM, int32_t kout, double* lam_out, double* X, int64_t ldx,
-                hipStream_t s, int32_t max_sweeps = 40);
+                hipStream_t s, int32_t max_sweeps = 40, double sigma = 0.0);
+
+    // ---- spectral projection (large problems that want few eigenpairs)
+    // The projector P = (I + sign(sigma I - C)) / 2 onto the eigenvectors of C
+    // below sigma by the Newton-Schulz iteration X <- X (3 I - X^2) / 2 (only
+    // matrix products), its rank cnt = trace P, a basis Y = P G of its range
+    // (G a fixed Gaussian block), and the lowest kout eigenpairs of C from
+    // the Rayleigh-Ritz problem on span Y, solved twice (the second time on
+    // the first pass's Ritz basis, whose Gram matrix is close to I).
+    static constexpr int32_t PROJ_MIN_K = 512;
+    static constexpr int32_t NS_MAX_IT = 80;
+    DeviceBuffer pstore;
+    int32_t pm = 0;   // m the projection arrays are sized for
+    double *PX = nullptr, *PT = nullptr, *PXn = nullptr, *PG = nullptr, *PY = nullptr, *PCY = nullptr,
+           *PY2 = nullptr, *PA = nullptr, *PB = nullptr, *PW = nullptr, *plam = nullptr, *ppart = nullptr,
+           *pout = nullptr;
+    unsigned long long* pbound = nullptr;
+    std::unique_ptr<DenseGEP> sub;
+    int32_t ns_iters = 0, proj_rank = 0;   // of the last projection (0: not used)
+    void setup_proj();
+    // lowest kout eigenpairs of C (V: m x kout, orthonormal) or -1 (the caller
+    // falls back to the Jacobi sweeps); returns the Jacobi sweeps of the two
+    // Rayleigh-Ritz problems
+    int32_t project(int32_t kout, double sigma, double* lam_out, double* Vout, hipStream_t s);
 };
 
 
 int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* lam_out, double* X, int64_t ldx,
-                      hipStream_t s, int32_t max_sweeps) {
+                      hipStream_t s, int32_t max_sweeps, double sigma) {
     HIPCHECK(launch_equilibrate(dS, dM, k, S2, M2, e, s));
     HIPCHECK(launch_dense_to_front(M2, k, tiles, Mt, s));
     factor(s);
@@ -309,6 +336,18 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     // C = D^-1/2 W D^-1/2 (symmetrised) embedded in m x m; dis = D^-1/2
     HIPCHECK(launch_sym_scale(W, D, k, W2, s));
     HIPCHECK(launch_embed_pad(W2, k, m, C, normf, dis, D, Qs, s));   // Qs (>= 1024 doubles) free until the sweeps
+    ns_iters = proj_rank = 0;
+    if (sigma > 0 && owned && k >= PROJ_MIN_K && 2 * kout <= k) {
+        // V (m x kout) = the lowest kout eigenvectors of C, then the same back
+        // transformation as below
+        const int32_t sw = project(kout, sigma, lam_out, V, s);
+        if (sw >= 0) {
+            HIPCHECK(launch_row_scale(V, dis, false, k, kout, kout, W, s));
+            bwd(W, W2, kout, kout, s);
+            HIPCHECK(launch_diag_scale(e, k, W2, kout, kout, X, ldx, s));
+            return sw;
+        }
+    }
     HIPCHECK(launch_identity(V, m, s));
     const double tol_rel = 1e-15, tol_abs_rel = 1e-17;
     int32_t sweeps = 0;
@@ -329,6 +368,102 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     bwd(W, W2, kout, kout, s);
     HIPCHECK(launch_diag_scale(e, k, W2, kout, kout, X, ldx, s));
     return std::min(sweeps, max_sweeps);
+}
+
+void DenseGEP::setup_proj() {
+    if (pm == m) return;
+    const size_t mm = (size_t)m * m;
+    // X, T, Xn, G, Y, C Y, Y2: m x m each (Y blocks use at most k <= m columns);
+    // A, B, W: m x m each (Rayleigh-Ritz problems of at most m unknowns)
+    const size_t doubles = 10 * mm + (size_t)m + 256 + 8;
+    pstore.alloc(doubles * sizeof(double) + 256);
+    double* b = pstore.as<double>();
+    PX = b;
+    PT = PX + mm;
+    PXn = PT + mm;
+    PG = PXn + mm;
+    PY = PG + mm;
+    PCY = PY + mm;
+    PY2 = PCY + mm;
+    PA = PY2 + mm;
+    PB = PA + mm;
+    PW = PB + mm;
+    plam = PW + mm;
+    ppart = plam + m;
+    pout = ppart + 256;
+    pbound = reinterpret_cast<unsigned long long*>(pout + 4);
+    // G: a fixed Gaussian block (seeded; the same for every call of this size)
+    std::vector<double> g(mm);
+    std::mt19937_64 rng(0x5eed0000ULL + (uint64_t)m);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (double& v : g) v = nd(rng);
+    HIPCHECK(hipMemcpy(PG, g.data(), mm * sizeof(double), hipMemcpyHostToDevice));
+    if (!sub) sub.reset(new DenseGEP());
+    pm = m;
+}
+
+int32_t DenseGEP::project(int32_t kout, double sigma, double* lam_out, double* Vout, hipStream_t s) {
+    setup_proj();
+    double host[2] = {0, 0};
+    auto readback = [&] {
+        HIPCHECK(hipMemcpyAsync(host, pout, sizeof(host), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+    };
+    int32_t cnt = 0;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        // sign(sigma I - C) by Newton-Schulz: T = X^2, X <- 1.5 X - 0.5 X T; the
+        // deviation ||X^2 - I||_F is checked every second step from step 12;
+        // once below 1e-5 two more steps bring it to rounding level
+        HIPCHECK(launch_ns_init(C, m, k, sigma, pbound, PX, s));
+        int32_t it = 0, extra = -1;
+        for (it = 0; it < NS_MAX_IT; ++it) {
+            HIPCHECK(launch_dgemm(false, m, m, m, 1.0, PX, m, PX, m, 0.0, nullptr, 0, PT, m, s));
+            if (extra < 0 && it >= 12 && it % 2 == 0) {
+                HIPCHECK(launch_ns_check(PT, nullptr, m, k, ppart, pout, s));
+                readback();
+                if (!std::isfinite(host[0])) break;
+                if (std::sqrt(host[0]) < 1e-5) extra = 2;
+            }
+            if (extra == 0) break;
+            HIPCHECK(launch_dgemm(false, m, m, m, -0.5, PX, m, PT, m, 1.5, PX, m, PXn, m, s));
+            std::swap(PX, PXn);
+            if (extra > 0) --extra;
+        }
+        ns_iters = it;
+        if (extra != 0) return -1;   // not converged: the caller runs the Jacobi sweeps
+        // rank of P = (k + trace of X over the leading block) / 2
+        HIPCHECK(launch_ns_check(PT, PX, m, k, ppart, pout, s));
+        readback();
+        cnt = (int32_t)std::lround(0.5 * (k + host[1]));
+        if (cnt < kout + 1) {
+            sigma *= std::max(1.25, 1.3 * (kout + 8) / std::max(cnt, 1));
+            continue;
+        }
+        if (cnt > std::min<int32_t>(k / 2 + kout / 2, 3 * kout)) {
+            sigma *= std::max(0.5, 1.3 * (kout + 8) / (double)cnt);
+            continue;
+        }
+        break;
+    }
+    if (cnt < kout + 1 || cnt > k) return -1;
+    proj_rank = cnt;
+    // Y = P G = (G + X G) / 2 (m x cnt), first Rayleigh-Ritz problem (Y^T C Y, Y^T Y)
+    HIPCHECK(launch_dgemm(false, m, cnt, m, 0.5, PX, m, PG, m, 0.5, PG, m, PY, cnt, s));
+    auto rayleigh_ritz = [&](const double* Yb, int32_t kk, double* lam, double* Wout) {
+        HIPCHECK(launch_dgemm(false, m, cnt, m, 1.0, C, m, Yb, cnt, 0.0, nullptr, 0, PCY, cnt, s));
+        HIPCHECK(launch_dgemm(true, cnt, cnt, m, 1.0, Yb, cnt, PCY, cnt, 0.0, nullptr, 0, PA, cnt, s));
+        HIPCHECK(launch_dgemm(true, cnt, cnt, m, 1.0, Yb, cnt, Yb, cnt, 0.0, nullptr, 0, PB, cnt, s));
+        sub->setup(cnt, s);
+        return sub->run(PA, PB, kk, lam, Wout, kk, s);
+    };
+    const int32_t sw1 = rayleigh_ritz(PY, cnt, plam, PW);
+    if (sw1 < 0) return -1;
+    // second problem on the Ritz basis Y2 = Y W (its Gram matrix is close to I)
+    HIPCHECK(launch_dgemm(false, m, cnt, cnt, 1.0, PY, cnt, PW, cnt, 0.0, nullptr, 0, PY2, cnt, s));
+    const int32_t sw2 = rayleigh_ritz(PY2, kout, lam_out, PW);
+    if (sw2 < 0) return -1;
+    HIPCHECK(launch_dgemm(false, m, kout, cnt, 1.0, PY2, cnt, PW, kout, 0.0, nullptr, 0, Vout, kout, s));
+    return sw1 + sw2;
 }
 
 // ============================== reduced eigenproblem without allocation
@@ -1577,8 +1712,22 @@ static void coarse_solve(hsim_hierarchy* h, int32_t k, double* d_lam, double* d_
     HIPCHECK(launch_densify(dptr<int64_t>(C.dS_ptr), dptr<int32_t>(C.dS_idx), dptr<double>(C.dM_val), nc,
                             dptr<double>(h->coarseM), s));
     h->coarse.setup((int32_t)nc, s);
-    int32_t sw = h->coarse.run(dptr<double>(h->coarseS), dptr<double>(h->coarseM), k, d_lam, d_Phi, ldphi, s);
+    // Weyl's law for a surface, N(lambda) ~ area lambda / (4 pi): an eigenvalue
+    // estimate a little above the k-th for the spectral projection (which
+    // moves it itself when the count below it comes out too small or too
+    // large); HSIM_COARSE_JACOBI=1 keeps the Jacobi sweeps on the whole level
+    double area = 0.0;
+    for (double v : C.Mval) area += v;
+    const double sigma = (area > 0 && env_int("HSIM_COARSE_JACOBI", 0) == 0) ? 4.0 * M_PI * (1.3 * k + 8.0) / area : 0.0;
+    int32_t sw = h->coarse.run(dptr<double>(h->coarseS), dptr<double>(h->coarseM), k, d_lam, d_Phi, ldphi, s,
+                               DenseGEP::MAX_SWEEPS, sigma);
     if (sw < 0) fail(HSIM_E_FACTOR, "coarsest level: the mass matrix is not positive definite");
+    if (env_int("HSIM_VERBOSE", 0) != 0)
+        fprintf(stderr, "[hsim] coarsest level (%lld unknowns): %s, Jacobi sweeps %d\n", (long long)nc,
+                h->coarse.proj_rank > 0 ? "spectral projection" : "Jacobi on the whole level", sw);
+    if (env_int("HSIM_VERBOSE", 0) != 0 && h->coarse.proj_rank > 0)
+        fprintf(stderr, "[hsim]   projector rank %d after %d Newton-Schulz steps\n", h->coarse.proj_rank,
+                h->coarse.ns_iters);
     if (sweeps) *sweeps = sw;
 }
 

@@ -224,4 +224,20 @@ hipError_t launch_import_cols(const double* in, int64_t nv, const int32_t* perm,
 hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t p, const int32_t* perm,
                                int64_t nout, double* evecs, double* work, hipStream_t s);
 
+// ------------------------------------------------------------ dense products
+// Out (M x N) = alpha op(A) B + beta D (row-major; op(A) = A stored M x K, or
+// A^T with A stored K x M; D null or any M x N block, Out may equal D)
+hipError_t launch_dgemm(bool transa, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double beta, const double* D, int64_t ldd, double* Out,
+                        int64_t ldo, hipStream_t s);
+// X = (sigma I - C) / g on the leading k x k block of the m x m C (g the
+// Gershgorin bound of C - sigma I there, written to *bound as its bit
+// pattern), -1 on the diagonal of the remaining rows, 0 elsewhere
+hipError_t launch_ns_init(const double* C, int32_t m, int32_t k, double sigma, unsigned long long* bound, double* X,
+                          hipStream_t s);
+// out[0] = ||T - I||_F^2 (m x m), out[1] = sum_{i < k} X_ii (X may be null);
+// part: 256 doubles of scratch
+hipError_t launch_ns_check(const double* T, const double* X, int32_t m, int32_t k, double* part, double* out,
+                           hipStream_t s);
+
 }  // namespace hsim

@@ -3243,4 +3243,194 @@ hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t
     return hipGetLastError();
 }
 
+// ============================================================ dense products
+// Out (M x N) = alpha op(A) B + beta D, row-major with leading dimensions;
+// op(A) = A (A stored M x K) or A^T (A stored K x M); D may be null (beta
+// ignored) or equal to Out.  FP64 matrix cores: a workgroup of four waves
+// takes a 64 x 64 output tile, each wave a 32 x 32 quarter (2 x 2 tiles of
+// the 16 x 16 x 4 product); the contraction goes through LDS 32 at a time,
+// the next 32 loaded into registers while the current ones are multiplied.
+// Every output entry is one fixed-order sum, so results are reproducible.
+namespace {
+constexpr int DG_T = 64;   // output tile
+constexpr int DG_K = 32;   // contraction per stage
+}  // namespace
+__global__ __launch_bounds__(256) void k_dgemm(int transa, int64_t M, int64_t N, int64_t K, double alpha,
+                                               const double* __restrict__ A, int64_t lda,
+                                               const double* __restrict__ B, int64_t ldb, double beta,
+                                               const double* D, int64_t ldd, double* Out, int64_t ldo) {
+    __shared__ double As[DG_T][DG_K + 1];   // As[i][kk] = op(A)[i0 + i][k0 + kk]
+    __shared__ double Bs[DG_K][DG_T + 2];   // Bs[kk][j] = B[k0 + kk][j0 + j]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int64_t i0 = (int64_t)blockIdx.y * DG_T, j0 = (int64_t)blockIdx.x * DG_T;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    constexpr int PE = DG_T * DG_K / 256;   // 8 values of each operand per thread
+    double ra[PE], rb[PE];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int idx = tid + 256 * e;
+            if (!transa) {
+                const int i = idx / DG_K, kk = idx % DG_K;
+                ra[e] = (i0 + i < M && k0 + kk < K) ? A[(i0 + i) * lda + k0 + kk] : 0.0;
+            } else {
+                const int kk = idx / DG_T, i = idx % DG_T;
+                ra[e] = (i0 + i < M && k0 + kk < K) ? A[(k0 + kk) * lda + i0 + i] : 0.0;
+            }
+            const int kk = idx / DG_T, j = idx % DG_T;
+            rb[e] = (k0 + kk < K && j0 + j < N) ? B[(k0 + kk) * ldb + j0 + j] : 0.0;
+        }
+    };
+    auto stash = [&] {
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int idx = tid + 256 * e;
+            if (!transa)
+                As[idx / DG_K][idx % DG_K] = ra[e];
+            else
+                As[idx % DG_T][idx / DG_T] = ra[e];
+            Bs[idx / DG_T][idx % DG_T] = rb[e];
+        }
+    };
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[t][0] = acc[t][1] = dbl4{0, 0, 0, 0};
+    const int64_t nk = (K + DG_K - 1) / DG_K;
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) fetch((kt + 1) * DG_K);
+#pragma unroll
+        for (int ks = 0; ks < DG_K / 4; ++ks) {
+            const double a0 = As[wr + li][4 * ks + lk], a1 = As[wr + 16 + li][4 * ks + lk];
+            const double b0 = Bs[4 * ks + lk][wc + li], b1 = Bs[4 * ks + lk][wc + 16 + li];
+            acc[0][0] = mfma4(a0, b0, acc[0][0]);
+            acc[0][1] = mfma4(a0, b1, acc[0][1]);
+            acc[1][0] = mfma4(a1, b0, acc[1][0]);
+            acc[1][1] = mfma4(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            stash();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = i0 + wr + 16 * t + lk + 4 * v, j = j0 + wc + 16 * u + li;
+                if (i < M && j < N) {
+                    double r = alpha * acc[t][u][v];
+                    if (D) r += beta * D[i * ldd + j];
+                    Out[i * ldo + j] = r;
+                }
+            }
+}
+hipError_t launch_dgemm(bool transa, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double beta, const double* D, int64_t ldd, double* Out,
+                        int64_t ldo, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (K < 0) return hipErrorInvalidValue;
+    k_dgemm<<<dim3((unsigned)cdiv(N, DG_T), (unsigned)cdiv(M, DG_T)), 256, 0, s>>>(
+        transa ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd, Out, ldo);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ spectral projection helpers
+// Gershgorin bound of C - sigma I over the leading k x k block of the m x m C:
+// max over rows i < k of |c_ii - sigma| + sum_{j != i, j < k} |c_ij|.  One wave
+// per row; the maximum goes through an atomic on the bit pattern (the bound
+// is non-negative, and non-negative doubles order like their bits), so the
+// result does not depend on the order of the rows.
+__global__ __launch_bounds__(256) void k_ns_bound(const double* __restrict__ C, int32_t m, int32_t k, double sigma,
+                                                  unsigned long long* bound) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= k) return;
+    double sum = 0.0;
+    for (int32_t j = lane; j < k; j += 64) sum += fabs(C[i * m + j] - (j == i ? sigma : 0.0));
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if (lane == 0) atomicMax(bound, (unsigned long long)__double_as_longlong(sum));
+}
+// X = (sigma I - C) / g on the leading k x k block (g: the bound above), -1 on
+// the diagonal of the decoupled dummies, 0 elsewhere
+__global__ void k_ns_init(const double* __restrict__ C, int32_t m, int32_t k, double sigma,
+                          const unsigned long long* __restrict__ bound, double* X) {
+    const double g = __longlong_as_double((long long)*bound);
+    const double ginv = g > 0 ? 1.0 / g : 1.0;
+    const int64_t tot = (int64_t)m * m;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = (int32_t)(t / m), j = (int32_t)(t % m);
+        double v;
+        if (i < k && j < k)
+            v = ((i == j ? sigma : 0.0) - C[t]) * ginv;
+        else
+            v = i == j ? -1.0 : 0.0;
+        X[t] = v;
+    }
+}
+hipError_t launch_ns_init(const double* C, int32_t m, int32_t k, double sigma, unsigned long long* bound, double* X,
+                          hipStream_t s) {
+    if (k <= 0 || k > m) return hipErrorInvalidValue;
+    hipError_t e = launch_fill(reinterpret_cast<double*>(bound), 1, 0.0, s);   // +0.0: all bits zero
+    if (e != hipSuccess) return e;
+    k_ns_bound<<<(unsigned)cdiv(k, 4), 256, 0, s>>>(C, m, k, sigma, bound);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_ns_init<<<grid_for((int64_t)m * m, 256), 256, 0, s>>>(C, m, k, sigma, bound, X);
+    return hipGetLastError();
+}
+// out[0] = sum over the m x m T of (t_ij - delta_ij)^2, out[1] = sum_{i < k}
+// x_ii; fixed-order sums (workgroup b over its own range, then one workgroup)
+constexpr int NSRED_WG = 256;
+__global__ __launch_bounds__(256) void k_ns_dev_part(const double* __restrict__ T, int32_t m, double* part) {
+    __shared__ double red[256];
+    const int64_t tot = (int64_t)m * m, chunk = (tot + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = blockIdx.x * chunk, t1 = min(tot, t0 + chunk);
+    double sq = 0.0;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+        const double d = T[t] - ((t / m) == (t % m) ? 1.0 : 0.0);
+        sq += d * d;
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(256) void k_ns_finish(const double* __restrict__ part, const double* __restrict__ X,
+                                                   int32_t m, int32_t k, double* out) {
+    __shared__ double red[256], tr[256];
+    red[threadIdx.x] = part[threadIdx.x];
+    double t = 0.0;
+    if (X)
+        for (int32_t i = threadIdx.x; i < k; i += blockDim.x) t += X[(int64_t)i * m + i];
+    tr[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            tr[threadIdx.x] += tr[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0];
+        out[1] = tr[0];
+    }
+}
+hipError_t launch_ns_check(const double* T, const double* X, int32_t m, int32_t k, double* part, double* out,
+                           hipStream_t s) {
+    k_ns_dev_part<<<NSRED_WG, 256, 0, s>>>(T, m, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ns_finish<<<1, 256, 0, s>>>(part, X, m, k, out);
+    return hipGetLastError();
+}
+
 }  // namespace hsim

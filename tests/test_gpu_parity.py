@@ -165,6 +165,39 @@ def test_coarsest_dense_solve(small):
     assert err[1:].max() < 1e-8
 
 
+@pytest.mark.parametrize("p", [20, 100])
+def test_coarsest_spectral_projection(cuda, monkeypatch, capfd, p):
+    """The library's default coarsest level (1000 unknowns) wants q of its
+    eigenpairs: the spectral projection (Newton-Schulz sign of sigma I - C,
+    Rayleigh-Ritz on the projector's range) against LAPACK's dense generalized
+    eigensolver, and the Jacobi sweeps over the whole level against both."""
+    import paper_2111_09039_amd as hs
+    V, F, d = synth.config_mesh("sphere2k", seed=0)
+    H = hs.Hierarchy(V, F, p, levels=3)
+    e = H.export(H.levels - 1)
+    n = len(e["verts"])
+    assert n == 1000
+    Sc = sp.csr_matrix((e["S_data"], e["S_indices"], e["S_indptr"]), shape=(n, n)).toarray()
+    Mc = sp.csr_matrix((e["M_data"], e["S_indices"], e["S_indptr"]), shape=(n, n)).toarray()
+    lr, Xr = sl.eigh(Sc, Mc)
+    k = H.q
+    results = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("HSIM_COARSE_JACOBI", mode)
+        monkeypatch.setenv("HSIM_VERBOSE", "1")
+        lam, X, sweeps = H.coarse(k)
+        lam, X = lam.cpu().numpy(), X.cpu().numpy()
+        out = capfd.readouterr().err
+        assert ("spectral projection" in out) == (mode == "0"), out
+        print(f"[coarsest p={p} q={k} jacobi={mode}] {out.strip()}", flush=True)
+        assert np.abs(lam - lr[:k]).max() <= 1e-12 * lr[k - 1]
+        assert np.abs(X.T @ Mc @ X - np.eye(k)).max() < 1e-11
+        err = metrics.eigenvector_err(X, Xr, Mc, lr)
+        assert err[1:].max() < 1e-8, err.max()
+        results[mode] = lam
+    assert np.abs(results["0"] - results["1"]).max() <= 2e-12 * lr[k - 1]
+
+
 def test_ritz_update_and_residual(small):
     V, F, S, m, lv, H = small
     rng = np.random.default_rng(4)
