@@ -404,6 +404,16 @@ void DenseGEP::setup_proj() {
 
 int32_t DenseGEP::project(int32_t kout, double sigma, double* lam_out, double* Vout, hipStream_t s) {
     setup_proj();
+    // HSIM_VERBOSE=2: the time of every phase (with a synchronisation after each)
+    const bool timed = env_int("HSIM_VERBOSE", 0) >= 2;
+    auto tp = std::chrono::steady_clock::now();
+    auto phase = [&](const char* name) {
+        if (!timed) return;
+        HIPCHECK(hipStreamSynchronize(s));
+        const auto now = std::chrono::steady_clock::now();
+        fprintf(stderr, "[hsim projection] %-24s %8.3f ms\n", name, std::chrono::duration<double, std::milli>(now - tp).count());
+        tp = now;
+    };
     double host[2] = {0, 0};
     auto readback = [&] {
         HIPCHECK(hipMemcpyAsync(host, pout, sizeof(host), hipMemcpyDeviceToHost, s));
@@ -411,21 +421,32 @@ int32_t DenseGEP::project(int32_t kout, double sigma, double* lam_out, double* V
     };
     int32_t cnt = 0;
     for (int attempt = 0; attempt < 4; ++attempt) {
-        // sign(sigma I - C) by Newton-Schulz: T = X^2, X <- 1.5 X - 0.5 X T; the
-        // deviation ||X^2 - I||_F is checked every second step from step 12;
-        // once below 1e-5 two more steps bring it to rounding level
+        // sign(sigma I - C) by the scaled Newton-Schulz iteration: T = X^2,
+        // X <- a X (3 I - a^2 T) / 2 with a = sqrt(3 / (1 + l + l^2)) for an
+        // assumed lower bound l of |eigenvalues of X| (Chen and Chow's scaling:
+        // [l, 1] goes to [l', 1], nothing grows past 1, smaller values grow by
+        // at least 1.5 a per step; a -> 1 as l -> 1, the plain quadratically
+        // convergent step).  The deviation ||X^2 - I||_F is checked every
+        // second step from step 10; once below 1e-5 two more plain steps bring
+        // it to rounding level.
         HIPCHECK(launch_ns_init(C, m, k, sigma, pbound, PX, s));
+        double lb = 1e-6;
         int32_t it = 0, extra = -1;
         for (it = 0; it < NS_MAX_IT; ++it) {
             HIPCHECK(launch_dgemm(false, m, m, m, 1.0, PX, m, PX, m, 0.0, nullptr, 0, PT, m, s));
-            if (extra < 0 && it >= 12 && it % 2 == 0) {
+            if (extra < 0 && it >= 10 && it % 2 == 0) {
                 HIPCHECK(launch_ns_check(PT, nullptr, m, k, ppart, pout, s));
                 readback();
                 if (!std::isfinite(host[0])) break;
-                if (std::sqrt(host[0]) < 1e-5) extra = 2;
+                if (std::sqrt(host[0]) < 1e-5) {
+                    extra = 2;
+                    lb = 1.0;   // the plain step from here (a = 1 keeps 1 fixed)
+                }
             }
             if (extra == 0) break;
-            HIPCHECK(launch_dgemm(false, m, m, m, -0.5, PX, m, PT, m, 1.5, PX, m, PXn, m, s));
+            const double a = std::sqrt(3.0 / (1.0 + lb + lb * lb));
+            HIPCHECK(launch_dgemm(false, m, m, m, -0.5 * a * a * a, PX, m, PT, m, 1.5 * a, PX, m, PXn, m, s));
+            lb = std::min(1.0, 0.5 * a * lb * (3.0 - a * a * lb * lb));
             std::swap(PX, PXn);
             if (extra > 0) --extra;
         }
@@ -447,6 +468,7 @@ int32_t DenseGEP::project(int32_t kout, double sigma, double* lam_out, double* V
     }
     if (cnt < kout + 1 || cnt > k) return -1;
     proj_rank = cnt;
+    phase("sign iteration + rank");
     // Y = P G = (G + X G) / 2 (m x cnt), first Rayleigh-Ritz problem (Y^T C Y, Y^T Y)
     HIPCHECK(launch_dgemm(false, m, cnt, m, 0.5, PX, m, PG, m, 0.5, PG, m, PY, cnt, s));
     auto rayleigh_ritz = [&](const double* Yb, int32_t kk, double* lam, double* Wout) {
@@ -458,11 +480,13 @@ int32_t DenseGEP::project(int32_t kout, double sigma, double* lam_out, double* V
     };
     const int32_t sw1 = rayleigh_ritz(PY, cnt, plam, PW);
     if (sw1 < 0) return -1;
+    phase("first Rayleigh-Ritz");
     // second problem on the Ritz basis Y2 = Y W (its Gram matrix is close to I)
     HIPCHECK(launch_dgemm(false, m, cnt, cnt, 1.0, PY, cnt, PW, cnt, 0.0, nullptr, 0, PY2, cnt, s));
     const int32_t sw2 = rayleigh_ritz(PY2, kout, lam_out, PW);
     if (sw2 < 0) return -1;
     HIPCHECK(launch_dgemm(false, m, kout, cnt, 1.0, PY2, cnt, PW, kout, 0.0, nullptr, 0, Vout, kout, s));
+    phase("second Rayleigh-Ritz");
     return sw1 + sw2;
 }
 

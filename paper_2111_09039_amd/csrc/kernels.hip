@@ -3247,26 +3247,44 @@ hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t
 // Out (M x N) = alpha op(A) B + beta D, row-major with leading dimensions;
 // op(A) = A (A stored M x K) or A^T (A stored K x M); D may be null (beta
 // ignored) or equal to Out.  FP64 matrix cores: a workgroup of four waves
-// takes a 64 x 64 output tile, each wave a 32 x 32 quarter (2 x 2 tiles of
-// the 16 x 16 x 4 product); the contraction goes through LDS 32 at a time,
-// the next 32 loaded into registers while the current ones are multiplied.
-// Every output entry is one fixed-order sum, so results are reproducible.
+// takes a 64 x 64 output tile, each wave a 32 x 32 quarter (2 x 2 tiles of the
+// 16 x 16 x 4 product); the contraction goes through LDS 64 at a time in two
+// buffers (one barrier per stage), the next 64 loaded into registers while the
+// current ones are multiplied.  Every output entry is one fixed-order sum, so
+// results are reproducible.
 namespace {
 constexpr int DG_T = 64;   // output tile
-constexpr int DG_K = 32;   // contraction per stage
+constexpr int DG_K = 64;   // contraction per stage
+constexpr int DG_AS = DG_K + 1, DG_BS = DG_T + 2;   // LDS row strides
+constexpr size_t dgemm_lds() { return 2 * (size_t)(DG_T * DG_AS + DG_K * DG_BS) * sizeof(double); }
 }  // namespace
+// FULL: M, N and K are multiples of 64 (no bounds checks in the loads)
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_dgemm(int transa, int64_t M, int64_t N, int64_t K, double alpha,
                                                const double* __restrict__ A, int64_t lda,
                                                const double* __restrict__ B, int64_t ldb, double beta,
                                                const double* D, int64_t ldd, double* Out, int64_t ldo) {
-    __shared__ double As[DG_T][DG_K + 1];   // As[i][kk] = op(A)[i0 + i][k0 + kk]
-    __shared__ double Bs[DG_K][DG_T + 2];   // Bs[kk][j] = B[k0 + kk][j0 + j]
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* lds = reinterpret_cast<double*>(smem_raw);
+    // buffer b: As[i][kk] = op(A)[i0 + i][k0 + kk] at lds + b * BUF, Bs[kk][j] after it
+    constexpr int BUF = DG_T * DG_AS + DG_K * DG_BS;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.y * DG_T, j0 = (int64_t)blockIdx.x * DG_T;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    constexpr int PE = DG_T * DG_K / 256;   // 8 values of each operand per thread
+    constexpr int PE = DG_T * DG_K / 256;   // 16 values of each operand per thread
     double ra[PE], rb[PE];
+    // FULL: thread (w, lane) loads rows w + 4 e of the stage, element lane
+    const double* pa = !transa ? A + (i0 + w) * lda + lane : A + (int64_t)w * lda + i0 + lane;
+    const double* pb = B + (int64_t)w * ldb + j0 + lane;
     auto fetch = [&](int64_t k0) {
+        if (FULL) {
+#pragma unroll
+            for (int e = 0; e < PE; ++e) {
+                ra[e] = !transa ? pa[(int64_t)(4 * e) * lda + k0] : pa[(k0 + 4 * e) * lda];
+                rb[e] = pb[(k0 + 4 * e) * ldb];
+            }
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
             const int idx = tid + 256 * e;
@@ -3281,15 +3299,17 @@ __global__ __launch_bounds__(256) void k_dgemm(int transa, int64_t M, int64_t N,
             rb[e] = (k0 + kk < K && j0 + j < N) ? B[(k0 + kk) * ldb + j0 + j] : 0.0;
         }
     };
-    auto stash = [&] {
+    auto stash = [&](int b) {
+        double* As = lds + b * BUF;
+        double* Bs = As + DG_T * DG_AS;
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
             const int idx = tid + 256 * e;
             if (!transa)
-                As[idx / DG_K][idx % DG_K] = ra[e];
+                As[(idx / DG_K) * DG_AS + idx % DG_K] = ra[e];
             else
-                As[idx % DG_T][idx / DG_T] = ra[e];
-            Bs[idx / DG_T][idx % DG_T] = rb[e];
+                As[(idx % DG_T) * DG_AS + idx / DG_T] = ra[e];
+            Bs[(idx / DG_T) * DG_BS + idx % DG_T] = rb[e];
         }
     };
     dbl4 acc[2][2];
@@ -3297,24 +3317,25 @@ __global__ __launch_bounds__(256) void k_dgemm(int transa, int64_t M, int64_t N,
     for (int t = 0; t < 2; ++t) acc[t][0] = acc[t][1] = dbl4{0, 0, 0, 0};
     const int64_t nk = (K + DG_K - 1) / DG_K;
     fetch(0);
-    stash();
+    stash(0);
     __syncthreads();
     for (int64_t kt = 0; kt < nk; ++kt) {
         if (kt + 1 < nk) fetch((kt + 1) * DG_K);
+        const double* As = lds + (kt & 1) * BUF;
+        const double* Bs = As + DG_T * DG_AS;
 #pragma unroll
         for (int ks = 0; ks < DG_K / 4; ++ks) {
-            const double a0 = As[wr + li][4 * ks + lk], a1 = As[wr + 16 + li][4 * ks + lk];
-            const double b0 = Bs[4 * ks + lk][wc + li], b1 = Bs[4 * ks + lk][wc + 16 + li];
+            const int kc = 4 * ks + lk;
+            const double a0 = As[(wr + li) * DG_AS + kc], a1 = As[(wr + 16 + li) * DG_AS + kc];
+            const double b0 = Bs[kc * DG_BS + wc + li], b1 = Bs[kc * DG_BS + wc + 16 + li];
             acc[0][0] = mfma4(a0, b0, acc[0][0]);
             acc[0][1] = mfma4(a0, b1, acc[0][1]);
             acc[1][0] = mfma4(a1, b0, acc[1][0]);
             acc[1][1] = mfma4(a1, b1, acc[1][1]);
         }
+        // the other buffer was last read before the previous barrier
+        if (kt + 1 < nk) stash((int)((kt + 1) & 1));
         __syncthreads();
-        if (kt + 1 < nk) {
-            stash();
-            __syncthreads();
-        }
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -3335,8 +3356,19 @@ hipError_t launch_dgemm(bool transa, int64_t M, int64_t N, int64_t K, double alp
                         int64_t ldo, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (K < 0) return hipErrorInvalidValue;
-    k_dgemm<<<dim3((unsigned)cdiv(N, DG_T), (unsigned)cdiv(M, DG_T)), 256, 0, s>>>(
-        transa ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd, Out, ldo);
+    const dim3 grid((unsigned)cdiv(N, DG_T), (unsigned)cdiv(M, DG_T));
+    hipError_t e;
+    if (M % DG_T == 0 && N % DG_T == 0 && K % DG_K == 0 && K > 0) {
+        e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_dgemm<true>), dgemm_lds(), 0);
+        if (e != hipSuccess) return e;
+        k_dgemm<true><<<grid, 256, dgemm_lds(), s>>>(transa ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd,
+                                                     Out, ldo);
+    } else {
+        e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_dgemm<false>), dgemm_lds(), 0);
+        if (e != hipSuccess) return e;
+        k_dgemm<false><<<grid, 256, dgemm_lds(), s>>>(transa ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, D,
+                                                      ldd, Out, ldo);
+    }
     return hipGetLastError();
 }
 
