@@ -3259,8 +3259,8 @@ constexpr int DG_AS = DG_K + 1, DG_BS = DG_T + 2;   // LDS row strides
 constexpr size_t dgemm_lds() { return 2 * (size_t)(DG_T * DG_AS + DG_K * DG_BS) * sizeof(double); }
 }  // namespace
 // FULL: M, N and K are multiples of 64 (no bounds checks in the loads)
-template <bool FULL>
-__global__ __launch_bounds__(256) void k_dgemm(int transa, int64_t M, int64_t N, int64_t K, double alpha,
+template <bool FULL, bool transa>
+__global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
                                                const double* __restrict__ A, int64_t lda,
                                                const double* __restrict__ B, int64_t ldb, double beta,
                                                const double* D, int64_t ldd, double* Out, int64_t ldo) {
@@ -3357,18 +3357,19 @@ hipError_t launch_dgemm(bool transa, int64_t M, int64_t N, int64_t K, double alp
     if (M <= 0 || N <= 0) return hipSuccess;
     if (K < 0) return hipErrorInvalidValue;
     const dim3 grid((unsigned)cdiv(N, DG_T), (unsigned)cdiv(M, DG_T));
+    const bool full = M % DG_T == 0 && N % DG_T == 0 && K % DG_K == 0 && K > 0;
+    auto go = [&](auto kern) {
+        hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), dgemm_lds(), 0);
+        if (e != hipSuccess) return e;
+        kern<<<grid, 256, dgemm_lds(), s>>>(M, N, K, alpha, A, lda, B, ldb, beta, D, ldd, Out, ldo);
+        return hipSuccess;
+    };
     hipError_t e;
-    if (M % DG_T == 0 && N % DG_T == 0 && K % DG_K == 0 && K > 0) {
-        e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_dgemm<true>), dgemm_lds(), 0);
-        if (e != hipSuccess) return e;
-        k_dgemm<true><<<grid, 256, dgemm_lds(), s>>>(transa ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd,
-                                                     Out, ldo);
-    } else {
-        e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_dgemm<false>), dgemm_lds(), 0);
-        if (e != hipSuccess) return e;
-        k_dgemm<false><<<grid, 256, dgemm_lds(), s>>>(transa ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, D,
-                                                      ldd, Out, ldo);
-    }
+    if (full)
+        e = transa ? go(&k_dgemm<true, true>) : go(&k_dgemm<true, false>);
+    else
+        e = transa ? go(&k_dgemm<false, true>) : go(&k_dgemm<false, false>);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
