@@ -3246,48 +3246,55 @@ hipError_t launch_export_evecs(const double* Phi, int64_t ld, int64_t n, int32_t
 // ============================================================ dense products
 // Out (M x N) = alpha op(A) B + beta D, row-major with leading dimensions;
 // op(A) = A (A stored M x K) or A^T (A stored K x M); D may be null (beta
-// ignored) or equal to Out.  FP64 matrix cores: a workgroup of four waves
-// takes a 64 x 64 output tile, each wave a 32 x 32 quarter (2 x 2 tiles of the
-// 16 x 16 x 4 product); the contraction goes through LDS 64 at a time in two
-// buffers (one barrier per stage), the next 64 loaded into registers while the
-// current ones are multiplied.  Every output entry is one fixed-order sum, so
-// results are reproducible.
+// ignored) or equal to Out.  FP64 matrix cores: a workgroup of eight waves
+// (two per SIMD) takes a 64 x 64 output tile, waves w and w + 4 the 32 x 32
+// quarter w (2 x 2 tiles of the 16 x 16 x 4 product) over the two halves of
+// every stage's contraction; the contraction goes through LDS 64 at a time in
+// two buffers (one barrier per stage), the next 64 loaded into registers while
+// the current ones are multiplied, and the two halves' sums are added in a
+// fixed order at the end, so results are reproducible.
 namespace {
 constexpr int DG_T = 64;   // output tile
 constexpr int DG_K = 64;   // contraction per stage
+constexpr int DG_W = 8;    // waves per workgroup (two per SIMD)
 constexpr int DG_AS = DG_K + 1, DG_BS = DG_T + 2;   // LDS row strides
 constexpr size_t dgemm_lds() { return 2 * (size_t)(DG_T * DG_AS + DG_K * DG_BS) * sizeof(double); }
 }  // namespace
 // FULL: M, N and K are multiples of 64 (no bounds checks in the loads)
 template <bool FULL, bool transa>
-__global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
-                                               const double* __restrict__ A, int64_t lda,
-                                               const double* __restrict__ B, int64_t ldb, double beta,
-                                               const double* D, int64_t ldd, double* Out, int64_t ldo) {
+__global__ __launch_bounds__(64 * DG_W) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
+                                                    const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb, double beta,
+                                                    const double* D, int64_t ldd, double* Out, int64_t ldo) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* lds = reinterpret_cast<double*>(smem_raw);
     // buffer b: As[i][kk] = op(A)[i0 + i][k0 + kk] at lds + b * BUF, Bs[kk][j] after it
     constexpr int BUF = DG_T * DG_AS + DG_K * DG_BS;
+    constexpr int NT = 64 * DG_W;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.y * DG_T, j0 = (int64_t)blockIdx.x * DG_T;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    constexpr int PE = DG_T * DG_K / 256;   // 16 values of each operand per thread
+    // waves w and w + 4 share the 32 x 32 quarter w % 4 and take the two halves
+    // of every stage's contraction
+    const int wq = w & 3, kh = (w >> 2) * (DG_K / 2);
+    const int wr = (wq >> 1) * 32, wc = (wq & 1) * 32;
+    constexpr int PE = DG_T * DG_K / NT;   // values of each operand per thread
+    constexpr int RSTEP = NT / 64;         // stage rows per load step
     double ra[PE], rb[PE];
-    // FULL: thread (w, lane) loads rows w + 4 e of the stage, element lane
+    // FULL: thread (w, lane) loads rows w + RSTEP e of the stage, element lane
     const double* pa = !transa ? A + (i0 + w) * lda + lane : A + (int64_t)w * lda + i0 + lane;
     const double* pb = B + (int64_t)w * ldb + j0 + lane;
     auto fetch = [&](int64_t k0) {
         if (FULL) {
 #pragma unroll
             for (int e = 0; e < PE; ++e) {
-                ra[e] = !transa ? pa[(int64_t)(4 * e) * lda + k0] : pa[(k0 + 4 * e) * lda];
-                rb[e] = pb[(k0 + 4 * e) * ldb];
+                ra[e] = !transa ? pa[(int64_t)(RSTEP * e) * lda + k0] : pa[(k0 + RSTEP * e) * lda];
+                rb[e] = pb[(k0 + RSTEP * e) * ldb];
             }
             return;
         }
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
-            const int idx = tid + 256 * e;
+            const int idx = tid + NT * e;
             if (!transa) {
                 const int i = idx / DG_K, kk = idx % DG_K;
                 ra[e] = (i0 + i < M && k0 + kk < K) ? A[(i0 + i) * lda + k0 + kk] : 0.0;
@@ -3304,7 +3311,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
         double* Bs = As + DG_T * DG_AS;
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
-            const int idx = tid + 256 * e;
+            const int idx = tid + NT * e;
             if (!transa)
                 As[(idx / DG_K) * DG_AS + idx % DG_K] = ra[e];
             else
@@ -3324,8 +3331,8 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
         const double* As = lds + (kt & 1) * BUF;
         const double* Bs = As + DG_T * DG_AS;
 #pragma unroll
-        for (int ks = 0; ks < DG_K / 4; ++ks) {
-            const int kc = 4 * ks + lk;
+        for (int ks = 0; ks < DG_K / 8; ++ks) {
+            const int kc = kh + 4 * ks + lk;
             const double a0 = As[(wr + li) * DG_AS + kc], a1 = As[(wr + 16 + li) * DG_AS + kc];
             const double b0 = Bs[kc * DG_BS + wc + li], b1 = Bs[kc * DG_BS + wc + 16 + li];
             acc[0][0] = mfma4(a0, b0, acc[0][0]);
@@ -3337,19 +3344,32 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
         if (kt + 1 < nk) stash((int)((kt + 1) & 1));
         __syncthreads();
     }
+    // the upper waves' partial sums through LDS (free after the last barrier),
+    // added by the lower waves in a fixed order
+    dbl4* red = reinterpret_cast<dbl4*>(smem_raw);
+    if (w >= 4) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) red[((wq * 2 + t) * 2 + u) * 64 + lane] = acc[t][u];
+    }
+    __syncthreads();
+    if (w >= 4) return;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 2; ++u) {
+            const dbl4 o = red[((wq * 2 + t) * 2 + u) * 64 + lane];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + wr + 16 * t + lk + 4 * v, j = j0 + wc + 16 * u + li;
                 if (i < M && j < N) {
-                    double r = alpha * acc[t][u][v];
+                    double r = alpha * (acc[t][u][v] + o[v]);
                     if (D) r += beta * D[i * ldd + j];
                     Out[i * ldo + j] = r;
                 }
             }
+        }
 }
 hipError_t launch_dgemm(bool transa, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                         const double* B, int64_t ldb, double beta, const double* D, int64_t ldd, double* Out,
@@ -3361,7 +3381,7 @@ hipError_t launch_dgemm(bool transa, int64_t M, int64_t N, int64_t K, double alp
     auto go = [&](auto kern) {
         hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), dgemm_lds(), 0);
         if (e != hipSuccess) return e;
-        kern<<<grid, 256, dgemm_lds(), s>>>(M, N, K, alpha, A, lda, B, ldb, beta, D, ldd, Out, ldo);
+        kern<<<grid, 64 * DG_W, dgemm_lds(), s>>>(M, N, K, alpha, A, lda, B, ldb, beta, D, ldd, Out, ldo);
         return hipSuccess;
     };
     hipError_t e;
