@@ -246,7 +246,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
-                    help="one FP64 solve and a copy of known size, no timing loop (for rocprofv3)")
+                    help="one solve (FP64 unless --profile-precision mixed) and a copy of known size, no timing loop (for rocprofv3)")
+    ap.add_argument("--profile-precision", choices=["fp64", "mixed"], default="fp64",
+                    help="precision of the one solve of --profile-only")
     ap.add_argument("--batch", type=int, default=0,
                     help="the batched workload instead: this many of the 256 seeded meshes (2k-50k vertices), p = 50")
     ap.add_argument("--streams", type=int, default=8, help="worker streams of the batched solve")
@@ -298,7 +300,8 @@ def main():
 
     if args.profile_only:
         copy_calibration()
-        _, _, _, st = H.solve(tol=args.tol, precision=hs.FP64)
+        prec = hs.MIXED if args.profile_precision == "mixed" else hs.FP64
+        _, _, _, st = H.solve(tol=args.tol, precision=prec)
         torch.cuda.synchronize()
         log(f"profile-only solve done: iterations {st['iters']}, block solves {st['block_solves']}, "
             f"columns {st['block_solve_cols']}")
