@@ -320,12 +320,16 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     HIPCHECK(launch_equilibrate(dS, dM, k, S2, M2, e, s));
     HIPCHECK(launch_dense_to_front(M2, k, tiles, Mt, s));
     factor(s);
-    {
-        // the (equilibrated) mass matrix must be positive definite: a negative,
-        // zero or non-finite pivot is reported to the caller (-1) instead of
-        // turning into NaN through D^-1/2
+    // the (equilibrated) mass matrix must be positive definite: a negative,
+    // zero or non-finite pivot is reported to the caller (-1), nothing is
+    // returned from a reduction through D^-1/2 of such a factor.  The pivot
+    // counts go to rot[2..3] and are read with the first synchronisation (the
+    // steps up to it only compute; NaN from a failed factor stops no kernel)
+    HIPCHECK(hipMemcpyAsync(rot + 2, counters, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    const bool try_proj = sigma > 0 && owned && k >= PROJ_MIN_K && 2 * kout <= k;
+    if (try_proj) {
         int32_t piv[2] = {0, 0};
-        HIPCHECK(hipMemcpyAsync(piv, counters, sizeof(piv), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(piv, rot + 2, sizeof(piv), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         if (piv[0] > 0 || piv[1] > 0) return -1;
     }
@@ -337,7 +341,7 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     HIPCHECK(launch_sym_scale(W, D, k, W2, s));
     HIPCHECK(launch_embed_pad(W2, k, m, C, normf, dis, D, Qs, s));   // Qs (>= 1024 doubles) free until the sweeps
     ns_iters = proj_rank = 0;
-    if (sigma > 0 && owned && k >= PROJ_MIN_K && 2 * kout <= k) {
+    if (try_proj) {
         // V (m x kout) = the lowest kout eigenvectors of C, then the same back
         // transformation as below
         const int32_t sw = project(kout, sigma, lam_out, V, s);
@@ -353,14 +357,19 @@ int32_t DenseGEP::run(const double* dS, const double* dM, int32_t kout, double* 
     int32_t sweeps = 0;
     max_sweeps = std::min(max_sweeps, MAX_SWEEPS);
     // a sweep ends the iteration when it rotated nothing or when no entry is
-    // left above the threshold (the next sweep would rotate nothing)
+    // left above the threshold (the next sweep would rotate nothing).  The
+    // first sweep's counts are not read: a second sweep after one that
+    // converged rotates nothing and changes no entry, so the result is the
+    // same, and the host waits once less
     for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
         HIPCHECK(launch_fill_i32(rot, 2, 0, s));
         HIPCHECK(launch_bj_sweep(bj, C, V, m, Qs, normf, tol_rel, tol_abs_rel, 1, rot, qrot, s));
         HIPCHECK(launch_bj_offcount(C, m, normf, tol_rel, tol_abs_rel, rot + 1, s));
-        int32_t cnt[2] = {0, 0};
+        if (sweeps == 1 && max_sweeps > 1) continue;
+        int32_t cnt[4] = {0, 0, 0, 0};
         HIPCHECK(hipMemcpyAsync(cnt, rot, sizeof(cnt), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
+        if (cnt[2] > 0 || cnt[3] > 0) return -1;   // the pivot counts of the factor
         if (cnt[0] == 0 || cnt[1] == 0) break;
     }
     // Y = D^-1/2 V (sorted, first kout columns), X' = L^-T Y, X = E X'
