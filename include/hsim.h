@@ -385,7 +385,12 @@ hsim_status hsim_step_ritz(hsim_hierarchy* h, int32_t level, int32_t k, const do
 
 /* Coarsest level: first k eigenpairs of the coarsest level's dense problem
  * S^{T-1} Phi = M^{T-1} Phi Lambda (Algorithm 2, initial subspace).  d_lam [k],
- * d_Phi [n^{T-1} x k]. */
+ * d_Phi [n^{T-1} x k] (M-orthonormal columns); *sweeps (host, may be NULL): the
+ * Jacobi sweeps used.  Levels of at least 512 unknowns with k at most half of
+ * them compute the k pairs by spectral projection (Newton-Schulz sign of
+ * sigma I - C, then Rayleigh-Ritz on the projector's range); smaller ones,
+ * larger k, or the environment variable HSIM_COARSE_JACOBI=1 take block
+ * Jacobi on the whole level.  Synchronizes the stream. */
 hsim_status hsim_step_coarse(hsim_hierarchy* h, int32_t k, double* d_lam, double* d_Phi,
                              int32_t* sweeps, void* stream);
 
