@@ -1838,16 +1838,24 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         // shift and factorisation (re-shift on breakdown)
         double mu = choose_shift(lam, p, so.shift_alpha);
         const int32_t j = (int32_t)std::floor(so.shift_alpha * p + 1e-12);
-        for (int attempt = 0;; ++attempt) {
-            try {
-                factor_level(h, L, mu, s, mixed);
-                break;
-            } catch (const Error& e) {
-                if (e.code != HSIM_E_FACTOR || attempt >= 3) throw;
-                const int32_t jj = std::min<int32_t>(j + 1, q - 1);
-                mu += 0.25 * std::max(lam[jj] - lam[std::min<int32_t>(j, q - 1)], 1e-6 * std::fabs(lam[jj]));
+        // a quarter of the gap above the shift's eigenvalue estimate (lam: the
+        // coarser level's estimates, or this level's latest Ritz values)
+        auto shift_step = [&] {
+            const int32_t jj = std::min<int32_t>(j + 1, q - 1);
+            return 0.25 * std::max(lam[jj] - lam[std::min<int32_t>(j, q - 1)], 1e-6 * std::fabs(lam[jj]));
+        };
+        auto factor_reshift = [&] {
+            for (int attempt = 0;; ++attempt) {
+                try {
+                    factor_level(h, L, mu, s, mixed);
+                    break;
+                } catch (const Error& e) {
+                    if (e.code != HSIM_E_FACTOR || attempt >= 3) throw;
+                    mu += shift_step();
+                }
             }
-        }
+        };
+        factor_reshift();
         st.mu[li] = mu;
         st.neg_pivots[li] = L.neg_pivots;
         auto t2 = std::chrono::steady_clock::now();
@@ -1858,6 +1866,7 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
         double rmax = INFINITY;   // largest residual of the first p pairs after the last Rayleigh-Ritz step
         bool fp64_gram = false;
         double est32 = -1.0;      // backward error of a plain FP32 solve on this level's factor
+        int32_t rr_reshifts = 0;
         for (it = 1; it <= so.max_iters; ++it) {
             auto a0 = std::chrono::steady_clock::now();
             const int32_t act = q - locked;
@@ -1950,12 +1959,35 @@ hsim_status hsim_solve(hsim_hierarchy* h, const hsim_solve_opts* opts, double* d
             // one when asked for
             bool low_gram = mixed && !fp64_gram && gram32 && rmax > std::max(100.0 * so.tol, 1e-4);
             const int mode = low_gram ? GRAM_FP32 : (fp64_gram ? GRAM_FP64 : hi_gram);
-            if (!rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, mode)) {
-                // the low-precision Gram lost the definiteness of the reduced mass matrix
-                // (an ill-conditioned basis): this step and the rest of the level in FP64
-                fp64_gram = true;
-                low_gram = false;
-                rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, GRAM_FP64);
+            bool rr_done = false;
+            try {
+                if (!rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, mode)) {
+                    // the low-precision Gram lost the definiteness of the reduced mass matrix
+                    // (an ill-conditioned basis): this step and the rest of the level in FP64
+                    fp64_gram = true;
+                    low_gram = false;
+                    rayleigh_ritz(h, L, lam, res, s, &st.ms_gram, &st.ms_rr, &st.ms_ritz, GRAM_FP64);
+                }
+                rr_done = true;
+            } catch (const Error& e) {
+                if (e.code != HSIM_E_FACTOR || rr_reshifts >= 3) throw;
+            }
+            if (!rr_done) {
+                // even the FP64 reduced mass matrix is not positive definite: the
+                // two inverse iterations multiplied the component of an
+                // eigenvector whose eigenvalue lies almost on the shift by
+                // 1 / (lambda - mu)^2 until the columns were numerically
+                // dependent.  The shift moves as after a factorisation breakdown,
+                // the level is factored again and this step is redone from Phi
+                // (which a failed step leaves unchanged)
+                ++rr_reshifts;
+                mu += shift_step();
+                factor_reshift();
+                st.mu[li] = mu;
+                st.neg_pivots[li] = L.neg_pivots;
+                est32 = -1.0;
+                --it;
+                continue;
             }
             auto check = [&] {
                 conv = true;

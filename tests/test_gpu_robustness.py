@@ -97,6 +97,37 @@ def test_singular_shift(torus):
     assert r.cpu().numpy().max() < 1e-8
 
 
+def test_shift_next_to_an_eigenvalue_is_moved(cuda, monkeypatch):
+    """Mesh 201 of the batched workload (a noisy torus of 26,112 vertices,
+    p = 50, T = 2) with the coarsest level solved by block Jacobi and the
+    default block-solve plan: the shift from the coarsest estimate of
+    eigenvalue 5 lies so close to an eigenvalue of the finest level that the
+    first step's two inverse iterations make the basis numerically dependent
+    (the FP64 reduced mass matrix is not positive definite).  The solve moves
+    the shift, factors again and converges to the same eigenpairs as the
+    solve through the spectral projection, whose shift differs in the last
+    digits and needs no move."""
+    import paper_2111_09039_amd as hs
+    V, F = synth.batch_mesh(201, count=256)
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("HSIM_COARSE_JACOBI", mode)
+        H = hs.Hierarchy(V, F, 50, levels=2)
+        lam_c = H.coarse(H.q)[0].cpu().numpy()
+        ev, X, r, st = H.solve(tol=1e-6)
+        print(f"[coarse jacobi={mode}] shift {st['mu'][1]!r} (coarsest estimate {lam_c[5]!r}), "
+              f"iterations {st['iters']}", flush=True)
+        assert st["status"] == "HSIM_OK"
+        assert r.cpu().numpy().max() < 1e-6
+        out[mode] = (ev.cpu().numpy(), lam_c, st["mu"][1])
+    ev_j, lam_j, mu_j = out["1"]
+    ev_p, lam_p, mu_p = out["0"]
+    assert mu_j > lam_j[5]            # moved up from the coarsest estimate
+    assert mu_p == lam_p[5]           # taken as it is
+    rel = np.abs(ev_j - ev_p)[1:] / np.abs(ev_p[1:])
+    assert rel.max() < 1e-9, rel.max()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_two_solves_are_bitwise_equal(torus, precision):
     import torch
