@@ -18,6 +18,13 @@ with G_jk the symmetrised x_j^T g_k.  The cluster form is exact for losses
 that do not change under rotations inside a cluster (the reading taken for
 near-degenerate eigenvalues, e.g. the sphere's 2l+1 multiplets); for simple
 eigenvalues it equals the textbook formula.
+
+Dirichlet condition (Section 5, surfaces with boundary): the problem keeps the
+interior rows and columns of S and M, so for vectors extended by zero to the
+boundary vertices a^T S_II b = a~^T S b~ and a^T M_II b = a~^T M b~.  The
+derivatives above therefore hold unchanged with every vector (x_k, w_k and the
+cluster terms) extended by zero; only the eigenpairs come from the interior
+problem, and dL/dx_k is read on the interior rows.
 """
 from __future__ import annotations
 
@@ -25,7 +32,7 @@ import numpy as np
 import scipy.linalg as sl
 import torch
 
-from .assembly import assemble
+from .assembly import assemble, dirichlet
 
 
 def _corner_terms(Vt, Ft):
@@ -69,19 +76,30 @@ def clusters_of(lam, gap=1e-2):
     return cl
 
 
-def reference_gradient(V, F, p, grad_lam=None, grad_X=None, density=None, gap=1e-2):
+def reference_gradient(V, F, p, grad_lam=None, grad_X=None, density=None, gap=1e-2, boundary="neumann"):
     """dL/dV (n x 3) for L with dL/dlambda = grad_lam(lam[:p]) and
-    dL/dX = grad_X(X[:, :p]) at the exact eigenpairs (dense, all n pairs;
-    the dense generalized eigensolver is a library routine).  Returns
-    (grad, lam[:p], X[:, :p])."""
+    dL/dX = grad_X(X[:, :p]) at the exact eigenpairs (dense, all pairs of the
+    problem; the dense generalized eigensolver is a library routine).
+    boundary="dirichlet" takes the eigenpairs of the interior problem, the
+    eigenvectors extended by zero to the whole mesh.  Returns
+    (grad, lam[:p], X[:, :p]) with X over all mesh vertices."""
     V = np.asarray(V, dtype=np.float64)
     F = np.asarray(F, dtype=np.int64)
     S, m = assemble(V, F, density=density)
-    lam, X = sl.eigh(S.toarray(), np.diag(m))
+    if boundary == "dirichlet":
+        Si, mi, interior = dirichlet(S, m, F)
+        lam, Xi = sl.eigh(Si.toarray(), np.diag(mi))
+        X = np.zeros((len(V), len(lam)))
+        X[interior] = Xi
+    elif boundary == "neumann":
+        lam, X = sl.eigh(S.toarray(), np.diag(m))
+    else:
+        raise ValueError("boundary must be 'neumann' or 'dirichlet'")
     n = len(lam)
+    nv = len(V)
     x = X[:, :p]
     gl = np.zeros(p) if grad_lam is None else np.asarray(grad_lam(lam[:p]), dtype=np.float64)
-    W = np.zeros((n, p))
+    W = np.zeros((nv, p))
     Gam = np.zeros((n, p))
     if grad_X is not None:
         gX = np.asarray(grad_X(x), dtype=np.float64)
