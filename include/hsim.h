@@ -276,10 +276,15 @@ hsim_status hsim_autotune(hsim_hierarchy* h, int32_t level, void* stream, hsim_t
  *   d_grad_evals  device, [p] dL/dlambda, or NULL
  *   d_grad_evecs  device, [nv x p] column-major dL/dX, or NULL
  *   d_grad_V      device, [nv x 3] row-major, overwritten with dL/dV
+ * Under the Dirichlet option (Section 5, surfaces with boundary) the problem
+ * keeps the interior rows and columns of S and M; with the eigenvectors and the
+ * adjoint vectors extended by zero the same formulas hold over the whole mesh.
+ * The rows of d_grad_evecs at boundary vertices are ignored (those eigenvector
+ * entries are fixed at zero); d_grad_V covers every vertex, the boundary ones
+ * included, since they move the interior problem's cotangent weights and masses.
  * HSIM_E_STATE before a converged hsim_solve on this hierarchy (after none, after
  * one that ended with HSIM_E_NOCONV or another error, or after a step-level call).
- * HSIM_E_UNIMPLEMENTED for a hierarchy built with the Dirichlet boundary
- * option or with circumcentric lumping.
+ * HSIM_E_UNIMPLEMENTED for a hierarchy built with circumcentric lumping.
  */
 hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals,
                                 const double* d_grad_evecs, double* d_grad_V, void* stream);

@@ -2230,7 +2230,11 @@ static void backward_setup(hsim_hierarchy* h) {
     h->bV.upload(m.V);
     h->bF.upload(m.F);
     if (!h->density.empty()) h->bRho.upload(h->density);
-    h->bIperm.upload(L0.sy.iperm);
+    // mesh vertex -> internal row of level 0; -1 for a vertex the level does not
+    // keep (the boundary under the Dirichlet condition), whose values are zero
+    std::vector<int32_t> vrow(m.nv, -1);
+    for (int64_t j = 0; j < L0.n; ++j) vrow[L0.verts[j]] = L0.sy.iperm[j];
+    h->bIperm.upload(vrow);
     // vertex -> (triangle, corner) lists in triangle order
     std::vector<int64_t> ptr(m.nv + 1, 0), vt(3 * m.nf);
     for (int64_t t = 0; t < m.nf; ++t)
@@ -2259,7 +2263,6 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
     if (h->host_only) fail(HSIM_E_STATE, "hierarchy was built host-only");
     if (!h->solved) fail(HSIM_E_STATE, "hsim_solve_backward before a successful hsim_solve");
     if (h->bo.lumping != 0) fail(HSIM_E_UNIMPLEMENTED, "the adjoint supports the barycentric lumping only");
-    if (h->lv[0]->n < h->mesh.nv) fail(HSIM_E_UNIMPLEMENTED, "the adjoint of the Dirichlet problem is not implemented");
     hipStream_t s = S_(stream);
     backward_setup(h);
     Level& L0 = *h->lv[0];
@@ -2292,7 +2295,9 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
         // dL/dPhi_k = sign_k dL/dx_k
         const int64_t nch_exp = (n + 8191) / 8192;
         const double* sign = dptr<double>(h->exportw) + 2 * nch_exp * p;
-        HIPCHECK(launch_import_cols(d_grad_evecs, nv, dptr<int32_t>(L0.dperm), n, p, Gb, ld, s, sign));
+        // rows of the kept vertices only: a boundary row of an eigenvector is zero
+        // under the Dirichlet condition, so its gradient there does not enter
+        HIPCHECK(launch_import_cols(d_grad_evecs, nv, dptr<int32_t>(L0.dmeshmap), n, p, Gb, ld, s, sign));
         HIPCHECK(launch_diag_scale(md, n, X, ld, q, MX, ld, s));
         std::vector<double> lamh(q);
         HIPCHECK(hipMemcpyAsync(lamh.data(), lam, q * sizeof(double), hipMemcpyDeviceToHost, s));

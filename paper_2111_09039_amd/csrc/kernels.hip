@@ -3011,7 +3011,8 @@ hipError_t launch_div_cols(const double* num, const double* den, double* out, in
 // ============================================================ assembly derivative (vertex positions)
 // Per vertex (mesh order): nu_i = rho_i sum_k [ -lam_k glam_k x_ki^2 + lam_k w_ki x_ki - y_ki x_ki / 2 ],
 // the coefficient of the lumped-mass derivative (Y = X_cluster Gamma carries
-// the normalisation terms).
+// the normalisation terms).  iperm[v] < 0 marks a vertex without a row (the
+// boundary under the Dirichlet condition): its values are zero, so nu_v = 0.
 __global__ void k_bwd_vertex(int64_t nv, int32_t p, const double* __restrict__ X, const double* __restrict__ W,
                              const double* __restrict__ Y, int64_t ld, const int32_t* __restrict__ iperm,
                              const double* __restrict__ lam, const double* __restrict__ glam,
@@ -3019,7 +3020,7 @@ __global__ void k_bwd_vertex(int64_t nv, int32_t p, const double* __restrict__ X
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = iperm[v];
         double s = 0;
-        for (int k = 0; k < p; ++k) {
+        for (int k = 0; r >= 0 && k < p; ++k) {
             const double x = X[r * ld + k];
             double t = 0;
             if (glam) t -= lam[k] * glam[k] * x * x;
@@ -3046,6 +3047,8 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
 // Per triangle: derivative of sum over corners of (1/2) e_opp cot(theta) plus
 // (nu_a + nu_b + nu_c)/3 * area, with e_opp = sum_k [glam_k (x_i - x_j)^2 -
 // (w_i - w_j)(x_i - x_j)] over the edge opposite the corner.  G[t][corner][xyz].
+// A corner whose vertex has no row (iperm < 0) has x = w = 0: the zero extension
+// of the interior problem's vectors under the Dirichlet condition.
 __global__ void k_bwd_tri(int64_t nf, const int32_t* __restrict__ F, const double* __restrict__ V, int32_t p,
                           const double* __restrict__ X, const double* __restrict__ W, int64_t ld,
                           const int32_t* __restrict__ iperm, const double* __restrict__ glam,
@@ -3058,10 +3061,12 @@ __global__ void k_bwd_tri(int64_t nf, const int32_t* __restrict__ F, const doubl
             for (int d = 0; d < 3; ++d) P[a][d] = V[3 * (int64_t)vi[a] + d];
         double e[3] = {0, 0, 0};   // per corner: its opposite edge
         for (int k = 0; k < p; ++k) {
-            const double x0 = X[ri[0] * ld + k], x1 = X[ri[1] * ld + k], x2 = X[ri[2] * ld + k];
-            const double xs[3] = {x0, x1, x2};
-            double ws[3] = {0, 0, 0};
-            if (W) { ws[0] = W[ri[0] * ld + k]; ws[1] = W[ri[1] * ld + k]; ws[2] = W[ri[2] * ld + k]; }
+            double xs[3] = {0, 0, 0}, ws[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                if (ri[a] >= 0) {
+                    xs[a] = X[ri[a] * ld + k];
+                    if (W) ws[a] = W[ri[a] * ld + k];
+                }
             const double g = glam ? glam[k] : 0.0;
             for (int c = 0; c < 3; ++c) {
                 const int i = (c + 1) % 3, j = (c + 2) % 3;

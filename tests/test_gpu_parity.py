@@ -284,13 +284,52 @@ def test_hsim_dirichlet_end_to_end(cuda):
     evm, Xm = evm.cpu().numpy(), Xm.cpu().numpy()
     assert np.abs(evm - lr[:p]).max() <= 1e-9 * lr[p - 1], np.abs(evm - lr[:p]).max()
     assert (Xm[boundary] == 0).all() and rm.max().item() < 1e-10
-    with pytest.raises(Exception, match="UNIMPLEMENTED"):
-        H.backward(grad_evals=torch_ones(p))
 
 
-def torch_ones(k):
+def test_adjoint_dirichlet_vs_dense_reference(cuda):
+    # Dirichlet condition: eigenvalue + cluster-invariant eigenvector loss on a
+    # bumped open sheet with density, against the oracle's dense gradient of the
+    # interior problem (boundary vertices included: they move the interior's
+    # cotangent weights and masses)
     import torch
-    return torch.ones(k, dtype=torch.float64, device="cuda")
+    import paper_2111_09039_amd as hs
+    from oracle import gradient
+    rng = np.random.default_rng(12)
+    V, F = synth.rectangle_grid(40, 30, 0.05)
+    V = synth.isotropic_noise(V, F, 0.15 * synth.mean_edge_length(V, F), rng)
+    V[:, 2] += 0.3 * np.exp(-((V[:, 0] - 1.0) ** 2 + (V[:, 1] - 0.7) ** 2) / 0.2)
+    d = synth.random_density(len(V), rng)
+    p = 12
+    H = hs.Hierarchy(V, F, p, levels=2, n_coarsest=200, boundary="dirichlet", density=d)
+    print(f"[adjoint dirichlet] n={len(V)} p={p}", flush=True)
+    ev, X, r, st = H.solve(tol=1e-11, save_forward=True)
+    lam = ev.cpu().numpy()
+    cl = gradient.clusters_of(lam, 1e-2)
+    wl = np.random.default_rng(1).uniform(0.5, 2.0, p)
+    T = np.random.default_rng(4).standard_normal((len(V), p))
+
+    def grad_X(Xn):
+        G = np.zeros_like(Xn)
+        for c in np.unique(cl[:p]):
+            idx = np.nonzero(cl[:p] == c)[0]
+            G[:, idx] = 2 * T[:, idx] @ (Xn[:, idx].T @ T[:, idx]).T
+        return G
+
+    gl = torch.from_numpy(2 * wl * lam).cuda()
+    gX = torch.from_numpy(grad_X(X.cpu().numpy())).cuda()
+    gV = H.backward(grad_evals=gl, grad_evecs=gX).cpu().numpy()
+    gr, lr, _ = gradient.reference_gradient(V, F, p, grad_lam=lambda l: 2 * wl * l, grad_X=grad_X, density=d,
+                                            boundary="dirichlet")
+    assert np.abs(lam - lr).max() <= 1e-9 * lr[-1]
+    err = np.linalg.norm(gV - gr) / np.linalg.norm(gr)
+    print(f"[adjoint dirichlet] rel err vs dense reference {err:.2e}", flush=True)
+    assert err < 1e-6
+    # eigenvalue part alone, the tighter bar of the Neumann test
+    gV1 = H.backward(grad_evals=gl).cpu().numpy()
+    gr1, _, _ = gradient.reference_gradient(V, F, p, grad_lam=lambda l: 2 * wl * l, density=d, boundary="dirichlet")
+    assert np.linalg.norm(gV1 - gr1) / np.linalg.norm(gr1) < 1e-7
+
+
 
 
 # ---------------------------------------------------------------- mixed precision
