@@ -7,7 +7,8 @@ Plain definitions, written with PyTorch CPU autograd for the assembly part:
   over the edge (i, j) opposite the corner (eq. massStiffMatrices with the
   cotangent formula);
 * a^T M(V) b = sum_i m_i(V) a_i b_i, m_i = rho_i sum_{t containing i} area(t)/3
-  (barycentric lumping).
+  (barycentric lumping), or rho_i times the circumcentric dual area (each
+  corner's cot(theta) |e|^2 / 8 over its opposite edge e, to both ends of e).
 
 Eigenvalue derivative (simple eigenvalue, x^T M x = 1):
     d lambda_k = x_k^T (dS - lambda_k dM) x_k.
@@ -56,12 +57,22 @@ def bilinear_S(Vt, Ft, A, B):
     return tot
 
 
-def lumped_mass_torch(Vt, Ft, rho=None):
-    a, b, c = Vt[Ft[:, 0]], Vt[Ft[:, 1]], Vt[Ft[:, 2]]
-    area = 0.5 * torch.linalg.norm(torch.cross(b - a, c - a, dim=1), dim=1)
+def lumped_mass_torch(Vt, Ft, rho=None, lumping="barycentric"):
+    """Lumped masses as a function of the positions: barycentric (area / 3 per
+    corner) or circumcentric (each corner's cot times its opposite edge's
+    squared length / 8, to both ends of that edge)."""
     m = torch.zeros(Vt.shape[0], dtype=Vt.dtype)
-    for k in range(3):
-        m = m.index_add(0, Ft[:, k], area / 3.0)
+    if lumping == "barycentric":
+        a, b, c = Vt[Ft[:, 0]], Vt[Ft[:, 1]], Vt[Ft[:, 2]]
+        area = 0.5 * torch.linalg.norm(torch.cross(b - a, c - a, dim=1), dim=1)
+        for k in range(3):
+            m = m.index_add(0, Ft[:, k], area / 3.0)
+    elif lumping == "voronoi":
+        for cot, i, j in _corner_terms(Vt, Ft):
+            t = cot * ((Vt[i] - Vt[j]) ** 2).sum(1) / 8.0
+            m = m.index_add(0, i, t).index_add(0, j, t)
+    else:
+        raise ValueError(lumping)
     if rho is not None:
         m = m * torch.as_tensor(rho, dtype=Vt.dtype)
     return m
@@ -76,7 +87,8 @@ def clusters_of(lam, gap=1e-2):
     return cl
 
 
-def reference_gradient(V, F, p, grad_lam=None, grad_X=None, density=None, gap=1e-2, boundary="neumann"):
+def reference_gradient(V, F, p, grad_lam=None, grad_X=None, density=None, gap=1e-2, boundary="neumann",
+                       lumping="barycentric"):
     """dL/dV (n x 3) for L with dL/dlambda = grad_lam(lam[:p]) and
     dL/dX = grad_X(X[:, :p]) at the exact eigenpairs (dense, all pairs of the
     problem; the dense generalized eigensolver is a library routine).
@@ -85,7 +97,7 @@ def reference_gradient(V, F, p, grad_lam=None, grad_X=None, density=None, gap=1e
     (grad, lam[:p], X[:, :p]) with X over all mesh vertices."""
     V = np.asarray(V, dtype=np.float64)
     F = np.asarray(F, dtype=np.int64)
-    S, m = assemble(V, F, density=density)
+    S, m = assemble(V, F, lumping=lumping, density=density)
     if boundary == "dirichlet":
         Si, mi, interior = dirichlet(S, m, F)
         lam, Xi = sl.eigh(Si.toarray(), np.diag(mi))
@@ -116,7 +128,7 @@ def reference_gradient(V, F, p, grad_lam=None, grad_X=None, density=None, gap=1e
     Ft = torch.tensor(F)
     xt = torch.tensor(x)
     lt = torch.tensor(lam[:p])
-    m_t = lumped_mass_torch(Vt, Ft, density)
+    m_t = lumped_mass_torch(Vt, Ft, density, lumping)
     # eigenvalue part: sum_k gl_k x_k^T (S - lam_k M) x_k
     phi = bilinear_S(Vt, Ft, xt * torch.tensor(gl)[None, :], xt)
     phi = phi - (m_t[:, None] * xt * xt * (torch.tensor(gl) * lt)[None, :]).sum()

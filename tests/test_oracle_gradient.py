@@ -154,3 +154,57 @@ def test_dirichlet_gradient_differs_from_neumann():
     gn, ln, _ = gradient.reference_gradient(V, F, p, grad_lam=gl, density=d)
     assert ld[0] > 1.0 and abs(ln[0]) < 1e-8
     assert np.linalg.norm(gd - gn) > 0.1 * np.linalg.norm(gd)
+
+
+def test_circumcentric_mass_torch_matches_assembly():
+    # the differentiable masses equal the assembly's circumcentric masses
+    import torch
+    V, F, d = _mesh(9)
+    m = assembly.lumped_mass(V, F, lumping="voronoi", density=d)
+    mt = gradient.lumped_mass_torch(torch.tensor(V), torch.tensor(F.astype(np.int64)), d, "voronoi").numpy()
+    assert np.abs(mt - m).max() <= 1e-14 * np.abs(m).max()
+    assert np.abs(m - assembly.lumped_mass(V, F, density=d)).max() > 1e-3 * m.max()
+
+
+def test_circumcentric_gradient_matches_fd():
+    # circumcentric lumping: eigenvalue and eigenvector losses against central
+    # differences of the dense eigenpairs of that lumping
+    V, F, d = _mesh(10)
+    p = 8
+
+    def eig(Vx):
+        S, m = assembly.assemble(Vx, F, lumping="voronoi", density=d)
+        assert m.min() > 0
+        return sl.eigh(S.toarray(), np.diag(m))
+
+    lam0, X0 = eig(V)
+    cl = gradient.clusters_of(lam0, 1e-2)
+    wl = np.random.default_rng(1).uniform(0.5, 2.0, p)
+    T = np.random.default_rng(11).standard_normal((len(V), p))
+
+    def loss_of(lam, X):
+        tot = np.sum(wl * lam[:p] ** 2)
+        for c in np.unique(cl[:p]):
+            idx = np.nonzero(cl[:p] == c)[0]
+            tot += np.sum((X[:, idx].T @ T[:, idx]) ** 2)
+        return tot
+
+    def grad_X(X):
+        G = np.zeros_like(X)
+        for c in np.unique(cl[:p]):
+            idx = np.nonzero(cl[:p] == c)[0]
+            G[:, idx] = 2 * T[:, idx] @ (X[:, idx].T @ T[:, idx]).T
+        return G
+
+    g, lam, X = gradient.reference_gradient(V, F, p, grad_lam=lambda l: 2 * wl * l, grad_X=grad_X, density=d,
+                                            lumping="voronoi")
+    gb, _, _ = gradient.reference_gradient(V, F, p, grad_lam=lambda l: 2 * wl * l, grad_X=grad_X, density=d)
+    assert np.linalg.norm(g - gb) > 1e-3 * np.linalg.norm(g)
+    rng = np.random.default_rng(12)
+    for _ in range(4):
+        D = rng.standard_normal(V.shape)
+        h = 1e-6
+        lp, Xp = eig(V + h * D)
+        lm, Xm = eig(V - h * D)
+        fd = (loss_of(lp, Xp[:, :p]) - loss_of(lm, Xm[:, :p])) / (2 * h)
+        assert abs(fd - np.sum(g * D)) <= 1e-5 * abs(fd), (fd, np.sum(g * D))
