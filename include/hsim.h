@@ -282,9 +282,11 @@ hsim_status hsim_autotune(hsim_hierarchy* h, int32_t level, void* stream, hsim_t
  * The rows of d_grad_evecs at boundary vertices are ignored (those eigenvector
  * entries are fixed at zero); d_grad_V covers every vertex, the boundary ones
  * included, since they move the interior problem's cotangent weights and masses.
+ * The mass derivative follows the hierarchy's lumping: area / 3 per vertex
+ * (barycentric) or, circumcentric, each corner's cot(theta) |e|^2 / 8 over its
+ * opposite edge e to both ends of e.
  * HSIM_E_STATE before a converged hsim_solve on this hierarchy (after none, after
  * one that ended with HSIM_E_NOCONV or another error, or after a step-level call).
- * HSIM_E_UNIMPLEMENTED for a hierarchy built with circumcentric lumping.
  */
 hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals,
                                 const double* d_grad_evecs, double* d_grad_V, void* stream);

@@ -2262,7 +2262,6 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
     if (!h || !d_grad_V) fail(HSIM_E_INVALID, "null argument");
     if (h->host_only) fail(HSIM_E_STATE, "hierarchy was built host-only");
     if (!h->solved) fail(HSIM_E_STATE, "hsim_solve_backward before a successful hsim_solve");
-    if (h->bo.lumping != 0) fail(HSIM_E_UNIMPLEMENTED, "the adjoint supports the barycentric lumping only");
     hipStream_t s = S_(stream);
     backward_setup(h);
     Level& L0 = *h->lv[0];
@@ -2388,7 +2387,7 @@ hsim_status hsim_solve_backward(hsim_hierarchy* h, const double* d_grad_evals, c
     HIPCHECK(launch_bwd_vertex(nv, p, X, W, Y, ld, ip, lam, d_grad_evals, h->density.empty() ? nullptr : dptr<double>(h->bRho),
                                dptr<double>(h->bNu), s));
     HIPCHECK(launch_bwd_tri(nf, dptr<int32_t>(h->bF), dptr<double>(h->bV), p, X, W, ld, ip, d_grad_evals,
-                            dptr<double>(h->bNu), dptr<double>(h->bG), s));
+                            dptr<double>(h->bNu), h->bo.lumping, dptr<double>(h->bG), s));
     HIPCHECK(launch_bwd_gather(nv, dptr<int64_t>(h->bVtPtr), dptr<int64_t>(h->bVt), dptr<double>(h->bG), d_grad_V, s));
     HIPCHECK(hipStreamSynchronize(s));
     API_END

@@ -209,8 +209,8 @@ hipError_t launch_bwd_vertex(int64_t nv, int32_t p, const double* X, const doubl
                              const int32_t* iperm, const double* lam, const double* glam, const double* rho, double* nu,
                              hipStream_t s);
 hipError_t launch_bwd_tri(int64_t nf, const int32_t* F, const double* V, int32_t p, const double* X, const double* W,
-                          int64_t ld, const int32_t* iperm, const double* glam, const double* nu, double* G,
-                          hipStream_t s);
+                          int64_t ld, const int32_t* iperm, const double* glam, const double* nu, int32_t lumping,
+                          double* G, hipStream_t s);
 hipError_t launch_bwd_gather(int64_t nv, const int64_t* vt_ptr, const int64_t* vt, const double* G, double* gradV,
                              hipStream_t s);
 // out[r, c] = sign[c] * in[c * nv + perm[r]] (sign may be null)

@@ -3048,11 +3048,14 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
 // (nu_a + nu_b + nu_c)/3 * area, with e_opp = sum_k [glam_k (x_i - x_j)^2 -
 // (w_i - w_j)(x_i - x_j)] over the edge opposite the corner.  G[t][corner][xyz].
 // A corner whose vertex has no row (iperm < 0) has x = w = 0: the zero extension
-// of the interior problem's vectors under the Dirichlet condition.
+// of the interior problem's vectors under the Dirichlet condition.  The mass
+// term is nu times the derivative of the lumped masses: area / 3 per vertex
+// (lumping 0), or, circumcentric (lumping 1), each corner's cot(theta) |e|^2 / 8
+// over its opposite edge e to both ends of e.
 __global__ void k_bwd_tri(int64_t nf, const int32_t* __restrict__ F, const double* __restrict__ V, int32_t p,
                           const double* __restrict__ X, const double* __restrict__ W, int64_t ld,
                           const int32_t* __restrict__ iperm, const double* __restrict__ glam,
-                          const double* __restrict__ nu, double* __restrict__ G) {
+                          const double* __restrict__ nu, int32_t lumping, double* __restrict__ G) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
         const int32_t vi[3] = {F[3 * t], F[3 * t + 1], F[3 * t + 2]};
         const int64_t ri[3] = {iperm[vi[0]], iperm[vi[1]], iperm[vi[2]]};
@@ -3086,7 +3089,19 @@ __global__ void k_bwd_tri(int64_t nf, const int32_t* __restrict__ F, const doubl
             double wc[3], cu[3];
             cross3(w, cr, wc);
             cross3(cr, u, cu);
-            const double f = 0.5 * e[c];
+            double f = 0.5 * e[c];
+            if (lumping == 1) {
+                // nu-weighted derivative of cot(theta_c) |P_i - P_j|^2 / 8 (to m_i and m_j)
+                const double mc = 0.125 * (nu[vi[i]] + nu[vi[j]]);
+                double dij[3];
+                for (int d = 0; d < 3; ++d) dij[d] = P[i][d] - P[j][d];
+                f += mc * (dij[0] * dij[0] + dij[1] * dij[1] + dij[2] * dij[2]);
+                const double gl = 2.0 * mc * dot / sn;
+                for (int d = 0; d < 3; ++d) {
+                    grad[i][d] += gl * dij[d];
+                    grad[j][d] -= gl * dij[d];
+                }
+            }
             for (int d = 0; d < 3; ++d) {
                 const double du = w[d] / sn - dot * wc[d] / (s2 * sn);   // d cot / d u
                 const double dw = u[d] / sn - dot * cu[d] / (s2 * sn);   // d cot / d w
@@ -3095,8 +3110,8 @@ __global__ void k_bwd_tri(int64_t nf, const int32_t* __restrict__ F, const doubl
                 grad[c][d] -= f * (du + dw);
             }
         }
-        // area term
-        {
+        // barycentric mass term: nu times the derivative of area / 3
+        if (lumping == 0) {
             double e1[3], e2[3], cr[3], a1[3], a2[3];
             for (int d = 0; d < 3; ++d) { e1[d] = P[1][d] - P[0][d]; e2[d] = P[2][d] - P[0][d]; }
             cross3(e1, e2, cr);
@@ -3115,9 +3130,10 @@ __global__ void k_bwd_tri(int64_t nf, const int32_t* __restrict__ F, const doubl
     }
 }
 hipError_t launch_bwd_tri(int64_t nf, const int32_t* F, const double* V, int32_t p, const double* X, const double* W,
-                          int64_t ld, const int32_t* iperm, const double* glam, const double* nu, double* G,
-                          hipStream_t s) {
-    k_bwd_tri<<<grid_for(nf, 256), 256, 0, s>>>(nf, F, V, p, X, W, ld, iperm, glam, nu, G);
+                          int64_t ld, const int32_t* iperm, const double* glam, const double* nu, int32_t lumping,
+                          double* G, hipStream_t s) {
+    if (lumping != 0 && lumping != 1) return hipErrorInvalidValue;
+    k_bwd_tri<<<grid_for(nf, 256), 256, 0, s>>>(nf, F, V, p, X, W, ld, iperm, glam, nu, lumping, G);
     return hipGetLastError();
 }
 // gradV[v] = sum over the (triangle, corner) entries listed for v, in list order

@@ -330,6 +330,47 @@ def test_adjoint_dirichlet_vs_dense_reference(cuda):
     assert np.linalg.norm(gV1 - gr1) / np.linalg.norm(gr1) < 1e-7
 
 
+def test_adjoint_circumcentric_vs_dense_reference(cuda):
+    # circumcentric lumping: eigenvalue + cluster-invariant eigenvector loss on a
+    # noisy torus with density, against the oracle's dense gradient of that lumping
+    import torch
+    import paper_2111_09039_amd as hs
+    from oracle import gradient
+    rng = np.random.default_rng(13)
+    V, F = synth.torus(36, 24)
+    V = synth.isotropic_noise(V, F, 0.1 * synth.mean_edge_length(V, F), rng)
+    d = synth.random_density(len(V), rng)
+    assert assembly.lumped_mass(V, F, lumping="voronoi").min() > 0
+    p = 12
+    H = hs.Hierarchy(V, F, p, levels=2, n_coarsest=200, lumping=1, density=d)
+    print(f"[adjoint circumcentric] n={len(V)} p={p}", flush=True)
+    ev, X, r, st = H.solve(tol=1e-11, save_forward=True)
+    lam = ev.cpu().numpy()
+    cl = gradient.clusters_of(lam, 1e-2)
+    wl = np.random.default_rng(1).uniform(0.5, 2.0, p)
+    T = np.random.default_rng(4).standard_normal((len(V), p))
+
+    def grad_X(Xn):
+        G = np.zeros_like(Xn)
+        for c in np.unique(cl[:p]):
+            idx = np.nonzero(cl[:p] == c)[0]
+            G[:, idx] = 2 * T[:, idx] @ (Xn[:, idx].T @ T[:, idx]).T
+        return G
+
+    gl = torch.from_numpy(2 * wl * lam).cuda()
+    gX = torch.from_numpy(grad_X(X.cpu().numpy())).cuda()
+    gV = H.backward(grad_evals=gl, grad_evecs=gX).cpu().numpy()
+    gr, lr, _ = gradient.reference_gradient(V, F, p, grad_lam=lambda l: 2 * wl * l, grad_X=grad_X, density=d,
+                                            lumping="voronoi")
+    assert np.abs(lam - lr)[1:].max() <= 1e-9 * lr[-1]
+    err = np.linalg.norm(gV - gr) / np.linalg.norm(gr)
+    print(f"[adjoint circumcentric] rel err vs dense reference {err:.2e}", flush=True)
+    assert err < 1e-6
+    gV1 = H.backward(grad_evals=gl).cpu().numpy()
+    gr1, _, _ = gradient.reference_gradient(V, F, p, grad_lam=lambda l: 2 * wl * l, density=d, lumping="voronoi")
+    assert np.linalg.norm(gV1 - gr1) / np.linalg.norm(gr1) < 1e-7
+
+
 
 
 # ---------------------------------------------------------------- mixed precision
